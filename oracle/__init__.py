@@ -1,0 +1,110 @@
+"""CPU oracle for the stage-1 structural index -- TEST INFRASTRUCTURE ONLY.
+
+Wraps the plain byte-at-a-time C definition in ``jsidx_oracle.c`` (stage 1 of
+Langdale & Lemire, "Parsing Gigabytes of JSON per Second", Sec. 3.1) with
+ctypes.  Only the tests, the smoke check and the CPU-baseline leg of the
+benchmark may import this package; the HIP library never does.
+
+Flag bits (defined here independently of the HIP library's header):
+UTF8 = 0x1, UNCLOSED_STRING = 0x2, TRAILING_ESCAPE = 0x4, EMPTY = 0x8.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+ERR_UTF8 = 0x1
+ERR_UNCLOSED_STRING = 0x2
+ERR_TRAILING_ESCAPE = 0x4
+ERR_EMPTY = 0x8
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "jsidx_oracle.c")
+_LIB = os.path.join(_HERE, "libjsidx_oracle.so")
+_lib = None
+
+
+def build() -> str:
+    """Compile the oracle with the host C compiler (plain -O2, no tuning)."""
+    subprocess.run(
+        ["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-shared", "-fPIC",
+         "-o", _LIB, _SRC],
+        check=True)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        build()
+    lib = ctypes.CDLL(_LIB)
+    u8p = ctypes.POINTER(ctypes.c_uint8)
+    u32p = ctypes.POINTER(ctypes.c_uint32)
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    lib.oracle_index.argtypes = [u8p, ctypes.c_uint64, u32p, u32p]
+    lib.oracle_index.restype = ctypes.c_uint32
+    lib.oracle_index_batch.argtypes = [u8p, u64p, ctypes.c_uint32, u32p, u32p, u32p]
+    lib.oracle_index_batch.restype = ctypes.c_int
+    lib.oracle_utf8_valid.argtypes = [u8p, ctypes.c_uint64]
+    lib.oracle_utf8_valid.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _u8(buf) -> np.ndarray:
+    if isinstance(buf, (bytes, bytearray, memoryview)):
+        return np.frombuffer(bytes(buf), dtype=np.uint8)
+    a = np.ascontiguousarray(buf, dtype=np.uint8)
+    return a
+
+
+def _ptr(a: np.ndarray, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+def index(buf) -> tuple[np.ndarray, int]:
+    """Index one document. Returns (uint32 positions, flags)."""
+    a = _u8(buf)
+    out = np.empty(max(1, a.size), dtype=np.uint32)
+    err = np.zeros(1, dtype=np.uint32)
+    n = _load().oracle_index(_ptr(a, ctypes.c_uint8) if a.size else None, a.size,
+                             _ptr(out, ctypes.c_uint32), _ptr(err, ctypes.c_uint32))
+    return out[:n].copy(), int(err[0])
+
+
+def index_batch(bufs, offsets) -> tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """Index a batch; document d is bufs[offsets[d]:offsets[d+1]].
+
+    Returns (out_idx, out_n, out_err): out_idx has offsets[-1] entries and doc
+    d's positions (relative to its start) are out_idx[offsets[d]:offsets[d]+out_n[d]].
+    """
+    a = _u8(bufs)
+    off = np.ascontiguousarray(offsets, dtype=np.uint64)
+    nd = off.size - 1
+    if nd < 0:
+        raise ValueError("offsets must hold ndocs+1 entries")
+    if int(off[-1]) > a.size:
+        raise ValueError("offsets exceed buffer")
+    out = np.zeros(max(1, int(off[-1])), dtype=np.uint32)
+    out_n = np.zeros(max(1, nd), dtype=np.uint32)
+    out_err = np.zeros(max(1, nd), dtype=np.uint32)
+    rc = _load().oracle_index_batch(
+        _ptr(a, ctypes.c_uint8) if a.size else None, _ptr(off, ctypes.c_uint64), nd,
+        _ptr(out, ctypes.c_uint32), _ptr(out_n, ctypes.c_uint32),
+        _ptr(out_err, ctypes.c_uint32))
+    if rc != 0:
+        raise ValueError("offsets must be nondecreasing")
+    return out[: int(off[-1])], out_n[:nd], out_err[:nd]
+
+
+def utf8_valid(buf) -> bool:
+    """True iff buf is a concatenation of the well-formed UTF-8 sequences of
+    the paper's table of code points (Sec. 3.1.5)."""
+    a = _u8(buf)
+    return bool(_load().oracle_utf8_valid(_ptr(a, ctypes.c_uint8) if a.size else None,
+                                          a.size))

@@ -1,0 +1,161 @@
+/*
+ * jsidx_oracle.c -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, byte-at-a-time CPU definition of stage 1 of the JSON parser
+ * of Langdale & Lemire, "Parsing Gigabytes of JSON per Second" (Sec. 3.1):
+ * the structural index (structural, opening-quote and pseudo-structural byte
+ * positions) plus per-document validity flags.  Only tests/, the smoke check
+ * and the CPU-baseline leg of the benchmark may load this library; the product
+ * path (the HIP library) never links or calls it, and the two share no code.
+ *
+ * Everything here is exact integer work.  One state variable is stepped per
+ * input byte, in document order, with no blocking or reordering:
+ *
+ *   esc     -- this byte is escaped: the bytes just before it are a run of
+ *              backslashes of odd length (Sec. 3.1.1, Fig. 3: only an odd run
+ *              escapes what follows; an even run is a series of escaped
+ *              backslashes).
+ *   in_str  -- inclusive prefix XOR of the unescaped quotes seen so far
+ *              (Sec. 3.1.1, Fig. 4: an opening quote is inside the string
+ *              range, a closing quote is outside it).
+ *   pred    -- the previous byte was structural, white space or an unescaped
+ *              quote (Sec. 3.1.3, Fig. 5: the candidates for pseudo-structural
+ *              characters are the successors of such bytes).  The byte before
+ *              the document counts as white space, so that a scalar root value
+ *              is indexed (reading of the paper, which never shows a document
+ *              that does not start with a brace).
+ *
+ * Byte classes (Sec. 3.1.2, Table "vectorized classification"):
+ *   structural  , : [ ] { }      (0x2C 0x3A 0x5B 0x5D 0x7B 0x7D)
+ *   white space TAB LF CR SPACE  (0x09 0x0A 0x0D 0x20)
+ *   quote 0x22, backslash 0x5C, everything else "other" (incl. bytes >= 0x80).
+ *
+ * A byte i is emitted into the index (Sec. 3.1.3, last row of Fig. 5) iff
+ *   - it is an unescaped quote that opens a string, or
+ *   - it is a structural byte outside strings, or
+ *   - it is outside strings, is neither white space, structural nor an
+ *     unescaped quote, and its predecessor set `pred` (pseudo-structural).
+ * Closing quotes are removed (last step of Fig. 5).
+ *
+ * UTF-8 validation (Sec. 3.1.5, Table "unicode"): the document must be a
+ * concatenation of the byte sequences that table lists; a multi-byte sequence
+ * cut off by the end of the document is an error.  The check never changes
+ * the index.
+ *
+ * Flags at end of document (bit values match include/jsidx.h by definition,
+ * not by sharing a header):
+ *   0x1 UTF8             not a concatenation of well-formed sequences
+ *   0x2 UNCLOSED_STRING  in_str is set after the last byte
+ *   0x4 TRAILING_ESCAPE  the document ends with an odd run of backslashes
+ *   0x8 EMPTY            the index is empty
+ */
+#include <stddef.h>
+#include <stdint.h>
+
+#define OR_ERR_UTF8 0x1u
+#define OR_ERR_UNCLOSED_STRING 0x2u
+#define OR_ERR_TRAILING_ESCAPE 0x4u
+#define OR_ERR_EMPTY 0x8u
+
+/* ---- UTF-8: the rows of the paper's table of well-formed sequences ----
+ * Each row gives the accepted range of the first byte and of each following
+ * byte; a row with `len` bytes uses the first `len` ranges. */
+struct utf8_row {
+  int len;
+  uint8_t lo[4];
+  uint8_t hi[4];
+};
+
+static const struct utf8_row UTF8_ROWS[] = {
+    {1, {0x00, 0, 0, 0}, {0x7F, 0, 0, 0}},
+    {2, {0xC2, 0x80, 0, 0}, {0xDF, 0xBF, 0, 0}},
+    {3, {0xE0, 0xA0, 0x80, 0}, {0xE0, 0xBF, 0xBF, 0}},
+    {3, {0xE1, 0x80, 0x80, 0}, {0xEC, 0xBF, 0xBF, 0}},
+    {3, {0xED, 0x80, 0x80, 0}, {0xED, 0x9F, 0xBF, 0}},
+    {3, {0xEE, 0x80, 0x80, 0}, {0xEF, 0xBF, 0xBF, 0}},
+    {4, {0xF0, 0x90, 0x80, 0x80}, {0xF0, 0xBF, 0xBF, 0xBF}},
+    {4, {0xF1, 0x80, 0x80, 0x80}, {0xF3, 0xBF, 0xBF, 0xBF}},
+    {4, {0xF4, 0x80, 0x80, 0x80}, {0xF4, 0x8F, 0xBF, 0xBF}},
+};
+#define N_UTF8_ROWS (sizeof(UTF8_ROWS) / sizeof(UTF8_ROWS[0]))
+
+/* Length of the well-formed sequence starting at buf[i], or 0 if none of the
+ * table's rows matches there (including a sequence cut off at `len`). */
+static int utf8_match(const uint8_t *buf, uint64_t len, uint64_t i) {
+  for (size_t r = 0; r < N_UTF8_ROWS; r++) {
+    const struct utf8_row *row = &UTF8_ROWS[r];
+    if (buf[i] < row->lo[0] || buf[i] > row->hi[0]) continue;
+    if (i + (uint64_t)row->len > len) return 0; /* truncated at end */
+    for (int k = 1; k < row->len; k++) {
+      uint8_t b = buf[i + (uint64_t)k];
+      if (b < row->lo[k] || b > row->hi[k]) return 0;
+    }
+    return row->len;
+  }
+  return 0;
+}
+
+/* 1 if buf[0..len) is a concatenation of the table's sequences. */
+int oracle_utf8_valid(const uint8_t *buf, uint64_t len) {
+  uint64_t i = 0;
+  while (i < len) {
+    int n = utf8_match(buf, len, i);
+    if (n == 0) return 0;
+    i += (uint64_t)n;
+  }
+  return 1;
+}
+
+static int is_structural(uint8_t b) {
+  return b == 0x2C || b == 0x3A || b == 0x5B || b == 0x5D || b == 0x7B || b == 0x7D;
+}
+
+static int is_whitespace(uint8_t b) {
+  return b == 0x09 || b == 0x0A || b == 0x0D || b == 0x20;
+}
+
+/* Index one document.  out_idx must have room for `len` entries (one per
+ * byte at most).  Returns the number of entries written; *out_err receives the
+ * flags.  Positions are relative to buf. */
+uint32_t oracle_index(const uint8_t *buf, uint64_t len, uint32_t *out_idx,
+                      uint32_t *out_err) {
+  int esc = 0, in_str = 0, pred = 1;
+  uint32_t n = 0;
+  for (uint64_t i = 0; i < len; i++) {
+    uint8_t b = buf[i];
+    int c = is_structural(b);
+    int w = is_whitespace(b);
+    int q = (b == 0x22) && !esc;
+    if (q) in_str ^= 1;
+    int r = in_str;
+    int emit = (q && r) || (!r && c) || (!r && !q && !w && !c && pred);
+    if (emit) out_idx[n++] = (uint32_t)i;
+    pred = c || w || q;
+    esc = (b == 0x5C) && !esc;
+  }
+  uint32_t err = 0;
+  if (!oracle_utf8_valid(buf, len)) err |= OR_ERR_UTF8;
+  if (in_str) err |= OR_ERR_UNCLOSED_STRING;
+  if (esc) err |= OR_ERR_TRAILING_ESCAPE;
+  if (n == 0) err |= OR_ERR_EMPTY;
+  *out_err = err;
+  return n;
+}
+
+/* Index a batch: document d is bufs[offsets[d] .. offsets[d+1]), indexed on its
+ * own with fresh state.  Its entries go to out_idx[offsets[d] ...] (so out_idx
+ * holds offsets[ndocs] entries) and are
+ * relative to the document start; out_n[d] and out_err[d] get its count and
+ * flags.  Returns 0, or -1 if the offsets decrease. */
+int oracle_index_batch(const uint8_t *bufs, const uint64_t *offsets,
+                       uint32_t ndocs, uint32_t *out_idx, uint32_t *out_n,
+                       uint32_t *out_err) {
+  for (uint32_t d = 0; d < ndocs; d++) {
+    if (offsets[d + 1] < offsets[d]) return -1;
+  }
+  for (uint32_t d = 0; d < ndocs; d++) {
+    uint64_t a = offsets[d], e = offsets[d + 1];
+    out_n[d] = oracle_index(bufs + a, e - a, out_idx + a, &out_err[d]);
+  }
+  return 0;
+}

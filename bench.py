@@ -1,0 +1,202 @@
+#!/usr/bin/env python3
+"""Benchmark of the stage-1 structural index on one MI355X.
+
+Workload (default): one 256 MiB minified twitter-like JSON document (seed 1),
+resident in HBM.  A step is one jsidx_build call over the whole document
+(every stage-1 step: UTF-8 validation, escapes, string ranges, structural and
+pseudo-structural bytes, flattening to uint32 positions, flags).  Three copies
+of the input and outputs are rotated so that the 256 MB Infinity Cache does
+not hold the data between steps.
+
+Prints ONE JSON line.  value = input GB/s (1e9 bytes/s) over the timed steps;
+roofline = algorithmic bytes (N read + 4*S written) per launch over the launch
+time against 8 TB/s HBM; cpu_baseline = the CPU oracle on the same document.
+Extra workloads (numeric pretty-printed document, 100k-document batch vs one
+launch per document) are reported under "extra".
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "structural-index GB/s (1 doc & batched) vs HBM peak; docs/s; p99 latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def time_single(jx, torch, host: bytes, steps: int, warmup: int, copies: int = 3):
+    dev = torch.device("cuda:0")
+    n = len(host)
+    src = torch.frombuffer(bytearray(host), dtype=torch.uint8)
+    bufs = [src.to(dev) for _ in range(copies)]
+    outs = [torch.empty(n, dtype=torch.int32, device=dev) for _ in range(copies)]
+    cnts = [torch.empty(1, dtype=torch.int32, device=dev) for _ in range(copies)]
+    errs = [torch.empty(1, dtype=torch.int32, device=dev) for _ in range(copies)]
+    stream = torch.cuda.current_stream()
+    jx.reserve(n, stream)
+    for i in range(warmup):
+        k = i % copies
+        jx.build(bufs[k], outs[k], cnts[k], errs[k], stream)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    wall0 = time.perf_counter()
+    t0.record(stream)
+    for i in range(steps):
+        k = i % copies
+        jx.build(bufs[k], outs[k], cnts[k], errs[k], stream)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms = t0.elapsed_time(t1)
+    S = int(cnts[0].item())
+    err = int(errs[0].item())
+    diag = jx.diag(stream)
+    del bufs, outs
+    return {"ms_total": ms, "ms_per_launch": ms / steps, "S": S, "N": n, "flags": err, "diag": diag,
+            "wall_s": wall}
+
+
+def time_batch(jx, torch, data: bytes, offsets: np.ndarray, steps: int, warmup: int):
+    dev = torch.device("cuda:0")
+    total = int(offsets[-1])
+    nd = offsets.size - 1
+    bufs = torch.frombuffer(bytearray(data), dtype=torch.uint8).to(dev)
+    offs = torch.from_numpy(offsets.astype(np.int64)).to(dev)
+    out = torch.empty(total, dtype=torch.int32, device=dev)
+    cnt = torch.empty(nd, dtype=torch.int32, device=dev)
+    err = torch.empty(nd, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+    jx.reserve(total, stream)
+    for _ in range(warmup):
+        jx.build_batch(bufs, offs, out, cnt, err, stream)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for _ in range(steps):
+        jx.build_batch(bufs, offs, out, cnt, err, stream)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / steps
+    S = int(cnt.to(torch.int64).sum().item())
+    # comparator: one jsidx_build launch per document, back to back
+    per_doc_docs = min(nd, 20000)
+    offs_h = offsets
+    torch.cuda.synchronize()
+    t0.record(stream)
+    for d in range(per_doc_docs):
+        a, b = int(offs_h[d]), int(offs_h[d + 1])
+        jx.build(bufs[a:b], out[a:], cnt[d:d + 1], err[d:d + 1], stream, length=b - a)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    per_doc_ms = t0.elapsed_time(t1)
+    return {"ms_per_launch": ms, "S": S, "N": total, "ndocs": nd,
+            "docs_per_s": nd / (ms / 1e3), "per_doc_launch_docs_per_s": per_doc_docs / (per_doc_ms / 1e3)}
+
+
+def cpu_baseline(host: bytes, budget_s: float = 10.0):
+    import oracle
+    oracle.index(host[: 1 << 20])  # load
+    reps = 0
+    t0 = time.perf_counter()
+    while True:
+        oracle.index(host)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or reps >= 50:
+            break
+    return {"value": len(host) * reps / el / 1e9, "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"whole document ({len(host)} bytes) indexed {reps}x by the byte-at-a-time C oracle "
+                      f"on one host core ({el:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-extra", action="store_true", help="skip the numeric and batched workloads")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--size-mib", type=int, default=256)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is "
+              "documented but not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1902_08318_amd as jx
+    from paper_1902_08318_amd import synth
+    assert torch.cuda.is_available(), "needs a HIP device"
+
+    log("generating C1 (twitter-like, minified)")
+    c1 = synth.gen_c1(1, args.size_mib << 20)
+    log(f"timing C1: {len(c1.data)} bytes, {args.steps} steps")
+    r1 = time_single(jx, torch, c1.data, args.steps, args.warmup)
+    value = r1["N"] * args.steps / (r1["ms_total"] / 1e3) / 1e9
+    alg_bytes = r1["N"] + 4 * r1["S"]
+    achieved = alg_bytes / (r1["ms_per_launch"] / 1e3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r1["ms_per_launch"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": "C1: one minified twitter-like JSON document, seed 1",
+                   "bytes": r1["N"], "index_entries": r1["S"], "bytes_per_entry": round(r1["N"] / max(1, r1["S"]), 2),
+                   "flags": r1["flags"]},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+    }
+    extra = {}
+    if not args.no_extra:
+        log("generating C2 (numeric, pretty-printed)")
+        c2 = synth.gen_c2(2, args.size_mib << 20)
+        r2 = time_single(jx, torch, c2.data, args.steps, args.warmup)
+        extra["C2"] = {"bytes": r2["N"], "index_entries": r2["S"], "input_GBps": round(r2["N"] / (r2["ms_per_launch"] / 1e3) / 1e9, 2),
+                       "alg_GBps": round((r2["N"] + 4 * r2["S"]) / (r2["ms_per_launch"] / 1e3) / 1e9, 1),
+                       "ms_per_launch": round(r2["ms_per_launch"], 4)}
+        del c2
+        log("generating C3 (100k-document batch)")
+        data, offs, kinds = synth.gen_c3(3)
+        r3 = time_batch(jx, torch, data, offs, max(3, args.steps // 2), 2)
+        extra["C3"] = {"bytes": r3["N"], "ndocs": r3["ndocs"], "index_entries": r3["S"],
+                       "input_GBps": round(r3["N"] / (r3["ms_per_launch"] / 1e3) / 1e9, 2),
+                       "alg_GBps": round((r3["N"] + 4 * r3["S"] + 16 * r3["ndocs"]) / (r3["ms_per_launch"] / 1e3) / 1e9, 1),
+                       "docs_per_s": round(r3["docs_per_s"]), "per_doc_launch_docs_per_s": round(r3["per_doc_launch_docs_per_s"]),
+                       "batched_vs_per_doc": round(r3["docs_per_s"] / r3["per_doc_launch_docs_per_s"], 1),
+                       "ms_per_launch": round(r3["ms_per_launch"], 4)}
+        del data
+    if extra:
+        out["extra"] = extra
+    if not args.no_cpu:
+        log("timing the CPU oracle")
+        out["cpu_baseline"] = cpu_baseline(c1.data)
+    else:
+        out["cpu_baseline"] = None
+    if r1["diag"]:
+        out["warning"] = "look-back diagnostic set"
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,139 @@
+/*
+ * jsidx.h -- C ABI of the MI355X (gfx950) stage-1 JSON structural indexer.
+ *
+ * Stage 1 of Langdale & Lemire, "Parsing Gigabytes of JSON per Second"
+ * (arXiv 1902.08318), Sec. 3.1: given the bytes of a JSON document, find the
+ * positions of every structural character (, : [ ] { }) outside strings,
+ * every opening quote, and every pseudo-structural byte (a byte outside
+ * strings that is neither white space nor structural nor a quote and follows
+ * a structural, white-space or quote byte; Sec. 3.1.3), in increasing order,
+ * as uint32 offsets (Sec. 3.1.4).  Quotes preceded by an odd-length run of
+ * backslashes are escaped (Sec. 3.1.1, Fig. 3); the string ranges are the
+ * inclusive prefix XOR of the unescaped quotes (Fig. 4); closing quotes are
+ * not indexed (last step of Fig. 5).  The input is also validated as UTF-8
+ * against the table of well-formed byte sequences of Sec. 3.1.5; the error
+ * is accumulated over the document and reported once (Sec. 3.1.5, last
+ * paragraph), it never changes the index.  The byte before a document counts
+ * as white space, so a scalar root value is indexed.
+ *
+ * All entry points are asynchronous on the HIP stream they are given; data
+ * pointers are DEVICE pointers owned by the caller.  The library never reads
+ * or writes host memory on behalf of a call.
+ *
+ * Input contract.  Document bytes are read-only and never modified.  The
+ * kernels load whole aligned 16-byte granules: a granule that holds at least
+ * one byte of the input may be read in full, including bytes just before the
+ * first or just after the last input byte (an aligned granule never crosses a
+ * page, so this never faults); such bytes never influence any result.
+ *
+ * Output contract.  The index and the flags are a total function of the bytes:
+ * both are produced for every document, valid JSON or not.  Flags are sound,
+ * not complete: a set bit proves the document is not valid JSON; zero flags
+ * do not prove it is (number, string and structure checks belong to stage 2).
+ */
+#ifndef JSIDX_H
+#define JSIDX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Opaque stream handle: a hipStream_t (0 = the legacy default stream). */
+typedef void *jsidx_stream_t;
+
+/* ---- status codes (API errors; nothing is launched when one is returned) */
+#define JSIDX_OK 0
+#define JSIDX_E_INVAL (-1)       /* NULL pointer, len >= 2^32, ndocs == 0   */
+#define JSIDX_E_NOWORKSPACE (-2) /* workspace could not be allocated          */
+#define JSIDX_E_HIP (-3)         /* a HIP runtime call failed                 */
+#define JSIDX_E_TOO_LARGE (-4)   /* input exceeds what the workspace can hold */
+
+/* ---- per-document flag bits written to out_err ---------------------------
+ * Document validity is NOT a status code: it is reported per document. */
+#define JSIDX_ERR_UTF8 0x1u            /* not well-formed UTF-8 (Sec. 3.1.5
+                                          table), including a multi-byte
+                                          sequence cut off by the end        */
+#define JSIDX_ERR_UNCLOSED_STRING 0x2u /* odd number of unescaped quotes:
+                                          the document ends inside a string  */
+#define JSIDX_ERR_TRAILING_ESCAPE 0x4u /* the document ends with an odd run
+                                          of backslashes                      */
+#define JSIDX_ERR_EMPTY 0x8u           /* the index is empty (empty or
+                                          all-white-space document)           */
+#define JSIDX_ERR_CAPACITY 0x80000000u /* not indexed: the batch is larger
+                                          than the stream's reserved
+                                          workspace (out_n is 0)              */
+
+/*
+ * jsidx_build -- index one document (Sec. 3.1).
+ *   buf      device pointer to `len` bytes (any alignment).
+ *   len      byte count, 0 <= len < 2^32 (positions are uint32, Sec. 3.1.4).
+ *   out_idx  device array of at least max(len, 1) uint32: receives the
+ *            positions in increasing order; entries past *out_n unspecified.
+ *   out_n    device uint32: number of positions written.
+ *   out_err  device uint32: JSIDX_ERR_* flags of the document.
+ *   stream   hipStream_t to run on.
+ * Returns JSIDX_OK or a negative JSIDX_E_* code (then nothing was launched).
+ * The first call on a stream may allocate the stream's workspace (see
+ * jsidx_reserve); later calls of a size the workspace covers allocate nothing.
+ */
+int jsidx_build(const uint8_t *buf, uint64_t len, uint32_t *out_idx,
+                uint32_t *out_n, uint32_t *out_err, jsidx_stream_t stream);
+
+/*
+ * jsidx_build_batch -- index many independent documents in one launch.
+ *   bufs     device pointer to the concatenated document bytes.
+ *   offsets  device array of ndocs+1 nondecreasing uint64: document d is
+ *            bufs[offsets[d] .. offsets[d+1]); offsets[0] may be nonzero;
+ *            each document must be shorter than 2^32 bytes.
+ *   ndocs    number of documents, >= 1.
+ *   out_idx  device array of at least max(offsets[ndocs], 1) uint32; document d
+ *            writes its positions (relative to its own first byte) to
+ *            out_idx[offsets[d] .. offsets[d] + out_n[d]).
+ *   out_n, out_err  device arrays of ndocs uint32 (count and flags per doc).
+ * Each document's results are identical to jsidx_build on that document.
+ * Offsets are read on the device.  If the stream has a workspace (from
+ * jsidx_reserve or an earlier call) the call never synchronises, and a batch
+ * larger than that workspace covers is not indexed: every out_err[d] is set to
+ * JSIDX_ERR_CAPACITY.  If the stream has no workspace yet, the call copies
+ * offsets[0] and offsets[ndocs] to the host (synchronising the stream) to size
+ * one.  Offsets that decrease give unspecified results for the affected
+ * documents (no fault, no out-of-range access).
+ */
+int jsidx_build_batch(const uint8_t *bufs, const uint64_t *offsets,
+                      uint32_t ndocs, uint32_t *out_idx, uint32_t *out_n,
+                      uint32_t *out_err, jsidx_stream_t stream);
+
+/*
+ * jsidx_reserve -- size the workspace of `stream` for inputs of up to
+ * max_total_len bytes in total (single document or batch).  Call it before
+ * capturing a HIP graph so that the captured calls allocate nothing.  The
+ * workspace (tile descriptors and counters, about 8 bytes per 16 KiB of input)
+ * is owned by the library, kept per stream until jsidx_release.
+ */
+int jsidx_reserve(uint64_t max_total_len, jsidx_stream_t stream);
+
+/* Bytes of workspace needed for max_total_len input bytes. */
+size_t jsidx_workspace_bytes(uint64_t max_total_len);
+
+/* Free the workspace of `stream` (synchronises the stream first). */
+int jsidx_release(jsidx_stream_t stream);
+
+/*
+ * jsidx_stream_diag -- synchronise `stream` and return in *out_flags the
+ * sticky diagnostic word of its workspace (0 = healthy; bit 0: a tile's wait
+ * for its predecessor's carry gave up after about half a second, so some
+ * results of that launch may be wrong -- never expected, it guards against a
+ * hang).  Clears the word.
+ */
+int jsidx_stream_diag(jsidx_stream_t stream, uint32_t *out_flags);
+
+/* Human-readable text for a status code. */
+const char *jsidx_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* JSIDX_H */

@@ -1,0 +1,12 @@
+"""jsidx: stage-1 JSON structural indexing on MI355X (gfx950).
+
+Stage 1 of Langdale & Lemire, "Parsing Gigabytes of JSON per Second"
+(Sec. 3.1): UTF-8 validation, escape and string-range resolution,
+structural / pseudo-structural classification and flattening into uint32
+positions, all in hand-written HIP kernels behind the C ABI of
+include/jsidx.h.  This package only marshals arguments to that library.
+"""
+from .binding import (  # noqa: F401
+    ERR_CAPACITY, ERR_EMPTY, ERR_TRAILING_ESCAPE, ERR_UNCLOSED_STRING, ERR_UTF8,
+    JsidxError, build, build_batch, diag, index, index_batch, library_path, release, reserve,
+)

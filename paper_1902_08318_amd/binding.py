@@ -1,0 +1,127 @@
+"""ctypes binding of libjsidx.so (argument marshalling only).
+
+Every entry point mirrors a function of include/jsidx.h.  Tensors must be
+device (HIP) tensors; PyTorch provides the memory and the stream.  There is no
+fallback: if the library is not built, importing the functions that need it
+raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+ERR_UTF8 = 0x1
+ERR_UNCLOSED_STRING = 0x2
+ERR_TRAILING_ESCAPE = 0x4
+ERR_EMPTY = 0x8
+ERR_CAPACITY = 0x80000000
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libjsidx.so")
+_lib = None
+
+# Every symbol include/jsidx.h declares, with its ctypes signature.
+_VP = ctypes.c_void_p
+SIGNATURES = {
+    "jsidx_build": ([_VP, ctypes.c_uint64, _VP, _VP, _VP, _VP], ctypes.c_int),
+    "jsidx_build_batch": ([_VP, _VP, ctypes.c_uint32, _VP, _VP, _VP, _VP], ctypes.c_int),
+    "jsidx_reserve": ([ctypes.c_uint64, _VP], ctypes.c_int),
+    "jsidx_workspace_bytes": ([ctypes.c_uint64], ctypes.c_size_t),
+    "jsidx_release": ([_VP], ctypes.c_int),
+    "jsidx_stream_diag": ([_VP, ctypes.POINTER(ctypes.c_uint32)], ctypes.c_int),
+    "jsidx_status_string": ([ctypes.c_int], ctypes.c_char_p),
+}
+
+
+class JsidxError(RuntimeError):
+    pass
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def lib():
+    """Load libjsidx.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise JsidxError(f"{_LIB_PATH} is missing: build it with paper_1902_08318_amd/build.py")
+        l = ctypes.CDLL(_LIB_PATH)
+        for name, (args, res) in SIGNATURES.items():
+            f = getattr(l, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = l
+    return _lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise JsidxError(f"jsidx error {rc}: {lib().jsidx_status_string(rc).decode()}")
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def build(buf, out_idx, out_n, out_err, stream=None, length=None):
+    """jsidx_build on device tensors (buf: uint8; outputs: int32/uint32)."""
+    n = buf.numel() if length is None else int(length)
+    _check(lib().jsidx_build(_ptr(buf), n, _ptr(out_idx), _ptr(out_n), _ptr(out_err), _stream(stream)))
+
+
+def build_batch(bufs, offsets, out_idx, out_n, out_err, stream=None):
+    """jsidx_build_batch on device tensors (offsets: int64, ndocs+1 entries)."""
+    nd = offsets.numel() - 1
+    _check(lib().jsidx_build_batch(_ptr(bufs), _ptr(offsets), nd, _ptr(out_idx), _ptr(out_n),
+                                   _ptr(out_err), _stream(stream)))
+
+
+def reserve(max_total_len: int, stream=None):
+    _check(lib().jsidx_reserve(int(max_total_len), _stream(stream)))
+
+
+def release(stream=None):
+    _check(lib().jsidx_release(_stream(stream)))
+
+
+def diag(stream=None) -> int:
+    v = ctypes.c_uint32(0)
+    _check(lib().jsidx_stream_diag(_stream(stream), ctypes.byref(v)))
+    return int(v.value)
+
+
+def index(buf, stream=None):
+    """Index one document held in a uint8 device tensor.
+
+    Returns (positions int32 tensor of length n, n, flags) -- synchronises.
+    """
+    import torch
+    dev = buf.device
+    out = torch.empty(max(1, buf.numel()), dtype=torch.int32, device=dev)
+    n = torch.empty(1, dtype=torch.int32, device=dev)
+    err = torch.empty(1, dtype=torch.int32, device=dev)
+    build(buf, out, n, err, stream)
+    nn = int(n.item())
+    return out[:nn], nn, int(err.item()) & 0xFFFFFFFF
+
+
+def index_batch(bufs, offsets, stream=None):
+    """Index a batch; returns (out_idx, out_n, out_err) device tensors."""
+    import torch
+    dev = bufs.device
+    total = int(offsets[-1].item())
+    nd = offsets.numel() - 1
+    out = torch.empty(max(1, total), dtype=torch.int32, device=dev)
+    n = torch.empty(nd, dtype=torch.int32, device=dev)
+    err = torch.empty(nd, dtype=torch.int32, device=dev)
+    build_batch(bufs, offsets, out, n, err, stream)
+    return out, n, err

@@ -1,0 +1,215 @@
+// jsidx.hip -- MI355X (gfx950) stage-1 JSON structural index (Langdale &
+// Lemire, "Parsing Gigabytes of JSON per Second", Sec. 3.1) behind the C ABI
+// of include/jsidx.h.
+//
+// One persistent launch indexes one document or a batch.  Work is cut into
+// tiles of kTileBytes of the concatenated input; a workgroup of 256 lanes
+// takes tiles in order from a ticket counter.  Inside a tile every lane owns
+// one 32-byte segment per row and builds 32-bit class masks for it (Sec.
+// 3.1.2); escapes (Fig. 3), string ranges (Fig. 4) and pseudo-structural
+// bytes (Fig. 5) are computed per segment, with the carries between segments
+// resolved by wave ballots and a small LDS scan, and the carries between tiles
+// by a decoupled look-back over per-tile descriptors (the paper's per-block
+// carries, elided in its footnote, become a scan).  Document starts reset all
+// carries, so a batch of documents is one segmented scan.  Set bits are
+// flattened into uint32 positions per document (Sec. 3.1.4): a popcount per
+// segment, a segmented prefix sum over the tile and the look-back gives each
+// bit its output slot.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <mutex>
+#include <vector>
+
+#include "jsidx.h"
+#include "jsidx_kernel.h"
+
+namespace jsidx {
+
+__global__ void __launch_bounds__(kThreads) index_kernel(Args a) { index_tiles(a); }
+
+// ---------------------------------------------------------------------------
+// host side
+struct StreamWs {
+  int device;
+  hipStream_t stream;
+  Workspace* ws;
+  uint64_t cap_tiles;
+};
+
+std::mutex g_mu;
+std::vector<StreamWs> g_ws;
+int g_slots[64];  // resident workgroups per device (0 = not queried)
+
+uint64_t tiles_for(uint64_t total_len) {
+  uint64_t t = (total_len + 15 + kTileBytes - 1) / kTileBytes;
+  return t ? t : 1;
+}
+
+size_t ws_bytes_for_tiles(uint64_t tiles) { return sizeof(Workspace) + (size_t)tiles * sizeof(uint64_t); }
+
+int slots_for_device(int dev) {
+  if (dev < 0 || dev >= 64) return 1024;
+  if (g_slots[dev]) return g_slots[dev];
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, index_kernel, kThreads, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+  hipDeviceProp_t prop;
+  int cus = 256;
+  if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
+  g_slots[dev] = per_cu * cus;
+  return g_slots[dev];
+}
+
+// Find or grow the workspace of (current device, stream).  Caller holds g_mu.
+int get_ws(hipStream_t stream, uint64_t need_tiles, bool grow, StreamWs** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return JSIDX_E_HIP;
+  for (auto& e : g_ws) {
+    if (e.device == dev && e.stream == stream) {
+      if (e.cap_tiles >= need_tiles || !grow) { *out = &e; return JSIDX_OK; }
+      if (hipStreamSynchronize(stream) != hipSuccess) return JSIDX_E_HIP;
+      (void)hipFree(e.ws);
+      e.ws = nullptr;
+      void* p = nullptr;
+      if (hipMalloc(&p, ws_bytes_for_tiles(need_tiles)) != hipSuccess) return JSIDX_E_NOWORKSPACE;
+      if (hipMemsetAsync(p, 0, ws_bytes_for_tiles(need_tiles), stream) != hipSuccess) return JSIDX_E_HIP;
+      if (hipStreamSynchronize(stream) != hipSuccess) return JSIDX_E_HIP;
+      e.ws = (Workspace*)p;
+      e.cap_tiles = need_tiles;
+      *out = &e;
+      return JSIDX_OK;
+    }
+  }
+  if (!grow) { *out = nullptr; return JSIDX_OK; }
+  void* p = nullptr;
+  if (hipMalloc(&p, ws_bytes_for_tiles(need_tiles)) != hipSuccess) return JSIDX_E_NOWORKSPACE;
+  if (hipMemsetAsync(p, 0, ws_bytes_for_tiles(need_tiles), stream) != hipSuccess) return JSIDX_E_HIP;
+  if (hipStreamSynchronize(stream) != hipSuccess) return JSIDX_E_HIP;
+  g_ws.push_back(StreamWs{dev, stream, (Workspace*)p, need_tiles});
+  *out = &g_ws.back();
+  return JSIDX_OK;
+}
+
+int launch(const Args& args, hipStream_t stream, uint64_t tiles_hint) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return JSIDX_E_HIP;
+  uint64_t slots = (uint64_t)slots_for_device(dev);
+  uint64_t grid = tiles_hint < slots ? tiles_hint : slots;
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL(index_kernel, dim3((uint32_t)grid), dim3(kThreads), 0, stream, args);
+  if (hipGetLastError() != hipSuccess) return JSIDX_E_HIP;
+  return JSIDX_OK;
+}
+
+}  // namespace jsidx
+
+using namespace jsidx;
+
+extern "C" {
+
+int jsidx_build(const uint8_t* buf, uint64_t len, uint32_t* out_idx, uint32_t* out_n, uint32_t* out_err,
+                jsidx_stream_t stream_) {
+  hipStream_t stream = (hipStream_t)stream_;
+  if (!out_idx || !out_n || !out_err || (!buf && len)) return JSIDX_E_INVAL;
+  if (len >= (1ull << 32)) return JSIDX_E_INVAL;
+  std::lock_guard<std::mutex> lk(g_mu);
+  StreamWs* e = nullptr;
+  uint64_t need = tiles_for(len);
+  int rc = get_ws(stream, need, true, &e);
+  if (rc) return rc;
+  Args a;
+  a.base = buf ? buf : reinterpret_cast<const uint8_t*>(out_idx);  // never read when len == 0
+  a.offsets = nullptr;
+  a.len = len;
+  a.ndocs = 1;
+  a.out_idx = out_idx;
+  a.out_n = out_n;
+  a.out_err = out_err;
+  a.ws = e->ws;
+  a.cap_tiles = e->cap_tiles;
+  return launch(a, stream, need);
+}
+
+int jsidx_build_batch(const uint8_t* bufs, const uint64_t* offsets, uint32_t ndocs, uint32_t* out_idx,
+                      uint32_t* out_n, uint32_t* out_err, jsidx_stream_t stream_) {
+  hipStream_t stream = (hipStream_t)stream_;
+  if (!bufs || !offsets || !out_idx || !out_n || !out_err || ndocs == 0) return JSIDX_E_INVAL;
+  std::lock_guard<std::mutex> lk(g_mu);
+  StreamWs* e = nullptr;
+  int rc = get_ws(stream, 0, false, &e);
+  if (rc) return rc;
+  if (!e) {
+    uint64_t ends[2];
+    if (hipMemcpyAsync(&ends[0], offsets, 8, hipMemcpyDeviceToHost, stream) != hipSuccess) return JSIDX_E_HIP;
+    if (hipMemcpyAsync(&ends[1], offsets + ndocs, 8, hipMemcpyDeviceToHost, stream) != hipSuccess) return JSIDX_E_HIP;
+    if (hipStreamSynchronize(stream) != hipSuccess) return JSIDX_E_HIP;
+    uint64_t total = ends[1] > ends[0] ? ends[1] - ends[0] : 0;
+    rc = get_ws(stream, tiles_for(total), true, &e);
+    if (rc) return rc;
+  }
+  Args a;
+  a.base = bufs;
+  a.offsets = offsets;
+  a.len = 0;
+  a.ndocs = ndocs;
+  a.out_idx = out_idx;
+  a.out_n = out_n;
+  a.out_err = out_err;
+  a.ws = e->ws;
+  a.cap_tiles = e->cap_tiles;
+  return launch(a, stream, e->cap_tiles);
+}
+
+int jsidx_reserve(uint64_t max_total_len, jsidx_stream_t stream_) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  StreamWs* e = nullptr;
+  return get_ws((hipStream_t)stream_, tiles_for(max_total_len), true, &e);
+}
+
+size_t jsidx_workspace_bytes(uint64_t max_total_len) { return ws_bytes_for_tiles(tiles_for(max_total_len)); }
+
+int jsidx_release(jsidx_stream_t stream_) {
+  hipStream_t stream = (hipStream_t)stream_;
+  std::lock_guard<std::mutex> lk(g_mu);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return JSIDX_E_HIP;
+  for (size_t i = 0; i < g_ws.size(); i++) {
+    if (g_ws[i].device == dev && g_ws[i].stream == stream) {
+      if (hipStreamSynchronize(stream) != hipSuccess) return JSIDX_E_HIP;
+      (void)hipFree(g_ws[i].ws);
+      g_ws.erase(g_ws.begin() + (long)i);
+      return JSIDX_OK;
+    }
+  }
+  return JSIDX_OK;
+}
+
+int jsidx_stream_diag(jsidx_stream_t stream_, uint32_t* out_flags) {
+  hipStream_t stream = (hipStream_t)stream_;
+  if (!out_flags) return JSIDX_E_INVAL;
+  std::lock_guard<std::mutex> lk(g_mu);
+  StreamWs* e = nullptr;
+  int rc = get_ws(stream, 0, false, &e);
+  if (rc) return rc;
+  *out_flags = 0;
+  if (!e) return JSIDX_OK;
+  if (hipStreamSynchronize(stream) != hipSuccess) return JSIDX_E_HIP;
+  uint32_t v = 0;
+  if (hipMemcpy(&v, &e->ws->diag, 4, hipMemcpyDeviceToHost) != hipSuccess) return JSIDX_E_HIP;
+  if (v && hipMemset(&e->ws->diag, 0, 4) != hipSuccess) return JSIDX_E_HIP;
+  *out_flags = v;
+  return JSIDX_OK;
+}
+
+const char* jsidx_status_string(int status) {
+  switch (status) {
+    case JSIDX_OK: return "ok";
+    case JSIDX_E_INVAL: return "invalid argument";
+    case JSIDX_E_NOWORKSPACE: return "workspace allocation failed";
+    case JSIDX_E_HIP: return "HIP runtime error";
+    case JSIDX_E_TOO_LARGE: return "input too large for the workspace";
+    default: return "unknown status";
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,58 @@
+// Hardware primitives used by the indexing kernel (gfx950 / wave64).
+//
+// The kernel is written against this small set of functions only, so every
+// instruction-level choice sits in one place: byte permutes (v_perm_b32),
+// 4x8-bit dot products (v_dot4_u32_u8), funnel byte shifts (v_alignbyte_b32),
+// wave ballots, lane shuffles, workgroup barriers and agent-scope atomics.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define JSIDX_DEV __device__ __forceinline__
+#define JSIDX_DEVFN __device__
+
+namespace jsidx {
+namespace prim {
+
+JSIDX_DEV uint32_t perm(uint32_t hi, uint32_t lo, uint32_t sel) { return __builtin_amdgcn_perm(hi, lo, sel); }
+JSIDX_DEV uint32_t udot4(uint32_t a, uint32_t b, uint32_t c) { return __builtin_amdgcn_udot4(a, b, c, false); }
+JSIDX_DEV uint32_t alignbyte(uint32_t hi, uint32_t lo, uint32_t s) { return __builtin_amdgcn_alignbyte(hi, lo, s); }
+
+JSIDX_DEV uint32_t tid() { return threadIdx.x; }
+JSIDX_DEV uint32_t block() { return blockIdx.x; }
+JSIDX_DEV uint32_t grid() { return gridDim.x; }
+JSIDX_DEV uint32_t lane() { return __lane_id(); }
+
+JSIDX_DEV uint64_t ballot(bool p) { return __ballot(p); }
+JSIDX_DEV uint32_t shfl(uint32_t v, int src) { return (uint32_t)__shfl((int)v, src); }
+JSIDX_DEV uint32_t shfl_up(uint32_t v, int d) { return (uint32_t)__shfl_up((int)v, d); }
+JSIDX_DEV uint32_t shfl_xor(uint32_t v, int m) { return (uint32_t)__shfl_xor((int)v, m); }
+
+JSIDX_DEV void sync() { __syncthreads(); }
+JSIDX_DEV int sync_count(bool p) { return __syncthreads_count(p); }
+JSIDX_DEV void sleep() { __builtin_amdgcn_s_sleep(1); }
+// Look-back waits give up after this many sleeps (about half a second).
+constexpr uint32_t kSpinLimit = 1u << 23;
+JSIDX_DEV void fence() { __threadfence(); }
+
+JSIDX_DEV uint64_t ld_agent(const uint64_t* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+JSIDX_DEV uint32_t ld_agent32(const uint32_t* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+JSIDX_DEV void st_agent(uint64_t* p, uint64_t v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+JSIDX_DEV void st_agent32(uint32_t* p, uint32_t v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+JSIDX_DEV uint32_t add_agent32(uint32_t* p, uint32_t v) { return atomicAdd(p, v); }
+JSIDX_DEV void min_lds(int32_t* p, int32_t v) { atomicMin(p, v); }
+
+// One instance per workgroup (LDS).
+template <class T>
+JSIDX_DEV T& lds_object() {
+  __shared__ T obj;
+  return obj;
+}
+
+JSIDX_DEV uint4 load16(const uint8_t* p) { return *reinterpret_cast<const uint4*>(p); }
+JSIDX_DEV uint32_t load4(const uint8_t* p) { return *reinterpret_cast<const uint32_t*>(p); }
+JSIDX_DEV uint64_t load8(const uint64_t* p) { return *p; }
+JSIDX_DEV void st_out(uint32_t* p, uint32_t v) { *p = v; }
+
+}  // namespace prim
+}  // namespace jsidx

@@ -1,0 +1,71 @@
+// Runs the indexing kernel body on the CPU through the emulated primitives --
+// TEST INFRASTRUCTURE ONLY (see jsidx_prims.h next to this file).
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <thread>
+#include <vector>
+
+#include "jsidx_kernel.h"
+
+namespace jsidx {
+namespace prim {
+thread_local ThreadCtx tctx;
+}
+}  // namespace jsidx
+
+using namespace jsidx;
+
+extern "C" {
+
+// Index through the kernel body with `nblocks` concurrent workgroups.
+//   granule_lo/hi: the bytes the kernel may read (the aligned 16-byte granules
+//   overlapping the input).  Returns the number of out-of-range accesses.
+//   ws_state: persistent workspace (caller allocated, zeroed once) so that
+//   several launches can reuse it like the real library does.
+long emu_run(const uint8_t* base, const uint64_t* offsets, uint64_t len, uint32_t ndocs, uint32_t* out_idx,
+             uint64_t out_cap, uint32_t* out_n, uint32_t* out_err, int nblocks, void* ws_mem, uint64_t cap_tiles,
+             const uint8_t* granule_lo, const uint8_t* granule_hi) {
+  prim::EmuEnv env;
+  env.reads[env.nreads++] = {granule_lo, granule_hi};
+  if (offsets) env.reads[env.nreads++] = {offsets, offsets + ndocs + 1};
+  env.writes[env.nwrites++] = {out_idx, out_idx + out_cap};
+  env.writes[env.nwrites++] = {out_n, out_n + ndocs};
+  env.writes[env.nwrites++] = {out_err, out_err + ndocs};
+
+  Args a;
+  a.base = base;
+  a.offsets = offsets;
+  a.len = len;
+  a.ndocs = ndocs;
+  a.out_idx = out_idx;
+  a.out_n = out_n;
+  a.out_err = out_err;
+  a.ws = (Workspace*)ws_mem;
+  a.cap_tiles = cap_tiles;
+
+  std::vector<prim::GroupCtx*> groups;
+  for (int b = 0; b < nblocks; b++) groups.push_back(new prim::GroupCtx());
+  std::vector<std::thread> th;
+  for (int b = 0; b < nblocks; b++) {
+    for (uint32_t t = 0; t < (uint32_t)kThreads; t++) {
+      th.emplace_back([&, b, t] {
+        prim::tctx.tid = t;
+        prim::tctx.block = (uint32_t)b;
+        prim::tctx.grid = (uint32_t)nblocks;
+        prim::tctx.g = groups[(size_t)b];
+        prim::tctx.env = &env;
+        index_tiles(a);
+      });
+    }
+  }
+  for (auto& x : th) x.join();
+  for (auto* g : groups) delete g;
+  return env.violations.load();
+}
+
+uint64_t emu_ws_bytes(uint64_t cap_tiles) { return sizeof(Workspace) + cap_tiles * sizeof(uint64_t); }
+uint32_t emu_tile_bytes() { return (uint32_t)kTileBytes; }
+
+}  // extern "C"

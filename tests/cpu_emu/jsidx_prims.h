@@ -1,0 +1,211 @@
+// CPU emulation of the kernel primitives -- TEST INFRASTRUCTURE ONLY.
+//
+// Lets the indexing kernel body (paper_1902_08318_amd/csrc/jsidx_kernel.h)
+// run unchanged on the host: every workgroup is 256 OS threads, every wave 64
+// of them; ballots and shuffles exchange values through a per-wave slot array
+// between two wave barriers; LDS is per-workgroup host memory.  The byte
+// permute, dot product and byte-align instructions are emulated from their ISA
+// definitions.  Every global load and store is bounds-checked against ranges
+// the harness registers, so an access the GPU would make out of range aborts
+// here instead.
+#pragma once
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <mutex>
+#include <thread>
+
+#define JSIDX_DEV inline
+#define JSIDX_DEVFN inline
+
+struct uint4 {
+  uint32_t x, y, z, w;
+};
+
+namespace jsidx {
+namespace prim {
+
+struct Barrier {
+  std::mutex m;
+  std::condition_variable cv;
+  int n;
+  int count = 0;
+  uint64_t gen = 0;
+  explicit Barrier(int n_) : n(n_) {}
+  void wait() {
+    std::unique_lock<std::mutex> lk(m);
+    uint64_t g = gen;
+    if (++count == n) {
+      count = 0;
+      gen++;
+      cv.notify_all();
+    } else {
+      cv.wait(lk, [&] { return gen != g; });
+    }
+  }
+};
+
+struct WaveCtx {
+  Barrier bar{64};
+  uint64_t slot[64];
+};
+
+struct GroupCtx {
+  Barrier bar{256};
+  WaveCtx waves[4];
+  std::atomic<int> count{0};
+  int count_result = 0;
+  alignas(64) unsigned char lds[1 << 16];
+};
+
+struct Range {
+  const void* lo;
+  const void* hi;
+};
+
+struct EmuEnv {
+  Range reads[4];
+  int nreads = 0;
+  Range writes[4];
+  int nwrites = 0;
+  std::atomic<long> violations{0};
+};
+
+struct ThreadCtx {
+  uint32_t tid, block, grid;
+  GroupCtx* g;
+  EmuEnv* env;
+};
+
+extern thread_local ThreadCtx tctx;
+
+inline void check(const void* p, size_t n, bool write) {
+  EmuEnv* e = tctx.env;
+  const Range* r = write ? e->writes : e->reads;
+  int nr = write ? e->nwrites : e->nreads;
+  const char* c = (const char*)p;
+  for (int i = 0; i < nr; i++)
+    if (c >= (const char*)r[i].lo && c + n <= (const char*)r[i].hi) return;
+  if (e->violations.fetch_add(1) < 5)
+    fprintf(stderr, "cpu_emu: out-of-range %s of %zu bytes at %p (block %u tid %u)\n", write ? "store" : "load", n, p,
+            tctx.block, tctx.tid);
+}
+
+inline uint32_t perm(uint32_t hi, uint32_t lo, uint32_t sel) {
+  uint64_t data = ((uint64_t)hi << 32) | lo;
+  uint32_t out = 0;
+  for (int k = 0; k < 4; k++) {
+    uint32_t s = (sel >> (8 * k)) & 0xFFu, b;
+    if (s >= 13) b = 0xFF;
+    else if (s == 12) b = 0;
+    else if (s >= 8) {
+      static const int src[4] = {1, 3, 5, 7};
+      b = ((data >> (8 * src[s - 8] + 7)) & 1) ? 0xFF : 0;
+    } else b = (uint32_t)(data >> (8 * s)) & 0xFFu;
+    out |= b << (8 * k);
+  }
+  return out;
+}
+inline uint32_t udot4(uint32_t a, uint32_t b, uint32_t c) {
+  uint32_t s = c;
+  for (int k = 0; k < 4; k++) s += ((a >> (8 * k)) & 0xFF) * ((b >> (8 * k)) & 0xFF);
+  return s;
+}
+inline uint32_t alignbyte(uint32_t hi, uint32_t lo, uint32_t s) {
+  return (uint32_t)((((uint64_t)hi << 32) | lo) >> (8 * (s & 3)));
+}
+
+inline uint32_t tid() { return tctx.tid; }
+inline uint32_t block() { return tctx.block; }
+inline uint32_t grid() { return tctx.grid; }
+inline uint32_t lane() { return tctx.tid & 63u; }
+
+inline WaveCtx& wave() { return tctx.g->waves[tctx.tid >> 6]; }
+inline uint64_t ballot(bool p) {
+  WaveCtx& w = wave();
+  w.slot[lane()] = p ? 1 : 0;
+  w.bar.wait();
+  uint64_t m = 0;
+  for (int i = 0; i < 64; i++) m |= (w.slot[i] ? 1ull : 0ull) << i;
+  w.bar.wait();
+  return m;
+}
+inline uint32_t exchange(uint32_t v, int src) {
+  WaveCtx& w = wave();
+  w.slot[lane()] = v;
+  w.bar.wait();
+  uint32_t r = (uint32_t)w.slot[src & 63];
+  w.bar.wait();
+  return r;
+}
+inline uint32_t shfl(uint32_t v, int src) { return exchange(v, src); }
+inline uint32_t shfl_up(uint32_t v, int d) {
+  int src = (int)lane() - d;
+  return exchange(v, src < 0 ? (int)lane() : src);
+}
+inline uint32_t shfl_xor(uint32_t v, int m) { return exchange(v, (int)(lane() ^ (uint32_t)m)); }
+
+inline void sync() { tctx.g->bar.wait(); }
+inline int sync_count(bool p) {
+  GroupCtx* g = tctx.g;
+  if (p) g->count.fetch_add(1);
+  g->bar.wait();
+  if (tctx.tid == 0) g->count_result = g->count.exchange(0);
+  g->bar.wait();
+  int r = g->count_result;
+  g->bar.wait();
+  return r;
+}
+inline void sleep() { std::this_thread::sleep_for(std::chrono::microseconds(20)); }
+constexpr uint32_t kSpinLimit = 1u << 20;  // ~20 s of emulated waiting
+inline void fence() { std::atomic_thread_fence(std::memory_order_seq_cst); }
+
+inline uint64_t ld_agent(const uint64_t* p) { return __atomic_load_n(p, __ATOMIC_RELAXED); }
+inline uint32_t ld_agent32(const uint32_t* p) { return __atomic_load_n(p, __ATOMIC_RELAXED); }
+inline void st_agent(uint64_t* p, uint64_t v) { __atomic_store_n(p, v, __ATOMIC_RELAXED); }
+inline void st_agent32(uint32_t* p, uint32_t v) { __atomic_store_n(p, v, __ATOMIC_RELAXED); }
+inline uint32_t add_agent32(uint32_t* p, uint32_t v) { return __atomic_fetch_add(p, v, __ATOMIC_RELAXED); }
+inline void min_lds(int32_t* p, int32_t v) {
+  int32_t cur = __atomic_load_n(p, __ATOMIC_RELAXED);
+  while (v < cur && !__atomic_compare_exchange_n(p, &cur, v, false, __ATOMIC_RELAXED, __ATOMIC_RELAXED)) {
+  }
+}
+
+template <class T>
+inline T& lds_object() {
+  static_assert(sizeof(T) <= sizeof(GroupCtx::lds), "LDS object too large");
+  return *reinterpret_cast<T*>(tctx.g->lds);
+}
+
+inline uint4 load16(const uint8_t* p) {
+  check(p, 16, false);
+  if ((uintptr_t)p & 15) {
+    fprintf(stderr, "cpu_emu: misaligned 16-byte load at %p\n", (const void*)p);
+    tctx.env->violations++;
+  }
+  uint4 v;
+  memcpy(&v, p, 16);
+  return v;
+}
+inline uint32_t load4(const uint8_t* p) {
+  check(p, 4, false);
+  uint32_t v;
+  memcpy(&v, p, 4);
+  return v;
+}
+inline uint64_t load8(const uint64_t* p) {
+  check(p, 8, false);
+  return *p;
+}
+inline void st_out(uint32_t* p, uint32_t v) {
+  check(p, 4, true);
+  *p = v;
+}
+
+}  // namespace prim
+}  // namespace jsidx

@@ -1,0 +1,111 @@
+"""Driver for the CPU emulation of the indexing kernel (test infrastructure).
+
+Builds tests/cpu_emu/harness.cpp together with the product kernel body and
+runs it through ctypes on host buffers laid out like device memory.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+SRC = os.path.join(HERE, "cpu_emu", "harness.cpp")
+OUT_DIR = os.path.join(HERE, "cpu_emu", "_build")
+LIB = os.path.join(OUT_DIR, "libjsidx_emu.so")
+_lib = None
+
+
+def _deps():
+    csrc = os.path.join(ROOT, "paper_1902_08318_amd", "csrc")
+    files = [SRC, os.path.join(HERE, "cpu_emu", "jsidx_prims.h"), os.path.join(ROOT, "include", "jsidx.h")]
+    files += [os.path.join(csrc, f) for f in os.listdir(csrc) if f.endswith(".h")]
+    return files
+
+
+def build() -> str:
+    os.makedirs(OUT_DIR, exist_ok=True)
+    subprocess.run(
+        ["g++", "-std=c++17", "-O1", "-g", "-shared", "-fPIC", "-pthread",
+         "-I", os.path.join(HERE, "cpu_emu"), "-I", os.path.join(ROOT, "include"),
+         "-I", os.path.join(ROOT, "paper_1902_08318_amd", "csrc"), "-o", LIB, SRC],
+        check=True)
+    return LIB
+
+
+def load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB) or any(os.path.getmtime(f) > os.path.getmtime(LIB) for f in _deps()):
+        build()
+    lib = ctypes.CDLL(LIB)
+    vp = ctypes.c_void_p
+    lib.emu_run.argtypes = [vp, vp, ctypes.c_uint64, ctypes.c_uint32, vp, ctypes.c_uint64, vp, vp,
+                            ctypes.c_int, vp, ctypes.c_uint64, vp, vp]
+    lib.emu_run.restype = ctypes.c_long
+    lib.emu_ws_bytes.argtypes = [ctypes.c_uint64]
+    lib.emu_ws_bytes.restype = ctypes.c_uint64
+    lib.emu_tile_bytes.restype = ctypes.c_uint32
+    _lib = lib
+    return lib
+
+
+def tile_bytes() -> int:
+    return int(load().emu_tile_bytes())
+
+
+class Workspace:
+    def __init__(self, cap_tiles: int):
+        self.cap = cap_tiles
+        self.mem = np.zeros(int(load().emu_ws_bytes(cap_tiles)) // 8 + 1, dtype=np.uint64)
+
+
+def _aligned(nbytes: int, shift: int) -> tuple[np.ndarray, int]:
+    """A zero-filled uint8 buffer whose element `shift` is 64-byte aligned + shift."""
+    raw = np.zeros(nbytes + 256, dtype=np.uint8)
+    addr = raw.ctypes.data
+    off = (-addr) % 64 + shift
+    return raw, off
+
+
+def run(data: bytes, offsets=None, nblocks: int = 2, misalign: int = 0, ws: Workspace | None = None,
+        garbage: int = 0xEE):
+    """Index `data` (one document if offsets is None, else a batch).
+
+    misalign: the buffer starts this many bytes past a 64-byte boundary.  The
+    bytes around the input inside its 16-byte granules are filled with
+    `garbage` so that any influence of them shows up.
+    Returns (out_idx, out_n, out_err, violations).
+    """
+    lib = load()
+    n = len(data)
+    raw, off = _aligned(n + 64, misalign + 16)
+    raw[:] = garbage
+    raw[off:off + n] = np.frombuffer(data, dtype=np.uint8)
+    base = raw.ctypes.data + off
+    if offsets is None:
+        begin, end = 0, n
+        offs = None
+        ndocs = 1
+    else:
+        offs = np.ascontiguousarray(offsets, dtype=np.uint64)
+        ndocs = offs.size - 1
+        begin, end = int(offs[0]), int(offs[-1])
+    glo = (base + begin) & ~15
+    ghi = ((base + end + 15) & ~15) if end > begin else glo
+    out_cap = max(end, 1)
+    out_idx = np.full(out_cap, 0xDEADBEEF, dtype=np.uint32)
+    out_n = np.full(ndocs, 0xDEADBEEF, dtype=np.uint32)
+    out_err = np.full(ndocs, 0xDEADBEEF, dtype=np.uint32)
+    tb = tile_bytes()
+    need = max(1, (end - begin + 15 + tb - 1) // tb)
+    if ws is None:
+        ws = Workspace(need)
+    v = lib.emu_run(ctypes.c_void_p(base), offs.ctypes.data if offs is not None else None, n, ndocs,
+                    out_idx.ctypes.data, out_cap, out_n.ctypes.data, out_err.ctypes.data, nblocks,
+                    ws.mem.ctypes.data, ws.cap, ctypes.c_void_p(glo), ctypes.c_void_p(ghi))
+    return out_idx, out_n, out_err, int(v)

@@ -1,0 +1,204 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle,
+bit-exact on index positions, counts and flags."""
+import itertools
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_common import assert_batch_matches, assert_single_matches, gpu_index_batch, gpu_index_single
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+TILE = 16384
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def test_library_loads_and_reports_healthy():
+    import paper_1902_08318_amd as jx
+    _say("case: library load")
+    assert os.path.exists(jx.library_path())
+    assert jx.diag() == 0
+
+
+def test_paper_examples():
+    rows = {}
+    for line in open(os.path.join(GOLDEN, "paper_fig3_5_rows.txt"), encoding="utf-8"):
+        if not line.startswith("#") and line.strip():
+            k, v = line.rstrip("\n").split("\t")
+            rows[k] = v
+    docs = [rows["INPUT"].encode(), open(os.path.join(GOLDEN, "paper_fig1_document.json"), "rb").read(),
+            b'{"key1":"val1", "key2":"val2"}', b'"[1,2]"', b"[12 a]", b"123", b" 1 ", b"",
+            b" \t\r\n", b"\\", b'"', b'["\\"",1]', b'["\\\\",1]', b'"\xe2\x82', b'["\xb1\x87"]']
+    for i, d in enumerate(docs):
+        _say(f"case: paper example {i} len {len(d)}")
+        for mis in (0, 1, 7, 15):
+            assert_single_matches(d, mis, f"example {i} misalign {mis}")
+
+
+def test_fig5_final_row_on_gpu():
+    rows = {}
+    for line in open(os.path.join(GOLDEN, "paper_fig3_5_rows.txt"), encoding="utf-8"):
+        if not line.startswith("#") and line.strip():
+            k, v = line.rstrip("\n").split("\t")
+            rows[k] = v
+    idx, n, err = gpu_index_single(rows["INPUT"].encode())
+    want = [i for i, c in enumerate(rows["FINAL.fig5"]) if c == "1"]
+    assert list(idx) == want and err == 0
+
+
+ALPHABET = [0x22, 0x5C, 0x5B, 0x3A, 0x2C, 0x61, 0x20, 0xC3, 0xA9]
+
+
+def test_brute_force_all_short_strings_as_batch():
+    """Every string of length 0..6 over {quote, backslash, bracket, colon,
+    comma, letter, space, 0xC3, 0xA9}, one document each, in one batch."""
+    alpha = np.array(ALPHABET, dtype=np.uint8)
+    parts, lens = [], []
+    for L in range(0, 7):
+        grid = np.array(list(itertools.product(range(len(alpha)), repeat=L)), dtype=np.int64).reshape(-1, L)
+        X = alpha[grid] if L else np.zeros((1, 0), dtype=np.uint8)
+        parts.append(X.reshape(-1))
+        lens.append(np.full(X.shape[0], L, dtype=np.uint64))
+    data = np.concatenate(parts)
+    lens = np.concatenate(lens)
+    offs = np.zeros(lens.size + 1, dtype=np.uint64)
+    np.cumsum(lens, out=offs[1:])
+    _say(f"case: brute force batch ndocs {lens.size} bytes {data.size}")
+    assert_batch_matches(data, offs, 0, "brute force")
+    assert_batch_matches(data, offs, 5, "brute force lead 5")
+
+
+def _soup(rng, n, alpha=b'"\\[]{},: \tax1\xc3\xa9\xe2\x82\xac\xf0\x9f\x98\x80\n'):
+    a = np.frombuffer(alpha, dtype=np.uint8)
+    return a[rng.integers(0, a.size, n)].tobytes()
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_random_single_documents(seed):
+    rng = np.random.default_rng(100 + seed)
+    for k in range(12):
+        n = int(rng.integers(0, 6 * TILE))
+        d = _soup(rng, n)
+        mis = int(rng.integers(0, 16))
+        _say(f"case: random single seed {seed} k {k} len {n} misalign {mis}")
+        assert_single_matches(d, mis, f"seed {seed} k {k}")
+
+
+def test_backslash_runs_across_tiles():
+    """Backslash runs of every length class ending at and around tile and
+    segment boundaries, followed by a quote or a letter."""
+    rng = np.random.default_rng(5)
+    for run in [1, 2, 3, 31, 32, 33, 63, 64, 65, TILE - 1, TILE, TILE + 1, 2 * TILE + 3, 3 * TILE]:
+        for start in [0, 1, 31, 32, TILE - run % TILE if run % TILE else 5, TILE - 1, TILE - 2]:
+            for nxt in (b'"', b"a", b"\\"):
+                d = b'["' + b"x" * start + b"\\" * run + nxt + b'",1] "' + _soup(rng, 100)
+                _say(f"case: bs run {run} start {start} next {nxt!r}")
+                assert_single_matches(d, 0, f"run {run} start {start}")
+
+
+def test_quote_at_tile_edges_and_split_utf8():
+    for off in range(-3, 4):
+        base = b"a" * (TILE + off)
+        for tail in (b'"x"', b'\\"x"', b"\xf0\x9f\x98\x80", b"\xe2\x82\xac", b"\xc3\xa9", b"\xf0\x9f\x98",
+                     b"]", b" 1"):
+            d = b'["' + base + b'", ' + tail + b' "z" ' + tail
+            _say(f"case: tile edge off {off} tail {tail!r}")
+            assert_single_matches(d, 0, f"edge {off} {tail!r}")
+            assert_single_matches(d, 3, f"edge {off} {tail!r} mis3")
+
+
+def test_dense_index_and_whitespace():
+    for n in (1, 63, 64, 65, TILE - 1, TILE, TILE + 1, 3 * TILE + 7):
+        _say(f"case: dense n {n}")
+        assert_single_matches(b"[" * n, 0, f"dense {n}")
+        assert_single_matches(b" " * n, 0, f"ws {n}")
+        assert_single_matches(b"1," * n, 1, f"atoms {n}")
+
+
+def test_generated_c0_and_corruptions():
+    from paper_1902_08318_amd import synth
+    for seed in range(5):
+        doc = synth.gen_c0(seed, 1 << 20)
+        _say(f"case: C0 seed {seed} len {len(doc.data)}")
+        assert_single_matches(doc.data, seed, f"C0 seed {seed}")
+        rng = np.random.default_rng(seed)
+        for kind in (1, 2, 3):
+            bad = synth.corrupt(doc.data, kind, rng)
+            assert_single_matches(bad, 0, f"C0 seed {seed} corrupt {kind}")
+
+
+def test_batch_mixed_sizes_including_empty():
+    rng = np.random.default_rng(11)
+    for trial in range(6):
+        docs = []
+        for _ in range(int(rng.integers(1, 400))):
+            r = rng.random()
+            L = 0 if r < 0.15 else (1 if r < 0.25 else int(rng.integers(2, 3000 if r < 0.95 else 3 * TILE)))
+            docs.append(_soup(rng, L))
+        lens = np.array([len(d) for d in docs], dtype=np.uint64)
+        offs = np.zeros(len(docs) + 1, dtype=np.uint64)
+        np.cumsum(lens, out=offs[1:])
+        lead = int(rng.integers(0, 40))
+        _say(f"case: batch trial {trial} ndocs {len(docs)} bytes {int(offs[-1])} lead {lead}")
+        assert_batch_matches(b"".join(docs), offs, lead, f"batch {trial}")
+
+
+def test_many_empty_documents_in_one_tile():
+    # more documents in one tile than the per-tile table holds
+    docs = [b""] * 3000 + [b"[1]"] + [b""] * 2000 + [b'"a"'] * 1500 + [b""] * 10
+    lens = np.array([len(d) for d in docs], dtype=np.uint64)
+    offs = np.zeros(len(docs) + 1, dtype=np.uint64)
+    np.cumsum(lens, out=offs[1:])
+    _say(f"case: many empty docs {len(docs)}")
+    assert_batch_matches(b"".join(docs), offs, 3, "many empty")
+
+
+def test_batch_equals_single_calls():
+    from paper_1902_08318_amd import synth
+    data, offs, kinds = synth.gen_c3(3, ndocs=300, pool=60)
+    gi, gn, ge = gpu_index_batch(data, offs)
+    for d in range(0, 300, 7):
+        a, b = int(offs[d]), int(offs[d + 1])
+        si, sn, se = gpu_index_single(data[a:b])
+        assert sn == gn[d] and se == ge[d]
+        assert np.array_equal(si, gi[a:a + sn])
+        if kinds[d]:
+            assert se != 0
+
+
+def test_repeated_launches_reuse_workspace():
+    """Many launches of varying size on one stream: the per-launch epoch and
+    the descriptor scrub must keep every launch independent."""
+    import paper_1902_08318_amd as jx
+    rng = np.random.default_rng(21)
+    for k in range(60):
+        n = int(rng.integers(0, 8 * TILE)) if k % 5 else int(rng.integers(20 * TILE, 40 * TILE))
+        d = _soup(rng, n)
+        if k % 10 == 0:
+            _say(f"case: repeated launch {k} len {n}")
+        assert_single_matches(d, k % 16, f"launch {k}")
+    assert jx.diag() == 0
+
+
+def test_generated_c1_c2_full_size():
+    from paper_1902_08318_amd import synth
+    for name, doc in (("C1", synth.gen_c1(1)), ("C2", synth.gen_c2(2))):
+        _say(f"case: {name} full size {len(doc.data)}")
+        assert_single_matches(doc.data, 0, name)
+
+
+def test_generated_c3_full_batch():
+    from paper_1902_08318_amd import synth
+    data, offs, kinds = synth.gen_c3(3)
+    _say(f"case: C3 full batch ndocs {offs.size - 1} bytes {len(data)}")
+    assert_batch_matches(data, offs, 0, "C3")
+    _, _, oe = oracle.index_batch(np.frombuffer(data, dtype=np.uint8), offs)
+    assert np.all((oe[kinds > 0] & 0x7) != 0)

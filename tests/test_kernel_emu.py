@@ -1,0 +1,65 @@
+"""The kernel body of the HIP library, run on the CPU through emulated
+primitives (tests/cpu_emu), against the oracle.  Catches logic and
+out-of-range accesses without a GPU; the GPU tests remain the parity proof."""
+import numpy as np
+import pytest
+
+import emu
+import oracle
+
+TB = emu.tile_bytes()
+
+
+def _check_single(d, nblocks, misalign):
+    idx, n, err, viol = emu.run(d, nblocks=nblocks, misalign=misalign)
+    oi, oe = oracle.index(d)
+    assert viol == 0
+    assert n[0] == len(oi) and err[0] == oe
+    assert np.array_equal(idx[:n[0]], oi)
+
+
+def _check_batch(docs, nblocks, misalign, lead):
+    data = b"\x00" * lead + b"".join(docs)
+    offs = np.concatenate([[lead], lead + np.cumsum([len(x) for x in docs])]).astype(np.uint64)
+    idx, n, err, viol = emu.run(data, offsets=offs, nblocks=nblocks, misalign=misalign)
+    oi, on, oe = oracle.index_batch(np.frombuffer(data, dtype=np.uint8), offs)
+    assert viol == 0
+    assert np.array_equal(n, on) and np.array_equal(err, oe)
+    for d in range(len(docs)):
+        a = int(offs[d])
+        assert np.array_equal(idx[a:a + n[d]], oi[a:a + on[d]]), d
+
+
+def _soup(rng, n):
+    a = np.frombuffer(b'"\\[]{},: \tax1\xc3\xa9\xe2\x82\xac\xf0\x9f\x98\x80', dtype=np.uint8)
+    return a[rng.integers(0, a.size, n)].tobytes()
+
+
+def test_small_documents():
+    for d in (b"", b"1", b'{"a":1}', b"\\", b'"', b" ", b"[12 a]", b'"\xe2\x82'):
+        _check_single(d, 1, 3)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_random_multi_tile_documents(seed):
+    rng = np.random.default_rng(seed)
+    for _ in range(3):
+        _check_single(_soup(rng, int(rng.integers(TB, 3 * TB))), int(rng.integers(1, 4)), int(rng.integers(0, 16)))
+
+
+def test_backslash_runs_spanning_tiles():
+    for run, nxt in ((TB, b'"'), (TB + 1, b'"'), (2 * TB + 5, b"a"), (TB - 3, b'"')):
+        for start in (0, 7, TB - 2):
+            d = b'["' + b"x" * start + b"\\" * run + nxt + b'",1] "z" [1]'
+            _check_single(d, 3, 0)
+
+
+def test_batches_with_empty_and_tiny_documents():
+    rng = np.random.default_rng(4)
+    for trial in range(3):
+        docs = []
+        for _ in range(int(rng.integers(1, 50))):
+            r = rng.random()
+            L = 0 if r < 0.15 else (1 if r < 0.25 else int(rng.integers(2, 3000 if r < 0.9 else 2 * TB)))
+            docs.append(_soup(rng, L))
+        _check_batch(docs, int(rng.integers(1, 4)), int(rng.integers(0, 16)), int(rng.integers(0, 40)))

@@ -42,9 +42,18 @@ def library_path() -> str:
 
 
 def lib():
-    """Load libjsidx.so (raises if it has not been built)."""
+    """Load libjsidx.so (raises if it has not been built).
+
+    PyTorch is imported first: its wheel carries its own HIP runtime
+    (SONAME libamdhip64.so.7, loaded under the file name libamdhip64.so).  Once
+    that runtime is in the process, the loader resolves this library's
+    dependency on libamdhip64.so.7 to it by SONAME, so device pointers and
+    streams from PyTorch are used by the same runtime instance.  Loading this
+    library first would bring in a second runtime from /opt/rocm.
+    """
     global _lib
     if _lib is None:
+        import torch  # noqa: F401  (see above)
         if not os.path.exists(_LIB_PATH):
             raise JsidxError(f"{_LIB_PATH} is missing: build it with paper_1902_08318_amd/build.py")
         l = ctypes.CDLL(_LIB_PATH)

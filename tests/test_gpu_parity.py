@@ -62,9 +62,11 @@ def test_brute_force_all_short_strings_as_batch():
     comma, letter, space, 0xC3, 0xA9}, one document each, in one batch."""
     alpha = np.array(ALPHABET, dtype=np.uint8)
     parts, lens = [], []
-    for L in range(0, 7):
-        grid = np.array(list(itertools.product(range(len(alpha)), repeat=L)), dtype=np.int64).reshape(-1, L)
-        X = alpha[grid] if L else np.zeros((1, 0), dtype=np.uint8)
+    parts.append(np.zeros(0, dtype=np.uint8))
+    lens.append(np.zeros(1, dtype=np.uint64))  # the empty string
+    for L in range(1, 7):
+        grid = np.array(list(itertools.product(range(len(alpha)), repeat=L)), dtype=np.int64)
+        X = alpha[grid]
         parts.append(X.reshape(-1))
         lens.append(np.full(X.shape[0], L, dtype=np.uint64))
     data = np.concatenate(parts)

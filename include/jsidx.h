@@ -94,13 +94,13 @@ int jsidx_build(const uint8_t *buf, uint64_t len, uint32_t *out_idx,
  *            out_idx[offsets[d] .. offsets[d] + out_n[d]).
  *   out_n, out_err  device arrays of ndocs uint32 (count and flags per doc).
  * Each document's results are identical to jsidx_build on that document.
- * Offsets are read on the device.  If the stream has a workspace (from
- * jsidx_reserve or an earlier call) the call never synchronises, and a batch
- * larger than that workspace covers is not indexed: every out_err[d] is set to
- * JSIDX_ERR_CAPACITY.  If the stream has no workspace yet, the call copies
- * offsets[0] and offsets[ndocs] to the host (synchronising the stream) to size
- * one.  Offsets that decrease give unspecified results for the affected
- * documents (no fault, no out-of-range access).
+ * Offsets are read on the device.  After jsidx_reserve on the stream, the
+ * call never synchronises and never allocates, and a batch larger than the
+ * reserved size is not indexed: every out_err[d] is set to JSIDX_ERR_CAPACITY
+ * and out_n[d] to 0.  Without a reservation the call copies offsets[0] and
+ * offsets[ndocs] to the host (synchronising the stream) and grows the stream's
+ * workspace if needed.  Offsets that decrease give unspecified results for the
+ * affected documents (no fault, no out-of-range access).
  */
 int jsidx_build_batch(const uint8_t *bufs, const uint64_t *offsets,
                       uint32_t ndocs, uint32_t *out_idx, uint32_t *out_n,
@@ -108,8 +108,10 @@ int jsidx_build_batch(const uint8_t *bufs, const uint64_t *offsets,
 
 /*
  * jsidx_reserve -- size the workspace of `stream` for inputs of up to
- * max_total_len bytes in total (single document or batch).  Call it before
- * capturing a HIP graph so that the captured calls allocate nothing.  The
+ * max_total_len bytes in total (single document or batch) and switch batch
+ * calls on that stream to the no-synchronisation mode described above.  Call
+ * it before capturing a HIP graph so that the captured calls allocate nothing
+ * (a later jsidx_build larger than the reservation still grows it).  The
  * workspace (tile descriptors and counters, about 8 bytes per 16 KiB of input)
  * is owned by the library, kept per stream until jsidx_release.
  */

@@ -35,6 +35,7 @@ struct StreamWs {
   hipStream_t stream;
   Workspace* ws;
   uint64_t cap_tiles;
+  bool reserved;  // sized by jsidx_reserve: batch calls trust it and never sync
 };
 
 std::mutex g_mu;
@@ -85,7 +86,7 @@ int get_ws(hipStream_t stream, uint64_t need_tiles, bool grow, StreamWs** out) {
   if (hipMalloc(&p, ws_bytes_for_tiles(need_tiles)) != hipSuccess) return JSIDX_E_NOWORKSPACE;
   if (hipMemsetAsync(p, 0, ws_bytes_for_tiles(need_tiles), stream) != hipSuccess) return JSIDX_E_HIP;
   if (hipStreamSynchronize(stream) != hipSuccess) return JSIDX_E_HIP;
-  g_ws.push_back(StreamWs{dev, stream, (Workspace*)p, need_tiles});
+  g_ws.push_back(StreamWs{dev, stream, (Workspace*)p, need_tiles, false});
   *out = &g_ws.back();
   return JSIDX_OK;
 }
@@ -138,7 +139,7 @@ int jsidx_build_batch(const uint8_t* bufs, const uint64_t* offsets, uint32_t ndo
   StreamWs* e = nullptr;
   int rc = get_ws(stream, 0, false, &e);
   if (rc) return rc;
-  if (!e) {
+  if (!e || !e->reserved) {
     uint64_t ends[2];
     if (hipMemcpyAsync(&ends[0], offsets, 8, hipMemcpyDeviceToHost, stream) != hipSuccess) return JSIDX_E_HIP;
     if (hipMemcpyAsync(&ends[1], offsets + ndocs, 8, hipMemcpyDeviceToHost, stream) != hipSuccess) return JSIDX_E_HIP;
@@ -163,7 +164,9 @@ int jsidx_build_batch(const uint8_t* bufs, const uint64_t* offsets, uint32_t ndo
 int jsidx_reserve(uint64_t max_total_len, jsidx_stream_t stream_) {
   std::lock_guard<std::mutex> lk(g_mu);
   StreamWs* e = nullptr;
-  return get_ws((hipStream_t)stream_, tiles_for(max_total_len), true, &e);
+  int rc = get_ws((hipStream_t)stream_, tiles_for(max_total_len), true, &e);
+  if (rc == JSIDX_OK) e->reserved = true;
+  return rc;
 }
 
 size_t jsidx_workspace_bytes(uint64_t max_total_len) { return ws_bytes_for_tiles(tiles_for(max_total_len)); }

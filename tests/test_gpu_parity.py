@@ -204,3 +204,31 @@ def test_generated_c3_full_batch():
     assert_batch_matches(data, offs, 0, "C3")
     _, _, oe = oracle.index_batch(np.frombuffer(data, dtype=np.uint8), offs)
     assert np.all((oe[kinds > 0] & 0x7) != 0)
+
+
+def test_reserved_capacity_is_enforced_without_sync():
+    """After jsidx_reserve, a batch larger than the reservation is flagged
+    JSIDX_ERR_CAPACITY for every document (and nothing else is written)."""
+    import torch
+    import paper_1902_08318_amd as jx
+    _say("case: reserved capacity")
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        jx.reserve(1000, s)
+        docs = [b'{"a":[1,2,3]}'] * 5000
+        data = b"".join(docs)
+        offs = np.arange(len(docs) + 1, dtype=np.int64) * len(docs[0])
+        bufs = torch.frombuffer(bytearray(data), dtype=torch.uint8).to("cuda:0")
+        toffs = torch.from_numpy(offs).to("cuda:0")
+        out = torch.zeros(len(data), dtype=torch.int32, device="cuda:0")
+        n = torch.full((len(docs),), 7, dtype=torch.int32, device="cuda:0")
+        err = torch.zeros(len(docs), dtype=torch.int32, device="cuda:0")
+        jx.build_batch(bufs, toffs, out, n, err, s)
+        s.synchronize()
+        assert torch.all(n == 0).item()
+        assert torch.all(err == jx.ERR_CAPACITY).item()
+        jx.reserve(len(data), s)
+        jx.build_batch(bufs, toffs, out, n, err, s)
+        s.synchronize()
+        assert torch.all(n == 5).item() and torch.all(err == 0).item()
+        jx.release(s)

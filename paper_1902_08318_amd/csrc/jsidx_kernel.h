@@ -216,6 +216,7 @@ JSIDX_DEVFN void index_tiles(const Args& a) {
     prim::sync();
     const int64_t t = sh.tile;
     if (t >= ntiles) break;
+    prim::trace(t, 0);
     const int64_t P0 = pos_g0 + t * kTileBytes;  // position of tile byte 0
     const int64_t Pend = P0 + kTileBytes;
 
@@ -280,6 +281,7 @@ JSIDX_DEVFN void index_tiles(const Args& a) {
     }
     prim::sync();
 
+    prim::trace(t, 1);
     // ---- phase 1: load, classify, local scans -------------------------------
     Seg sg[kRows];
 #pragma unroll
@@ -381,6 +383,7 @@ JSIDX_DEVFN void index_tiles(const Args& a) {
       }
     }
 
+    prim::trace(t, 2);
     // ---- escape scan -----------------------------------------------------
     // A segment with a non-backslash byte or a document start fixes the escape
     // state after it; an all-backslash segment (32 bytes, even) passes it on.
@@ -525,6 +528,7 @@ JSIDX_DEVFN void index_tiles(const Args& a) {
       }
     }
 
+    prim::trace(t, 3);
     // ---- phase 2: carry-in state by look-back --------------------------------
     if (wave == 0) {
       uint32_t s_in = 0;
@@ -565,6 +569,7 @@ JSIDX_DEVFN void index_tiles(const Args& a) {
             acc = has_acc ? tab_compose(comp, acc) : comp;
             has_acc = true;
           }
+          prim::trace_count(t, 8);
           if (inc) {
             uint32_t st = prim::shfl(pay, lim) & 0xFu;
             s_in = has_acc ? tab_apply(acc, st) : st;
@@ -577,6 +582,7 @@ JSIDX_DEVFN void index_tiles(const Args& a) {
       if (lane == 0) sh.state_in = s_in;
     }
     prim::sync();
+    prim::trace(t, 4);
     const uint32_t s_in = sh.state_in;
     const uint32_t eT = s_in & 1u, qT = (s_in >> 1) & 1u, pT = (s_in >> 2) & 1u, uT = (s_in >> 3) & 1u;
 
@@ -654,6 +660,7 @@ JSIDX_DEVFN void index_tiles(const Args& a) {
       tile_count = c;
     }
 
+    prim::trace(t, 5);
     // ---- phase 4: output base by look-back ------------------------------------
     if (wave == 0) {
       uint32_t base = 0;
@@ -685,6 +692,7 @@ JSIDX_DEVFN void index_tiles(const Args& a) {
 #pragma unroll
           for (int o = 32; o >= 1; o >>= 1) v += prim::shfl_xor(v, o);
           base += v;
+          prim::trace_count(t, 9);
           if (stop || jhi < 64) break;
           jhi -= 64;
         }
@@ -696,6 +704,7 @@ JSIDX_DEVFN void index_tiles(const Args& a) {
       if (lane == 0) sh.base = base;
     }
     prim::sync();
+    prim::trace(t, 6);
     const uint32_t base = sh.base;
 
     // ---- phase 5: positions and per-document results ---------------------------
@@ -751,6 +760,7 @@ JSIDX_DEVFN void index_tiles(const Args& a) {
       }
     }
     prim::sync();
+    prim::trace(t, 7);
   }
 
 finish:

@@ -49,6 +49,10 @@ JSIDX_DEV T& lds_object() {
   return obj;
 }
 
+// Timing hooks for probe builds (no-ops in the library).
+JSIDX_DEV void trace(int64_t, int) {}
+JSIDX_DEV void trace_count(int64_t, int) {}
+
 JSIDX_DEV uint4 load16(const uint8_t* p) { return *reinterpret_cast<const uint4*>(p); }
 JSIDX_DEV uint32_t load4(const uint8_t* p) { return *reinterpret_cast<const uint32_t*>(p); }
 JSIDX_DEV uint64_t load8(const uint64_t* p) { return *p; }

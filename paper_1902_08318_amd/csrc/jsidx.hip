@@ -26,7 +26,10 @@
 
 namespace jsidx {
 
-__global__ void __launch_bounds__(kThreads) index_kernel(Args a) { index_tiles(a); }
+// Four waves per SIMD: 128 VGPRs, enough to keep two rows of input in flight per wave.
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) index_kernel(Args a) {
+  index_tiles(a);
+}
 
 // ---------------------------------------------------------------------------
 // host side

@@ -1,5 +1,20 @@
 // jsidx_kernel.h -- the stage-1 indexing kernel body (see jsidx.hip for the
 // design summary).  Written against the primitives of jsidx_prims.h only.
+//
+// One wave is one workgroup and owns one tile of kTileBytes at a time: kRows
+// rows of 64 lanes x 32 bytes, processed one row after the other.  All carries
+// inside a tile (escape, in-string, predecessor, UTF-8 error, counts) move
+// between lanes by wave ballots and between rows in scalar registers, so a
+// tile needs no workgroup barrier.  Carries between tiles use a single
+// decoupled look-back per tile.  Because a tile's result depends on whether it
+// starts inside a string, each tile keeps two masks per row: K, the bytes that
+// are candidates (structural, quote, or a pseudo-structural candidate), and
+// F0, the indexed bytes assuming the tile does not start inside a string.  If
+// it does, the indexed bytes of the region before the tile's first document
+// start are F0 ^ K (every candidate flips: Sec. 3.1.3's formulas are symmetric
+// in R), so the look-back only has to deliver the incoming state.  Bytes at or
+// after the first document start never depend on the incoming state; they are
+// written during the local pass, before the look-back.
 #pragma once
 #include <stdint.h>
 
@@ -8,20 +23,25 @@
 
 namespace jsidx {
 
-constexpr int kThreads = 256;
-constexpr int kWaves = kThreads / 64;
+constexpr int kThreads = 64;  // one wave per workgroup
 constexpr int kSegBytes = 32;
-constexpr int kRowBytes = kThreads * kSegBytes;  // 8 KiB
-constexpr int kRows = 2;
+constexpr int kRowBytes = kThreads * kSegBytes;  // 2 KiB
+constexpr int kRows = 8;
 constexpr int kTileBytes = kRows * kRowBytes;  // 16 KiB
-constexpr int kDocCap = 1024;                  // documents per tile held in LDS
+constexpr int kDocCap = 256;                   // documents per tile held in LDS
 constexpr int kScrub = 4096;                   // descriptors cleared per launch
+static_assert(kTileBytes < 32768, "tile counts must fit in 15 bits");
 
-// ---- tile descriptors for the look-back -----------------------------------
-// bits 0..2 flag, 3..10 payload, 11..42 count, 43..63 launch epoch (21 bits).
-enum : uint32_t { kNone = 0, kStateAgg = 1, kStateInc = 2, kCountAgg = 3, kCountInc = 4 };
-constexpr uint32_t kEpochBits = 21;
-constexpr uint32_t kEpochMask = (1u << kEpochBits) - 1u;
+// ---- tile descriptors for the look-back ----------------------------------
+// bits 0..1 flag, 2..41 payload, 42..63 launch epoch.
+//   aggregate: 2..9 transfer table, 10..24 count if the tile starts outside a
+//              string, 25..39 count if inside, 40 byte 0 is a pseudo-structural
+//              candidate, 41 the tile's counts depend on the incoming escape
+//   inclusive: 2..5 state after the tile, 6 a document starts in the tile,
+//              7..38 count of the current document up to the tile's end
+enum : uint32_t { kNone = 0, kAgg = 1, kInc = 2 };
+constexpr uint32_t kEpochShift = 42;
+constexpr uint64_t kEpochMask = (1ull << 22) - 1;
 
 struct Workspace {
   uint32_t ticket;  // next tile to hand out
@@ -31,21 +51,29 @@ struct Workspace {
   uint64_t desc[1];  // one per tile
 };
 
-JSIDX_DEV uint64_t make_desc(uint32_t flag, uint32_t payload, uint32_t count, uint32_t epoch) {
-  return (uint64_t)flag | ((uint64_t)(payload & 0xFFu) << 3) | ((uint64_t)count << 11) |
-         ((uint64_t)(epoch & kEpochMask) << 43);
+JSIDX_DEV uint64_t epoch_bits(uint32_t epoch) { return ((uint64_t)epoch & kEpochMask) << kEpochShift; }
+JSIDX_DEV uint64_t make_agg(uint32_t table, uint32_t c0, uint32_t c1, uint32_t elig0, uint32_t esens, uint32_t epoch) {
+  return (uint64_t)kAgg | ((uint64_t)(table & 0xFFu) << 2) | ((uint64_t)(c0 & 0x7FFFu) << 10) |
+         ((uint64_t)(c1 & 0x7FFFu) << 25) | ((uint64_t)(elig0 & 1u) << 40) | ((uint64_t)(esens & 1u) << 41) |
+         epoch_bits(epoch);
 }
-JSIDX_DEV uint32_t desc_flag(uint64_t d) { return (uint32_t)(d & 7u); }
-JSIDX_DEV uint32_t desc_payload(uint64_t d) { return (uint32_t)((d >> 3) & 0xFFu); }
-JSIDX_DEV uint32_t desc_count(uint64_t d) { return (uint32_t)(d >> 11); }
-JSIDX_DEV uint32_t desc_epoch(uint64_t d) { return (uint32_t)(d >> 43); }
+JSIDX_DEV uint64_t make_inc(uint32_t state, uint32_t reset, uint32_t count, uint32_t epoch) {
+  return (uint64_t)kInc | ((uint64_t)(state & 0xFu) << 2) | ((uint64_t)(reset & 1u) << 6) | ((uint64_t)count << 7) |
+         epoch_bits(epoch);
+}
+JSIDX_DEV uint32_t d_flag(uint64_t d) { return (uint32_t)(d & 3u); }
+JSIDX_DEV bool d_current(uint64_t d, uint32_t epoch) { return (d >> kEpochShift) == ((uint64_t)epoch & kEpochMask); }
+JSIDX_DEV uint32_t d_table(uint64_t d) { return (uint32_t)(d >> 2) & 0xFFu; }
+JSIDX_DEV uint32_t d_c0(uint64_t d) { return (uint32_t)(d >> 10) & 0x7FFFu; }
+JSIDX_DEV uint32_t d_c1(uint64_t d) { return (uint32_t)(d >> 25) & 0x7FFFu; }
+JSIDX_DEV uint32_t d_elig0(uint64_t d) { return (uint32_t)(d >> 40) & 1u; }
+JSIDX_DEV uint32_t d_esens(uint64_t d) { return (uint32_t)(d >> 41) & 1u; }
+JSIDX_DEV uint32_t d_state(uint64_t d) { return (uint32_t)(d >> 2) & 0xFu; }
+JSIDX_DEV uint32_t d_reset(uint64_t d) { return (uint32_t)(d >> 6) & 1u; }
+JSIDX_DEV uint32_t d_count(uint64_t d) { return (uint32_t)(d >> 7); }
 
-JSIDX_DEV uint64_t ld_desc(Workspace* ws, int64_t j) {
-  return prim::ld_agent(&ws->desc[j]);
-}
-JSIDX_DEV void st_desc(Workspace* ws, int64_t j, uint64_t v) {
-  prim::st_agent(&ws->desc[j], v);
-}
+JSIDX_DEV uint64_t ld_desc(Workspace* ws, int64_t j) { return prim::ld_agent(&ws->desc[j]); }
+JSIDX_DEV void st_desc(Workspace* ws, int64_t j, uint64_t v) { prim::st_agent(&ws->desc[j], v); }
 
 // ---- carry state between tiles ---------------------------------------------
 // state bits: 0 e (next byte escaped), 1 q (inside a string), 2 p (previous
@@ -62,22 +90,6 @@ JSIDX_DEV uint32_t tab_apply(uint32_t T, uint32_t s) {
   uint32_t qn = reset ? q2 : (q ^ q2);
   uint32_t un = reset ? tu : (u | tu);
   return e2 | (qn << 1) | (p2 << 2) | (un << 3);
-}
-// A then B.
-JSIDX_DEV uint32_t tab_compose(uint32_t A, uint32_t B) {
-  uint32_t C = (A & 1u) | (B & 1u);
-  uint32_t bu = (B >> 1) & 1u;
-  uint32_t cu = (B & 1u) ? bu : (((A >> 1) & 1u) | bu);
-  C |= cu << 1;
-#pragma unroll
-  for (uint32_t e = 0; e < 2; e++) {
-    uint32_t a = (A >> (2 + 3 * e)) & 7u;
-    uint32_t b = (B >> (2 + 3 * (a & 1u))) & 7u;
-    uint32_t q = (B & 1u) ? ((b >> 1) & 1u) : (((a >> 1) ^ (b >> 1)) & 1u);
-    uint32_t ent = (b & 1u) | (q << 1) | (b & 4u);
-    C |= ent << (2 + 3 * e);
-  }
-  return C;
 }
 
 struct Args {
@@ -97,47 +109,45 @@ JSIDX_DEV int64_t doc_off(const Args& a, int64_t d) {
   return d <= 0 ? 0 : (int64_t)a.len;
 }
 
-// ---- per-lane, per-row state ----------------------------------------------
-struct Seg {
-  uint32_t C, W, Q, R, PR, EA;  // classes, in-string, predecessor, escape-after
-  uint32_t Qraw, B;
-  uint32_t D;    // document starts at bits 0..31
-  uint32_t d32;  // a document starts right after bit 31
-  uint32_t V;    // bytes inside [begin, end)
-  uint32_t UE;   // UTF-8 error of the piece starting at this bit
-  int32_t head;  // local index of the document holding bit 0 (-1: none)
-  uint32_t F;    // final index bits
-  uint32_t cin;  // output rank of the first head bit
-  uint32_t uin;  // UTF-8 error of the head document before this segment
-};
-
+// Per-wave LDS.
 struct Shared {
-  int64_t tile;
   int64_t d_first;
   int64_t first_off;
   int32_t ntab;
   int32_t overflow;
   int32_t tab[kDocCap + 1];
-  // wave aggregates, [row][wave]
-  uint32_t agg_a[kRows][kWaves];
-  uint32_t agg_b[kRows][kWaves];
-  uint32_t agg_c[kRows][kWaves];
-  // tile facts
-  uint32_t lead_pos;  // first byte that is not a backslash or starts a doc
-  uint32_t qsens;     // that byte is a quote (its escape depends on e_in)
-  uint32_t r0;        // first document start in the tile (kTileBytes: none)
-  uint32_t state_in;  // carry-in state
-  uint32_t base;      // rank of the tile's first head bit
-  uint32_t is_last;
+  // head region (bytes before the tile's first document start), kept for the
+  // pass after the look-back: candidate bits and indexed bits assuming the
+  // tile starts outside a string
+  uint32_t hK[kRows][kThreads];
+  uint32_t hF[kRows][kThreads];
+  // the head document ends in the head region: its last byte and flags there
+  uint32_t he_valid, he_R0, he_EA, he_u;
+  uint32_t tile;
   uint32_t epoch;
-  int32_t min_reset;
+  uint32_t is_last;
 };
 
-// Local document index of tile-relative position rel: the last document
-// starting at or before it (empty documents at the same place come first).
-// (Only used while the table holds every document of the tile.)
+// Facts about a tile computed by tile_local (wave-uniform unless noted).
+struct TileFacts {
+  uint32_t carry;      // state after the tile
+  uint32_t any_const;  // some byte is not a backslash or a document starts
+  uint32_t lead_pos;   // first byte that is not a backslash or starts a doc
+  uint32_t lead_reset; // ... and it is a document start
+  uint32_t qsens;      // ... and it is a quote (its escape depends on e_in)
+  uint32_t reset_any;
+  uint32_t r0;         // first document start (kTileBytes: none)
+  uint32_t elig0;      // byte 0 is a pseudo-structural candidate if p_in
+  uint32_t head_rows;  // rows holding head-region bytes
+  uint32_t a0, a1;     // per lane, head region: popcount(F0), popcount(K & ~F0)
+  uint32_t tail_count; // count of the document open at the tile's end, since
+                       // its start in this tile (valid if reset_any)
+};
+
+// Local document index of tile-relative position rel (table mode only): the
+// last document starting at or before it (empty documents there come first).
 JSIDX_DEVFN int32_t local_doc_of(const Shared& sh, int32_t rel) {
-  int32_t lo = 0, hi = sh.ntab;  // first entry > rel
+  int32_t lo = 0, hi = sh.ntab;
   while (lo < hi) {
     int32_t mid = (lo + hi) >> 1;
     if (sh.tab[mid] <= rel) lo = mid + 1; else hi = mid;
@@ -154,12 +164,73 @@ JSIDX_DEVFN int64_t global_upper(const Args& a, int64_t lo, int64_t hi, int64_t 
   return lo;
 }
 
-JSIDX_DEV uint32_t lane_id() { return prim::lane(); }
+// Document (local index) holding tile-relative position rel, and its offset.
+JSIDX_DEV int32_t doc_at(const Args& a, const Shared& sh, int64_t P0, int64_t d_first, int32_t rel) {
+  if (!sh.overflow) return local_doc_of(sh, rel);
+  return (int32_t)(global_upper(a, d_first, (int64_t)a.ndocs + 1, P0 + rel) - 1 - d_first);
+}
+JSIDX_DEV int64_t doc_start(const Args& a, const Shared& sh, int64_t P0, int64_t d_first, int32_t dloc) {
+  if (dloc == 0) return sh.first_off;
+  return !sh.overflow ? (int64_t)sh.tab[dloc] + P0 : doc_off(a, d_first + dloc);
+}
+
 JSIDX_DEV uint64_t lt_lanes() {
-  uint32_t l = lane_id();
+  uint32_t l = prim::lane();
   return l == 0 ? 0ull : (~0ull >> (64 - l));
 }
+JSIDX_DEV uint64_t lanes_below(int k) { return k <= 0 ? 0ull : (k >= 64 ? ~0ull : (~0ull >> (64 - k))); }
 JSIDX_DEV int msb64(uint64_t m) { return 63 - __builtin_clzll(m); }
+JSIDX_DEV uint32_t parity64(uint64_t m) { return (uint32_t)__builtin_popcountll(m) & 1u; }
+
+// Lanes [k, lane) where k is the last lane below this one with `reset` set;
+// all lanes below if none.  *from_carry: no such lane (the row carry applies).
+JSIDX_DEV uint64_t span_since_reset(uint64_t resets, bool* from_carry) {
+  uint64_t lt = lt_lanes();
+  uint64_t m = resets & lt;
+  *from_carry = (m == 0);
+  if (!m) return lt;
+  return lt & ~lanes_below(msb64(m));
+}
+// Lanes from the last reset lane (inclusive) to 63; all lanes if none.
+JSIDX_DEV uint64_t tail_lanes(uint64_t resets) {
+  if (!resets) return ~0ull;
+  return ~lanes_below(msb64(resets));
+}
+
+JSIDX_DEV uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += prim::shfl_xor(v, o);
+  return v;
+}
+JSIDX_DEV uint32_t wave_incl_sum(uint32_t v) {
+  uint32_t lane = prim::lane();
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    uint32_t y = prim::shfl_up(v, o);
+    if (lane >= (uint32_t)o) v += y;
+  }
+  return v;
+}
+
+// Segmented exclusive prefix of per-lane counts cv over the row: lanes after
+// the last lane with a document start below them get the row carry cc added.
+// Returns the lane's rank base; *cc becomes the carry after the row.
+JSIDX_DEV uint32_t row_ranks(uint32_t cv, uint64_t Rs, uint32_t* cc) {
+  const uint32_t lane = prim::lane();
+  const uint32_t S = wave_incl_sum(cv);
+  uint32_t Sprev = prim::shfl(S, (int)((lane + 63u) & 63u));
+  if (lane == 0) Sprev = 0u;
+  const uint64_t below = Rs & lt_lanes();
+  const int k = below ? msb64(below) : -1;
+  const uint32_t Sk = prim::shfl(S, k > 0 ? k - 1 : 0);
+  uint32_t cin = Sprev - (k > 0 ? Sk : 0u);
+  if (k < 0) cin += *cc;
+  const uint32_t tot = prim::shfl(S, 63);
+  const int kl = Rs ? msb64(Rs) : -1;
+  const uint32_t Skl = prim::shfl(S, kl > 0 ? kl - 1 : 0);
+  *cc = Rs ? tot - (kl > 0 ? Skl : 0u) : *cc + tot;
+  return cin;
+}
 
 // Mask bytes of word k (bytes 4k..4k+3 of the segment) by the bit mask keep.
 JSIDX_DEV uint32_t keep_bytes(uint32_t w, uint32_t keep, int k) {
@@ -182,15 +253,405 @@ JSIDX_DEVFN uint32_t utf8_piece(const uint32_t w[8], uint32_t halo, uint32_t kee
   return err;
 }
 
+JSIDX_DEV void load_segment(const Args& a, int64_t pos, int64_t begin, int64_t end, uint32_t w[8]) {
+  const uint8_t* p = a.base + pos;  // 16-byte aligned
+#pragma unroll
+  for (int h = 0; h < 2; h++) {
+    // only granules overlapping [begin, end) are read
+    if (begin < end && pos + 16 * h < end && pos + 16 * h + 16 > begin) {
+      uint4 v = prim::load16(p + 16 * h);
+      w[4 * h + 0] = v.x; w[4 * h + 1] = v.y; w[4 * h + 2] = v.z; w[4 * h + 3] = v.w;
+    } else {
+      w[4 * h + 0] = w[4 * h + 1] = w[4 * h + 2] = w[4 * h + 3] = 0u;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The local pass over one tile, given the incoming state st_in.  Bytes at or
+// after the tile's first document start do not depend on st_in: their
+// positions and per-document results are written here.  Bytes before it (the
+// head region) are written here too if `defer` is false (st_in and head_base,
+// the head document's count before the tile, are then exact); otherwise
+// their candidate and indexed bits go to LDS for the pass after the look-back.
+JSIDX_DEV void tile_local(const Args& a, Shared& sh, int64_t P0, int64_t begin, int64_t end, int64_t d_first,
+                          uint32_t st_in, bool defer, uint32_t head_base, TileFacts& T) {
+  const uint32_t lane = prim::lane();
+  uint32_t ce = st_in & 1u, cq = (st_in >> 1) & 1u, cp = (st_in >> 2) & 1u, cu = (st_in >> 3) & 1u;
+  uint32_t cc = head_base;  // count of the open document before this row
+  T.any_const = 0; T.lead_pos = kTileBytes; T.lead_reset = 0; T.qsens = 0;
+  T.reset_any = 0; T.r0 = kTileBytes; T.elig0 = 0; T.head_rows = 0; T.a0 = 0; T.a1 = 0; T.tail_count = 0;
+  if (lane == 0) sh.he_valid = 0;
+
+  uint32_t wn[8];
+  load_segment(a, P0 + (int64_t)lane * kSegBytes, begin, end, wn);
+#pragma unroll 1
+  for (int r = 0; r < kRows; r++) {
+    const int32_t rel = r * kRowBytes + (int32_t)lane * kSegBytes;  // tile-relative
+    const int64_t pos = P0 + rel;
+    uint32_t w[8];
+#pragma unroll
+    for (int k = 0; k < 8; k++) w[k] = wn[k];
+    if (r + 1 < kRows) load_segment(a, pos + kRowBytes, begin, end, wn);  // prefetch
+
+    // documents: starts in this segment (D), start right after it (d32),
+    // document holding byte 0 (head), valid bytes (V)
+    int32_t head = doc_at(a, sh, P0, d_first, rel);
+    uint32_t D = 0, d32 = 0;
+    for (int32_t i = head < 0 ? 0 : head;; i++) {
+      int64_t o;
+      if (!sh.overflow) {
+        if (i >= sh.ntab) break;
+        o = i == 0 ? sh.first_off : (int64_t)sh.tab[i] + P0;
+      } else {
+        if (d_first + i > (int64_t)a.ndocs) break;
+        o = doc_off(a, d_first + i);
+      }
+      if (o < pos) continue;
+      if (o > pos + 32) break;
+      if (o == pos + 32) d32 = 1; else D |= 1u << (uint32_t)(o - pos);
+    }
+    const int64_t vlo = begin - pos, vhi = end - pos;
+    const uint32_t V = ge_mask((uint32_t)(vlo < 0 ? 0 : (vlo > 32 ? 32 : vlo))) &
+                       lt_mask((uint32_t)(vhi < 0 ? 0 : (vhi > 32 ? 32 : vhi)));
+    if (head >= 0 && d_first + head >= (int64_t)a.ndocs) head = -1;
+
+    // The 4 bytes before the segment, as far as they belong to the document
+    // holding byte 0 (UTF-8 context); 0x00 otherwise.
+    uint32_t halo = 0;
+    if (head >= 0 && !(D & 1u) && begin < end && pos > begin && pos - 16 < end) {
+      halo = prim::load4(a.base + pos - 4);
+      const int64_t hlo = doc_start(a, sh, P0, d_first, head) - (pos - 4);  // halo bytes before the doc
+      if (hlo > 0) halo &= hlo >= 4 ? 0u : (~0u << (8 * hlo));
+    }
+    if (V != ~0u) {
+#pragma unroll
+      for (int k = 0; k < 8; k++) w[k] = keep_bytes(w[k], V, k);
+    }
+
+    uint32_t hidx[8], sgn[8];
+    const ClassMasks cm = classify_segment(w, hidx, sgn);
+
+    // UTF-8 errors per piece (pieces start at bit 0 and at every document
+    // start); rows without non-ASCII bytes skip the check.
+    uint32_t UE = 0;
+    const bool need = (cm.hi | (halo & 0x80808080u)) != 0u;
+    if (prim::ballot(need) != 0ull) {
+      if (D == 0 && !d32) {
+        Utf8Word prev = utf8_lookup_raw(halo);
+        uint32_t err = 0;
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+          Utf8Word cur = utf8_lookup(w[k], hidx[k], sgn[k]);
+          err |= utf8_pair_errors(prev, cur);
+          prev = cur;
+        }
+        UE = err ? 1u : 0u;
+      } else {
+        uint32_t starts = D | 1u;
+        while (starts) {
+          const uint32_t st = (uint32_t)__builtin_ctz(starts);
+          starts &= starts - 1u;
+          const uint32_t nx = starts ? (uint32_t)__builtin_ctz(starts) : 32u;
+          const bool ends_doc = nx < 32u || d32;
+          const uint32_t hh = (st == 0 && !(D & 1u)) ? halo : 0u;
+          if (utf8_piece(w, hh, ge_mask(st) & lt_mask(nx), ends_doc)) UE |= 1u << st;
+        }
+      }
+    }
+
+    // escapes: a segment with a non-backslash byte or a document start fixes
+    // the escape state after it; an all-backslash segment (even length) keeps it
+    const bool isconst = (cm.B != ~0u) || (D != 0u);
+    const uint32_t hi_reset = D ? 31u - (uint32_t)__builtin_clz(D) : 0u;
+    const uint32_t nb = ~(cm.B & ge_mask(hi_reset));
+    const uint32_t eo = (nb ? (uint32_t)__builtin_clz(nb) : 32u) & 1u;
+    const uint64_t Kc = prim::ballot(isconst);
+    const uint64_t Ec = prim::ballot(eo != 0u);
+    const uint64_t mk = Kc & lt_lanes();
+    const uint32_t e_in = mk ? (uint32_t)((Ec >> msb64(mk)) & 1ull) : ce;
+    if (!T.any_const && Kc) {
+      const int f = __builtin_ctzll(Kc);
+      const uint32_t pl = (uint32_t)__builtin_ctz(~cm.B | D);
+      const uint32_t pf = prim::shfl(pl, f);
+      const uint32_t rf = prim::shfl((D >> pl) & 1u, f);
+      const uint32_t qf = prim::shfl((cm.Q >> pl) & 1u, f);
+      T.lead_pos = (uint32_t)(r * kRowBytes + f * kSegBytes) + pf;
+      T.lead_reset = rf;
+      T.qsens = rf ? 0u : qf;
+      T.any_const = 1;
+    }
+    if (Kc) ce = (uint32_t)((Ec >> msb64(Kc)) & 1ull);
+
+    uint32_t EA;
+    const uint32_t OD = escaped_bytes(cm.B, D, e_in, &EA);
+    const uint32_t Q = cm.Q & ~OD;
+
+    // string ranges: prefix XOR, restarted at document starts
+    const uint32_t PX = prefix_xor(Q);
+    uint32_t corr = 0, c_old = 0, rest = D;
+    while (rest) {
+      const uint32_t d = (uint32_t)__builtin_ctz(rest);
+      rest &= rest - 1u;
+      const uint32_t c_new = d ? ((PX >> (d - 1u)) & 1u) : 0u;
+      if (c_new != c_old) corr ^= ge_mask(d);
+      c_old = c_new;
+    }
+    uint32_t R0 = PX ^ corr;
+    const uint32_t qv = D ? (R0 >> 31) : (uint32_t)(__builtin_popcount(Q) & 1);
+    const uint32_t last_start = D ? 31u - (uint32_t)__builtin_clz(D) : 0u;
+    const uint32_t uv = (UE >> last_start) & 1u;
+    const uint32_t P0m = cm.C | cm.W | Q;
+
+    const uint64_t Rs = prim::ballot(D != 0u);
+    const uint64_t Qv = prim::ballot(qv != 0u);
+    const uint64_t Uv = prim::ballot(uv != 0u);
+    const uint64_t Pb = prim::ballot((P0m >> 31) != 0u);
+    bool from_carry;
+    const uint64_t sp = span_since_reset(Rs, &from_carry);
+    uint32_t qin = parity64(Qv & sp);
+    uint32_t uin = (Uv & sp) ? 1u : 0u;
+    if (from_carry) { qin ^= cq; uin |= cu; }
+    const uint32_t first_reset = D ? (uint32_t)__builtin_ctz(D) : 32u;
+    if (qin) R0 ^= lt_mask(first_reset);
+    const uint32_t pin = lane ? (uint32_t)((Pb >> (lane - 1)) & 1ull) : cp;
+    const uint32_t PR = ((P0m << 1) | pin) | D;
+    const uint64_t tl = tail_lanes(Rs);
+    if (Rs) { cq = parity64(Qv & tl); cu = (Uv & tl) ? 1u : 0u; }
+    else { cq ^= parity64(Qv); cu |= Uv ? 1u : 0u; }
+    cp = (uint32_t)(Pb >> 63);
+
+    if (r == 0) {
+      const uint32_t other0 = (V & 1u) && !(D & 1u) && !((cm.C | cm.W | cm.Q) & 1u);
+      T.elig0 = prim::shfl(other0, 0);
+    }
+    const bool had_reset = T.reset_any != 0;
+    if (Rs && !had_reset) {
+      const int fl = __builtin_ctzll(Rs);
+      T.r0 = (uint32_t)(r * kRowBytes + fl * kSegBytes) + prim::shfl(first_reset, fl);
+      T.reset_any = 1;
+    }
+
+    const uint32_t K = (cm.C | Q | (PR & ~P0m)) & V;
+    const uint32_t F0 = K & ~(Q ^ R0);
+    // head region of this lane: tile positions before the first document start
+    const uint32_t hm = (uint32_t)rel >= T.r0 ? 0u : (T.r0 - (uint32_t)rel >= 32u ? ~0u : lt_mask(T.r0 - (uint32_t)rel));
+    const bool row_has_head = !had_reset;
+    if (defer && row_has_head) {
+      sh.hK[r][lane] = K & hm;
+      sh.hF[r][lane] = F0 & hm;
+      T.head_rows = (uint32_t)r + 1u;
+      T.a0 += (uint32_t)__builtin_popcount(F0 & hm);
+      T.a1 += (uint32_t)__builtin_popcount(K & ~F0 & hm);
+    }
+
+    // positions and per-document results of the pieces written now
+    const uint32_t cv = (uint32_t)__builtin_popcount(F0 & ge_mask(last_start));
+    const uint32_t cin = row_ranks(cv, Rs, &cc);
+    const uint32_t wmask = defer ? ~hm : ~0u;
+    uint32_t starts = D | 1u;
+    while (starts) {
+      const uint32_t st = (uint32_t)__builtin_ctz(starts);
+      starts &= starts - 1u;
+      const uint32_t nx = starts ? (uint32_t)__builtin_ctz(starts) : 32u;
+      const bool ends_doc = nx < 32u || d32;
+      const bool cont = (st == 0 && !(D & 1u));  // continues the previous lane's document
+      const bool deferred = defer && ((hm >> st) & 1u);
+      if (deferred) {
+        // the head document ends inside the head region: keep its flags
+        if (ends_doc) {
+          const uint32_t e = nx - 1u;
+          sh.he_R0 = (R0 >> e) & 1u;
+          sh.he_EA = (EA >> e) & 1u;
+          sh.he_u = ((UE >> st) & 1u) | (cont ? uin : 0u);
+          sh.he_valid = 1;
+        }
+        continue;
+      }
+      const int32_t dloc = cont ? head : doc_at(a, sh, P0, d_first, rel + (int32_t)st);
+      const int64_t dglob = d_first + dloc;
+      if (dloc < 0 || dglob >= (int64_t)a.ndocs) continue;
+      const int64_t doff = doc_start(a, sh, P0, d_first, dloc);
+      uint32_t* out = a.out_idx + doff;
+      const uint32_t rel_doc = (uint32_t)(pos - doff);
+      uint32_t f = F0 & wmask & ge_mask(st) & lt_mask(nx);
+      uint32_t kk = cont ? cin : 0u;
+      while (f) {
+        const uint32_t j = (uint32_t)__builtin_ctz(f);
+        f &= f - 1u;
+        if ((uint64_t)(doff + kk) < (uint64_t)end) prim::st_out(out + kk, rel_doc + j);
+        kk++;
+      }
+      if (ends_doc) {
+        const uint32_t e = nx - 1u;
+        uint32_t err = 0;
+        if (((UE >> st) & 1u) | (cont ? uin : 0u)) err |= JSIDX_ERR_UTF8;
+        if ((R0 >> e) & 1u) err |= JSIDX_ERR_UNCLOSED_STRING;
+        if ((EA >> e) & 1u) err |= JSIDX_ERR_TRAILING_ESCAPE;
+        if (kk == 0) err |= JSIDX_ERR_EMPTY;
+        prim::st_out(a.out_n + dglob, kk);
+        prim::st_out(a.out_err + dglob, err);
+      }
+    }
+  }
+  T.carry = ce | (cq << 1) | (cp << 2) | (cu << 3);
+  T.tail_count = cc;
+}
+
+// ---- the look-back ----------------------------------------------------------
+// Each lane reads 4 consecutive predecessors (lane 0 the newest), so one round
+// trip covers 256 tiles.  Lanes fold their 4 descriptors into either a known
+// state (if one is inclusive) or a transfer of the same kind as a tile's; the
+// walk from the newest lane with a known state to tile t is then done for all
+// lanes at once with ballots (segmented parity / OR scans) and one wave sum.
+struct LaneFold {
+  bool known, has, pending, blocked;
+  uint32_t ks, kc;                       // known state and count
+  uint32_t fr, fec, fev, fp, fq, fu;     // transfer: reset, e const?, e value, p, q, u
+  uint32_t C0, C1, E0;                   // counts for q_in = 0 / 1; first tile's elig0
+  uint32_t b0, b1;                       // an escape-sensitive tile sees e = 1
+                                         //   if the lane starts with e_in = 0 / 1
+};
+
+JSIDX_DEV void fold_desc(LaneFold& L, uint64_t d, bool valid) {
+  if (!valid) return;
+  const uint32_t fl = d_flag(d);
+  if (fl == kNone) { L.pending = true; return; }
+  if (fl == kInc) {
+    L.known = true; L.has = false; L.pending = false; L.blocked = false;
+    L.ks = d_state(d); L.kc = d_count(d);
+    return;
+  }
+  const uint32_t T = d_table(d), c0 = d_c0(d), c1 = d_c1(d), el = d_elig0(d), es = d_esens(d);
+  const uint32_t ent0 = (T >> 2) & 7u, ent1 = (T >> 5) & 7u;
+  const uint32_t Bec = ((ent0 ^ ent1) & 1u) == 0u;  // e_out does not depend on e_in
+  const uint32_t Bev = ent0 & 1u, Bq = (ent0 >> 1) & 1u, Bp = (ent0 >> 2) & 1u, Bu = (T >> 1) & 1u;
+  const uint32_t Br = T & 1u;
+  if (L.known) {
+    if (es && (L.ks & 1u)) L.blocked = true;
+    const uint32_t q = (L.ks >> 1) & 1u, p = (L.ks >> 2) & 1u;
+    L.kc = Br ? c0 : L.kc + (q ? c1 : c0 + (p & el));
+    L.ks = tab_apply(T, L.ks);
+    return;
+  }
+  if (!L.has) {
+    L.has = true;
+    L.fr = Br; L.fec = Bec; L.fev = Bev; L.fp = Bp; L.fq = Bq; L.fu = Bu;
+    L.C0 = c0; L.C1 = Br ? c0 : c1; L.E0 = Br ? 0u : el;
+    L.b0 = 0; L.b1 = es;
+    return;
+  }
+  L.b0 |= es & (L.fec ? L.fev : 0u);
+  L.b1 |= es & (L.fec ? L.fev : 1u);
+  if (Bec) { L.fec = 1; L.fev = Bev; }
+  if (Br) {
+    L.fr = 1; L.fq = Bq; L.fu = Bu; L.C0 = L.C1 = c0;
+  } else {
+    const uint32_t qa0 = L.fr ? L.fq : L.fq;        // q entering B when the lane starts with q = 0
+    const uint32_t qa1 = L.fr ? L.fq : (1u ^ L.fq);  // ... with q = 1
+    L.C0 += qa0 ? c1 : c0 + (L.fp & el);
+    L.C1 += qa1 ? c1 : c0 + (L.fp & el);
+    L.fq ^= Bq;
+    L.fu |= Bu;
+  }
+  L.fp = Bp;
+}
+
+// State entering tile t and the count of its head document before it.
+JSIDX_DEV void look_back(Workspace* ws, int64_t t, uint32_t epoch, uint32_t* s_out, uint32_t* base_out) {
+  const uint32_t lane = prim::lane();
+  for (uint32_t polls = 0;; polls++) {
+    LaneFold L;
+    L.known = L.has = L.pending = L.blocked = false;
+    L.ks = L.kc = 0; L.fr = L.fec = L.fev = L.fp = L.fq = L.fu = 0; L.C0 = L.C1 = L.E0 = 0; L.b0 = L.b1 = 0;
+    const int64_t j0 = t - 1 - 4 * (int64_t)lane;  // this lane's newest tile
+    uint64_t d[4];
+#pragma unroll
+    for (int m = 0; m < 4; m++) d[m] = (j0 - m >= 0) ? ld_desc(ws, j0 - m) : 0ull;
+#pragma unroll
+    for (int m = 3; m >= 0; m--) {
+      const bool valid = j0 - m >= 0;
+      uint64_t dm = d[m];
+      if (valid && !d_current(dm, epoch)) dm = 0ull;  // not yet written in this launch
+      fold_desc(L, dm, valid);
+    }
+    prim::trace_count(t, 8);
+    const uint64_t Kn = prim::ballot(L.known);
+    const int k = Kn ? __builtin_ctzll(Kn) : 64;
+    const uint64_t below = lanes_below(k);
+    const uint64_t pend = prim::ballot(L.pending) & (below | (k < 64 ? (1ull << k) : 0ull));
+    if (Kn == 0 || pend) {
+      if (polls > prim::kSpinLimit) {  // never expected: give up, flag it
+        prim::st_agent32(&ws->diag, 1u);
+        *s_out = 0; *base_out = 0;
+        return;
+      }
+      prim::sleep();
+      continue;
+    }
+    // known start: lane k, after its newest tile
+    const uint32_t ks = prim::shfl(L.ks, k), kc = prim::shfl(L.kc, k);
+    const uint32_t kblk = prim::shfl(L.blocked ? 1u : 0u, k);
+    // lanes below k are transfers; lane 0 is the newest
+    const uint64_t Ec = prim::ballot(L.has && L.fec) & below;
+    const uint64_t Ev = prim::ballot(L.fev != 0u);
+    const uint64_t Rs = prim::ballot(L.has && L.fr) & below;
+    const uint64_t Qv = prim::ballot(L.fq != 0u);
+    const uint64_t Uv = prim::ballot(L.fu != 0u);
+    const uint64_t above = ~lanes_below((int)lane + 1);  // older lanes
+    // escape at this lane's entry: nearest older lane that fixes it, else ks
+    const uint64_t me = Ec & above;
+    const uint32_t e_ent = me ? (uint32_t)((Ev >> __builtin_ctzll(me)) & 1ull) : (ks & 1u);
+    // in-string and UTF-8 state at entry: from the nearest older reset lane
+    const uint64_t mr = Rs & above;
+    const uint64_t span = (mr ? lanes_below(__builtin_ctzll(mr) + 1) : below) & above;
+    uint32_t q_ent = parity64(Qv & span);
+    uint32_t u_ent = (Uv & span) ? 1u : 0u;
+    if (!mr) { q_ent ^= (ks >> 1) & 1u; u_ent |= (ks >> 3) & 1u; }
+    uint32_t p_ent = prim::shfl(L.fp, (int)((lane + 1u) & 63u));
+    if ((int)lane + 1 >= k) p_ent = (ks >> 2) & 1u;
+    const bool blk = L.has && (e_ent ? L.b1 : L.b0);
+    const bool any_blk = (prim::ballot(blk) & below) != 0ull || (kblk != 0u);
+    // count: from the newest reset lane below k (absolute), else from kc
+    uint32_t contrib = 0;
+    if (L.has) contrib = L.fr ? L.C0 : (q_ent ? L.C1 : L.C0 + (p_ent & L.E0));
+    const int rn = Rs ? __builtin_ctzll(Rs) : -1;
+    const uint64_t cm = rn >= 0 ? lanes_below(rn + 1) : below;
+    const uint32_t sum = wave_sum(((cm >> lane) & 1ull) ? contrib : 0u);
+    // state after lane 0
+    uint32_t st0;
+    if (k == 0) {
+      st0 = ks;
+    } else {
+      const uint32_t e_after = L.fec ? L.fev : e_ent;
+      const uint32_t q_after = L.fr ? L.fq : (q_ent ^ L.fq);
+      const uint32_t u_after = L.fr ? L.fu : (u_ent | L.fu);
+      st0 = prim::shfl(e_after | (q_after << 1) | (L.fp << 2) | (u_after << 3), 0);
+    }
+    if (any_blk) {
+      // some tile's counts depend on an escape that turned out to be set:
+      // wait for the predecessor's own inclusive value instead
+      prim::trace_count(t, 10);
+      for (uint32_t spins = 0;; spins++) {
+        const uint64_t dp = ld_desc(ws, t - 1);
+        if (d_current(dp, epoch) && d_flag(dp) == kInc) { *s_out = d_state(dp); *base_out = d_count(dp); return; }
+        if (spins > prim::kSpinLimit) { prim::st_agent32(&ws->diag, 1u); *s_out = 0; *base_out = 0; return; }
+        prim::sleep();
+      }
+    }
+    *s_out = st0;
+    *base_out = rn >= 0 ? sum : kc + sum;
+    return;
+  }
+}
+
 // ---------------------------------------------------------------------------
 JSIDX_DEVFN void index_tiles(const Args& a) {
   Shared& sh = prim::lds_object<Shared>();
-  const uint32_t tid = prim::tid();
-  const uint32_t wave = tid >> 6;
-  const uint32_t lane = tid & 63u;
+  const uint32_t lane = prim::lane();
   Workspace* ws = a.ws;
 
-  if (tid == 0) sh.epoch = prim::ld_agent32(&ws->epoch);
+  if (lane == 0) sh.epoch = prim::ld_agent32(&ws->epoch);
   prim::sync();
   const uint32_t epoch = sh.epoch;
 
@@ -199,12 +660,12 @@ JSIDX_DEVFN void index_tiles(const Args& a) {
   const uintptr_t base_addr = (uintptr_t)a.base;
   const uintptr_t g0 = (base_addr + (uintptr_t)begin) & ~(uintptr_t)15;
   const int64_t pos_g0 = (int64_t)(g0 - base_addr);  // position of tile 0 byte 0
-  int64_t span = end - pos_g0;
-  int64_t ntiles = span > 0 ? (span + kTileBytes - 1) / kTileBytes : 1;
+  const int64_t span = end - pos_g0;
+  const int64_t ntiles = span > 0 ? (span + kTileBytes - 1) / kTileBytes : 1;
 
   if ((uint64_t)ntiles > a.cap_tiles) {
     // Not indexed: flag every document.
-    for (int64_t d = (int64_t)prim::block() * kThreads + tid; d < a.ndocs; d += (int64_t)prim::grid() * kThreads) {
+    for (int64_t d = (int64_t)prim::block() * kThreads + lane; d < a.ndocs; d += (int64_t)prim::grid() * kThreads) {
       prim::st_out(a.out_n + d, 0u);
       prim::st_out(a.out_err + d, JSIDX_ERR_CAPACITY);
     }
@@ -212,551 +673,156 @@ JSIDX_DEVFN void index_tiles(const Args& a) {
   }
 
   while (true) {
-    if (tid == 0) sh.tile = (int64_t)prim::add_agent32(&ws->ticket, 1u);
+    if (lane == 0) sh.tile = prim::add_agent32(&ws->ticket, 1u);
     prim::sync();
-    const int64_t t = sh.tile;
+    const int64_t t = (int64_t)sh.tile;
     if (t >= ntiles) break;
     prim::trace(t, 0);
     const int64_t P0 = pos_g0 + t * kTileBytes;  // position of tile byte 0
     const int64_t Pend = P0 + kTileBytes;
 
-    // ---- documents of this tile -------------------------------------------
+    // ---- documents of this tile ---------------------------------------------
     // d_first: the first document whose end is at or after the tile start.
-    if (wave == 0) {
+    int64_t d_first;
+    {
       int64_t lo = 0, hi = (int64_t)a.ndocs - 1;
       while (lo < hi) {
-        int64_t step = (hi - lo + 64) / 64;
-        int64_t d = lo + (int64_t)lane * step;
-        bool ok = d <= hi;
-        bool pr = ok && doc_off(a, d + 1) >= P0;
-        uint64_t b = prim::ballot(pr);
-        int64_t f = b ? (int64_t)__builtin_ctzll(b) : -1;
-        int64_t dfound = f >= 0 ? lo + f * step : hi;
+        const int64_t step = (hi - lo + 64) / 64;
+        const int64_t d = lo + (int64_t)lane * step;
+        const bool pr = d <= hi && doc_off(a, d + 1) >= P0;
+        const uint64_t b = prim::ballot(pr);
+        const int64_t f = b ? (int64_t)__builtin_ctzll(b) : -1;
         int64_t nprobe = (hi - lo) / step;  // last valid probe lane
         if (nprobe > 63) nprobe = 63;
-        int64_t nlo = f > 0 ? lo + (f - 1) * step + 1 : (f == 0 ? lo : lo + nprobe * step + 1);
+        const int64_t nlo = f > 0 ? lo + (f - 1) * step + 1 : (f == 0 ? lo : lo + nprobe * step + 1);
+        hi = f >= 0 ? lo + f * step : hi;
         lo = nlo;
-        hi = dfound;
       }
-      if (lane == 0) {
-        sh.d_first = lo;
-        sh.first_off = doc_off(a, lo);
-        sh.overflow = 0;
-        sh.ntab = 0;
-        sh.min_reset = 0x7FFFFFFF;
-      }
+      d_first = lo;
     }
-    prim::sync();
-    const int64_t d_first = sh.d_first;
-    // Table of starts of documents d_first.. with start <= Pend, relative to P0;
-    // entry 0 clamped at -1.  Empty documents owned by this tile are finished
-    // here: the tile owning a position owns the empty documents there.
+    // Table of starts of documents d_first.. up to Pend, relative to P0
+    // (entry 0 clamped at -1).  Empty documents owned by this tile are
+    // finished here: the tile owning a position owns the empty documents there.
     {
       int32_t count = 0;
       for (int64_t i0 = 0;; i0 += kThreads) {
-        int64_t d = d_first + i0 + tid;
+        const int64_t d = d_first + i0 + lane;
         bool in = d <= (int64_t)a.ndocs;
-        int64_t o = in ? doc_off(a, d) : 0;
+        const int64_t o = in ? doc_off(a, d) : 0;
         in = in && o <= Pend;
-        if (in && i0 + tid < kDocCap + 1) {
-          int64_t r = o - P0;
-          sh.tab[i0 + tid] = (int32_t)(r < -1 ? -1 : r);
+        if (in && i0 + lane < kDocCap + 1) {
+          const int64_t r = o - P0;
+          sh.tab[i0 + lane] = (int32_t)(r < -1 ? -1 : r);
         }
         if (in && d < (int64_t)a.ndocs) {
-          int64_t o2 = doc_off(a, d + 1);
-          bool owned = (o >= P0 && o < Pend) || (o == end && t == ntiles - 1);
+          const int64_t o2 = doc_off(a, d + 1);
+          const bool owned = (o >= P0 && o < Pend) || (o == end && t == ntiles - 1);
           if (o2 == o && owned) {
             prim::st_out(a.out_n + d, 0u);
             prim::st_out(a.out_err + d, JSIDX_ERR_EMPTY);
           }
         }
-        int n_in = prim::sync_count(in);
+        const int n_in = __builtin_popcountll(prim::ballot(in));
         count += n_in;
         if (n_in < kThreads) break;
       }
-      if (tid == 0) {
+      if (lane == 0) {
+        sh.d_first = d_first;
+        sh.first_off = doc_off(a, d_first);
         sh.ntab = count;
         sh.overflow = count > kDocCap + 1;
       }
     }
     prim::sync();
-
     prim::trace(t, 1);
-    // ---- phase 1: load, classify, local scans -------------------------------
-    Seg sg[kRows];
-#pragma unroll
-    for (int r = 0; r < kRows; r++) {
-      Seg& s = sg[r];
-      const int32_t rel = r * kRowBytes + (int32_t)tid * kSegBytes;  // tile-relative
-      const int64_t pos = P0 + rel;
-      // documents
-      int32_t lo;
-      if (!sh.overflow) {
-        lo = local_doc_of(sh, rel);
-      } else {
-        lo = (int32_t)(global_upper(a, d_first, (int64_t)a.ndocs + 1, pos) - 1 - d_first);
-      }
-      s.head = lo;
-      uint32_t D = 0, d32 = 0;
-      for (int32_t i = lo < 0 ? 0 : lo;; i++) {
-        int64_t o;
-        if (!sh.overflow) {
-          if (i >= sh.ntab) break;
-          o = (int64_t)sh.tab[i] + P0;
-          if (i == 0) o = sh.first_off;
-        } else {
-          if (d_first + i > (int64_t)a.ndocs) break;
-          o = doc_off(a, d_first + i);
-        }
-        if (o < pos) continue;
-        if (o > pos + 32) break;
-        if (o == pos + 32) d32 = 1; else D |= 1u << (uint32_t)(o - pos);
-      }
-      s.D = D;
-      s.d32 = d32;
-      int64_t vlo = begin - pos, vhi = end - pos;
-      uint32_t V = ge_mask((uint32_t)(vlo < 0 ? 0 : (vlo > 32 ? 32 : vlo))) &
-                   lt_mask((uint32_t)(vhi < 0 ? 0 : (vhi > 32 ? 32 : vhi)));
-      s.V = V;
-      if (s.head >= 0 && d_first + s.head >= (int64_t)a.ndocs) s.head = -1;
 
-      // load the 32 bytes and the 4 bytes before them
-      uint32_t w[8];
-      const uint8_t* p = a.base + pos;  // 16-byte aligned
-      // only granules overlapping [begin, end) are read
-#pragma unroll
-      for (int h = 0; h < 2; h++) {
-        if (begin < end && pos + 16 * h < end && pos + 16 * h + 16 > begin) {
-          uint4 v = prim::load16(p + 16 * h);
-          w[4 * h + 0] = v.x; w[4 * h + 1] = v.y; w[4 * h + 2] = v.z; w[4 * h + 3] = v.w;
-        } else {
-          w[4 * h + 0] = w[4 * h + 1] = w[4 * h + 2] = w[4 * h + 3] = 0u;
-        }
-      }
-      // The 4 bytes before the segment, as far as they belong to the document
-      // holding byte 0 (UTF-8 context); 0x00 otherwise.
-      uint32_t halo = 0;
-      if (s.head >= 0 && !(D & 1u) && begin < end && pos > begin && pos - 16 < end) {
-        halo = prim::load4(p - 4);
-        int64_t hd_off = s.head == 0 ? sh.first_off
-                                     : (!sh.overflow ? (int64_t)sh.tab[s.head] + P0 : doc_off(a, d_first + s.head));
-        int64_t hlo = hd_off - (pos - 4);  // halo bytes before the document start
-        if (hlo > 0) halo &= hlo >= 4 ? 0u : (~0u << (8 * hlo));
-      }
-      if (V != ~0u) {
-#pragma unroll
-        for (int k = 0; k < 8; k++) w[k] = keep_bytes(w[k], V, k);
-      }
-
-      uint32_t hidx[8], sgn[8];
-      ClassMasks cm = classify_segment(w, hidx, sgn);
-      s.C = cm.C; s.W = cm.W; s.Qraw = cm.Q; s.B = cm.B;
-
-      // UTF-8 errors, per piece of the segment (pieces start at bit 0 and at
-      // every document start).  Waves without non-ASCII bytes skip it.
-      s.UE = 0;
-      bool need = (cm.hi | (halo & 0x80808080u)) != 0u;
-      if (prim::ballot(need) != 0ull) {
-        if (D == 0 && !d32) {
-          // one piece, continued on both sides
-          Utf8Word prev = utf8_lookup_raw(halo);
-          uint32_t err = 0;
-#pragma unroll
-          for (int k = 0; k < 8; k++) {
-            Utf8Word cur = utf8_lookup(w[k], hidx[k], sgn[k]);
-            err |= utf8_pair_errors(prev, cur);
-            prev = cur;
-          }
-          s.UE = err ? 1u : 0u;
-        } else {
-          uint32_t starts = D | 1u;
-          while (starts) {
-            uint32_t st = (uint32_t)__builtin_ctz(starts);
-            starts &= starts - 1u;
-            uint32_t nx = starts ? (uint32_t)__builtin_ctz(starts) : 32u;
-            bool ends_doc = nx < 32u || d32;
-            uint32_t keep = ge_mask(st) & lt_mask(nx);
-            uint32_t hh = (st == 0 && !(D & 1u)) ? halo : 0u;
-            if (utf8_piece(w, hh, keep, ends_doc)) s.UE |= 1u << st;
-          }
-        }
-      }
-    }
-
+    // ---- local pass, look-back, and (rarely) an exact second local pass ------
+    TileFacts T;
+    uint32_t s_in = 0, base = 0;
+    bool exact = (t == 0);  // tile 0's carry-in is the initial state
+    tile_local(a, sh, P0, begin, end, d_first, 0u, !exact, 0u, T);
     prim::trace(t, 2);
-    // ---- escape scan -----------------------------------------------------
-    // A segment with a non-backslash byte or a document start fixes the escape
-    // state after it; an all-backslash segment (32 bytes, even) passes it on.
-    uint32_t e_out_c[kRows];
-#pragma unroll
-    for (int r = 0; r < kRows; r++) {
-      Seg& s = sg[r];
-      bool isconst = (s.B != ~0u) || (s.D != 0u);
-      uint32_t hi_reset = s.D ? 31u - (uint32_t)__builtin_clz(s.D) : 0u;
-      uint32_t last_b = s.B & ge_mask(hi_reset);
-      uint32_t nb = ~last_b;
-      e_out_c[r] = (nb ? (uint32_t)__builtin_clz(nb) : 32u) & 1u;
-      uint64_t K = prim::ballot(isconst);
-      uint64_t E = prim::ballot(e_out_c[r] != 0u);
-      if (lane == 0) sh.agg_a[r][wave] = K ? (1u | ((uint32_t)((E >> msb64(K)) & 1ull) << 1)) : 0u;
-    }
-    prim::sync();
-    // carry-in per (row, wave) with e_T = 0; tile-level facts
-    uint32_t e_in[kRows];
+    uint32_t table = 0, cnt0 = 0, cnt1 = 0;
     {
-      uint32_t e = 0;
-      uint32_t any_const = 0;
-#pragma unroll
-      for (int r = 0; r < kRows; r++) {
-        for (int wv = 0; wv < kWaves; wv++) {
-          uint32_t ag = sh.agg_a[r][wv];
-          if (wv == (int)wave) {
-            Seg& s = sg[r];
-            bool isconst = (s.B != ~0u) || (s.D != 0u);
-            uint64_t K = prim::ballot(isconst);
-            uint64_t E = prim::ballot(e_out_c[r] != 0u);
-            uint64_t m = K & lt_lanes();
-            e_in[r] = m ? (uint32_t)((E >> msb64(m)) & 1ull) : e;
-            // the first state-fixing segment of the tile reports its lead byte
-            if (!any_const && K && lane == (uint32_t)__builtin_ctzll(K)) {
-              uint32_t p = (uint32_t)__builtin_ctz(~s.B | s.D);
-              bool reset_first = (s.D >> p) & 1u;
-              sh.lead_pos = (uint32_t)(r * kRowBytes) + tid * kSegBytes + p;
-              sh.qsens = reset_first ? 0u : ((s.Qraw >> p) & 1u);
-            }
-          }
-          if (ag & 1u) { e = (ag >> 1) & 1u; any_const = 1; }
-        }
-      }
-      if (tid == 0 && !any_const) { sh.lead_pos = kTileBytes; sh.qsens = 0; }
-      if (tid == 0) sh.agg_c[0][0] = any_const | (e << 1);
-    }
-    prim::sync();
-    const uint32_t tile_any_const = sh.agg_c[0][0] & 1u;
-    const uint32_t tile_e_last = (sh.agg_c[0][0] >> 1) & 1u;
-
-    // ---- escapes, quotes, string ranges, predecessor bits ------------------
-    uint32_t qval[kRows], pbit[kRows], uval[kRows];
-#pragma unroll
-    for (int r = 0; r < kRows; r++) {
-      Seg& s = sg[r];
-      uint32_t OD = escaped_bytes(s.B, s.D, e_in[r], &s.EA);
-      s.Q = s.Qraw & ~OD;
-      uint32_t PX = prefix_xor(s.Q);
-      uint32_t corr = 0, c_old = 0, rest = s.D;
-      while (rest) {
-        uint32_t d = (uint32_t)__builtin_ctz(rest);
-        rest &= rest - 1u;
-        uint32_t c_new = d ? ((PX >> (d - 1u)) & 1u) : 0u;
-        if (c_new != c_old) corr ^= ge_mask(d);
-        c_old = c_new;
-      }
-      s.R = PX ^ corr;  // with q_in = 0
-      qval[r] = s.D ? (s.R >> 31) : (uint32_t)(__builtin_popcount(s.Q) & 1);
-      uint32_t P0m = s.C | s.W | s.Q;
-      s.PR = P0m << 1;  // bit 0 filled after the scan
-      pbit[r] = P0m >> 31;
-      // UTF-8: value passed on: the last piece's error (reset) or the segment's
-      uint32_t last_start = s.D ? 31u - (uint32_t)__builtin_clz(s.D) : 0u;
-      uval[r] = (s.UE >> last_start) & 1u;
-      if (!s.D) uval[r] = s.UE & 1u;
-      uint64_t Rs = prim::ballot(s.D != 0u);
-      uint64_t Qv = prim::ballot(qval[r] != 0u);
-      uint64_t Uv = prim::ballot(uval[r] != 0u);
-      uint64_t Pb = prim::ballot(pbit[r] != 0u);
-      if (lane == 0) {
-        uint64_t from = Rs ? (~0ull << msb64(Rs)) : ~0ull;
-        uint32_t qp = (uint32_t)(__builtin_popcountll(Qv & from) & 1);
-        uint32_t uo = (Uv & from) ? 1u : 0u;
-        sh.agg_a[r][wave] = (Rs ? 1u : 0u) | (qp << 1) | (uo << 2) | ((uint32_t)(Pb >> 63) << 3);
-      }
-      if (Rs && lane == (uint32_t)__builtin_ctzll(Rs)) {
-        int32_t rp = r * kRowBytes + (int32_t)tid * kSegBytes + __builtin_ctz(s.D);
-        prim::min_lds(&sh.min_reset, rp);
-      }
-    }
-    prim::sync();
-    uint32_t tile_state_out;  // with zero carry-in
-    uint32_t tile_reset;
-    {
-      uint32_t q = 0, u = 0, p = 0, any_reset = 0;
-#pragma unroll
-      for (int r = 0; r < kRows; r++) {
-        for (int wv = 0; wv < kWaves; wv++) {
-          uint32_t ag = sh.agg_a[r][wv];
-          if (wv == (int)wave) {
-            Seg& s = sg[r];
-            uint64_t Rs = prim::ballot(s.D != 0u);
-            uint64_t Qv = prim::ballot(qval[r] != 0u);
-            uint64_t Uv = prim::ballot(uval[r] != 0u);
-            uint64_t Pb = prim::ballot(pbit[r] != 0u);
-            uint64_t m = Rs & lt_lanes();
-            uint64_t span_m = m ? (lt_lanes() & ~(msb64(m) ? (~0ull >> (64 - msb64(m))) : 0ull)) : lt_lanes();
-            uint32_t qin = (uint32_t)(__builtin_popcountll(Qv & span_m) & 1);
-            uint32_t uin = (Uv & span_m) ? 1u : 0u;
-            if (!m) { qin ^= q; uin |= u; }
-            uint32_t pin = lane ? (uint32_t)((Pb >> (lane - 1)) & 1ull) : p;
-            uint32_t first_reset = s.D ? (uint32_t)__builtin_ctz(s.D) : 32u;
-            if (qin) s.R ^= lt_mask(first_reset);
-            s.PR |= pin;
-            s.PR |= s.D;
-            s.uin = uin;
-          }
-          if (ag & 1u) { q = (ag >> 1) & 1u; u = (ag >> 2) & 1u; any_reset = 1; }
-          else { q ^= (ag >> 1) & 1u; u |= (ag >> 2) & 1u; }
-          p = (ag >> 3) & 1u;
-        }
-      }
-      tile_reset = any_reset;
-      tile_state_out = tile_e_last | (q << 1) | (p << 2) | (u << 3);
-    }
-    // tile transfer table
-    const uint32_t lead_pos = sh.lead_pos;
-    const uint32_t qsens = sh.qsens;
-    const uint32_t r0 = sh.min_reset == 0x7FFFFFFF ? (uint32_t)kTileBytes : (uint32_t)sh.min_reset;
-    uint32_t table;
-    {
-      uint32_t q0 = (tile_state_out >> 1) & 1u, p0 = (tile_state_out >> 2) & 1u, u0 = (tile_state_out >> 3) & 1u;
-      table = tile_reset | (u0 << 1);
+      const uint32_t q0 = (T.carry >> 1) & 1u, p0 = (T.carry >> 2) & 1u, u0 = (T.carry >> 3) & 1u;
+      const uint32_t e_last = T.carry & 1u;
+      table = T.reset_any | (u0 << 1);
 #pragma unroll
       for (uint32_t e = 0; e < 2; e++) {
-        uint32_t eo = tile_any_const ? tile_e_last : e;
-        uint32_t flip = e & qsens;
-        uint32_t qo = tile_reset ? q0 : (q0 ^ flip);
-        uint32_t po = p0 ^ (flip & (lead_pos == (uint32_t)kTileBytes - 1u ? 1u : 0u));
+        const uint32_t eo = T.any_const ? e_last : e;
+        const uint32_t flip = e & T.qsens;
+        const uint32_t qo = T.reset_any ? q0 : (q0 ^ flip);
+        const uint32_t po = p0 ^ (flip & (T.lead_pos == (uint32_t)kTileBytes - 1u ? 1u : 0u));
         table |= (eo | (qo << 1) | (po << 2)) << (2 + 3 * e);
       }
+      if (T.reset_any) {
+        cnt0 = cnt1 = T.tail_count;
+      } else if (!exact) {
+        cnt0 = wave_sum(T.a0);
+        cnt1 = wave_sum(T.a1);
+      }
+    }
+    const uint32_t esens = T.qsens | ((T.lead_reset && T.lead_pos > 0) ? 1u : 0u);
+    if (!exact) {
+      if (lane == 0) st_desc(ws, t, make_agg(table, cnt0, cnt1, T.elig0, esens, epoch));
+      look_back(ws, t, epoch, &s_in, &base);
+      prim::trace(t, 3);
+      if ((s_in & 1u) && esens) {
+        // the escape carried in changes this tile's head: redo it exactly
+        prim::trace_count(t, 9);
+        tile_local(a, sh, P0, begin, end, d_first, s_in, false, base, T);
+        exact = true;
+      }
     }
 
-    prim::trace(t, 3);
-    // ---- phase 2: carry-in state by look-back --------------------------------
-    if (wave == 0) {
-      uint32_t s_in = 0;
-      if (t == 0) {
-        if (lane == 0) st_desc(ws, t, make_desc(kStateInc, tab_apply(table, 0u) | (tile_reset << 4), 0, epoch));
-      } else {
-        if (lane == 0) st_desc(ws, t, make_desc(kStateAgg, table, 0, epoch));
-        uint32_t acc = 0;
-        bool has_acc = false;
-        int64_t jhi = t - 1;
-        while (true) {
-          int64_t j = jhi - (int64_t)lane;
-          uint64_t d = 0;
-          if (j >= 0) {
-            for (uint32_t spins = 0;; spins++) {
-              d = ld_desc(ws, j);
-              if (desc_epoch(d) == (epoch & kEpochMask) && desc_flag(d) >= kStateAgg) break;
-              if (spins > prim::kSpinLimit) {  // never expected: give up, flag it
-                prim::st_agent32(&ws->diag, 1u);
-                d = make_desc(kCountInc, 0u, 0u, epoch);
-                break;
-              }
-              prim::sleep();
-            }
-          }
-          uint64_t inc = prim::ballot(j >= 0 && desc_flag(d) >= kStateInc);
-          int lim = inc ? __builtin_ctzll(inc) : (int)((jhi + 1) < 64 ? (jhi + 1) : 64);
-          uint32_t pay = desc_payload(d);
-          // compose the aggregates of lanes lim-1 .. 0 (oldest first)
-          uint32_t comp = 0;
-          bool has = false;
-          for (int i = lim - 1; i >= 0; i--) {
-            uint32_t ti = prim::shfl(pay, i);
-            comp = has ? tab_compose(comp, ti) : ti;
-            has = true;
-          }
-          if (has) {
-            acc = has_acc ? tab_compose(comp, acc) : comp;
-            has_acc = true;
-          }
-          prim::trace_count(t, 8);
-          if (inc) {
-            uint32_t st = prim::shfl(pay, lim) & 0xFu;
-            s_in = has_acc ? tab_apply(acc, st) : st;
-            break;
-          }
-          jhi -= 64;
-        }
-        if (lane == 0) st_desc(ws, t, make_desc(kStateInc, tab_apply(table, s_in) | (tile_reset << 4), 0, epoch));
-      }
-      if (lane == 0) sh.state_in = s_in;
+    // ---- own inclusive value -------------------------------------------------
+    uint32_t st_out, inc_count;
+    if (exact) {
+      st_out = T.carry;
+      inc_count = T.tail_count;  // exact pass: the open document's full count
+    } else {
+      st_out = tab_apply(table, s_in);
+      const uint32_t q = (s_in >> 1) & 1u, p = (s_in >> 2) & 1u;
+      inc_count = T.reset_any ? cnt0 : base + (q ? cnt1 : cnt0 + (p & T.elig0));
     }
-    prim::sync();
+    if (lane == 0) st_desc(ws, t, make_inc(st_out, T.reset_any, inc_count, epoch));
     prim::trace(t, 4);
-    const uint32_t s_in = sh.state_in;
-    const uint32_t eT = s_in & 1u, qT = (s_in >> 1) & 1u, pT = (s_in >> 2) & 1u, uT = (s_in >> 3) & 1u;
 
-    // ---- phase 3: apply the carry-in, final masks, counts --------------------
-    const uint32_t flipQ = eT & qsens;
-    uint32_t cval[kRows];
-#pragma unroll
-    for (int r = 0; r < kRows; r++) {
-      Seg& s = sg[r];
-      const uint32_t rel = (uint32_t)(r * kRowBytes) + tid * kSegBytes;
-      // head region: tile positions < r0
-      uint32_t head = rel >= r0 ? 0u : (r0 - rel >= 32u ? ~0u : lt_mask(r0 - rel));
-      uint32_t x = qT ? head : 0u;
-      if (flipQ) {
-        uint32_t ge = lead_pos <= rel ? ~0u : (lead_pos - rel >= 32u ? 0u : ge_mask(lead_pos - rel));
-        x ^= head & ge;
-        if (lead_pos >= rel && lead_pos < rel + 32u) s.Q ^= 1u << (lead_pos - rel);
-        // the byte after the flipped quote sees a different predecessor
-        uint32_t nxt = lead_pos + 1u;
-        if (nxt >= rel && nxt < rel + 32u && !((s.D >> (nxt - rel)) & 1u)) s.PR ^= 1u << (nxt - rel);
-      }
-      s.R ^= x;
-      if (rel == 0 && pT) s.PR |= 1u;
-      if (eT) {
-        // escape state after each byte of the tile's leading backslash run flips
-        uint32_t lead = lead_pos <= rel ? 0u : (lead_pos - rel >= 32u ? ~0u : lt_mask(lead_pos - rel));
-        s.EA ^= lead & head;
-      }
-      if (rel < r0) s.uin |= uT;
-      uint32_t cwq = s.C | s.W | s.Q;
-      s.F = ((s.C & ~s.R) | (s.Q & s.R) | (s.PR & ~s.R & ~cwq)) & s.V;
-      uint32_t last_start = s.D ? 31u - (uint32_t)__builtin_clz(s.D) : 0u;
-      cval[r] = (uint32_t)__builtin_popcount(s.F & ge_mask(last_start));
-      // wave-level segmented scan of counts
-      uint32_t S = cval[r];
-#pragma unroll
-      for (int o = 1; o < 64; o <<= 1) {
-        uint32_t y = prim::shfl_up(S, o);
-        if (lane >= (uint32_t)o) S += y;
-      }
-      uint64_t Rs = prim::ballot(s.D != 0u);
-      uint64_t m = Rs & lt_lanes();
-      uint32_t Sprev = prim::shfl_up(S, 1);
-      if (lane == 0) Sprev = 0;
-      int k = m ? msb64(m) : -1;
-      uint32_t Sk = prim::shfl(S, k > 0 ? k - 1 : 0);
-      if (k <= 0) Sk = 0;
-      s.cin = Sprev - Sk;  // lanes [k, lane) (or [0, lane))
-      uint32_t tot = prim::shfl(S, 63);
-      int kl = Rs ? msb64(Rs) : -1;
-      uint32_t Skl = prim::shfl(S, kl > 0 ? kl - 1 : 0);
-      if (kl <= 0) Skl = 0;
-      if (lane == 0) {
-        sh.agg_b[r][wave] = Rs ? 1u : 0u;
-        sh.agg_c[r][wave] = tot - Skl;
-      }
-      // remember whether this lane's carry comes from earlier waves
-      s.d32 |= (m ? 0u : 2u);
-    }
-    prim::sync();
-    uint32_t tile_count;
-    {
-      uint32_t c = 0;
-#pragma unroll
-      for (int r = 0; r < kRows; r++) {
-        for (int wv = 0; wv < kWaves; wv++) {
-          if (wv == (int)wave) {
-            Seg& s = sg[r];
-            if (s.d32 & 2u) s.cin += c;
-            s.d32 &= 1u;
-          }
-          if (sh.agg_b[r][wv]) c = sh.agg_c[r][wv]; else c += sh.agg_c[r][wv];
+    // ---- head region: positions and the head document's result ---------------
+    if (!exact) {
+      const uint32_t qT = (s_in >> 1) & 1u;
+      const uint32_t pfix = (((s_in >> 2) & 1u) && T.elig0 && !qT) ? 1u : 0u;
+      const uint32_t uT = (s_in >> 3) & 1u;
+      const int32_t hd = doc_at(a, sh, P0, d_first, 0);
+      const bool hvalid = hd >= 0 && d_first + hd < (int64_t)a.ndocs && T.r0 > 0;
+      const int64_t hoff = hvalid ? doc_start(a, sh, P0, d_first, hd) : 0;
+      uint32_t cc = base;
+#pragma unroll 1
+      for (uint32_t r = 0; r < T.head_rows; r++) {
+        const uint32_t hK = sh.hK[r][lane], hF = sh.hF[r][lane];
+        uint32_t F = qT ? (hF ^ hK) : hF;
+        if (r == 0 && lane == 0) F |= pfix;
+        const uint32_t cin = row_ranks((uint32_t)__builtin_popcount(F), 0ull, &cc);
+        if (!hvalid) continue;
+        const int64_t pos = P0 + (int64_t)r * kRowBytes + (int64_t)lane * kSegBytes;
+        uint32_t* out = a.out_idx + hoff;
+        const uint32_t rel_doc = (uint32_t)(pos - hoff);
+        uint32_t kk = cin;
+        while (F) {
+          const uint32_t j = (uint32_t)__builtin_ctz(F);
+          F &= F - 1u;
+          if ((uint64_t)(hoff + kk) < (uint64_t)end) prim::st_out(out + kk, rel_doc + j);
+          kk++;
         }
       }
-      tile_count = c;
-    }
-
-    prim::trace(t, 5);
-    // ---- phase 4: output base by look-back ------------------------------------
-    if (wave == 0) {
-      uint32_t base = 0;
-      uint32_t st_inc = tab_apply(table, s_in) | (tile_reset << 4);
-      if (t == 0) {
-        if (lane == 0) st_desc(ws, t, make_desc(kCountInc, st_inc, tile_count, epoch));
-      } else {
-        if (lane == 0) st_desc(ws, t, make_desc(kCountAgg, st_inc, tile_count, epoch));
-        int64_t jhi = t - 1;
-        while (true) {
-          int64_t j = jhi - (int64_t)lane;
-          uint64_t d = 0;
-          if (j >= 0) {
-            for (uint32_t spins = 0;; spins++) {
-              d = ld_desc(ws, j);
-              if (desc_epoch(d) == (epoch & kEpochMask) && desc_flag(d) >= kCountAgg) break;
-              if (spins > prim::kSpinLimit) {  // never expected: give up, flag it
-                prim::st_agent32(&ws->diag, 1u);
-                d = make_desc(kCountInc, 0u, 0u, epoch);
-                break;
-              }
-              prim::sleep();
-            }
-          }
-          bool stop_l = j >= 0 && (desc_flag(d) == kCountInc || ((desc_payload(d) >> 4) & 1u));
-          uint64_t stop = prim::ballot(stop_l);
-          int lim = stop ? __builtin_ctzll(stop) : 64;
-          uint32_t v = (j >= 0 && (int)lane <= lim) ? desc_count(d) : 0u;
-#pragma unroll
-          for (int o = 32; o >= 1; o >>= 1) v += prim::shfl_xor(v, o);
-          base += v;
-          prim::trace_count(t, 9);
-          if (stop || jhi < 64) break;
-          jhi -= 64;
-        }
-        if (lane == 0) {
-          uint32_t inc = tile_reset ? tile_count : base + tile_count;
-          st_desc(ws, t, make_desc(kCountInc, st_inc, inc, epoch));
-        }
-      }
-      if (lane == 0) sh.base = base;
-    }
-    prim::sync();
-    prim::trace(t, 6);
-    const uint32_t base = sh.base;
-
-    // ---- phase 5: positions and per-document results ---------------------------
-#pragma unroll
-    for (int r = 0; r < kRows; r++) {
-      Seg& s = sg[r];
-      const uint32_t rel = (uint32_t)(r * kRowBytes) + tid * kSegBytes;
-      const int64_t pos = P0 + rel;
-      if (rel < r0) s.cin += base;
-      uint32_t starts = s.D | 1u;
-      while (starts) {
-        uint32_t st = (uint32_t)__builtin_ctz(starts);
-        starts &= starts - 1u;
-        uint32_t nx = starts ? (uint32_t)__builtin_ctz(starts) : 32u;
-        bool is_head = (st == 0 && !(s.D & 1u));
-        int64_t dloc;
-        if (is_head) {
-          dloc = s.head;
-        } else if (!sh.overflow) {
-          dloc = local_doc_of(sh, (int32_t)(rel + st));
-        } else {
-          dloc = global_upper(a, d_first, (int64_t)a.ndocs + 1, pos + st) - 1 - d_first;
-        }
-        int64_t dglob = d_first + dloc;
-        if (dloc < 0 || dglob >= (int64_t)a.ndocs) continue;
-        int64_t doff = dloc == 0 ? sh.first_off
-                                 : (!sh.overflow ? (int64_t)sh.tab[dloc] + P0 : doc_off(a, dglob));
-        uint32_t rank = is_head ? s.cin : 0u;
-        uint32_t Fs = s.F & ge_mask(st) & lt_mask(nx);
-        uint32_t* out = a.out_idx + doff;
-        uint32_t rel_doc = (uint32_t)(pos - doff);
-        uint32_t f = Fs;
-        uint32_t k = rank;
-        while (f) {
-          uint32_t j = (uint32_t)__builtin_ctz(f);
-          f &= f - 1u;
-          if ((uint64_t)(doff + k) < (uint64_t)end) prim::st_out(out + k, rel_doc + j);
-          k++;
-        }
-        bool ends_doc = nx < 32u || s.d32;
-        if (ends_doc) {
-          uint32_t e = nx - 1u;
-          uint32_t n = k;
-          uint32_t err = 0;
-          uint32_t u8 = ((s.UE >> st) & 1u) | (is_head ? s.uin : 0u);
-          if (u8) err |= JSIDX_ERR_UTF8;
-          if ((s.R >> e) & 1u) err |= JSIDX_ERR_UNCLOSED_STRING;
-          if ((s.EA >> e) & 1u) err |= JSIDX_ERR_TRAILING_ESCAPE;
-          if (n == 0) err |= JSIDX_ERR_EMPTY;
-          prim::st_out(a.out_n + dglob, n);
-          prim::st_out(a.out_err + dglob, err);
-        }
+      if (hvalid && sh.he_valid && lane == 0) {
+        uint32_t err = 0;
+        if (sh.he_u | uT) err |= JSIDX_ERR_UTF8;
+        if (sh.he_R0 ^ qT) err |= JSIDX_ERR_UNCLOSED_STRING;
+        if (sh.he_EA) err |= JSIDX_ERR_TRAILING_ESCAPE;
+        if (cc == 0) err |= JSIDX_ERR_EMPTY;
+        prim::st_out(a.out_n + d_first + hd, cc);
+        prim::st_out(a.out_err + d_first + hd, err);
       }
     }
     prim::sync();
@@ -768,18 +834,18 @@ finish:
   // a rotating window of descriptors so that no stale descriptor can ever
   // carry a matching epoch.
   prim::sync();
-  if (tid == 0) {
+  if (lane == 0) {
     prim::fence();
-    uint32_t old = prim::add_agent32(&ws->done, 1u);
+    const uint32_t old = prim::add_agent32(&ws->done, 1u);
     sh.is_last = (old == prim::grid() - 1) ? 1u : 0u;
   }
   prim::sync();
   if (sh.is_last) {
-    uint64_t nwin = (a.cap_tiles + kScrub - 1) / kScrub;
-    uint64_t w0 = (uint64_t)(epoch % (uint32_t)(nwin ? nwin : 1)) * kScrub;
-    for (uint64_t j = w0 + tid; j < w0 + kScrub && j < a.cap_tiles; j += kThreads) st_desc(ws, (int64_t)j, 0ull);
+    const uint64_t nwin = (a.cap_tiles + kScrub - 1) / kScrub;
+    const uint64_t w0 = (uint64_t)(epoch % (uint32_t)(nwin ? nwin : 1)) * kScrub;
+    for (uint64_t j = w0 + lane; j < w0 + kScrub && j < a.cap_tiles; j += kThreads) st_desc(ws, (int64_t)j, 0ull);
     prim::sync();
-    if (tid == 0) {
+    if (lane == 0) {
       prim::st_agent32(&ws->ticket, 0u);
       prim::st_agent32(&ws->done, 0u);
       prim::st_agent32(&ws->epoch, epoch + 1u);

@@ -46,7 +46,7 @@ long emu_run(const uint8_t* base, const uint64_t* offsets, uint64_t len, uint32_
   a.cap_tiles = cap_tiles;
 
   std::vector<prim::GroupCtx*> groups;
-  for (int b = 0; b < nblocks; b++) groups.push_back(new prim::GroupCtx());
+  for (int b = 0; b < nblocks; b++) groups.push_back(new prim::GroupCtx(kThreads));
   std::vector<std::thread> th;
   for (int b = 0; b < nblocks; b++) {
     for (uint32_t t = 0; t < (uint32_t)kThreads; t++) {

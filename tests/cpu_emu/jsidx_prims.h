@@ -56,7 +56,8 @@ struct WaveCtx {
 };
 
 struct GroupCtx {
-  Barrier bar{256};
+  explicit GroupCtx(int threads) : bar(threads) {}
+  Barrier bar;
   WaveCtx waves[4];
   std::atomic<int> count{0};
   int count_result = 0;

@@ -629,15 +629,17 @@ JSIDX_DEV void look_back(Workspace* ws, int64_t t, uint32_t epoch, uint32_t* s_o
       st0 = prim::shfl(e_after | (q_after << 1) | (L.fp << 2) | (u_after << 3), 0);
     }
     if (any_blk) {
-      // some tile's counts depend on an escape that turned out to be set:
-      // wait for the predecessor's own inclusive value instead
+      // some tile's counts depend on an escape that turned out to be set; that
+      // tile redoes its local pass and publishes an exact inclusive value: poll
+      // until it has (waiting on just that tile, not on the whole chain)
       prim::trace_count(t, 10);
-      for (uint32_t spins = 0;; spins++) {
-        const uint64_t dp = ld_desc(ws, t - 1);
-        if (d_current(dp, epoch) && d_flag(dp) == kInc) { *s_out = d_state(dp); *base_out = d_count(dp); return; }
-        if (spins > prim::kSpinLimit) { prim::st_agent32(&ws->diag, 1u); *s_out = 0; *base_out = 0; return; }
-        prim::sleep();
+      if (polls > prim::kSpinLimit) {
+        prim::st_agent32(&ws->diag, 1u);
+        *s_out = 0; *base_out = 0;
+        return;
       }
+      prim::sleep();
+      continue;
     }
     *s_out = st0;
     *base_out = rn >= 0 ? sum : kc + sum;

@@ -130,6 +130,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the numeric and batched workloads")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--size-mib", type=int, default=256)
+    ap.add_argument("--workload", choices=["c1", "c2", "c3"], default="c1",
+                    help="headline workload (c2/c3 only for profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is "
@@ -141,9 +143,16 @@ def main():
     from paper_1902_08318_amd import synth
     assert torch.cuda.is_available(), "needs a HIP device"
 
-    log("generating C1 (twitter-like, minified)")
-    c1 = synth.gen_c1(1, args.size_mib << 20)
-    log(f"timing C1: {len(c1.data)} bytes, {args.steps} steps")
+    if args.workload == "c3":
+        data, offs, _ = synth.gen_c3(3)
+        r3 = time_batch(jx, torch, data, offs, args.steps, args.warmup)
+        print(json.dumps({"workload": "C3", **r3}), flush=True)
+        return
+    if args.workload == "c2":
+        c1 = synth.gen_c2(2, args.size_mib << 20)
+    else:
+        c1 = synth.gen_c1(1, args.size_mib << 20)
+    log(f"timing {args.workload}: {len(c1.data)} bytes, {args.steps} steps")
     r1 = time_single(jx, torch, c1.data, args.steps, args.warmup)
     value = r1["N"] * args.steps / (r1["ms_total"] / 1e3) / 1e9
     alg_bytes = r1["N"] + 4 * r1["S"]
@@ -161,7 +170,8 @@ def main():
         "vs_baseline": None,
         "dtype": "u8",
         "data": "synthetic",
-        "config": {"workload": "C1: one minified twitter-like JSON document, seed 1",
+        "config": {"workload": "C1: one minified twitter-like JSON document, seed 1" if args.workload == "c1"
+                   else "C2: one pretty-printed numeric (canada-like) JSON document, seed 2",
                    "bytes": r1["N"], "index_entries": r1["S"], "bytes_per_entry": round(r1["N"] / max(1, r1["S"]), 2),
                    "flags": r1["flags"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

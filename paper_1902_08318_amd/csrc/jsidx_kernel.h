@@ -26,22 +26,23 @@ namespace jsidx {
 constexpr int kThreads = 64;  // one wave per workgroup
 constexpr int kSegBytes = 32;
 constexpr int kRowBytes = kThreads * kSegBytes;  // 2 KiB
-constexpr int kRows = 8;
-constexpr int kTileBytes = kRows * kRowBytes;  // 16 KiB
+constexpr int kRows = 16;
+constexpr int kTileBytes = kRows * kRowBytes;  // 32 KiB
 constexpr int kDocCap = 256;                   // documents per tile held in LDS
 constexpr int kScrub = 4096;                   // descriptors cleared per launch
-static_assert(kTileBytes < 32768, "tile counts must fit in 15 bits");
+constexpr int kEscSteps = 4;                   // backslash run scanned back: 4 x 1 KiB
+static_assert(kTileBytes < 65536, "tile counts must fit in 16 bits");
 
 // ---- tile descriptors for the look-back ----------------------------------
-// bits 0..1 flag, 2..41 payload, 42..63 launch epoch.
-//   aggregate: 2..9 transfer table, 10..24 count if the tile starts outside a
-//              string, 25..39 count if inside, 40 byte 0 is a pseudo-structural
-//              candidate, 41 the tile's counts depend on the incoming escape
+// bits 0..1 flag, 2..43 payload, 44..63 launch epoch.
+//   aggregate: 2..9 transfer table, 10..25 count if the tile starts outside a
+//              string, 26..41 count if inside, 42 byte 0 is a pseudo-structural
+//              candidate, 43 the tile's counts depend on the incoming escape
 //   inclusive: 2..5 state after the tile, 6 a document starts in the tile,
 //              7..38 count of the current document up to the tile's end
 enum : uint32_t { kNone = 0, kAgg = 1, kInc = 2 };
-constexpr uint32_t kEpochShift = 42;
-constexpr uint64_t kEpochMask = (1ull << 22) - 1;
+constexpr uint32_t kEpochShift = 44;
+constexpr uint64_t kEpochMask = (1ull << 20) - 1;
 
 struct Workspace {
   uint32_t ticket;  // next tile to hand out
@@ -53,8 +54,8 @@ struct Workspace {
 
 JSIDX_DEV uint64_t epoch_bits(uint32_t epoch) { return ((uint64_t)epoch & kEpochMask) << kEpochShift; }
 JSIDX_DEV uint64_t make_agg(uint32_t table, uint32_t c0, uint32_t c1, uint32_t elig0, uint32_t esens, uint32_t epoch) {
-  return (uint64_t)kAgg | ((uint64_t)(table & 0xFFu) << 2) | ((uint64_t)(c0 & 0x7FFFu) << 10) |
-         ((uint64_t)(c1 & 0x7FFFu) << 25) | ((uint64_t)(elig0 & 1u) << 40) | ((uint64_t)(esens & 1u) << 41) |
+  return (uint64_t)kAgg | ((uint64_t)(table & 0xFFu) << 2) | ((uint64_t)(c0 & 0xFFFFu) << 10) |
+         ((uint64_t)(c1 & 0xFFFFu) << 26) | ((uint64_t)(elig0 & 1u) << 42) | ((uint64_t)(esens & 1u) << 43) |
          epoch_bits(epoch);
 }
 JSIDX_DEV uint64_t make_inc(uint32_t state, uint32_t reset, uint32_t count, uint32_t epoch) {
@@ -64,10 +65,10 @@ JSIDX_DEV uint64_t make_inc(uint32_t state, uint32_t reset, uint32_t count, uint
 JSIDX_DEV uint32_t d_flag(uint64_t d) { return (uint32_t)(d & 3u); }
 JSIDX_DEV bool d_current(uint64_t d, uint32_t epoch) { return (d >> kEpochShift) == ((uint64_t)epoch & kEpochMask); }
 JSIDX_DEV uint32_t d_table(uint64_t d) { return (uint32_t)(d >> 2) & 0xFFu; }
-JSIDX_DEV uint32_t d_c0(uint64_t d) { return (uint32_t)(d >> 10) & 0x7FFFu; }
-JSIDX_DEV uint32_t d_c1(uint64_t d) { return (uint32_t)(d >> 25) & 0x7FFFu; }
-JSIDX_DEV uint32_t d_elig0(uint64_t d) { return (uint32_t)(d >> 40) & 1u; }
-JSIDX_DEV uint32_t d_esens(uint64_t d) { return (uint32_t)(d >> 41) & 1u; }
+JSIDX_DEV uint32_t d_c0(uint64_t d) { return (uint32_t)(d >> 10) & 0xFFFFu; }
+JSIDX_DEV uint32_t d_c1(uint64_t d) { return (uint32_t)(d >> 26) & 0xFFFFu; }
+JSIDX_DEV uint32_t d_elig0(uint64_t d) { return (uint32_t)(d >> 42) & 1u; }
+JSIDX_DEV uint32_t d_esens(uint64_t d) { return (uint32_t)(d >> 43) & 1u; }
 JSIDX_DEV uint32_t d_state(uint64_t d) { return (uint32_t)(d >> 2) & 0xFu; }
 JSIDX_DEV uint32_t d_reset(uint64_t d) { return (uint32_t)(d >> 6) & 1u; }
 JSIDX_DEV uint32_t d_count(uint64_t d) { return (uint32_t)(d >> 7); }
@@ -274,8 +275,11 @@ JSIDX_DEV void load_segment(const Args& a, int64_t pos, int64_t begin, int64_t e
 // head region) are written here too if `defer` is false (st_in and head_base,
 // the head document's count before the tile, are then exact); otherwise
 // their candidate and indexed bits go to LDS for the pass after the look-back.
+// `simple`: no document starts in [P0, P0 + kTileBytes], so every byte of the
+// tile belongs to document hd, which starts at hs (before the tile).
 JSIDX_DEV void tile_local(const Args& a, Shared& sh, int64_t P0, int64_t begin, int64_t end, int64_t d_first,
-                          uint32_t st_in, bool defer, uint32_t head_base, TileFacts& T) {
+                          bool simple, int32_t hd, int64_t hs, uint32_t st_in, bool defer, uint32_t head_base,
+                          TileFacts& T) {
   const uint32_t lane = prim::lane();
   uint32_t ce = st_in & 1u, cq = (st_in >> 1) & 1u, cp = (st_in >> 2) & 1u, cu = (st_in >> 3) & 1u;
   uint32_t cc = head_base;  // count of the open document before this row
@@ -296,8 +300,12 @@ JSIDX_DEV void tile_local(const Args& a, Shared& sh, int64_t P0, int64_t begin, 
 
     // documents: starts in this segment (D), start right after it (d32),
     // document holding byte 0 (head), valid bytes (V)
-    int32_t head = doc_at(a, sh, P0, d_first, rel);
+    int32_t head = hd;
     uint32_t D = 0, d32 = 0;
+    uint32_t V = ~0u;
+    int64_t head_start = hs;
+    if (!simple) {
+    head = doc_at(a, sh, P0, d_first, rel);
     for (int32_t i = head < 0 ? 0 : head;; i++) {
       int64_t o;
       if (!sh.overflow) {
@@ -312,16 +320,18 @@ JSIDX_DEV void tile_local(const Args& a, Shared& sh, int64_t P0, int64_t begin, 
       if (o == pos + 32) d32 = 1; else D |= 1u << (uint32_t)(o - pos);
     }
     const int64_t vlo = begin - pos, vhi = end - pos;
-    const uint32_t V = ge_mask((uint32_t)(vlo < 0 ? 0 : (vlo > 32 ? 32 : vlo))) &
-                       lt_mask((uint32_t)(vhi < 0 ? 0 : (vhi > 32 ? 32 : vhi)));
+    V = ge_mask((uint32_t)(vlo < 0 ? 0 : (vlo > 32 ? 32 : vlo))) &
+        lt_mask((uint32_t)(vhi < 0 ? 0 : (vhi > 32 ? 32 : vhi)));
     if (head >= 0 && d_first + head >= (int64_t)a.ndocs) head = -1;
+    if (head >= 0) head_start = doc_start(a, sh, P0, d_first, head);
+    }
 
     // The 4 bytes before the segment, as far as they belong to the document
     // holding byte 0 (UTF-8 context); 0x00 otherwise.
     uint32_t halo = 0;
     if (head >= 0 && !(D & 1u) && begin < end && pos > begin && pos - 16 < end) {
       halo = prim::load4(a.base + pos - 4);
-      const int64_t hlo = doc_start(a, sh, P0, d_first, head) - (pos - 4);  // halo bytes before the doc
+      const int64_t hlo = head_start - (pos - 4);  // halo bytes before the document
       if (hlo > 0) halo &= hlo >= 4 ? 0u : (~0u << (8 * hlo));
     }
     if (V != ~0u) {
@@ -445,7 +455,9 @@ JSIDX_DEV void tile_local(const Args& a, Shared& sh, int64_t P0, int64_t begin, 
       T.a1 += (uint32_t)__builtin_popcount(K & ~F0 & hm);
     }
 
-    // positions and per-document results of the pieces written now
+    // positions and per-document results of the pieces written now (none
+    // while the whole row lies in a deferred head region)
+    if (defer && !had_reset && Rs == 0ull && prim::ballot(d32 != 0u) == 0ull) continue;
     const uint32_t cv = (uint32_t)__builtin_popcount(F0 & ge_mask(last_start));
     const uint32_t cin = row_ranks(cv, Rs, &cc);
     const uint32_t wmask = defer ? ~hm : ~0u;
@@ -739,10 +751,55 @@ JSIDX_DEVFN void index_tiles(const Args& a) {
     prim::trace(t, 1);
 
     // ---- local pass, look-back, and (rarely) an exact second local pass ------
+    // ---- escape state entering the tile -------------------------------------
+    // Only the backslash run ending right before the tile decides it (odd run:
+    // the tile's first byte is escaped), so it is read from the bytes before the
+    // tile instead of waiting for the look-back.  Usually the byte before is
+    // not a backslash; otherwise the wave measures the run, 1 KiB per step.
+    // Runs longer than kEscSteps KiB leave it to the look-back.
+    const int32_t hd = doc_at(a, sh, P0, d_first, 0);
+    const bool hd_ok = hd >= 0 && d_first + hd < (int64_t)a.ndocs;
+    const int64_t hs = hd_ok ? doc_start(a, sh, P0, d_first, hd) : P0;  // head document start
+    uint32_t e_T = 0, e_known = 1;
+    if (t > 0 && hs < P0) {
+      const uint32_t w0 = prim::load4(a.base + P0 - 4);  // granule [P0-16, P0) holds document bytes
+      if ((w0 >> 24) == 0x5Cu) {
+        e_known = 0;
+        for (int step = 0; step < kEscSteps; step++) {
+          const int64_t c = P0 - (int64_t)kThreads * 16 * step - 16 * ((int64_t)lane + 1);  // lane 0 nearest
+          uint32_t bs = 0;  // bit i: byte c+i is a backslash of the document
+          if (c + 16 > hs) {
+            const uint4 v = prim::load16(a.base + c);
+            const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+              const uint32_t x = wv[k] ^ 0x5C5C5C5Cu;  // zero bytes are backslashes
+              const uint32_t z = ~(((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x) & 0x80808080u;
+              bs |= ((z >> 7) & 1u) << (4 * k) | ((z >> 15) & 1u) << (4 * k + 1) |
+                    ((z >> 23) & 1u) << (4 * k + 2) | ((z >> 31) & 1u) << (4 * k + 3);
+            }
+            if (c < hs) bs &= ~0u << (uint32_t)(hs - c);
+          }
+          const uint32_t trail = (uint32_t)__builtin_clz(~(bs << 16));  // run at the top, 0..16
+          const uint64_t full = prim::ballot(trail >= 16u);
+          const uint64_t notfull = ~full;
+          if (notfull) {
+            const int f = __builtin_ctzll(notfull);
+            const uint32_t run = (uint32_t)f * 16u + prim::shfl(trail, f);
+            e_T = run & 1u;  // runs of whole steps are even
+            e_known = 1;
+            break;
+          }
+        }
+      }
+    }
+    prim::trace(t, 5);
+
     TileFacts T;
     uint32_t s_in = 0, base = 0;
     bool exact = (t == 0);  // tile 0's carry-in is the initial state
-    tile_local(a, sh, P0, begin, end, d_first, 0u, !exact, 0u, T);
+    const bool simple = !sh.overflow && sh.ntab == 1 && sh.tab[0] < 0 && hd_ok;
+    tile_local(a, sh, P0, begin, end, d_first, simple, hd, hs, e_T, !exact, 0u, T);
     prim::trace(t, 2);
     uint32_t table = 0, cnt0 = 0, cnt1 = 0;
     {
@@ -751,8 +808,9 @@ JSIDX_DEVFN void index_tiles(const Args& a) {
       table = T.reset_any | (u0 << 1);
 #pragma unroll
       for (uint32_t e = 0; e < 2; e++) {
-        const uint32_t eo = T.any_const ? e_last : e;
-        const uint32_t flip = e & T.qsens;
+        // with the incoming escape known, both entries are the tile's outcome
+        const uint32_t eo = (T.any_const || e_known) ? e_last : e;
+        const uint32_t flip = e_known ? 0u : (e & T.qsens);
         const uint32_t qo = T.reset_any ? q0 : (q0 ^ flip);
         const uint32_t po = p0 ^ (flip & (T.lead_pos == (uint32_t)kTileBytes - 1u ? 1u : 0u));
         table |= (eo | (qo << 1) | (po << 2)) << (2 + 3 * e);
@@ -764,7 +822,7 @@ JSIDX_DEVFN void index_tiles(const Args& a) {
         cnt1 = wave_sum(T.a1);
       }
     }
-    const uint32_t esens = T.qsens | ((T.lead_reset && T.lead_pos > 0) ? 1u : 0u);
+    const uint32_t esens = e_known ? 0u : (T.qsens | ((T.lead_reset && T.lead_pos > 0) ? 1u : 0u));
     if (!exact) {
       if (lane == 0) st_desc(ws, t, make_agg(table, cnt0, cnt1, T.elig0, esens, epoch));
       look_back(ws, t, epoch, &s_in, &base);
@@ -772,7 +830,7 @@ JSIDX_DEVFN void index_tiles(const Args& a) {
       if ((s_in & 1u) && esens) {
         // the escape carried in changes this tile's head: redo it exactly
         prim::trace_count(t, 9);
-        tile_local(a, sh, P0, begin, end, d_first, s_in, false, base, T);
+        tile_local(a, sh, P0, begin, end, d_first, simple, hd, hs, s_in, false, base, T);
         exact = true;
       }
     }
@@ -795,9 +853,8 @@ JSIDX_DEVFN void index_tiles(const Args& a) {
       const uint32_t qT = (s_in >> 1) & 1u;
       const uint32_t pfix = (((s_in >> 2) & 1u) && T.elig0 && !qT) ? 1u : 0u;
       const uint32_t uT = (s_in >> 3) & 1u;
-      const int32_t hd = doc_at(a, sh, P0, d_first, 0);
-      const bool hvalid = hd >= 0 && d_first + hd < (int64_t)a.ndocs && T.r0 > 0;
-      const int64_t hoff = hvalid ? doc_start(a, sh, P0, d_first, hd) : 0;
+      const bool hvalid = hd_ok && T.r0 > 0;
+      const int64_t hoff = hvalid ? hs : 0;
       uint32_t cc = base;
 #pragma unroll 1
       for (uint32_t r = 0; r < T.head_rows; r++) {

@@ -13,7 +13,7 @@ from gpu_common import assert_batch_matches, assert_single_matches, gpu_index_ba
 
 pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
-TILE = 16384
+TILE = 32768
 
 
 def _say(msg):

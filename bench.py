@@ -132,6 +132,8 @@ def main():
     ap.add_argument("--size-mib", type=int, default=256)
     ap.add_argument("--workload", choices=["c1", "c2", "c3"], default="c1",
                     help="headline workload (c2/c3 only for profiling runs)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run plain 256 MiB device copies (scale for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is "
@@ -142,6 +144,16 @@ def main():
     import paper_1902_08318_amd as jx
     from paper_1902_08318_amd import synth
     assert torch.cuda.is_available(), "needs a HIP device"
+
+    if args.copy_calibration:
+        n = args.size_mib << 20
+        src = torch.randint(0, 255, (n,), dtype=torch.uint8, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(args.steps):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "copies": args.steps}), flush=True)
+        return
 
     if args.workload == "c3":
         data, offs, _ = synth.gen_c3(3)

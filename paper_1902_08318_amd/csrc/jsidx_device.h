@@ -19,101 +19,78 @@ JSIDX_DEV uint32_t bfi(uint32_t m, uint32_t a, uint32_t b) {
   return (m & a) | (~m & b);
 }
 
-// 0xFF in every byte of v whose top bit is set, 0x00 elsewhere.  v_perm_b32
-// selectors 8..11 replicate the sign bit of bytes 1, 3, 5, 7 of its 64-bit
-// source; feeding (v << 8, v) exposes the sign of all four bytes of v.
-JSIDX_DEV uint32_t signmask(uint32_t v) {
-  return perm(v << 8, v, 0x090B080Au);
-}
-
-// 0xFF in byte k iff bit k of the low nibble n is set (selector 12 -> 0x00,
-// selector 13 -> 0xFF).
-JSIDX_DEV uint32_t nibble_bytemask(uint32_t n) {
-  uint32_t spread = (n & 1u) | ((n & 2u) << 7) | ((n & 4u) << 14) | ((n & 8u) << 21);
-  return perm(0u, 0u, 0x0C0C0C0Cu + spread);
-}
-
 JSIDX_DEV uint32_t ge_mask(uint32_t a) { return a >= 32u ? 0u : (~0u << a); }
 JSIDX_DEV uint32_t lt_mask(uint32_t a) { return a >= 32u ? ~0u : ((1u << a) - 1u); }
 
-// ---- Byte classes (Sec. 3.1.2) -------------------------------------------
-// The class byte of each input byte is looked up from its two nibbles and the
-// two results are ANDed, as in the paper's table-driven classification; here
-// the tables live in v_perm_b32 operands.  Bits of the class byte:
-//   0 quote 0x22 | 1 white space 09 0A 0D | 2 white space 20
-//   3 comma 2C | 4 colon 3A | 5 brackets/braces 5B 5D 7B 7D | 6 backslash 5C
-// High-nibble table (nibbles 0..7; bytes >= 0x80 are cleared separately):
-//   [0]=02 [1]=00 [2]=0D [3]=10 [4]=00 [5]=60 [6]=00 [7]=20
-// Low-nibble table (nibbles 0..15):
-//   [0]=04 [2]=01 [9]=02 [A]=12 [B]=20 [C]=48 [D]=22, others 00.
-// A 16-entry lookup is done with two v_perm_b32 whose halves are selected by
-// XORing the nibble with 2 and then with 8: out-of-range selectors yield 0xFF
-// (neutral under AND) except selector 12 (0x00), which the XOR with 2 sends to
-// nibbles 6 and 14, both of class 0.  Entries at odd table positions carry a
-// spare 0x80 bit so that selectors 8..11 also yield 0xFF; bit 7 of the class
-// byte is never used.
-constexpr uint32_t kHiLo = 0x100D0002u, kHiHi = 0x20006000u;
-constexpr uint32_t kT1Lo = 0x80048001u, kT1Hi = 0x80008000u;
-constexpr uint32_t kT2Lo = 0x8200A012u, kT2Hi = 0xA2488000u;
-
-struct ClassWord {
-  uint32_t cls;   // class byte per input byte
-  uint32_t hidx;  // high nibble & 7 per byte (shared with UTF-8 lookups)
-  uint32_t sgn;   // 0xFF per byte >= 0x80
-};
-
-JSIDX_DEV ClassWord classify_word(uint32_t x) {
-  ClassWord c;
-  c.hidx = (x >> 4) & 0x07070707u;
-  uint32_t rhi = perm(kHiHi, kHiLo, c.hidx);
-  uint32_t n1 = (x ^ 0x02020202u) & 0x0F0F0F0Fu;
-  uint32_t r1 = perm(kT1Hi, kT1Lo, n1);
-  uint32_t r2 = perm(kT2Hi, kT2Lo, n1 ^ 0x08080808u);
-  c.sgn = signmask(x);
-  c.cls = bfi(c.sgn, 0u, r1 & r2 & rhi);
-  return c;
-}
-
-// Gather one flag per byte of eight words into a 32-bit mask (bit 4k+j =
-// byte j of word k).  Every byte of f[k] holds 0 or (1 << SH); v_dot4_u32_u8
-// with weights {1,2,4,8} / {16,32,64,128} packs two words into one byte.
-template <int SH>
-JSIDX_DEV uint32_t compact8(const uint32_t f[8]) {
-  uint32_t b0 = prim::udot4(f[1], 0x80402010u, prim::udot4(f[0], 0x08040201u, 0u));
-  uint32_t b1 = prim::udot4(f[3], 0x80402010u, prim::udot4(f[2], 0x08040201u, 0u));
-  uint32_t b2 = prim::udot4(f[5], 0x80402010u, prim::udot4(f[4], 0x08040201u, 0u));
-  uint32_t b3 = prim::udot4(f[7], 0x80402010u, prim::udot4(f[6], 0x08040201u, 0u));
-  uint32_t lo16 = b0 | (b1 << 8);
-  uint32_t hi16 = b2 | (b3 << 8);
-  return (lo16 >> SH) | (hi16 << (16 - SH));
-}
-
-struct ClassMasks {
-  uint32_t C, W, Q, B;  // structural, white space, quote, backslash
-  uint32_t hi;          // OR of the bytes' top bits (non-ASCII present)
-};
-
-JSIDX_DEV ClassMasks classify_segment(const uint32_t w[8], uint32_t hidx[8], uint32_t sgn[8]) {
-  uint32_t fq[8], fw[8], fc[8], fb[8];
-  uint32_t any = 0;
+// ---- Bit planes --------------------------------------------------------------
+// p[b] bit i = bit b of byte i of the segment (w and p must not alias).  With the segment's bytes as
+// planes, every byte class below is a few three-input logic operations on
+// whole 32-bit masks (v_bitop3_b32), with no per-byte packing step.
+//   1. byte transpose (v_perm_b32): u[k] byte j = segment byte 8j + k;
+//   2. three swap stages exchange bit s of the register index with bit s of
+//      the bit-in-byte index, so register b ends up holding bit b of byte
+//      8j + k at position 8j + k.
+JSIDX_DEV void bit_planes(const uint32_t w[8], uint32_t p[8]) {
 #pragma unroll
-  for (int k = 0; k < 8; k++) {
-    ClassWord c = classify_word(w[k]);
-    hidx[k] = c.hidx;
-    sgn[k] = c.sgn;
-    any |= w[k];
-    fq[k] = c.cls & 0x01010101u;
-    fw[k] = ((c.cls & 0x06060606u) + 0x06060606u) & 0x08080808u;
-    fc[k] = ((c.cls & 0x38383838u) + 0x38383838u) & 0x40404040u;
-    fb[k] = c.cls & 0x40404040u;
+  for (int h = 0; h < 2; h++) {
+    const uint32_t A = w[h], B = w[h + 2], C = w[h + 4], D = w[h + 6];
+    const uint32_t X = perm(B, A, 0x05010400u), Y = perm(B, A, 0x07030602u);
+    const uint32_t Z = perm(D, C, 0x05010400u), W = perm(D, C, 0x07030602u);
+    p[4 * h + 0] = perm(Z, X, 0x05040100u);
+    p[4 * h + 1] = perm(Z, X, 0x07060302u);
+    p[4 * h + 2] = perm(W, Y, 0x05040100u);
+    p[4 * h + 3] = perm(W, Y, 0x07060302u);
   }
+#pragma unroll
+  for (int s = 0; s < 3; s++) {
+    const int sh = 1 << s;
+    const uint32_t m = s == 0 ? 0x55555555u : (s == 1 ? 0x33333333u : 0x0F0F0F0Fu);
+#pragma unroll
+    for (int r = 0; r < 8; r++) {
+      if (r & sh) continue;
+      const uint32_t a = p[r], c = p[r + sh];
+      p[r] = bfi(m, a, c << sh);
+      p[r + sh] = bfi(m, a >> sh, c);
+    }
+  }
+}
+
+// ---- Byte classes (Sec. 3.1.2) -------------------------------------------
+// The paper splits each byte into its two nibbles and combines per-nibble
+// lookups; on bit planes the same nibble tests are logic on planes 4..7 (high
+// nibble) and 0..3 (low nibble).
+struct ClassMasks {
+  uint32_t C, W, Q, B;  // structural , : [ ] { } | white space | quote | backslash
+};
+
+JSIDX_DEV ClassMasks classify_planes(const uint32_t p[8]) {
+  const uint32_t n76 = ~(p[7] | p[6]);
+  const uint32_t H0 = n76 & ~(p[5] | p[4]);   // 0x0_
+  const uint32_t H2 = n76 & p[5] & ~p[4];     // 0x2_
+  const uint32_t H3 = n76 & p[5] & p[4];      // 0x3_
+  const uint32_t H57 = ~p[7] & p[6] & p[4];   // 0x5_ or 0x7_
+  const uint32_t n32 = ~(p[3] | p[2]);
+  const uint32_t L0 = n32 & ~(p[1] | p[0]);
+  const uint32_t L2 = n32 & p[1] & ~p[0];
+  const uint32_t LC = p[3] & p[2] & ~(p[1] | p[0]);
+  const uint32_t LA = p[3] & ~p[2] & p[1] & ~p[0];
+  const uint32_t LBD = p[3] & p[0] & (p[2] ^ p[1]);                               // B, D
+  const uint32_t L9AD = p[3] & ((~p[2] & (p[1] ^ p[0])) | (p[2] & ~p[1] & p[0]));  // 9, A, D
   ClassMasks m;
-  m.Q = compact8<0>(fq);
-  m.W = compact8<3>(fw);
-  m.C = compact8<6>(fc);
-  m.B = compact8<6>(fb);
-  m.hi = any & 0x80808080u;
+  m.Q = H2 & L2;                                        // 22
+  m.B = H57 & ~p[5] & LC;                               // 5C
+  m.C = (H2 & LC) | (H3 & LA) | (H57 & LBD);            // 2C 3A 5B 5D 7B 7D
+  m.W = (H2 & L0) | (H0 & L9AD);                        // 20 09 0A 0D
   return m;
+}
+
+// (x << 1) with bit 0 taken from bit 31 of x in the previous lane; lane 0
+// takes *cin (0/1), which becomes bit 31 of lane 63's x for the next row.
+JSIDX_DEV uint32_t shift_in1(uint32_t x, uint32_t* cin) {
+  const uint64_t m = prim::ballot((int32_t)x < 0);
+  const uint64_t sh = (m << 1) | (uint64_t)*cin;
+  *cin = (uint32_t)(m >> 63);
+  return (x << 1) | (prim::lane_bit(sh) ? 1u : 0u);
 }
 
 // ---- Odd-length backslash runs (Sec. 3.1.1, Fig. 3) -----------------------
@@ -171,52 +148,60 @@ JSIDX_DEV uint32_t prefix_xor(uint32_t m) {
 }
 
 // ---- UTF-8 (Sec. 3.1.5, table of well-formed sequences) --------------------
-// Each byte is checked against the byte before it with three nibble lookups
-// whose AND is non-zero exactly for ill-formed (previous, current) pairs; a
-// separate test requires continuation bytes 2 and 3 positions after a 3- and
-// 4-byte lead.  Error-class bits (tables derived from the well-formed ranges):
-//   01 lead not followed by a continuation   02 continuation after ASCII
-//   04 E0 followed by 80..9F                 08 ED followed by A0..BF
-//   10 C0/C1 lead                            20 F4 + 90..BF, or F5..FF lead
-//   40 F0 + 80..8F, or F5..FF + 80..8F       80 continuation after continuation
-// Bit 80 is XORed with the "must be continuation" test, so a third or fourth
-// byte passes only where a 3- or 4-byte lead requires it.
-// Previous-byte high nibble 8..F (0..7 -> 02):
-constexpr uint32_t kU1Hi = 0x610D0111u, kU1Lo = 0x80808080u;
-// Current-byte high nibble 8..F (0..7 -> 11):
-constexpr uint32_t kU3Hi = 0x11111111u, kU3Lo = 0xBABAB6D6u;
-// Previous-byte low nibble 0..7 and 8..F:
-constexpr uint32_t kU2aHi = 0xE3E3E3A3u, kU2aLo = 0x838393D7u;
-constexpr uint32_t kU2bHi = 0xE3E3EBE3u, kU2bLo = 0xE3E3E3E3u;
-
-struct Utf8Word {
-  uint32_t t1, t2, t3, gE, gF;
+// On bit planes: a byte is a continuation (10xxxxxx) exactly where the
+// sequence rules require one.  lead = 11xxxxxx needs one continuation after
+// it, 111xxxxx a second, 1111xxxx a third; C0, C1 and F5..FF never occur, and
+// the byte after E0 / ED / F0 / F4 is restricted to A0..BF / 80..9F / 90..BF
+// / 80..8F.  D marks document starts (nothing before them counts), E the last
+// byte of a document (a sequence still open there is truncated).  Bits are
+// set where an error is detected, inside the document it belongs to.
+// Carry state between rows: bit 31 of the shifted masks in the lane before.
+struct U8Carry {
+  uint32_t l4, x, pa, m1, m2, m3;
 };
 
-JSIDX_DEV Utf8Word utf8_lookup(uint32_t w, uint32_t hidx, uint32_t sgn) {
-  Utf8Word u;
-  u.t1 = bfi(sgn, perm(kU1Hi, kU1Lo, hidx), 0x02020202u);
-  u.t3 = bfi(sgn, perm(kU3Hi, kU3Lo, hidx), 0x11111111u);
-  uint32_t lidx = w & 0x07070707u;
-  uint32_t m3 = signmask(w << 4);
-  u.t2 = bfi(m3, perm(kU2bHi, kU2bLo, lidx), perm(kU2aHi, kU2aLo, lidx));
-  u.gE = w & (w << 1) & (w << 2);  // top bit: byte >= 0xE0
-  u.gF = u.gE & (w << 3);          // top bit: byte >= 0xF0
-  return u;
+JSIDX_DEV U8Carry u8_carry_zero() { return U8Carry{0u, 0u, 0u, 0u, 0u, 0u}; }
+
+// Carry state after the last 4 bytes before a segment (byte 3 is the last;
+// bytes not in the document must be 0).
+JSIDX_DEV U8Carry u8_carry_from_word(uint32_t h) {
+  const uint32_t b1 = (h >> 8) & 0xFFu, b2 = (h >> 16) & 0xFFu, b3 = h >> 24;
+  U8Carry c;
+  c.l4 = b3 >= 0xF0u;
+  c.x = (b3 >= 0xE0u) | (b2 >= 0xF0u);
+  c.pa = (b3 >= 0xC0u) | (b2 >= 0xE0u) | (b1 >= 0xF0u);
+  c.m1 = (b3 == 0xE0u) | (b3 == 0xF0u);
+  c.m2 = (b3 == 0xEDu) | (b3 == 0xF4u);
+  c.m3 = (b3 == 0xF0u) | (b3 == 0xF4u);
+  return c;
 }
 
-JSIDX_DEV Utf8Word utf8_lookup_raw(uint32_t w) {
-  return utf8_lookup(w, (w >> 4) & 0x07070707u, signmask(w));
-}
+JSIDX_DEV bool u8_carry_pending(const U8Carry& c) { return (c.l4 | c.x | c.pa) != 0u; }
 
-// Error bits of word `cur` given the word before it.
-JSIDX_DEV uint32_t utf8_pair_errors(const Utf8Word& prev, const Utf8Word& cur) {
-  uint32_t t1p = prim::alignbyte(cur.t1, prev.t1, 3);
-  uint32_t t2p = prim::alignbyte(cur.t2, prev.t2, 3);
-  uint32_t special = t1p & t2p & cur.t3;
-  uint32_t must = (prim::alignbyte(cur.gE, prev.gE, 2) |
-                   prim::alignbyte(cur.gF, prev.gF, 1)) & 0x80808080u;
-  return special ^ must;
+JSIDX_DEV uint32_t utf8_errors(const uint32_t p[8], uint32_t D, uint32_t E, U8Carry* c) {
+  const uint32_t cont = p[7] & ~p[6];
+  const uint32_t lead = p[7] & p[6];
+  const uint32_t L3 = lead & p[5];
+  const uint32_t L4 = L3 & p[4];
+  const uint32_t A1 = shift_in1(L4, &c->l4) & ~D;        // a 4-byte lead one back
+  const uint32_t A2 = shift_in1(L3 | A1, &c->x) & ~D;    // 3+ lead one back or 4-byte two back
+  const uint32_t PA = lead | A2;                         // the next byte must continue
+  const uint32_t need = shift_in1(PA, &c->pa) & ~D;
+  uint32_t err = (cont ^ need) | (PA & E);
+  err |= lead & ~(p[5] | p[4] | p[3] | p[2] | p[1]);     // C0, C1
+  err |= L4 & (p[3] | (p[2] & (p[1] | p[0])));           // F5..FF
+  const uint32_t lowz = ~(p[3] | p[2] | p[1] | p[0]);
+  const uint32_t x3 = L3 & ~p[4];                        // E0..EF
+  const uint32_t E0 = x3 & lowz;
+  const uint32_t ED = x3 & p[3] & p[2] & ~p[1] & p[0];
+  const uint32_t F0 = L4 & lowz;
+  const uint32_t F4 = L4 & ~p[3] & p[2] & ~p[1] & ~p[0];
+  const uint32_t m1 = shift_in1(E0 | F0, &c->m1) & ~D;   // low second bytes are errors
+  const uint32_t m2 = shift_in1(ED | F4, &c->m2) & ~D;   // high second bytes are errors
+  const uint32_t m3 = shift_in1(F0 | F4, &c->m3) & ~D;   // 4-byte lead: the bound is 0x90
+  const uint32_t hi4 = m3 & p[4];
+  err |= (m1 & ~p[5] & ~hi4) | (m2 & (p[5] | hi4));
+  return err;
 }
 
 }  // namespace jsidx

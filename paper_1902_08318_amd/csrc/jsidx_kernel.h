@@ -198,68 +198,33 @@ JSIDX_DEV uint64_t tail_lanes(uint64_t resets) {
   return ~lanes_below(msb64(resets));
 }
 
-JSIDX_DEV uint32_t wave_sum(uint32_t v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += prim::shfl_xor(v, o);
-  return v;
-}
-JSIDX_DEV uint32_t wave_incl_sum(uint32_t v) {
-  uint32_t lane = prim::lane();
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    uint32_t y = prim::shfl_up(v, o);
-    if (lane >= (uint32_t)o) v += y;
-  }
-  return v;
-}
+JSIDX_DEV uint32_t wave_sum(uint32_t v) { return prim::readlane(prim::incl_scan(v), 63); }
 
-// Segmented exclusive prefix of per-lane counts cv over the row: lanes after
-// the last lane with a document start below them get the row carry cc added.
-// Returns the lane's rank base; *cc becomes the carry after the row.
+// Segmented exclusive prefix of per-lane counts cv over the row: a lane with
+// a document start (bit set in Rs) restarts the sum after it.  Returns the
+// rank base of this lane's first piece (the one continuing from lanes below);
+// *cc (uniform) is the count carried into the row and becomes the carry out.
 JSIDX_DEV uint32_t row_ranks(uint32_t cv, uint64_t Rs, uint32_t* cc) {
-  const uint32_t lane = prim::lane();
-  const uint32_t S = wave_incl_sum(cv);
-  uint32_t Sprev = prim::shfl(S, (int)((lane + 63u) & 63u));
-  if (lane == 0) Sprev = 0u;
-  const uint64_t below = Rs & lt_lanes();
-  const int k = below ? msb64(below) : -1;
-  const uint32_t Sk = prim::shfl(S, k > 0 ? k - 1 : 0);
-  uint32_t cin = Sprev - (k > 0 ? Sk : 0u);
-  if (k < 0) cin += *cc;
-  const uint32_t tot = prim::shfl(S, 63);
-  const int kl = Rs ? msb64(Rs) : -1;
-  const uint32_t Skl = prim::shfl(S, kl > 0 ? kl - 1 : 0);
-  *cc = Rs ? tot - (kl > 0 ? Skl : 0u) : *cc + tot;
+  const uint32_t S = prim::incl_scan(cv);
+  const uint32_t Sx = S - cv;  // sum over the lanes below
+  // The last reset lane below has the largest exclusive sum among the reset
+  // lanes below (+1 so that a sum of 0 still marks it).
+  const uint32_t Mi = prim::incl_max_scan(prim::lane_bit(Rs) ? Sx + 1u : 0u);
+  const uint32_t Me = prim::shr1(Mi, 0u);
+  const uint32_t cin = Me ? Sx - (Me - 1u) : Sx + *cc;
+  const uint32_t tot = prim::readlane(S, 63);
+  if (Rs) *cc = tot - prim::readlane(Sx, msb64(Rs));
+  else *cc += tot;
   return cin;
 }
 
-// Mask bytes of word k (bytes 4k..4k+3 of the segment) by the bit mask keep.
-JSIDX_DEV uint32_t keep_bytes(uint32_t w, uint32_t keep, int k) {
-  return w & nibble_bytemask((keep >> (4 * k)) & 0xFu);
-}
-
-// UTF-8 errors of the bytes kept by `keep` (others read as 0x00), with the
-// word before the segment `halo` and, if tail, a zero word after it.
-JSIDX_DEVFN uint32_t utf8_piece(const uint32_t w[8], uint32_t halo, uint32_t keep, bool tail) {
-  Utf8Word prev = utf8_lookup_raw(halo);
-  uint32_t err = 0;
-#pragma unroll
-  for (int k = 0; k < 8; k++) {
-    uint32_t x = keep_bytes(w[k], keep, k);
-    Utf8Word cur = utf8_lookup_raw(x);
-    err |= utf8_pair_errors(prev, cur);
-    prev = cur;
-  }
-  if (tail) err |= utf8_pair_errors(prev, utf8_lookup_raw(0u));
-  return err;
-}
-
+template <bool INTERIOR>
 JSIDX_DEV void load_segment(const Args& a, int64_t pos, int64_t begin, int64_t end, uint32_t w[8]) {
   const uint8_t* p = a.base + pos;  // 16-byte aligned
 #pragma unroll
   for (int h = 0; h < 2; h++) {
     // only granules overlapping [begin, end) are read
-    if (begin < end && pos + 16 * h < end && pos + 16 * h + 16 > begin) {
+    if (INTERIOR || (begin < end && pos + 16 * h < end && pos + 16 * h + 16 > begin)) {
       uint4 v = prim::load16(p + 16 * h);
       w[4 * h + 0] = v.x; w[4 * h + 1] = v.y; w[4 * h + 2] = v.z; w[4 * h + 3] = v.w;
     } else {
@@ -275,11 +240,12 @@ JSIDX_DEV void load_segment(const Args& a, int64_t pos, int64_t begin, int64_t e
 // head region) are written here too if `defer` is false (st_in and head_base,
 // the head document's count before the tile, are then exact); otherwise
 // their candidate and indexed bits go to LDS for the pass after the look-back.
-// `simple`: no document starts in [P0, P0 + kTileBytes], so every byte of the
-// tile belongs to document hd, which starts at hs (before the tile).
+// SIMPLE: no document starts or ends in [P0, P0 + kTileBytes] and the tile
+// lies inside the input (every byte belongs to document hd, which starts at
+// hs < P0), the escape state entering the tile is known, and defer is set.
+template <bool SIMPLE>
 JSIDX_DEV void tile_local(const Args& a, Shared& sh, int64_t P0, int64_t begin, int64_t end, int64_t d_first,
-                          bool simple, int32_t hd, int64_t hs, uint32_t st_in, bool defer, uint32_t head_base,
-                          TileFacts& T) {
+                          int32_t hd, int64_t hs, uint32_t st_in, bool defer, uint32_t head_base, TileFacts& T) {
   const uint32_t lane = prim::lane();
   uint32_t ce = st_in & 1u, cq = (st_in >> 1) & 1u, cp = (st_in >> 2) & 1u, cu = (st_in >> 3) & 1u;
   uint32_t cc = head_base;  // count of the open document before this row
@@ -287,8 +253,19 @@ JSIDX_DEV void tile_local(const Args& a, Shared& sh, int64_t P0, int64_t begin, 
   T.reset_any = 0; T.r0 = kTileBytes; T.elig0 = 0; T.head_rows = 0; T.a0 = 0; T.a1 = 0; T.tail_count = 0;
   if (lane == 0) sh.he_valid = 0;
 
+  // UTF-8 context entering the tile: the last bytes of the head document
+  // before it (the word lies in the granule before P0, which holds document
+  // bytes since hs < P0)
+  U8Carry uc = u8_carry_zero();
+  if (hs < P0 && begin < end) {
+    uint32_t h = prim::load4(a.base + P0 - 4);
+    const int64_t hlo = hs - (P0 - 4);  // bytes of the word before the document
+    if (hlo > 0) h &= hlo >= 4 ? 0u : (~0u << (8 * hlo));
+    uc = u8_carry_from_word(h);
+  }
+
   uint32_t wn[8];
-  load_segment(a, P0 + (int64_t)lane * kSegBytes, begin, end, wn);
+  load_segment<SIMPLE>(a, P0 + (int64_t)lane * kSegBytes, begin, end, wn);
 #pragma unroll 1
   for (int r = 0; r < kRows; r++) {
     const int32_t rel = r * kRowBytes + (int32_t)lane * kSegBytes;  // tile-relative
@@ -296,154 +273,159 @@ JSIDX_DEV void tile_local(const Args& a, Shared& sh, int64_t P0, int64_t begin, 
     uint32_t w[8];
 #pragma unroll
     for (int k = 0; k < 8; k++) w[k] = wn[k];
-    if (r + 1 < kRows) load_segment(a, pos + kRowBytes, begin, end, wn);  // prefetch
+    if (r + 1 < kRows) load_segment<SIMPLE>(a, pos + kRowBytes, begin, end, wn);  // prefetch
 
     // documents: starts in this segment (D), start right after it (d32),
     // document holding byte 0 (head), valid bytes (V)
     int32_t head = hd;
-    uint32_t D = 0, d32 = 0;
-    uint32_t V = ~0u;
-    int64_t head_start = hs;
-    if (!simple) {
-    head = doc_at(a, sh, P0, d_first, rel);
-    for (int32_t i = head < 0 ? 0 : head;; i++) {
-      int64_t o;
-      if (!sh.overflow) {
-        if (i >= sh.ntab) break;
-        o = i == 0 ? sh.first_off : (int64_t)sh.tab[i] + P0;
-      } else {
-        if (d_first + i > (int64_t)a.ndocs) break;
-        o = doc_off(a, d_first + i);
-      }
-      if (o < pos) continue;
-      if (o > pos + 32) break;
-      if (o == pos + 32) d32 = 1; else D |= 1u << (uint32_t)(o - pos);
-    }
-    const int64_t vlo = begin - pos, vhi = end - pos;
-    V = ge_mask((uint32_t)(vlo < 0 ? 0 : (vlo > 32 ? 32 : vlo))) &
-        lt_mask((uint32_t)(vhi < 0 ? 0 : (vhi > 32 ? 32 : vhi)));
-    if (head >= 0 && d_first + head >= (int64_t)a.ndocs) head = -1;
-    if (head >= 0) head_start = doc_start(a, sh, P0, d_first, head);
-    }
-
-    // The 4 bytes before the segment, as far as they belong to the document
-    // holding byte 0 (UTF-8 context); 0x00 otherwise.
-    uint32_t halo = 0;
-    if (head >= 0 && !(D & 1u) && begin < end && pos > begin && pos - 16 < end) {
-      halo = prim::load4(a.base + pos - 4);
-      const int64_t hlo = head_start - (pos - 4);  // halo bytes before the document
-      if (hlo > 0) halo &= hlo >= 4 ? 0u : (~0u << (8 * hlo));
-    }
-    if (V != ~0u) {
-#pragma unroll
-      for (int k = 0; k < 8; k++) w[k] = keep_bytes(w[k], V, k);
-    }
-
-    uint32_t hidx[8], sgn[8];
-    const ClassMasks cm = classify_segment(w, hidx, sgn);
-
-    // UTF-8 errors per piece (pieces start at bit 0 and at every document
-    // start); rows without non-ASCII bytes skip the check.
-    uint32_t UE = 0;
-    const bool need = (cm.hi | (halo & 0x80808080u)) != 0u;
-    if (prim::ballot(need) != 0ull) {
-      if (D == 0 && !d32) {
-        Utf8Word prev = utf8_lookup_raw(halo);
-        uint32_t err = 0;
-#pragma unroll
-        for (int k = 0; k < 8; k++) {
-          Utf8Word cur = utf8_lookup(w[k], hidx[k], sgn[k]);
-          err |= utf8_pair_errors(prev, cur);
-          prev = cur;
+    uint32_t D = 0, d32 = 0, V = ~0u;
+    if constexpr (!SIMPLE) {
+      head = doc_at(a, sh, P0, d_first, rel);
+      for (int32_t i = head < 0 ? 0 : head;; i++) {
+        int64_t o;
+        if (!sh.overflow) {
+          if (i >= sh.ntab) break;
+          o = i == 0 ? sh.first_off : (int64_t)sh.tab[i] + P0;
+        } else {
+          if (d_first + i > (int64_t)a.ndocs) break;
+          o = doc_off(a, d_first + i);
         }
-        UE = err ? 1u : 0u;
-      } else {
-        uint32_t starts = D | 1u;
-        while (starts) {
-          const uint32_t st = (uint32_t)__builtin_ctz(starts);
-          starts &= starts - 1u;
-          const uint32_t nx = starts ? (uint32_t)__builtin_ctz(starts) : 32u;
-          const bool ends_doc = nx < 32u || d32;
-          const uint32_t hh = (st == 0 && !(D & 1u)) ? halo : 0u;
-          if (utf8_piece(w, hh, ge_mask(st) & lt_mask(nx), ends_doc)) UE |= 1u << st;
-        }
+        if (o < pos) continue;
+        if (o > pos + 32) break;
+        if (o == pos + 32) d32 = 1; else D |= 1u << (uint32_t)(o - pos);
       }
+      const int64_t vlo = begin - pos, vhi = end - pos;
+      V = ge_mask((uint32_t)(vlo < 0 ? 0 : (vlo > 32 ? 32 : vlo))) &
+          lt_mask((uint32_t)(vhi < 0 ? 0 : (vhi > 32 ? 32 : vhi)));
+      if (head >= 0 && d_first + head >= (int64_t)a.ndocs) head = -1;
+    }
+
+    uint32_t pl[8];
+    bit_planes(w, pl);
+    if constexpr (!SIMPLE) {
+      if (V != ~0u) {
+#pragma unroll
+        for (int k = 0; k < 8; k++) pl[k] &= V;
+      }
+    }
+    const ClassMasks cm = classify_planes(pl);
+
+    // UTF-8: rows without non-ASCII bytes and with no sequence open from the
+    // row before have no errors
+    uint32_t errm = 0;
+    if (prim::ballot(pl[7] != 0u) != 0ull || u8_carry_pending(uc)) {
+      errm = utf8_errors(pl, D, SIMPLE ? 0u : ((D >> 1) | (d32 << 31)), &uc);
+    } else {
+      uc = u8_carry_zero();
     }
 
     // escapes: a segment with a non-backslash byte or a document start fixes
     // the escape state after it; an all-backslash segment (even length) keeps it
-    const bool isconst = (cm.B != ~0u) || (D != 0u);
-    const uint32_t hi_reset = D ? 31u - (uint32_t)__builtin_clz(D) : 0u;
-    const uint32_t nb = ~(cm.B & ge_mask(hi_reset));
-    const uint32_t eo = (nb ? (uint32_t)__builtin_clz(nb) : 32u) & 1u;
-    const uint64_t Kc = prim::ballot(isconst);
-    const uint64_t Ec = prim::ballot(eo != 0u);
-    const uint64_t mk = Kc & lt_lanes();
-    const uint32_t e_in = mk ? (uint32_t)((Ec >> msb64(mk)) & 1ull) : ce;
-    if (!T.any_const && Kc) {
-      const int f = __builtin_ctzll(Kc);
-      const uint32_t pl = (uint32_t)__builtin_ctz(~cm.B | D);
-      const uint32_t pf = prim::shfl(pl, f);
-      const uint32_t rf = prim::shfl((D >> pl) & 1u, f);
-      const uint32_t qf = prim::shfl((cm.Q >> pl) & 1u, f);
-      T.lead_pos = (uint32_t)(r * kRowBytes + f * kSegBytes) + pf;
-      T.lead_reset = rf;
-      T.qsens = rf ? 0u : qf;
-      T.any_const = 1;
+    uint32_t e_in = 0, OD = 0, EA = 0;
+    bool done_e = false;
+    if constexpr (SIMPLE) {
+      if (prim::ballot(cm.B != 0u) == 0ull) {
+        e_in = lane == 0 ? ce : 0u;
+        OD = e_in;
+        ce = 0u;
+        done_e = true;
+      } else if (prim::ballot(cm.B == ~0u) == 0ull) {
+        const uint32_t eo = (uint32_t)__builtin_clz(~cm.B) & 1u;  // trailing run is odd
+        e_in = shift_in1(eo << 31, &ce) & 1u;
+        OD = odd_run_ends(cm.B & ~e_in) | e_in;
+        done_e = true;
+      }
     }
-    if (Kc) ce = (uint32_t)((Ec >> msb64(Kc)) & 1ull);
-
-    uint32_t EA;
-    const uint32_t OD = escaped_bytes(cm.B, D, e_in, &EA);
+    if (!done_e) {
+      const bool isconst = (cm.B != ~0u) || (D != 0u);
+      const uint32_t hi_reset = D ? 31u - (uint32_t)__builtin_clz(D) : 0u;
+      const uint32_t nb = ~(cm.B & ge_mask(hi_reset));
+      const uint32_t eo = (nb ? (uint32_t)__builtin_clz(nb) : 32u) & 1u;
+      const uint64_t Kc = prim::ballot(isconst);
+      const uint64_t Ec = prim::ballot(eo != 0u);
+      const uint64_t mk = Kc & lt_lanes();
+      e_in = mk ? (uint32_t)((Ec >> msb64(mk)) & 1ull) : ce;
+      if (!SIMPLE && !T.any_const && Kc) {
+        const int f = __builtin_ctzll(Kc);
+        const uint32_t pl0 = (uint32_t)__builtin_ctz(~cm.B | D);
+        const uint32_t pf = prim::readlane(pl0, f);
+        const uint32_t rf = prim::readlane((D >> pl0) & 1u, f);
+        const uint32_t qf = prim::readlane((cm.Q >> pl0) & 1u, f);
+        T.lead_pos = (uint32_t)(r * kRowBytes + f * kSegBytes) + pf;
+        T.lead_reset = rf;
+        T.qsens = rf ? 0u : qf;
+        T.any_const = 1;
+      }
+      if (Kc) ce = (uint32_t)((Ec >> msb64(Kc)) & 1ull);
+      OD = escaped_bytes(cm.B, D, e_in, &EA);
+    }
     const uint32_t Q = cm.Q & ~OD;
 
     // string ranges: prefix XOR, restarted at document starts
     const uint32_t PX = prefix_xor(Q);
-    uint32_t corr = 0, c_old = 0, rest = D;
-    while (rest) {
-      const uint32_t d = (uint32_t)__builtin_ctz(rest);
-      rest &= rest - 1u;
-      const uint32_t c_new = d ? ((PX >> (d - 1u)) & 1u) : 0u;
-      if (c_new != c_old) corr ^= ge_mask(d);
-      c_old = c_new;
+    uint32_t R0 = PX;
+    uint64_t Rs = 0;
+    uint32_t uin = 0, first_reset = 32u, last_start = 0;
+    if constexpr (SIMPLE) {
+      const uint64_t Qb = prim::ballot((__builtin_popcount(Q) & 1u) != 0u);
+      const uint32_t qin = (prim::mbcnt(Qb) & 1u) ^ cq;
+      R0 ^= 0u - qin;
+      cq ^= parity64(Qb);
+      if (prim::ballot(errm != 0u)) cu = 1u;
+    } else {
+      uint32_t corr = 0, c_old = 0, rest = D;
+      while (rest) {
+        const uint32_t d = (uint32_t)__builtin_ctz(rest);
+        rest &= rest - 1u;
+        const uint32_t c_new = d ? ((PX >> (d - 1u)) & 1u) : 0u;
+        if (c_new != c_old) corr ^= ge_mask(d);
+        c_old = c_new;
+      }
+      R0 = PX ^ corr;
+      last_start = D ? 31u - (uint32_t)__builtin_clz(D) : 0u;
+      const uint32_t qv = D ? (R0 >> 31) : (uint32_t)(__builtin_popcount(Q) & 1);
+      const uint32_t uv = (errm & ge_mask(last_start)) != 0u;
+      Rs = prim::ballot(D != 0u);
+      const uint64_t Qv = prim::ballot(qv != 0u);
+      const uint64_t Uv = prim::ballot(uv != 0u);
+      bool from_carry;
+      const uint64_t sp = span_since_reset(Rs, &from_carry);
+      uint32_t qin = parity64(Qv & sp);
+      uin = (Uv & sp) ? 1u : 0u;
+      if (from_carry) { qin ^= cq; uin |= cu; }
+      first_reset = D ? (uint32_t)__builtin_ctz(D) : 32u;
+      if (qin) R0 ^= lt_mask(first_reset);
+      const uint64_t tl = tail_lanes(Rs);
+      if (Rs) { cq = parity64(Qv & tl); cu = (Uv & tl) ? 1u : 0u; }
+      else { cq ^= parity64(Qv); cu |= Uv ? 1u : 0u; }
     }
-    uint32_t R0 = PX ^ corr;
-    const uint32_t qv = D ? (R0 >> 31) : (uint32_t)(__builtin_popcount(Q) & 1);
-    const uint32_t last_start = D ? 31u - (uint32_t)__builtin_clz(D) : 0u;
-    const uint32_t uv = (UE >> last_start) & 1u;
-    const uint32_t P0m = cm.C | cm.W | Q;
 
-    const uint64_t Rs = prim::ballot(D != 0u);
-    const uint64_t Qv = prim::ballot(qv != 0u);
-    const uint64_t Uv = prim::ballot(uv != 0u);
-    const uint64_t Pb = prim::ballot((P0m >> 31) != 0u);
-    bool from_carry;
-    const uint64_t sp = span_since_reset(Rs, &from_carry);
-    uint32_t qin = parity64(Qv & sp);
-    uint32_t uin = (Uv & sp) ? 1u : 0u;
-    if (from_carry) { qin ^= cq; uin |= cu; }
-    const uint32_t first_reset = D ? (uint32_t)__builtin_ctz(D) : 32u;
-    if (qin) R0 ^= lt_mask(first_reset);
-    const uint32_t pin = lane ? (uint32_t)((Pb >> (lane - 1)) & 1ull) : cp;
-    const uint32_t PR = ((P0m << 1) | pin) | D;
-    const uint64_t tl = tail_lanes(Rs);
-    if (Rs) { cq = parity64(Qv & tl); cu = (Uv & tl) ? 1u : 0u; }
-    else { cq ^= parity64(Qv); cu |= Uv ? 1u : 0u; }
-    cp = (uint32_t)(Pb >> 63);
+    // pseudo-structural candidates: the byte before is structural, white
+    // space or a quote (or the byte starts a document)
+    const uint32_t P0m = cm.C | cm.W | Q;
+    const uint32_t PR = shift_in1(P0m, &cp) | D;
 
     if (r == 0) {
       const uint32_t other0 = (V & 1u) && !(D & 1u) && !((cm.C | cm.W | cm.Q) & 1u);
-      T.elig0 = prim::shfl(other0, 0);
+      T.elig0 = prim::readlane(other0, 0);
     }
+    const uint32_t K = (cm.C | Q | (PR & ~P0m)) & V;
+    const uint32_t F0 = K & ~(Q ^ R0);
+    if constexpr (SIMPLE) {
+      sh.hK[r][lane] = K;
+      sh.hF[r][lane] = F0;
+      T.head_rows = (uint32_t)r + 1u;
+      T.a0 += (uint32_t)__builtin_popcount(F0);
+      T.a1 += (uint32_t)__builtin_popcount(K & ~F0);
+      continue;
+    }
+
     const bool had_reset = T.reset_any != 0;
     if (Rs && !had_reset) {
       const int fl = __builtin_ctzll(Rs);
-      T.r0 = (uint32_t)(r * kRowBytes + fl * kSegBytes) + prim::shfl(first_reset, fl);
+      T.r0 = (uint32_t)(r * kRowBytes + fl * kSegBytes) + prim::readlane(first_reset, fl);
       T.reset_any = 1;
     }
-
-    const uint32_t K = (cm.C | Q | (PR & ~P0m)) & V;
-    const uint32_t F0 = K & ~(Q ^ R0);
     // head region of this lane: tile positions before the first document start
     const uint32_t hm = (uint32_t)rel >= T.r0 ? 0u : (T.r0 - (uint32_t)rel >= 32u ? ~0u : lt_mask(T.r0 - (uint32_t)rel));
     const bool row_has_head = !had_reset;
@@ -468,6 +450,8 @@ JSIDX_DEV void tile_local(const Args& a, Shared& sh, int64_t P0, int64_t begin, 
       const uint32_t nx = starts ? (uint32_t)__builtin_ctz(starts) : 32u;
       const bool ends_doc = nx < 32u || d32;
       const bool cont = (st == 0 && !(D & 1u));  // continues the previous lane's document
+      const uint32_t segm = ge_mask(st) & lt_mask(nx);
+      const uint32_t pu = ((errm & segm) != 0u ? 1u : 0u) | (cont ? uin : 0u);
       const bool deferred = defer && ((hm >> st) & 1u);
       if (deferred) {
         // the head document ends inside the head region: keep its flags
@@ -475,7 +459,7 @@ JSIDX_DEV void tile_local(const Args& a, Shared& sh, int64_t P0, int64_t begin, 
           const uint32_t e = nx - 1u;
           sh.he_R0 = (R0 >> e) & 1u;
           sh.he_EA = (EA >> e) & 1u;
-          sh.he_u = ((UE >> st) & 1u) | (cont ? uin : 0u);
+          sh.he_u = pu;
           sh.he_valid = 1;
         }
         continue;
@@ -486,7 +470,7 @@ JSIDX_DEV void tile_local(const Args& a, Shared& sh, int64_t P0, int64_t begin, 
       const int64_t doff = doc_start(a, sh, P0, d_first, dloc);
       uint32_t* out = a.out_idx + doff;
       const uint32_t rel_doc = (uint32_t)(pos - doff);
-      uint32_t f = F0 & wmask & ge_mask(st) & lt_mask(nx);
+      uint32_t f = F0 & wmask & segm;
       uint32_t kk = cont ? cin : 0u;
       while (f) {
         const uint32_t j = (uint32_t)__builtin_ctz(f);
@@ -497,7 +481,7 @@ JSIDX_DEV void tile_local(const Args& a, Shared& sh, int64_t P0, int64_t begin, 
       if (ends_doc) {
         const uint32_t e = nx - 1u;
         uint32_t err = 0;
-        if (((UE >> st) & 1u) | (cont ? uin : 0u)) err |= JSIDX_ERR_UTF8;
+        if (pu) err |= JSIDX_ERR_UTF8;
         if ((R0 >> e) & 1u) err |= JSIDX_ERR_UNCLOSED_STRING;
         if ((EA >> e) & 1u) err |= JSIDX_ERR_TRAILING_ESCAPE;
         if (kk == 0) err |= JSIDX_ERR_EMPTY;
@@ -580,6 +564,32 @@ JSIDX_DEV void look_back(Workspace* ws, int64_t t, uint32_t epoch, uint32_t* s_o
     uint64_t d[4];
 #pragma unroll
     for (int m = 0; m < 4; m++) d[m] = (j0 - m >= 0) ? ld_desc(ws, j0 - m) : 0ull;
+    // Ready when some lane holds an inclusive descriptor and every descriptor
+    // newer than the newest one is published: only then fold (a failed poll
+    // costs a few operations).
+    {
+      uint32_t m_inc = 4, m_none = 4;  // newest inclusive / unpublished in this lane
+#pragma unroll
+      for (int m = 3; m >= 0; m--) {
+        if (j0 - m < 0) continue;
+        const uint32_t fl = d_current(d[m], epoch) ? d_flag(d[m]) : (uint32_t)kNone;
+        if (fl == kInc) m_inc = (uint32_t)m;
+        if (fl == kNone) m_none = (uint32_t)m;
+      }
+      const uint64_t Ki = prim::ballot(m_inc < 4u);
+      const int ki = Ki ? __builtin_ctzll(Ki) : 64;
+      const uint64_t Pn = prim::ballot(m_none < m_inc) & (lanes_below(ki) | (ki < 64 ? (1ull << ki) : 0ull));
+      if (Ki == 0ull || Pn != 0ull) {
+        prim::trace_count(t, 8);
+        if (polls > prim::kSpinLimit) {  // never expected: give up, flag it
+          prim::st_agent32(&ws->diag, 1u);
+          *s_out = 0; *base_out = 0;
+          return;
+        }
+        prim::sleep();
+        continue;
+      }
+    }
 #pragma unroll
     for (int m = 3; m >= 0; m--) {
       const bool valid = j0 - m >= 0;
@@ -602,8 +612,8 @@ JSIDX_DEV void look_back(Workspace* ws, int64_t t, uint32_t epoch, uint32_t* s_o
       continue;
     }
     // known start: lane k, after its newest tile
-    const uint32_t ks = prim::shfl(L.ks, k), kc = prim::shfl(L.kc, k);
-    const uint32_t kblk = prim::shfl(L.blocked ? 1u : 0u, k);
+    const uint32_t ks = prim::readlane(L.ks, k), kc = prim::readlane(L.kc, k);
+    const uint32_t kblk = prim::readlane(L.blocked ? 1u : 0u, k);
     // lanes below k are transfers; lane 0 is the newest
     const uint64_t Ec = prim::ballot(L.has && L.fec) & below;
     const uint64_t Ev = prim::ballot(L.fev != 0u);
@@ -638,7 +648,7 @@ JSIDX_DEV void look_back(Workspace* ws, int64_t t, uint32_t epoch, uint32_t* s_o
       const uint32_t e_after = L.fec ? L.fev : e_ent;
       const uint32_t q_after = L.fr ? L.fq : (q_ent ^ L.fq);
       const uint32_t u_after = L.fr ? L.fu : (u_ent | L.fu);
-      st0 = prim::shfl(e_after | (q_after << 1) | (L.fp << 2) | (u_after << 3), 0);
+      st0 = prim::readlane(e_after | (q_after << 1) | (L.fp << 2) | (u_after << 3), 0);
     }
     if (any_blk) {
       // some tile's counts depend on an escape that turned out to be set; that
@@ -785,7 +795,7 @@ JSIDX_DEVFN void index_tiles(const Args& a) {
           const uint64_t notfull = ~full;
           if (notfull) {
             const int f = __builtin_ctzll(notfull);
-            const uint32_t run = (uint32_t)f * 16u + prim::shfl(trail, f);
+            const uint32_t run = (uint32_t)f * 16u + prim::readlane(trail, f);
             e_T = run & 1u;  // runs of whole steps are even
             e_known = 1;
             break;
@@ -798,41 +808,47 @@ JSIDX_DEVFN void index_tiles(const Args& a) {
     TileFacts T;
     uint32_t s_in = 0, base = 0;
     bool exact = (t == 0);  // tile 0's carry-in is the initial state
-    const bool simple = !sh.overflow && sh.ntab == 1 && sh.tab[0] < 0 && hd_ok;
-    tile_local(a, sh, P0, begin, end, d_first, simple, hd, hs, e_T, !exact, 0u, T);
-    prim::trace(t, 2);
-    uint32_t table = 0, cnt0 = 0, cnt1 = 0;
-    {
-      const uint32_t q0 = (T.carry >> 1) & 1u, p0 = (T.carry >> 2) & 1u, u0 = (T.carry >> 3) & 1u;
-      const uint32_t e_last = T.carry & 1u;
-      table = T.reset_any | (u0 << 1);
+    const bool simple = !sh.overflow && sh.ntab == 1 && sh.tab[0] < 0 && hd_ok && e_known && !exact;
+    uint32_t table = 0, cnt0 = 0, cnt1 = 0, esens = 0;
+    // pass 0: the local pass with the escape state read before the tile;
+    // pass 1 (rare): an exact local pass, when the escape carried in turned
+    // out to change this tile's head
+    for (int pass = 0;; pass++) {
+      if (pass == 0 && simple) tile_local<true>(a, sh, P0, begin, end, d_first, hd, hs, e_T, true, 0u, T);
+      else tile_local<false>(a, sh, P0, begin, end, d_first, hd, hs, pass ? s_in : e_T, pass ? false : !exact,
+                             pass ? base : 0u, T);
+      if (pass == 1) {
+        exact = true;
+        break;
+      }
+      prim::trace(t, 2);
+      {
+        const uint32_t q0 = (T.carry >> 1) & 1u, p0 = (T.carry >> 2) & 1u, u0 = (T.carry >> 3) & 1u;
+        const uint32_t e_last = T.carry & 1u;
+        table = T.reset_any | (u0 << 1);
 #pragma unroll
-      for (uint32_t e = 0; e < 2; e++) {
-        // with the incoming escape known, both entries are the tile's outcome
-        const uint32_t eo = (T.any_const || e_known) ? e_last : e;
-        const uint32_t flip = e_known ? 0u : (e & T.qsens);
-        const uint32_t qo = T.reset_any ? q0 : (q0 ^ flip);
-        const uint32_t po = p0 ^ (flip & (T.lead_pos == (uint32_t)kTileBytes - 1u ? 1u : 0u));
-        table |= (eo | (qo << 1) | (po << 2)) << (2 + 3 * e);
+        for (uint32_t e = 0; e < 2; e++) {
+          // with the incoming escape known, both entries are the tile's outcome
+          const uint32_t eo = (T.any_const || e_known) ? e_last : e;
+          const uint32_t flip = e_known ? 0u : (e & T.qsens);
+          const uint32_t qo = T.reset_any ? q0 : (q0 ^ flip);
+          const uint32_t po = p0 ^ (flip & (T.lead_pos == (uint32_t)kTileBytes - 1u ? 1u : 0u));
+          table |= (eo | (qo << 1) | (po << 2)) << (2 + 3 * e);
+        }
+        if (T.reset_any) {
+          cnt0 = cnt1 = T.tail_count;
+        } else if (!exact) {
+          cnt0 = wave_sum(T.a0);
+          cnt1 = wave_sum(T.a1);
+        }
       }
-      if (T.reset_any) {
-        cnt0 = cnt1 = T.tail_count;
-      } else if (!exact) {
-        cnt0 = wave_sum(T.a0);
-        cnt1 = wave_sum(T.a1);
-      }
-    }
-    const uint32_t esens = e_known ? 0u : (T.qsens | ((T.lead_reset && T.lead_pos > 0) ? 1u : 0u));
-    if (!exact) {
+      esens = e_known ? 0u : (T.qsens | ((T.lead_reset && T.lead_pos > 0) ? 1u : 0u));
+      if (exact) break;
       if (lane == 0) st_desc(ws, t, make_agg(table, cnt0, cnt1, T.elig0, esens, epoch));
       look_back(ws, t, epoch, &s_in, &base);
       prim::trace(t, 3);
-      if ((s_in & 1u) && esens) {
-        // the escape carried in changes this tile's head: redo it exactly
-        prim::trace_count(t, 9);
-        tile_local(a, sh, P0, begin, end, d_first, simple, hd, hs, s_in, false, base, T);
-        exact = true;
-      }
+      if (!((s_in & 1u) && esens)) break;
+      prim::trace_count(t, 9);
     }
 
     // ---- own inclusive value -------------------------------------------------
@@ -849,32 +865,46 @@ JSIDX_DEVFN void index_tiles(const Args& a) {
     prim::trace(t, 4);
 
     // ---- head region: positions and the head document's result ---------------
-    if (!exact) {
+    const bool hvalid = hd_ok && T.r0 > 0;
+    if (!exact && hvalid) {
       const uint32_t qT = (s_in >> 1) & 1u;
       const uint32_t pfix = (((s_in >> 2) & 1u) && T.elig0 && !qT) ? 1u : 0u;
       const uint32_t uT = (s_in >> 3) & 1u;
-      const bool hvalid = hd_ok && T.r0 > 0;
-      const int64_t hoff = hvalid ? hs : 0;
+      uint32_t* out = a.out_idx + hs;
+      // ranks of the head document stay below end - hs unless a look-back
+      // wait gave up; rows that could pass it check every write
+      const uint64_t lim = (uint64_t)(end - hs);
+      const uint32_t rel0 = (uint32_t)(P0 - hs) + lane * (uint32_t)kSegBytes;
       uint32_t cc = base;
 #pragma unroll 1
       for (uint32_t r = 0; r < T.head_rows; r++) {
         const uint32_t hK = sh.hK[r][lane], hF = sh.hF[r][lane];
         uint32_t F = qT ? (hF ^ hK) : hF;
         if (r == 0 && lane == 0) F |= pfix;
-        const uint32_t cin = row_ranks((uint32_t)__builtin_popcount(F), 0ull, &cc);
-        if (!hvalid) continue;
-        const int64_t pos = P0 + (int64_t)r * kRowBytes + (int64_t)lane * kSegBytes;
-        uint32_t* out = a.out_idx + hoff;
-        const uint32_t rel_doc = (uint32_t)(pos - hoff);
-        uint32_t kk = cin;
-        while (F) {
-          const uint32_t j = (uint32_t)__builtin_ctz(F);
-          F &= F - 1u;
-          if ((uint64_t)(hoff + kk) < (uint64_t)end) prim::st_out(out + kk, rel_doc + j);
-          kk++;
+        const uint32_t n = (uint32_t)__builtin_popcount(F);
+        const uint32_t incl = prim::incl_scan(n);
+        const uint32_t row_n = prim::readlane(incl, 63);
+        uint32_t kk = cc + incl - n;
+        const bool checked = (uint64_t)cc + row_n > lim;
+        cc += row_n;
+        const uint32_t rel = rel0 + r * (uint32_t)kRowBytes;
+        if (!checked) {
+          while (F) {
+            const uint32_t j = (uint32_t)__builtin_ctz(F);
+            F &= F - 1u;
+            prim::st_out(out + kk, rel + j);
+            kk++;
+          }
+        } else {
+          while (F) {
+            const uint32_t j = (uint32_t)__builtin_ctz(F);
+            F &= F - 1u;
+            if ((uint64_t)kk < lim) prim::st_out(out + kk, rel + j);
+            kk++;
+          }
         }
       }
-      if (hvalid && sh.he_valid && lane == 0) {
+      if (sh.he_valid && lane == 0) {
         uint32_t err = 0;
         if (sh.he_u | uT) err |= JSIDX_ERR_UTF8;
         if (sh.he_R0 ^ qT) err |= JSIDX_ERR_UNCLOSED_STRING;

@@ -27,6 +27,36 @@ JSIDX_DEV uint64_t ballot(bool p) { return __ballot(p); }
 JSIDX_DEV uint32_t shfl(uint32_t v, int src) { return (uint32_t)__shfl((int)v, src); }
 JSIDX_DEV uint32_t shfl_up(uint32_t v, int d) { return (uint32_t)__shfl_up((int)v, d); }
 JSIDX_DEV uint32_t shfl_xor(uint32_t v, int m) { return (uint32_t)__shfl_xor((int)v, m); }
+// Bit `lane` of a wave-uniform mask (v_cndmask on the mask as a lane mask).
+JSIDX_DEV bool lane_bit(uint64_t m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
+// Set bits of m below this lane.
+JSIDX_DEV uint32_t mbcnt(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+JSIDX_DEV uint32_t readlane(uint32_t v, int l) { return __builtin_amdgcn_readlane(v, l); }
+// Inclusive prefix sum over the wave: DPP row shifts 1, 2, 4, 8 inside rows of
+// 16 lanes, then row broadcasts of lanes 15 and 31.
+JSIDX_DEV uint32_t incl_scan(uint32_t v) {
+  v += __builtin_amdgcn_update_dpp(0u, v, 0x111, 0xF, 0xF, false);
+  v += __builtin_amdgcn_update_dpp(0u, v, 0x112, 0xF, 0xF, false);
+  v += __builtin_amdgcn_update_dpp(0u, v, 0x114, 0xF, 0xF, false);
+  v += __builtin_amdgcn_update_dpp(0u, v, 0x118, 0xF, 0xF, false);
+  v += __builtin_amdgcn_update_dpp(0u, v, 0x142, 0xA, 0xF, false);
+  v += __builtin_amdgcn_update_dpp(0u, v, 0x143, 0xC, 0xF, false);
+  return v;
+}
+// Inclusive prefix maximum over the wave (same DPP pattern).
+JSIDX_DEV uint32_t incl_max_scan(uint32_t v) {
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0u, v, 0x111, 0xF, 0xF, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0u, v, 0x112, 0xF, 0xF, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0u, v, 0x114, 0xF, 0xF, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0u, v, 0x118, 0xF, 0xF, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0u, v, 0x142, 0xA, 0xF, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0u, v, 0x143, 0xC, 0xF, false));
+  return v;
+}
+// Value of the previous lane (DPP wave_shr:1); lane 0 gets `fill`.
+JSIDX_DEV uint32_t shr1(uint32_t v, uint32_t fill) { return __builtin_amdgcn_update_dpp(fill, v, 0x138, 0xF, 0xF, false); }
 
 JSIDX_DEV void sync() { __syncthreads(); }
 JSIDX_DEV int sync_count(bool p) { return __syncthreads_count(p); }

@@ -150,6 +150,34 @@ inline uint32_t shfl_up(uint32_t v, int d) {
   return exchange(v, src < 0 ? (int)lane() : src);
 }
 inline uint32_t shfl_xor(uint32_t v, int m) { return exchange(v, (int)(lane() ^ (uint32_t)m)); }
+inline bool lane_bit(uint64_t m) { return (m >> lane()) & 1ull; }
+inline uint32_t mbcnt(uint64_t m) {
+  const uint32_t l = lane();
+  return (uint32_t)__builtin_popcountll(l ? (m & (~0ull >> (64 - l))) : 0ull);
+}
+inline uint32_t readlane(uint32_t v, int l) { return exchange(v, l); }
+inline uint32_t incl_max_scan(uint32_t v) {
+  WaveCtx& w = wave();
+  w.slot[lane()] = v;
+  w.bar.wait();
+  uint32_t s = 0;
+  for (uint32_t i = 0; i <= lane(); i++) s = s > (uint32_t)w.slot[i] ? s : (uint32_t)w.slot[i];
+  w.bar.wait();
+  return s;
+}
+inline uint32_t shr1(uint32_t v, uint32_t fill) {
+  uint32_t r = exchange(v, lane() == 0 ? 0 : (int)lane() - 1);
+  return lane() == 0 ? fill : r;
+}
+inline uint32_t incl_scan(uint32_t v) {
+  WaveCtx& w = wave();
+  w.slot[lane()] = v;
+  w.bar.wait();
+  uint32_t s = 0;
+  for (uint32_t i = 0; i <= lane(); i++) s += (uint32_t)w.slot[i];
+  w.bar.wait();
+  return s;
+}
 
 inline void sync() { tctx.g->bar.wait(); }
 inline int sync_count(bool p) {

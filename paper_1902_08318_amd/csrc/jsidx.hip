@@ -50,7 +50,7 @@ uint64_t tiles_for(uint64_t total_len) {
   return t ? t : 1;
 }
 
-size_t ws_bytes_for_tiles(uint64_t tiles) { return sizeof(Workspace) + (size_t)tiles * sizeof(uint64_t); }
+size_t ws_bytes_for_tiles(uint64_t tiles) { return (size_t)workspace_bytes(tiles); }
 
 int slots_for_device(int dev) {
   if (dev < 0 || dev >= 64) return 1024;

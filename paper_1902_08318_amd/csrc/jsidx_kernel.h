@@ -31,6 +31,13 @@ constexpr int kTileBytes = kRows * kRowBytes;  // 32 KiB
 constexpr int kDocCap = 256;                   // documents per tile held in LDS
 constexpr int kScrub = 4096;                   // descriptors cleared per launch
 constexpr int kEscSteps = 4;                   // backslash run scanned back: 4 x 1 KiB
+// Tiles per look-back block (at most 4 per lane); test builds shrink it to
+// reach many blocks with small inputs.
+#ifndef JSIDX_BLOCK_TILES
+#define JSIDX_BLOCK_TILES 256
+#endif
+constexpr int kBlockTiles = JSIDX_BLOCK_TILES;
+static_assert(kBlockTiles >= 1 && kBlockTiles <= 256, "a block must fit one look-back window");
 static_assert(kTileBytes < 65536, "tile counts must fit in 16 bits");
 
 // ---- tile descriptors for the look-back ----------------------------------
@@ -44,6 +51,8 @@ enum : uint32_t { kNone = 0, kAgg = 1, kInc = 2 };
 constexpr uint32_t kEpochShift = 44;
 constexpr uint64_t kEpochMask = (1ull << 20) - 1;
 
+// Workspace: this header, then cap_tiles tile descriptors, 3 words per block
+// of block descriptors, and one 32-bit counter per block.
 struct Workspace {
   uint32_t ticket;  // next tile to hand out
   uint32_t done;    // workgroups that have left the tile loop
@@ -51,6 +60,11 @@ struct Workspace {
   uint32_t diag;    // sticky: 1 = a look-back wait gave up (never expected)
   uint64_t desc[1];  // one per tile
 };
+
+inline constexpr uint64_t blocks_for_tiles(uint64_t tiles) { return (tiles + kBlockTiles - 1) / kBlockTiles; }
+inline constexpr uint64_t workspace_bytes(uint64_t tiles) {
+  return sizeof(Workspace) + tiles * sizeof(uint64_t) + blocks_for_tiles(tiles) * (3 * sizeof(uint64_t) + sizeof(uint32_t));
+}
 
 JSIDX_DEV uint64_t epoch_bits(uint32_t epoch) { return ((uint64_t)epoch & kEpochMask) << kEpochShift; }
 JSIDX_DEV uint64_t make_agg(uint32_t table, uint32_t c0, uint32_t c1, uint32_t elig0, uint32_t esens, uint32_t epoch) {
@@ -495,19 +509,42 @@ JSIDX_DEV void tile_local(const Args& a, Shared& sh, int64_t P0, int64_t begin, 
 }
 
 // ---- the look-back ----------------------------------------------------------
-// Each lane reads 4 consecutive predecessors (lane 0 the newest), so one round
-// trip covers 256 tiles.  Lanes fold their 4 descriptors into either a known
-// state (if one is inclusive) or a transfer of the same kind as a tile's; the
-// walk from the newest lane with a known state to tile t is then done for all
-// lanes at once with ballots (segmented parity / OR scans) and one wave sum.
+// Tiles are grouped in blocks of kBlockTiles.  A tile's incoming state comes
+// from two windows, each read in one round trip: the blocks before its own
+// (one block descriptor per lane, up to 64 blocks back; before block 0 lies
+// the initial state) and the tiles of its own block before it (4 tile
+// descriptors per lane).  The last tile of a block to publish its aggregate
+// folds the block's tile descriptors into a block aggregate; the block's last
+// tile publishes the block's inclusive value once it is resolved.  So no tile
+// waits for a tile with a higher index, and the wait of a tile is bounded by
+// the local passes of the tiles before it, not by a chain of look-backs.
+//
+// Lanes fold their descriptors (oldest first) into either a known state (if
+// one is inclusive) or a transfer of the same kind as a tile's; the walk from
+// the newest lane with a known state to the newest descriptor is then done
+// for all lanes at once with ballots (segmented parity / OR scans) and one
+// wave sum.
 struct LaneFold {
   bool known, has, pending, blocked;
   uint32_t ks, kc;                       // known state and count
   uint32_t fr, fec, fev, fp, fq, fu;     // transfer: reset, e const?, e value, p, q, u
   uint32_t C0, C1, E0;                   // counts for q_in = 0 / 1; first tile's elig0
   uint32_t b0, b1;                       // an escape-sensitive tile sees e = 1
-                                         //   if the lane starts with e_in = 0 / 1
+                                         //   if the run starts with e_in = 0 / 1
 };
+
+JSIDX_DEV LaneFold fold_empty() {
+  LaneFold L;
+  L.known = L.has = L.pending = L.blocked = false;
+  L.ks = L.kc = 0; L.fr = L.fec = L.fev = L.fp = L.fq = L.fu = 0; L.C0 = L.C1 = L.E0 = 0; L.b0 = L.b1 = 0;
+  return L;
+}
+
+JSIDX_DEV LaneFold fold_known(uint32_t state, uint32_t count) {
+  LaneFold L = fold_empty();
+  L.known = true; L.ks = state; L.kc = count;
+  return L;
+}
 
 JSIDX_DEV void fold_desc(LaneFold& L, uint64_t d, bool valid) {
   if (!valid) return;
@@ -543,7 +580,7 @@ JSIDX_DEV void fold_desc(LaneFold& L, uint64_t d, bool valid) {
   if (Br) {
     L.fr = 1; L.fq = Bq; L.fu = Bu; L.C0 = L.C1 = c0;
   } else {
-    const uint32_t qa0 = L.fr ? L.fq : L.fq;        // q entering B when the lane starts with q = 0
+    const uint32_t qa0 = L.fq;                       // q entering B when the run starts with q = 0
     const uint32_t qa1 = L.fr ? L.fq : (1u ^ L.fq);  // ... with q = 1
     L.C0 += qa0 ? c1 : c0 + (L.fp & el);
     L.C1 += qa1 ? c1 : c0 + (L.fp & el);
@@ -553,17 +590,227 @@ JSIDX_DEV void fold_desc(LaneFold& L, uint64_t d, bool valid) {
   L.fp = Bp;
 }
 
-// State entering tile t and the count of its head document before it.
-JSIDX_DEV void look_back(Workspace* ws, int64_t t, uint32_t epoch, uint32_t* s_out, uint32_t* base_out) {
+// A := A then B (B covers the newer descriptors).
+JSIDX_DEV void compose(LaneFold& A, const LaneFold& B) {
+  if (B.known) { A = B; return; }
+  if (!B.has) return;
+  if (A.known) {
+    const uint32_t e_in = A.ks & 1u, q_in = (A.ks >> 1) & 1u, p_in = (A.ks >> 2) & 1u, u_in = (A.ks >> 3) & 1u;
+    if (e_in ? B.b1 : B.b0) A.blocked = true;
+    const uint32_t e = B.fec ? B.fev : e_in;
+    const uint32_t q = B.fr ? B.fq : (q_in ^ B.fq);
+    const uint32_t u = B.fr ? B.fu : (u_in | B.fu);
+    A.kc = B.fr ? B.C0 : A.kc + (q_in ? B.C1 : B.C0 + (p_in & B.E0));
+    A.ks = e | (q << 1) | (B.fp << 2) | (u << 3);
+    return;
+  }
+  if (!A.has) { A = B; return; }
+  const uint32_t ea0 = A.fec ? A.fev : 0u, ea1 = A.fec ? A.fev : 1u;  // e entering B
+  A.b0 |= ea0 ? B.b1 : B.b0;
+  A.b1 |= ea1 ? B.b1 : B.b0;
+  if (B.fec) { A.fec = 1; A.fev = B.fev; }
+  if (B.fr) {
+    A.fr = 1; A.fq = B.fq; A.fu = B.fu; A.C0 = A.C1 = B.C0;
+  } else {
+    const uint32_t qa0 = A.fq, qa1 = A.fr ? A.fq : (1u ^ A.fq);
+    const uint32_t pe = A.fp & B.E0;
+    A.C0 += qa0 ? B.C1 : B.C0 + pe;
+    A.C1 += qa1 ? B.C1 : B.C0 + pe;
+    A.fq ^= B.fq;
+    A.fu |= B.fu;
+  }
+  A.fp = B.fp;
+}
+
+// Transfer flags of a fold in one word (for lane shuffles); the counts travel
+// separately (C0 holds the known count of a known fold).
+JSIDX_DEV uint32_t fold_flags(const LaneFold& L) {
+  return (L.known ? 1u : 0u) | (L.has ? 2u : 0u) | (L.blocked ? 4u : 0u) | (L.fr << 3) | (L.fec << 4) |
+         (L.fev << 5) | (L.fp << 6) | (L.fq << 7) | (L.fu << 8) | (L.E0 << 9) | (L.b0 << 10) | (L.b1 << 11) |
+         (L.ks << 12);
+}
+JSIDX_DEV LaneFold fold_unpack(uint32_t f, uint32_t c0, uint32_t c1) {
+  LaneFold L = fold_empty();
+  L.known = f & 1u; L.has = (f >> 1) & 1u; L.blocked = (f >> 2) & 1u;
+  L.fr = (f >> 3) & 1u; L.fec = (f >> 4) & 1u; L.fev = (f >> 5) & 1u; L.fp = (f >> 6) & 1u;
+  L.fq = (f >> 7) & 1u; L.fu = (f >> 8) & 1u; L.E0 = (f >> 9) & 1u; L.b0 = (f >> 10) & 1u; L.b1 = (f >> 11) & 1u;
+  L.ks = (f >> 12) & 0xFu;
+  L.kc = c0; L.C0 = c0; L.C1 = c1;
+  return L;
+}
+
+// ---- block descriptors: 3 words per block ----------------------------------
+// [0], [1] aggregate (both flagged kAgg with the epoch): word 0 bits 2..10
+// transfer flags (fr fec fev fp fq fu E0 b0 b1), bits 11..34 C0; word 1 bits
+// 2..25 C1.  [2] inclusive, in the tile inclusive format.
+JSIDX_DEV uint64_t* block_desc(const Args& a) { return a.ws->desc + a.cap_tiles; }
+JSIDX_DEV uint32_t* block_count(const Args& a) {
+  return reinterpret_cast<uint32_t*>(block_desc(a) + 3 * blocks_for_tiles(a.cap_tiles));
+}
+
+JSIDX_DEV LaneFold read_block(const Args& a, int64_t bb, uint32_t epoch) {
+  if (bb < -1) return fold_empty();
+  if (bb == -1) return fold_known(0u, 0u);  // the state before the input
+  const uint64_t* bd = block_desc(a) + 3 * bb;
+  const uint64_t inc = prim::ld_agent(bd + 2);
+  if (d_current(inc, epoch) && d_flag(inc) == kInc) return fold_known(d_state(inc), d_count(inc));
+  const uint64_t w0 = prim::ld_agent(bd), w1 = prim::ld_agent(bd + 1);
+  LaneFold L = fold_empty();
+  if (!(d_current(w0, epoch) && d_flag(w0) == kAgg && d_current(w1, epoch) && d_flag(w1) == kAgg)) {
+    L.pending = true;
+    return L;
+  }
+  const uint32_t f = (uint32_t)(w0 >> 2) & 0x1FFu;
+  L.has = true;
+  L.fr = f & 1u; L.fec = (f >> 1) & 1u; L.fev = (f >> 2) & 1u; L.fp = (f >> 3) & 1u; L.fq = (f >> 4) & 1u;
+  L.fu = (f >> 5) & 1u; L.E0 = (f >> 6) & 1u; L.b0 = (f >> 7) & 1u; L.b1 = (f >> 8) & 1u;
+  L.C0 = (uint32_t)(w0 >> 11) & 0xFFFFFFu;
+  L.C1 = (uint32_t)(w1 >> 2) & 0xFFFFFFu;
+  return L;
+}
+
+// The last tile of block b to publish its aggregate folds the block: each
+// lane folds 4 tile descriptors, then lanes are combined pairwise (older
+// partner at lane + s).  A block holding an inclusive tile gets an inclusive
+// block value right away.
+JSIDX_DEV void compose_block(const Args& a, int64_t b, int64_t ntiles, uint32_t epoch) {
   const uint32_t lane = prim::lane();
+  const int64_t lo = b * kBlockTiles;
+  const int64_t hi = lo + kBlockTiles < ntiles ? lo + kBlockTiles : ntiles;
+  const int64_t j0 = hi - 1 - 4 * (int64_t)lane;
+  LaneFold L;
   for (uint32_t polls = 0;; polls++) {
-    LaneFold L;
-    L.known = L.has = L.pending = L.blocked = false;
-    L.ks = L.kc = 0; L.fr = L.fec = L.fev = L.fp = L.fq = L.fu = 0; L.C0 = L.C1 = L.E0 = 0; L.b0 = L.b1 = 0;
+    L = fold_empty();
+    uint64_t d[4];
+#pragma unroll
+    for (int m = 0; m < 4; m++) d[m] = (j0 - m >= lo) ? ld_desc(a.ws, j0 - m) : 0ull;
+#pragma unroll
+    for (int m = 3; m >= 0; m--) {
+      const bool valid = j0 - m >= lo;
+      fold_desc(L, (valid && d_current(d[m], epoch)) ? d[m] : 0ull, valid);
+    }
+    // every tile of the block has published (the counter says so); a stale
+    // read is retried
+    if (prim::ballot(L.pending && !L.known) == 0ull) break;
+    if (polls > prim::kSpinLimit) { prim::st_agent32(&a.ws->diag, 1u); return; }
+    prim::sleep();
+  }
+#pragma unroll 1
+  for (int s = 1; s < 64; s <<= 1) {
+    const uint32_t f = fold_flags(L), c0 = L.known ? L.kc : L.C0, c1 = L.C1;
+    const int src = (int)(lane + (uint32_t)s) & 63;
+    const uint32_t of = prim::shfl(f, src), oc0 = prim::shfl(c0, src), oc1 = prim::shfl(c1, src);
+    if ((lane & (uint32_t)(2 * s - 1)) == 0u) {
+      LaneFold O = fold_unpack(of, oc0, oc1);
+      compose(O, L);
+      L = O;
+    }
+  }
+  if (lane == 0) {
+    uint64_t* bd = block_desc(a) + 3 * b;
+    if (L.known && !L.blocked) {
+      prim::st_agent(bd + 2, make_inc(L.ks, 0u, L.kc, epoch));
+    } else if (L.has) {
+      const uint32_t f = L.fr | (L.fec << 1) | (L.fev << 2) | (L.fp << 3) | (L.fq << 4) | (L.fu << 5) | (L.E0 << 6) |
+                         (L.b0 << 7) | (L.b1 << 8);
+      prim::st_agent(bd + 1, (uint64_t)kAgg | ((uint64_t)(L.C1 & 0xFFFFFFu) << 2) | epoch_bits(epoch));
+      prim::st_agent(bd, (uint64_t)kAgg | ((uint64_t)f << 2) | ((uint64_t)(L.C0 & 0xFFFFFFu) << 11) | epoch_bits(epoch));
+    }
+    // a known but blocked fold publishes nothing: the block's inclusive value
+    // follows once its escape-sensitive tile has redone its pass
+  }
+}
+
+struct WalkOut {
+  bool ready, blocked;
+  uint32_t state, count;
+};
+
+// From the newest lane with a known state to the end of lane 0's run (lane 0
+// holds the newest descriptors): the state and the count of the open document.
+JSIDX_DEV WalkOut walk(const LaneFold& L) {
+  const uint32_t lane = prim::lane();
+  WalkOut w;
+  w.ready = false; w.blocked = false; w.state = 0; w.count = 0;
+  const uint64_t Kn = prim::ballot(L.known);
+  const int k = Kn ? __builtin_ctzll(Kn) : 64;
+  const uint64_t below = lanes_below(k);
+  const uint64_t pend = prim::ballot(L.pending) & (below | (k < 64 ? (1ull << k) : 0ull));
+  if (Kn == 0 || pend) return w;
+  // known start: lane k, after its newest descriptor
+  const uint32_t ks = prim::readlane(L.ks, k), kc = prim::readlane(L.kc, k);
+  const uint32_t kblk = prim::readlane(L.blocked ? 1u : 0u, k);
+  // lanes below k are transfers; lane 0 is the newest
+  const uint64_t Ec = prim::ballot(L.has && L.fec) & below;
+  const uint64_t Ev = prim::ballot(L.fev != 0u);
+  const uint64_t Rs = prim::ballot(L.has && L.fr) & below;
+  const uint64_t Qv = prim::ballot(L.fq != 0u);
+  const uint64_t Uv = prim::ballot(L.fu != 0u);
+  const uint64_t above = ~lanes_below((int)lane + 1);  // older lanes
+  // escape at this lane's entry: nearest older lane that fixes it, else ks
+  const uint64_t me = Ec & above;
+  const uint32_t e_ent = me ? (uint32_t)((Ev >> __builtin_ctzll(me)) & 1ull) : (ks & 1u);
+  // in-string and UTF-8 state at entry: from the nearest older reset lane
+  const uint64_t mr = Rs & above;
+  const uint64_t span = (mr ? lanes_below(__builtin_ctzll(mr) + 1) : below) & above;
+  uint32_t q_ent = parity64(Qv & span);
+  uint32_t u_ent = (Uv & span) ? 1u : 0u;
+  if (!mr) { q_ent ^= (ks >> 1) & 1u; u_ent |= (ks >> 3) & 1u; }
+  uint32_t p_ent = prim::shfl(L.fp, (int)((lane + 1u) & 63u));
+  if ((int)lane + 1 >= k) p_ent = (ks >> 2) & 1u;
+  const bool blk = L.has && (e_ent ? L.b1 : L.b0);
+  w.blocked = (prim::ballot(blk) & below) != 0ull || (kblk != 0u);
+  // count: from the newest reset lane below k (absolute), else from kc
+  uint32_t contrib = 0;
+  if (L.has) contrib = L.fr ? L.C0 : (q_ent ? L.C1 : L.C0 + (p_ent & L.E0));
+  const int rn = Rs ? __builtin_ctzll(Rs) : -1;
+  const uint64_t cm = rn >= 0 ? lanes_below(rn + 1) : below;
+  const uint32_t sum = wave_sum(((cm >> lane) & 1ull) ? contrib : 0u);
+  // state after lane 0
+  if (k == 0) {
+    w.state = ks;
+  } else {
+    const uint32_t e_after = L.fec ? L.fev : e_ent;
+    const uint32_t q_after = L.fr ? L.fq : (q_ent ^ L.fq);
+    const uint32_t u_after = L.fr ? L.fu : (u_ent | L.fu);
+    w.state = prim::readlane(e_after | (q_after << 1) | (L.fp << 2) | (u_after << 3), 0);
+  }
+  w.count = rn >= 0 ? sum : kc + sum;
+  w.ready = true;
+  return w;
+}
+
+// State entering tile t and the count of its head document before it.
+JSIDX_DEV void look_back(const Args& a, int64_t t, uint32_t epoch, uint32_t* s_out, uint32_t* base_out) {
+  const uint32_t lane = prim::lane();
+  Workspace* ws = a.ws;
+  const int64_t b = t / kBlockTiles, lo = b * kBlockTiles;
+  bool have_blk = false;
+  uint32_t bs = 0, bc = 0;  // state and count entering the block
+  for (uint32_t polls = 0;; polls++) {
+    if (polls > prim::kSpinLimit) {  // never expected: give up, flag it
+      prim::st_agent32(&ws->diag, 1u);
+      *s_out = 0; *base_out = 0;
+      return;
+    }
+    if (!have_blk) {
+      const WalkOut w2 = walk(read_block(a, b - 1 - (int64_t)lane, epoch));
+      if (!w2.ready || w2.blocked) {
+        prim::trace_count(t, w2.blocked ? 10 : 8);
+        prim::sleep();
+        continue;
+      }
+      have_blk = true; bs = w2.state; bc = w2.count;
+    }
+    // the tiles of this block before t; the tile before the block holds the
+    // block's incoming value
     const int64_t j0 = t - 1 - 4 * (int64_t)lane;  // this lane's newest tile
     uint64_t d[4];
 #pragma unroll
-    for (int m = 0; m < 4; m++) d[m] = (j0 - m >= 0) ? ld_desc(ws, j0 - m) : 0ull;
+    for (int m = 0; m < 4; m++) {
+      const int64_t j = j0 - m;
+      d[m] = j >= lo ? ld_desc(ws, j) : (j == lo - 1 ? make_inc(bs, 0u, bc, epoch) : 0ull);
+    }
     // Ready when some lane holds an inclusive descriptor and every descriptor
     // newer than the newest one is published: only then fold (a failed poll
     // costs a few operations).
@@ -571,7 +818,7 @@ JSIDX_DEV void look_back(Workspace* ws, int64_t t, uint32_t epoch, uint32_t* s_o
       uint32_t m_inc = 4, m_none = 4;  // newest inclusive / unpublished in this lane
 #pragma unroll
       for (int m = 3; m >= 0; m--) {
-        if (j0 - m < 0) continue;
+        if (j0 - m < lo - 1) continue;
         const uint32_t fl = d_current(d[m], epoch) ? d_flag(d[m]) : (uint32_t)kNone;
         if (fl == kInc) m_inc = (uint32_t)m;
         if (fl == kNone) m_none = (uint32_t)m;
@@ -581,90 +828,27 @@ JSIDX_DEV void look_back(Workspace* ws, int64_t t, uint32_t epoch, uint32_t* s_o
       const uint64_t Pn = prim::ballot(m_none < m_inc) & (lanes_below(ki) | (ki < 64 ? (1ull << ki) : 0ull));
       if (Ki == 0ull || Pn != 0ull) {
         prim::trace_count(t, 8);
-        if (polls > prim::kSpinLimit) {  // never expected: give up, flag it
-          prim::st_agent32(&ws->diag, 1u);
-          *s_out = 0; *base_out = 0;
-          return;
-        }
         prim::sleep();
         continue;
       }
     }
+    LaneFold L = fold_empty();
 #pragma unroll
     for (int m = 3; m >= 0; m--) {
-      const bool valid = j0 - m >= 0;
-      uint64_t dm = d[m];
-      if (valid && !d_current(dm, epoch)) dm = 0ull;  // not yet written in this launch
-      fold_desc(L, dm, valid);
+      const bool valid = j0 - m >= lo - 1;
+      fold_desc(L, (valid && d_current(d[m], epoch)) ? d[m] : 0ull, valid);
     }
     prim::trace_count(t, 8);
-    const uint64_t Kn = prim::ballot(L.known);
-    const int k = Kn ? __builtin_ctzll(Kn) : 64;
-    const uint64_t below = lanes_below(k);
-    const uint64_t pend = prim::ballot(L.pending) & (below | (k < 64 ? (1ull << k) : 0ull));
-    if (Kn == 0 || pend) {
-      if (polls > prim::kSpinLimit) {  // never expected: give up, flag it
-        prim::st_agent32(&ws->diag, 1u);
-        *s_out = 0; *base_out = 0;
-        return;
-      }
-      prim::sleep();
-      continue;
-    }
-    // known start: lane k, after its newest tile
-    const uint32_t ks = prim::readlane(L.ks, k), kc = prim::readlane(L.kc, k);
-    const uint32_t kblk = prim::readlane(L.blocked ? 1u : 0u, k);
-    // lanes below k are transfers; lane 0 is the newest
-    const uint64_t Ec = prim::ballot(L.has && L.fec) & below;
-    const uint64_t Ev = prim::ballot(L.fev != 0u);
-    const uint64_t Rs = prim::ballot(L.has && L.fr) & below;
-    const uint64_t Qv = prim::ballot(L.fq != 0u);
-    const uint64_t Uv = prim::ballot(L.fu != 0u);
-    const uint64_t above = ~lanes_below((int)lane + 1);  // older lanes
-    // escape at this lane's entry: nearest older lane that fixes it, else ks
-    const uint64_t me = Ec & above;
-    const uint32_t e_ent = me ? (uint32_t)((Ev >> __builtin_ctzll(me)) & 1ull) : (ks & 1u);
-    // in-string and UTF-8 state at entry: from the nearest older reset lane
-    const uint64_t mr = Rs & above;
-    const uint64_t span = (mr ? lanes_below(__builtin_ctzll(mr) + 1) : below) & above;
-    uint32_t q_ent = parity64(Qv & span);
-    uint32_t u_ent = (Uv & span) ? 1u : 0u;
-    if (!mr) { q_ent ^= (ks >> 1) & 1u; u_ent |= (ks >> 3) & 1u; }
-    uint32_t p_ent = prim::shfl(L.fp, (int)((lane + 1u) & 63u));
-    if ((int)lane + 1 >= k) p_ent = (ks >> 2) & 1u;
-    const bool blk = L.has && (e_ent ? L.b1 : L.b0);
-    const bool any_blk = (prim::ballot(blk) & below) != 0ull || (kblk != 0u);
-    // count: from the newest reset lane below k (absolute), else from kc
-    uint32_t contrib = 0;
-    if (L.has) contrib = L.fr ? L.C0 : (q_ent ? L.C1 : L.C0 + (p_ent & L.E0));
-    const int rn = Rs ? __builtin_ctzll(Rs) : -1;
-    const uint64_t cm = rn >= 0 ? lanes_below(rn + 1) : below;
-    const uint32_t sum = wave_sum(((cm >> lane) & 1ull) ? contrib : 0u);
-    // state after lane 0
-    uint32_t st0;
-    if (k == 0) {
-      st0 = ks;
-    } else {
-      const uint32_t e_after = L.fec ? L.fev : e_ent;
-      const uint32_t q_after = L.fr ? L.fq : (q_ent ^ L.fq);
-      const uint32_t u_after = L.fr ? L.fu : (u_ent | L.fu);
-      st0 = prim::readlane(e_after | (q_after << 1) | (L.fp << 2) | (u_after << 3), 0);
-    }
-    if (any_blk) {
+    const WalkOut w = walk(L);
+    if (!w.ready || w.blocked) {
       // some tile's counts depend on an escape that turned out to be set; that
-      // tile redoes its local pass and publishes an exact inclusive value: poll
-      // until it has (waiting on just that tile, not on the whole chain)
+      // tile redoes its local pass and publishes an exact inclusive value
       prim::trace_count(t, 10);
-      if (polls > prim::kSpinLimit) {
-        prim::st_agent32(&ws->diag, 1u);
-        *s_out = 0; *base_out = 0;
-        return;
-      }
       prim::sleep();
       continue;
     }
-    *s_out = st0;
-    *base_out = rn >= 0 ? sum : kc + sum;
+    *s_out = w.state;
+    *base_out = w.count;
     return;
   }
 }
@@ -807,7 +991,7 @@ JSIDX_DEVFN void index_tiles(const Args& a) {
 
     TileFacts T;
     uint32_t s_in = 0, base = 0;
-    bool exact = (t == 0);  // tile 0's carry-in is the initial state
+    bool exact = false;  // set by the rare exact second pass
     const bool simple = !sh.overflow && sh.ntab == 1 && sh.tab[0] < 0 && hd_ok && e_known && !exact;
     uint32_t table = 0, cnt0 = 0, cnt1 = 0, esens = 0;
     // pass 0: the local pass with the escape state read before the tile;
@@ -844,8 +1028,22 @@ JSIDX_DEVFN void index_tiles(const Args& a) {
       }
       esens = e_known ? 0u : (T.qsens | ((T.lead_reset && T.lead_pos > 0) ? 1u : 0u));
       if (exact) break;
-      if (lane == 0) st_desc(ws, t, make_agg(table, cnt0, cnt1, T.elig0, esens, epoch));
-      look_back(ws, t, epoch, &s_in, &base);
+      if (pass == 0) {
+        if (lane == 0) st_desc(ws, t, make_agg(table, cnt0, cnt1, T.elig0, esens, epoch));
+        // count the block's published tiles; the last one folds the block
+        const int64_t blk = t / kBlockTiles;
+        const int64_t nblk = (ntiles - blk * kBlockTiles) < kBlockTiles ? (ntiles - blk * kBlockTiles) : kBlockTiles;
+        prim::fence();
+        uint32_t old = 0;
+        if (lane == 0) old = prim::add_agent32(block_count(a) + blk, 1u);
+        old = prim::readlane(old, 0);
+        if ((int64_t)old == nblk - 1) {
+          prim::fence();
+          compose_block(a, blk, ntiles, epoch);
+          if (lane == 0) prim::st_agent32(block_count(a) + blk, 0u);  // ready for the next launch
+        }
+      }
+      look_back(a, t, epoch, &s_in, &base);
       prim::trace(t, 3);
       if (!((s_in & 1u) && esens)) break;
       prim::trace_count(t, 9);
@@ -861,7 +1059,11 @@ JSIDX_DEVFN void index_tiles(const Args& a) {
       const uint32_t q = (s_in >> 1) & 1u, p = (s_in >> 2) & 1u;
       inc_count = T.reset_any ? cnt0 : base + (q ? cnt1 : cnt0 + (p & T.elig0));
     }
-    if (lane == 0) st_desc(ws, t, make_inc(st_out, T.reset_any, inc_count, epoch));
+    if (lane == 0) {
+      const uint64_t inc = make_inc(st_out, T.reset_any, inc_count, epoch);
+      st_desc(ws, t, inc);
+      if (t % kBlockTiles == kBlockTiles - 1) prim::st_agent(block_desc(a) + 3 * (t / kBlockTiles) + 2, inc);
+    }
     prim::trace(t, 4);
 
     // ---- head region: positions and the head document's result ---------------
@@ -933,6 +1135,7 @@ finish:
     const uint64_t nwin = (a.cap_tiles + kScrub - 1) / kScrub;
     const uint64_t w0 = (uint64_t)(epoch % (uint32_t)(nwin ? nwin : 1)) * kScrub;
     for (uint64_t j = w0 + lane; j < w0 + kScrub && j < a.cap_tiles; j += kThreads) st_desc(ws, (int64_t)j, 0ull);
+    for (uint64_t j = lane; j < 3 * blocks_for_tiles(a.cap_tiles); j += kThreads) prim::st_agent(block_desc(a) + j, 0ull);
     prim::sync();
     if (lane == 0) {
       prim::st_agent32(&ws->ticket, 0u);

@@ -65,7 +65,7 @@ long emu_run(const uint8_t* base, const uint64_t* offsets, uint64_t len, uint32_
   return env.violations.load();
 }
 
-uint64_t emu_ws_bytes(uint64_t cap_tiles) { return sizeof(Workspace) + cap_tiles * sizeof(uint64_t); }
+uint64_t emu_ws_bytes(uint64_t cap_tiles) { return workspace_bytes(cap_tiles); }
 uint32_t emu_tile_bytes() { return (uint32_t)kTileBytes; }
 
 }  // extern "C"

@@ -26,23 +26,33 @@ def _deps():
     return files
 
 
-def build() -> str:
+def build(block_tiles: int | None = None) -> str:
+    """Build the emulation library; block_tiles overrides the look-back block
+    size (tests use 2 so that small inputs span many blocks)."""
     os.makedirs(OUT_DIR, exist_ok=True)
+    lib = LIB if block_tiles is None else LIB.replace(".so", f"_b{block_tiles}.so")
+    defs = [] if block_tiles is None else [f"-DJSIDX_BLOCK_TILES={block_tiles}"]
     subprocess.run(
-        ["g++", "-std=c++17", "-O1", "-g", "-shared", "-fPIC", "-pthread",
+        ["g++", "-std=c++17", "-O1", "-g", "-shared", "-fPIC", "-pthread", *defs,
          "-I", os.path.join(HERE, "cpu_emu"), "-I", os.path.join(ROOT, "include"),
-         "-I", os.path.join(ROOT, "paper_1902_08318_amd", "csrc"), "-o", LIB, SRC],
+         "-I", os.path.join(ROOT, "paper_1902_08318_amd", "csrc"), "-o", lib, SRC],
         check=True)
-    return LIB
+    return lib
 
 
-def load():
+_libs = {}
+
+
+def load(block_tiles: int | None = None):
     global _lib
-    if _lib is not None:
+    if block_tiles is None and _lib is not None:
         return _lib
-    if not os.path.exists(LIB) or any(os.path.getmtime(f) > os.path.getmtime(LIB) for f in _deps()):
-        build()
-    lib = ctypes.CDLL(LIB)
+    if block_tiles in _libs:
+        return _libs[block_tiles]
+    path = LIB if block_tiles is None else LIB.replace(".so", f"_b{block_tiles}.so")
+    if not os.path.exists(path) or any(os.path.getmtime(f) > os.path.getmtime(path) for f in _deps()):
+        build(block_tiles)
+    lib = ctypes.CDLL(path)
     vp = ctypes.c_void_p
     lib.emu_run.argtypes = [vp, vp, ctypes.c_uint64, ctypes.c_uint32, vp, ctypes.c_uint64, vp, vp,
                             ctypes.c_int, vp, ctypes.c_uint64, vp, vp]
@@ -50,7 +60,9 @@ def load():
     lib.emu_ws_bytes.argtypes = [ctypes.c_uint64]
     lib.emu_ws_bytes.restype = ctypes.c_uint64
     lib.emu_tile_bytes.restype = ctypes.c_uint32
-    _lib = lib
+    if block_tiles is None:
+        _lib = lib
+    _libs[block_tiles] = lib
     return lib
 
 
@@ -59,9 +71,10 @@ def tile_bytes() -> int:
 
 
 class Workspace:
-    def __init__(self, cap_tiles: int):
+    def __init__(self, cap_tiles: int, block_tiles: int | None = None):
         self.cap = cap_tiles
-        self.mem = np.zeros(int(load().emu_ws_bytes(cap_tiles)) // 8 + 1, dtype=np.uint64)
+        self.block_tiles = block_tiles
+        self.mem = np.zeros(int(load(block_tiles).emu_ws_bytes(cap_tiles)) // 8 + 1, dtype=np.uint64)
 
 
 def _aligned(nbytes: int, shift: int) -> tuple[np.ndarray, int]:
@@ -73,15 +86,18 @@ def _aligned(nbytes: int, shift: int) -> tuple[np.ndarray, int]:
 
 
 def run(data: bytes, offsets=None, nblocks: int = 2, misalign: int = 0, ws: Workspace | None = None,
-        garbage: int = 0xEE):
+        garbage: int = 0xEE, block_tiles: int | None = None):
     """Index `data` (one document if offsets is None, else a batch).
 
     misalign: the buffer starts this many bytes past a 64-byte boundary.  The
     bytes around the input inside its 16-byte granules are filled with
     `garbage` so that any influence of them shows up.
+    block_tiles: look-back block size of the build (None: the library's).
     Returns (out_idx, out_n, out_err, violations).
     """
-    lib = load()
+    if ws is not None:
+        block_tiles = ws.block_tiles
+    lib = load(block_tiles)
     n = len(data)
     raw, off = _aligned(n + 64, misalign + 16)
     raw[:] = garbage
@@ -104,7 +120,7 @@ def run(data: bytes, offsets=None, nblocks: int = 2, misalign: int = 0, ws: Work
     tb = tile_bytes()
     need = max(1, (end - begin + 15 + tb - 1) // tb)
     if ws is None:
-        ws = Workspace(need)
+        ws = Workspace(need, block_tiles)
     v = lib.emu_run(ctypes.c_void_p(base), offs.ctypes.data if offs is not None else None, n, ndocs,
                     out_idx.ctypes.data, out_cap, out_n.ctypes.data, out_err.ctypes.data, nblocks,
                     ws.mem.ctypes.data, ws.cap, ctypes.c_void_p(glo), ctypes.c_void_p(ghi))

@@ -10,18 +10,18 @@ import oracle
 TB = emu.tile_bytes()
 
 
-def _check_single(d, nblocks, misalign):
-    idx, n, err, viol = emu.run(d, nblocks=nblocks, misalign=misalign)
+def _check_single(d, nblocks, misalign, block_tiles=None):
+    idx, n, err, viol = emu.run(d, nblocks=nblocks, misalign=misalign, block_tiles=block_tiles)
     oi, oe = oracle.index(d)
     assert viol == 0
     assert n[0] == len(oi) and err[0] == oe
     assert np.array_equal(idx[:n[0]], oi)
 
 
-def _check_batch(docs, nblocks, misalign, lead):
+def _check_batch(docs, nblocks, misalign, lead, block_tiles=None):
     data = b"\x00" * lead + b"".join(docs)
     offs = np.concatenate([[lead], lead + np.cumsum([len(x) for x in docs])]).astype(np.uint64)
-    idx, n, err, viol = emu.run(data, offsets=offs, nblocks=nblocks, misalign=misalign)
+    idx, n, err, viol = emu.run(data, offsets=offs, nblocks=nblocks, misalign=misalign, block_tiles=block_tiles)
     oi, on, oe = oracle.index_batch(np.frombuffer(data, dtype=np.uint8), offs)
     assert viol == 0
     assert np.array_equal(n, on) and np.array_equal(err, oe)
@@ -63,3 +63,25 @@ def test_batches_with_empty_and_tiny_documents():
             L = 0 if r < 0.15 else (1 if r < 0.25 else int(rng.integers(2, 3000 if r < 0.9 else 2 * TB)))
             docs.append(_soup(rng, L))
         _check_batch(docs, int(rng.integers(1, 4)), int(rng.integers(0, 16)), int(rng.integers(0, 40)))
+
+
+@pytest.mark.parametrize("block_tiles", [1, 2])
+def test_many_lookback_blocks(block_tiles):
+    """Builds with tiny look-back blocks, so that a few MiB span more blocks
+    than one block window (64): block aggregates, block inclusive values, and
+    escape-sensitive tiles inside blocks all come into play."""
+    from paper_1902_08318_amd import synth
+    d = synth.gen_c1(7, 3 << 20, pool=64).data
+    idx, n, err, viol = emu.run(d, nblocks=64, misalign=3, block_tiles=block_tiles)
+    oi, oe = oracle.index(d)
+    assert viol == 0 and n[0] == len(oi) and err[0] == oe
+    assert np.array_equal(idx[:n[0]], oi)
+    # backslash runs long enough that the escape state entering a tile is
+    # only known from the look-back
+    for run, end in ((4097, 2 * TB), (TB + 1, 5 * TB + 1), (3 * TB + 2, 9 * TB)):
+        s = bytearray(synth.gen_c1(9, 12 * TB, pool=16).data)
+        s[end - run:end] = b"\\" * run
+        _check_single(bytes(s), 40, 0, block_tiles)
+    rng = np.random.default_rng(block_tiles)
+    docs = [synth.gen_c0(int(rng.integers(0, 1000)), 5000).data[:int(rng.integers(0, 5000))] for _ in range(300)]
+    _check_batch(docs, 48, 1, 5, block_tiles)

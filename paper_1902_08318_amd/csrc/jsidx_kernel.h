@@ -640,9 +640,12 @@ JSIDX_DEV LaneFold fold_unpack(uint32_t f, uint32_t c0, uint32_t c1) {
 }
 
 // ---- block descriptors: 3 words per block ----------------------------------
-// [0], [1] aggregate (both flagged kAgg with the epoch): word 0 bits 2..10
-// transfer flags (fr fec fev fp fq fu E0 b0 b1), bits 11..34 C0; word 1 bits
-// 2..25 C1.  [2] inclusive, in the tile inclusive format.
+// [0] aggregate: bits 0..1 kAgg, 2..10 transfer flags (fr fec fev fp fq fu E0
+//     b0 b1), 11..34 C0, 35..58 C1, 59..63 low epoch bits;
+// [1] inclusive and [2] incoming (state and count before the block), both in
+//     the tile inclusive format.
+// All block words are cleared at the end of every launch.
+constexpr uint64_t kAggEpochMask = 31;
 JSIDX_DEV uint64_t* block_desc(const Args& a) { return a.ws->desc + a.cap_tiles; }
 JSIDX_DEV uint32_t* block_count(const Args& a) {
   return reinterpret_cast<uint32_t*>(block_desc(a) + 3 * blocks_for_tiles(a.cap_tiles));
@@ -652,73 +655,21 @@ JSIDX_DEV LaneFold read_block(const Args& a, int64_t bb, uint32_t epoch) {
   if (bb < -1) return fold_empty();
   if (bb == -1) return fold_known(0u, 0u);  // the state before the input
   const uint64_t* bd = block_desc(a) + 3 * bb;
-  const uint64_t inc = prim::ld_agent(bd + 2);
+  const uint64_t inc = prim::ld_agent(bd + 1);
   if (d_current(inc, epoch) && d_flag(inc) == kInc) return fold_known(d_state(inc), d_count(inc));
-  const uint64_t w0 = prim::ld_agent(bd), w1 = prim::ld_agent(bd + 1);
+  const uint64_t w = prim::ld_agent(bd);
   LaneFold L = fold_empty();
-  if (!(d_current(w0, epoch) && d_flag(w0) == kAgg && d_current(w1, epoch) && d_flag(w1) == kAgg)) {
+  if (d_flag(w) != kAgg || (w >> 59) != ((uint64_t)epoch & kAggEpochMask)) {
     L.pending = true;
     return L;
   }
-  const uint32_t f = (uint32_t)(w0 >> 2) & 0x1FFu;
+  const uint32_t f = (uint32_t)(w >> 2) & 0x1FFu;
   L.has = true;
   L.fr = f & 1u; L.fec = (f >> 1) & 1u; L.fev = (f >> 2) & 1u; L.fp = (f >> 3) & 1u; L.fq = (f >> 4) & 1u;
   L.fu = (f >> 5) & 1u; L.E0 = (f >> 6) & 1u; L.b0 = (f >> 7) & 1u; L.b1 = (f >> 8) & 1u;
-  L.C0 = (uint32_t)(w0 >> 11) & 0xFFFFFFu;
-  L.C1 = (uint32_t)(w1 >> 2) & 0xFFFFFFu;
+  L.C0 = (uint32_t)(w >> 11) & 0xFFFFFFu;
+  L.C1 = (uint32_t)(w >> 35) & 0xFFFFFFu;
   return L;
-}
-
-// The last tile of block b to publish its aggregate folds the block: each
-// lane folds 4 tile descriptors, then lanes are combined pairwise (older
-// partner at lane + s).  A block holding an inclusive tile gets an inclusive
-// block value right away.
-JSIDX_DEV void compose_block(const Args& a, int64_t b, int64_t ntiles, uint32_t epoch) {
-  const uint32_t lane = prim::lane();
-  const int64_t lo = b * kBlockTiles;
-  const int64_t hi = lo + kBlockTiles < ntiles ? lo + kBlockTiles : ntiles;
-  const int64_t j0 = hi - 1 - 4 * (int64_t)lane;
-  LaneFold L;
-  for (uint32_t polls = 0;; polls++) {
-    L = fold_empty();
-    uint64_t d[4];
-#pragma unroll
-    for (int m = 0; m < 4; m++) d[m] = (j0 - m >= lo) ? ld_desc(a.ws, j0 - m) : 0ull;
-#pragma unroll
-    for (int m = 3; m >= 0; m--) {
-      const bool valid = j0 - m >= lo;
-      fold_desc(L, (valid && d_current(d[m], epoch)) ? d[m] : 0ull, valid);
-    }
-    // every tile of the block has published (the counter says so); a stale
-    // read is retried
-    if (prim::ballot(L.pending && !L.known) == 0ull) break;
-    if (polls > prim::kSpinLimit) { prim::st_agent32(&a.ws->diag, 1u); return; }
-    prim::sleep();
-  }
-#pragma unroll 1
-  for (int s = 1; s < 64; s <<= 1) {
-    const uint32_t f = fold_flags(L), c0 = L.known ? L.kc : L.C0, c1 = L.C1;
-    const int src = (int)(lane + (uint32_t)s) & 63;
-    const uint32_t of = prim::shfl(f, src), oc0 = prim::shfl(c0, src), oc1 = prim::shfl(c1, src);
-    if ((lane & (uint32_t)(2 * s - 1)) == 0u) {
-      LaneFold O = fold_unpack(of, oc0, oc1);
-      compose(O, L);
-      L = O;
-    }
-  }
-  if (lane == 0) {
-    uint64_t* bd = block_desc(a) + 3 * b;
-    if (L.known && !L.blocked) {
-      prim::st_agent(bd + 2, make_inc(L.ks, 0u, L.kc, epoch));
-    } else if (L.has) {
-      const uint32_t f = L.fr | (L.fec << 1) | (L.fev << 2) | (L.fp << 3) | (L.fq << 4) | (L.fu << 5) | (L.E0 << 6) |
-                         (L.b0 << 7) | (L.b1 << 8);
-      prim::st_agent(bd + 1, (uint64_t)kAgg | ((uint64_t)(L.C1 & 0xFFFFFFu) << 2) | epoch_bits(epoch));
-      prim::st_agent(bd, (uint64_t)kAgg | ((uint64_t)f << 2) | ((uint64_t)(L.C0 & 0xFFFFFFu) << 11) | epoch_bits(epoch));
-    }
-    // a known but blocked fold publishes nothing: the block's inclusive value
-    // follows once its escape-sensitive tile has redone its pass
-  }
 }
 
 struct WalkOut {
@@ -780,13 +731,95 @@ JSIDX_DEV WalkOut walk(const LaneFold& L) {
   return w;
 }
 
+// Back-off between polls: 1, 2, 4, then 16 sleeps of 64 clocks.
+JSIDX_DEV void poll_sleep(uint32_t polls) {
+  const int n = polls < 2 ? 1 : (polls < 4 ? 2 : (polls < 8 ? 4 : 16));
+  for (int i = 0; i < n; i++) prim::sleep();
+}
+
+// The last tile of block b to publish its aggregate folds the block (each
+// lane folds 4 tile descriptors, then lanes combine pairwise, the older
+// partner at lane + s) and publishes the block aggregate.  It then walks the
+// blocks before (one per lane, up to 64 back) for the state entering block b,
+// which every tile of the block waits for, and the block's inclusive value.
+JSIDX_DEV void compose_block(const Args& a, int64_t b, int64_t ntiles, uint32_t epoch) {
+  const uint32_t lane = prim::lane();
+  const int64_t lo = b * kBlockTiles;
+  const int64_t hi = lo + kBlockTiles < ntiles ? lo + kBlockTiles : ntiles;
+  const int64_t j0 = hi - 1 - 4 * (int64_t)lane;
+  uint64_t* bd = block_desc(a) + 3 * b;
+  LaneFold L;
+  for (uint32_t polls = 0;; polls++) {
+    L = fold_empty();
+    uint64_t d[4];
+#pragma unroll
+    for (int m = 0; m < 4; m++) d[m] = (j0 - m >= lo) ? ld_desc(a.ws, j0 - m) : 0ull;
+#pragma unroll
+    for (int m = 3; m >= 0; m--) {
+      const bool valid = j0 - m >= lo;
+      fold_desc(L, (valid && d_current(d[m], epoch)) ? d[m] : 0ull, valid);
+    }
+    // every tile of the block has published (the counter says so); a stale
+    // read is retried
+    if (prim::ballot(L.pending && !L.known) == 0ull) break;
+    if (polls > prim::kSpinLimit) { prim::st_agent32(&a.ws->diag, 1u); return; }
+    poll_sleep(polls);
+  }
+#pragma unroll 1
+  for (int s = 1; s < 64; s <<= 1) {
+    const uint32_t f = fold_flags(L), c0 = L.known ? L.kc : L.C0, c1 = L.C1;
+    const int src = (int)(lane + (uint32_t)s) & 63;
+    const uint32_t of = prim::shfl(f, src), oc0 = prim::shfl(c0, src), oc1 = prim::shfl(c1, src);
+    if ((lane & (uint32_t)(2 * s - 1)) == 0u) {
+      LaneFold O = fold_unpack(of, oc0, oc1);
+      compose(O, L);
+      L = O;
+    }
+  }
+  // lane 0 holds the block's fold
+  const uint32_t bf = prim::readlane(fold_flags(L), 0);
+  const uint32_t b0 = prim::readlane(L.known ? L.kc : L.C0, 0), b1 = prim::readlane(L.C1, 0);
+  const LaneFold B = fold_unpack(bf, b0, b1);
+  if (lane == 0) {
+    if (B.known && !B.blocked) {
+      prim::st_agent(bd + 1, make_inc(B.ks, 0u, B.kc, epoch));
+    } else if (B.has) {
+      const uint32_t tf = B.fr | (B.fec << 1) | (B.fev << 2) | (B.fp << 3) | (B.fq << 4) | (B.fu << 5) |
+                          (B.E0 << 6) | (B.b0 << 7) | (B.b1 << 8);
+      prim::st_agent(bd, (uint64_t)kAgg | ((uint64_t)tf << 2) | ((uint64_t)(B.C0 & 0xFFFFFFu) << 11) |
+                             ((uint64_t)(B.C1 & 0xFFFFFFu) << 35) | (((uint64_t)epoch & kAggEpochMask) << 59));
+    }
+    // a known but blocked fold publishes nothing here: the block's inclusive
+    // value follows from its last tile once the escape-sensitive tile has
+    // redone its pass
+  }
+  // the state entering block b
+  uint32_t es = 0, ec = 0;
+  if (b > 0) {
+    for (uint32_t polls = 0;; polls++) {
+      const WalkOut w2 = walk(read_block(a, b - 1 - (int64_t)lane, epoch));
+      if (w2.ready && !w2.blocked) { es = w2.state; ec = w2.count; break; }
+      if (polls > prim::kSpinLimit) { prim::st_agent32(&a.ws->diag, 1u); break; }
+      poll_sleep(polls);
+    }
+  }
+  if (lane == 0) {
+    prim::st_agent(bd + 2, make_inc(es, 0u, ec, epoch));
+    if (!B.known && B.has) {
+      LaneFold K = fold_known(es, ec);
+      compose(K, B);
+      if (!K.blocked) prim::st_agent(bd + 1, make_inc(K.ks, 0u, K.kc, epoch));
+    }
+  }
+}
+
 // State entering tile t and the count of its head document before it.
 JSIDX_DEV void look_back(const Args& a, int64_t t, uint32_t epoch, uint32_t* s_out, uint32_t* base_out) {
   const uint32_t lane = prim::lane();
   Workspace* ws = a.ws;
   const int64_t b = t / kBlockTiles, lo = b * kBlockTiles;
-  bool have_blk = false;
-  uint32_t bs = 0, bc = 0;  // state and count entering the block
+  bool have_blk = b == 0;
+  uint32_t bs = 0, bc = 0;  // state and count entering the block (block 0: the initial state)
   for (uint32_t polls = 0;; polls++) {
     if (polls > prim::kSpinLimit) {  // never expected: give up, flag it
       prim::st_agent32(&ws->diag, 1u);
@@ -794,13 +827,16 @@ JSIDX_DEV void look_back(const Args& a, int64_t t, uint32_t epoch, uint32_t* s_o
       return;
     }
     if (!have_blk) {
-      const WalkOut w2 = walk(read_block(a, b - 1 - (int64_t)lane, epoch));
-      if (!w2.ready || w2.blocked) {
-        prim::trace_count(t, w2.blocked ? 10 : 8);
-        prim::sleep();
+      uint64_t v = 0;
+      if (lane == 0) v = prim::ld_agent(block_desc(a) + 3 * b + 2);
+      const uint32_t lo32 = prim::readlane((uint32_t)v, 0), hi32 = prim::readlane((uint32_t)(v >> 32), 0);
+      v = ((uint64_t)hi32 << 32) | lo32;
+      if (!(d_current(v, epoch) && d_flag(v) == kInc)) {
+        prim::trace_count(t, 8);
+        poll_sleep(polls);
         continue;
       }
-      have_blk = true; bs = w2.state; bc = w2.count;
+      have_blk = true; bs = d_state(v); bc = d_count(v);
     }
     // the tiles of this block before t; the tile before the block holds the
     // block's incoming value
@@ -828,7 +864,7 @@ JSIDX_DEV void look_back(const Args& a, int64_t t, uint32_t epoch, uint32_t* s_o
       const uint64_t Pn = prim::ballot(m_none < m_inc) & (lanes_below(ki) | (ki < 64 ? (1ull << ki) : 0ull));
       if (Ki == 0ull || Pn != 0ull) {
         prim::trace_count(t, 8);
-        prim::sleep();
+        poll_sleep(polls);
         continue;
       }
     }
@@ -844,7 +880,7 @@ JSIDX_DEV void look_back(const Args& a, int64_t t, uint32_t epoch, uint32_t* s_o
       // some tile's counts depend on an escape that turned out to be set; that
       // tile redoes its local pass and publishes an exact inclusive value
       prim::trace_count(t, 10);
-      prim::sleep();
+      poll_sleep(polls);
       continue;
     }
     *s_out = w.state;
@@ -1062,7 +1098,7 @@ JSIDX_DEVFN void index_tiles(const Args& a) {
     if (lane == 0) {
       const uint64_t inc = make_inc(st_out, T.reset_any, inc_count, epoch);
       st_desc(ws, t, inc);
-      if (t % kBlockTiles == kBlockTiles - 1) prim::st_agent(block_desc(a) + 3 * (t / kBlockTiles) + 2, inc);
+      if (t % kBlockTiles == kBlockTiles - 1) prim::st_agent(block_desc(a) + 3 * (t / kBlockTiles) + 1, inc);
     }
     prim::trace(t, 4);
 

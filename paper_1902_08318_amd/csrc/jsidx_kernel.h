@@ -1069,12 +1069,11 @@ JSIDX_DEVFN void index_tiles(const Args& a) {
         // count the block's published tiles; the last one folds the block
         const int64_t blk = t / kBlockTiles;
         const int64_t nblk = (ntiles - blk * kBlockTiles) < kBlockTiles ? (ntiles - blk * kBlockTiles) : kBlockTiles;
-        prim::fence();
+        prim::wait_mem();  // the aggregate is written before it is counted
         uint32_t old = 0;
         if (lane == 0) old = prim::add_agent32(block_count(a) + blk, 1u);
         old = prim::readlane(old, 0);
         if ((int64_t)old == nblk - 1) {
-          prim::fence();
           compose_block(a, blk, ntiles, epoch);
           if (lane == 0) prim::st_agent32(block_count(a) + blk, 0u);  // ready for the next launch
         }
@@ -1162,7 +1161,7 @@ finish:
   // carry a matching epoch.
   prim::sync();
   if (lane == 0) {
-    prim::fence();
+    prim::wait_mem();
     const uint32_t old = prim::add_agent32(&ws->done, 1u);
     sh.is_last = (old == prim::grid() - 1) ? 1u : 0u;
   }

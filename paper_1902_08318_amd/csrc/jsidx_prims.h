@@ -63,7 +63,15 @@ JSIDX_DEV int sync_count(bool p) { return __syncthreads_count(p); }
 JSIDX_DEV void sleep() { __builtin_amdgcn_s_sleep(1); }
 // Look-back waits give up after this many sleeps (about half a second).
 constexpr uint32_t kSpinLimit = 1u << 23;
-JSIDX_DEV void fence() { __threadfence(); }
+// Waits until this wave's memory operations have completed (s_waitcnt 0),
+// without the L2 write-back and invalidate of an agent-scope fence.  Enough
+// to order device-scope atomic accesses (the descriptor protocol uses only
+// those) before a later one.
+JSIDX_DEV void wait_mem() {
+  __asm__ __volatile__("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(0);
+  __asm__ __volatile__("" ::: "memory");
+}
 
 JSIDX_DEV uint64_t ld_agent(const uint64_t* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
 JSIDX_DEV uint32_t ld_agent32(const uint32_t* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }

@@ -192,7 +192,7 @@ inline int sync_count(bool p) {
 }
 inline void sleep() { std::this_thread::sleep_for(std::chrono::microseconds(20)); }
 constexpr uint32_t kSpinLimit = 1u << 20;  // ~20 s of emulated waiting
-inline void fence() { std::atomic_thread_fence(std::memory_order_seq_cst); }
+inline void wait_mem() { std::atomic_thread_fence(std::memory_order_seq_cst); }
 
 inline uint64_t ld_agent(const uint64_t* p) { return __atomic_load_n(p, __ATOMIC_RELAXED); }
 inline uint32_t ld_agent32(const uint32_t* p) { return __atomic_load_n(p, __ATOMIC_RELAXED); }

@@ -27,7 +27,7 @@
 namespace jsidx {
 
 // Four waves per SIMD: 128 VGPRs, enough to keep two rows of input in flight per wave.
-__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) index_kernel(Args a) {
+__global__ void __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per_eu(4))) index_kernel(Args a) {
   index_tiles(a);
 }
 
@@ -56,7 +56,8 @@ int slots_for_device(int dev) {
   if (dev < 0 || dev >= 64) return 1024;
   if (g_slots[dev]) return g_slots[dev];
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, index_kernel, kThreads, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, index_kernel, kGroupThreads, 0) != hipSuccess || per_cu < 1)
+    per_cu = 1;
   hipDeviceProp_t prop;
   int cus = 256;
   if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
@@ -98,9 +99,10 @@ int launch(const Args& args, hipStream_t stream, uint64_t tiles_hint) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return JSIDX_E_HIP;
   uint64_t slots = (uint64_t)slots_for_device(dev);
-  uint64_t grid = tiles_hint < slots ? tiles_hint : slots;
+  const uint64_t groups = (tiles_hint + kWaves - 1) / kWaves;
+  uint64_t grid = groups < slots ? groups : slots;
   if (grid < 1) grid = 1;
-  hipLaunchKernelGGL(index_kernel, dim3((uint32_t)grid), dim3(kThreads), 0, stream, args);
+  hipLaunchKernelGGL(index_kernel, dim3((uint32_t)grid), dim3(kGroupThreads), 0, stream, args);
   if (hipGetLastError() != hipSuccess) return JSIDX_E_HIP;
   return JSIDX_OK;
 }

@@ -23,7 +23,9 @@
 
 namespace jsidx {
 
-constexpr int kThreads = 64;  // one wave per workgroup
+constexpr int kThreads = 64;  // lanes per wave; a wave owns one tile at a time
+constexpr int kWaves = 8;     // waves per workgroup (they share only their first tickets)
+constexpr int kGroupThreads = kWaves * kThreads;
 constexpr int kSegBytes = 32;
 constexpr int kRowBytes = kThreads * kSegBytes;  // 2 KiB
 constexpr int kRows = 16;
@@ -138,9 +140,12 @@ struct Shared {
   uint32_t hF[kRows][kThreads];
   // the head document ends in the head region: its last byte and flags there
   uint32_t he_valid, he_R0, he_EA, he_u;
-  uint32_t tile;
-  uint32_t epoch;
-  uint32_t is_last;
+};
+
+struct GroupShared {
+  Shared w[kWaves];
+  uint32_t first;    // the workgroup's first ticket
+  uint32_t is_last;  // this workgroup finishes the launch
 };
 
 // Facts about a tile computed by tile_local (wave-uniform unless noted).
@@ -891,13 +896,15 @@ JSIDX_DEV void look_back(const Args& a, int64_t t, uint32_t epoch, uint32_t* s_o
 
 // ---------------------------------------------------------------------------
 JSIDX_DEVFN void index_tiles(const Args& a) {
-  Shared& sh = prim::lds_object<Shared>();
+  GroupShared& gs = prim::lds_object<GroupShared>();
+  const uint32_t wv = prim::wave_id();
+  Shared& sh = gs.w[wv];
   const uint32_t lane = prim::lane();
   Workspace* ws = a.ws;
 
-  if (lane == 0) sh.epoch = prim::ld_agent32(&ws->epoch);
-  prim::sync();
-  const uint32_t epoch = sh.epoch;
+  uint32_t epoch = 0;
+  if (lane == 0) epoch = prim::ld_agent32(&ws->epoch);
+  epoch = prim::readlane(epoch, 0);
 
   const int64_t begin = doc_off(a, 0);
   const int64_t end = doc_off(a, (int64_t)a.ndocs);
@@ -909,17 +916,27 @@ JSIDX_DEVFN void index_tiles(const Args& a) {
 
   if ((uint64_t)ntiles > a.cap_tiles) {
     // Not indexed: flag every document.
-    for (int64_t d = (int64_t)prim::block() * kThreads + lane; d < a.ndocs; d += (int64_t)prim::grid() * kThreads) {
+    for (int64_t d = ((int64_t)prim::block() * kWaves + wv) * kThreads + lane; d < a.ndocs;
+         d += (int64_t)prim::grid() * kGroupThreads) {
       prim::st_out(a.out_n + d, 0u);
       prim::st_out(a.out_err + d, JSIDX_ERR_CAPACITY);
     }
     goto finish;
   }
 
-  while (true) {
-    if (lane == 0) sh.tile = prim::add_agent32(&ws->ticket, 1u);
-    prim::sync();
-    const int64_t t = (int64_t)sh.tile;
+  // A workgroup takes its first kWaves tiles with one atomic (a launch starts
+  // thousands of waves at once; one counter would serialise them), then each
+  // wave takes tiles one at a time.  Tiles are only ever handed to running
+  // waves, in increasing order.
+  if (wv == 0 && lane == 0) gs.first = prim::add_agent32(&ws->ticket, (uint32_t)kWaves);
+  prim::sync();
+  for (uint32_t tk = gs.first + wv, first = 1;; first = 0) {
+    if (!first) {
+      uint32_t v = 0;
+      if (lane == 0) v = prim::add_agent32(&ws->ticket, 1u);
+      tk = prim::readlane(v, 0);
+    }
+    const int64_t t = (int64_t)tk;
     if (t >= ntiles) break;
     prim::trace(t, 0);
     const int64_t P0 = pos_g0 + t * kTileBytes;  // position of tile byte 0
@@ -977,7 +994,7 @@ JSIDX_DEVFN void index_tiles(const Args& a) {
         sh.overflow = count > kDocCap + 1;
       }
     }
-    prim::sync();
+    prim::wave_sync();
     prim::trace(t, 1);
 
     // ---- local pass, look-back, and (rarely) an exact second local pass ------
@@ -1151,7 +1168,7 @@ JSIDX_DEVFN void index_tiles(const Args& a) {
         prim::st_out(a.out_err + d_first + hd, err);
       }
     }
-    prim::sync();
+    prim::wave_sync();
     prim::trace(t, 7);
   }
 
@@ -1160,19 +1177,20 @@ finish:
   // a rotating window of descriptors so that no stale descriptor can ever
   // carry a matching epoch.
   prim::sync();
-  if (lane == 0) {
+  if (wv == 0 && lane == 0) {
     prim::wait_mem();
     const uint32_t old = prim::add_agent32(&ws->done, 1u);
-    sh.is_last = (old == prim::grid() - 1) ? 1u : 0u;
+    gs.is_last = (old == prim::grid() - 1) ? 1u : 0u;
   }
   prim::sync();
-  if (sh.is_last) {
+  if (gs.is_last) {
+    const uint64_t gl = (uint64_t)wv * kThreads + lane;
     const uint64_t nwin = (a.cap_tiles + kScrub - 1) / kScrub;
     const uint64_t w0 = (uint64_t)(epoch % (uint32_t)(nwin ? nwin : 1)) * kScrub;
-    for (uint64_t j = w0 + lane; j < w0 + kScrub && j < a.cap_tiles; j += kThreads) st_desc(ws, (int64_t)j, 0ull);
-    for (uint64_t j = lane; j < 3 * blocks_for_tiles(a.cap_tiles); j += kThreads) prim::st_agent(block_desc(a) + j, 0ull);
+    for (uint64_t j = w0 + gl; j < w0 + kScrub && j < a.cap_tiles; j += kGroupThreads) st_desc(ws, (int64_t)j, 0ull);
+    for (uint64_t j = gl; j < 3 * blocks_for_tiles(a.cap_tiles); j += kGroupThreads) prim::st_agent(block_desc(a) + j, 0ull);
     prim::sync();
-    if (lane == 0) {
+    if (wv == 0 && lane == 0) {
       prim::st_agent32(&ws->ticket, 0u);
       prim::st_agent32(&ws->done, 0u);
       prim::st_agent32(&ws->epoch, epoch + 1u);

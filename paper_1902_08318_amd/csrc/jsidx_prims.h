@@ -22,6 +22,7 @@ JSIDX_DEV uint32_t tid() { return threadIdx.x; }
 JSIDX_DEV uint32_t block() { return blockIdx.x; }
 JSIDX_DEV uint32_t grid() { return gridDim.x; }
 JSIDX_DEV uint32_t lane() { return __lane_id(); }
+JSIDX_DEV uint32_t wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
 JSIDX_DEV uint64_t ballot(bool p) { return __ballot(p); }
 JSIDX_DEV uint32_t shfl(uint32_t v, int src) { return (uint32_t)__shfl((int)v, src); }
@@ -59,6 +60,13 @@ JSIDX_DEV uint32_t incl_max_scan(uint32_t v) {
 JSIDX_DEV uint32_t shr1(uint32_t v, uint32_t fill) { return __builtin_amdgcn_update_dpp(fill, v, 0x138, 0xF, 0xF, false); }
 
 JSIDX_DEV void sync() { __syncthreads(); }
+// LDS written by some lanes of a wave is visible to the wave's other lanes.
+JSIDX_DEV void wave_sync() {
+  __asm__ __volatile__("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+  __builtin_amdgcn_wave_barrier();
+  __asm__ __volatile__("" ::: "memory");
+}
 JSIDX_DEV int sync_count(bool p) { return __syncthreads_count(p); }
 JSIDX_DEV void sleep() { __builtin_amdgcn_s_sleep(1); }
 // Look-back waits give up after this many sleeps (about half a second).

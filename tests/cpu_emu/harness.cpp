@@ -19,7 +19,8 @@ using namespace jsidx;
 
 extern "C" {
 
-// Index through the kernel body with `nblocks` concurrent workgroups.
+// Index through the kernel body with `nblocks` concurrent waves (rounded up
+// to whole workgroups).
 //   granule_lo/hi: the bytes the kernel may read (the aligned 16-byte granules
 //   overlapping the input).  Returns the number of out-of-range accesses.
 //   ws_state: persistent workspace (caller allocated, zeroed once) so that
@@ -45,15 +46,17 @@ long emu_run(const uint8_t* base, const uint64_t* offsets, uint64_t len, uint32_
   a.ws = (Workspace*)ws_mem;
   a.cap_tiles = cap_tiles;
 
+  // nblocks counts waves; they run as whole workgroups of kWaves waves
+  const int ngroups = (nblocks + kWaves - 1) / kWaves;
   std::vector<prim::GroupCtx*> groups;
-  for (int b = 0; b < nblocks; b++) groups.push_back(new prim::GroupCtx(kThreads));
+  for (int b = 0; b < ngroups; b++) groups.push_back(new prim::GroupCtx(kGroupThreads));
   std::vector<std::thread> th;
-  for (int b = 0; b < nblocks; b++) {
-    for (uint32_t t = 0; t < (uint32_t)kThreads; t++) {
+  for (int b = 0; b < ngroups; b++) {
+    for (uint32_t t = 0; t < (uint32_t)kGroupThreads; t++) {
       th.emplace_back([&, b, t] {
         prim::tctx.tid = t;
         prim::tctx.block = (uint32_t)b;
-        prim::tctx.grid = (uint32_t)nblocks;
+        prim::tctx.grid = (uint32_t)ngroups;
         prim::tctx.g = groups[(size_t)b];
         prim::tctx.env = &env;
         index_tiles(a);

@@ -58,10 +58,10 @@ struct WaveCtx {
 struct GroupCtx {
   explicit GroupCtx(int threads) : bar(threads) {}
   Barrier bar;
-  WaveCtx waves[4];
+  WaveCtx waves[16];
   std::atomic<int> count{0};
   int count_result = 0;
-  alignas(64) unsigned char lds[1 << 16];
+  alignas(64) unsigned char lds[1 << 18];
 };
 
 struct Range {
@@ -125,6 +125,7 @@ inline uint32_t tid() { return tctx.tid; }
 inline uint32_t block() { return tctx.block; }
 inline uint32_t grid() { return tctx.grid; }
 inline uint32_t lane() { return tctx.tid & 63u; }
+inline uint32_t wave_id() { return tctx.tid >> 6; }
 
 inline WaveCtx& wave() { return tctx.g->waves[tctx.tid >> 6]; }
 inline uint64_t ballot(bool p) {
@@ -180,6 +181,7 @@ inline uint32_t incl_scan(uint32_t v) {
 }
 
 inline void sync() { tctx.g->bar.wait(); }
+inline void wave_sync() { wave().bar.wait(); }
 inline int sync_count(bool p) {
   GroupCtx* g = tctx.g;
   if (p) g->count.fetch_add(1);

@@ -252,6 +252,34 @@ JSIDX_DEV void load_segment(const Args& a, int64_t pos, int64_t begin, int64_t e
   }
 }
 
+// Writes the positions of this lane's set bits of F (the lane's 32 bytes start
+// at document offset rel) at ranks from *cc plus the lanes below; *cc
+// advances by the row's total.  Ranks at or past lim are not written (only a
+// look-back that gave up could produce them).
+JSIDX_DEV void write_row(uint32_t* out, uint64_t lim, uint32_t* cc, uint32_t F, uint32_t rel) {
+  const uint32_t n = (uint32_t)__builtin_popcount(F);
+  const uint32_t incl = prim::incl_scan(n);
+  const uint32_t row_n = prim::readlane(incl, 63);
+  uint32_t kk = *cc + incl - n;
+  const bool checked = (uint64_t)*cc + row_n > lim;
+  *cc += row_n;
+  if (!checked) {
+    while (F) {
+      const uint32_t j = (uint32_t)__builtin_ctz(F);
+      F &= F - 1u;
+      prim::st_out(out + kk, rel + j);
+      kk++;
+    }
+  } else {
+    while (F) {
+      const uint32_t j = (uint32_t)__builtin_ctz(F);
+      F &= F - 1u;
+      if ((uint64_t)kk < lim) prim::st_out(out + kk, rel + j);
+      kk++;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // The local pass over one tile, given the incoming state st_in.  Bytes at or
 // after the tile's first document start do not depend on st_in: their
@@ -338,11 +366,32 @@ JSIDX_DEV void tile_local(const Args& a, Shared& sh, int64_t P0, int64_t begin, 
       uc = u8_carry_zero();
     }
 
+    // A plain row has no document start or end and only valid bytes: every
+    // lane continues the document open at the row start.
+    const bool plain = SIMPLE || prim::ballot(D != 0u || d32 != 0u || V != ~0u) == 0ull;
+
     // escapes: a segment with a non-backslash byte or a document start fixes
     // the escape state after it; an all-backslash segment (even length) keeps it
+    if (!SIMPLE && !T.any_const) {
+      // the tile's first byte that is not a backslash or starts a document
+      // (used when the escape entering the tile is only known later)
+      const uint64_t Kc = prim::ballot((cm.B != ~0u) || (D != 0u));
+      if (Kc) {
+        const int f = __builtin_ctzll(Kc);
+        const uint32_t nbd = ~cm.B | D;
+        const uint32_t pl0 = nbd ? (uint32_t)__builtin_ctz(nbd) : 0u;
+        const uint32_t pf = prim::readlane(pl0, f);
+        const uint32_t rf = prim::readlane((D >> pl0) & 1u, f);
+        const uint32_t qf = prim::readlane((cm.Q >> pl0) & 1u, f);
+        T.lead_pos = (uint32_t)(r * kRowBytes + f * kSegBytes) + pf;
+        T.lead_reset = rf;
+        T.qsens = rf ? 0u : qf;
+        T.any_const = 1;
+      }
+    }
     uint32_t e_in = 0, OD = 0, EA = 0;
     bool done_e = false;
-    if constexpr (SIMPLE) {
+    if (plain) {
       if (prim::ballot(cm.B != 0u) == 0ull) {
         e_in = lane == 0 ? ce : 0u;
         OD = e_in;
@@ -364,17 +413,6 @@ JSIDX_DEV void tile_local(const Args& a, Shared& sh, int64_t P0, int64_t begin, 
       const uint64_t Ec = prim::ballot(eo != 0u);
       const uint64_t mk = Kc & lt_lanes();
       e_in = mk ? (uint32_t)((Ec >> msb64(mk)) & 1ull) : ce;
-      if (!SIMPLE && !T.any_const && Kc) {
-        const int f = __builtin_ctzll(Kc);
-        const uint32_t pl0 = (uint32_t)__builtin_ctz(~cm.B | D);
-        const uint32_t pf = prim::readlane(pl0, f);
-        const uint32_t rf = prim::readlane((D >> pl0) & 1u, f);
-        const uint32_t qf = prim::readlane((cm.Q >> pl0) & 1u, f);
-        T.lead_pos = (uint32_t)(r * kRowBytes + f * kSegBytes) + pf;
-        T.lead_reset = rf;
-        T.qsens = rf ? 0u : qf;
-        T.any_const = 1;
-      }
       if (Kc) ce = (uint32_t)((Ec >> msb64(Kc)) & 1ull);
       OD = escaped_bytes(cm.B, D, e_in, &EA);
     }
@@ -385,7 +423,7 @@ JSIDX_DEV void tile_local(const Args& a, Shared& sh, int64_t P0, int64_t begin, 
     uint32_t R0 = PX;
     uint64_t Rs = 0;
     uint32_t uin = 0, first_reset = 32u, last_start = 0;
-    if constexpr (SIMPLE) {
+    if (plain) {
       const uint64_t Qb = prim::ballot((__builtin_popcount(Q) & 1u) != 0u);
       const uint32_t qin = (prim::mbcnt(Qb) & 1u) ^ cq;
       R0 ^= 0u - qin;
@@ -430,7 +468,9 @@ JSIDX_DEV void tile_local(const Args& a, Shared& sh, int64_t P0, int64_t begin, 
     }
     const uint32_t K = (cm.C | Q | (PR & ~P0m)) & V;
     const uint32_t F0 = K & ~(Q ^ R0);
-    if constexpr (SIMPLE) {
+    const bool had_reset = T.reset_any != 0;
+    if (SIMPLE || (plain && defer && !had_reset)) {
+      // the whole row lies in the head region
       sh.hK[r][lane] = K;
       sh.hF[r][lane] = F0;
       T.head_rows = (uint32_t)r + 1u;
@@ -438,8 +478,14 @@ JSIDX_DEV void tile_local(const Args& a, Shared& sh, int64_t P0, int64_t begin, 
       T.a1 += (uint32_t)__builtin_popcount(K & ~F0);
       continue;
     }
+    if (plain) {
+      // the whole row continues the open document
+      const int32_t h0 = prim::readlane((uint32_t)head, 0);
+      const int64_t doff = doc_start(a, sh, P0, d_first, h0);
+      write_row(a.out_idx + doff, (uint64_t)(end - doff), &cc, F0, (uint32_t)(pos - doff));
+      continue;
+    }
 
-    const bool had_reset = T.reset_any != 0;
     if (Rs && !had_reset) {
       const int fl = __builtin_ctzll(Rs);
       T.r0 = (uint32_t)(r * kRowBytes + fl * kSegBytes) + prim::readlane(first_reset, fl);
@@ -489,12 +535,14 @@ JSIDX_DEV void tile_local(const Args& a, Shared& sh, int64_t P0, int64_t begin, 
       const int64_t doff = doc_start(a, sh, P0, d_first, dloc);
       uint32_t* out = a.out_idx + doff;
       const uint32_t rel_doc = (uint32_t)(pos - doff);
+      const int64_t room = end - doff;
+      const uint32_t lim = room > 0xFFFFFFFFll ? 0xFFFFFFFFu : (uint32_t)room;
       uint32_t f = F0 & wmask & segm;
       uint32_t kk = cont ? cin : 0u;
       while (f) {
         const uint32_t j = (uint32_t)__builtin_ctz(f);
         f &= f - 1u;
-        if ((uint64_t)(doff + kk) < (uint64_t)end) prim::st_out(out + kk, rel_doc + j);
+        if (kk < lim) prim::st_out(out + kk, rel_doc + j);
         kk++;
       }
       if (ends_doc) {
@@ -1135,28 +1183,7 @@ JSIDX_DEVFN void index_tiles(const Args& a) {
         const uint32_t hK = sh.hK[r][lane], hF = sh.hF[r][lane];
         uint32_t F = qT ? (hF ^ hK) : hF;
         if (r == 0 && lane == 0) F |= pfix;
-        const uint32_t n = (uint32_t)__builtin_popcount(F);
-        const uint32_t incl = prim::incl_scan(n);
-        const uint32_t row_n = prim::readlane(incl, 63);
-        uint32_t kk = cc + incl - n;
-        const bool checked = (uint64_t)cc + row_n > lim;
-        cc += row_n;
-        const uint32_t rel = rel0 + r * (uint32_t)kRowBytes;
-        if (!checked) {
-          while (F) {
-            const uint32_t j = (uint32_t)__builtin_ctz(F);
-            F &= F - 1u;
-            prim::st_out(out + kk, rel + j);
-            kk++;
-          }
-        } else {
-          while (F) {
-            const uint32_t j = (uint32_t)__builtin_ctz(F);
-            F &= F - 1u;
-            if ((uint64_t)kk < lim) prim::st_out(out + kk, rel + j);
-            kk++;
-          }
-        }
+        write_row(out, lim, &cc, F, rel0 + r * (uint32_t)kRowBytes);
       }
       if (sh.he_valid && lane == 0) {
         uint32_t err = 0;

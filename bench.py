@@ -29,6 +29,32 @@ sys.path.insert(0, ROOT)
 
 METRIC = "structural-index GB/s (1 doc & batched) vs HBM peak; docs/s; p99 latency"
 HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ["jsidx.hip", "jsidx_device.h", "jsidx_kernel.h", "jsidx_prims.h"]
+PROFILE = os.path.join(ROOT, "profiles", "index_kernel_c1_256MiB.md")
+
+
+def kernel_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1902_08318_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic():
+    """HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)
+    from the committed C1 profile, if it was taken on the current kernel."""
+    try:
+        text = open(PROFILE).read()
+    except OSError:
+        return None
+    import re
+    m_hash = re.search(r"sha256\[:16\]: `([0-9a-f]{16})`", text)
+    m_bytes = re.search(r"traffic_bytes_per_launch: (\d+)", text)
+    if not m_hash or not m_bytes or m_hash.group(1) != kernel_hash():
+        return None
+    return int(m_bytes.group(1))
 
 
 def log(msg):
@@ -187,7 +213,8 @@ def main():
                    "bytes": r1["N"], "index_entries": r1["S"], "bytes_per_entry": round(r1["N"] / max(1, r1["S"]), 2),
                    "flags": r1["flags"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": profiled_traffic() if args.workload == "c1" else None},
     }
     extra = {}
     if not args.no_extra:

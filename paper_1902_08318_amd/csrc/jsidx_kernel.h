@@ -28,7 +28,11 @@ constexpr int kWaves = 8;     // waves per workgroup (they share only their firs
 constexpr int kGroupThreads = kWaves * kThreads;
 constexpr int kSegBytes = 32;
 constexpr int kRowBytes = kThreads * kSegBytes;  // 2 KiB
-constexpr int kRows = 16;
+// Rows per tile (test and tuning builds may override).
+#ifndef JSIDX_TILE_ROWS
+#define JSIDX_TILE_ROWS 16
+#endif
+constexpr int kRows = JSIDX_TILE_ROWS;
 constexpr int kTileBytes = kRows * kRowBytes;  // 32 KiB
 constexpr int kDocCap = 256;                   // documents per tile held in LDS
 constexpr int kScrub = 4096;                   // descriptors cleared per launch
@@ -140,6 +144,10 @@ struct Shared {
   uint32_t hF[kRows][kThreads];
   // the head document ends in the head region: its last byte and flags there
   uint32_t he_valid, he_R0, he_EA, he_u;
+  // plain rows after a document start, written after publishing: the
+  // document's start and its count before the row
+  int64_t tr_doff[kRows];
+  uint32_t tr_cc[kRows];
 };
 
 struct GroupShared {
@@ -162,6 +170,8 @@ struct TileFacts {
   uint32_t a0, a1;     // per lane, head region: popcount(F0), popcount(K & ~F0)
   uint32_t tail_count; // count of the document open at the tile's end, since
                        // its start in this tile (valid if reset_any)
+  uint32_t tail_rows;  // plain rows after a document start kept for writing
+                       // after the tile has published (bit r = row r)
 };
 
 // Local document index of tile-relative position rel (table mode only): the
@@ -298,6 +308,7 @@ JSIDX_DEV void tile_local(const Args& a, Shared& sh, int64_t P0, int64_t begin, 
   uint32_t cc = head_base;  // count of the open document before this row
   T.any_const = 0; T.lead_pos = kTileBytes; T.lead_reset = 0; T.qsens = 0;
   T.reset_any = 0; T.r0 = kTileBytes; T.elig0 = 0; T.head_rows = 0; T.a0 = 0; T.a1 = 0; T.tail_count = 0;
+  T.tail_rows = 0;
   if (lane == 0) sh.he_valid = 0;
 
   // UTF-8 context entering the tile: the last bytes of the head document
@@ -479,10 +490,18 @@ JSIDX_DEV void tile_local(const Args& a, Shared& sh, int64_t P0, int64_t begin, 
       continue;
     }
     if (plain) {
-      // the whole row continues the open document
+      // the whole row continues the open document; in the first pass its
+      // positions are written after the tile has published its descriptor
       const int32_t h0 = prim::readlane((uint32_t)head, 0);
       const int64_t doff = doc_start(a, sh, P0, d_first, h0);
-      write_row(a.out_idx + doff, (uint64_t)(end - doff), &cc, F0, (uint32_t)(pos - doff));
+      if (defer) {
+        sh.hF[r][lane] = F0;
+        if (lane == 0) { sh.tr_doff[r] = doff; sh.tr_cc[r] = cc; }
+        T.tail_rows |= 1u << r;
+        cc += wave_sum((uint32_t)__builtin_popcount(F0));
+      } else {
+        write_row(a.out_idx + doff, (uint64_t)(end - doff), &cc, F0, (uint32_t)(pos - doff));
+      }
       continue;
     }
 
@@ -790,11 +809,12 @@ JSIDX_DEV void poll_sleep(uint32_t polls) {
   for (int i = 0; i < n; i++) prim::sleep();
 }
 
-// The last tile of block b to publish its aggregate folds the block (each
+// The last tile of block b to publish its descriptor folds the block (each
 // lane folds 4 tile descriptors, then lanes combine pairwise, the older
-// partner at lane + s) and publishes the block aggregate.  It then walks the
-// blocks before (one per lane, up to 64 back) for the state entering block b,
-// which every tile of the block waits for, and the block's inclusive value.
+// partner at lane + s) and publishes the block aggregate.  Unless the fold is
+// already an inclusive value, it then walks the blocks before (one per lane,
+// up to 64 back) for the state entering block b and publishes the block's
+// inclusive value, which the tiles of block b + 1 wait for.
 JSIDX_DEV void compose_block(const Args& a, int64_t b, int64_t ntiles, uint32_t epoch) {
   const uint32_t lane = prim::lane();
   const int64_t lo = b * kBlockTiles;
@@ -846,23 +866,22 @@ JSIDX_DEV void compose_block(const Args& a, int64_t b, int64_t ntiles, uint32_t 
     // value follows from its last tile once the escape-sensitive tile has
     // redone its pass
   }
-  // the state entering block b
+  if (B.known || !B.has) return;
+  // the state entering block b (walk over the blocks before), then the
+  // block's inclusive value
   uint32_t es = 0, ec = 0;
   if (b > 0) {
     for (uint32_t polls = 0;; polls++) {
       const WalkOut w2 = walk(read_block(a, b - 1 - (int64_t)lane, epoch));
       if (w2.ready && !w2.blocked) { es = w2.state; ec = w2.count; break; }
-      if (polls > prim::kSpinLimit) { prim::st_agent32(&a.ws->diag, 1u); break; }
+      if (polls > prim::kSpinLimit) { prim::st_agent32(&a.ws->diag, 1u); return; }
       poll_sleep(polls);
     }
   }
   if (lane == 0) {
-    prim::st_agent(bd + 2, make_inc(es, 0u, ec, epoch));
-    if (!B.known && B.has) {
-      LaneFold K = fold_known(es, ec);
-      compose(K, B);
-      if (!K.blocked) prim::st_agent(bd + 1, make_inc(K.ks, 0u, K.kc, epoch));
-    }
+    LaneFold K = fold_known(es, ec);
+    compose(K, B);
+    if (!K.blocked) prim::st_agent(bd + 1, make_inc(K.ks, 0u, K.kc, epoch));
   }
 }
 
@@ -880,16 +899,13 @@ JSIDX_DEV void look_back(const Args& a, int64_t t, uint32_t epoch, uint32_t* s_o
       return;
     }
     if (!have_blk) {
+      // the previous block's inclusive value (not needed if this block's
+      // tiles before t hold an inclusive descriptor)
       uint64_t v = 0;
-      if (lane == 0) v = prim::ld_agent(block_desc(a) + 3 * b + 2);
+      if (lane == 0) v = prim::ld_agent(block_desc(a) + 3 * (b - 1) + 1);
       const uint32_t lo32 = prim::readlane((uint32_t)v, 0), hi32 = prim::readlane((uint32_t)(v >> 32), 0);
       v = ((uint64_t)hi32 << 32) | lo32;
-      if (!(d_current(v, epoch) && d_flag(v) == kInc)) {
-        prim::trace_count(t, 8);
-        poll_sleep(polls);
-        continue;
-      }
-      have_blk = true; bs = d_state(v); bc = d_count(v);
+      if (d_current(v, epoch) && d_flag(v) == kInc) { have_blk = true; bs = d_state(v); bc = d_count(v); }
     }
     // the tiles of this block before t; the tile before the block holds the
     // block's incoming value
@@ -898,7 +914,7 @@ JSIDX_DEV void look_back(const Args& a, int64_t t, uint32_t epoch, uint32_t* s_o
 #pragma unroll
     for (int m = 0; m < 4; m++) {
       const int64_t j = j0 - m;
-      d[m] = j >= lo ? ld_desc(ws, j) : (j == lo - 1 ? make_inc(bs, 0u, bc, epoch) : 0ull);
+      d[m] = j >= lo ? ld_desc(ws, j) : ((j == lo - 1 && have_blk) ? make_inc(bs, 0u, bc, epoch) : 0ull);
     }
     // Ready when some lane holds an inclusive descriptor and every descriptor
     // newer than the newest one is published: only then fold (a failed poll
@@ -1095,6 +1111,7 @@ JSIDX_DEVFN void index_tiles(const Args& a) {
     bool exact = false;  // set by the rare exact second pass
     const bool simple = !sh.overflow && sh.ntab == 1 && sh.tab[0] < 0 && hd_ok && e_known && !exact;
     uint32_t table = 0, cnt0 = 0, cnt1 = 0, esens = 0;
+    bool inc_done = false;
     // pass 0: the local pass with the escape state read before the tile;
     // pass 1 (rare): an exact local pass, when the escape carried in turned
     // out to change this tile's head
@@ -1128,13 +1145,23 @@ JSIDX_DEVFN void index_tiles(const Args& a) {
         }
       }
       esens = e_known ? 0u : (T.qsens | ((T.lead_reset && T.lead_pos > 0) ? 1u : 0u));
-      if (exact) break;
-      if (pass == 0) {
-        if (lane == 0) st_desc(ws, t, make_agg(table, cnt0, cnt1, T.elig0, esens, epoch));
+      // Publish.  After a document start nothing depends on earlier tiles, so
+      // a tile holding one publishes its inclusive value right away.
+      inc_done = T.reset_any != 0;
+      if (lane == 0) {
+        if (inc_done) {
+          const uint64_t inc = make_inc(T.carry, 1u, T.tail_count, epoch);
+          st_desc(ws, t, inc);
+          if (t % kBlockTiles == kBlockTiles - 1) prim::st_agent(block_desc(a) + 3 * (t / kBlockTiles) + 1, inc);
+        } else {
+          st_desc(ws, t, make_agg(table, cnt0, cnt1, T.elig0, esens, epoch));
+        }
+      }
+      {
         // count the block's published tiles; the last one folds the block
         const int64_t blk = t / kBlockTiles;
         const int64_t nblk = (ntiles - blk * kBlockTiles) < kBlockTiles ? (ntiles - blk * kBlockTiles) : kBlockTiles;
-        prim::wait_mem();  // the aggregate is written before it is counted
+        prim::wait_mem();  // the descriptor is written before it is counted
         uint32_t old = 0;
         if (lane == 0) old = prim::add_agent32(block_count(a) + blk, 1u);
         old = prim::readlane(old, 0);
@@ -1142,6 +1169,23 @@ JSIDX_DEVFN void index_tiles(const Args& a) {
           compose_block(a, blk, ntiles, epoch);
           if (lane == 0) prim::st_agent32(block_count(a) + blk, 0u);  // ready for the next launch
         }
+      }
+      // plain rows after a document start
+      if (T.tail_rows) {
+        prim::wave_sync();
+        uint32_t rows = T.tail_rows;
+        while (rows) {
+          const int r = __builtin_ctz(rows);
+          rows &= rows - 1u;
+          const int64_t doff = sh.tr_doff[r];
+          uint32_t cc = sh.tr_cc[r];
+          const int64_t pos = P0 + (int64_t)r * kRowBytes + (int64_t)lane * kSegBytes;
+          write_row(a.out_idx + doff, (uint64_t)(end - doff), &cc, sh.hF[r][lane], (uint32_t)(pos - doff));
+        }
+      }
+      if (inc_done && !(hd_ok && T.r0 > 0)) {  // no head region: nothing needs the look-back
+        prim::trace(t, 3);
+        break;
       }
       look_back(a, t, epoch, &s_in, &base);
       prim::trace(t, 3);
@@ -1159,7 +1203,7 @@ JSIDX_DEVFN void index_tiles(const Args& a) {
       const uint32_t q = (s_in >> 1) & 1u, p = (s_in >> 2) & 1u;
       inc_count = T.reset_any ? cnt0 : base + (q ? cnt1 : cnt0 + (p & T.elig0));
     }
-    if (lane == 0) {
+    if (lane == 0 && !inc_done) {
       const uint64_t inc = make_inc(st_out, T.reset_any, inc_count, epoch);
       st_desc(ws, t, inc);
       if (t % kBlockTiles == kBlockTiles - 1) prim::st_agent(block_desc(a) + 3 * (t / kBlockTiles) + 1, inc);

@@ -582,14 +582,14 @@ JSIDX_DEV void tile_local(const Args& a, Shared& sh, int64_t P0, int64_t begin, 
 
 // ---- the look-back ----------------------------------------------------------
 // Tiles are grouped in blocks of kBlockTiles.  A tile's incoming state comes
-// from one window read in one round trip: the tiles of its block before it
-// and the whole block before that, 8 tile descriptors per lane, plus the
-// inclusive value of the block two back (before block 0 lies the initial
-// state).  The last tile of a block to publish folds the block's tile
-// descriptors into a block aggregate and, walking the blocks before it (one
-// per lane, up to 64 back), the block's inclusive value.  So no tile waits
-// for a tile with a higher index, and the wait of a tile is bounded by the
-// local passes of the tiles before it, not by a chain of look-backs.
+// from two windows, each read in one round trip: the blocks before its own
+// (one block descriptor per lane, up to 64 blocks back; before block 0 lies
+// the initial state) and the tiles of its own block before it (4 tile
+// descriptors per lane).  The last tile of a block to publish its aggregate
+// folds the block's tile descriptors into a block aggregate; the block's last
+// tile publishes the block's inclusive value once it is resolved.  So no tile
+// waits for a tile with a higher index, and the wait of a tile is bounded by
+// the local passes of the tiles before it, not by a chain of look-backs.
 //
 // Lanes fold their descriptors (oldest first) into either a known state (if
 // one is inclusive) or a transfer of the same kind as a tile's; the walk from
@@ -814,7 +814,7 @@ JSIDX_DEV void poll_sleep(uint32_t polls) {
 // partner at lane + s) and publishes the block aggregate.  Unless the fold is
 // already an inclusive value, it then walks the blocks before (one per lane,
 // up to 64 back) for the state entering block b and publishes the block's
-// inclusive value, which the tiles of block b + 2 start their window from.
+// inclusive value, which the tiles of block b + 1 wait for.
 JSIDX_DEV void compose_block(const Args& a, int64_t b, int64_t ntiles, uint32_t epoch) {
   const uint32_t lane = prim::lane();
   const int64_t lo = b * kBlockTiles;
@@ -885,20 +885,13 @@ JSIDX_DEV void compose_block(const Args& a, int64_t b, int64_t ntiles, uint32_t 
   }
 }
 
-// State entering tile t and the count of its head document before it.  The
-// window is the tiles of t's block before it and the whole block before that
-// (8 descriptors per lane); the value entering the window is the inclusive
-// value of the block two back, which is normally published long before.
-constexpr int kLbPerLane = 8;
-static_assert(kLbPerLane * 64 >= 2 * kBlockTiles, "the window must hold two blocks");
-
+// State entering tile t and the count of its head document before it.
 JSIDX_DEV void look_back(const Args& a, int64_t t, uint32_t epoch, uint32_t* s_out, uint32_t* base_out) {
   const uint32_t lane = prim::lane();
   Workspace* ws = a.ws;
-  const int64_t b = t / kBlockTiles;
-  const int64_t lo = b > 0 ? (b - 1) * kBlockTiles : 0;  // oldest tile of the window
-  bool have_blk = b <= 1;
-  uint32_t bs = 0, bc = 0;  // state and count entering the window (the initial state before block 0)
+  const int64_t b = t / kBlockTiles, lo = b * kBlockTiles;
+  bool have_blk = b == 0;
+  uint32_t bs = 0, bc = 0;  // state and count entering the block (block 0: the initial state)
   for (uint32_t polls = 0;; polls++) {
     if (polls > prim::kSpinLimit) {  // never expected: give up, flag it
       prim::st_agent32(&ws->diag, 1u);
@@ -906,20 +899,20 @@ JSIDX_DEV void look_back(const Args& a, int64_t t, uint32_t epoch, uint32_t* s_o
       return;
     }
     if (!have_blk) {
-      // the inclusive value of block b - 2 (not needed if the window holds an
-      // inclusive tile descriptor)
+      // the previous block's inclusive value (not needed if this block's
+      // tiles before t hold an inclusive descriptor)
       uint64_t v = 0;
-      if (lane == 0) v = prim::ld_agent(block_desc(a) + 3 * (b - 2) + 1);
+      if (lane == 0) v = prim::ld_agent(block_desc(a) + 3 * (b - 1) + 1);
       const uint32_t lo32 = prim::readlane((uint32_t)v, 0), hi32 = prim::readlane((uint32_t)(v >> 32), 0);
       v = ((uint64_t)hi32 << 32) | lo32;
       if (d_current(v, epoch) && d_flag(v) == kInc) { have_blk = true; bs = d_state(v); bc = d_count(v); }
     }
-    // this lane's tiles, newest first; the tile before the window holds the
-    // window's incoming value
-    const int64_t j0 = t - 1 - kLbPerLane * (int64_t)lane;
-    uint64_t d[kLbPerLane];
+    // the tiles of this block before t; the tile before the block holds the
+    // block's incoming value
+    const int64_t j0 = t - 1 - 4 * (int64_t)lane;  // this lane's newest tile
+    uint64_t d[4];
 #pragma unroll
-    for (int m = 0; m < kLbPerLane; m++) {
+    for (int m = 0; m < 4; m++) {
       const int64_t j = j0 - m;
       d[m] = j >= lo ? ld_desc(ws, j) : ((j == lo - 1 && have_blk) ? make_inc(bs, 0u, bc, epoch) : 0ull);
     }
@@ -927,15 +920,15 @@ JSIDX_DEV void look_back(const Args& a, int64_t t, uint32_t epoch, uint32_t* s_o
     // newer than the newest one is published: only then fold (a failed poll
     // costs a few operations).
     {
-      uint32_t m_inc = kLbPerLane, m_none = kLbPerLane;  // newest inclusive / unpublished in this lane
+      uint32_t m_inc = 4, m_none = 4;  // newest inclusive / unpublished in this lane
 #pragma unroll
-      for (int m = kLbPerLane - 1; m >= 0; m--) {
+      for (int m = 3; m >= 0; m--) {
         if (j0 - m < lo - 1) continue;
         const uint32_t fl = d_current(d[m], epoch) ? d_flag(d[m]) : (uint32_t)kNone;
         if (fl == kInc) m_inc = (uint32_t)m;
         if (fl == kNone) m_none = (uint32_t)m;
       }
-      const uint64_t Ki = prim::ballot(m_inc < (uint32_t)kLbPerLane);
+      const uint64_t Ki = prim::ballot(m_inc < 4u);
       const int ki = Ki ? __builtin_ctzll(Ki) : 64;
       const uint64_t Pn = prim::ballot(m_none < m_inc) & (lanes_below(ki) | (ki < 64 ? (1ull << ki) : 0ull));
       if (Ki == 0ull || Pn != 0ull) {
@@ -946,7 +939,7 @@ JSIDX_DEV void look_back(const Args& a, int64_t t, uint32_t epoch, uint32_t* s_o
     }
     LaneFold L = fold_empty();
 #pragma unroll
-    for (int m = kLbPerLane - 1; m >= 0; m--) {
+    for (int m = 3; m >= 0; m--) {
       const bool valid = j0 - m >= lo - 1;
       fold_desc(L, (valid && d_current(d[m], epoch)) ? d[m] : 0ull, valid);
     }

@@ -112,8 +112,9 @@ int jsidx_build_batch(const uint8_t *bufs, const uint64_t *offsets,
  * calls on that stream to the no-synchronisation mode described above.  Call
  * it before capturing a HIP graph so that the captured calls allocate nothing
  * (a later jsidx_build larger than the reservation still grows it).  The
- * workspace (tile descriptors and counters, about 8 bytes per 16 KiB of input)
- * is owned by the library, kept per stream until jsidx_release.
+ * workspace (tile descriptors and counters, plus 2 bits per input byte of
+ * deferred masks: about a quarter of the input size) is owned by the
+ * library, kept per stream until jsidx_release.
  */
 int jsidx_reserve(uint64_t max_total_len, jsidx_stream_t stream);
 

@@ -68,9 +68,14 @@ struct Workspace {
 };
 
 inline constexpr uint64_t blocks_for_tiles(uint64_t tiles) { return (tiles + kBlockTiles - 1) / kBlockTiles; }
-inline constexpr uint64_t workspace_bytes(uint64_t tiles) {
-  return sizeof(Workspace) + tiles * sizeof(uint64_t) + blocks_for_tiles(tiles) * (3 * sizeof(uint64_t) + sizeof(uint32_t));
+// Head-region masks of a tile (candidates, indexed bits if the tile starts
+// outside a string): one pair per lane and row.
+constexpr uint64_t kMaskBytesPerTile = (uint64_t)kRows * kThreads * 8;
+inline constexpr uint64_t mask_offset(uint64_t tiles) {
+  return (sizeof(Workspace) + tiles * sizeof(uint64_t) + blocks_for_tiles(tiles) * (3 * sizeof(uint64_t) + sizeof(uint32_t)) +
+          255) & ~(uint64_t)255;
 }
+inline constexpr uint64_t workspace_bytes(uint64_t tiles) { return mask_offset(tiles) + tiles * kMaskBytesPerTile; }
 
 JSIDX_DEV uint64_t epoch_bits(uint32_t epoch) { return ((uint64_t)epoch & kEpochMask) << kEpochShift; }
 JSIDX_DEV uint64_t make_agg(uint32_t table, uint32_t c0, uint32_t c1, uint32_t elig0, uint32_t esens, uint32_t epoch) {
@@ -137,10 +142,8 @@ struct Shared {
   int32_t ntab;
   int32_t overflow;
   int32_t tab[kDocCap + 1];
-  // head region (bytes before the tile's first document start), kept for the
-  // pass after the look-back: candidate bits and indexed bits assuming the
-  // tile starts outside a string
-  uint32_t hK[kRows][kThreads];
+  // indexed bits of plain rows after a document start, written after the
+  // tile has published (the head region's masks live in the workspace)
   uint32_t hF[kRows][kThreads];
   // the head document ends in the head region: its last byte and flags there
   uint32_t he_valid, he_R0, he_EA, he_u;
@@ -296,13 +299,15 @@ JSIDX_DEV void write_row(uint32_t* out, uint64_t lim, uint32_t* cc, uint32_t F, 
 // positions and per-document results are written here.  Bytes before it (the
 // head region) are written here too if `defer` is false (st_in and head_base,
 // the head document's count before the tile, are then exact); otherwise
-// their candidate and indexed bits go to LDS for the pass after the look-back.
+// their candidate and indexed bits go to the tile's mask slot (hmask) for the
+// pass after the look-back.
 // SIMPLE: no document starts or ends in [P0, P0 + kTileBytes] and the tile
 // lies inside the input (every byte belongs to document hd, which starts at
 // hs < P0), the escape state entering the tile is known, and defer is set.
 template <bool SIMPLE>
-JSIDX_DEV void tile_local(const Args& a, Shared& sh, int64_t P0, int64_t begin, int64_t end, int64_t d_first,
-                          int32_t hd, int64_t hs, uint32_t st_in, bool defer, uint32_t head_base, TileFacts& T) {
+JSIDX_DEV void tile_local(const Args& a, Shared& sh, uint2* hmask, int64_t P0, int64_t begin, int64_t end,
+                          int64_t d_first, int32_t hd, int64_t hs, uint32_t st_in, bool defer, uint32_t head_base,
+                          TileFacts& T) {
   const uint32_t lane = prim::lane();
   uint32_t ce = st_in & 1u, cq = (st_in >> 1) & 1u, cp = (st_in >> 2) & 1u, cu = (st_in >> 3) & 1u;
   uint32_t cc = head_base;  // count of the open document before this row
@@ -482,8 +487,7 @@ JSIDX_DEV void tile_local(const Args& a, Shared& sh, int64_t P0, int64_t begin, 
     const bool had_reset = T.reset_any != 0;
     if (SIMPLE || (plain && defer && !had_reset)) {
       // the whole row lies in the head region
-      sh.hK[r][lane] = K;
-      sh.hF[r][lane] = F0;
+      prim::st_pair(hmask + r * kThreads + lane, K, F0);
       T.head_rows = (uint32_t)r + 1u;
       T.a0 += (uint32_t)__builtin_popcount(F0);
       T.a1 += (uint32_t)__builtin_popcount(K & ~F0);
@@ -514,8 +518,7 @@ JSIDX_DEV void tile_local(const Args& a, Shared& sh, int64_t P0, int64_t begin, 
     const uint32_t hm = (uint32_t)rel >= T.r0 ? 0u : (T.r0 - (uint32_t)rel >= 32u ? ~0u : lt_mask(T.r0 - (uint32_t)rel));
     const bool row_has_head = !had_reset;
     if (defer && row_has_head) {
-      sh.hK[r][lane] = K & hm;
-      sh.hF[r][lane] = F0 & hm;
+      prim::st_pair(hmask + r * kThreads + lane, K & hm, F0 & hm);
       T.head_rows = (uint32_t)r + 1u;
       T.a0 += (uint32_t)__builtin_popcount(F0 & hm);
       T.a1 += (uint32_t)__builtin_popcount(K & ~F0 & hm);
@@ -719,6 +722,9 @@ JSIDX_DEV LaneFold fold_unpack(uint32_t f, uint32_t c0, uint32_t c1) {
 // All block words are cleared at the end of every launch.
 constexpr uint64_t kAggEpochMask = 31;
 JSIDX_DEV uint64_t* block_desc(const Args& a) { return a.ws->desc + a.cap_tiles; }
+JSIDX_DEV uint2* head_masks(const Args& a, int64_t t) {
+  return reinterpret_cast<uint2*>(reinterpret_cast<uint8_t*>(a.ws) + mask_offset(a.cap_tiles)) + t * (kRows * kThreads);
+}
 JSIDX_DEV uint32_t* block_count(const Args& a) {
   return reinterpret_cast<uint32_t*>(block_desc(a) + 3 * blocks_for_tiles(a.cap_tiles));
 }
@@ -959,6 +965,294 @@ JSIDX_DEV void look_back(const Args& a, int64_t t, uint32_t epoch, uint32_t* s_o
 }
 
 // ---------------------------------------------------------------------------
+// Per-tile set-up: the documents of the tile (LDS table) and the escape state
+// entering it.
+struct TileSetup {
+  int64_t t, P0, d_first, hs;
+  int32_t hd;
+  bool hd_ok, simple;
+  uint32_t e_T, e_known;
+};
+
+JSIDX_DEV TileSetup begin_tile(const Args& a, Shared& sh, int64_t t, int64_t pos_g0, int64_t end, int64_t ntiles) {
+  const uint32_t lane = prim::lane();
+  TileSetup S;
+  S.t = t;
+  S.P0 = pos_g0 + t * kTileBytes;  // position of tile byte 0
+  const int64_t P0 = S.P0, Pend = P0 + kTileBytes;
+  // d_first: the first document whose end is at or after the tile start.
+  int64_t d_first;
+  {
+    int64_t lo = 0, hi = (int64_t)a.ndocs - 1;
+    while (lo < hi) {
+      const int64_t step = (hi - lo + 64) / 64;
+      const int64_t d = lo + (int64_t)lane * step;
+      const bool pr = d <= hi && doc_off(a, d + 1) >= P0;
+      const uint64_t b = prim::ballot(pr);
+      const int64_t f = b ? (int64_t)__builtin_ctzll(b) : -1;
+      int64_t nprobe = (hi - lo) / step;  // last valid probe lane
+      if (nprobe > 63) nprobe = 63;
+      const int64_t nlo = f > 0 ? lo + (f - 1) * step + 1 : (f == 0 ? lo : lo + nprobe * step + 1);
+      hi = f >= 0 ? lo + f * step : hi;
+      lo = nlo;
+    }
+    d_first = lo;
+  }
+  S.d_first = d_first;
+  // Table of starts of documents d_first.. up to Pend, relative to P0
+  // (entry 0 clamped at -1).  Empty documents owned by this tile are
+  // finished here: the tile owning a position owns the empty documents there.
+  {
+    int32_t count = 0;
+    for (int64_t i0 = 0;; i0 += kThreads) {
+      const int64_t d = d_first + i0 + lane;
+      bool in = d <= (int64_t)a.ndocs;
+      const int64_t o = in ? doc_off(a, d) : 0;
+      in = in && o <= Pend;
+      if (in && i0 + lane < kDocCap + 1) {
+        const int64_t r = o - P0;
+        sh.tab[i0 + lane] = (int32_t)(r < -1 ? -1 : r);
+      }
+      if (in && d < (int64_t)a.ndocs) {
+        const int64_t o2 = doc_off(a, d + 1);
+        const bool owned = (o >= P0 && o < Pend) || (o == end && t == ntiles - 1);
+        if (o2 == o && owned) {
+          prim::st_out(a.out_n + d, 0u);
+          prim::st_out(a.out_err + d, JSIDX_ERR_EMPTY);
+        }
+      }
+      const int n_in = __builtin_popcountll(prim::ballot(in));
+      count += n_in;
+      if (n_in < kThreads) break;
+    }
+    if (lane == 0) {
+      sh.d_first = d_first;
+      sh.first_off = doc_off(a, d_first);
+      sh.ntab = count;
+      sh.overflow = count > kDocCap + 1;
+    }
+  }
+  prim::wave_sync();
+  prim::trace(t, 1);
+
+  // ---- escape state entering the tile -------------------------------------
+  // Only the backslash run ending right before the tile decides it (odd run:
+  // the tile's first byte is escaped), so it is read from the bytes before the
+  // tile instead of waiting for the look-back.  Usually the byte before is
+  // not a backslash; otherwise the wave measures the run, 1 KiB per step.
+  // Runs longer than kEscSteps KiB leave it to the look-back.
+  S.hd = doc_at(a, sh, P0, d_first, 0);
+  S.hd_ok = S.hd >= 0 && d_first + S.hd < (int64_t)a.ndocs;
+  S.hs = S.hd_ok ? doc_start(a, sh, P0, d_first, S.hd) : P0;  // head document start
+  const int64_t hs = S.hs;
+  S.e_T = 0; S.e_known = 1;
+  if (t > 0 && hs < P0) {
+    const uint32_t w0 = prim::load4(a.base + P0 - 4);  // granule [P0-16, P0) holds document bytes
+    if ((w0 >> 24) == 0x5Cu) {
+      S.e_known = 0;
+      for (int step = 0; step < kEscSteps; step++) {
+        const int64_t c = P0 - (int64_t)kThreads * 16 * step - 16 * ((int64_t)lane + 1);  // lane 0 nearest
+        uint32_t bs = 0;  // bit i: byte c+i is a backslash of the document
+        if (c + 16 > hs) {
+          const uint4 v = prim::load16(a.base + c);
+          const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+          for (int k = 0; k < 4; k++) {
+            const uint32_t x = wv[k] ^ 0x5C5C5C5Cu;  // zero bytes are backslashes
+            const uint32_t z = ~(((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x) & 0x80808080u;
+            bs |= ((z >> 7) & 1u) << (4 * k) | ((z >> 15) & 1u) << (4 * k + 1) |
+                  ((z >> 23) & 1u) << (4 * k + 2) | ((z >> 31) & 1u) << (4 * k + 3);
+          }
+          if (c < hs) bs &= ~0u << (uint32_t)(hs - c);
+        }
+        const uint32_t trail = (uint32_t)__builtin_clz(~(bs << 16));  // run at the top, 0..16
+        const uint64_t full = prim::ballot(trail >= 16u);
+        const uint64_t notfull = ~full;
+        if (notfull) {
+          const int f = __builtin_ctzll(notfull);
+          const uint32_t run = (uint32_t)f * 16u + prim::readlane(trail, f);
+          S.e_T = run & 1u;  // runs of whole steps are even
+          S.e_known = 1;
+          break;
+        }
+      }
+    }
+  }
+  S.simple = !sh.overflow && sh.ntab == 1 && sh.tab[0] < 0 && S.hd_ok && S.e_known;
+  prim::trace(t, 5);
+  return S;
+}
+
+// What a tile still owes after publishing: its look-back, its inclusive value
+// (unless already published) and its head region (wave-uniform).
+struct Pending {
+  bool valid;
+  TileSetup S;
+  uint32_t table, cnt0, cnt1, esens, elig0, reset_any, r0, head_rows, carry, tail_count;
+  bool inc_done;
+  uint32_t he_valid, he_R0, he_EA, he_u;
+};
+
+// The local pass of a tile, its descriptor, its block's fold if it is the
+// block's last to publish, and the positions that need nothing from earlier
+// tiles.  The head region's masks go to the tile's slot in the workspace.
+JSIDX_DEV Pending start_tile(const Args& a, Shared& sh, const TileSetup& S, int64_t begin, int64_t end,
+                             int64_t ntiles, uint32_t epoch) {
+  const uint32_t lane = prim::lane();
+  Workspace* ws = a.ws;
+  const int64_t t = S.t, P0 = S.P0;
+  uint2* hmask = head_masks(a, t);
+  TileFacts T;
+  if (S.simple) tile_local<true>(a, sh, hmask, P0, begin, end, S.d_first, S.hd, S.hs, S.e_T, true, 0u, T);
+  else tile_local<false>(a, sh, hmask, P0, begin, end, S.d_first, S.hd, S.hs, S.e_T, true, 0u, T);
+  prim::trace(t, 2);
+  Pending R;
+  R.valid = true;
+  R.S = S;
+  {
+    const uint32_t q0 = (T.carry >> 1) & 1u, p0 = (T.carry >> 2) & 1u, u0 = (T.carry >> 3) & 1u;
+    const uint32_t e_last = T.carry & 1u;
+    uint32_t table = T.reset_any | (u0 << 1);
+#pragma unroll
+    for (uint32_t e = 0; e < 2; e++) {
+      // with the incoming escape known, both entries are the tile's outcome
+      const uint32_t eo = (T.any_const || S.e_known) ? e_last : e;
+      const uint32_t flip = S.e_known ? 0u : (e & T.qsens);
+      const uint32_t qo = T.reset_any ? q0 : (q0 ^ flip);
+      const uint32_t po = p0 ^ (flip & (T.lead_pos == (uint32_t)kTileBytes - 1u ? 1u : 0u));
+      table |= (eo | (qo << 1) | (po << 2)) << (2 + 3 * e);
+    }
+    R.table = table;
+    if (T.reset_any) {
+      R.cnt0 = R.cnt1 = T.tail_count;
+    } else {
+      R.cnt0 = wave_sum(T.a0);
+      R.cnt1 = wave_sum(T.a1);
+    }
+  }
+  R.esens = S.e_known ? 0u : (T.qsens | ((T.lead_reset && T.lead_pos > 0) ? 1u : 0u));
+  R.elig0 = T.elig0; R.reset_any = T.reset_any; R.r0 = T.r0; R.head_rows = T.head_rows;
+  R.carry = T.carry; R.tail_count = T.tail_count;
+  // Publish.  After a document start nothing depends on earlier tiles, so a
+  // tile holding one publishes its inclusive value right away.
+  R.inc_done = T.reset_any != 0;
+  if (lane == 0) {
+    if (R.inc_done) {
+      const uint64_t inc = make_inc(T.carry, 1u, T.tail_count, epoch);
+      st_desc(ws, t, inc);
+      if (t % kBlockTiles == kBlockTiles - 1) prim::st_agent(block_desc(a) + 3 * (t / kBlockTiles) + 1, inc);
+    } else {
+      st_desc(ws, t, make_agg(R.table, R.cnt0, R.cnt1, T.elig0, R.esens, epoch));
+    }
+  }
+  {
+    // count the block's published tiles; the last one folds the block
+    const int64_t blk = t / kBlockTiles;
+    const int64_t nblk = (ntiles - blk * kBlockTiles) < kBlockTiles ? (ntiles - blk * kBlockTiles) : kBlockTiles;
+    prim::wait_mem();  // the descriptor is written before it is counted
+    uint32_t old = 0;
+    if (lane == 0) old = prim::add_agent32(block_count(a) + blk, 1u);
+    old = prim::readlane(old, 0);
+    if ((int64_t)old == nblk - 1) {
+      compose_block(a, blk, ntiles, epoch);
+      if (lane == 0) prim::st_agent32(block_count(a) + blk, 0u);  // ready for the next launch
+    }
+  }
+  prim::wave_sync();
+  // the head document's flags, if it ends inside the head region
+  R.he_valid = sh.he_valid; R.he_R0 = sh.he_R0; R.he_EA = sh.he_EA; R.he_u = sh.he_u;
+  // plain rows after a document start
+  uint32_t rows = T.tail_rows;
+  while (rows) {
+    const int r = __builtin_ctz(rows);
+    rows &= rows - 1u;
+    const int64_t doff = sh.tr_doff[r];
+    uint32_t cc = sh.tr_cc[r];
+    const int64_t pos = P0 + (int64_t)r * kRowBytes + (int64_t)lane * kSegBytes;
+    write_row(a.out_idx + doff, (uint64_t)(end - doff), &cc, sh.hF[r][lane], (uint32_t)(pos - doff));
+  }
+  prim::wave_sync();
+  return R;
+}
+
+// The look-back of a published tile, the rare exact second pass (when the
+// escape carried in turns out to change the tile's head), its inclusive
+// value, and its head region's positions and head document's result.
+JSIDX_DEV void finish_tile(const Args& a, Shared& sh, const Pending& R, int64_t pos_g0, int64_t begin, int64_t end,
+                           int64_t ntiles, uint32_t epoch) {
+  const uint32_t lane = prim::lane();
+  Workspace* ws = a.ws;
+  const TileSetup& S = R.S;
+  const int64_t t = S.t, P0 = S.P0;
+  const bool hvalid = S.hd_ok && R.r0 > 0;
+  if (R.inc_done && !hvalid) {  // no head region: nothing needs the look-back
+    prim::trace(t, 3);
+    prim::trace(t, 4);
+    prim::trace(t, 7);
+    return;
+  }
+  uint32_t s_in = 0, base = 0;
+  look_back(a, t, epoch, &s_in, &base);
+  prim::trace(t, 3);
+  if ((s_in & 1u) && R.esens) {
+    // exact second pass with the incoming state now known; it writes every
+    // position of the tile itself
+    prim::trace_count(t, 9);
+    const TileSetup S2 = begin_tile(a, sh, t, pos_g0, end, ntiles);
+    TileFacts T;
+    tile_local<false>(a, sh, head_masks(a, t), P0, begin, end, S2.d_first, S2.hd, S2.hs, s_in, false, base, T);
+    if (lane == 0 && !R.inc_done) {
+      const uint64_t inc = make_inc(T.carry, T.reset_any, T.tail_count, epoch);
+      st_desc(ws, t, inc);
+      if (t % kBlockTiles == kBlockTiles - 1) prim::st_agent(block_desc(a) + 3 * (t / kBlockTiles) + 1, inc);
+    }
+    prim::wave_sync();
+    prim::trace(t, 4);
+    prim::trace(t, 7);
+    return;
+  }
+  if (lane == 0 && !R.inc_done) {
+    const uint32_t q = (s_in >> 1) & 1u, p = (s_in >> 2) & 1u;
+    const uint32_t cnt = R.reset_any ? R.cnt0 : base + (q ? R.cnt1 : R.cnt0 + (p & R.elig0));
+    const uint64_t inc = make_inc(tab_apply(R.table, s_in), R.reset_any, cnt, epoch);
+    st_desc(ws, t, inc);
+    if (t % kBlockTiles == kBlockTiles - 1) prim::st_agent(block_desc(a) + 3 * (t / kBlockTiles) + 1, inc);
+  }
+  prim::trace(t, 4);
+
+  // ---- head region: positions and the head document's result ---------------
+  if (hvalid) {
+    const uint32_t qT = (s_in >> 1) & 1u;
+    const uint32_t pfix = (((s_in >> 2) & 1u) && R.elig0 && !qT) ? 1u : 0u;
+    const uint32_t uT = (s_in >> 3) & 1u;
+    uint32_t* out = a.out_idx + S.hs;
+    // ranks of the head document stay below end - hs unless a look-back
+    // wait gave up; rows that could pass it check every write
+    const uint64_t lim = (uint64_t)(end - S.hs);
+    const uint32_t rel0 = (uint32_t)(P0 - S.hs) + lane * (uint32_t)kSegBytes;
+    const uint2* hmask = head_masks(a, t);
+    uint32_t cc = base;
+#pragma unroll 1
+    for (uint32_t r = 0; r < R.head_rows; r++) {
+      const uint2 kf = prim::ld_pair(hmask + r * kThreads + lane);
+      uint32_t F = qT ? (kf.y ^ kf.x) : kf.y;
+      if (r == 0 && lane == 0) F |= pfix;
+      write_row(out, lim, &cc, F, rel0 + r * (uint32_t)kRowBytes);
+    }
+    if (R.he_valid && lane == 0) {
+      uint32_t err = 0;
+      if (R.he_u | uT) err |= JSIDX_ERR_UTF8;
+      if (R.he_R0 ^ qT) err |= JSIDX_ERR_UNCLOSED_STRING;
+      if (R.he_EA) err |= JSIDX_ERR_TRAILING_ESCAPE;
+      if (cc == 0) err |= JSIDX_ERR_EMPTY;
+      prim::st_out(a.out_n + S.d_first + S.hd, cc);
+      prim::st_out(a.out_err + S.d_first + S.hd, err);
+    }
+  }
+  prim::trace(t, 7);
+}
+
+// ---------------------------------------------------------------------------
 JSIDX_DEVFN void index_tiles(const Args& a) {
   GroupShared& gs = prim::lds_object<GroupShared>();
   const uint32_t wv = prim::wave_id();
@@ -985,265 +1279,35 @@ JSIDX_DEVFN void index_tiles(const Args& a) {
       prim::st_out(a.out_n + d, 0u);
       prim::st_out(a.out_err + d, JSIDX_ERR_CAPACITY);
     }
-    goto finish;
+  } else {
+    // A workgroup takes its first kWaves tiles with one atomic (a launch
+    // starts thousands of waves at once; one counter would serialise them),
+    // then each wave takes tiles one at a time.  Tiles are only ever handed
+    // to running waves, in increasing order.  A wave finishes a tile (its
+    // look-back and head region) after the local pass of its next tile, so
+    // that the look-back rarely waits; every tile publishes before its wave
+    // waits for anything.
+    if (wv == 0 && lane == 0) gs.first = prim::add_agent32(&ws->ticket, (uint32_t)kWaves);
+    prim::sync();
+    Pending pend;
+    pend.valid = false;
+    for (uint32_t tk = gs.first + wv, first = 1;; first = 0) {
+      if (!first) {
+        uint32_t v = 0;
+        if (lane == 0) v = prim::add_agent32(&ws->ticket, 1u);
+        tk = prim::readlane(v, 0);
+      }
+      const int64_t t = (int64_t)tk;
+      if (t >= ntiles) break;
+      prim::trace(t, 0);
+      const TileSetup S = begin_tile(a, sh, t, pos_g0, end, ntiles);
+      const Pending cur = start_tile(a, sh, S, begin, end, ntiles, epoch);
+      if (pend.valid) finish_tile(a, sh, pend, pos_g0, begin, end, ntiles, epoch);
+      pend = cur;
+    }
+    if (pend.valid) finish_tile(a, sh, pend, pos_g0, begin, end, ntiles, epoch);
   }
 
-  // A workgroup takes its first kWaves tiles with one atomic (a launch starts
-  // thousands of waves at once; one counter would serialise them), then each
-  // wave takes tiles one at a time.  Tiles are only ever handed to running
-  // waves, in increasing order.
-  if (wv == 0 && lane == 0) gs.first = prim::add_agent32(&ws->ticket, (uint32_t)kWaves);
-  prim::sync();
-  for (uint32_t tk = gs.first + wv, first = 1;; first = 0) {
-    if (!first) {
-      uint32_t v = 0;
-      if (lane == 0) v = prim::add_agent32(&ws->ticket, 1u);
-      tk = prim::readlane(v, 0);
-    }
-    const int64_t t = (int64_t)tk;
-    if (t >= ntiles) break;
-    prim::trace(t, 0);
-    const int64_t P0 = pos_g0 + t * kTileBytes;  // position of tile byte 0
-    const int64_t Pend = P0 + kTileBytes;
-
-    // ---- documents of this tile ---------------------------------------------
-    // d_first: the first document whose end is at or after the tile start.
-    int64_t d_first;
-    {
-      int64_t lo = 0, hi = (int64_t)a.ndocs - 1;
-      while (lo < hi) {
-        const int64_t step = (hi - lo + 64) / 64;
-        const int64_t d = lo + (int64_t)lane * step;
-        const bool pr = d <= hi && doc_off(a, d + 1) >= P0;
-        const uint64_t b = prim::ballot(pr);
-        const int64_t f = b ? (int64_t)__builtin_ctzll(b) : -1;
-        int64_t nprobe = (hi - lo) / step;  // last valid probe lane
-        if (nprobe > 63) nprobe = 63;
-        const int64_t nlo = f > 0 ? lo + (f - 1) * step + 1 : (f == 0 ? lo : lo + nprobe * step + 1);
-        hi = f >= 0 ? lo + f * step : hi;
-        lo = nlo;
-      }
-      d_first = lo;
-    }
-    // Table of starts of documents d_first.. up to Pend, relative to P0
-    // (entry 0 clamped at -1).  Empty documents owned by this tile are
-    // finished here: the tile owning a position owns the empty documents there.
-    {
-      int32_t count = 0;
-      for (int64_t i0 = 0;; i0 += kThreads) {
-        const int64_t d = d_first + i0 + lane;
-        bool in = d <= (int64_t)a.ndocs;
-        const int64_t o = in ? doc_off(a, d) : 0;
-        in = in && o <= Pend;
-        if (in && i0 + lane < kDocCap + 1) {
-          const int64_t r = o - P0;
-          sh.tab[i0 + lane] = (int32_t)(r < -1 ? -1 : r);
-        }
-        if (in && d < (int64_t)a.ndocs) {
-          const int64_t o2 = doc_off(a, d + 1);
-          const bool owned = (o >= P0 && o < Pend) || (o == end && t == ntiles - 1);
-          if (o2 == o && owned) {
-            prim::st_out(a.out_n + d, 0u);
-            prim::st_out(a.out_err + d, JSIDX_ERR_EMPTY);
-          }
-        }
-        const int n_in = __builtin_popcountll(prim::ballot(in));
-        count += n_in;
-        if (n_in < kThreads) break;
-      }
-      if (lane == 0) {
-        sh.d_first = d_first;
-        sh.first_off = doc_off(a, d_first);
-        sh.ntab = count;
-        sh.overflow = count > kDocCap + 1;
-      }
-    }
-    prim::wave_sync();
-    prim::trace(t, 1);
-
-    // ---- local pass, look-back, and (rarely) an exact second local pass ------
-    // ---- escape state entering the tile -------------------------------------
-    // Only the backslash run ending right before the tile decides it (odd run:
-    // the tile's first byte is escaped), so it is read from the bytes before the
-    // tile instead of waiting for the look-back.  Usually the byte before is
-    // not a backslash; otherwise the wave measures the run, 1 KiB per step.
-    // Runs longer than kEscSteps KiB leave it to the look-back.
-    const int32_t hd = doc_at(a, sh, P0, d_first, 0);
-    const bool hd_ok = hd >= 0 && d_first + hd < (int64_t)a.ndocs;
-    const int64_t hs = hd_ok ? doc_start(a, sh, P0, d_first, hd) : P0;  // head document start
-    uint32_t e_T = 0, e_known = 1;
-    if (t > 0 && hs < P0) {
-      const uint32_t w0 = prim::load4(a.base + P0 - 4);  // granule [P0-16, P0) holds document bytes
-      if ((w0 >> 24) == 0x5Cu) {
-        e_known = 0;
-        for (int step = 0; step < kEscSteps; step++) {
-          const int64_t c = P0 - (int64_t)kThreads * 16 * step - 16 * ((int64_t)lane + 1);  // lane 0 nearest
-          uint32_t bs = 0;  // bit i: byte c+i is a backslash of the document
-          if (c + 16 > hs) {
-            const uint4 v = prim::load16(a.base + c);
-            const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-            for (int k = 0; k < 4; k++) {
-              const uint32_t x = wv[k] ^ 0x5C5C5C5Cu;  // zero bytes are backslashes
-              const uint32_t z = ~(((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x) & 0x80808080u;
-              bs |= ((z >> 7) & 1u) << (4 * k) | ((z >> 15) & 1u) << (4 * k + 1) |
-                    ((z >> 23) & 1u) << (4 * k + 2) | ((z >> 31) & 1u) << (4 * k + 3);
-            }
-            if (c < hs) bs &= ~0u << (uint32_t)(hs - c);
-          }
-          const uint32_t trail = (uint32_t)__builtin_clz(~(bs << 16));  // run at the top, 0..16
-          const uint64_t full = prim::ballot(trail >= 16u);
-          const uint64_t notfull = ~full;
-          if (notfull) {
-            const int f = __builtin_ctzll(notfull);
-            const uint32_t run = (uint32_t)f * 16u + prim::readlane(trail, f);
-            e_T = run & 1u;  // runs of whole steps are even
-            e_known = 1;
-            break;
-          }
-        }
-      }
-    }
-    prim::trace(t, 5);
-
-    TileFacts T;
-    uint32_t s_in = 0, base = 0;
-    bool exact = false;  // set by the rare exact second pass
-    const bool simple = !sh.overflow && sh.ntab == 1 && sh.tab[0] < 0 && hd_ok && e_known && !exact;
-    uint32_t table = 0, cnt0 = 0, cnt1 = 0, esens = 0;
-    bool inc_done = false;
-    // pass 0: the local pass with the escape state read before the tile;
-    // pass 1 (rare): an exact local pass, when the escape carried in turned
-    // out to change this tile's head
-    for (int pass = 0;; pass++) {
-      if (pass == 0 && simple) tile_local<true>(a, sh, P0, begin, end, d_first, hd, hs, e_T, true, 0u, T);
-      else tile_local<false>(a, sh, P0, begin, end, d_first, hd, hs, pass ? s_in : e_T, pass ? false : !exact,
-                             pass ? base : 0u, T);
-      if (pass == 1) {
-        exact = true;
-        break;
-      }
-      prim::trace(t, 2);
-      {
-        const uint32_t q0 = (T.carry >> 1) & 1u, p0 = (T.carry >> 2) & 1u, u0 = (T.carry >> 3) & 1u;
-        const uint32_t e_last = T.carry & 1u;
-        table = T.reset_any | (u0 << 1);
-#pragma unroll
-        for (uint32_t e = 0; e < 2; e++) {
-          // with the incoming escape known, both entries are the tile's outcome
-          const uint32_t eo = (T.any_const || e_known) ? e_last : e;
-          const uint32_t flip = e_known ? 0u : (e & T.qsens);
-          const uint32_t qo = T.reset_any ? q0 : (q0 ^ flip);
-          const uint32_t po = p0 ^ (flip & (T.lead_pos == (uint32_t)kTileBytes - 1u ? 1u : 0u));
-          table |= (eo | (qo << 1) | (po << 2)) << (2 + 3 * e);
-        }
-        if (T.reset_any) {
-          cnt0 = cnt1 = T.tail_count;
-        } else if (!exact) {
-          cnt0 = wave_sum(T.a0);
-          cnt1 = wave_sum(T.a1);
-        }
-      }
-      esens = e_known ? 0u : (T.qsens | ((T.lead_reset && T.lead_pos > 0) ? 1u : 0u));
-      // Publish.  After a document start nothing depends on earlier tiles, so
-      // a tile holding one publishes its inclusive value right away.
-      inc_done = T.reset_any != 0;
-      if (lane == 0) {
-        if (inc_done) {
-          const uint64_t inc = make_inc(T.carry, 1u, T.tail_count, epoch);
-          st_desc(ws, t, inc);
-          if (t % kBlockTiles == kBlockTiles - 1) prim::st_agent(block_desc(a) + 3 * (t / kBlockTiles) + 1, inc);
-        } else {
-          st_desc(ws, t, make_agg(table, cnt0, cnt1, T.elig0, esens, epoch));
-        }
-      }
-      {
-        // count the block's published tiles; the last one folds the block
-        const int64_t blk = t / kBlockTiles;
-        const int64_t nblk = (ntiles - blk * kBlockTiles) < kBlockTiles ? (ntiles - blk * kBlockTiles) : kBlockTiles;
-        prim::wait_mem();  // the descriptor is written before it is counted
-        uint32_t old = 0;
-        if (lane == 0) old = prim::add_agent32(block_count(a) + blk, 1u);
-        old = prim::readlane(old, 0);
-        if ((int64_t)old == nblk - 1) {
-          compose_block(a, blk, ntiles, epoch);
-          if (lane == 0) prim::st_agent32(block_count(a) + blk, 0u);  // ready for the next launch
-        }
-      }
-      // plain rows after a document start
-      if (T.tail_rows) {
-        prim::wave_sync();
-        uint32_t rows = T.tail_rows;
-        while (rows) {
-          const int r = __builtin_ctz(rows);
-          rows &= rows - 1u;
-          const int64_t doff = sh.tr_doff[r];
-          uint32_t cc = sh.tr_cc[r];
-          const int64_t pos = P0 + (int64_t)r * kRowBytes + (int64_t)lane * kSegBytes;
-          write_row(a.out_idx + doff, (uint64_t)(end - doff), &cc, sh.hF[r][lane], (uint32_t)(pos - doff));
-        }
-      }
-      if (inc_done && !(hd_ok && T.r0 > 0)) {  // no head region: nothing needs the look-back
-        prim::trace(t, 3);
-        break;
-      }
-      look_back(a, t, epoch, &s_in, &base);
-      prim::trace(t, 3);
-      if (!((s_in & 1u) && esens)) break;
-      prim::trace_count(t, 9);
-    }
-
-    // ---- own inclusive value -------------------------------------------------
-    uint32_t st_out, inc_count;
-    if (exact) {
-      st_out = T.carry;
-      inc_count = T.tail_count;  // exact pass: the open document's full count
-    } else {
-      st_out = tab_apply(table, s_in);
-      const uint32_t q = (s_in >> 1) & 1u, p = (s_in >> 2) & 1u;
-      inc_count = T.reset_any ? cnt0 : base + (q ? cnt1 : cnt0 + (p & T.elig0));
-    }
-    if (lane == 0 && !inc_done) {
-      const uint64_t inc = make_inc(st_out, T.reset_any, inc_count, epoch);
-      st_desc(ws, t, inc);
-      if (t % kBlockTiles == kBlockTiles - 1) prim::st_agent(block_desc(a) + 3 * (t / kBlockTiles) + 1, inc);
-    }
-    prim::trace(t, 4);
-
-    // ---- head region: positions and the head document's result ---------------
-    const bool hvalid = hd_ok && T.r0 > 0;
-    if (!exact && hvalid) {
-      const uint32_t qT = (s_in >> 1) & 1u;
-      const uint32_t pfix = (((s_in >> 2) & 1u) && T.elig0 && !qT) ? 1u : 0u;
-      const uint32_t uT = (s_in >> 3) & 1u;
-      uint32_t* out = a.out_idx + hs;
-      // ranks of the head document stay below end - hs unless a look-back
-      // wait gave up; rows that could pass it check every write
-      const uint64_t lim = (uint64_t)(end - hs);
-      const uint32_t rel0 = (uint32_t)(P0 - hs) + lane * (uint32_t)kSegBytes;
-      uint32_t cc = base;
-#pragma unroll 1
-      for (uint32_t r = 0; r < T.head_rows; r++) {
-        const uint32_t hK = sh.hK[r][lane], hF = sh.hF[r][lane];
-        uint32_t F = qT ? (hF ^ hK) : hF;
-        if (r == 0 && lane == 0) F |= pfix;
-        write_row(out, lim, &cc, F, rel0 + r * (uint32_t)kRowBytes);
-      }
-      if (sh.he_valid && lane == 0) {
-        uint32_t err = 0;
-        if (sh.he_u | uT) err |= JSIDX_ERR_UTF8;
-        if (sh.he_R0 ^ qT) err |= JSIDX_ERR_UNCLOSED_STRING;
-        if (sh.he_EA) err |= JSIDX_ERR_TRAILING_ESCAPE;
-        if (cc == 0) err |= JSIDX_ERR_EMPTY;
-        prim::st_out(a.out_n + d_first + hd, cc);
-        prim::st_out(a.out_err + d_first + hd, err);
-      }
-    }
-    prim::wave_sync();
-    prim::trace(t, 7);
-  }
-
-finish:
   // The last workgroup out resets the counters for the next launch and clears
   // a rotating window of descriptors so that no stale descriptor can ever
   // carry a matching epoch.

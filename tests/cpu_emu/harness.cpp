@@ -34,6 +34,8 @@ long emu_run(const uint8_t* base, const uint64_t* offsets, uint64_t len, uint32_
   env.writes[env.nwrites++] = {out_idx, out_idx + out_cap};
   env.writes[env.nwrites++] = {out_n, out_n + ndocs};
   env.writes[env.nwrites++] = {out_err, out_err + ndocs};
+  env.writes[env.nwrites++] = {ws_mem, (const uint8_t*)ws_mem + workspace_bytes(cap_tiles)};
+  env.reads[env.nreads++] = {ws_mem, (const uint8_t*)ws_mem + workspace_bytes(cap_tiles)};
 
   Args a;
   a.base = base;

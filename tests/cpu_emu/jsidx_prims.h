@@ -26,6 +26,9 @@
 struct uint4 {
   uint32_t x, y, z, w;
 };
+struct uint2 {
+  uint32_t x, y;
+};
 
 namespace jsidx {
 namespace prim {
@@ -70,9 +73,9 @@ struct Range {
 };
 
 struct EmuEnv {
-  Range reads[4];
+  Range reads[8];
   int nreads = 0;
-  Range writes[4];
+  Range writes[8];
   int nwrites = 0;
   std::atomic<long> violations{0};
 };
@@ -239,6 +242,15 @@ inline uint64_t load8(const uint64_t* p) {
 inline void st_out(uint32_t* p, uint32_t v) {
   check(p, 4, true);
   *p = v;
+}
+inline uint2 ld_pair(const uint2* p) {
+  check(p, 8, false);
+  return *p;
+}
+inline void st_pair(uint2* p, uint32_t x, uint32_t y) {
+  check(p, 8, true);
+  p->x = x;
+  p->y = y;
 }
 
 }  // namespace prim

@@ -24,7 +24,12 @@
 namespace jsidx {
 
 constexpr int kThreads = 64;  // lanes per wave; a wave owns one tile at a time
-constexpr int kWaves = 8;     // waves per workgroup (they share only their first tickets)
+// Waves per workgroup (they share only their first tickets); tuning builds
+// may override.
+#ifndef JSIDX_GROUP_WAVES
+#define JSIDX_GROUP_WAVES 8
+#endif
+constexpr int kWaves = JSIDX_GROUP_WAVES;
 constexpr int kGroupThreads = kWaves * kThreads;
 constexpr int kSegBytes = 32;
 constexpr int kRowBytes = kThreads * kSegBytes;  // 2 KiB
@@ -305,9 +310,9 @@ JSIDX_DEV void write_row(uint32_t* out, uint64_t lim, uint32_t* cc, uint32_t F, 
 // lies inside the input (every byte belongs to document hd, which starts at
 // hs < P0), the escape state entering the tile is known, and defer is set.
 template <bool SIMPLE>
-JSIDX_DEV void tile_local(const Args& a, Shared& sh, uint2* hmask, int64_t P0, int64_t begin, int64_t end,
-                          int64_t d_first, int32_t hd, int64_t hs, uint32_t st_in, bool defer, uint32_t head_base,
-                          TileFacts& T) {
+JSIDX_DEV void tile_local(const Args& a, Shared& sh, uint2* hmask, const uint32_t* first_row, int64_t P0,
+                          int64_t begin, int64_t end, int64_t d_first, int32_t hd, int64_t hs, uint32_t st_in,
+                          bool defer, uint32_t head_base, TileFacts& T) {
   const uint32_t lane = prim::lane();
   uint32_t ce = st_in & 1u, cq = (st_in >> 1) & 1u, cp = (st_in >> 2) & 1u, cu = (st_in >> 3) & 1u;
   uint32_t cc = head_base;  // count of the open document before this row
@@ -328,7 +333,12 @@ JSIDX_DEV void tile_local(const Args& a, Shared& sh, uint2* hmask, int64_t P0, i
   }
 
   uint32_t wn[8];
-  load_segment<SIMPLE>(a, P0 + (int64_t)lane * kSegBytes, begin, end, wn);
+  if (first_row) {
+#pragma unroll
+    for (int k = 0; k < 8; k++) wn[k] = first_row[k];
+  } else {
+    load_segment<SIMPLE>(a, P0 + (int64_t)lane * kSegBytes, begin, end, wn);
+  }
 #pragma unroll 1
   for (int r = 0; r < kRows; r++) {
     const int32_t rel = r * kRowBytes + (int32_t)lane * kSegBytes;  // tile-relative
@@ -972,14 +982,18 @@ struct TileSetup {
   int32_t hd;
   bool hd_ok, simple;
   uint32_t e_T, e_known;
+  uint32_t w0[8];  // this lane's segment of row 0, loaded first
 };
 
-JSIDX_DEV TileSetup begin_tile(const Args& a, Shared& sh, int64_t t, int64_t pos_g0, int64_t end, int64_t ntiles) {
+JSIDX_DEV TileSetup begin_tile(const Args& a, Shared& sh, int64_t t, int64_t pos_g0, int64_t begin, int64_t end,
+                               int64_t ntiles) {
   const uint32_t lane = prim::lane();
   TileSetup S;
   S.t = t;
   S.P0 = pos_g0 + t * kTileBytes;  // position of tile byte 0
   const int64_t P0 = S.P0, Pend = P0 + kTileBytes;
+  // the first row's loads go out before anything else of the tile
+  load_segment<false>(a, P0 + (int64_t)lane * kSegBytes, begin, end, S.w0);
   // d_first: the first document whose end is at or after the tile start.
   int64_t d_first;
   {
@@ -1103,8 +1117,8 @@ JSIDX_DEV Pending start_tile(const Args& a, Shared& sh, const TileSetup& S, int6
   const int64_t t = S.t, P0 = S.P0;
   uint2* hmask = head_masks(a, t);
   TileFacts T;
-  if (S.simple) tile_local<true>(a, sh, hmask, P0, begin, end, S.d_first, S.hd, S.hs, S.e_T, true, 0u, T);
-  else tile_local<false>(a, sh, hmask, P0, begin, end, S.d_first, S.hd, S.hs, S.e_T, true, 0u, T);
+  if (S.simple) tile_local<true>(a, sh, hmask, S.w0, P0, begin, end, S.d_first, S.hd, S.hs, S.e_T, true, 0u, T);
+  else tile_local<false>(a, sh, hmask, S.w0, P0, begin, end, S.d_first, S.hd, S.hs, S.e_T, true, 0u, T);
   prim::trace(t, 2);
   Pending R;
   R.valid = true;
@@ -1198,9 +1212,10 @@ JSIDX_DEV void finish_tile(const Args& a, Shared& sh, const Pending& R, int64_t 
     // exact second pass with the incoming state now known; it writes every
     // position of the tile itself
     prim::trace_count(t, 9);
-    const TileSetup S2 = begin_tile(a, sh, t, pos_g0, end, ntiles);
+    const TileSetup S2 = begin_tile(a, sh, t, pos_g0, begin, end, ntiles);
     TileFacts T;
-    tile_local<false>(a, sh, head_masks(a, t), P0, begin, end, S2.d_first, S2.hd, S2.hs, s_in, false, base, T);
+    tile_local<false>(a, sh, head_masks(a, t), S2.w0, P0, begin, end, S2.d_first, S2.hd, S2.hs, s_in, false, base,
+                      T);
     if (lane == 0 && !R.inc_done) {
       const uint64_t inc = make_inc(T.carry, T.reset_any, T.tail_count, epoch);
       st_desc(ws, t, inc);
@@ -1230,15 +1245,27 @@ JSIDX_DEV void finish_tile(const Args& a, Shared& sh, const Pending& R, int64_t 
     // wait gave up; rows that could pass it check every write
     const uint64_t lim = (uint64_t)(end - S.hs);
     const uint32_t rel0 = (uint32_t)(P0 - S.hs) + lane * (uint32_t)kSegBytes;
+    // All rows' masks are loaded at once (one round trip); their indexed bits
+    // go to the wave's LDS rows (free now: the tail rows of the tile started
+    // since were written right after it published), so that the writes below
+    // never wait on a load.
     const uint2* hmask = head_masks(a, t);
+    uint32_t Fr[kRows];
+#pragma unroll
+    for (int r = 0; r < kRows; r++) {
+      uint2 kf;
+      kf.x = 0u; kf.y = 0u;
+      if ((uint32_t)r < R.head_rows) kf = prim::ld_pair(hmask + r * kThreads + lane);
+      Fr[r] = qT ? (kf.y ^ kf.x) : kf.y;
+    }
+    if (lane == 0) Fr[0] |= pfix;
+#pragma unroll
+    for (int r = 0; r < kRows; r++) sh.hF[r][lane] = Fr[r];
+    prim::wave_sync();
     uint32_t cc = base;
 #pragma unroll 1
-    for (uint32_t r = 0; r < R.head_rows; r++) {
-      const uint2 kf = prim::ld_pair(hmask + r * kThreads + lane);
-      uint32_t F = qT ? (kf.y ^ kf.x) : kf.y;
-      if (r == 0 && lane == 0) F |= pfix;
-      write_row(out, lim, &cc, F, rel0 + r * (uint32_t)kRowBytes);
-    }
+    for (uint32_t r = 0; r < R.head_rows; r++)
+      write_row(out, lim, &cc, sh.hF[r][lane], rel0 + r * (uint32_t)kRowBytes);
     if (R.he_valid && lane == 0) {
       uint32_t err = 0;
       if (R.he_u | uT) err |= JSIDX_ERR_UTF8;
@@ -1291,19 +1318,18 @@ JSIDX_DEVFN void index_tiles(const Args& a) {
     prim::sync();
     Pending pend;
     pend.valid = false;
-    for (uint32_t tk = gs.first + wv, first = 1;; first = 0) {
-      if (!first) {
-        uint32_t v = 0;
-        if (lane == 0) v = prim::add_agent32(&ws->ticket, 1u);
-        tk = prim::readlane(v, 0);
-      }
+    for (uint32_t tk = gs.first + wv;;) {
       const int64_t t = (int64_t)tk;
       if (t >= ntiles) break;
+      // the next ticket is taken now and used after this tile
+      uint32_t nv = 0;
+      if (lane == 0) nv = prim::add_agent32(&ws->ticket, 1u);
       prim::trace(t, 0);
-      const TileSetup S = begin_tile(a, sh, t, pos_g0, end, ntiles);
+      const TileSetup S = begin_tile(a, sh, t, pos_g0, begin, end, ntiles);
       const Pending cur = start_tile(a, sh, S, begin, end, ntiles, epoch);
       if (pend.valid) finish_tile(a, sh, pend, pos_g0, begin, end, ntiles, epoch);
       pend = cur;
+      tk = prim::readlane(nv, 0);
     }
     if (pend.valid) finish_tile(a, sh, pend, pos_g0, begin, end, ntiles, epoch);
   }

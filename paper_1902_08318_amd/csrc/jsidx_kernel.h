@@ -255,18 +255,24 @@ JSIDX_DEV uint32_t row_ranks(uint32_t cv, uint64_t Rs, uint32_t* cc) {
   return cin;
 }
 
+// This lane's 32 bytes at pos.  Only granules overlapping [begin, end) may be
+// read: a granule outside is read from the granule holding byte `begin`
+// instead, and its bytes are masked out by the caller's valid-byte mask.  The
+// loads are unconditional, so no register write races a load in flight.
 template <bool INTERIOR>
 JSIDX_DEV void load_segment(const Args& a, int64_t pos, int64_t begin, int64_t end, uint32_t w[8]) {
-  const uint8_t* p = a.base + pos;  // 16-byte aligned
+  if (!INTERIOR && begin >= end) {  // empty input: nothing may be read
+#pragma unroll
+    for (int k = 0; k < 8; k++) w[k] = 0u;
+    return;
+  }
+  const uint8_t* safe = reinterpret_cast<const uint8_t*>((reinterpret_cast<uintptr_t>(a.base) + (uintptr_t)begin) & ~(uintptr_t)15);
 #pragma unroll
   for (int h = 0; h < 2; h++) {
-    // only granules overlapping [begin, end) are read
-    if (INTERIOR || (begin < end && pos + 16 * h < end && pos + 16 * h + 16 > begin)) {
-      uint4 v = prim::load16(p + 16 * h);
-      w[4 * h + 0] = v.x; w[4 * h + 1] = v.y; w[4 * h + 2] = v.z; w[4 * h + 3] = v.w;
-    } else {
-      w[4 * h + 0] = w[4 * h + 1] = w[4 * h + 2] = w[4 * h + 3] = 0u;
-    }
+    const int64_t g = pos + 16 * h;  // 16-byte aligned
+    const bool ok = INTERIOR || (g < end && g + 16 > begin);
+    const uint4 v = prim::load16(ok ? a.base + g : safe);
+    w[4 * h + 0] = v.x; w[4 * h + 1] = v.y; w[4 * h + 2] = v.z; w[4 * h + 3] = v.w;
   }
 }
 

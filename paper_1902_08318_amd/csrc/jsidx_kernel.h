@@ -31,6 +31,7 @@ constexpr int kThreads = 64;  // lanes per wave; a wave owns one tile at a time
 #endif
 constexpr int kWaves = JSIDX_GROUP_WAVES;
 constexpr int kGroupThreads = kWaves * kThreads;
+constexpr int kTicketTiles = 2;  // consecutive tiles per ticket (when every wave gets at least 2 tiles)
 constexpr int kSegBytes = 32;
 constexpr int kRowBytes = kThreads * kSegBytes;  // 2 KiB
 // Rows per tile (test and tuning builds may override).
@@ -1313,29 +1314,34 @@ JSIDX_DEVFN void index_tiles(const Args& a) {
       prim::st_out(a.out_err + d, JSIDX_ERR_CAPACITY);
     }
   } else {
-    // A workgroup takes its first kWaves tiles with one atomic (a launch
-    // starts thousands of waves at once; one counter would serialise them),
-    // then each wave takes tiles one at a time.  Tiles are only ever handed
-    // to running waves, in increasing order.  A wave finishes a tile (its
-    // look-back and head region) after the local pass of its next tile, so
-    // that the look-back rarely waits; every tile publishes before its wave
-    // waits for anything.
-    if (wv == 0 && lane == 0) gs.first = prim::add_agent32(&ws->ticket, (uint32_t)kWaves);
+    // A ticket is tt consecutive tiles.  A workgroup takes its
+    // waves' first tickets with one atomic (a launch starts thousands of
+    // waves at once, and waves finishing together would otherwise queue on
+    // one counter), then each wave takes tickets one at a time.  Tiles are
+    // only ever handed to running waves, in increasing order.  A wave
+    // finishes a tile (its look-back and head region) after the local pass
+    // of its next tile, so that the look-back rarely waits; every tile
+    // publishes before its wave waits for anything.
+    const uint32_t tt = ntiles >= (int64_t)kTicketTiles * prim::grid() * kWaves ? (uint32_t)kTicketTiles : 1u;
+    if (wv == 0 && lane == 0) gs.first = prim::add_agent32(&ws->ticket, (uint32_t)kWaves * tt);
     prim::sync();
     Pending pend;
     pend.valid = false;
-    for (uint32_t tk = gs.first + wv;;) {
+    for (uint32_t tk = gs.first + wv * tt, left = tt;;) {
       const int64_t t = (int64_t)tk;
       if (t >= ntiles) break;
-      // the next ticket is taken now and used after this tile
-      uint32_t nv = 0;
-      if (lane == 0) nv = prim::add_agent32(&ws->ticket, 1u);
       prim::trace(t, 0);
       const TileSetup S = begin_tile(a, sh, t, pos_g0, begin, end, ntiles);
       const Pending cur = start_tile(a, sh, S, begin, end, ntiles, epoch);
       if (pend.valid) finish_tile(a, sh, pend, pos_g0, begin, end, ntiles, epoch);
       pend = cur;
-      tk = prim::readlane(nv, 0);
+      tk++;
+      if (--left == 0) {
+        uint32_t nv = 0;
+        if (lane == 0) nv = prim::add_agent32(&ws->ticket, tt);
+        tk = prim::readlane(nv, 0);
+        left = tt;
+      }
     }
     if (pend.valid) finish_tile(a, sh, pend, pos_g0, begin, end, ntiles, epoch);
   }

@@ -85,3 +85,12 @@ def test_many_lookback_blocks(block_tiles):
     rng = np.random.default_rng(block_tiles)
     docs = [synth.gen_c0(int(rng.integers(0, 1000)), 5000).data[:int(rng.integers(0, 5000))] for _ in range(300)]
     _check_batch(docs, 48, 1, 5, block_tiles)
+
+
+def test_two_tile_tickets():
+    """With at least two tiles per wave, a ticket hands out two consecutive
+    tiles (and a wave finishes one tile after starting the next)."""
+    from paper_1902_08318_amd import synth
+    d = synth.gen_c1(7, 2 << 20, pool=64).data
+    for nb in (8, 16):
+        _check_single(d, nb, 5)

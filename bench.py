@@ -62,6 +62,9 @@ def log(msg):
 
 
 def time_single(jx, torch, host: bytes, steps: int, warmup: int, copies: int = 3):
+    """Time `steps` launches over rotating copies of one document: an event
+    before every launch and after the last gives the per-launch durations
+    (kernel time on the launch stream) and their sum the timed region."""
     dev = torch.device("cuda:0")
     n = len(host)
     src = torch.frombuffer(bytearray(host), dtype=torch.uint8)
@@ -75,23 +78,36 @@ def time_single(jx, torch, host: bytes, steps: int, warmup: int, copies: int = 3
         k = i % copies
         jx.build(bufs[k], outs[k], cnts[k], errs[k], stream)
     torch.cuda.synchronize()
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     wall0 = time.perf_counter()
-    t0.record(stream)
+    evs[0].record(stream)
     for i in range(steps):
         k = i % copies
         jx.build(bufs[k], outs[k], cnts[k], errs[k], stream)
-    t1.record(stream)
+        evs[i + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
-    ms = t0.elapsed_time(t1)
+    per = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(steps)])
+    ms = float(per.sum())
     S = int(cnts[0].item())
     err = int(errs[0].item())
+    # end to end: launch, then read the count back to the host (synchronous)
+    e2e = []
+    for i in range(max(5, min(steps, 20))):
+        k = i % copies
+        t = time.perf_counter()
+        jx.build(bufs[k], outs[k], cnts[k], errs[k], stream)
+        int(cnts[k].item())
+        e2e.append((time.perf_counter() - t) * 1e3)
     diag = jx.diag(stream)
     del bufs, outs
     return {"ms_total": ms, "ms_per_launch": ms / steps, "S": S, "N": n, "flags": err, "diag": diag,
-            "wall_s": wall}
+            "wall_s": wall, "launch_ms": pct(per), "e2e_ms": pct(np.array(e2e))}
+
+
+def pct(x: np.ndarray) -> dict:
+    return {"median": round(float(np.median(x)), 4), "p10": round(float(np.percentile(x, 10)), 4),
+            "p90": round(float(np.percentile(x, 90)), 4), "n": int(x.size)}
 
 
 def time_batch(jx, torch, data: bytes, offsets: np.ndarray, steps: int, warmup: int):
@@ -108,28 +124,70 @@ def time_batch(jx, torch, data: bytes, offsets: np.ndarray, steps: int, warmup: 
     for _ in range(warmup):
         jx.build_batch(bufs, offs, out, cnt, err, stream)
     torch.cuda.synchronize()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    evs[0].record(stream)
+    for i in range(steps):
+        jx.build_batch(bufs, offs, out, cnt, err, stream)
+        evs[i + 1].record(stream)
+    torch.cuda.synchronize()
+    per = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(steps)])
+    ms = float(per.mean())
+    S = int(cnt.to(torch.int64).sum().item())
+    # comparator: one jsidx_build launch per document, back to back on the same
+    # stream (raw pointers, so the host loop costs as little as it can)
+    lib = jx.binding.lib()
+    import ctypes
+    sp = ctypes.c_void_p(stream.cuda_stream)
+    VP = ctypes.c_void_p
+    b0, o0, c0, e0 = bufs.data_ptr(), out.data_ptr(), cnt.data_ptr(), err.data_ptr()
+    per_doc_docs = min(nd, 20000)
+    torch.cuda.synchronize()
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     t0.record(stream)
-    for _ in range(steps):
-        jx.build_batch(bufs, offs, out, cnt, err, stream)
-    t1.record(stream)
-    torch.cuda.synchronize()
-    ms = t0.elapsed_time(t1) / steps
-    S = int(cnt.to(torch.int64).sum().item())
-    # comparator: one jsidx_build launch per document, back to back
-    per_doc_docs = min(nd, 20000)
-    offs_h = offsets
-    torch.cuda.synchronize()
-    t0.record(stream)
     for d in range(per_doc_docs):
-        a, b = int(offs_h[d]), int(offs_h[d + 1])
-        jx.build(bufs[a:b], out[a:], cnt[d:d + 1], err[d:d + 1], stream, length=b - a)
+        a, b = int(offsets[d]), int(offsets[d + 1])
+        rc = lib.jsidx_build(VP(b0 + a), b - a, VP(o0 + 4 * a), VP(c0 + 4 * d), VP(e0 + 4 * d), sp)
+        if rc:
+            raise RuntimeError(f"jsidx_build failed ({rc})")
     t1.record(stream)
     torch.cuda.synchronize()
     per_doc_ms = t0.elapsed_time(t1)
-    return {"ms_per_launch": ms, "S": S, "N": total, "ndocs": nd,
+    return {"ms_per_launch": ms, "S": S, "N": total, "ndocs": nd, "launch_ms": pct(per),
             "docs_per_s": nd / (ms / 1e3), "per_doc_launch_docs_per_s": per_doc_docs / (per_doc_ms / 1e3)}
+
+
+def cpu_batch_baseline(data: bytes, offsets: np.ndarray, budget_s: float = 6.0) -> dict:
+    """The oracle over a batch: one core, then the documents partitioned into
+    contiguous byte-balanced ranges over every host core (one thread each; the
+    oracle's C loop runs without the interpreter lock)."""
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    arr = np.frombuffer(data, dtype=np.uint8)
+    nd = offsets.size - 1
+    t = time.perf_counter()
+    oracle.index_batch(arr, offsets)
+    one = time.perf_counter() - t
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    cores = max(1, min(cores, 64))
+    cuts = np.searchsorted(offsets, np.linspace(0, int(offsets[-1]), cores + 1)).clip(0, nd)
+    parts = [(int(cuts[i]), int(cuts[i + 1])) for i in range(cores) if cuts[i + 1] > cuts[i]]
+
+    def work(p):
+        a, b = p
+        return oracle.index_batch(arr, (offsets[a:b + 1]).copy())
+
+    with ThreadPoolExecutor(len(parts)) as ex:
+        reps, t = 0, time.perf_counter()
+        while True:
+            list(ex.map(work, parts))
+            reps += 1
+            el = time.perf_counter() - t
+            if el >= budget_s or reps >= 20:
+                break
+    return {"docs_per_s_1core": round(nd / one), "GBps_1core": round(len(data) / one / 1e9, 3),
+            "docs_per_s_all_cores": round(nd * reps / el), "GBps_all_cores": round(len(data) * reps / el / 1e9, 3),
+            "cores": len(parts), "kind": "oracle", "sample": f"the whole {nd}-document batch"}
 
 
 def cpu_baseline(host: bytes, budget_s: float = 10.0):
@@ -148,6 +206,28 @@ def cpu_baseline(host: bytes, budget_s: float = 10.0):
                       f"on one host core ({el:.1f} s)"}
 
 
+def serve_c4(jx, torch, synth, seconds: float) -> dict:
+    """C4: Poisson arrivals of documents of 100 B..16 MB (log-normal) served by
+    the continuous-batching loop at 30/60/90% of its saturated rate."""
+    from paper_1902_08318_amd import serve
+    log("generating C4 (request ring)")
+    data, offs = synth.gen_c4(4)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        ring = serve.Ring(data, offs, 256 << 20, stream)
+        del data
+        sat = serve.saturated_rate(ring)
+        loads = []
+        for i, f in enumerate((0.3, 0.6, 0.9)):
+            log(f"C4 serving at {int(f * 100)}% of saturation")
+            loads.append(serve.run_load(ring, sat, f, seconds, 40 + i).as_dict())
+        diag = jx.diag(stream)
+    return {"ring_bytes": ring.total, "ring_docs": ring.ndocs, "mean_doc_bytes": round(ring.total / ring.ndocs),
+            "saturated_GBps": round(sat / 1e9, 2), "loads": loads, "budget_bytes": 32 << 30,
+            "note": "request bytes resident in HBM at arrival; latency = host-observed completion - arrival",
+            **({"warning": "look-back diagnostic set"} if diag else {})}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -158,6 +238,8 @@ def main():
     ap.add_argument("--size-mib", type=int, default=256)
     ap.add_argument("--workload", choices=["c1", "c2", "c3"], default="c1",
                     help="headline workload (c2/c3 only for profiling runs)")
+    ap.add_argument("--serve-seconds", type=float, default=1.0,
+                    help="C4 serving loop: seconds per offered load (0 skips it)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run plain 256 MiB device copies (scale for the HBM byte counters)")
     args = ap.parse_args()
@@ -211,7 +293,7 @@ def main():
         "config": {"workload": "C1: one minified twitter-like JSON document, seed 1" if args.workload == "c1"
                    else "C2: one pretty-printed numeric (canada-like) JSON document, seed 2",
                    "bytes": r1["N"], "index_entries": r1["S"], "bytes_per_entry": round(r1["N"] / max(1, r1["S"]), 2),
-                   "flags": r1["flags"]},
+                   "flags": r1["flags"], "launch_ms": r1["launch_ms"], "end_to_end_ms": r1["e2e_ms"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": profiled_traffic() if args.workload == "c1" else None},
@@ -223,7 +305,7 @@ def main():
         r2 = time_single(jx, torch, c2.data, args.steps, args.warmup)
         extra["C2"] = {"bytes": r2["N"], "index_entries": r2["S"], "input_GBps": round(r2["N"] / (r2["ms_per_launch"] / 1e3) / 1e9, 2),
                        "alg_GBps": round((r2["N"] + 4 * r2["S"]) / (r2["ms_per_launch"] / 1e3) / 1e9, 1),
-                       "ms_per_launch": round(r2["ms_per_launch"], 4)}
+                       "ms_per_launch": round(r2["ms_per_launch"], 4), "launch_ms": r2["launch_ms"]}
         del c2
         log("generating C3 (100k-document batch)")
         data, offs, kinds = synth.gen_c3(3)
@@ -233,8 +315,13 @@ def main():
                        "alg_GBps": round((r3["N"] + 4 * r3["S"] + 16 * r3["ndocs"]) / (r3["ms_per_launch"] / 1e3) / 1e9, 1),
                        "docs_per_s": round(r3["docs_per_s"]), "per_doc_launch_docs_per_s": round(r3["per_doc_launch_docs_per_s"]),
                        "batched_vs_per_doc": round(r3["docs_per_s"] / r3["per_doc_launch_docs_per_s"], 1),
-                       "ms_per_launch": round(r3["ms_per_launch"], 4)}
+                       "ms_per_launch": round(r3["ms_per_launch"], 4), "launch_ms": r3["launch_ms"]}
+        if not args.no_cpu:
+            log("timing the CPU oracle on C3 (1 core, then all cores)")
+            extra["C3"]["cpu_oracle"] = cpu_batch_baseline(data, offs)
         del data
+        if args.serve_seconds > 0:
+            extra["C4"] = serve_c4(jx, torch, synth, args.serve_seconds)
     if extra:
         out["extra"] = extra
     if not args.no_cpu:

@@ -1,0 +1,172 @@
+"""Continuous-batching serving loop over jsidx_build_batch.
+
+Requests are documents of a ring resident in HBM (request r is ring document
+r mod ndocs); each has a host arrival time.  The loop admits every request
+that has arrived (up to an in-flight byte budget), launches the admitted
+requests as one batch -- a contiguous run of ring documents, so one offsets
+slice and one jsidx_build_batch call -- and keeps up to `depth` batches in
+flight on one stream.  A request completes when the host sees the event
+recorded after its batch; its latency is that time minus its arrival time.
+
+Per request there is no host work: admission is a binary search over the
+arrival times and completion a vectorised store, so the loop runs once per
+batch, not once per request.  Ring slots are reused by later requests; the
+outputs of slot d live at out_idx + offsets[d] and out_n/out_err[d], written
+again (with the same values) by every request that maps to d, in stream order.
+"""
+from __future__ import annotations
+
+import ctypes
+import gc
+import time
+from collections import deque
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import binding
+
+
+@dataclass
+class ServeResult:
+    offered_fraction: float
+    offered_docs_per_s: float
+    requests: int
+    seconds: float
+    served_bytes: int
+    batches: int
+    p50_us: float
+    p90_us: float
+    p99_us: float
+    max_us: float
+
+    def as_dict(self):
+        return {k: (round(v, 3) if isinstance(v, float) else v) for k, v in self.__dict__.items()} | {
+            "sustained_GBps": round(self.served_bytes / self.seconds / 1e9, 2),
+            "docs_per_s": round(self.requests / self.seconds)}
+
+
+class Ring:
+    """Device-resident request ring: bytes, offsets (int64, ndocs+1) and the
+    per-slot outputs (index positions, counts, flags)."""
+
+    def __init__(self, data: bytes, offsets: np.ndarray, max_batch_bytes: int, stream):
+        import torch
+        dev = torch.device("cuda:0")
+        self.ndocs = offsets.size - 1
+        self.total = int(offsets[-1])
+        self.offs_h = offsets.astype(np.int64)
+        self.bufs = torch.frombuffer(bytearray(data), dtype=torch.uint8).to(dev)
+        self.offs = torch.from_numpy(self.offs_h).to(dev)
+        self.out = torch.empty(max(1, self.total), dtype=torch.int32, device=dev)
+        self.cnt = torch.zeros(self.ndocs, dtype=torch.int32, device=dev)
+        self.err = torch.zeros(self.ndocs, dtype=torch.int32, device=dev)
+        self.stream = stream
+        self.max_batch_bytes = int(max_batch_bytes)
+        binding.reserve(self.max_batch_bytes, stream)
+        self._lib = binding.lib()
+        self._p = (self.bufs.data_ptr(), self.offs.data_ptr(), self.out.data_ptr(), self.cnt.data_ptr(),
+                   self.err.data_ptr())
+        self._s = ctypes.c_void_p(stream.cuda_stream)
+
+    def launch(self, d0: int, nd: int):
+        """Index ring documents [d0, d0 + nd) with one batched launch."""
+        b, o, out, cnt, err = self._p
+        rc = self._lib.jsidx_build_batch(ctypes.c_void_p(b), ctypes.c_void_p(o + 8 * d0), nd,
+                                         ctypes.c_void_p(out), ctypes.c_void_p(cnt + 4 * d0),
+                                         ctypes.c_void_p(err + 4 * d0), self._s)
+        if rc:
+            binding._check(rc)
+
+    def batch_end(self, r0: int, r_avail: int) -> int:
+        """Last request (exclusive) of a batch starting at request r0 that
+        stays inside the ring (no wrap) and within the reserved byte size."""
+        d0 = r0 % self.ndocs
+        lim = min(r_avail - r0, self.ndocs - d0)
+        cap = self.offs_h[d0] + self.max_batch_bytes
+        k = int(np.searchsorted(self.offs_h, cap, side="right")) - 1 - d0  # docs that fit
+        return r0 + max(1, min(lim, k))
+
+
+def poisson_arrivals(rng: np.random.Generator, rate: float, n: int) -> np.ndarray:
+    return np.cumsum(rng.exponential(1.0 / rate, n))
+
+
+def serve(ring: Ring, arrivals: np.ndarray, depth: int = 2, budget_bytes: int = 32 << 30) -> tuple:
+    """Run the loop over requests with the given arrival times (seconds from
+    the start).  Returns (latency seconds per request, elapsed seconds,
+    served bytes, batches)."""
+    import torch
+    nreq = arrivals.size
+    doc_len = np.diff(ring.offs_h)
+    lat = np.empty(nreq)
+    inflight = deque()
+    nxt = 0        # first request not launched
+    done = 0       # requests completed
+    held = 0       # bytes admitted and not completed
+    served = 0
+    batches = 0
+    budget = min(int(budget_bytes), ring.total)
+    ev_pool = [torch.cuda.Event() for _ in range(depth + 1)]
+    ev_i = 0
+    gc_was = gc.isenabled()
+    gc.disable()
+    try:
+        t0 = time.perf_counter()
+        while done < nreq:
+            now = time.perf_counter() - t0
+            while inflight and inflight[0][0].query():
+                tc = time.perf_counter() - t0
+                _, r0, r1, nb = inflight.popleft()
+                lat[r0:r1] = tc - arrivals[r0:r1]
+                done = r1
+                held -= nb
+                served += nb
+            if len(inflight) < depth and nxt < nreq:
+                avail = int(np.searchsorted(arrivals, now, side="right"))
+                if avail > nxt:
+                    r1 = ring.batch_end(nxt, avail)
+                    d0 = nxt % ring.ndocs
+                    nb = int(ring.offs_h[d0 + (r1 - nxt)] - ring.offs_h[d0])
+                    if held == 0 or held + nb <= budget:
+                        ring.launch(d0, r1 - nxt)
+                        ev = ev_pool[ev_i]
+                        ev_i = (ev_i + 1) % len(ev_pool)
+                        ev.record(ring.stream)
+                        inflight.append((ev, nxt, r1, nb))
+                        held += nb
+                        nxt = r1
+                        batches += 1
+        elapsed = time.perf_counter() - t0
+    finally:
+        if gc_was:
+            gc.enable()
+    del doc_len
+    return lat, elapsed, served, batches
+
+
+def saturated_rate(ring: Ring, seconds: float = 0.5) -> float:
+    """Bytes per second with every request already waiting (max-size batches
+    back to back through the same loop)."""
+    n = ring.ndocs
+    reps = 1
+    arr = np.zeros(n * reps)
+    lat, el, served, _ = serve(ring, arr)
+    while el < seconds and reps < 64:
+        reps *= 2
+        arr = np.zeros(n * reps)
+        lat, el, served, _ = serve(ring, arr)
+    return served / el
+
+
+def run_load(ring: Ring, sat_bytes_per_s: float, fraction: float, seconds: float, seed: int,
+             min_requests: int = 100_000) -> ServeResult:
+    mean = ring.total / ring.ndocs
+    rate = fraction * sat_bytes_per_s / mean
+    n = max(min_requests, int(rate * seconds))
+    rng = np.random.default_rng(seed)
+    arr = poisson_arrivals(rng, rate, n)
+    lat, el, served, batches = serve(ring, arr)
+    us = lat * 1e6
+    return ServeResult(fraction, rate, n, el, served, batches, float(np.percentile(us, 50)),
+                       float(np.percentile(us, 90)), float(np.percentile(us, 99)), float(us.max()))

@@ -290,3 +290,30 @@ def gen_c3(seed: int = 3, ndocs: int = 100_000, median: int = 2048, sigma: float
     offsets = np.zeros(ndocs + 1, dtype=np.uint64)
     np.cumsum(lens, out=offsets[1:])
     return b"".join(docs), offsets, kinds
+
+
+def gen_c4(seed: int = 4, ring_bytes: int = 1 << 30, median: int = 4096, sigma: float = 2.0,
+           lo: int = 100, hi: int = 16 << 20, pool: int = 160):
+    """Request stream for the serving loop: documents with log-normal sizes
+    (median 4 KB, sigma 2, clipped to 100 B..16 MB), up to 64 KB generated as
+    gen_c0 (pretty-printed mixed values) and above as gen_c1 (minified
+    twitter-like records), laid end to end until `ring_bytes`.  Request r of
+    a run is document r mod ndocs of this ring.  Returns (bytes, offsets)."""
+    rng = np.random.default_rng(seed)
+    psizes = np.unique(np.geomspace(lo, hi, pool).astype(np.int64))
+    pool_docs = []
+    for i, t in enumerate(psizes):
+        s = seed * 100003 + i
+        pool_docs.append(gen_c0(s, int(t)).data if t <= 65536 else gen_c1(s, int(t), pool=64).data)
+    plen = np.array([len(d) for d in pool_docs])
+    mean = float(np.exp(np.log(median) + sigma * sigma / 2))
+    n = int(ring_bytes / mean * 1.5) + 16
+    want = lognormal_sizes(rng, n, median, sigma, lo, hi)
+    pick = np.clip(np.searchsorted(plen, want), 0, len(pool_docs) - 1)
+    lens = plen[pick]
+    keep = int(np.searchsorted(np.cumsum(lens), ring_bytes, side="right"))
+    keep = max(1, keep)
+    pick, lens = pick[:keep], lens[:keep]
+    offsets = np.zeros(keep + 1, dtype=np.uint64)
+    np.cumsum(lens, out=offsets[1:])
+    return b"".join(pool_docs[int(i)] for i in pick), offsets

@@ -62,9 +62,10 @@ def log(msg):
 
 
 def time_single(jx, torch, host: bytes, steps: int, warmup: int, copies: int = 3):
-    """Time `steps` launches over rotating copies of one document: an event
-    before every launch and after the last gives the per-launch durations
-    (kernel time on the launch stream) and their sum the timed region."""
+    """Time `steps` launches over rotating copies of one document between two
+    events on the launch stream (the timed region), then the same launches
+    with an event after each for the per-launch distribution, then launches
+    each followed by reading the count back to the host (end to end)."""
     dev = torch.device("cuda:0")
     n = len(host)
     src = torch.frombuffer(bytearray(host), dtype=torch.uint8)
@@ -78,19 +79,29 @@ def time_single(jx, torch, host: bytes, steps: int, warmup: int, copies: int = 3
         k = i % copies
         jx.build(bufs[k], outs[k], cnts[k], errs[k], stream)
     torch.cuda.synchronize()
-    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
     wall0 = time.perf_counter()
+    t0.record(stream)
+    for i in range(steps):
+        k = i % copies
+        jx.build(bufs[k], outs[k], cnts[k], errs[k], stream)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms = t0.elapsed_time(t1)
+    S = int(cnts[0].item())
+    err = int(errs[0].item())
+    # per-launch distribution: a second pass with an event after every launch
+    # (each event adds a little of its own time)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     evs[0].record(stream)
     for i in range(steps):
         k = i % copies
         jx.build(bufs[k], outs[k], cnts[k], errs[k], stream)
         evs[i + 1].record(stream)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
     per = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(steps)])
-    ms = float(per.sum())
-    S = int(cnts[0].item())
-    err = int(errs[0].item())
     # end to end: launch, then read the count back to the host (synchronous)
     e2e = []
     for i in range(max(5, min(steps, 20))):
@@ -124,6 +135,14 @@ def time_batch(jx, torch, data: bytes, offsets: np.ndarray, steps: int, warmup: 
     for _ in range(warmup):
         jx.build_batch(bufs, offs, out, cnt, err, stream)
     torch.cuda.synchronize()
+    a0 = torch.cuda.Event(enable_timing=True)
+    a1 = torch.cuda.Event(enable_timing=True)
+    a0.record(stream)
+    for i in range(steps):
+        jx.build_batch(bufs, offs, out, cnt, err, stream)
+    a1.record(stream)
+    torch.cuda.synchronize()
+    ms = a0.elapsed_time(a1) / steps
     evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     evs[0].record(stream)
     for i in range(steps):
@@ -131,7 +150,6 @@ def time_batch(jx, torch, data: bytes, offsets: np.ndarray, steps: int, warmup: 
         evs[i + 1].record(stream)
     torch.cuda.synchronize()
     per = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(steps)])
-    ms = float(per.mean())
     S = int(cnt.to(torch.int64).sum().item())
     # comparator: one jsidx_build launch per document, back to back on the same
     # stream (raw pointers, so the host loop costs as little as it can)
@@ -190,40 +208,77 @@ def cpu_batch_baseline(data: bytes, offsets: np.ndarray, budget_s: float = 6.0) 
             "cores": len(parts), "kind": "oracle", "sample": f"the whole {nd}-document batch"}
 
 
+def host_cpu() -> dict:
+    model = "unknown"
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"cpu_model": model, "nproc": n}
+
+
 def cpu_baseline(host: bytes, budget_s: float = 10.0):
     import oracle
     oracle.index(host[: 1 << 20])  # load
-    reps = 0
+    times = []
     t0 = time.perf_counter()
     while True:
+        t = time.perf_counter()
         oracle.index(host)
-        reps += 1
+        times.append(time.perf_counter() - t)
         el = time.perf_counter() - t0
-        if el >= budget_s or reps >= 50:
+        if el >= budget_s or len(times) >= 50:
             break
-    return {"value": len(host) * reps / el / 1e9, "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": f"whole document ({len(host)} bytes) indexed {reps}x by the byte-at-a-time C oracle "
-                      f"on one host core ({el:.1f} s)"}
+    med = float(np.median(times))
+    return {"value": len(host) / med / 1e9, "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"whole document ({len(host)} bytes) indexed {len(times)}x by the byte-at-a-time C oracle "
+                      f"on one host core ({el:.1f} s); value from the median run",
+            **host_cpu()}
 
 
-def serve_c4(jx, torch, synth, seconds: float) -> dict:
+def copy_ceiling(torch, nbytes: int = 256 << 20, reps: int = 20) -> dict:
+    """Measured HBM ceiling: a plain device-to-device copy (reads and writes
+    nbytes each), rotating buffers so the last-level cache does not hold them."""
+    dev = torch.device("cuda:0")
+    src = [torch.empty(nbytes, dtype=torch.uint8, device=dev).fill_(7) for _ in range(2)]
+    dst = [torch.empty(nbytes, dtype=torch.uint8, device=dev) for _ in range(2)]
+    for i in range(3):
+        dst[i % 2].copy_(src[i % 2])
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for i in range(reps):
+        dst[i % 2].copy_(src[(i + 1) % 2])
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    return {"bytes_moved_per_copy": 2 * nbytes, "GBps": round(2 * nbytes / (ms / 1e3) / 1e9, 1),
+            "frac_of_peak": round(2 * nbytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
+def serve_c4(jx, torch, synth, seconds: float, nstreams: int = 3) -> dict:
     """C4: Poisson arrivals of documents of 100 B..16 MB (log-normal) served by
-    the continuous-batching loop at 30/60/90% of its saturated rate."""
+    the continuous-batching loop (batches on `nstreams` streams at once) at
+    30/60/90% of its saturated rate."""
     from paper_1902_08318_amd import serve
     log("generating C4 (request ring)")
     data, offs = synth.gen_c4(4)
-    stream = torch.cuda.Stream()
-    with torch.cuda.stream(stream):
-        ring = serve.Ring(data, offs, 256 << 20, stream)
-        del data
-        sat = serve.saturated_rate(ring)
-        loads = []
-        for i, f in enumerate((0.3, 0.6, 0.9)):
-            log(f"C4 serving at {int(f * 100)}% of saturation")
-            loads.append(serve.run_load(ring, sat, f, seconds, 40 + i).as_dict())
-        diag = jx.diag(stream)
+    streams = [torch.cuda.Stream() for _ in range(nstreams)]
+    ring = serve.Ring(data, offs, 256 << 20, streams)
+    del data
+    sat = serve.saturated_rate(ring)
+    loads = []
+    for i, f in enumerate((0.3, 0.6, 0.9)):
+        log(f"C4 serving at {int(f * 100)}% of saturation")
+        loads.append(serve.run_load(ring, sat, f, seconds, 40 + i).as_dict())
+    diag = any(jx.diag(st) for st in streams)
     return {"ring_bytes": ring.total, "ring_docs": ring.ndocs, "mean_doc_bytes": round(ring.total / ring.ndocs),
-            "saturated_GBps": round(sat / 1e9, 2), "loads": loads, "budget_bytes": 32 << 30,
+            "streams": nstreams, "saturated_GBps": round(sat / 1e9, 2), "loads": loads, "budget_bytes": 32 << 30,
             "note": "request bytes resident in HBM at arrival; latency = host-observed completion - arrival",
             **({"warning": "look-back diagnostic set"} if diag else {})}
 
@@ -240,6 +295,7 @@ def main():
                     help="headline workload (c2/c3 only for profiling runs)")
     ap.add_argument("--serve-seconds", type=float, default=1.0,
                     help="C4 serving loop: seconds per offered load (0 skips it)")
+    ap.add_argument("--no-tune", action="store_true", help="keep the built-in tile size choice")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run plain 256 MiB device copies (scale for the HBM byte counters)")
     args = ap.parse_args()
@@ -263,15 +319,21 @@ def main():
         print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "copies": args.steps}), flush=True)
         return
 
+    tuning = None
+    c3 = None
+    c1 = None
+    if args.workload != "c3":
+        c1 = synth.gen_c2(2, args.size_mib << 20) if args.workload == "c2" else synth.gen_c1(1, args.size_mib << 20)
+    if not args.no_tune:
+        from paper_1902_08318_amd import tune
+        log("autotuning the tile size on the 100k-document batch and the headline document")
+        c3 = synth.gen_c3(3)
+        tuning = tune.autotune(c3[0], c3[1], c1.data if c1 is not None else None, log=log)
     if args.workload == "c3":
-        data, offs, _ = synth.gen_c3(3)
+        data, offs, _ = c3 if c3 is not None else synth.gen_c3(3)
         r3 = time_batch(jx, torch, data, offs, args.steps, args.warmup)
         print(json.dumps({"workload": "C3", **r3}), flush=True)
         return
-    if args.workload == "c2":
-        c1 = synth.gen_c2(2, args.size_mib << 20)
-    else:
-        c1 = synth.gen_c1(1, args.size_mib << 20)
     log(f"timing {args.workload}: {len(c1.data)} bytes, {args.steps} steps")
     r1 = time_single(jx, torch, c1.data, args.steps, args.warmup)
     value = r1["N"] * args.steps / (r1["ms_total"] / 1e3) / 1e9
@@ -298,6 +360,7 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": profiled_traffic() if args.workload == "c1" else None},
     }
+    out["roofline"]["copy_ceiling"] = copy_ceiling(torch)
     extra = {}
     if not args.no_extra:
         log("generating C2 (numeric, pretty-printed)")
@@ -308,7 +371,8 @@ def main():
                        "ms_per_launch": round(r2["ms_per_launch"], 4), "launch_ms": r2["launch_ms"]}
         del c2
         log("generating C3 (100k-document batch)")
-        data, offs, kinds = synth.gen_c3(3)
+        data, offs, kinds = c3 if c3 is not None else synth.gen_c3(3)
+        c3 = None
         r3 = time_batch(jx, torch, data, offs, max(3, args.steps // 2), 2)
         extra["C3"] = {"bytes": r3["N"], "ndocs": r3["ndocs"], "index_entries": r3["S"],
                        "input_GBps": round(r3["N"] / (r3["ms_per_launch"] / 1e3) / 1e9, 2),
@@ -324,6 +388,9 @@ def main():
             extra["C4"] = serve_c4(jx, torch, synth, args.serve_seconds)
     if extra:
         out["extra"] = extra
+    if tuning is not None:
+        out["tuning"] = {"tile_rows_by_log2_bytes": {str(b): r for b, r in enumerate(tuning["table"]) if r},
+                         "arch": tuning["arch"]}
     if not args.no_cpu:
         log("timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(c1.data)

@@ -133,6 +133,28 @@ int jsidx_release(jsidx_stream_t stream);
  */
 int jsidx_stream_diag(jsidx_stream_t stream, uint32_t *out_flags);
 
+/*
+ * jsidx_set_tile_rows -- tuning: the tile size by input size, for later
+ * launches on every device and stream of the process (the autotuner of the
+ * Python package measures and sets it).  A launch cuts its input into tiles
+ * of `rows` rows of 2 KiB; one wave indexes a tile row after row, so small
+ * tiles shorten each wave's serial work and large tiles make fewer tiles
+ * (less per-tile work, fewer carries to resolve).
+ *   rows_by_log2  host array of n entries: entry b applies to launches whose
+ *                 span (bytes from the 16-byte granule holding the first byte
+ *                 to the last byte) has floor(log2(span)) == b; 0 keeps the
+ *                 built-in choice (the largest tile that still gives every
+ *                 wave of the device one), otherwise 2, 4, 8 or 16.
+ *   n             0..64; n == 0 restores the built-in choice everywhere.
+ * Returns JSIDX_E_INVAL (table unchanged) for other values.  Results never
+ * depend on the tile size.
+ */
+int jsidx_set_tile_rows(const uint8_t *rows_by_log2, uint32_t n);
+
+/* Rows per tile that a launch over `span` bytes would use on the current
+ * device (written to *out_rows). */
+int jsidx_tile_rows(uint64_t span, uint32_t *out_rows);
+
 /* Human-readable text for a status code. */
 const char *jsidx_status_string(int status);
 

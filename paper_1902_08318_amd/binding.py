@@ -30,6 +30,8 @@ SIGNATURES = {
     "jsidx_release": ([_VP], ctypes.c_int),
     "jsidx_stream_diag": ([_VP, ctypes.POINTER(ctypes.c_uint32)], ctypes.c_int),
     "jsidx_status_string": ([ctypes.c_int], ctypes.c_char_p),
+    "jsidx_set_tile_rows": ([_VP, ctypes.c_uint32], ctypes.c_int),
+    "jsidx_tile_rows": ([ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint32)], ctypes.c_int),
 }
 
 
@@ -105,6 +107,20 @@ def release(stream=None):
 def diag(stream=None) -> int:
     v = ctypes.c_uint32(0)
     _check(lib().jsidx_stream_diag(_stream(stream), ctypes.byref(v)))
+    return int(v.value)
+
+
+def set_tile_rows(rows_by_log2) -> None:
+    """jsidx_set_tile_rows: rows per tile by floor(log2(span)) (0 = built-in);
+    an empty sequence restores the built-in choice."""
+    t = bytes(int(r) for r in rows_by_log2)
+    buf = ctypes.create_string_buffer(t, max(1, len(t)))
+    _check(lib().jsidx_set_tile_rows(ctypes.cast(buf, ctypes.c_void_p), len(t)))
+
+
+def tile_rows(span: int) -> int:
+    v = ctypes.c_uint32(0)
+    _check(lib().jsidx_tile_rows(int(span), ctypes.byref(v)))
     return int(v.value)
 
 

@@ -37,12 +37,13 @@ struct StreamWs {
   int device;
   hipStream_t stream;
   Workspace* ws;
-  uint64_t cap_tiles;
+  uint64_t cap_tiles;  // in largest tiles
   bool reserved;  // sized by jsidx_reserve: batch calls trust it and never sync
 };
 
 std::mutex g_mu;
 std::vector<StreamWs> g_ws;
+uint64_t g_rows_tab[4];  // tile rows by size class (jsidx_set_tile_rows), 0 = default
 int g_slots[64];  // resident workgroups per device (0 = not queried)
 
 uint64_t tiles_for(uint64_t total_len) {
@@ -95,14 +96,31 @@ int get_ws(hipStream_t stream, uint64_t need_tiles, bool grow, StreamWs** out) {
   return JSIDX_OK;
 }
 
-int launch(const Args& args, hipStream_t stream, uint64_t tiles_hint) {
+// Launch over a workspace of e->cap_tiles largest tiles.  span >= 0: the
+// bytes from the 16-byte granule holding the first byte to the end (one
+// document, known here), so the tile size and the grid fit the input;
+// span < 0 (batch, sizes on the device): the grid covers the workspace and
+// the kernel picks the tile size.
+int launch(Args& a, hipStream_t stream, const StreamWs& e, int64_t span) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return JSIDX_E_HIP;
-  uint64_t slots = (uint64_t)slots_for_device(dev);
-  const uint64_t groups = (tiles_hint + kWaves - 1) / kWaves;
+  const uint64_t slots = (uint64_t)slots_for_device(dev);
+  a.ws = e.ws;
+  a.cap_tiles = desc_slots(e.cap_tiles);
+  a.cap_rows = e.cap_tiles * (uint64_t)kRows;
+  uint64_t tiles = a.cap_tiles;
+  a.rows = 0;
+  for (int i = 0; i < 4; i++) a.rows_tab[i] = g_rows_tab[i];
+  if (span >= 0) {
+    a.rows = rows_for(span, slots * kWaves, a.rows_tab);
+    const uint64_t tb = (uint64_t)a.rows * kRowBytes;
+    tiles = span > 0 ? ((uint64_t)span + tb - 1) / tb : 1;
+  }
+  const uint64_t groups = (tiles + kWaves - 1) / kWaves;
   uint64_t grid = groups < slots ? groups : slots;
   if (grid < 1) grid = 1;
-  hipLaunchKernelGGL(index_kernel, dim3((uint32_t)grid), dim3(kGroupThreads), 0, stream, args);
+  a.fill_waves = (uint32_t)(grid * kWaves);
+  hipLaunchKernelGGL(index_kernel, dim3((uint32_t)grid), dim3(kGroupThreads), 0, stream, a);
   if (hipGetLastError() != hipSuccess) return JSIDX_E_HIP;
   return JSIDX_OK;
 }
@@ -131,9 +149,7 @@ int jsidx_build(const uint8_t* buf, uint64_t len, uint32_t* out_idx, uint32_t* o
   a.out_idx = out_idx;
   a.out_n = out_n;
   a.out_err = out_err;
-  a.ws = e->ws;
-  a.cap_tiles = e->cap_tiles;
-  return launch(a, stream, need);
+  return launch(a, stream, *e, (int64_t)(len + ((uintptr_t)a.base & 15u)));
 }
 
 int jsidx_build_batch(const uint8_t* bufs, const uint64_t* offsets, uint32_t ndocs, uint32_t* out_idx,
@@ -161,9 +177,7 @@ int jsidx_build_batch(const uint8_t* bufs, const uint64_t* offsets, uint32_t ndo
   a.out_idx = out_idx;
   a.out_n = out_n;
   a.out_err = out_err;
-  a.ws = e->ws;
-  a.cap_tiles = e->cap_tiles;
-  return launch(a, stream, e->cap_tiles);
+  return launch(a, stream, *e, -1);
 }
 
 int jsidx_reserve(uint64_t max_total_len, jsidx_stream_t stream_) {
@@ -206,6 +220,33 @@ int jsidx_stream_diag(jsidx_stream_t stream_, uint32_t* out_flags) {
   if (hipMemcpy(&v, &e->ws->diag, 4, hipMemcpyDeviceToHost) != hipSuccess) return JSIDX_E_HIP;
   if (v && hipMemset(&e->ws->diag, 0, 4) != hipSuccess) return JSIDX_E_HIP;
   *out_flags = v;
+  return JSIDX_OK;
+}
+
+int jsidx_set_tile_rows(const uint8_t* rows_by_log2, uint32_t n) {
+  if (n > 64 || (n && !rows_by_log2)) return JSIDX_E_INVAL;
+  uint64_t tab[4] = {0, 0, 0, 0};
+  for (uint32_t b = 0; b < n; b++) {
+    const uint32_t r = rows_by_log2[b];
+    uint32_t code = 0;
+    if (r) {
+      if (r < (uint32_t)kMinRows || r > (uint32_t)kRows || (r & (r - 1u))) return JSIDX_E_INVAL;
+      code = (uint32_t)__builtin_ctz(r);
+    }
+    tab[b >> 4] |= (uint64_t)code << (4u * (b & 15u));
+  }
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (int i = 0; i < 4; i++) g_rows_tab[i] = tab[i];
+  return JSIDX_OK;
+}
+
+int jsidx_tile_rows(uint64_t span, uint32_t* out_rows) {
+  if (!out_rows) return JSIDX_E_INVAL;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return JSIDX_E_HIP;
+  std::lock_guard<std::mutex> lk(g_mu);
+  const uint64_t slots = (uint64_t)slots_for_device(dev);
+  *out_rows = rows_for((int64_t)span, slots * kWaves, g_rows_tab);
   return JSIDX_OK;
 }
 

@@ -34,12 +34,15 @@ constexpr int kGroupThreads = kWaves * kThreads;
 constexpr int kTicketTiles = 2;  // consecutive tiles per ticket (when every wave gets at least 2 tiles)
 constexpr int kSegBytes = 32;
 constexpr int kRowBytes = kThreads * kSegBytes;  // 2 KiB
-// Rows per tile (test and tuning builds may override).
+// Rows per tile: at most kRows (tuning builds may override), at least
+// kMinRows.  Each launch picks its tile size (see pick_rows).
 #ifndef JSIDX_TILE_ROWS
 #define JSIDX_TILE_ROWS 16
 #endif
 constexpr int kRows = JSIDX_TILE_ROWS;
-constexpr int kTileBytes = kRows * kRowBytes;  // 32 KiB
+constexpr int kMinRows = 2;
+constexpr int kTileBytes = kRows * kRowBytes;  // largest tile: 32 KiB
+static_assert(kRows >= kMinRows && kRows % kMinRows == 0 && (kRows & (kRows - 1)) == 0, "tile rows");
 constexpr int kDocCap = 256;                   // documents per tile held in LDS
 constexpr int kScrub = 4096;                   // descriptors cleared per launch
 constexpr int kEscSteps = 4;                   // backslash run scanned back: 4 x 1 KiB
@@ -64,7 +67,9 @@ constexpr uint32_t kEpochShift = 44;
 constexpr uint64_t kEpochMask = (1ull << 20) - 1;
 
 // Workspace: this header, then cap_tiles tile descriptors, 3 words per block
-// of block descriptors, and one 32-bit counter per block.
+// of block descriptors, one 32-bit counter per block, and the head-region
+// masks of every tile.  A workspace is sized in largest tiles (tiles16); it
+// holds a descriptor for every smallest tile of that many bytes.
 struct Workspace {
   uint32_t ticket;  // next tile to hand out
   uint32_t done;    // workgroups that have left the tile loop
@@ -77,11 +82,32 @@ inline constexpr uint64_t blocks_for_tiles(uint64_t tiles) { return (tiles + kBl
 // Head-region masks of a tile (candidates, indexed bits if the tile starts
 // outside a string): one pair per lane and row.
 constexpr uint64_t kMaskBytesPerTile = (uint64_t)kRows * kThreads * 8;
-inline constexpr uint64_t mask_offset(uint64_t tiles) {
-  return (sizeof(Workspace) + tiles * sizeof(uint64_t) + blocks_for_tiles(tiles) * (3 * sizeof(uint64_t) + sizeof(uint32_t)) +
+inline constexpr uint64_t desc_slots(uint64_t tiles16) { return tiles16 * (uint64_t)(kRows / kMinRows); }
+inline constexpr uint64_t mask_offset(uint64_t slots) {
+  return (sizeof(Workspace) + slots * sizeof(uint64_t) + blocks_for_tiles(slots) * (3 * sizeof(uint64_t) + sizeof(uint32_t)) +
           255) & ~(uint64_t)255;
 }
-inline constexpr uint64_t workspace_bytes(uint64_t tiles) { return mask_offset(tiles) + tiles * kMaskBytesPerTile; }
+inline constexpr uint64_t workspace_bytes(uint64_t tiles16) {
+  return mask_offset(desc_slots(tiles16)) + tiles16 * kMaskBytesPerTile;
+}
+// Rows per tile for a launch over `span` bytes with `waves` waves, unless
+// tuned: the largest tile that still makes a tile for every eighth wave
+// (small inputs get small tiles, so that more waves share them and a tile's
+// serial chain of rows is short; past that, larger tiles cost less per
+// byte), never below kMinRows.
+inline constexpr uint32_t pick_rows(int64_t span, uint64_t waves) {
+  uint32_t r = (uint32_t)kRows;
+  const uint64_t target = waves / 8 ? waves / 8 : 1;
+  while (r > (uint32_t)kMinRows && (uint64_t)(span > 0 ? span : 0) < (uint64_t)r * kRowBytes * target) r >>= 1;
+  return r;
+}
+// Rows per tile from a tuning table: 4 bits per size class b =
+// floor(log2(span)) (b = 0 for span <= 1), 0 = pick_rows, else rows = 1 << code.
+inline constexpr uint32_t rows_for(int64_t span, uint64_t waves, const uint64_t* tab) {
+  const uint32_t b = span > 1 ? 63u - (uint32_t)__builtin_clzll((uint64_t)span) : 0u;
+  const uint32_t code = (uint32_t)(tab[b >> 4] >> (4u * (b & 15u))) & 15u;
+  return code ? (1u << code) : pick_rows(span, waves);
+}
 
 JSIDX_DEV uint64_t epoch_bits(uint32_t epoch) { return ((uint64_t)epoch & kEpochMask) << kEpochShift; }
 JSIDX_DEV uint64_t make_agg(uint32_t table, uint32_t c0, uint32_t c1, uint32_t elig0, uint32_t esens, uint32_t epoch) {
@@ -133,8 +159,14 @@ struct Args {
   uint32_t* out_n;
   uint32_t* out_err;
   Workspace* ws;
-  uint64_t cap_tiles;  // descriptors available
+  uint64_t cap_tiles;   // descriptors available (tiles of kMinRows rows)
+  uint64_t cap_rows;    // rows of head-region masks available
+  uint32_t rows;        // rows per tile (0: the kernel picks them)
+  uint32_t fill_waves;  // waves of the launch (for picking rows)
+  uint64_t rows_tab[4];  // tuning table of rows_for
 };
+
+
 
 JSIDX_DEV int64_t doc_off(const Args& a, int64_t d) {
   if (a.offsets) return (int64_t)prim::load8(a.offsets + d);
@@ -317,7 +349,7 @@ JSIDX_DEV void write_row(uint32_t* out, uint64_t lim, uint32_t* cc, uint32_t F, 
 // lies inside the input (every byte belongs to document hd, which starts at
 // hs < P0), the escape state entering the tile is known, and defer is set.
 template <bool SIMPLE>
-JSIDX_DEV void tile_local(const Args& a, Shared& sh, uint2* hmask, const uint32_t* first_row, int64_t P0,
+JSIDX_DEV void tile_local(const Args& a, uint32_t rows, Shared& sh, uint2* hmask, const uint32_t* first_row, int64_t P0,
                           int64_t begin, int64_t end, int64_t d_first, int32_t hd, int64_t hs, uint32_t st_in,
                           bool defer, uint32_t head_base, TileFacts& T) {
   const uint32_t lane = prim::lane();
@@ -347,13 +379,13 @@ JSIDX_DEV void tile_local(const Args& a, Shared& sh, uint2* hmask, const uint32_
     load_segment<SIMPLE>(a, P0 + (int64_t)lane * kSegBytes, begin, end, wn);
   }
 #pragma unroll 1
-  for (int r = 0; r < kRows; r++) {
+  for (int r = 0; r < (int)rows; r++) {
     const int32_t rel = r * kRowBytes + (int32_t)lane * kSegBytes;  // tile-relative
     const int64_t pos = P0 + rel;
     uint32_t w[8];
 #pragma unroll
     for (int k = 0; k < 8; k++) w[k] = wn[k];
-    if (r + 1 < kRows) load_segment<SIMPLE>(a, pos + kRowBytes, begin, end, wn);  // prefetch
+    if (r + 1 < (int)rows) load_segment<SIMPLE>(a, pos + kRowBytes, begin, end, wn);  // prefetch
 
     // documents: starts in this segment (D), start right after it (d32),
     // document holding byte 0 (head), valid bytes (V)
@@ -739,8 +771,8 @@ JSIDX_DEV LaneFold fold_unpack(uint32_t f, uint32_t c0, uint32_t c1) {
 // All block words are cleared at the end of every launch.
 constexpr uint64_t kAggEpochMask = 31;
 JSIDX_DEV uint64_t* block_desc(const Args& a) { return a.ws->desc + a.cap_tiles; }
-JSIDX_DEV uint2* head_masks(const Args& a, int64_t t) {
-  return reinterpret_cast<uint2*>(reinterpret_cast<uint8_t*>(a.ws) + mask_offset(a.cap_tiles)) + t * (kRows * kThreads);
+JSIDX_DEV uint2* head_masks(const Args& a, uint32_t rows, int64_t t) {
+  return reinterpret_cast<uint2*>(reinterpret_cast<uint8_t*>(a.ws) + mask_offset(a.cap_tiles)) + t * ((int64_t)rows * kThreads);
 }
 JSIDX_DEV uint32_t* block_count(const Args& a) {
   return reinterpret_cast<uint32_t*>(block_desc(a) + 3 * blocks_for_tiles(a.cap_tiles));
@@ -986,19 +1018,22 @@ JSIDX_DEV void look_back(const Args& a, int64_t t, uint32_t epoch, uint32_t* s_o
 // entering it.
 struct TileSetup {
   int64_t t, P0, d_first, hs;
+  uint32_t rows;  // rows of the launch's tiles
   int32_t hd;
   bool hd_ok, simple;
   uint32_t e_T, e_known;
   uint32_t w0[8];  // this lane's segment of row 0, loaded first
 };
 
-JSIDX_DEV TileSetup begin_tile(const Args& a, Shared& sh, int64_t t, int64_t pos_g0, int64_t begin, int64_t end,
-                               int64_t ntiles) {
+JSIDX_DEV TileSetup begin_tile(const Args& a, uint32_t rows, Shared& sh, int64_t t, int64_t pos_g0, int64_t begin,
+                               int64_t end, int64_t ntiles) {
   const uint32_t lane = prim::lane();
   TileSetup S;
+  S.rows = rows;
   S.t = t;
-  S.P0 = pos_g0 + t * kTileBytes;  // position of tile byte 0
-  const int64_t P0 = S.P0, Pend = P0 + kTileBytes;
+  const int64_t tb = (int64_t)rows * kRowBytes;
+  S.P0 = pos_g0 + t * tb;  // position of tile byte 0
+  const int64_t P0 = S.P0, Pend = P0 + tb;
   // the first row's loads go out before anything else of the tile
   load_segment<false>(a, P0 + (int64_t)lane * kSegBytes, begin, end, S.w0);
   // d_first: the first document whose end is at or after the tile start.
@@ -1122,10 +1157,10 @@ JSIDX_DEV Pending start_tile(const Args& a, Shared& sh, const TileSetup& S, int6
   const uint32_t lane = prim::lane();
   Workspace* ws = a.ws;
   const int64_t t = S.t, P0 = S.P0;
-  uint2* hmask = head_masks(a, t);
+  uint2* hmask = head_masks(a, S.rows, t);
   TileFacts T;
-  if (S.simple) tile_local<true>(a, sh, hmask, S.w0, P0, begin, end, S.d_first, S.hd, S.hs, S.e_T, true, 0u, T);
-  else tile_local<false>(a, sh, hmask, S.w0, P0, begin, end, S.d_first, S.hd, S.hs, S.e_T, true, 0u, T);
+  if (S.simple) tile_local<true>(a, S.rows, sh, hmask, S.w0, P0, begin, end, S.d_first, S.hd, S.hs, S.e_T, true, 0u, T);
+  else tile_local<false>(a, S.rows, sh, hmask, S.w0, P0, begin, end, S.d_first, S.hd, S.hs, S.e_T, true, 0u, T);
   prim::trace(t, 2);
   Pending R;
   R.valid = true;
@@ -1140,7 +1175,7 @@ JSIDX_DEV Pending start_tile(const Args& a, Shared& sh, const TileSetup& S, int6
       const uint32_t eo = (T.any_const || S.e_known) ? e_last : e;
       const uint32_t flip = S.e_known ? 0u : (e & T.qsens);
       const uint32_t qo = T.reset_any ? q0 : (q0 ^ flip);
-      const uint32_t po = p0 ^ (flip & (T.lead_pos == (uint32_t)kTileBytes - 1u ? 1u : 0u));
+      const uint32_t po = p0 ^ (flip & (T.lead_pos == S.rows * (uint32_t)kRowBytes - 1u ? 1u : 0u));
       table |= (eo | (qo << 1) | (po << 2)) << (2 + 3 * e);
     }
     R.table = table;
@@ -1219,9 +1254,9 @@ JSIDX_DEV void finish_tile(const Args& a, Shared& sh, const Pending& R, int64_t 
     // exact second pass with the incoming state now known; it writes every
     // position of the tile itself
     prim::trace_count(t, 9);
-    const TileSetup S2 = begin_tile(a, sh, t, pos_g0, begin, end, ntiles);
+    const TileSetup S2 = begin_tile(a, S.rows, sh, t, pos_g0, begin, end, ntiles);
     TileFacts T;
-    tile_local<false>(a, sh, head_masks(a, t), S2.w0, P0, begin, end, S2.d_first, S2.hd, S2.hs, s_in, false, base,
+    tile_local<false>(a, S.rows, sh, head_masks(a, S.rows, t), S2.w0, P0, begin, end, S2.d_first, S2.hd, S2.hs, s_in, false, base,
                       T);
     if (lane == 0 && !R.inc_done) {
       const uint64_t inc = make_inc(T.carry, T.reset_any, T.tail_count, epoch);
@@ -1256,7 +1291,7 @@ JSIDX_DEV void finish_tile(const Args& a, Shared& sh, const Pending& R, int64_t 
     // go to the wave's LDS rows (free now: the tail rows of the tile started
     // since were written right after it published), so that the writes below
     // never wait on a load.
-    const uint2* hmask = head_masks(a, t);
+    const uint2* hmask = head_masks(a, S.rows, t);
     uint32_t Fr[kRows];
 #pragma unroll
     for (int r = 0; r < kRows; r++) {
@@ -1304,9 +1339,11 @@ JSIDX_DEVFN void index_tiles(const Args& a) {
   const uintptr_t g0 = (base_addr + (uintptr_t)begin) & ~(uintptr_t)15;
   const int64_t pos_g0 = (int64_t)(g0 - base_addr);  // position of tile 0 byte 0
   const int64_t span = end - pos_g0;
-  const int64_t ntiles = span > 0 ? (span + kTileBytes - 1) / kTileBytes : 1;
+  const uint32_t rows = a.rows ? a.rows : rows_for(span, a.fill_waves, a.rows_tab);
+  const int64_t tb = (int64_t)rows * kRowBytes;
+  const int64_t ntiles = span > 0 ? (span + tb - 1) / tb : 1;
 
-  if ((uint64_t)ntiles > a.cap_tiles) {
+  if ((uint64_t)ntiles > a.cap_tiles || (uint64_t)ntiles * rows > a.cap_rows) {
     // Not indexed: flag every document.
     for (int64_t d = ((int64_t)prim::block() * kWaves + wv) * kThreads + lane; d < a.ndocs;
          d += (int64_t)prim::grid() * kGroupThreads) {
@@ -1331,7 +1368,7 @@ JSIDX_DEVFN void index_tiles(const Args& a) {
       const int64_t t = (int64_t)tk;
       if (t >= ntiles) break;
       prim::trace(t, 0);
-      const TileSetup S = begin_tile(a, sh, t, pos_g0, begin, end, ntiles);
+      const TileSetup S = begin_tile(a, rows, sh, t, pos_g0, begin, end, ntiles);
       const Pending cur = start_tile(a, sh, S, begin, end, ntiles, epoch);
       if (pend.valid) finish_tile(a, sh, pend, pos_g0, begin, end, ntiles, epoch);
       pend = cur;

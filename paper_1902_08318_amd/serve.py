@@ -2,24 +2,26 @@
 
 Requests are documents of a ring resident in HBM (request r is ring document
 r mod ndocs); each has a host arrival time.  The loop admits every request
-that has arrived (up to an in-flight byte budget), launches the admitted
+that has arrived (up to an in-flight byte budget) and launches the admitted
 requests as one batch -- a contiguous run of ring documents, so one offsets
-slice and one jsidx_build_batch call -- and keeps up to `depth` batches in
-flight on one stream.  A request completes when the host sees the event
-recorded after its batch; its latency is that time minus its arrival time.
+slice and one jsidx_build_batch call -- on a free stream.  Several streams,
+each with its own reserved workspace, keep batches in flight at once: work
+admitted while earlier batches run overlaps with them on the device.  A
+request completes when the host sees the event recorded after its batch; its
+latency is that time minus its arrival time.
 
 Per request there is no host work: admission is a binary search over the
 arrival times and completion a vectorised store, so the loop runs once per
 batch, not once per request.  Ring slots are reused by later requests; the
-outputs of slot d live at out_idx + offsets[d] and out_n/out_err[d], written
-again (with the same values) by every request that maps to d, in stream order.
+outputs of slot d live at out_idx + offsets[d] and out_n/out_err[d].  The
+requests in flight always span less than one turn of the ring, so no two
+batches in flight share a slot.
 """
 from __future__ import annotations
 
 import ctypes
 import gc
 import time
-from collections import deque
 from dataclasses import dataclass
 
 import numpy as np
@@ -48,33 +50,37 @@ class ServeResult:
 
 class Ring:
     """Device-resident request ring: bytes, offsets (int64, ndocs+1) and the
-    per-slot outputs (index positions, counts, flags)."""
+    per-slot outputs (index positions, counts, flags), plus the streams that
+    batches run on (each with a workspace reserved for max_batch_bytes)."""
 
-    def __init__(self, data: bytes, offsets: np.ndarray, max_batch_bytes: int, stream):
+    def __init__(self, data: bytes, offsets: np.ndarray, max_batch_bytes: int, streams):
         import torch
         dev = torch.device("cuda:0")
         self.ndocs = offsets.size - 1
         self.total = int(offsets[-1])
         self.offs_h = offsets.astype(np.int64)
+        self.max_doc = int(np.diff(self.offs_h).max()) if self.ndocs else 0
         self.bufs = torch.frombuffer(bytearray(data), dtype=torch.uint8).to(dev)
         self.offs = torch.from_numpy(self.offs_h).to(dev)
         self.out = torch.empty(max(1, self.total), dtype=torch.int32, device=dev)
         self.cnt = torch.zeros(self.ndocs, dtype=torch.int32, device=dev)
         self.err = torch.zeros(self.ndocs, dtype=torch.int32, device=dev)
-        self.stream = stream
+        self.streams = list(streams) if isinstance(streams, (list, tuple)) else [streams]
         self.max_batch_bytes = int(max_batch_bytes)
-        binding.reserve(self.max_batch_bytes, stream)
+        for st in self.streams:
+            binding.reserve(self.max_batch_bytes, st)
+        torch.cuda.synchronize()
         self._lib = binding.lib()
         self._p = (self.bufs.data_ptr(), self.offs.data_ptr(), self.out.data_ptr(), self.cnt.data_ptr(),
                    self.err.data_ptr())
-        self._s = ctypes.c_void_p(stream.cuda_stream)
+        self._s = [ctypes.c_void_p(st.cuda_stream) for st in self.streams]
 
-    def launch(self, d0: int, nd: int):
-        """Index ring documents [d0, d0 + nd) with one batched launch."""
+    def launch(self, d0: int, nd: int, k: int = 0):
+        """Index ring documents [d0, d0 + nd) with one batched launch on stream k."""
         b, o, out, cnt, err = self._p
         rc = self._lib.jsidx_build_batch(ctypes.c_void_p(b), ctypes.c_void_p(o + 8 * d0), nd,
                                          ctypes.c_void_p(out), ctypes.c_void_p(cnt + 4 * d0),
-                                         ctypes.c_void_p(err + 4 * d0), self._s)
+                                         ctypes.c_void_p(err + 4 * d0), self._s[k])
         if rc:
             binding._check(rc)
 
@@ -92,56 +98,70 @@ def poisson_arrivals(rng: np.random.Generator, rate: float, n: int) -> np.ndarra
     return np.cumsum(rng.exponential(1.0 / rate, n))
 
 
-def serve(ring: Ring, arrivals: np.ndarray, depth: int = 2, budget_bytes: int = 32 << 30) -> tuple:
+def serve(ring: Ring, arrivals: np.ndarray, budget_bytes: int = 32 << 30) -> tuple:
     """Run the loop over requests with the given arrival times (seconds from
-    the start).  Returns (latency seconds per request, elapsed seconds,
-    served bytes, batches)."""
+    the start), one batch in flight per stream of the ring.  Returns (latency
+    seconds per request, elapsed seconds, served bytes, batches)."""
     import torch
     nreq = arrivals.size
-    doc_len = np.diff(ring.offs_h)
+    ns = len(ring.streams)
     lat = np.empty(nreq)
-    inflight = deque()
-    nxt = 0        # first request not launched
-    done = 0       # requests completed
-    held = 0       # bytes admitted and not completed
+    busy = [None] * ns      # per stream: (event, r0, r1, bytes) of its batch in flight
+    events = [torch.cuda.Event() for _ in range(ns)]
+    nxt = 0                 # first request not launched
+    done = 0                # requests completed
+    held = 0                # bytes admitted and not completed
     served = 0
     batches = 0
     budget = min(int(budget_bytes), ring.total)
-    ev_pool = [torch.cuda.Event() for _ in range(depth + 1)]
-    ev_i = 0
     gc_was = gc.isenabled()
     gc.disable()
     try:
         t0 = time.perf_counter()
         while done < nreq:
+            oldest = nxt
+            free = -1
+            for k in range(ns):
+                job = busy[k]
+                if job is not None and job[0].query():
+                    tc = time.perf_counter() - t0
+                    _, r0, r1, nb = job
+                    lat[r0:r1] = tc - arrivals[r0:r1]
+                    done += r1 - r0
+                    held -= nb
+                    served += nb
+                    busy[k] = job = None
+                if job is None:
+                    if free < 0:
+                        free = k
+                elif job[1] < oldest:
+                    oldest = job[1]
+            if free < 0 or nxt >= nreq:
+                continue
             now = time.perf_counter() - t0
-            while inflight and inflight[0][0].query():
-                tc = time.perf_counter() - t0
-                _, r0, r1, nb = inflight.popleft()
-                lat[r0:r1] = tc - arrivals[r0:r1]
-                done = r1
-                held -= nb
-                served += nb
-            if len(inflight) < depth and nxt < nreq:
-                avail = int(np.searchsorted(arrivals, now, side="right"))
-                if avail > nxt:
-                    r1 = ring.batch_end(nxt, avail)
-                    d0 = nxt % ring.ndocs
-                    nb = int(ring.offs_h[d0 + (r1 - nxt)] - ring.offs_h[d0])
-                    if held == 0 or held + nb <= budget:
-                        ring.launch(d0, r1 - nxt)
-                        ev = ev_pool[ev_i]
-                        ev_i = (ev_i + 1) % len(ev_pool)
-                        ev.record(ring.stream)
-                        inflight.append((ev, nxt, r1, nb))
-                        held += nb
-                        nxt = r1
-                        batches += 1
+            avail = int(np.searchsorted(arrivals, now, side="right"))
+            if avail <= nxt:
+                continue
+            r1 = ring.batch_end(nxt, avail)
+            # in flight: requests [oldest, r1) must stay within one turn of the ring
+            r1 = min(r1, oldest + ring.ndocs)
+            if r1 <= nxt:
+                continue
+            d0 = nxt % ring.ndocs
+            nb = int(ring.offs_h[d0 + (r1 - nxt)] - ring.offs_h[d0])
+            if held and held + nb > budget:
+                continue
+            ring.launch(d0, r1 - nxt, free)
+            ev = events[free]
+            ev.record(ring.streams[free])
+            busy[free] = (ev, nxt, r1, nb)
+            held += nb
+            nxt = r1
+            batches += 1
         elapsed = time.perf_counter() - t0
     finally:
         if gc_was:
             gc.enable()
-    del doc_len
     return lat, elapsed, served, batches
 
 

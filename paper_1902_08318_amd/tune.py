@@ -1,0 +1,149 @@
+"""Autotuner of the tile size (rows of 2 KiB per tile) by input size.
+
+A launch cuts its input into tiles; one wave indexes a tile row after row.
+Small tiles shorten the serial chain of one wave and spread a small input
+over more waves; large tiles amortise the per-tile work (document table,
+carry descriptors, look-back).  Where the balance lies depends on the device,
+so it is measured: for every size class b (inputs of 2^b to 2^(b+1) bytes)
+the tuner times a batch of documents of about 1.5 * 2^b bytes, and one
+document of that size, at each candidate tile size and keeps the fastest.  The table goes to the library
+(jsidx_set_tile_rows) and to a JSON cache keyed by the GPU architecture.
+Results never depend on the tile size; only time does.
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+
+import numpy as np
+
+from . import binding
+
+CANDIDATES = (2, 4, 8, 16)
+
+
+def default_cache_path(arch: str) -> str:
+    root = os.environ.get("JSIDX_TUNE_CACHE") or os.path.join(os.path.expanduser("~"), ".cache", "jsidx")
+    return os.path.join(root, f"tile_rows_{arch}.json")
+
+
+def _arch(torch) -> str:
+    p = torch.cuda.get_device_properties(0)
+    return getattr(p, "gcnArchName", "unknown").split(":")[0]
+
+
+def _time(torch, call, stream, reps):
+    """Microseconds per launch: `reps` launches back to back between two
+    events (an event between launches would add its own cost to each)."""
+    for _ in range(3):
+        rc = call()
+        if rc:
+            binding._check(rc)
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        call()
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps * 1e3
+
+
+def autotune(data: bytes, offsets: np.ndarray, single: bytes | None = None, classes=range(12, 29),
+             reps: int = 20, log=None) -> dict:
+    """Measure every size class b on a prefix of the batch (whole documents,
+    about 1.5 * 2^b bytes) and, if given, a prefix of one large document, at
+    each candidate tile size; keep the size with the smallest sum of times
+    relative to the best of each workload (ties: the larger tile).  Classes
+    that neither input reaches keep the built-in choice.  Sets the table in
+    the library and returns it with the timings (microseconds per launch)."""
+    import ctypes
+    import torch
+    VP = ctypes.c_void_p
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream()
+    sp = VP(stream.cuda_stream)
+    lib = binding.lib()
+    total = int(offsets[-1])
+    bufs = torch.frombuffer(bytearray(data), dtype=torch.uint8).to(dev)
+    offs = torch.from_numpy(offsets.astype(np.int64)).to(dev)
+    nd_all = offsets.size - 1
+    cap = max(total, len(single) if single else 0)
+    out = torch.empty(max(1, cap), dtype=torch.int32, device=dev)
+    cnt = torch.empty(max(1, nd_all), dtype=torch.int32, device=dev)
+    err = torch.empty(max(1, nd_all), dtype=torch.int32, device=dev)
+    sbuf = torch.frombuffer(bytearray(single), dtype=torch.uint8).to(dev) if single else None
+    binding.reserve(cap, stream)
+    b0, o0, out0, c0, e0 = bufs.data_ptr(), offs.data_ptr(), out.data_ptr(), cnt.data_ptr(), err.data_ptr()
+
+    def batch_call(nd):
+        return lambda: lib.jsidx_build_batch(VP(b0), VP(o0), nd, VP(out0), VP(c0), VP(e0), sp)
+
+    def single_call(n):
+        return lambda: lib.jsidx_build(VP(sbuf.data_ptr()), n, VP(out0), VP(c0), VP(e0), sp)
+
+    table = [0] * 64
+    timings = {}
+    try:
+        binding.set_tile_rows([])
+        _time(torch, batch_call(nd_all), stream, 10)  # clocks up, memory touched
+        for b in classes:
+            work = {}
+            want = int(1.5 * (1 << b))
+            nd = int(np.searchsorted(offsets, offsets[0] + want, side="right")) - 1
+            nd = max(1, min(nd, nd_all))
+            got = int(offsets[nd] - offsets[0])
+            if (1 << b) <= got < (1 << (b + 1)) - 16:
+                work["batch"] = (batch_call(nd), got, nd)
+            if single:
+                n = min(len(single), want)
+                if (1 << b) <= n < (1 << (b + 1)) - 16:
+                    work["single"] = (single_call(n), n, 1)
+            if not work:
+                continue
+            res = {k: {} for k in work}
+            for r in CANDIDATES:
+                t = [0] * 64
+                t[b] = r
+                binding.set_tile_rows(t)
+                for k, (call, _, _) in work.items():
+                    res[k][r] = _time(torch, call, stream, reps)
+            score = {r: sum(res[k][r] / min(res[k].values()) for k in work) for r in CANDIDATES}
+            best = min(CANDIDATES, key=lambda r: (score[r], -r))
+            table[b] = best
+            timings[b] = {k: {"bytes": work[k][1], "docs": work[k][2],
+                              "us": {str(r): round(v, 2) for r, v in res[k].items()}} for k in work}
+            timings[b]["rows"] = best
+            if log:
+                log(f"tune: class 2^{b}: " + "; ".join(
+                    f"{k} ({work[k][1]} B): " + " ".join(f"{r}:{res[k][r]:.1f}" for r in CANDIDATES) for k in work)
+                    + f" us -> {best} rows")
+    finally:
+        binding.release(stream)
+    binding.set_tile_rows(table)
+    return {"arch": _arch(torch), "table": table, "timings": timings, "when": time.strftime("%Y-%m-%d %H:%M:%S")}
+
+
+def save(result: dict, path: str | None = None) -> str:
+    path = path or default_cache_path(result["arch"])
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w") as f:
+        json.dump(result, f, indent=1)
+    return path
+
+
+def load(path: str | None = None) -> dict | None:
+    """Apply a cached table for this device's architecture, if there is one."""
+    import torch
+    arch = _arch(torch)
+    path = path or default_cache_path(arch)
+    try:
+        with open(path) as f:
+            res = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if res.get("arch") != arch or len(res.get("table", [])) != 64:
+        return None
+    binding.set_tile_rows(res["table"])
+    return res

@@ -24,10 +24,12 @@ extern "C" {
 //   granule_lo/hi: the bytes the kernel may read (the aligned 16-byte granules
 //   overlapping the input).  Returns the number of out-of-range accesses.
 //   ws_state: persistent workspace (caller allocated, zeroed once) so that
-//   several launches can reuse it like the real library does.
+//   several launches can reuse it like the real library does; cap_tiles
+//   counts largest tiles.
+//   rows: rows per tile (0: the kernel picks them for the launch's waves).
 long emu_run(const uint8_t* base, const uint64_t* offsets, uint64_t len, uint32_t ndocs, uint32_t* out_idx,
              uint64_t out_cap, uint32_t* out_n, uint32_t* out_err, int nblocks, void* ws_mem, uint64_t cap_tiles,
-             const uint8_t* granule_lo, const uint8_t* granule_hi) {
+             uint32_t rows, const uint8_t* granule_lo, const uint8_t* granule_hi) {
   prim::EmuEnv env;
   env.reads[env.nreads++] = {granule_lo, granule_hi};
   if (offsets) env.reads[env.nreads++] = {offsets, offsets + ndocs + 1};
@@ -46,10 +48,14 @@ long emu_run(const uint8_t* base, const uint64_t* offsets, uint64_t len, uint32_
   a.out_n = out_n;
   a.out_err = out_err;
   a.ws = (Workspace*)ws_mem;
-  a.cap_tiles = cap_tiles;
+  a.cap_tiles = desc_slots(cap_tiles);
+  a.cap_rows = cap_tiles * (uint64_t)kRows;
 
   // nblocks counts waves; they run as whole workgroups of kWaves waves
   const int ngroups = (nblocks + kWaves - 1) / kWaves;
+  a.rows = rows;
+  a.fill_waves = (uint32_t)(ngroups * kWaves);
+  for (int i = 0; i < 4; i++) a.rows_tab[i] = 0;
   std::vector<prim::GroupCtx*> groups;
   for (int b = 0; b < ngroups; b++) groups.push_back(new prim::GroupCtx(kGroupThreads));
   std::vector<std::thread> th;
@@ -72,5 +78,6 @@ long emu_run(const uint8_t* base, const uint64_t* offsets, uint64_t len, uint32_
 
 uint64_t emu_ws_bytes(uint64_t cap_tiles) { return workspace_bytes(cap_tiles); }
 uint32_t emu_tile_bytes() { return (uint32_t)kTileBytes; }
+uint32_t emu_pick_rows(int64_t span, uint64_t waves) { return pick_rows(span, waves); }
 
 }  // extern "C"

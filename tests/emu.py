@@ -55,11 +55,13 @@ def load(block_tiles: int | None = None):
     lib = ctypes.CDLL(path)
     vp = ctypes.c_void_p
     lib.emu_run.argtypes = [vp, vp, ctypes.c_uint64, ctypes.c_uint32, vp, ctypes.c_uint64, vp, vp,
-                            ctypes.c_int, vp, ctypes.c_uint64, vp, vp]
+                            ctypes.c_int, vp, ctypes.c_uint64, ctypes.c_uint32, vp, vp]
     lib.emu_run.restype = ctypes.c_long
     lib.emu_ws_bytes.argtypes = [ctypes.c_uint64]
     lib.emu_ws_bytes.restype = ctypes.c_uint64
     lib.emu_tile_bytes.restype = ctypes.c_uint32
+    lib.emu_pick_rows.argtypes = [ctypes.c_int64, ctypes.c_uint64]
+    lib.emu_pick_rows.restype = ctypes.c_uint32
     if block_tiles is None:
         _lib = lib
     _libs[block_tiles] = lib
@@ -67,7 +69,12 @@ def load(block_tiles: int | None = None):
 
 
 def tile_bytes() -> int:
+    """Bytes of the largest tile."""
     return int(load().emu_tile_bytes())
+
+
+def pick_rows(span: int, waves: int) -> int:
+    return int(load().emu_pick_rows(span, waves))
 
 
 class Workspace:
@@ -86,13 +93,14 @@ def _aligned(nbytes: int, shift: int) -> tuple[np.ndarray, int]:
 
 
 def run(data: bytes, offsets=None, nblocks: int = 2, misalign: int = 0, ws: Workspace | None = None,
-        garbage: int = 0xEE, block_tiles: int | None = None):
+        garbage: int = 0xEE, block_tiles: int | None = None, rows: int | None = None):
     """Index `data` (one document if offsets is None, else a batch).
 
     misalign: the buffer starts this many bytes past a 64-byte boundary.  The
     bytes around the input inside its 16-byte granules are filled with
     `garbage` so that any influence of them shows up.
     block_tiles: look-back block size of the build (None: the library's).
+    rows: rows per tile (None: the largest tile; 0: the kernel picks them).
     Returns (out_idx, out_n, out_err, violations).
     """
     if ws is not None:
@@ -123,5 +131,6 @@ def run(data: bytes, offsets=None, nblocks: int = 2, misalign: int = 0, ws: Work
         ws = Workspace(need, block_tiles)
     v = lib.emu_run(ctypes.c_void_p(base), offs.ctypes.data if offs is not None else None, n, ndocs,
                     out_idx.ctypes.data, out_cap, out_n.ctypes.data, out_err.ctypes.data, nblocks,
-                    ws.mem.ctypes.data, ws.cap, ctypes.c_void_p(glo), ctypes.c_void_p(ghi))
+                    ws.mem.ctypes.data, ws.cap, tile_bytes() // 2048 if rows is None else rows,
+                    ctypes.c_void_p(glo), ctypes.c_void_p(ghi))
     return out_idx, out_n, out_err, int(v)

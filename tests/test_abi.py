@@ -54,3 +54,21 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(binding, "_LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(binding.JsidxError):
         binding.lib()
+
+
+def test_tile_rows_table_is_validated_on_the_host():
+    """jsidx_set_tile_rows takes 0 (built-in) or 2/4/8/16 per size class and
+    rejects anything else without changing the table (no device needed)."""
+    import paper_1902_08318_amd as jx
+    lib = jx.binding.lib()
+    good = (ctypes.c_uint8 * 64)(*([0] * 10 + [2, 4, 8, 16] + [0] * 50))
+    assert lib.jsidx_set_tile_rows(good, 64) == 0
+    for bad in (1, 3, 5, 32, 255):
+        t = (ctypes.c_uint8 * 1)(bad)
+        assert lib.jsidx_set_tile_rows(t, 1) == -1
+    assert lib.jsidx_set_tile_rows(good, 65) == -1
+    assert lib.jsidx_set_tile_rows(None, 3) == -1
+    assert lib.jsidx_set_tile_rows(None, 0) == 0
+    with pytest.raises(jx.JsidxError):
+        jx.set_tile_rows([3])
+    jx.set_tile_rows([])

@@ -234,3 +234,30 @@ def test_reserved_capacity_is_enforced_without_sync():
         assert want == 11
         assert torch.all(n == want).item() and torch.all(err == 0).item()
         jx.release(s)
+
+
+@pytest.mark.parametrize("rows", [2, 4, 8, 16])
+def test_every_tile_size(rows):
+    """The tile size is a tuning choice (jsidx_set_tile_rows): with every
+    launch forced to `rows` rows per tile, single documents (several tiles,
+    backslash runs over tile edges) and batches still match the oracle."""
+    import paper_1902_08318_amd as jx
+    from paper_1902_08318_amd import synth
+    _say(f"case: tile rows forced to {rows}")
+    jx.set_tile_rows([rows] * 64)
+    try:
+        assert jx.tile_rows(1 << 20) == rows
+        rng = np.random.default_rng(100 + rows)
+        tb = 2048 * rows
+        for k in range(4):
+            assert_single_matches(_soup(rng, int(rng.integers(tb, 9 * tb))), k * 5, f"rows {rows} soup {k}")
+        for run in (tb - 1, tb + 1, 3 * tb + 2, 4097):
+            d = b'["' + b"x" * (tb - 3) + b"\\" * run + b'"' + b'",1] "z" [1]'
+            assert_single_matches(d, 1, f"rows {rows} run {run}")
+        doc = synth.gen_c1(50 + rows, 6 << 20, pool=64).data
+        assert_single_matches(doc, 3, f"rows {rows} C1-like 6 MiB")
+        data, offs, _ = synth.gen_c3(60 + rows, ndocs=3000, pool=100)
+        assert_batch_matches(data, offs, 5, f"rows {rows} batch")
+    finally:
+        jx.set_tile_rows([])
+    assert jx.diag() == 0

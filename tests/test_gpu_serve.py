@@ -1,6 +1,7 @@
-"""The continuous-batching serving loop: every request completes, latencies are
-positive, and the outputs of every ring slot equal the oracle's for that
-document (each slot is rewritten by every request that maps to it)."""
+"""The continuous-batching serving loop on three streams: every request
+completes, latencies are positive, and each request's result in the mix (its
+ring slot, written by that request only) equals the result of indexing the
+document alone (jsidx_build on its own buffer) and the oracle's."""
 import sys
 
 import numpy as np
@@ -11,30 +12,70 @@ import oracle
 pytestmark = pytest.mark.gpu
 
 
-def test_serving_loop_completes_and_matches_oracle():
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def test_each_result_is_the_same_alone_and_in_the_mix():
     import torch
+    import paper_1902_08318_amd as jx
     from paper_1902_08318_amd import serve, synth
     data, offs = synth.gen_c4(7, ring_bytes=24 << 20, hi=2 << 20, pool=60)
-    print(f"case: serving loop ring {len(data)} bytes, {offs.size - 1} docs", flush=True)
-    sys.stdout.flush()
-    s = torch.cuda.Stream()
-    with torch.cuda.stream(s):
-        ring = serve.Ring(data, offs, 4 << 20, s)
-        sat = serve.saturated_rate(ring, seconds=0.05)
-        assert sat > 0
-        res = serve.run_load(ring, sat, 0.5, 0.2, 5, min_requests=3 * ring.ndocs)
-    s.synchronize()
-    assert res.requests >= 3 * ring.ndocs
-    assert res.served_bytes > 0 and res.batches > 0
+    nd = offs.size - 1
+    _say(f"case: serving mix, ring {len(data)} bytes, {nd} docs, 3 streams")
+    streams = [torch.cuda.Stream() for _ in range(3)]
+    ring = serve.Ring(data, offs, 4 << 20, streams)
+    sat = serve.saturated_rate(ring, seconds=0.05)
+    assert sat > 0
+    ring.out.fill_(-1)
+    ring.cnt.fill_(-1)
+    ring.err.fill_(-1)
+    torch.cuda.synchronize()
+    # one turn of the ring at 90% of saturation: every slot holds exactly one
+    # request's result, computed while other batches ran beside it
+    rate = 0.9 * sat / (len(data) / nd)
+    arr = serve.poisson_arrivals(np.random.default_rng(5), rate, nd)
+    lat, el, served, batches = serve.serve(ring, arr)
+    torch.cuda.synchronize()
+    assert served == len(data) and batches > 1
+    assert np.all(lat > 0)
+    mix_n = ring.cnt.cpu().numpy().view(np.uint32)
+    mix_e = ring.err.cpu().numpy().view(np.uint32)
+    mix_i = ring.out[:len(data)].cpu().numpy().view(np.uint32)
+    oi, on, oe = oracle.index_batch(np.frombuffer(data, dtype=np.uint8), offs)
+    assert np.array_equal(mix_n, on) and np.array_equal(mix_e, oe)
+    _say("case: each document alone")
+    for d in range(nd):
+        a, b = int(offs[d]), int(offs[d + 1])
+        alone, n, e = jx.index(ring.bufs[a:b].clone())
+        assert n == mix_n[d] and e == mix_e[d], f"doc {d}: alone ({n}, {e:#x}) vs mix ({mix_n[d]}, {mix_e[d]:#x})"
+        al = alone.cpu().numpy().view(np.uint32)
+        assert np.array_equal(al, mix_i[a:a + n]), f"doc {d}: positions differ alone vs in the mix"
+        assert np.array_equal(al, oi[a:a + on[d]]), f"doc {d}: positions differ from the oracle"
+    for st in streams:
+        assert jx.diag(st) == 0
+
+
+def test_serving_loop_over_many_turns_of_the_ring():
+    import torch
+    import paper_1902_08318_amd as jx
+    from paper_1902_08318_amd import serve, synth
+    data, offs = synth.gen_c4(8, ring_bytes=8 << 20, hi=1 << 20, pool=40)
+    _say(f"case: serving loop, ring {len(data)} bytes, {offs.size - 1} docs, many turns")
+    streams = [torch.cuda.Stream() for _ in range(2)]
+    ring = serve.Ring(data, offs, 2 << 20, streams)
+    sat = serve.saturated_rate(ring, seconds=0.05)
+    res = serve.run_load(ring, sat, 0.5, 0.2, 6, min_requests=5 * ring.ndocs)
+    torch.cuda.synchronize()
+    assert res.requests >= 5 * ring.ndocs and res.batches > 0
     assert 0 < res.p50_us <= res.p99_us <= res.max_us
     oi, on, oe = oracle.index_batch(np.frombuffer(data, dtype=np.uint8), offs)
-    gn = ring.cnt.cpu().numpy().view(np.uint32)
-    ge = ring.err.cpu().numpy().view(np.uint32)
-    assert np.array_equal(gn, on)
-    assert np.array_equal(ge, oe)
+    assert np.array_equal(ring.cnt.cpu().numpy().view(np.uint32), on)
+    assert np.array_equal(ring.err.cpu().numpy().view(np.uint32), oe)
     gi = ring.out[:len(data)].cpu().numpy().view(np.uint32)
     for d in range(ring.ndocs):
         a, n = int(offs[d]), int(on[d])
         assert np.array_equal(gi[a:a + n], oi[a:a + n]), f"slot {d} differs"
-    import paper_1902_08318_amd as jx
-    assert jx.diag(s) == 0
+    for st in streams:
+        assert jx.diag(st) == 0

@@ -10,18 +10,19 @@ import oracle
 TB = emu.tile_bytes()
 
 
-def _check_single(d, nblocks, misalign, block_tiles=None):
-    idx, n, err, viol = emu.run(d, nblocks=nblocks, misalign=misalign, block_tiles=block_tiles)
+def _check_single(d, nblocks, misalign, block_tiles=None, rows=None):
+    idx, n, err, viol = emu.run(d, nblocks=nblocks, misalign=misalign, block_tiles=block_tiles, rows=rows)
     oi, oe = oracle.index(d)
     assert viol == 0
     assert n[0] == len(oi) and err[0] == oe
     assert np.array_equal(idx[:n[0]], oi)
 
 
-def _check_batch(docs, nblocks, misalign, lead, block_tiles=None):
+def _check_batch(docs, nblocks, misalign, lead, block_tiles=None, rows=None):
     data = b"\x00" * lead + b"".join(docs)
     offs = np.concatenate([[lead], lead + np.cumsum([len(x) for x in docs])]).astype(np.uint64)
-    idx, n, err, viol = emu.run(data, offsets=offs, nblocks=nblocks, misalign=misalign, block_tiles=block_tiles)
+    idx, n, err, viol = emu.run(data, offsets=offs, nblocks=nblocks, misalign=misalign, block_tiles=block_tiles,
+                                rows=rows)
     oi, on, oe = oracle.index_batch(np.frombuffer(data, dtype=np.uint8), offs)
     assert viol == 0
     assert np.array_equal(n, on) and np.array_equal(err, oe)
@@ -94,3 +95,39 @@ def test_two_tile_tickets():
     d = synth.gen_c1(7, 2 << 20, pool=64).data
     for nb in (8, 16):
         _check_single(d, nb, 5)
+
+
+def test_pick_rows():
+    """Untuned, a launch takes the largest tile that still makes a tile for
+    every eighth wave, between 2 and 16 rows of 2 KiB."""
+    assert emu.pick_rows(0, 8) == 2
+    assert emu.pick_rows(256 << 20, 4096) == 16
+    assert emu.pick_rows(16 << 20, 4096) == 16
+    assert emu.pick_rows((16 << 20) - 1, 4096) == 8
+    assert emu.pick_rows(12 << 20, 4096) == 8
+    assert emu.pick_rows(3 << 20, 4096) == 2
+    assert emu.pick_rows(5 << 20, 4096) == 4
+    assert emu.pick_rows(12871, 4096) == 2
+    assert emu.pick_rows(300 << 10, 64) == 16
+    assert emu.pick_rows(100 << 10, 64) == 4
+
+
+@pytest.mark.parametrize("rows", [2, 4, 8, 0])
+def test_smaller_tiles(rows):
+    """Tiles of fewer rows (a launch over a small input uses them): documents
+    over several tiles, backslash runs across tile edges, batches; rows 0 lets
+    the kernel pick them for the launch's waves."""
+    rng = np.random.default_rng(10 + rows)
+    tb = 2048 * (rows or 2)
+    for _ in range(2):
+        _check_single(_soup(rng, int(rng.integers(tb, 6 * tb))), int(rng.integers(1, 12)), int(rng.integers(0, 16)),
+                      rows=rows)
+    for run, nxt in ((tb, b'"'), (tb + 1, b'"'), (2 * tb + 5, b"a"), (5 * 1024 + 3, b'"')):
+        d = b'["' + b"x" * (tb - 2) + b"\\" * run + nxt + b'",1] "z" [1]'
+        _check_single(d, 3, 0, rows=rows)
+    docs = []
+    for _ in range(60):
+        r = rng.random()
+        L = 0 if r < 0.15 else (1 if r < 0.25 else int(rng.integers(2, 3000 if r < 0.9 else 3 * tb)))
+        docs.append(_soup(rng, L))
+    _check_batch(docs, 20, 3, 7, rows=rows)

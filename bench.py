@@ -42,9 +42,10 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def profiled_traffic():
+def profiled_traffic(rows: int):
     """HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)
-    from the committed C1 profile, if it was taken on the current kernel."""
+    from the committed C1 profile, if it was taken on the current kernel with
+    the same tile size."""
     try:
         text = open(PROFILE).read()
     except OSError:
@@ -52,7 +53,10 @@ def profiled_traffic():
     import re
     m_hash = re.search(r"sha256\[:16\]: `([0-9a-f]{16})`", text)
     m_bytes = re.search(r"traffic_bytes_per_launch: (\d+)", text)
+    m_rows = re.search(r"(\d+) rows of 2 KiB per tile", text)
     if not m_hash or not m_bytes or m_hash.group(1) != kernel_hash():
+        return None
+    if not m_rows or int(m_rows.group(1)) != rows:
         return None
     return int(m_bytes.group(1))
 
@@ -336,6 +340,7 @@ def main():
         return
     log(f"timing {args.workload}: {len(c1.data)} bytes, {args.steps} steps")
     r1 = time_single(jx, torch, c1.data, args.steps, args.warmup)
+    rows1 = jx.tile_rows(len(c1.data))  # device buffers are 16-byte aligned: the span is the length
     value = r1["N"] * args.steps / (r1["ms_total"] / 1e3) / 1e9
     alg_bytes = r1["N"] + 4 * r1["S"]
     achieved = alg_bytes / (r1["ms_per_launch"] / 1e3) / 1e9
@@ -355,10 +360,11 @@ def main():
         "config": {"workload": "C1: one minified twitter-like JSON document, seed 1" if args.workload == "c1"
                    else "C2: one pretty-printed numeric (canada-like) JSON document, seed 2",
                    "bytes": r1["N"], "index_entries": r1["S"], "bytes_per_entry": round(r1["N"] / max(1, r1["S"]), 2),
-                   "flags": r1["flags"], "launch_ms": r1["launch_ms"], "end_to_end_ms": r1["e2e_ms"]},
+                   "flags": r1["flags"], "tile_rows": rows1, "launch_ms": r1["launch_ms"],
+                   "end_to_end_ms": r1["e2e_ms"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": profiled_traffic() if args.workload == "c1" else None},
+                     "traffic": profiled_traffic(rows1) if args.workload == "c1" else None},
     }
     out["roofline"]["copy_ceiling"] = copy_ceiling(torch)
     extra = {}

@@ -349,7 +349,8 @@ JSIDX_DEV void write_row(uint32_t* out, uint64_t lim, uint32_t* cc, uint32_t F, 
 // lies inside the input (every byte belongs to document hd, which starts at
 // hs < P0), the escape state entering the tile is known, and defer is set.
 template <bool SIMPLE>
-JSIDX_DEV void tile_local(const Args& a, uint32_t rows, Shared& sh, uint2* hmask, const uint32_t* first_row, int64_t P0,
+JSIDX_DEV void tile_local(const Args& a, uint32_t rows, Shared& sh, uint2* hmask, const uint32_t* first_row,
+                          int64_t P0,
                           int64_t begin, int64_t end, int64_t d_first, int32_t hd, int64_t hs, uint32_t st_in,
                           bool defer, uint32_t head_base, TileFacts& T) {
   const uint32_t lane = prim::lane();
@@ -771,8 +772,12 @@ JSIDX_DEV LaneFold fold_unpack(uint32_t f, uint32_t c0, uint32_t c1) {
 // All block words are cleared at the end of every launch.
 constexpr uint64_t kAggEpochMask = 31;
 JSIDX_DEV uint64_t* block_desc(const Args& a) { return a.ws->desc + a.cap_tiles; }
-JSIDX_DEV uint2* head_masks(const Args& a, uint32_t rows, int64_t t) {
-  return reinterpret_cast<uint2*>(reinterpret_cast<uint8_t*>(a.ws) + mask_offset(a.cap_tiles)) + t * ((int64_t)rows * kThreads);
+// Head-region masks: one slot of rows * kThreads pairs per tile, row after
+// row (a tile writes and later reads back one contiguous slot, which stays
+// in the caches between the two).
+JSIDX_DEV uint2* head_masks(const Args& a, int64_t t, uint32_t rows) {
+  return reinterpret_cast<uint2*>(reinterpret_cast<uint8_t*>(a.ws) + mask_offset(a.cap_tiles)) +
+         t * ((int64_t)rows * kThreads);
 }
 JSIDX_DEV uint32_t* block_count(const Args& a) {
   return reinterpret_cast<uint32_t*>(block_desc(a) + 3 * blocks_for_tiles(a.cap_tiles));
@@ -1157,7 +1162,7 @@ JSIDX_DEV Pending start_tile(const Args& a, Shared& sh, const TileSetup& S, int6
   const uint32_t lane = prim::lane();
   Workspace* ws = a.ws;
   const int64_t t = S.t, P0 = S.P0;
-  uint2* hmask = head_masks(a, S.rows, t);
+  uint2* hmask = head_masks(a, t, S.rows);
   TileFacts T;
   if (S.simple) tile_local<true>(a, S.rows, sh, hmask, S.w0, P0, begin, end, S.d_first, S.hd, S.hs, S.e_T, true, 0u, T);
   else tile_local<false>(a, S.rows, sh, hmask, S.w0, P0, begin, end, S.d_first, S.hd, S.hs, S.e_T, true, 0u, T);
@@ -1256,7 +1261,7 @@ JSIDX_DEV void finish_tile(const Args& a, Shared& sh, const Pending& R, int64_t 
     prim::trace_count(t, 9);
     const TileSetup S2 = begin_tile(a, S.rows, sh, t, pos_g0, begin, end, ntiles);
     TileFacts T;
-    tile_local<false>(a, S.rows, sh, head_masks(a, S.rows, t), S2.w0, P0, begin, end, S2.d_first, S2.hd, S2.hs, s_in, false, base,
+    tile_local<false>(a, S.rows, sh, head_masks(a, t, S.rows), S2.w0, P0, begin, end, S2.d_first, S2.hd, S2.hs, s_in, false, base,
                       T);
     if (lane == 0 && !R.inc_done) {
       const uint64_t inc = make_inc(T.carry, T.reset_any, T.tail_count, epoch);
@@ -1291,7 +1296,7 @@ JSIDX_DEV void finish_tile(const Args& a, Shared& sh, const Pending& R, int64_t 
     // go to the wave's LDS rows (free now: the tail rows of the tile started
     // since were written right after it published), so that the writes below
     // never wait on a load.
-    const uint2* hmask = head_masks(a, S.rows, t);
+    const uint2* hmask = head_masks(a, t, S.rows);
     uint32_t Fr[kRows];
 #pragma unroll
     for (int r = 0; r < kRows; r++) {

@@ -34,11 +34,17 @@ PROFILE = os.path.join(ROOT, "profiles", "index_kernel_c1_256MiB.md")
 
 
 def kernel_hash() -> str:
+    """sha256[:16] of the kernel sources with comments and white space removed
+    (a comment edit does not change the kernel)."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_1902_08318_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1902_08318_amd", "csrc", f)) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

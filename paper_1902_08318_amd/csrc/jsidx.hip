@@ -3,18 +3,19 @@
 // of include/jsidx.h.
 //
 // One persistent launch indexes one document or a batch.  Work is cut into
-// tiles of kTileBytes of the concatenated input; a workgroup of 256 lanes
-// takes tiles in order from a ticket counter.  Inside a tile every lane owns
-// one 32-byte segment per row and builds 32-bit class masks for it (Sec.
-// 3.1.2); escapes (Fig. 3), string ranges (Fig. 4) and pseudo-structural
-// bytes (Fig. 5) are computed per segment, with the carries between segments
-// resolved by wave ballots and a small LDS scan, and the carries between tiles
-// by a decoupled look-back over per-tile descriptors (the paper's per-block
-// carries, elided in its footnote, become a scan).  Document starts reset all
-// carries, so a batch of documents is one segmented scan.  Set bits are
-// flattened into uint32 positions per document (Sec. 3.1.4): a popcount per
-// segment, a segmented prefix sum over the tile and the look-back gives each
-// bit its output slot.
+// tiles of 2 to 16 rows of 2 KiB of the concatenated input (the tile size is
+// chosen per launch from the input size); each wave of a workgroup of 8
+// independent waves takes tiles in increasing order from a ticket counter.
+// Inside a tile every lane owns one 32-byte segment per row and builds
+// 32-bit class masks for it from bit planes (Sec. 3.1.2); escapes (Fig. 3),
+// string ranges (Fig. 4) and pseudo-structural bytes (Fig. 5) are computed
+// per segment, with the carries between segments resolved by wave ballots
+// and the carries between tiles by a decoupled look-back over per-tile and
+// per-block descriptors (the paper's per-block carries, elided in its
+// footnote, become a scan).  Document starts reset all carries, so a batch
+// of documents is one segmented scan.  Set bits are flattened into uint32
+// positions per document (Sec. 3.1.4): a popcount per segment and a wave
+// prefix sum give each bit its slot; the look-back gives each tile its base.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 

@@ -46,6 +46,19 @@ static_assert(kRows >= kMinRows && kRows % kMinRows == 0 && (kRows & (kRows - 1)
 constexpr int kDocCap = 256;                   // documents per tile held in LDS
 constexpr int kScrub = 4096;                   // descriptors cleared per launch
 constexpr int kEscSteps = 4;                   // backslash run scanned back: 4 x 1 KiB
+// Rows of input in flight ahead of the row being classified.
+#ifndef JSIDX_PREFETCH_ROWS
+#define JSIDX_PREFETCH_ROWS 1
+#endif
+// Flatten through LDS: a row's positions are gathered in LDS and written out
+// with coalesced stores (rows of at most kStage positions).
+#ifndef JSIDX_STAGED_FLATTEN
+#define JSIDX_STAGED_FLATTEN 1
+#endif
+constexpr int kStage = 512;
+#ifndef JSIDX_STAGE_LANE
+#define JSIDX_STAGE_LANE 8
+#endif
 // Tiles per look-back block (at most 4 per lane); test builds shrink it to
 // reach many blocks with small inputs.
 #ifndef JSIDX_BLOCK_TILES
@@ -189,6 +202,9 @@ struct Shared {
   // document's start and its count before the row
   int64_t tr_doff[kRows];
   uint32_t tr_cc[kRows];
+#if JSIDX_STAGED_FLATTEN
+  uint32_t stage[kStage];  // one row's positions on their way out
+#endif
 };
 
 struct GroupShared {
@@ -313,12 +329,34 @@ JSIDX_DEV void load_segment(const Args& a, int64_t pos, int64_t begin, int64_t e
 // at document offset rel) at ranks from *cc plus the lanes below; *cc
 // advances by the row's total.  Ranks at or past lim are not written (only a
 // look-back that gave up could produce them).
-JSIDX_DEV void write_row(uint32_t* out, uint64_t lim, uint32_t* cc, uint32_t F, uint32_t rel) {
+JSIDX_DEV void write_row(Shared& sh, uint32_t* out, uint64_t lim, uint32_t* cc, uint32_t F, uint32_t rel) {
   const uint32_t n = (uint32_t)__builtin_popcount(F);
   const uint32_t incl = prim::incl_scan(n);
   const uint32_t row_n = prim::readlane(incl, 63);
   uint32_t kk = *cc + incl - n;
   const bool checked = (uint64_t)*cc + row_n > lim;
+#if JSIDX_STAGED_FLATTEN
+  // Direct writes take as many store instructions as the busiest lane has
+  // positions, each touching several cache lines; through LDS they take one
+  // coalesced store per 64 positions.  Rows where some lane holds more than
+  // JSIDX_STAGE_LANE positions go through LDS.
+  if (!checked && row_n <= (uint32_t)kStage && prim::ballot(n > (uint32_t)JSIDX_STAGE_LANE) != 0ull) {
+    // each lane puts its positions at their ranks in LDS, then the wave
+    // writes the row's positions out as consecutive words
+    uint32_t k = incl - n;
+    while (F) {
+      const uint32_t j = (uint32_t)__builtin_ctz(F);
+      F &= F - 1u;
+      sh.stage[k++] = rel + j;
+    }
+    prim::wave_sync();
+    const uint32_t base = *cc;
+    for (uint32_t i = prim::lane(); i < row_n; i += (uint32_t)kThreads) prim::st_out(out + base + i, sh.stage[i]);
+    prim::wave_sync();  // the next row reuses the buffer
+    *cc += row_n;
+    return;
+  }
+#endif
   *cc += row_n;
   if (!checked) {
     while (F) {
@@ -379,6 +417,10 @@ JSIDX_DEV void tile_local(const Args& a, uint32_t rows, Shared& sh, uint2* hmask
   } else {
     load_segment<SIMPLE>(a, P0 + (int64_t)lane * kSegBytes, begin, end, wn);
   }
+#if JSIDX_PREFETCH_ROWS > 1
+  uint32_t wn2[8];
+  if (rows > 1) load_segment<SIMPLE>(a, P0 + kRowBytes + (int64_t)lane * kSegBytes, begin, end, wn2);
+#endif
 #pragma unroll 1
   for (int r = 0; r < (int)rows; r++) {
     const int32_t rel = r * kRowBytes + (int32_t)lane * kSegBytes;  // tile-relative
@@ -386,7 +428,13 @@ JSIDX_DEV void tile_local(const Args& a, uint32_t rows, Shared& sh, uint2* hmask
     uint32_t w[8];
 #pragma unroll
     for (int k = 0; k < 8; k++) w[k] = wn[k];
+#if JSIDX_PREFETCH_ROWS > 1
+#pragma unroll
+    for (int k = 0; k < 8; k++) wn[k] = wn2[k];
+    if (r + 2 < (int)rows) load_segment<SIMPLE>(a, pos + 2 * kRowBytes, begin, end, wn2);  // two rows ahead
+#else
     if (r + 1 < (int)rows) load_segment<SIMPLE>(a, pos + kRowBytes, begin, end, wn);  // prefetch
+#endif
 
     // documents: starts in this segment (D), start right after it (d32),
     // document holding byte 0 (head), valid bytes (V)
@@ -554,7 +602,7 @@ JSIDX_DEV void tile_local(const Args& a, uint32_t rows, Shared& sh, uint2* hmask
         T.tail_rows |= 1u << r;
         cc += wave_sum((uint32_t)__builtin_popcount(F0));
       } else {
-        write_row(a.out_idx + doff, (uint64_t)(end - doff), &cc, F0, (uint32_t)(pos - doff));
+        write_row(sh, a.out_idx + doff, (uint64_t)(end - doff), &cc, F0, (uint32_t)(pos - doff));
       }
       continue;
     }
@@ -1230,7 +1278,7 @@ JSIDX_DEV Pending start_tile(const Args& a, Shared& sh, const TileSetup& S, int6
     const int64_t doff = sh.tr_doff[r];
     uint32_t cc = sh.tr_cc[r];
     const int64_t pos = P0 + (int64_t)r * kRowBytes + (int64_t)lane * kSegBytes;
-    write_row(a.out_idx + doff, (uint64_t)(end - doff), &cc, sh.hF[r][lane], (uint32_t)(pos - doff));
+    write_row(sh, a.out_idx + doff, (uint64_t)(end - doff), &cc, sh.hF[r][lane], (uint32_t)(pos - doff));
   }
   prim::wave_sync();
   return R;
@@ -1312,7 +1360,7 @@ JSIDX_DEV void finish_tile(const Args& a, Shared& sh, const Pending& R, int64_t 
     uint32_t cc = base;
 #pragma unroll 1
     for (uint32_t r = 0; r < R.head_rows; r++)
-      write_row(out, lim, &cc, sh.hF[r][lane], rel0 + r * (uint32_t)kRowBytes);
+      write_row(sh, out, lim, &cc, sh.hF[r][lane], rel0 + r * (uint32_t)kRowBytes);
     if (R.he_valid && lane == 0) {
       uint32_t err = 0;
       if (R.he_u | uT) err |= JSIDX_ERR_UTF8;

@@ -31,7 +31,16 @@ constexpr int kThreads = 64;  // lanes per wave; a wave owns one tile at a time
 #endif
 constexpr int kWaves = JSIDX_GROUP_WAVES;
 constexpr int kGroupThreads = kWaves * kThreads;
-constexpr int kTicketTiles = 2;  // consecutive tiles per ticket (when every wave gets at least 2 tiles)
+// Consecutive tiles per ticket (when every wave gets at least that many).
+// A wave finishes a tile after starting the next, so with two tiles per
+// ticket both are published before the wave first waits.  With more, a
+// ticket's later tiles would be published only after the wave waited on
+// earlier tiles, whose owners wait in turn: a chain through every wave.
+#ifndef JSIDX_TICKET_TILES
+#define JSIDX_TICKET_TILES 2
+#endif
+constexpr int kTicketTiles = JSIDX_TICKET_TILES;
+static_assert(kTicketTiles == 1 || kTicketTiles == 2, "a ticket's tiles must all publish before its wave waits");
 constexpr int kSegBytes = 32;
 constexpr int kRowBytes = kThreads * kSegBytes;  // 2 KiB
 // Rows per tile: at most kRows (tuning builds may override), at least

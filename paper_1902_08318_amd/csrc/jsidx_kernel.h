@@ -430,6 +430,8 @@ JSIDX_DEV void tile_local(const Args& a, uint32_t rows, Shared& sh, uint2* hmask
   uint32_t wn2[8];
   if (rows > 1) load_segment<SIMPLE>(a, P0 + kRowBytes + (int64_t)lane * kSegBytes, begin, end, wn2);
 #endif
+  int32_t tab_cur = 0;  // first table entry not before the current row (table mode)
+  const int32_t ntab = SIMPLE ? 0 : (int32_t)prim::readlane((uint32_t)sh.ntab, 0);
 #pragma unroll 1
   for (int r = 0; r < (int)rows; r++) {
     const int32_t rel = r * kRowBytes + (int32_t)lane * kSegBytes;  // tile-relative
@@ -450,19 +452,31 @@ JSIDX_DEV void tile_local(const Args& a, uint32_t rows, Shared& sh, uint2* hmask
     int32_t head = hd;
     uint32_t D = 0, d32 = 0, V = ~0u;
     if constexpr (!SIMPLE) {
-      head = doc_at(a, sh, P0, d_first, rel);
-      for (int32_t i = head < 0 ? 0 : head;; i++) {
-        int64_t o;
-        if (!sh.overflow) {
-          if (i >= sh.ntab) break;
-          o = i == 0 ? sh.first_off : (int64_t)sh.tab[i] + P0;
-        } else {
-          if (d_first + i > (int64_t)a.ndocs) break;
-          o = doc_off(a, d_first + i);
+      if (!sh.overflow) {
+        // The table is sorted: a cursor moves past the starts before this
+        // row, then the wave visits the row's own starts (usually none or
+        // one), each lane taking the starts in or right after its segment
+        // and the last start at or before its first byte (its document).
+        const int32_t row0 = r * kRowBytes;
+        while (tab_cur < ntab && (int32_t)prim::readlane((uint32_t)sh.tab[tab_cur], 0) < row0) tab_cur++;
+        head = tab_cur - 1;
+        for (int32_t i = tab_cur; i < ntab; i++) {
+          const int32_t e = (int32_t)prim::readlane((uint32_t)sh.tab[i], 0);
+          if (e > row0 + kRowBytes) break;
+          const int32_t off = e - rel;
+          if (off <= 0) head = i;
+          if (off >= 0 && off < 32) D |= 1u << (uint32_t)off;
+          if (off == 32) d32 = 1;
         }
-        if (o < pos) continue;
-        if (o > pos + 32) break;
-        if (o == pos + 32) d32 = 1; else D |= 1u << (uint32_t)(o - pos);
+      } else {
+        head = doc_at(a, sh, P0, d_first, rel);
+        for (int32_t i = head < 0 ? 0 : head;; i++) {
+          if (d_first + i > (int64_t)a.ndocs) break;
+          const int64_t o = doc_off(a, d_first + i);
+          if (o < pos) continue;
+          if (o > pos + 32) break;
+          if (o == pos + 32) d32 = 1; else D |= 1u << (uint32_t)(o - pos);
+        }
       }
       const int64_t vlo = begin - pos, vhi = end - pos;
       V = ge_mask((uint32_t)(vlo < 0 ? 0 : (vlo > 32 ? 32 : vlo))) &

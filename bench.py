@@ -278,6 +278,14 @@ def serve_c4(jx, torch, synth, seconds: float, nstreams: int = 3) -> dict:
     from paper_1902_08318_amd import serve
     log("generating C4 (request ring)")
     data, offs = synth.gen_c4(4)
+    # the oracle per host core on the first ~100 MB of requests, as context
+    import oracle
+    k = int(np.searchsorted(offs, 100 << 20))
+    t = time.perf_counter()
+    oracle.index_batch(np.frombuffer(data, dtype=np.uint8)[:int(offs[k])], offs[:k + 1])
+    el = time.perf_counter() - t
+    cpu = {"GBps_per_core": round(int(offs[k]) / el / 1e9, 3), "docs_per_s_per_core": round(k / el),
+           "kind": "oracle", "sample": f"the first {k} requests ({int(offs[k])} bytes) on one host core"}
     streams = [torch.cuda.Stream() for _ in range(nstreams)]
     ring = serve.Ring(data, offs, 256 << 20, streams)
     del data
@@ -289,8 +297,21 @@ def serve_c4(jx, torch, synth, seconds: float, nstreams: int = 3) -> dict:
     diag = any(jx.diag(st) for st in streams)
     return {"ring_bytes": ring.total, "ring_docs": ring.ndocs, "mean_doc_bytes": round(ring.total / ring.ndocs),
             "streams": nstreams, "saturated_GBps": round(sat / 1e9, 2), "loads": loads, "budget_bytes": 32 << 30,
+            "cpu_oracle": cpu,
             "note": "request bytes resident in HBM at arrival; latency = host-observed completion - arrival",
             **({"warning": "look-back diagnostic set"} if diag else {})}
+
+
+def paper_context(n: int, s: int) -> dict:
+    """The paper's own single-core stage-1 figures (2019 x86, context only):
+    its cost model (Sec. 5: about 1.7 cycles per index entry plus 0.62 per
+    byte on a 3.4 GHz Skylake) applied to this workload's N and S, and its
+    measured cycles per byte for the twitter and canada files (appendix table
+    of stage-1 optimisations), converted at 3.4 GHz."""
+    cycles = 1.7 * s + 0.62 * n
+    return {"model_GBps_per_core_this_workload": round(n / (cycles / 3.4e9) / 1e9, 2),
+            "twitter_GBps_per_core": round(3.4 / 0.90, 2), "canada_GBps_per_core": round(3.4 / 0.90, 2),
+            "hardware": "one Skylake core at 3.4 GHz (derived from cycles per byte)"}
 
 
 def main():
@@ -400,6 +421,7 @@ def main():
             extra["C4"] = serve_c4(jx, torch, synth, args.serve_seconds)
     if extra:
         out["extra"] = extra
+    out["paper_context"] = paper_context(r1["N"], r1["S"])
     if tuning is not None:
         out["tuning"] = {"tile_rows_by_log2_bytes": {str(b): r for b, r in enumerate(tuning["table"]) if r},
                          "arch": tuning["arch"]}

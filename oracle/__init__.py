@@ -1,8 +1,8 @@
 """CPU oracle for the stage-1 structural index -- TEST INFRASTRUCTURE ONLY.
 
 Wraps the plain byte-at-a-time C definition in ``jsidx_oracle.c`` (stage 1 of
-Langdale & Lemire, "Parsing Gigabytes of JSON per Second", Sec. 3.1) with
-ctypes.  Only the tests, the smoke check and the CPU-baseline leg of the
+Langdale & Lemire, "Parsing Gigabytes of JSON per Second", Sec. 3.1, and the
+minified form of its dataset-size table) with ctypes.  Only the tests, the smoke check and the CPU-baseline leg of the
 benchmark may import this package; the HIP library never does.
 
 Flag bits (defined here independently of the HIP library's header):
@@ -50,6 +50,10 @@ def _load():
     lib.oracle_index.restype = ctypes.c_uint32
     lib.oracle_index_batch.argtypes = [u8p, u64p, ctypes.c_uint32, u32p, u32p, u32p]
     lib.oracle_index_batch.restype = ctypes.c_int
+    lib.oracle_minify.argtypes = [u8p, ctypes.c_uint64, u8p, u32p]
+    lib.oracle_minify.restype = ctypes.c_uint32
+    lib.oracle_minify_batch.argtypes = [u8p, u64p, ctypes.c_uint32, u8p, u32p, u32p]
+    lib.oracle_minify_batch.restype = ctypes.c_int
     lib.oracle_utf8_valid.argtypes = [u8p, ctypes.c_uint64]
     lib.oracle_utf8_valid.restype = ctypes.c_int
     _lib = lib
@@ -97,6 +101,38 @@ def index_batch(bufs, offsets) -> tuple[np.ndarray, np.ndarray, np.ndarray]:
         _ptr(a, ctypes.c_uint8) if a.size else None, _ptr(off, ctypes.c_uint64), nd,
         _ptr(out, ctypes.c_uint32), _ptr(out_n, ctypes.c_uint32),
         _ptr(out_err, ctypes.c_uint32))
+    if rc != 0:
+        raise ValueError("offsets must be nondecreasing")
+    return out[: int(off[-1])], out_n[:nd], out_err[:nd]
+
+
+def minify(buf) -> tuple[bytes, int]:
+    """Minify one document: drop the white-space bytes outside strings.
+    Returns (kept bytes, flags)."""
+    a = _u8(buf)
+    out = np.empty(max(1, a.size), dtype=np.uint8)
+    err = np.zeros(1, dtype=np.uint32)
+    n = _load().oracle_minify(_ptr(a, ctypes.c_uint8) if a.size else None, a.size,
+                              _ptr(out, ctypes.c_uint8), _ptr(err, ctypes.c_uint32))
+    return out[:n].tobytes(), int(err[0])
+
+
+def minify_batch(bufs, offsets) -> tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """Minify a batch; document d's kept bytes are out[offsets[d]:offsets[d]+out_n[d]].
+    Returns (out uint8, out_n, out_err)."""
+    a = _u8(bufs)
+    off = np.ascontiguousarray(offsets, dtype=np.uint64)
+    nd = off.size - 1
+    if nd < 0:
+        raise ValueError("offsets must hold ndocs+1 entries")
+    if int(off[-1]) > a.size:
+        raise ValueError("offsets exceed buffer")
+    out = np.zeros(max(1, int(off[-1])), dtype=np.uint8)
+    out_n = np.zeros(max(1, nd), dtype=np.uint32)
+    out_err = np.zeros(max(1, nd), dtype=np.uint32)
+    rc = _load().oracle_minify_batch(
+        _ptr(a, ctypes.c_uint8) if a.size else None, _ptr(off, ctypes.c_uint64), nd,
+        _ptr(out, ctypes.c_uint8), _ptr(out_n, ctypes.c_uint32), _ptr(out_err, ctypes.c_uint32))
     if rc != 0:
         raise ValueError("offsets must be nondecreasing")
     return out[: int(off[-1])], out_n[:nd], out_err[:nd]

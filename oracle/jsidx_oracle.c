@@ -159,3 +159,46 @@ int oracle_index_batch(const uint8_t *bufs, const uint64_t *offsets,
   }
   return 0;
 }
+
+/* Minify one document: the paper's "minified" form of its dataset-size table
+ * omits the white-space characters outside quotes.  Byte i is kept iff it is
+ * not white space or it lies inside a string, with in_str and esc stepped
+ * exactly as in oracle_index (the opening quote through the byte before the
+ * closing quote are inside).  Kept bytes go to out in order (out has room for
+ * len bytes); returns their number.  *out_err gets the flags of oracle_index
+ * for the same bytes, with EMPTY meaning that nothing is kept. */
+uint32_t oracle_minify(const uint8_t *buf, uint64_t len, uint8_t *out,
+                       uint32_t *out_err) {
+  int esc = 0, in_str = 0;
+  uint32_t n = 0;
+  for (uint64_t i = 0; i < len; i++) {
+    uint8_t b = buf[i];
+    int q = (b == 0x22) && !esc;
+    if (q) in_str ^= 1;
+    if (!is_whitespace(b) || in_str) out[n++] = b;
+    esc = (b == 0x5C) && !esc;
+  }
+  uint32_t err = 0;
+  if (!oracle_utf8_valid(buf, len)) err |= OR_ERR_UTF8;
+  if (in_str) err |= OR_ERR_UNCLOSED_STRING;
+  if (esc) err |= OR_ERR_TRAILING_ESCAPE;
+  if (n == 0) err |= OR_ERR_EMPTY;
+  *out_err = err;
+  return n;
+}
+
+/* Minify a batch: document d's kept bytes go to out[offsets[d] ...], out_n[d]
+ * and out_err[d] get its count and flags.  Returns 0, or -1 if the offsets
+ * decrease. */
+int oracle_minify_batch(const uint8_t *bufs, const uint64_t *offsets,
+                        uint32_t ndocs, uint8_t *out, uint32_t *out_n,
+                        uint32_t *out_err) {
+  for (uint32_t d = 0; d < ndocs; d++) {
+    if (offsets[d + 1] < offsets[d]) return -1;
+  }
+  for (uint32_t d = 0; d < ndocs; d++) {
+    uint64_t a = offsets[d], e = offsets[d + 1];
+    out_n[d] = oracle_minify(bufs + a, e - a, out + a, &out_err[d]);
+  }
+  return 0;
+}

@@ -185,6 +185,40 @@ def time_batch(jx, torch, data: bytes, offsets: np.ndarray, steps: int, warmup: 
             "docs_per_s": nd / (ms / 1e3), "per_doc_launch_docs_per_s": per_doc_docs / (per_doc_ms / 1e3)}
 
 
+def time_minify(jx, torch, data: bytes, offsets, steps: int, warmup: int = 2) -> dict:
+    """The minify pass (white space outside strings dropped) over one document
+    (offsets None) or a batch, resident in HBM; two events around the launches."""
+    dev = torch.device("cuda:0")
+    n = len(data)
+    buf = torch.frombuffer(bytearray(data), dtype=torch.uint8).to(dev)
+    out = torch.empty(max(1, n), dtype=torch.uint8, device=dev)
+    nd = 1 if offsets is None else offsets.size - 1
+    cnt = torch.empty(nd, dtype=torch.int32, device=dev)
+    err = torch.empty(nd, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+    jx.reserve(n, stream)
+    if offsets is None:
+        call = lambda: jx.minify(buf, out, cnt, err, stream)  # noqa: E731
+    else:
+        offs = torch.from_numpy(offsets.astype(np.int64)).to(dev)
+        call = lambda: jx.minify_batch(buf, offs, out, cnt, err, stream)  # noqa: E731
+    for _ in range(warmup):
+        call()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(steps):
+        call()
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    kept = int(cnt.to(torch.int64).sum().item())
+    return {"bytes": n, "kept_bytes": kept, "ms_per_launch": round(ms, 4),
+            "input_GBps": round(n / (ms / 1e3) / 1e9, 2),
+            "alg_GBps": round((n + kept + (16 * nd if offsets is not None else 0)) / (ms / 1e3) / 1e9, 1)}
+
+
 def cpu_batch_baseline(data: bytes, offsets: np.ndarray, budget_s: float = 6.0) -> dict:
     """The oracle over a batch: one core, then the documents partitioned into
     contiguous byte-balanced ranges over every host core (one thread each; the
@@ -402,6 +436,8 @@ def main():
         extra["C2"] = {"bytes": r2["N"], "index_entries": r2["S"], "input_GBps": round(r2["N"] / (r2["ms_per_launch"] / 1e3) / 1e9, 2),
                        "alg_GBps": round((r2["N"] + 4 * r2["S"]) / (r2["ms_per_launch"] / 1e3) / 1e9, 1),
                        "ms_per_launch": round(r2["ms_per_launch"], 4), "launch_ms": r2["launch_ms"]}
+        log("minify: C2 and the C3 batch")
+        extra["minify"] = {"C2": time_minify(jx, torch, c2.data, None, args.steps)}
         del c2
         log("generating C3 (100k-document batch)")
         data, offs, kinds = c3 if c3 is not None else synth.gen_c3(3)
@@ -413,6 +449,7 @@ def main():
                        "docs_per_s": round(r3["docs_per_s"]), "per_doc_launch_docs_per_s": round(r3["per_doc_launch_docs_per_s"]),
                        "batched_vs_per_doc": round(r3["docs_per_s"] / r3["per_doc_launch_docs_per_s"], 1),
                        "ms_per_launch": round(r3["ms_per_launch"], 4), "launch_ms": r3["launch_ms"]}
+        extra["minify"]["C3"] = time_minify(jx, torch, data, offs, max(3, args.steps // 2))
         if not args.no_cpu:
             log("timing the CPU oracle on C3 (1 core, then all cores)")
             extra["C3"]["cpu_oracle"] = cpu_batch_baseline(data, offs)

@@ -107,6 +107,37 @@ int jsidx_build_batch(const uint8_t *bufs, const uint64_t *offsets,
                       uint32_t *out_err, jsidx_stream_t stream);
 
 /*
+ * jsidx_minify -- minify one document: drop the white-space characters
+ * (TAB LF CR SPACE) outside strings and keep every other byte in order, the
+ * paper's minified form of a document (its table of dataset sizes; its
+ * appendix on the effect of minification).  A byte is inside a string from an
+ * unescaped opening quote through the byte before the closing quote, with the
+ * escapes and string ranges of Sec. 3.1.1 (Figs. 3 and 4); a backslash outside
+ * strings escapes the next byte, which is still dropped if it is white space.
+ *   buf      device pointer to `len` bytes (any alignment), 0 <= len < 2^32.
+ *   out      device array of at least max(len, 1) bytes: the kept bytes; bytes
+ *            past *out_n unspecified.
+ *   out_n    device uint32: number of bytes kept.
+ *   out_err  device uint32: the same flags as jsidx_build for these bytes
+ *            (JSIDX_ERR_EMPTY: nothing is kept, which happens exactly when
+ *            the index is empty).
+ * Same stream, workspace and error behaviour as jsidx_build.
+ */
+int jsidx_minify(const uint8_t *buf, uint64_t len, uint8_t *out,
+                 uint32_t *out_n, uint32_t *out_err, jsidx_stream_t stream);
+
+/*
+ * jsidx_minify_batch -- minify many independent documents in one launch.
+ * Document d's kept bytes go to out[offsets[d] .. offsets[d] + out_n[d]);
+ * out has at least max(offsets[ndocs], 1) bytes.  Arguments, reservation and
+ * capacity behaviour as jsidx_build_batch; each document's results are
+ * identical to jsidx_minify on that document.
+ */
+int jsidx_minify_batch(const uint8_t *bufs, const uint64_t *offsets,
+                       uint32_t ndocs, uint8_t *out, uint32_t *out_n,
+                       uint32_t *out_err, jsidx_stream_t stream);
+
+/*
  * jsidx_reserve -- size the workspace of `stream` for inputs of up to
  * max_total_len bytes in total (single document or batch) and switch batch
  * calls on that stream to the no-synchronisation mode described above.  Call

@@ -8,6 +8,6 @@ include/jsidx.h.  This package only marshals arguments to that library.
 """
 from .binding import (  # noqa: F401
     ERR_CAPACITY, ERR_EMPTY, ERR_TRAILING_ESCAPE, ERR_UNCLOSED_STRING, ERR_UTF8,
-    JsidxError, build, build_batch, diag, index, index_batch, library_path, release, reserve, set_tile_rows,
-    tile_rows,
+    JsidxError, build, build_batch, diag, index, index_batch, library_path, minify, minify_batch, release, reserve,
+    set_tile_rows, tile_rows,
 )

@@ -25,6 +25,8 @@ _VP = ctypes.c_void_p
 SIGNATURES = {
     "jsidx_build": ([_VP, ctypes.c_uint64, _VP, _VP, _VP, _VP], ctypes.c_int),
     "jsidx_build_batch": ([_VP, _VP, ctypes.c_uint32, _VP, _VP, _VP, _VP], ctypes.c_int),
+    "jsidx_minify": ([_VP, ctypes.c_uint64, _VP, _VP, _VP, _VP], ctypes.c_int),
+    "jsidx_minify_batch": ([_VP, _VP, ctypes.c_uint32, _VP, _VP, _VP, _VP], ctypes.c_int),
     "jsidx_reserve": ([ctypes.c_uint64, _VP], ctypes.c_int),
     "jsidx_workspace_bytes": ([ctypes.c_uint64], ctypes.c_size_t),
     "jsidx_release": ([_VP], ctypes.c_int),
@@ -94,6 +96,19 @@ def build_batch(bufs, offsets, out_idx, out_n, out_err, stream=None):
     nd = offsets.numel() - 1
     _check(lib().jsidx_build_batch(_ptr(bufs), _ptr(offsets), nd, _ptr(out_idx), _ptr(out_n),
                                    _ptr(out_err), _stream(stream)))
+
+
+def minify(buf, out, out_n, out_err, stream=None, length=None):
+    """jsidx_minify on device tensors (buf, out: uint8; out_n, out_err: int32/uint32)."""
+    n = buf.numel() if length is None else int(length)
+    _check(lib().jsidx_minify(_ptr(buf), n, _ptr(out), _ptr(out_n), _ptr(out_err), _stream(stream)))
+
+
+def minify_batch(bufs, offsets, out, out_n, out_err, stream=None):
+    """jsidx_minify_batch on device tensors (offsets: int64, ndocs+1 entries; out: uint8)."""
+    nd = offsets.numel() - 1
+    _check(lib().jsidx_minify_batch(_ptr(bufs), _ptr(offsets), nd, _ptr(out), _ptr(out_n), _ptr(out_err),
+                                    _stream(stream)))
 
 
 def reserve(max_total_len: int, stream=None):

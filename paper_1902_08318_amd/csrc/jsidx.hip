@@ -27,9 +27,19 @@
 
 namespace jsidx {
 
-// Four waves per SIMD: 128 VGPRs, enough to keep two rows of input in flight per wave.
-__global__ void __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per_eu(4))) index_kernel(Args a) {
-  index_tiles(a);
+// Waves per SIMD the register budget is sized for (4: up to 128 VGPRs).
+#ifndef JSIDX_WAVES_PER_EU
+#define JSIDX_WAVES_PER_EU 4
+#endif
+__global__ void __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per_eu(JSIDX_WAVES_PER_EU)))
+index_kernel(Args a) {
+  index_tiles<false>(a);
+}
+
+// The same pass with the kept bytes (not white space outside strings) as output.
+__global__ void __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per_eu(JSIDX_WAVES_PER_EU)))
+minify_kernel(Args a) {
+  index_tiles<true>(a);
 }
 
 // ---------------------------------------------------------------------------
@@ -45,7 +55,7 @@ struct StreamWs {
 std::mutex g_mu;
 std::vector<StreamWs> g_ws;
 uint64_t g_rows_tab[4];  // tile rows by size class (jsidx_set_tile_rows), 0 = default
-int g_slots[64];  // resident workgroups per device (0 = not queried)
+int g_slots[2][64];  // resident workgroups per kernel (index, minify) and device (0 = not queried)
 
 uint64_t tiles_for(uint64_t total_len) {
   uint64_t t = (total_len + 15 + kTileBytes - 1) / kTileBytes;
@@ -54,17 +64,20 @@ uint64_t tiles_for(uint64_t total_len) {
 
 size_t ws_bytes_for_tiles(uint64_t tiles) { return (size_t)workspace_bytes(tiles); }
 
-int slots_for_device(int dev) {
+int slots_for_device(int dev, bool minify) {
   if (dev < 0 || dev >= 64) return 1024;
-  if (g_slots[dev]) return g_slots[dev];
+  int& slots = g_slots[minify ? 1 : 0][dev];
+  if (slots) return slots;
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, index_kernel, kGroupThreads, 0) != hipSuccess || per_cu < 1)
-    per_cu = 1;
+  const hipError_t rc = minify
+      ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, minify_kernel, kGroupThreads, 0)
+      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, index_kernel, kGroupThreads, 0);
+  if (rc != hipSuccess || per_cu < 1) per_cu = 1;
   hipDeviceProp_t prop;
   int cus = 256;
   if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
-  g_slots[dev] = per_cu * cus;
-  return g_slots[dev];
+  slots = per_cu * cus;
+  return slots;
 }
 
 // Find or grow the workspace of (current device, stream).  Caller holds g_mu.
@@ -102,10 +115,10 @@ int get_ws(hipStream_t stream, uint64_t need_tiles, bool grow, StreamWs** out) {
 // document, known here), so the tile size and the grid fit the input;
 // span < 0 (batch, sizes on the device): the grid covers the workspace and
 // the kernel picks the tile size.
-int launch(Args& a, hipStream_t stream, const StreamWs& e, int64_t span) {
+int launch(Args& a, hipStream_t stream, const StreamWs& e, int64_t span, bool minify) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return JSIDX_E_HIP;
-  const uint64_t slots = (uint64_t)slots_for_device(dev);
+  const uint64_t slots = (uint64_t)slots_for_device(dev, minify);
   a.ws = e.ws;
   a.cap_tiles = desc_slots(e.cap_tiles);
   a.cap_rows = e.cap_tiles * (uint64_t)kRows;
@@ -121,7 +134,10 @@ int launch(Args& a, hipStream_t stream, const StreamWs& e, int64_t span) {
   uint64_t grid = groups < slots ? groups : slots;
   if (grid < 1) grid = 1;
   a.fill_waves = (uint32_t)(grid * kWaves);
-  hipLaunchKernelGGL(index_kernel, dim3((uint32_t)grid), dim3(kGroupThreads), 0, stream, a);
+  if (minify)
+    hipLaunchKernelGGL(minify_kernel, dim3((uint32_t)grid), dim3(kGroupThreads), 0, stream, a);
+  else
+    hipLaunchKernelGGL(index_kernel, dim3((uint32_t)grid), dim3(kGroupThreads), 0, stream, a);
   if (hipGetLastError() != hipSuccess) return JSIDX_E_HIP;
   return JSIDX_OK;
 }
@@ -130,12 +146,11 @@ int launch(Args& a, hipStream_t stream, const StreamWs& e, int64_t span) {
 
 using namespace jsidx;
 
-extern "C" {
+namespace jsidx {
 
-int jsidx_build(const uint8_t* buf, uint64_t len, uint32_t* out_idx, uint32_t* out_n, uint32_t* out_err,
-                jsidx_stream_t stream_) {
-  hipStream_t stream = (hipStream_t)stream_;
-  if (!out_idx || !out_n || !out_err || (!buf && len)) return JSIDX_E_INVAL;
+int build_one(const uint8_t* buf, uint64_t len, uint32_t* out, uint32_t* out_n, uint32_t* out_err,
+              hipStream_t stream, bool minify) {
+  if (!out || !out_n || !out_err || (!buf && len)) return JSIDX_E_INVAL;
   if (len >= (1ull << 32)) return JSIDX_E_INVAL;
   std::lock_guard<std::mutex> lk(g_mu);
   StreamWs* e = nullptr;
@@ -143,20 +158,19 @@ int jsidx_build(const uint8_t* buf, uint64_t len, uint32_t* out_idx, uint32_t* o
   int rc = get_ws(stream, need, true, &e);
   if (rc) return rc;
   Args a;
-  a.base = buf ? buf : reinterpret_cast<const uint8_t*>(out_idx);  // never read when len == 0
+  a.base = buf ? buf : reinterpret_cast<const uint8_t*>(out);  // never read when len == 0
   a.offsets = nullptr;
   a.len = len;
   a.ndocs = 1;
-  a.out_idx = out_idx;
+  a.out_idx = out;
   a.out_n = out_n;
   a.out_err = out_err;
-  return launch(a, stream, *e, (int64_t)(len + ((uintptr_t)a.base & 15u)));
+  return launch(a, stream, *e, (int64_t)(len + ((uintptr_t)a.base & 15u)), minify);
 }
 
-int jsidx_build_batch(const uint8_t* bufs, const uint64_t* offsets, uint32_t ndocs, uint32_t* out_idx,
-                      uint32_t* out_n, uint32_t* out_err, jsidx_stream_t stream_) {
-  hipStream_t stream = (hipStream_t)stream_;
-  if (!bufs || !offsets || !out_idx || !out_n || !out_err || ndocs == 0) return JSIDX_E_INVAL;
+int build_many(const uint8_t* bufs, const uint64_t* offsets, uint32_t ndocs, uint32_t* out, uint32_t* out_n,
+               uint32_t* out_err, hipStream_t stream, bool minify) {
+  if (!bufs || !offsets || !out || !out_n || !out_err || ndocs == 0) return JSIDX_E_INVAL;
   std::lock_guard<std::mutex> lk(g_mu);
   StreamWs* e = nullptr;
   int rc = get_ws(stream, 0, false, &e);
@@ -175,10 +189,35 @@ int jsidx_build_batch(const uint8_t* bufs, const uint64_t* offsets, uint32_t ndo
   a.offsets = offsets;
   a.len = 0;
   a.ndocs = ndocs;
-  a.out_idx = out_idx;
+  a.out_idx = out;
   a.out_n = out_n;
   a.out_err = out_err;
-  return launch(a, stream, *e, -1);
+  return launch(a, stream, *e, -1, minify);
+}
+
+}  // namespace jsidx
+
+extern "C" {
+
+int jsidx_build(const uint8_t* buf, uint64_t len, uint32_t* out_idx, uint32_t* out_n, uint32_t* out_err,
+                jsidx_stream_t stream) {
+  return build_one(buf, len, out_idx, out_n, out_err, (hipStream_t)stream, false);
+}
+
+int jsidx_build_batch(const uint8_t* bufs, const uint64_t* offsets, uint32_t ndocs, uint32_t* out_idx,
+                      uint32_t* out_n, uint32_t* out_err, jsidx_stream_t stream) {
+  return build_many(bufs, offsets, ndocs, out_idx, out_n, out_err, (hipStream_t)stream, false);
+}
+
+int jsidx_minify(const uint8_t* buf, uint64_t len, uint8_t* out, uint32_t* out_n, uint32_t* out_err,
+                 jsidx_stream_t stream) {
+  return build_one(buf, len, reinterpret_cast<uint32_t*>(out), out_n, out_err, (hipStream_t)stream, true);
+}
+
+int jsidx_minify_batch(const uint8_t* bufs, const uint64_t* offsets, uint32_t ndocs, uint8_t* out, uint32_t* out_n,
+                       uint32_t* out_err, jsidx_stream_t stream) {
+  return build_many(bufs, offsets, ndocs, reinterpret_cast<uint32_t*>(out), out_n, out_err, (hipStream_t)stream,
+                    true);
 }
 
 int jsidx_reserve(uint64_t max_total_len, jsidx_stream_t stream_) {
@@ -246,7 +285,7 @@ int jsidx_tile_rows(uint64_t span, uint32_t* out_rows) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return JSIDX_E_HIP;
   std::lock_guard<std::mutex> lk(g_mu);
-  const uint64_t slots = (uint64_t)slots_for_device(dev);
+  const uint64_t slots = (uint64_t)slots_for_device(dev, false);
   *out_rows = rows_for((int64_t)span, slots * kWaves, g_rows_tab);
   return JSIDX_OK;
 }

@@ -384,6 +384,47 @@ JSIDX_DEV void write_row(Shared& sh, uint32_t* out, uint64_t lim, uint32_t* cc, 
   }
 }
 
+// Byte J of a lane's 32-byte segment (J a compile-time constant, so that no
+// register array is indexed at run time).
+template <int J>
+JSIDX_DEV uint32_t seg_byte(const uint32_t w[8]) { return (w[J >> 2] >> (8 * (J & 3))) & 0xFFu; }
+
+// The bytes of F, in order, to dst[*k ...] (global memory, ranks below lim
+// only) or, with TO_LDS, to the wave's LDS staging buffer.
+template <int J, bool TO_LDS>
+JSIDX_DEV void put_kept(uint8_t* dst, uint32_t F, const uint32_t w[8], uint32_t* k, uint32_t lim) {
+  if ((F >> J) & 1u) {
+    if constexpr (TO_LDS) dst[*k] = (uint8_t)seg_byte<J>(w);
+    else if (*k < lim) prim::st_byte(dst + *k, seg_byte<J>(w));
+    ++*k;
+  }
+  if constexpr (J < 31) put_kept<J + 1, TO_LDS>(dst, F, w, k, lim);
+}
+
+// Minified output of one row: the bytes of F (this lane's kept bytes, w its
+// segment) at ranks from *cc plus the lanes below; *cc advances by the row's
+// total.  The row's bytes are gathered in LDS at their ranks and written out
+// with one store per 64 consecutive bytes.  Ranks at or past lim are not
+// written.
+JSIDX_DEV void write_bytes(Shared& sh, uint8_t* out, uint64_t lim, uint32_t* cc, uint32_t F, const uint32_t w[8]) {
+  const uint32_t n = (uint32_t)__builtin_popcount(F);
+  const uint32_t incl = prim::incl_scan(n);
+  const uint32_t row_n = prim::readlane(incl, 63);
+  const uint32_t base = *cc;
+  *cc += row_n;
+  if ((uint64_t)base + row_n <= lim) {
+    uint8_t* sb = reinterpret_cast<uint8_t*>(sh.stage);  // 4 * kStage >= kRowBytes bytes
+    uint32_t k = incl - n;
+    put_kept<0, true>(sb, F, w, &k, 0xFFFFFFFFu);
+    prim::wave_sync();
+    for (uint32_t i = prim::lane(); i < row_n; i += (uint32_t)kThreads) prim::st_byte(out + base + i, sb[i]);
+    prim::wave_sync();  // the next row reuses the buffer
+  } else {
+    uint32_t k = base + incl - n;
+    put_kept<0, false>(out, F, w, &k, lim > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)lim);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // The local pass over one tile, given the incoming state st_in.  Bytes at or
 // after the tile's first document start do not depend on st_in: their
@@ -395,7 +436,11 @@ JSIDX_DEV void write_row(Shared& sh, uint32_t* out, uint64_t lim, uint32_t* cc, 
 // SIMPLE: no document starts or ends in [P0, P0 + kTileBytes] and the tile
 // lies inside the input (every byte belongs to document hd, which starts at
 // hs < P0), the escape state entering the tile is known, and defer is set.
-template <bool SIMPLE>
+// MIN: minify instead of index.  A byte is kept if it is not white space or
+// lies inside a string (in the head region K marks the bytes whose fate flips
+// with the incoming in-string state, F0 the kept bytes if it is 0), and the
+// outputs are the kept bytes.
+template <bool SIMPLE, bool MIN = false>
 JSIDX_DEV void tile_local(const Args& a, uint32_t rows, Shared& sh, uint2* hmask, const uint32_t* first_row,
                           int64_t P0,
                           int64_t begin, int64_t end, int64_t d_first, int32_t hd, int64_t hs, uint32_t st_in,
@@ -599,19 +644,19 @@ JSIDX_DEV void tile_local(const Args& a, uint32_t rows, Shared& sh, uint2* hmask
     const uint32_t P0m = cm.C | cm.W | Q;
     const uint32_t PR = shift_in1(P0m, &cp) | D;
 
-    if (r == 0) {
+    if (r == 0 && !MIN) {
       const uint32_t other0 = (V & 1u) && !(D & 1u) && !((cm.C | cm.W | cm.Q) & 1u);
       T.elig0 = prim::readlane(other0, 0);
     }
-    const uint32_t K = (cm.C | Q | (PR & ~P0m)) & V;
-    const uint32_t F0 = K & ~(Q ^ R0);
+    const uint32_t K = MIN ? (cm.W & V) : ((cm.C | Q | (PR & ~P0m)) & V);
+    const uint32_t F0 = MIN ? ((~cm.W | R0) & V) : (K & ~(Q ^ R0));
     const bool had_reset = T.reset_any != 0;
     if (SIMPLE || (plain && defer && !had_reset)) {
       // the whole row lies in the head region
       prim::st_pair(hmask + r * kThreads + lane, K, F0);
       T.head_rows = (uint32_t)r + 1u;
       T.a0 += (uint32_t)__builtin_popcount(F0);
-      T.a1 += (uint32_t)__builtin_popcount(K & ~F0);
+      T.a1 += (uint32_t)__builtin_popcount(F0 ^ K);
       continue;
     }
     if (plain) {
@@ -619,7 +664,9 @@ JSIDX_DEV void tile_local(const Args& a, uint32_t rows, Shared& sh, uint2* hmask
       // positions are written after the tile has published its descriptor
       const int32_t h0 = prim::readlane((uint32_t)head, 0);
       const int64_t doff = doc_start(a, sh, P0, d_first, h0);
-      if (defer) {
+      if constexpr (MIN) {
+        write_bytes(sh, reinterpret_cast<uint8_t*>(a.out_idx) + doff, (uint64_t)(end - doff), &cc, F0, w);
+      } else if (defer) {
         sh.hF[r][lane] = F0;
         if (lane == 0) { sh.tr_doff[r] = doff; sh.tr_cc[r] = cc; }
         T.tail_rows |= 1u << r;
@@ -642,7 +689,7 @@ JSIDX_DEV void tile_local(const Args& a, uint32_t rows, Shared& sh, uint2* hmask
       prim::st_pair(hmask + r * kThreads + lane, K & hm, F0 & hm);
       T.head_rows = (uint32_t)r + 1u;
       T.a0 += (uint32_t)__builtin_popcount(F0 & hm);
-      T.a1 += (uint32_t)__builtin_popcount(K & ~F0 & hm);
+      T.a1 += (uint32_t)__builtin_popcount((F0 ^ K) & hm);
     }
 
     // positions and per-document results of the pieces written now (none
@@ -682,11 +729,15 @@ JSIDX_DEV void tile_local(const Args& a, uint32_t rows, Shared& sh, uint2* hmask
       const uint32_t lim = room > 0xFFFFFFFFll ? 0xFFFFFFFFu : (uint32_t)room;
       uint32_t f = F0 & wmask & segm;
       uint32_t kk = cont ? cin : 0u;
-      while (f) {
-        const uint32_t j = (uint32_t)__builtin_ctz(f);
-        f &= f - 1u;
-        if (kk < lim) prim::st_out(out + kk, rel_doc + j);
-        kk++;
+      if constexpr (MIN) {
+        put_kept<0, false>(reinterpret_cast<uint8_t*>(a.out_idx) + doff, f, w, &kk, lim);
+      } else {
+        while (f) {
+          const uint32_t j = (uint32_t)__builtin_ctz(f);
+          f &= f - 1u;
+          if (kk < lim) prim::st_out(out + kk, rel_doc + j);
+          kk++;
+        }
       }
       if (ends_doc) {
         const uint32_t e = nx - 1u;
@@ -1228,6 +1279,7 @@ struct Pending {
 // The local pass of a tile, its descriptor, its block's fold if it is the
 // block's last to publish, and the positions that need nothing from earlier
 // tiles.  The head region's masks go to the tile's slot in the workspace.
+template <bool MIN>
 JSIDX_DEV Pending start_tile(const Args& a, Shared& sh, const TileSetup& S, int64_t begin, int64_t end,
                              int64_t ntiles, uint32_t epoch) {
   const uint32_t lane = prim::lane();
@@ -1235,8 +1287,10 @@ JSIDX_DEV Pending start_tile(const Args& a, Shared& sh, const TileSetup& S, int6
   const int64_t t = S.t, P0 = S.P0;
   uint2* hmask = head_masks(a, t, S.rows);
   TileFacts T;
-  if (S.simple) tile_local<true>(a, S.rows, sh, hmask, S.w0, P0, begin, end, S.d_first, S.hd, S.hs, S.e_T, true, 0u, T);
-  else tile_local<false>(a, S.rows, sh, hmask, S.w0, P0, begin, end, S.d_first, S.hd, S.hs, S.e_T, true, 0u, T);
+  if (S.simple)
+    tile_local<true, MIN>(a, S.rows, sh, hmask, S.w0, P0, begin, end, S.d_first, S.hd, S.hs, S.e_T, true, 0u, T);
+  else
+    tile_local<false, MIN>(a, S.rows, sh, hmask, S.w0, P0, begin, end, S.d_first, S.hd, S.hs, S.e_T, true, 0u, T);
   prim::trace(t, 2);
   Pending R;
   R.valid = true;
@@ -1310,6 +1364,7 @@ JSIDX_DEV Pending start_tile(const Args& a, Shared& sh, const TileSetup& S, int6
 // The look-back of a published tile, the rare exact second pass (when the
 // escape carried in turns out to change the tile's head), its inclusive
 // value, and its head region's positions and head document's result.
+template <bool MIN>
 JSIDX_DEV void finish_tile(const Args& a, Shared& sh, const Pending& R, int64_t pos_g0, int64_t begin, int64_t end,
                            int64_t ntiles, uint32_t epoch) {
   const uint32_t lane = prim::lane();
@@ -1332,7 +1387,7 @@ JSIDX_DEV void finish_tile(const Args& a, Shared& sh, const Pending& R, int64_t 
     prim::trace_count(t, 9);
     const TileSetup S2 = begin_tile(a, S.rows, sh, t, pos_g0, begin, end, ntiles);
     TileFacts T;
-    tile_local<false>(a, S.rows, sh, head_masks(a, t, S.rows), S2.w0, P0, begin, end, S2.d_first, S2.hd, S2.hs, s_in, false, base,
+    tile_local<false, MIN>(a, S.rows, sh, head_masks(a, t, S.rows), S2.w0, P0, begin, end, S2.d_first, S2.hd, S2.hs, s_in, false, base,
                       T);
     if (lane == 0 && !R.inc_done) {
       const uint64_t inc = make_inc(T.carry, T.reset_any, T.tail_count, epoch);
@@ -1382,8 +1437,16 @@ JSIDX_DEV void finish_tile(const Args& a, Shared& sh, const Pending& R, int64_t 
     prim::wave_sync();
     uint32_t cc = base;
 #pragma unroll 1
-    for (uint32_t r = 0; r < R.head_rows; r++)
-      write_row(sh, out, lim, &cc, sh.hF[r][lane], rel0 + r * (uint32_t)kRowBytes);
+    for (uint32_t r = 0; r < R.head_rows; r++) {
+      if constexpr (MIN) {
+        // the kept bytes themselves: the row's segment is read again
+        uint32_t w[8];
+        load_segment<false>(a, P0 + (int64_t)r * kRowBytes + (int64_t)lane * kSegBytes, begin, end, w);
+        write_bytes(sh, reinterpret_cast<uint8_t*>(a.out_idx) + S.hs, lim, &cc, sh.hF[r][lane], w);
+      } else {
+        write_row(sh, out, lim, &cc, sh.hF[r][lane], rel0 + r * (uint32_t)kRowBytes);
+      }
+    }
     if (R.he_valid && lane == 0) {
       uint32_t err = 0;
       if (R.he_u | uT) err |= JSIDX_ERR_UTF8;
@@ -1398,6 +1461,7 @@ JSIDX_DEV void finish_tile(const Args& a, Shared& sh, const Pending& R, int64_t 
 }
 
 // ---------------------------------------------------------------------------
+template <bool MIN = false>
 JSIDX_DEVFN void index_tiles(const Args& a) {
   GroupShared& gs = prim::lds_object<GroupShared>();
   const uint32_t wv = prim::wave_id();
@@ -1445,8 +1509,8 @@ JSIDX_DEVFN void index_tiles(const Args& a) {
       if (t >= ntiles) break;
       prim::trace(t, 0);
       const TileSetup S = begin_tile(a, rows, sh, t, pos_g0, begin, end, ntiles);
-      const Pending cur = start_tile(a, sh, S, begin, end, ntiles, epoch);
-      if (pend.valid) finish_tile(a, sh, pend, pos_g0, begin, end, ntiles, epoch);
+      const Pending cur = start_tile<MIN>(a, sh, S, begin, end, ntiles, epoch);
+      if (pend.valid) finish_tile<MIN>(a, sh, pend, pos_g0, begin, end, ntiles, epoch);
       pend = cur;
       tk++;
       if (--left == 0) {
@@ -1456,7 +1520,7 @@ JSIDX_DEVFN void index_tiles(const Args& a) {
         left = tt;
       }
     }
-    if (pend.valid) finish_tile(a, sh, pend, pos_g0, begin, end, ntiles, epoch);
+    if (pend.valid) finish_tile<MIN>(a, sh, pend, pos_g0, begin, end, ntiles, epoch);
   }
 
   // The last workgroup out resets the counters for the next launch and clears

@@ -103,6 +103,7 @@ JSIDX_DEV uint4 load16(const uint8_t* p) { return *reinterpret_cast<const uint4*
 JSIDX_DEV uint32_t load4(const uint8_t* p) { return *reinterpret_cast<const uint32_t*>(p); }
 JSIDX_DEV uint64_t load8(const uint64_t* p) { return *p; }
 JSIDX_DEV void st_out(uint32_t* p, uint32_t v) { *p = v; }
+JSIDX_DEV void st_byte(uint8_t* p, uint32_t v) { *p = (uint8_t)v; }
 JSIDX_DEV void st_pair(uint2* p, uint32_t x, uint32_t y) { *p = make_uint2(x, y); }
 JSIDX_DEV uint2 ld_pair(const uint2* p) { return *p; }
 

@@ -27,13 +27,15 @@ extern "C" {
 //   several launches can reuse it like the real library does; cap_tiles
 //   counts largest tiles.
 //   rows: rows per tile (0: the kernel picks them for the launch's waves).
+//   minify: run the minify pass (out_idx then receives bytes).
 long emu_run(const uint8_t* base, const uint64_t* offsets, uint64_t len, uint32_t ndocs, uint32_t* out_idx,
              uint64_t out_cap, uint32_t* out_n, uint32_t* out_err, int nblocks, void* ws_mem, uint64_t cap_tiles,
-             uint32_t rows, const uint8_t* granule_lo, const uint8_t* granule_hi) {
+             uint32_t rows, const uint8_t* granule_lo, const uint8_t* granule_hi, int minify) {
   prim::EmuEnv env;
   env.reads[env.nreads++] = {granule_lo, granule_hi};
   if (offsets) env.reads[env.nreads++] = {offsets, offsets + ndocs + 1};
-  env.writes[env.nwrites++] = {out_idx, out_idx + out_cap};
+  // out_cap counts entries: uint32 positions, or bytes when minifying
+  env.writes[env.nwrites++] = {out_idx, reinterpret_cast<const uint8_t*>(out_idx) + out_cap * (minify ? 1 : 4)};
   env.writes[env.nwrites++] = {out_n, out_n + ndocs};
   env.writes[env.nwrites++] = {out_err, out_err + ndocs};
   env.writes[env.nwrites++] = {ws_mem, (const uint8_t*)ws_mem + workspace_bytes(cap_tiles)};
@@ -67,7 +69,7 @@ long emu_run(const uint8_t* base, const uint64_t* offsets, uint64_t len, uint32_
         prim::tctx.grid = (uint32_t)ngroups;
         prim::tctx.g = groups[(size_t)b];
         prim::tctx.env = &env;
-        index_tiles(a);
+        if (minify) index_tiles<true>(a); else index_tiles<false>(a);
       });
     }
   }

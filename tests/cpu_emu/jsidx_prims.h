@@ -243,6 +243,10 @@ inline void st_out(uint32_t* p, uint32_t v) {
   check(p, 4, true);
   *p = v;
 }
+inline void st_byte(uint8_t* p, uint32_t v) {
+  check(p, 1, true);
+  *p = (uint8_t)v;
+}
 inline uint2 ld_pair(const uint2* p) {
   check(p, 8, false);
   return *p;

@@ -55,7 +55,7 @@ def load(block_tiles: int | None = None):
     lib = ctypes.CDLL(path)
     vp = ctypes.c_void_p
     lib.emu_run.argtypes = [vp, vp, ctypes.c_uint64, ctypes.c_uint32, vp, ctypes.c_uint64, vp, vp,
-                            ctypes.c_int, vp, ctypes.c_uint64, ctypes.c_uint32, vp, vp]
+                            ctypes.c_int, vp, ctypes.c_uint64, ctypes.c_uint32, vp, vp, ctypes.c_int]
     lib.emu_run.restype = ctypes.c_long
     lib.emu_ws_bytes.argtypes = [ctypes.c_uint64]
     lib.emu_ws_bytes.restype = ctypes.c_uint64
@@ -93,7 +93,7 @@ def _aligned(nbytes: int, shift: int) -> tuple[np.ndarray, int]:
 
 
 def run(data: bytes, offsets=None, nblocks: int = 2, misalign: int = 0, ws: Workspace | None = None,
-        garbage: int = 0xEE, block_tiles: int | None = None, rows: int | None = None):
+        garbage: int = 0xEE, block_tiles: int | None = None, rows: int | None = None, minify: bool = False):
     """Index `data` (one document if offsets is None, else a batch).
 
     misalign: the buffer starts this many bytes past a 64-byte boundary.  The
@@ -101,6 +101,7 @@ def run(data: bytes, offsets=None, nblocks: int = 2, misalign: int = 0, ws: Work
     `garbage` so that any influence of them shows up.
     block_tiles: look-back block size of the build (None: the library's).
     rows: rows per tile (None: the largest tile; 0: the kernel picks them).
+    minify: run the minify pass; out_idx is then a uint8 array of kept bytes.
     Returns (out_idx, out_n, out_err, violations).
     """
     if ws is not None:
@@ -122,7 +123,7 @@ def run(data: bytes, offsets=None, nblocks: int = 2, misalign: int = 0, ws: Work
     glo = (base + begin) & ~15
     ghi = ((base + end + 15) & ~15) if end > begin else glo
     out_cap = max(end, 1)
-    out_idx = np.full(out_cap, 0xDEADBEEF, dtype=np.uint32)
+    out_idx = np.full(out_cap, 0xEE if minify else 0xDEADBEEF, dtype=np.uint8 if minify else np.uint32)
     out_n = np.full(ndocs, 0xDEADBEEF, dtype=np.uint32)
     out_err = np.full(ndocs, 0xDEADBEEF, dtype=np.uint32)
     tb = tile_bytes()
@@ -132,5 +133,5 @@ def run(data: bytes, offsets=None, nblocks: int = 2, misalign: int = 0, ws: Work
     v = lib.emu_run(ctypes.c_void_p(base), offs.ctypes.data if offs is not None else None, n, ndocs,
                     out_idx.ctypes.data, out_cap, out_n.ctypes.data, out_err.ctypes.data, nblocks,
                     ws.mem.ctypes.data, ws.cap, tile_bytes() // 2048 if rows is None else rows,
-                    ctypes.c_void_p(glo), ctypes.c_void_p(ghi))
+                    ctypes.c_void_p(glo), ctypes.c_void_p(ghi), 1 if minify else 0)
     return out_idx, out_n, out_err, int(v)

@@ -131,3 +131,39 @@ def test_smaller_tiles(rows):
         L = 0 if r < 0.15 else (1 if r < 0.25 else int(rng.integers(2, 3000 if r < 0.9 else 3 * tb)))
         docs.append(_soup(rng, L))
     _check_batch(docs, 20, 3, 7, rows=rows)
+
+
+def _check_minify_single(d, nblocks, misalign, rows=None, block_tiles=None):
+    out, n, err, viol = emu.run(d, nblocks=nblocks, misalign=misalign, rows=rows, block_tiles=block_tiles,
+                                minify=True)
+    m, e = oracle.minify(d)
+    assert viol == 0
+    assert n[0] == len(m) and err[0] == e
+    assert out[:n[0]].tobytes() == m
+
+
+@pytest.mark.parametrize("rows", [None, 2, 0])
+def test_minify(rows):
+    """The minify pass (same kernel body, kept bytes as output) against the
+    oracle: soups over tile edges, long backslash runs, a pretty-printed
+    document, and a batch with empty and white-space-only documents."""
+    from paper_1902_08318_amd import synth
+    rng = np.random.default_rng(30 + (rows or 0))
+    tb = 2048 * (rows or 16)
+    for k in range(3):
+        _check_minify_single(_soup(rng, int(rng.integers(tb, 4 * tb))), int(rng.integers(1, 12)), k * 5, rows)
+    for run in (tb + 1, 5 * 1024 + 3):
+        d = b'[ "' + b"x " * (tb // 4) + b"\\" * run + b'" , 1 ] "z"  [1 ]'
+        _check_minify_single(d, 3, 0, rows)
+    _check_minify_single(synth.gen_c0(4, 3 * tb).data, 8, 1, rows)
+    docs = [b"", b"   ", b" 1 ", b'{ "a" : [ 1 , 2 ] }', b'"open ', b"\\"] + \
+           [_soup(rng, int(rng.integers(0, 3 * tb))) for _ in range(20)]
+    data = b"\x00" * 3 + b"".join(docs)
+    offs = np.concatenate([[3], 3 + np.cumsum([len(x) for x in docs])]).astype(np.uint64)
+    out, n, err, viol = emu.run(data, offsets=offs, nblocks=10, misalign=2, rows=rows, minify=True)
+    om, on, oe = oracle.minify_batch(np.frombuffer(data, dtype=np.uint8), offs)
+    assert viol == 0
+    assert np.array_equal(n, on) and np.array_equal(err, oe)
+    for d in range(len(docs)):
+        a = int(offs[d])
+        assert out[a:a + n[d]].tobytes() == om[a:a + on[d]].tobytes(), d

@@ -6,7 +6,8 @@ minified form of its dataset-size table) with ctypes.  Only the tests, the smoke
 benchmark may import this package; the HIP library never does.
 
 Flag bits (defined here independently of the HIP library's header):
-UTF8 = 0x1, UNCLOSED_STRING = 0x2, TRAILING_ESCAPE = 0x4, EMPTY = 0x8.
+UTF8 = 0x1, UNCLOSED_STRING = 0x2, TRAILING_ESCAPE = 0x4, EMPTY = 0x8; scope
+matching: UNBALANCED = 0x10, MISMATCHED = 0x20.
 """
 from __future__ import annotations
 
@@ -54,6 +55,8 @@ def _load():
     lib.oracle_minify.restype = ctypes.c_uint32
     lib.oracle_minify_batch.argtypes = [u8p, u64p, ctypes.c_uint32, u8p, u32p, u32p]
     lib.oracle_minify_batch.restype = ctypes.c_int
+    lib.oracle_scopes.argtypes = [u8p, u32p, ctypes.c_uint32, u32p, u32p]
+    lib.oracle_scopes.restype = ctypes.c_uint32
     lib.oracle_utf8_valid.argtypes = [u8p, ctypes.c_uint64]
     lib.oracle_utf8_valid.restype = ctypes.c_int
     _lib = lib
@@ -136,6 +139,26 @@ def minify_batch(bufs, offsets) -> tuple[np.ndarray, np.ndarray, np.ndarray]:
     if rc != 0:
         raise ValueError("offsets must be nondecreasing")
     return out[: int(off[-1])], out_n[:nd], out_err[:nd]
+
+
+ERR_UNBALANCED = 0x10
+ERR_MISMATCHED = 0x20
+
+
+def scopes(buf, idx) -> tuple[np.ndarray, int]:
+    """Scope matching over a document's index (positions idx into buf): the
+    partner entry of every bracket (0xFFFFFFFF if unlinked or not a bracket)
+    and the flags (UNBALANCED, MISMATCHED)."""
+    a = _u8(buf)
+    ix = np.ascontiguousarray(idx, dtype=np.uint32)
+    n = ix.size
+    match = np.empty(max(1, n), dtype=np.uint32)
+    stack = np.empty(max(1, n), dtype=np.uint32)
+    if n and int(ix.max()) >= a.size:
+        raise ValueError("positions exceed the document")
+    err = _load().oracle_scopes(_ptr(a, ctypes.c_uint8) if a.size else None, _ptr(ix, ctypes.c_uint32), n,
+                                _ptr(match, ctypes.c_uint32), _ptr(stack, ctypes.c_uint32))
+    return match[:n].copy(), int(err)
 
 
 def utf8_valid(buf) -> bool:

@@ -202,3 +202,36 @@ int oracle_minify_batch(const uint8_t *bufs, const uint64_t *offsets,
   }
   return 0;
 }
+
+/* Scope matching over a document's structural index (the scope links of the
+ * tape, Sec. 3 and Fig. 2: a scope start is linked to its end and back).  The
+ * entries are taken in order with a stack: an opening bracket ( { or [ ) is
+ * pushed; a closing bracket ( } or ] ) is linked with the entry on top of the
+ * stack, which is popped, and sets MISMATCHED if their kinds differ; a closing
+ * bracket with the stack empty is left unlinked and sets UNBALANCED, as does
+ * any opening bracket still on the stack at the end.  match[i] receives the
+ * entry number of i's partner, or 0xFFFFFFFF for unlinked brackets and for
+ * entries that are not brackets.  stack must have room for n entries.
+ * Returns the flags (0x10 UNBALANCED, 0x20 MISMATCHED). */
+uint32_t oracle_scopes(const uint8_t *buf, const uint32_t *idx, uint32_t n,
+                       uint32_t *match, uint32_t *stack) {
+  uint32_t top = 0, err = 0;
+  for (uint32_t i = 0; i < n; i++) {
+    uint8_t b = buf[idx[i]];
+    match[i] = 0xFFFFFFFFu;
+    if (b == 0x7B || b == 0x5B) {
+      stack[top++] = i;
+    } else if (b == 0x7D || b == 0x5D) {
+      if (top == 0) {
+        err |= 0x10u;
+      } else {
+        uint32_t j = stack[--top];
+        match[i] = j;
+        match[j] = i;
+        if ((buf[idx[j]] == 0x7B) != (b == 0x7D)) err |= 0x20u;
+      }
+    }
+  }
+  if (top) err |= 0x10u;
+  return err;
+}

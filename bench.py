@@ -219,6 +219,36 @@ def time_minify(jx, torch, data: bytes, offsets, steps: int, warmup: int = 2) ->
             "alg_GBps": round((n + kept + (16 * nd if offsets is not None else 0)) / (ms / 1e3) / 1e9, 1)}
 
 
+def time_scopes(jx, torch, data: bytes, steps: int) -> dict:
+    """Scope links over the document's index (jsidx_scopes), the index already
+    built and resident; two events around the launches."""
+    dev = torch.device("cuda:0")
+    n = len(data)
+    buf = torch.frombuffer(bytearray(data), dtype=torch.uint8).to(dev)
+    idx = torch.empty(n, dtype=torch.int32, device=dev)
+    cnt = torch.empty(1, dtype=torch.int32, device=dev)
+    err = torch.empty(1, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+    jx.build(buf, idx, cnt, err, stream)
+    k = int(cnt.item())
+    match = torch.empty(k, dtype=torch.int32, device=dev)
+    serr = torch.empty(1, dtype=torch.int32, device=dev)
+    call = lambda: jx.scopes(buf, idx, match, serr, stream, n=k)  # noqa: E731
+    for _ in range(2):
+        call()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(steps):
+        call()
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    return {"entries": k, "ms_per_call": round(ms, 4), "entries_per_s": round(k / (ms / 1e3)),
+            "flags": int(serr.item()) & 0xFFFFFFFF}
+
+
 def cpu_batch_baseline(data: bytes, offsets: np.ndarray, budget_s: float = 6.0) -> dict:
     """The oracle over a batch: one core, then the documents partitioned into
     contiguous byte-balanced ranges over every host core (one thread each; the
@@ -436,6 +466,8 @@ def main():
         extra["C2"] = {"bytes": r2["N"], "index_entries": r2["S"], "input_GBps": round(r2["N"] / (r2["ms_per_launch"] / 1e3) / 1e9, 2),
                        "alg_GBps": round((r2["N"] + 4 * r2["S"]) / (r2["ms_per_launch"] / 1e3) / 1e9, 1),
                        "ms_per_launch": round(r2["ms_per_launch"], 4), "launch_ms": r2["launch_ms"]}
+        log("scope links over the C1 index")
+        extra["scopes"] = {"C1": time_scopes(jx, torch, c1.data, max(3, args.steps // 2))}
         log("minify: C2 and the C3 batch")
         extra["minify"] = {"C2": time_minify(jx, torch, c2.data, None, args.steps)}
         del c2

@@ -62,6 +62,10 @@ typedef void *jsidx_stream_t;
                                           of backslashes                      */
 #define JSIDX_ERR_EMPTY 0x8u           /* the index is empty (empty or
                                           all-white-space document)           */
+#define JSIDX_ERR_UNBALANCED 0x10u      /* jsidx_scopes: a bracket has no
+                                          partner                             */
+#define JSIDX_ERR_MISMATCHED 0x20u      /* jsidx_scopes: a '{' linked with a
+                                          ']' or a '[' with a '}'             */
 #define JSIDX_ERR_CAPACITY 0x80000000u /* not indexed: the batch is larger
                                           than the stream's reserved
                                           workspace (out_n is 0)              */
@@ -136,6 +140,31 @@ int jsidx_minify(const uint8_t *buf, uint64_t len, uint8_t *out,
 int jsidx_minify_batch(const uint8_t *bufs, const uint64_t *offsets,
                        uint32_t ndocs, uint8_t *out, uint32_t *out_n,
                        uint32_t *out_err, jsidx_stream_t stream);
+
+/*
+ * jsidx_scopes -- the scope links of a document's structural index: the
+ * paper's tape links the start of each object or array to its end and back
+ * (Sec. 3, Fig. 2).  Entries are taken in order with a bracket stack: an
+ * opening bracket ({ or [) is pushed; a closing one (} or ]) is linked with
+ * the opener on top, which is popped (JSIDX_ERR_MISMATCHED if their kinds
+ * differ), or, with nothing open, left unlinked (JSIDX_ERR_UNBALANCED); an
+ * opener still open at the end is unlinked (JSIDX_ERR_UNBALANCED).
+ *   buf        device pointer to the document's `len` bytes, len < 2^32.
+ *   idx        device array of the document's n index entries, as jsidx_build
+ *              writes them (positions below len; a position at or past len
+ *              counts as a non-bracket entry and is never read).
+ *   out_match  device array of n uint32: the entry number of each bracket's
+ *              partner, 0xFFFFFFFF for unlinked brackets and other entries.
+ *   out_err    device uint32: 0 or the two flags above.
+ * The computation is parallel (depth by a scan of clamped depth changes,
+ * then each opener's partner is the first later entry of at most its depth)
+ * and gives exactly the stack's links.  A per-stream workspace of about
+ * 9 bytes per entry is allocated on first use and grown as needed
+ * (synchronising the stream).  Asynchronous on `stream`.
+ */
+int jsidx_scopes(const uint8_t *buf, uint64_t len, const uint32_t *idx,
+                 uint32_t n, uint32_t *out_match, uint32_t *out_err,
+                 jsidx_stream_t stream);
 
 /*
  * jsidx_reserve -- size the workspace of `stream` for inputs of up to

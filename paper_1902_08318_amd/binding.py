@@ -14,6 +14,8 @@ ERR_UTF8 = 0x1
 ERR_UNCLOSED_STRING = 0x2
 ERR_TRAILING_ESCAPE = 0x4
 ERR_EMPTY = 0x8
+ERR_UNBALANCED = 0x10
+ERR_MISMATCHED = 0x20
 ERR_CAPACITY = 0x80000000
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -27,6 +29,7 @@ SIGNATURES = {
     "jsidx_build_batch": ([_VP, _VP, ctypes.c_uint32, _VP, _VP, _VP, _VP], ctypes.c_int),
     "jsidx_minify": ([_VP, ctypes.c_uint64, _VP, _VP, _VP, _VP], ctypes.c_int),
     "jsidx_minify_batch": ([_VP, _VP, ctypes.c_uint32, _VP, _VP, _VP, _VP], ctypes.c_int),
+    "jsidx_scopes": ([_VP, ctypes.c_uint64, _VP, ctypes.c_uint32, _VP, _VP, _VP], ctypes.c_int),
     "jsidx_reserve": ([ctypes.c_uint64, _VP], ctypes.c_int),
     "jsidx_workspace_bytes": ([ctypes.c_uint64], ctypes.c_size_t),
     "jsidx_release": ([_VP], ctypes.c_int),
@@ -109,6 +112,14 @@ def minify_batch(bufs, offsets, out, out_n, out_err, stream=None):
     nd = offsets.numel() - 1
     _check(lib().jsidx_minify_batch(_ptr(bufs), _ptr(offsets), nd, _ptr(out), _ptr(out_n), _ptr(out_err),
                                     _stream(stream)))
+
+
+def scopes(buf, idx, out_match, out_err, stream=None, n=None, length=None):
+    """jsidx_scopes on device tensors: buf (uint8, the document), idx (the
+    first n index entries), out_match (n uint32/int32), out_err (1)."""
+    n = idx.numel() if n is None else int(n)
+    ln = buf.numel() if length is None else int(length)
+    _check(lib().jsidx_scopes(_ptr(buf), ln, _ptr(idx), n, _ptr(out_match), _ptr(out_err), _stream(stream)))
 
 
 def reserve(max_total_len: int, stream=None):

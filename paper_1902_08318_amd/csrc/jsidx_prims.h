@@ -102,6 +102,8 @@ JSIDX_DEV void trace_count(int64_t, int) {}
 JSIDX_DEV uint4 load16(const uint8_t* p) { return *reinterpret_cast<const uint4*>(p); }
 JSIDX_DEV uint32_t load4(const uint8_t* p) { return *reinterpret_cast<const uint32_t*>(p); }
 JSIDX_DEV uint64_t load8(const uint64_t* p) { return *p; }
+JSIDX_DEV uint32_t load1(const uint8_t* p) { return *p; }
+JSIDX_DEV uint32_t or_agent32(uint32_t* p, uint32_t v) { return atomicOr(p, v); }
 JSIDX_DEV void st_out(uint32_t* p, uint32_t v) { *p = v; }
 JSIDX_DEV void st_byte(uint8_t* p, uint32_t v) { *p = (uint8_t)v; }
 JSIDX_DEV void st_pair(uint2* p, uint32_t x, uint32_t y) { *p = make_uint2(x, y); }

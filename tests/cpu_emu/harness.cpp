@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "jsidx_kernel.h"
+#include "jsidx_scopes.h"
 
 namespace jsidx {
 namespace prim {
@@ -77,6 +78,66 @@ long emu_run(const uint8_t* base, const uint64_t* offsets, uint64_t len, uint32_
   for (auto* g : groups) delete g;
   return env.violations.load();
 }
+
+// The scope-link kernels, each run as a grid of workgroups of kScopeThreads
+// threads, in launch order.  Returns the number of out-of-range accesses.
+long emu_scopes_run(const uint8_t* buf, uint64_t len, const uint32_t* idx, uint32_t n, uint32_t* match,
+                    uint32_t* err, void* ws, int far_groups) {
+  const ScopeLayout L = scope_layout(n);
+  prim::EmuEnv env;
+  if (len) env.reads[env.nreads++] = {buf, buf + len};
+  if (n) env.reads[env.nreads++] = {idx, idx + n};
+  env.writes[env.nwrites++] = {match, match + n};
+  env.writes[env.nwrites++] = {err, err + 1};
+  env.writes[env.nwrites++] = {ws, (const uint8_t*)ws + L.total};
+  env.reads[env.nreads++] = {ws, (const uint8_t*)ws + L.total};
+  env.reads[env.nreads++] = {match, match + n};
+  uint8_t* m = static_cast<uint8_t*>(ws);
+  ScopeArgs a;
+  a.buf = buf;
+  a.len = len;
+  a.idx = idx;
+  a.n = n;
+  a.nchunks = (uint32_t)((n + (uint64_t)kScopeChunk - 1) / kScopeChunk);
+  a.match = match;
+  a.err = err;
+  a.chunk_fn = reinterpret_cast<uint2*>(m + L.chunk_fn);
+  a.in_depth = reinterpret_cast<uint2*>(m + L.in_depth);
+  a.chunk_min = reinterpret_cast<uint32_t*>(m + L.chunk_min);
+  a.qcount = reinterpret_cast<uint32_t*>(m + L.qcount);
+  a.lev = reinterpret_cast<uint32_t*>(m + L.lev);
+  a.queue = reinterpret_cast<uint32_t*>(m + L.queue);
+  a.kind = m + L.kind;
+  auto phase = [&](int ngroups, void (*body)(const ScopeArgs&)) {
+    std::vector<prim::GroupCtx*> groups;
+    for (int b = 0; b < ngroups; b++) groups.push_back(new prim::GroupCtx(kScopeThreads));
+    std::vector<std::thread> th;
+    for (int b = 0; b < ngroups; b++) {
+      for (uint32_t t = 0; t < (uint32_t)kScopeThreads; t++) {
+        th.emplace_back([&, b, t] {
+          prim::tctx.tid = t;
+          prim::tctx.block = (uint32_t)b;
+          prim::tctx.grid = (uint32_t)ngroups;
+          prim::tctx.g = groups[(size_t)b];
+          prim::tctx.env = &env;
+          body(a);
+        });
+      }
+    }
+    for (auto& x : th) x.join();
+    for (auto* g : groups) delete g;
+  };
+  if (a.nchunks) phase((int)a.nchunks, scope_chunk_fn);
+  phase(1, scope_scan);
+  if (a.nchunks) {
+    phase((int)a.nchunks, scope_levels);
+    phase((int)a.nchunks, scope_local);
+    phase(far_groups, scope_far);
+  }
+  return env.violations.load();
+}
+
+uint64_t emu_scopes_ws_bytes(uint64_t n) { return scope_layout(n).total; }
 
 uint64_t emu_ws_bytes(uint64_t cap_tiles) { return workspace_bytes(cap_tiles); }
 uint32_t emu_tile_bytes() { return (uint32_t)kTileBytes; }

@@ -204,6 +204,7 @@ inline uint32_t ld_agent32(const uint32_t* p) { return __atomic_load_n(p, __ATOM
 inline void st_agent(uint64_t* p, uint64_t v) { __atomic_store_n(p, v, __ATOMIC_RELAXED); }
 inline void st_agent32(uint32_t* p, uint32_t v) { __atomic_store_n(p, v, __ATOMIC_RELAXED); }
 inline uint32_t add_agent32(uint32_t* p, uint32_t v) { return __atomic_fetch_add(p, v, __ATOMIC_RELAXED); }
+inline uint32_t or_agent32(uint32_t* p, uint32_t v) { return __atomic_fetch_or(p, v, __ATOMIC_RELAXED); }
 inline void min_lds(int32_t* p, int32_t v) {
   int32_t cur = __atomic_load_n(p, __ATOMIC_RELAXED);
   while (v < cur && !__atomic_compare_exchange_n(p, &cur, v, false, __ATOMIC_RELAXED, __ATOMIC_RELAXED)) {
@@ -234,6 +235,10 @@ inline uint32_t load4(const uint8_t* p) {
   uint32_t v;
   memcpy(&v, p, 4);
   return v;
+}
+inline uint32_t load1(const uint8_t* p) {
+  check(p, 1, false);
+  return *p;
 }
 inline uint64_t load8(const uint64_t* p) {
   check(p, 8, false);

@@ -57,6 +57,10 @@ def load(block_tiles: int | None = None):
     lib.emu_run.argtypes = [vp, vp, ctypes.c_uint64, ctypes.c_uint32, vp, ctypes.c_uint64, vp, vp,
                             ctypes.c_int, vp, ctypes.c_uint64, ctypes.c_uint32, vp, vp, ctypes.c_int]
     lib.emu_run.restype = ctypes.c_long
+    lib.emu_scopes_run.argtypes = [vp, ctypes.c_uint64, vp, ctypes.c_uint32, vp, vp, vp, ctypes.c_int]
+    lib.emu_scopes_run.restype = ctypes.c_long
+    lib.emu_scopes_ws_bytes.argtypes = [ctypes.c_uint64]
+    lib.emu_scopes_ws_bytes.restype = ctypes.c_uint64
     lib.emu_ws_bytes.argtypes = [ctypes.c_uint64]
     lib.emu_ws_bytes.restype = ctypes.c_uint64
     lib.emu_tile_bytes.restype = ctypes.c_uint32
@@ -135,3 +139,19 @@ def run(data: bytes, offsets=None, nblocks: int = 2, misalign: int = 0, ws: Work
                     ws.mem.ctypes.data, ws.cap, tile_bytes() // 2048 if rows is None else rows,
                     ctypes.c_void_p(glo), ctypes.c_void_p(ghi), 1 if minify else 0)
     return out_idx, out_n, out_err, int(v)
+
+
+def scopes(data: bytes, idx: np.ndarray, far_groups: int = 2, garbage_ws: bool = True):
+    """Scope links through the emulated scope kernels.  Returns (match, err,
+    violations).  The workspace starts full of garbage (the kernels must not
+    rely on it being zero)."""
+    lib = load()
+    n = int(idx.size)
+    buf = np.frombuffer(data, dtype=np.uint8) if data else np.zeros(1, dtype=np.uint8)
+    ix = np.ascontiguousarray(idx, dtype=np.uint32) if n else np.zeros(1, dtype=np.uint32)
+    match = np.full(max(1, n), 0xABABABAB, dtype=np.uint32)
+    err = np.full(1, 0xABABABAB, dtype=np.uint32)
+    ws = np.full(int(lib.emu_scopes_ws_bytes(n)) // 4 + 64, 0x5A5A5A5A if garbage_ws else 0, dtype=np.uint32)
+    v = lib.emu_scopes_run(buf.ctypes.data, len(data), ix.ctypes.data, n, match.ctypes.data, err.ctypes.data,
+                           ws.ctypes.data, far_groups)
+    return match[:n], int(err[0]), int(v)

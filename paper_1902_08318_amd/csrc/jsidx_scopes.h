@@ -111,10 +111,21 @@ JSIDX_DEV uint32_t kind_at(const ScopeArgs& a, uint32_t i) {
 struct ScopeGroup {
   DepthFn f[kScopeThreads];
   uint32_t m[kScopeThreads];
-  uint32_t L[kScopeChunk];
+  uint32_t L[kScopeChunk];  // levels of the chunk's entries
+  uint8_t K[kScopeChunk];   // kinds of the chunk's entries
 };
 
 JSIDX_DEV uint32_t scope_tid() { return prim::wave_id() * kScopeWave + prim::lane(); }
+
+// The kinds of chunk c's entries into LDS: consecutive threads read
+// consecutive entries (coalesced), then each thread works on its own run of
+// kScopePer entries in LDS.
+JSIDX_DEV void load_kinds(const ScopeArgs& a, ScopeGroup& g, uint32_t tid, uint32_t c) {
+  const uint64_t c0 = (uint64_t)c * kScopeChunk;
+  for (uint32_t j = tid; j < (uint32_t)kScopeChunk; j += kScopeThreads)
+    g.K[j] = (uint8_t)(c0 + j < a.n ? kind_at(a, (uint32_t)(c0 + j)) : kOther);
+  prim::sync();
+}
 
 // Ordered inclusive scan of the workgroup's per-thread functions; returns the
 // composition of the threads before this one.
@@ -136,10 +147,9 @@ JSIDX_DEV DepthFn group_exclusive(ScopeGroup& g, uint32_t tid, DepthFn mine) {
 JSIDX_DEVFN void scope_chunk_fn(const ScopeArgs& a) {
   ScopeGroup& g = prim::lds_object<ScopeGroup>();
   const uint32_t tid = scope_tid(), c = prim::block();
-  const uint64_t i0 = (uint64_t)c * kScopeChunk + (uint64_t)tid * kScopePer;
+  load_kinds(a, g, tid, c);
   DepthFn f = fn_id();
-  for (int k = 0; k < kScopePer; k++)
-    if (i0 + k < a.n) f = fn_then(f, fn_of(kind_at(a, (uint32_t)(i0 + k))));
+  for (int k = 0; k < kScopePer; k++) f = fn_then(f, fn_of(g.K[tid * kScopePer + k]));
   const DepthFn ex = group_exclusive(g, tid, f);
   if (tid == kScopeThreads - 1) {
     const DepthFn all = fn_then(ex, f);
@@ -179,22 +189,16 @@ JSIDX_DEVFN void scope_scan(const ScopeArgs& a) {
 JSIDX_DEVFN void scope_levels(const ScopeArgs& a) {
   ScopeGroup& g = prim::lds_object<ScopeGroup>();
   const uint32_t tid = scope_tid(), c = prim::block();
-  const uint64_t i0 = (uint64_t)c * kScopeChunk + (uint64_t)tid * kScopePer;
-  uint32_t kinds[kScopePer];
+  const uint64_t c0 = (uint64_t)c * kScopeChunk;
+  load_kinds(a, g, tid, c);
   DepthFn f = fn_id();
-#pragma unroll
-  for (int k = 0; k < kScopePer; k++) {
-    kinds[k] = i0 + k < a.n ? kind_at(a, (uint32_t)(i0 + k)) : kOther;
-    f = fn_then(f, fn_of(kinds[k]));
-  }
+  for (int k = 0; k < kScopePer; k++) f = fn_then(f, fn_of(g.K[tid * kScopePer + k]));
   const DepthFn ex = group_exclusive(g, tid, f);
   int64_t d = fn_apply(ex, unpack64(prim::ld_pair(a.in_depth + c)));
   uint32_t lo_level = kNoLevel, unmatched = 0;
-#pragma unroll
   for (int k = 0; k < kScopePer; k++) {
-    const uint64_t i = i0 + k;
-    if (i >= a.n) continue;
-    uint32_t kd = kinds[k], level = kNoLevel;
+    const uint32_t j = tid * kScopePer + (uint32_t)k;
+    uint32_t kd = g.K[j], level = kNoLevel;
     if (kd == kOpenSq || kd == kOpenCu) {
       level = (uint32_t)d;
       d++;
@@ -207,14 +211,20 @@ JSIDX_DEVFN void scope_levels(const ScopeArgs& a) {
         unmatched = 1;
       }
     }
-    prim::st_out(a.lev + i, level);
-    prim::st_byte(a.kind + i, kd);
-    prim::st_out(a.match + i, kUnlinked);
+    g.L[j] = level;
+    g.K[j] = (uint8_t)kd;
     if (level < lo_level) lo_level = level;
   }
   if (unmatched) prim::or_agent32(a.err, kErrUnbalanced);
   g.m[tid] = lo_level;
   prim::sync();
+  // the chunk's levels, kinds and cleared links go out as consecutive words
+  for (uint32_t j = tid; j < (uint32_t)kScopeChunk; j += kScopeThreads) {
+    if (c0 + j >= a.n) break;
+    prim::st_out(a.lev + c0 + j, g.L[j]);
+    prim::st_byte(a.kind + c0 + j, g.K[j]);
+    prim::st_out(a.match + c0 + j, kUnlinked);
+  }
   for (uint32_t s = kScopeThreads / 2; s > 0; s >>= 1) {
     if (tid < s && g.m[tid + s] < g.m[tid]) g.m[tid] = g.m[tid + s];
     prim::sync();
@@ -236,18 +246,38 @@ JSIDX_DEVFN void scope_local(const ScopeArgs& a) {
   const uint32_t tid = scope_tid(), c = prim::block();
   const uint64_t c0 = (uint64_t)c * kScopeChunk;
   const uint32_t cend = a.n - c0 < (uint64_t)kScopeChunk ? (uint32_t)(a.n - c0) : (uint32_t)kScopeChunk;
-  for (uint32_t j = tid; j < (uint32_t)kScopeChunk; j += kScopeThreads)
+  for (uint32_t j = tid; j < (uint32_t)kScopeChunk; j += kScopeThreads) {
     g.L[j] = j < cend ? prim::load4(reinterpret_cast<const uint8_t*>(a.lev + c0 + j)) : kNoLevel;
+    g.K[j] = (uint8_t)(j < cend ? prim::load1(a.kind + c0 + j) : kOther);
+  }
+  prim::sync();
+  // lowest level of each thread's run of kScopePer entries
+  uint32_t gmin = kNoLevel;
+  for (int k = 0; k < kScopePer; k++) {
+    const uint32_t v = g.L[tid * kScopePer + k];
+    gmin = v < gmin ? v : gmin;
+  }
+  g.m[tid] = gmin;
   prim::sync();
   for (int k = 0; k < kScopePer; k++) {
     const uint32_t j = tid * kScopePer + (uint32_t)k;
     if (j >= cend) break;
     const uint32_t i = (uint32_t)(c0 + j);
-    const uint32_t ki = prim::load1(a.kind + i);
+    const uint32_t ki = g.K[j];
     if (ki != kOpenSq && ki != kOpenCu) continue;
     const uint32_t lv = g.L[j];
+    // the rest of this run, then whole runs by their lowest level, then
+    // inside the first run that can hold the closer
     uint32_t p = j + 1;
-    while (p < cend && g.L[p] > lv) p++;
+    const uint32_t run_end = (tid + 1) * kScopePer;
+    while (p < run_end && g.L[p] > lv) p++;
+    if (p >= run_end) {
+      uint32_t r = tid + 1;
+      while (r < (uint32_t)kScopeThreads && g.m[r] > lv) r++;
+      p = r * kScopePer;
+      if (r < (uint32_t)kScopeThreads)
+        while (g.L[p] > lv) p++;  // ends inside run r: its lowest level is at most lv
+    }
     if (p < cend) {
       link(a, i, (uint32_t)(c0 + p), ki);
     } else {

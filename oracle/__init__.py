@@ -7,7 +7,7 @@ benchmark may import this package; the HIP library never does.
 
 Flag bits (defined here independently of the HIP library's header):
 UTF8 = 0x1, UNCLOSED_STRING = 0x2, TRAILING_ESCAPE = 0x4, EMPTY = 0x8; scope
-matching: UNBALANCED = 0x10, MISMATCHED = 0x20.
+matching: UNBALANCED = 0x10, MISMATCHED = 0x20; structure: SYNTAX = 0x40.
 """
 from __future__ import annotations
 
@@ -57,6 +57,8 @@ def _load():
     lib.oracle_minify_batch.restype = ctypes.c_int
     lib.oracle_scopes.argtypes = [u8p, u32p, ctypes.c_uint32, u32p, u32p]
     lib.oracle_scopes.restype = ctypes.c_uint32
+    lib.oracle_structure.argtypes = [u8p, u32p, ctypes.c_uint32, u32p]
+    lib.oracle_structure.restype = ctypes.c_uint32
     lib.oracle_utf8_valid.argtypes = [u8p, ctypes.c_uint64]
     lib.oracle_utf8_valid.restype = ctypes.c_int
     _lib = lib
@@ -159,6 +161,21 @@ def scopes(buf, idx) -> tuple[np.ndarray, int]:
     err = _load().oracle_scopes(_ptr(a, ctypes.c_uint8) if a.size else None, _ptr(ix, ctypes.c_uint32), n,
                                 _ptr(match, ctypes.c_uint32), _ptr(stack, ctypes.c_uint32))
     return match[:n].copy(), int(err)
+
+
+ERR_SYNTAX = 0x40
+
+
+def structure(buf, idx) -> int:
+    """0, or ERR_SYNTAX if the index entries' tokens do not form one JSON value
+    (token contents are not checked)."""
+    a = _u8(buf)
+    ix = np.ascontiguousarray(idx, dtype=np.uint32)
+    stack = np.empty(max(1, ix.size), dtype=np.uint32)
+    if ix.size and int(ix.max()) >= a.size:
+        raise ValueError("positions exceed the document")
+    return int(_load().oracle_structure(_ptr(a, ctypes.c_uint8) if a.size else None, _ptr(ix, ctypes.c_uint32),
+                                        ix.size, _ptr(stack, ctypes.c_uint32)))
 
 
 def utf8_valid(buf) -> bool:

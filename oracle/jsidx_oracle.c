@@ -235,3 +235,82 @@ uint32_t oracle_scopes(const uint8_t *buf, const uint32_t *idx, uint32_t n,
   if (top) err |= 0x10u;
   return err;
 }
+
+/* Structure of a document's index entries against the JSON grammar (the
+ * structural-sequence check that follows the index, Sec. 3.2): each entry is a
+ * token -- { } [ ] : , an opening quote (a string) or anything else (the start
+ * of a number or literal, an "atom") -- and the tokens must form exactly one
+ * value: objects hold "string : value" members separated by commas, arrays
+ * hold values separated by commas, nothing follows the root value, and the
+ * document is not empty.  Token contents (digits, escapes) are not checked.
+ * Returns 0x40 (SYNTAX) if the sequence is not valid, else 0.  stack needs
+ * room for n entries. */
+enum { OT_OBJ = 1, OT_ARR, OT_CLOSE_OBJ, OT_CLOSE_ARR, OT_COLON, OT_COMMA, OT_STR, OT_ATOM };
+enum { ST_VALUE, ST_DONE, ST_KEY_OR_CLOSE, ST_COLON, ST_OBJ_VALUE, ST_OBJ_NEXT, ST_KEY,
+       ST_VALUE_OR_CLOSE, ST_ARR_VALUE, ST_ARR_NEXT };
+
+static int token_of(uint8_t b) {
+  switch (b) {
+    case 0x7B: return OT_OBJ;
+    case 0x5B: return OT_ARR;
+    case 0x7D: return OT_CLOSE_OBJ;
+    case 0x5D: return OT_CLOSE_ARR;
+    case 0x3A: return OT_COLON;
+    case 0x2C: return OT_COMMA;
+    case 0x22: return OT_STR;
+    default: return OT_ATOM;
+  }
+}
+
+uint32_t oracle_structure(const uint8_t *buf, const uint32_t *idx, uint32_t n,
+                          uint32_t *stack) {
+  /* stack holds, per open scope, the state to return to in the parent */
+  uint32_t top = 0;
+  int st = ST_VALUE;  /* the root expects one value */
+  for (uint32_t i = 0; i < n; i++) {
+    int t = token_of(buf[idx[i]]);
+    int value_start = (t == OT_OBJ || t == OT_ARR || t == OT_STR || t == OT_ATOM);
+    switch (st) {
+      case ST_VALUE: case ST_OBJ_VALUE: case ST_ARR_VALUE: case ST_VALUE_OR_CLOSE:
+        if (st == ST_VALUE_OR_CLOSE && t == OT_CLOSE_ARR) {
+          if (top == 0) return 0x40u;
+          st = (int)stack[--top];
+          break;
+        }
+        if (!value_start) return 0x40u;
+        {
+          int after = st == ST_VALUE ? ST_DONE : (st == ST_OBJ_VALUE ? ST_OBJ_NEXT : ST_ARR_NEXT);
+          if (t == OT_OBJ) { stack[top++] = (uint32_t)after; st = ST_KEY_OR_CLOSE; }
+          else if (t == OT_ARR) { stack[top++] = (uint32_t)after; st = ST_VALUE_OR_CLOSE; }
+          else st = after;
+        }
+        break;
+      case ST_KEY_OR_CLOSE: case ST_KEY:
+        if (st == ST_KEY_OR_CLOSE && t == OT_CLOSE_OBJ) {
+          if (top == 0) return 0x40u;
+          st = (int)stack[--top];
+          break;
+        }
+        if (t != OT_STR) return 0x40u;
+        st = ST_COLON;
+        break;
+      case ST_COLON:
+        if (t != OT_COLON) return 0x40u;
+        st = ST_OBJ_VALUE;
+        break;
+      case ST_OBJ_NEXT:
+        if (t == OT_COMMA) { st = ST_KEY; break; }
+        if (t != OT_CLOSE_OBJ || top == 0) return 0x40u;
+        st = (int)stack[--top];
+        break;
+      case ST_ARR_NEXT:
+        if (t == OT_COMMA) { st = ST_ARR_VALUE; break; }
+        if (t != OT_CLOSE_ARR || top == 0) return 0x40u;
+        st = (int)stack[--top];
+        break;
+      default: /* ST_DONE: nothing may follow the root value */
+        return 0x40u;
+    }
+  }
+  return st == ST_DONE ? 0u : 0x40u;
+}

@@ -66,6 +66,8 @@ typedef void *jsidx_stream_t;
                                           partner                             */
 #define JSIDX_ERR_MISMATCHED 0x20u      /* jsidx_scopes: a '{' linked with a
                                           ']' or a '[' with a '}'             */
+#define JSIDX_ERR_SYNTAX 0x40u          /* jsidx_scopes: the entries' tokens
+                                          do not form one JSON value          */
 #define JSIDX_ERR_CAPACITY 0x80000000u /* not indexed: the batch is larger
                                           than the stream's reserved
                                           workspace (out_n is 0)              */
@@ -149,17 +151,26 @@ int jsidx_minify_batch(const uint8_t *bufs, const uint64_t *offsets,
  * the opener on top, which is popped (JSIDX_ERR_MISMATCHED if their kinds
  * differ), or, with nothing open, left unlinked (JSIDX_ERR_UNBALANCED); an
  * opener still open at the end is unlinked (JSIDX_ERR_UNBALANCED).
+ * It also checks the structure the way the paper's stage 2 does while it
+ * builds the tape (Sec. 3.2): taking each entry as a token (a bracket, ':',
+ * ',', a string at '"', any other byte an atom), the sequence must be one
+ * JSON value -- each token allowed after the one before it, with a ','
+ * followed by a key in an object and by a value in an array, a key followed
+ * by ':' -- else JSIDX_ERR_SYNTAX, which an empty index, JSIDX_ERR_UNBALANCED
+ * and JSIDX_ERR_MISMATCHED always imply.  Token contents (numbers, literals,
+ * string escapes) are not checked.
  *   buf        device pointer to the document's `len` bytes, len < 2^32.
  *   idx        device array of the document's n index entries, as jsidx_build
  *              writes them (positions below len; a position at or past len
  *              counts as a non-bracket entry and is never read).
  *   out_match  device array of n uint32: the entry number of each bracket's
  *              partner, 0xFFFFFFFF for unlinked brackets and other entries.
- *   out_err    device uint32: 0 or the two flags above.
+ *   out_err    device uint32: 0 or the three flags above.
  * The computation is parallel (depth by a scan of clamped depth changes,
- * then each opener's partner is the first later entry of at most its depth)
- * and gives exactly the stack's links.  A per-stream workspace of about
- * 9 bytes per entry is allocated on first use and grown as needed
+ * then each opener's partner, and the closer of each comma's scope, is the
+ * first later entry of at most its depth) and gives exactly the stack's
+ * links; the structure check then looks at each entry and the one or two
+ * before it.  A per-stream workspace of about 18 bytes per entry is allocated on first use and grown as needed
  * (synchronising the stream).  Asynchronous on `stream`.
  */
 int jsidx_scopes(const uint8_t *buf, uint64_t len, const uint32_t *idx,

@@ -16,6 +16,7 @@ ERR_TRAILING_ESCAPE = 0x4
 ERR_EMPTY = 0x8
 ERR_UNBALANCED = 0x10
 ERR_MISMATCHED = 0x20
+ERR_SYNTAX = 0x40
 ERR_CAPACITY = 0x80000000
 
 _HERE = os.path.dirname(os.path.abspath(__file__))

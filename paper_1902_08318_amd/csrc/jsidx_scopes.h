@@ -36,7 +36,9 @@ constexpr uint32_t kNoLevel = 0xFFFFFFFFu;
 constexpr uint32_t kUnlinked = 0xFFFFFFFFu;
 constexpr uint32_t kErrUnbalanced = 0x10u;
 constexpr uint32_t kErrMismatched = 0x20u;
-enum : uint32_t { kOther = 0, kOpenSq = 1, kOpenCu = 2, kCloseSq = 3, kCloseCu = 4 };
+constexpr uint32_t kErrSyntax = 0x40u;
+// Token of an index entry: atoms (numbers, literals, anything else) are kOther.
+enum : uint32_t { kOther = 0, kOpenSq = 1, kOpenCu = 2, kCloseSq = 3, kCloseCu = 4, kColon = 5, kComma = 6, kStr = 7 };
 
 struct DepthFn {  // x -> max(x + a, b)
   int64_t a, b;
@@ -68,14 +70,17 @@ struct ScopeArgs {
   uint2* in_depth;      // per chunk
   uint32_t* chunk_min;  // per chunk: lowest level
   uint32_t* qcount;     // scopes that leave their chunk
-  uint32_t* lev;        // per entry
-  uint8_t* kind;        // per entry
+  uint32_t* lev;        // per entry: level of a bracket (kNoLevel otherwise)
+  uint32_t* qt;         // per entry: threshold of its search (openers, commas)
+  uint32_t* dep;        // per entry: depth before it
+  uint8_t* kind;        // per entry: token
+  uint8_t* ck;          // per comma: the closing bracket of its scope
   uint32_t* queue;      // per entry at most
 };
 
 // Workspace layout for n entries (byte offsets; host side).
 struct ScopeLayout {
-  uint64_t chunk_fn, in_depth, chunk_min, qcount, lev, queue, kind, total;
+  uint64_t chunk_fn, in_depth, chunk_min, qcount, lev, qt, dep, queue, kind, ck, total;
 };
 inline uint64_t scope_align256(uint64_t x) { return (x + 255) & ~(uint64_t)255; }
 inline ScopeLayout scope_layout(uint64_t n) {
@@ -87,8 +92,11 @@ inline ScopeLayout scope_layout(uint64_t n) {
   L.chunk_min = o; o = scope_align256(o + nc * 4);
   L.qcount = o; o = scope_align256(o + 4);
   L.lev = o; o = scope_align256(o + n * 4);
+  L.qt = o; o = scope_align256(o + n * 4);
+  L.dep = o; o = scope_align256(o + n * 4);
   L.queue = o; o = scope_align256(o + n * 4);
   L.kind = o; o = scope_align256(o + n);
+  L.ck = o; o = scope_align256(o + n);
   L.total = o;
   return L;
 }
@@ -105,14 +113,16 @@ JSIDX_DEV uint32_t kind_at(const ScopeArgs& a, uint32_t i) {
   const uint32_t p = prim::load4(reinterpret_cast<const uint8_t*>(a.idx + i));
   if ((uint64_t)p >= a.len) return kOther;  // not a position of this document
   const uint32_t b = prim::load1(a.buf + p);
-  return b == 0x5Bu ? kOpenSq : b == 0x7Bu ? kOpenCu : b == 0x5Du ? kCloseSq : b == 0x7Du ? kCloseCu : kOther;
+  return b == 0x5Bu ? kOpenSq : b == 0x7Bu ? kOpenCu : b == 0x5Du ? kCloseSq : b == 0x7Du ? kCloseCu
+       : b == 0x3Au ? kColon : b == 0x2Cu ? kComma : b == 0x22u ? kStr : kOther;
 }
 
 struct ScopeGroup {
   DepthFn f[kScopeThreads];
   uint32_t m[kScopeThreads];
   uint32_t L[kScopeChunk];  // levels of the chunk's entries
-  uint8_t K[kScopeChunk];   // kinds of the chunk's entries
+  uint32_t T[kScopeChunk];  // search thresholds (scope_local), depths (scope_levels)
+  uint8_t K[kScopeChunk];   // tokens of the chunk's entries
 };
 
 JSIDX_DEV uint32_t scope_tid() { return prim::wave_id() * kScopeWave + prim::lane(); }
@@ -179,7 +189,7 @@ JSIDX_DEVFN void scope_scan(const ScopeArgs& a) {
     x = fn_apply(fc, x);
   }
   if (tid == 0) {
-    prim::st_out(a.err, 0u);
+    prim::st_out(a.err, a.n ? 0u : kErrSyntax);  // an empty index holds no value
     prim::st_out(a.qcount, 0u);
   }
 }
@@ -199,6 +209,7 @@ JSIDX_DEVFN void scope_levels(const ScopeArgs& a) {
   for (int k = 0; k < kScopePer; k++) {
     const uint32_t j = tid * kScopePer + (uint32_t)k;
     uint32_t kd = g.K[j], level = kNoLevel;
+    g.T[j] = (uint32_t)d;
     if (kd == kOpenSq || kd == kOpenCu) {
       level = (uint32_t)d;
       d++;
@@ -221,8 +232,15 @@ JSIDX_DEVFN void scope_levels(const ScopeArgs& a) {
   // the chunk's levels, kinds and cleared links go out as consecutive words
   for (uint32_t j = tid; j < (uint32_t)kScopeChunk; j += kScopeThreads) {
     if (c0 + j >= a.n) break;
+    const uint32_t kd = g.K[j], dj = g.T[j];
+    // search threshold: an opener looks for its closer, a comma for the
+    // closer of its scope (none at the root)
+    const uint32_t qt = (kd == kOpenSq || kd == kOpenCu) ? dj : (kd == kComma && dj > 0 ? dj - 1u : kNoLevel);
     prim::st_out(a.lev + c0 + j, g.L[j]);
-    prim::st_byte(a.kind + c0 + j, g.K[j]);
+    prim::st_out(a.qt + c0 + j, qt);
+    prim::st_out(a.dep + c0 + j, dj);
+    prim::st_byte(a.kind + c0 + j, kd);
+    prim::st_byte(a.ck + c0 + j, 0u);
     prim::st_out(a.match + c0 + j, kUnlinked);
   }
   for (uint32_t s = kScopeThreads / 2; s > 0; s >>= 1) {
@@ -232,10 +250,16 @@ JSIDX_DEVFN void scope_levels(const ScopeArgs& a) {
   if (tid == 0) prim::st_out(a.chunk_min + c, g.m[0]);
 }
 
-JSIDX_DEV void link(const ScopeArgs& a, uint32_t i, uint32_t k, uint32_t ki) {
+// The search of entry i (token ki) ended at entry k: an opener is linked with
+// its closer, a comma learns the closer of its scope.
+JSIDX_DEV void resolve(const ScopeArgs& a, uint32_t i, uint32_t k, uint32_t ki) {
+  const uint32_t kk = prim::load1(a.kind + k);
+  if (ki == kComma) {
+    prim::st_byte(a.ck + i, kk);
+    return;
+  }
   prim::st_out(a.match + i, k);
   prim::st_out(a.match + k, i);
-  const uint32_t kk = prim::load1(a.kind + k);
   if ((ki == kOpenCu) != (kk == kCloseCu)) prim::or_agent32(a.err, kErrMismatched);
 }
 
@@ -248,6 +272,7 @@ JSIDX_DEVFN void scope_local(const ScopeArgs& a) {
   const uint32_t cend = a.n - c0 < (uint64_t)kScopeChunk ? (uint32_t)(a.n - c0) : (uint32_t)kScopeChunk;
   for (uint32_t j = tid; j < (uint32_t)kScopeChunk; j += kScopeThreads) {
     g.L[j] = j < cend ? prim::load4(reinterpret_cast<const uint8_t*>(a.lev + c0 + j)) : kNoLevel;
+    g.T[j] = j < cend ? prim::load4(reinterpret_cast<const uint8_t*>(a.qt + c0 + j)) : kNoLevel;
     g.K[j] = (uint8_t)(j < cend ? prim::load1(a.kind + c0 + j) : kOther);
   }
   prim::sync();
@@ -264,8 +289,8 @@ JSIDX_DEVFN void scope_local(const ScopeArgs& a) {
     if (j >= cend) break;
     const uint32_t i = (uint32_t)(c0 + j);
     const uint32_t ki = g.K[j];
-    if (ki != kOpenSq && ki != kOpenCu) continue;
-    const uint32_t lv = g.L[j];
+    const uint32_t lv = g.T[j];
+    if (lv == kNoLevel) continue;  // neither an opener nor a comma inside a scope
     // the rest of this run, then whole runs by their lowest level, then
     // inside the first run that can hold the closer
     uint32_t p = j + 1;
@@ -279,7 +304,7 @@ JSIDX_DEVFN void scope_local(const ScopeArgs& a) {
         while (g.L[p] > lv) p++;  // ends inside run r: its lowest level is at most lv
     }
     if (p < cend) {
-      link(a, i, (uint32_t)(c0 + p), ki);
+      resolve(a, i, (uint32_t)(c0 + p), ki);
     } else {
       const uint32_t q = prim::add_agent32(a.qcount, 1u);
       prim::st_out(a.queue + q, i);
@@ -297,7 +322,7 @@ JSIDX_DEVFN void scope_far(const ScopeArgs& a) {
   const uint32_t nw = prim::grid() * waves_per_group;
   for (uint32_t q = prim::block() * waves_per_group + prim::wave_id(); q < qn; q += nw) {
     const uint32_t i = prim::readlane(prim::load4(reinterpret_cast<const uint8_t*>(a.queue + q)), 0);
-    const uint32_t lv = prim::readlane(prim::load4(reinterpret_cast<const uint8_t*>(a.lev + i)), 0);
+    const uint32_t lv = prim::readlane(prim::load4(reinterpret_cast<const uint8_t*>(a.qt + i)), 0);
     const uint32_t ki = prim::readlane(prim::load1(a.kind + i), 0);
     int64_t c2 = -1;
     for (uint64_t base = (uint64_t)i / kScopeChunk + 1; base < a.nchunks; base += kScopeWave) {
@@ -309,7 +334,7 @@ JSIDX_DEVFN void scope_far(const ScopeArgs& a) {
         break;
       }
     }
-    if (c2 < 0) {
+    if (c2 < 0) {  // an opener never closed, or a comma whose scope never closes
       if (lane == 0) prim::or_agent32(a.err, kErrUnbalanced);
       continue;
     }
@@ -325,8 +350,57 @@ JSIDX_DEVFN void scope_far(const ScopeArgs& a) {
         break;
       }
     }
-    if (found >= 0 && lane == 0) link(a, i, (uint32_t)found, ki);
+    if (found >= 0 && lane == 0) resolve(a, i, (uint32_t)found, ki);
   }
+}
+
+JSIDX_DEV bool value_start(uint32_t t) { return t == kOther || t == kOpenSq || t == kOpenCu || t == kStr; }
+JSIDX_DEV uint32_t tok_at(const ScopeArgs& a, int64_t i) { return i < 0 ? 0xFFu : prim::load1(a.kind + i); }
+// A string at entry j is an object key: it follows '{' or a comma of an object.
+JSIDX_DEV bool is_key(const ScopeArgs& a, int64_t j) {
+  if (j < 1) return false;
+  const uint32_t p = tok_at(a, j - 1);
+  return p == kOpenCu || (p == kComma && prim::load1(a.ck + j - 1) == kCloseCu);
+}
+
+// Structure check of entry i: its token must be allowed after the one before
+// it (a comma's successor by the comma's scope, a string's by whether it is a
+// key), nothing may follow the root value, and the last entry must end it.
+JSIDX_DEV void check_entry(const ScopeArgs& a, uint64_t i) {
+  const uint32_t cur = tok_at(a, (int64_t)i);
+  bool bad;
+  if (i == 0) {
+    bad = !value_start(cur);
+  } else {
+    const uint32_t p = tok_at(a, (int64_t)i - 1);
+    const bool key_before = p == kStr && is_key(a, (int64_t)i - 1);
+    if (p == kOpenCu) bad = !(cur == kStr || cur == kCloseCu);
+    else if (p == kOpenSq) bad = !(value_start(cur) || cur == kCloseSq);
+    else if (p == kColon) bad = !value_start(cur);
+    else if (p == kComma) {
+      const uint32_t s = prim::load1(a.ck + i - 1);
+      bad = s == kCloseCu ? cur != kStr : (s == kCloseSq ? !value_start(cur) : true);
+    } else if (key_before) {
+      bad = cur != kColon;
+    } else {  // after a value: a comma or a closer inside a scope, nothing at the root
+      bad = prim::load4(reinterpret_cast<const uint8_t*>(a.dep + i)) == 0u ||
+            !(cur == kComma || cur == kCloseSq || cur == kCloseCu);
+    }
+  }
+  if (i + 1 == a.n) {  // the last entry ends the root value
+    const bool ends = cur == kOther || cur == kCloseSq || cur == kCloseCu || (cur == kStr && !is_key(a, (int64_t)i));
+    bad = bad || !ends;
+  }
+  if (bad) prim::or_agent32(a.err, kErrSyntax);
+}
+
+// 6. The structure check over all entries (a grid-stride loop).  With the
+//    links unbalanced or mismatched the structure is invalid too.
+JSIDX_DEVFN void scope_check(const ScopeArgs& a) {
+  const uint64_t first = (uint64_t)prim::block() * kScopeThreads + scope_tid();
+  if (first == 0 && (prim::ld_agent32(a.err) & (kErrUnbalanced | kErrMismatched)))
+    prim::or_agent32(a.err, kErrSyntax);
+  for (uint64_t i = first; i < a.n; i += (uint64_t)prim::grid() * kScopeThreads) check_entry(a, i);
 }
 
 }  // namespace jsidx

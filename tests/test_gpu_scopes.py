@@ -1,5 +1,7 @@
 """GPU scope links (jsidx_scopes on the index jsidx_build wrote) against the
-oracle's bracket stack, bit-exact: every link and the flags."""
+oracle's bracket stack and structure check, bit-exact: every link and the
+flags."""
+import itertools
 import json
 import random
 import sys
@@ -42,6 +44,7 @@ def assert_scopes_match(data: bytes, label: str):
     oi, _ = oracle.index(data)
     assert np.array_equal(idx, oi), f"{label}: index differs"
     om, oe = oracle.scopes(data, oi)
+    oe |= oracle.structure(data, oi)
     assert e == oe, f"{label}: flags {e:#x} != {oe:#x}"
     bad = np.nonzero(m != om)[0]
     assert bad.size == 0, f"{label}: {bad.size} links differ, first entry {bad[0] if bad.size else -1}"
@@ -86,3 +89,27 @@ def test_scopes_full_size_c1():
     doc = synth.gen_c1(1).data
     _say(f"case: scopes C1 full size {len(doc)}")
     assert_scopes_match(doc, "C1")
+
+
+def test_structure_of_every_short_token_sequence():
+    _say("case: structure of token sequences up to 4")
+    toks = ["{", "}", "[", "]", ":", ",", '"s"', "1"]
+    for n in range(0, 5):
+        for seq in itertools.product(toks, repeat=n):
+            d = " ".join(seq).encode()
+            assert_scopes_match(d, repr(d))
+
+
+def test_structure_edits_of_generated_documents():
+    from paper_1902_08318_amd import synth
+    rng = random.Random(4)
+    for name, doc in (("C0", synth.gen_c0(3, 1 << 20).data), ("C2 4 MiB", synth.gen_c2(2, 4 << 20, pool=16).data)):
+        text = doc.decode("utf-8")
+        oi, _ = oracle.index(doc)
+        assert oracle.structure(doc, oi) == 0
+        for k in range(12):
+            p = int(oi[rng.randrange(oi.size)])
+            ch = rng.choice(["{", "}", "[", "]", ":", ",", " ", '"x"', "1"])
+            edited = (doc[:p] + ch.encode() + doc[p + 1:]) if k % 2 else (doc[:p] + b" " + ch.encode() + b" " + doc[p:])
+            _say(f"case: structure edit {name} {k} at {p}")
+            assert_scopes_match(edited, f"{name} edit {k}")

@@ -1,5 +1,6 @@
 """The scope-link kernels (jsidx_scopes.h), run on the CPU through the
-emulated primitives, against the oracle's bracket stack."""
+emulated primitives, against the oracle's bracket stack and structure check."""
+import itertools
 import json
 import random
 
@@ -13,6 +14,7 @@ def _check(data: bytes, far_groups: int = 2):
     idx, _ = oracle.index(data)
     m, e, v = emu.scopes(data, idx, far_groups)
     om, oe = oracle.scopes(data, idx)
+    oe |= oracle.structure(data, idx)
     assert v == 0
     assert e == oe, (e, oe)
     assert np.array_equal(m, om)
@@ -47,5 +49,36 @@ def test_scopes_across_chunks():
     _check(big[:-1])                    # the root never closes
     _check(big + b"]")                  # one closer too many
     _check(big.replace(b"}", b"]", 1))  # a mismatch somewhere early
-    _check(b"[" * 9000 + b"1" + b"]" * 9000)   # depth 9000 across three chunks
-    _check(b"[" * 5000 + b"]" * 4000, far_groups=1)
+    _check(b"[" * 2100 + b"1" + b"]" * 2100)   # depth 2100, the openers' closers in the next chunk
+    _check(b"[" * 4200 + b"]" * 4000, far_groups=3)
+
+
+TOKENS = ["{", "}", "[", "]", ":", ",", '"s"', "1"]
+
+
+def test_structure_of_short_token_sequences():
+    """Every sequence of up to two tokens, and a sample of longer ones."""
+    for n in range(0, 3):
+        for seq in itertools.product(TOKENS, repeat=n):
+            _check(" ".join(seq).encode(), far_groups=1)
+    rng = random.Random(23)
+    for _ in range(20):
+        seq = [rng.choice(TOKENS) for _ in range(rng.randrange(3, 8))]
+        _check(" ".join(seq).encode(), far_groups=1)
+
+
+def test_structure_edits_across_chunks():
+    """A valid document of several chunks, then one structural edit at a time
+    (a comma's scope is found outside its chunk, keys and values after it)."""
+    rng = random.Random(8)
+    items = []
+    while True:
+        items.append({f"k{i}": [i, {"x": "y"}] for i in range(rng.randrange(1, 5))})
+        big = json.dumps(items, separators=(",", ":"))
+        if oracle.index(big.encode())[0].size > 2 * 4096 + 300:
+            break
+    _check(big.encode(), far_groups=2)
+    for at, old, new in ((0.3, ",", " "), (0.2, ":", ","), (0.9, ",", ":"), (0.01, "{", "[")):
+        p = big.index(old, int(at * len(big)))
+        _check((big[:p] + new + big[p + 1:]).encode(), far_groups=2)
+    _check((big + " 1").encode())

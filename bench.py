@@ -48,23 +48,22 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def profiled_traffic(rows: int):
+def profiled_traffic(rows: int, variant: int = 0):
     """HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)
-    from the committed C1 profile, if it was taken on the current kernel with
-    the same tile size."""
+    from the committed C1 profile, if it was taken on the current kernel (the
+    default variant) with the same tile size."""
+    if variant != 0:
+        return None
     try:
         text = open(PROFILE).read()
     except OSError:
         return None
     import re
     m_hash = re.search(r"sha256\[:16\]: `([0-9a-f]{16})`", text)
-    m_bytes = re.search(r"traffic_bytes_per_launch: (\d+)", text)
-    m_rows = re.search(r"(\d+) rows of 2 KiB per tile", text)
-    if not m_hash or not m_bytes or m_hash.group(1) != kernel_hash():
+    if not m_hash or m_hash.group(1) != kernel_hash():
         return None
-    if not m_rows or int(m_rows.group(1)) != rows:
-        return None
-    return int(m_bytes.group(1))
+    m_bytes = re.search(r"traffic_bytes_per_launch \(%d rows of 2 KiB per tile\): (\d+)" % rows, text)
+    return int(m_bytes.group(1)) if m_bytes else None
 
 
 def log(msg):
@@ -124,6 +123,41 @@ def time_single(jx, torch, host: bytes, steps: int, warmup: int, copies: int = 3
     del bufs, outs
     return {"ms_total": ms, "ms_per_launch": ms / steps, "S": S, "N": n, "flags": err, "diag": diag,
             "wall_s": wall, "launch_ms": pct(per), "e2e_ms": pct(np.array(e2e))}
+
+
+# The paper's ablation of stage 1 (App. B, Table of optimizations), cycles per
+# input byte on one Skylake core: all optimizations, then without the carry-less
+# multiplication, with the naive bit extraction, with the naive classification.
+PAPER_ABLATION = {"twitter": {"default": 0.90, "xor_loop": 0.92, "direct_flatten": 1.14, "naive_classify": 1.00},
+                  "canada": {"default": 0.90, "xor_loop": 0.94, "direct_flatten": 0.96, "naive_classify": 0.96}}
+
+
+def ablation(jx, torch, docs: dict, steps: int, restore: int) -> dict:
+    """Each kernel variant (one of the paper's stage-1 optimizations turned
+    off) timed on the same documents as the default kernel: microseconds per
+    launch and the cost relative to the default, beside the paper's relative
+    costs (twitter for C1, canada for C2: the same kinds of document)."""
+    out = {}
+    try:
+        for name, v in jx.VARIANTS.items():
+            jx.set_variant(v)
+            out[name] = {}
+            for wl, data in docs.items():
+                r = time_single(jx, torch, data, steps, 2)
+                out[name][wl] = {"us_per_launch": round(r["ms_per_launch"] * 1e3, 2),
+                                 "input_GBps": round(r["N"] / (r["ms_per_launch"] / 1e3) / 1e9, 1),
+                                 "index_entries": r["S"]}
+    finally:
+        jx.set_variant(restore)
+    for name in out:
+        for wl in docs:
+            base = out["default"][wl]
+            if out[name][wl]["index_entries"] != base["index_entries"]:
+                raise RuntimeError(f"variant {name} gave a different index on {wl}")
+            out[name][wl]["vs_default"] = round(out[name][wl]["us_per_launch"] / base["us_per_launch"], 3)
+        out[name]["paper_vs_default"] = {f: round(PAPER_ABLATION[f][name] / PAPER_ABLATION[f]["default"], 3)
+                                         for f in PAPER_ABLATION}
+    return out
 
 
 def pct(x: np.ndarray) -> dict:
@@ -391,6 +425,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=1.0,
                     help="C4 serving loop: seconds per offered load (0 skips it)")
     ap.add_argument("--no-tune", action="store_true", help="keep the built-in tile size choice")
+    ap.add_argument("--tile-rows", type=int, choices=[2, 4, 8, 16], default=None,
+                    help="every launch uses tiles of this many rows (no tuning)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run plain 256 MiB device copies (scale for the HBM byte counters)")
     args = ap.parse_args()
@@ -419,7 +455,9 @@ def main():
     c1 = None
     if args.workload != "c3":
         c1 = synth.gen_c2(2, args.size_mib << 20) if args.workload == "c2" else synth.gen_c1(1, args.size_mib << 20)
-    if not args.no_tune:
+    if args.tile_rows:
+        jx.set_tile_rows([args.tile_rows] * 64)
+    elif not args.no_tune:
         from paper_1902_08318_amd import tune
         log("autotuning the tile size on the 100k-document batch and the headline document")
         c3 = synth.gen_c3(3)
@@ -455,7 +493,8 @@ def main():
                    "end_to_end_ms": r1["e2e_ms"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": profiled_traffic(rows1) if args.workload == "c1" else None},
+                     "traffic": profiled_traffic(rows1, tuning["variant"] if tuning is not None else 0)
+                     if args.workload == "c1" else None},
     }
     out["roofline"]["copy_ceiling"] = copy_ceiling(torch)
     extra = {}
@@ -470,6 +509,9 @@ def main():
         extra["scopes"] = {"C1": time_scopes(jx, torch, c1.data, max(3, args.steps // 2))}
         log("minify: C2 and the C3 batch")
         extra["minify"] = {"C2": time_minify(jx, torch, c2.data, None, args.steps)}
+        log("kernel variants (the paper's stage-1 ablation) on C1 and C2")
+        extra["ablation"] = ablation(jx, torch, {"C1": c1.data, "C2": c2.data}, max(3, args.steps // 2),
+                                     tuning["variant"] if tuning is not None else 0)
         del c2
         log("generating C3 (100k-document batch)")
         data, offs, kinds = c3 if c3 is not None else synth.gen_c3(3)
@@ -493,7 +535,7 @@ def main():
     out["paper_context"] = paper_context(r1["N"], r1["S"])
     if tuning is not None:
         out["tuning"] = {"tile_rows_by_log2_bytes": {str(b): r for b, r in enumerate(tuning["table"]) if r},
-                         "arch": tuning["arch"]}
+                         "variant": tuning["variant"], "variant_us": tuning["variant_us"], "arch": tuning["arch"]}
     if not args.no_cpu:
         log("timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(c1.data)

@@ -222,6 +222,29 @@ int jsidx_stream_diag(jsidx_stream_t stream, uint32_t *out_flags);
  */
 int jsidx_set_tile_rows(const uint8_t *rows_by_log2, uint32_t n);
 
+/*
+ * jsidx_set_variant -- the indexing kernel used by later jsidx_build and
+ * jsidx_build_batch launches on every device and stream of the process: the
+ * default (0) or a variant with one of the paper's stage-1 optimizations
+ * turned off, as in its ablation (App. B, Table of optimizations):
+ *   JSIDX_VARIANT_NAIVE_CLASSIFY  classes by one comparison per class
+ *                                 character and byte, ORed together, instead
+ *                                 of nibble logic (Sec. 3.1.2);
+ *   JSIDX_VARIANT_XOR_LOOP        the in-string mask by toggling at each
+ *                                 quote, one step per quote, instead of the
+ *                                 shift/XOR ladder (the GPU has no carry-less
+ *                                 multiply; Sec. 3.1.1);
+ *   JSIDX_VARIANT_DIRECT_FLATTEN  every lane stores its own positions with a
+ *                                 trailing-zero loop instead of staging dense
+ *                                 rows in LDS (Sec. 3.1.4, Fig. 6).
+ * Results never depend on the variant.  Returns JSIDX_E_INVAL (unchanged)
+ * for any other value.  Minify always uses the default kernel.
+ */
+#define JSIDX_VARIANT_NAIVE_CLASSIFY 1u
+#define JSIDX_VARIANT_XOR_LOOP 2u
+#define JSIDX_VARIANT_DIRECT_FLATTEN 4u
+int jsidx_set_variant(uint32_t variant);
+
 /* Rows per tile that a launch over `span` bytes would use on the current
  * device (written to *out_rows). */
 int jsidx_tile_rows(uint64_t span, uint32_t *out_rows);

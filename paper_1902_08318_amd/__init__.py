@@ -10,5 +10,5 @@ from .binding import (  # noqa: F401
     ERR_CAPACITY, ERR_EMPTY, ERR_MISMATCHED, ERR_SYNTAX, ERR_TRAILING_ESCAPE, ERR_UNBALANCED, ERR_UNCLOSED_STRING,
     ERR_UTF8,
     JsidxError, build, build_batch, diag, index, index_batch, library_path, minify, minify_batch, release, reserve,
-    scopes, set_tile_rows, tile_rows,
+    VARIANTS, scopes, set_tile_rows, set_variant, tile_rows,
 )

@@ -37,6 +37,7 @@ SIGNATURES = {
     "jsidx_stream_diag": ([_VP, ctypes.POINTER(ctypes.c_uint32)], ctypes.c_int),
     "jsidx_status_string": ([ctypes.c_int], ctypes.c_char_p),
     "jsidx_set_tile_rows": ([_VP, ctypes.c_uint32], ctypes.c_int),
+    "jsidx_set_variant": ([ctypes.c_uint32], ctypes.c_int),
     "jsidx_tile_rows": ([ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint32)], ctypes.c_int),
 }
 
@@ -143,6 +144,19 @@ def set_tile_rows(rows_by_log2) -> None:
     t = bytes(int(r) for r in rows_by_log2)
     buf = ctypes.create_string_buffer(t, max(1, len(t)))
     _check(lib().jsidx_set_tile_rows(ctypes.cast(buf, ctypes.c_void_p), len(t)))
+
+
+VARIANT_NAIVE_CLASSIFY = 1
+VARIANT_XOR_LOOP = 2
+VARIANT_DIRECT_FLATTEN = 4
+VARIANTS = {"default": 0, "naive_classify": VARIANT_NAIVE_CLASSIFY, "xor_loop": VARIANT_XOR_LOOP,
+            "direct_flatten": VARIANT_DIRECT_FLATTEN}
+
+
+def set_variant(variant: int) -> None:
+    """jsidx_set_variant: the indexing kernel for later build calls (0 or one
+    VARIANT_* flag)."""
+    _check(lib().jsidx_set_variant(int(variant)))
 
 
 def tile_rows(span: int) -> int:

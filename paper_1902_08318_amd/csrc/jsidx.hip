@@ -31,9 +31,10 @@ namespace jsidx {
 #ifndef JSIDX_WAVES_PER_EU
 #define JSIDX_WAVES_PER_EU 4
 #endif
+template <int VAR>
 __global__ void __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per_eu(JSIDX_WAVES_PER_EU)))
 index_kernel(Args a) {
-  index_tiles<false>(a);
+  index_tiles<false, VAR>(a);
 }
 
 // The same pass with the kept bytes (not white space outside strings) as output.
@@ -55,7 +56,25 @@ struct StreamWs {
 std::mutex g_mu;
 std::vector<StreamWs> g_ws;
 uint64_t g_rows_tab[4];  // tile rows by size class (jsidx_set_tile_rows), 0 = default
-int g_slots[2][64];  // resident workgroups per kernel (index, minify) and device (0 = not queried)
+uint32_t g_variant = 0;  // indexing kernel variant (jsidx_set_variant)
+// Kernels by slot: the index kernel's variants 0, naive classification, loop
+// prefix XOR, direct flatten; then the minify kernel.
+constexpr int kKernels = 5;
+constexpr int kMinifySlot = 4;
+const void* kernel_at(int k) {
+  switch (k) {
+    case 0: return reinterpret_cast<const void*>(&index_kernel<0>);
+    case 1: return reinterpret_cast<const void*>(&index_kernel<kVarNaiveClassify>);
+    case 2: return reinterpret_cast<const void*>(&index_kernel<kVarXorLoop>);
+    case 3: return reinterpret_cast<const void*>(&index_kernel<kVarDirectFlatten>);
+    default: return reinterpret_cast<const void*>(&minify_kernel);
+  }
+}
+int slot_of_variant(uint32_t v) {
+  return v == 0 ? 0 : v == (uint32_t)kVarNaiveClassify ? 1 : v == (uint32_t)kVarXorLoop ? 2
+       : v == (uint32_t)kVarDirectFlatten ? 3 : -1;
+}
+int g_slots[kKernels][64];  // resident workgroups per kernel and device (0 = not queried)
 
 uint64_t tiles_for(uint64_t total_len) {
   uint64_t t = (total_len + 15 + kTileBytes - 1) / kTileBytes;
@@ -64,14 +83,12 @@ uint64_t tiles_for(uint64_t total_len) {
 
 size_t ws_bytes_for_tiles(uint64_t tiles) { return (size_t)workspace_bytes(tiles); }
 
-int slots_for_device(int dev, bool minify) {
+int slots_for_device(int dev, int kernel) {
   if (dev < 0 || dev >= 64) return 1024;
-  int& slots = g_slots[minify ? 1 : 0][dev];
+  int& slots = g_slots[kernel][dev];
   if (slots) return slots;
   int per_cu = 0;
-  const hipError_t rc = minify
-      ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, minify_kernel, kGroupThreads, 0)
-      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, index_kernel, kGroupThreads, 0);
+  const hipError_t rc = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel_at(kernel), kGroupThreads, 0);
   if (rc != hipSuccess || per_cu < 1) per_cu = 1;
   hipDeviceProp_t prop;
   int cus = 256;
@@ -118,7 +135,8 @@ int get_ws(hipStream_t stream, uint64_t need_tiles, bool grow, StreamWs** out) {
 int launch(Args& a, hipStream_t stream, const StreamWs& e, int64_t span, bool minify) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return JSIDX_E_HIP;
-  const uint64_t slots = (uint64_t)slots_for_device(dev, minify);
+  const int kernel = minify ? kMinifySlot : slot_of_variant(g_variant);
+  const uint64_t slots = (uint64_t)slots_for_device(dev, kernel);
   a.ws = e.ws;
   a.cap_tiles = desc_slots(e.cap_tiles);
   a.cap_rows = e.cap_tiles * (uint64_t)kRows;
@@ -134,10 +152,17 @@ int launch(Args& a, hipStream_t stream, const StreamWs& e, int64_t span, bool mi
   uint64_t grid = groups < slots ? groups : slots;
   if (grid < 1) grid = 1;
   a.fill_waves = (uint32_t)(grid * kWaves);
-  if (minify)
-    hipLaunchKernelGGL(minify_kernel, dim3((uint32_t)grid), dim3(kGroupThreads), 0, stream, a);
-  else
-    hipLaunchKernelGGL(index_kernel, dim3((uint32_t)grid), dim3(kGroupThreads), 0, stream, a);
+  switch (kernel) {
+    case 0: hipLaunchKernelGGL(index_kernel<0>, dim3((uint32_t)grid), dim3(kGroupThreads), 0, stream, a); break;
+    case 1:
+      hipLaunchKernelGGL(index_kernel<kVarNaiveClassify>, dim3((uint32_t)grid), dim3(kGroupThreads), 0, stream, a);
+      break;
+    case 2: hipLaunchKernelGGL(index_kernel<kVarXorLoop>, dim3((uint32_t)grid), dim3(kGroupThreads), 0, stream, a); break;
+    case 3:
+      hipLaunchKernelGGL(index_kernel<kVarDirectFlatten>, dim3((uint32_t)grid), dim3(kGroupThreads), 0, stream, a);
+      break;
+    default: hipLaunchKernelGGL(minify_kernel, dim3((uint32_t)grid), dim3(kGroupThreads), 0, stream, a); break;
+  }
   if (hipGetLastError() != hipSuccess) return JSIDX_E_HIP;
   return JSIDX_OK;
 }
@@ -280,12 +305,19 @@ int jsidx_set_tile_rows(const uint8_t* rows_by_log2, uint32_t n) {
   return JSIDX_OK;
 }
 
+int jsidx_set_variant(uint32_t variant) {
+  if (slot_of_variant(variant) < 0) return JSIDX_E_INVAL;
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_variant = variant;
+  return JSIDX_OK;
+}
+
 int jsidx_tile_rows(uint64_t span, uint32_t* out_rows) {
   if (!out_rows) return JSIDX_E_INVAL;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return JSIDX_E_HIP;
   std::lock_guard<std::mutex> lk(g_mu);
-  const uint64_t slots = (uint64_t)slots_for_device(dev, false);
+  const uint64_t slots = (uint64_t)slots_for_device(dev, slot_of_variant(g_variant));
   *out_rows = rows_for((int64_t)span, slots * kWaves, g_rows_tab);
   return JSIDX_OK;
 }

@@ -84,6 +84,29 @@ JSIDX_DEV ClassMasks classify_planes(const uint32_t p[8]) {
   return m;
 }
 
+// The same classes by one comparison per class character and byte, ORed: the
+// non-vectorized classification the paper measures against (App. B).  Kept
+// out of line (the segment's words passed by value, in registers) so that its
+// temporaries do not raise the register pressure of the whole row loop.
+struct SegWords {
+  uint32_t w[8];
+};
+
+__attribute__((noinline)) JSIDX_DEV ClassMasks classify_bytes(SegWords sw) {
+  ClassMasks m{0u, 0u, 0u, 0u};
+#pragma unroll
+  for (int j = 0; j < 32; j++) {
+    const uint32_t b = (sw.w[j >> 2] >> (8 * (j & 3))) & 0xFFu;
+    const uint32_t c = (b == 0x2Cu) | (b == 0x3Au) | (b == 0x5Bu) | (b == 0x5Du) | (b == 0x7Bu) | (b == 0x7Du);
+    const uint32_t s = (b == 0x20u) | (b == 0x09u) | (b == 0x0Au) | (b == 0x0Du);
+    m.C |= c << j;
+    m.W |= s << j;
+    m.Q |= (uint32_t)(b == 0x22u) << j;
+    m.B |= (uint32_t)(b == 0x5Cu) << j;
+  }
+  return m;
+}
+
 // (x << 1) with bit 0 taken from bit 31 of x in the previous lane; lane 0
 // takes *cin (0/1), which becomes bit 31 of lane 63's x for the next row.
 JSIDX_DEV uint32_t shift_in1(uint32_t x, uint32_t* cin) {
@@ -145,6 +168,17 @@ JSIDX_DEV uint32_t prefix_xor(uint32_t m) {
   m ^= m << 8;
   m ^= m << 16;
   return m;
+}
+
+// The same by toggling every bit from each set bit upward, one step per set
+// bit (the variant without the ladder).
+JSIDX_DEV uint32_t prefix_xor_loop(uint32_t m) {
+  uint32_t r = 0;
+  while (m) {
+    r ^= ~0u << (uint32_t)__builtin_ctz(m);
+    m &= m - 1u;
+  }
+  return r;
 }
 
 // ---- UTF-8 (Sec. 3.1.5, table of well-formed sequences) --------------------

@@ -65,6 +65,17 @@ constexpr int kEscSteps = 4;                   // backslash run scanned back: 4 
 #define JSIDX_STAGED_FLATTEN 1
 #endif
 constexpr int kStage = 512;
+// Variants of the indexing kernel, each turning one of the paper's stage-1
+// optimizations off (the ablation of App. B, Table of optimizations, replayed):
+//   kVarNaiveClassify: classes by one comparison per class character and byte,
+//                      ORed, instead of nibble logic on bit planes;
+//   kVarXorLoop:       the in-string mask by toggling from each quote upward,
+//                      one step per quote, instead of the shift/XOR ladder;
+//   kVarDirectFlatten: every lane stores its own positions, the paper's naive
+//                      trailing-zero loop, instead of staging dense rows in LDS.
+constexpr int kVarNaiveClassify = 1;
+constexpr int kVarXorLoop = 2;
+constexpr int kVarDirectFlatten = 4;
 #ifndef JSIDX_STAGE_LANE
 #define JSIDX_STAGE_LANE 8
 #endif
@@ -338,6 +349,7 @@ JSIDX_DEV void load_segment(const Args& a, int64_t pos, int64_t begin, int64_t e
 // at document offset rel) at ranks from *cc plus the lanes below; *cc
 // advances by the row's total.  Ranks at or past lim are not written (only a
 // look-back that gave up could produce them).
+template <bool STAGED = true>
 JSIDX_DEV void write_row(Shared& sh, uint32_t* out, uint64_t lim, uint32_t* cc, uint32_t F, uint32_t rel) {
   const uint32_t n = (uint32_t)__builtin_popcount(F);
   const uint32_t incl = prim::incl_scan(n);
@@ -349,7 +361,7 @@ JSIDX_DEV void write_row(Shared& sh, uint32_t* out, uint64_t lim, uint32_t* cc, 
   // positions, each touching several cache lines; through LDS they take one
   // coalesced store per 64 positions.  Rows where some lane holds more than
   // JSIDX_STAGE_LANE positions go through LDS.
-  if (!checked && row_n <= (uint32_t)kStage && prim::ballot(n > (uint32_t)JSIDX_STAGE_LANE) != 0ull) {
+  if (STAGED && !checked && row_n <= (uint32_t)kStage && prim::ballot(n > (uint32_t)JSIDX_STAGE_LANE) != 0ull) {
     // each lane puts its positions at their ranks in LDS, then the wave
     // writes the row's positions out as consecutive words
     uint32_t k = incl - n;
@@ -440,7 +452,7 @@ JSIDX_DEV void write_bytes(Shared& sh, uint8_t* out, uint64_t lim, uint32_t* cc,
 // lies inside a string (in the head region K marks the bytes whose fate flips
 // with the incoming in-string state, F0 the kept bytes if it is 0), and the
 // outputs are the kept bytes.
-template <bool SIMPLE, bool MIN = false>
+template <bool SIMPLE, bool MIN = false, int VAR = 0>
 JSIDX_DEV void tile_local(const Args& a, uint32_t rows, Shared& sh, uint2* hmask, const uint32_t* first_row,
                           int64_t P0,
                           int64_t begin, int64_t end, int64_t d_first, int32_t hd, int64_t hs, uint32_t st_in,
@@ -529,6 +541,13 @@ JSIDX_DEV void tile_local(const Args& a, uint32_t rows, Shared& sh, uint2* hmask
       if (head >= 0 && d_first + head >= (int64_t)a.ndocs) head = -1;
     }
 
+    ClassMasks cm;
+    if constexpr ((VAR & kVarNaiveClassify) != 0) {  // before w is dead
+      SegWords sw;
+#pragma unroll
+      for (int k = 0; k < 8; k++) sw.w[k] = w[k];
+      cm = classify_bytes(sw);
+    }
     uint32_t pl[8];
     bit_planes(w, pl);
     if constexpr (!SIMPLE) {
@@ -537,7 +556,13 @@ JSIDX_DEV void tile_local(const Args& a, uint32_t rows, Shared& sh, uint2* hmask
         for (int k = 0; k < 8; k++) pl[k] &= V;
       }
     }
-    const ClassMasks cm = classify_planes(pl);
+    if constexpr ((VAR & kVarNaiveClassify) != 0) {
+      if constexpr (!SIMPLE) {
+        cm.C &= V; cm.W &= V; cm.Q &= V; cm.B &= V;
+      }
+    } else {
+      cm = classify_planes(pl);
+    }
 
     // UTF-8: rows without non-ASCII bytes and with no sequence open from the
     // row before have no errors
@@ -601,7 +626,7 @@ JSIDX_DEV void tile_local(const Args& a, uint32_t rows, Shared& sh, uint2* hmask
     const uint32_t Q = cm.Q & ~OD;
 
     // string ranges: prefix XOR, restarted at document starts
-    const uint32_t PX = prefix_xor(Q);
+    const uint32_t PX = (VAR & kVarXorLoop) ? prefix_xor_loop(Q) : prefix_xor(Q);
     uint32_t R0 = PX;
     uint64_t Rs = 0;
     uint32_t uin = 0, first_reset = 32u, last_start = 0;
@@ -672,7 +697,7 @@ JSIDX_DEV void tile_local(const Args& a, uint32_t rows, Shared& sh, uint2* hmask
         T.tail_rows |= 1u << r;
         cc += wave_sum((uint32_t)__builtin_popcount(F0));
       } else {
-        write_row(sh, a.out_idx + doff, (uint64_t)(end - doff), &cc, F0, (uint32_t)(pos - doff));
+        write_row<(VAR & kVarDirectFlatten) == 0>(sh, a.out_idx + doff, (uint64_t)(end - doff), &cc, F0, (uint32_t)(pos - doff));
       }
       continue;
     }
@@ -1279,7 +1304,7 @@ struct Pending {
 // The local pass of a tile, its descriptor, its block's fold if it is the
 // block's last to publish, and the positions that need nothing from earlier
 // tiles.  The head region's masks go to the tile's slot in the workspace.
-template <bool MIN>
+template <bool MIN, int VAR = 0>
 JSIDX_DEV Pending start_tile(const Args& a, Shared& sh, const TileSetup& S, int64_t begin, int64_t end,
                              int64_t ntiles, uint32_t epoch) {
   const uint32_t lane = prim::lane();
@@ -1288,9 +1313,9 @@ JSIDX_DEV Pending start_tile(const Args& a, Shared& sh, const TileSetup& S, int6
   uint2* hmask = head_masks(a, t, S.rows);
   TileFacts T;
   if (S.simple)
-    tile_local<true, MIN>(a, S.rows, sh, hmask, S.w0, P0, begin, end, S.d_first, S.hd, S.hs, S.e_T, true, 0u, T);
+    tile_local<true, MIN, VAR>(a, S.rows, sh, hmask, S.w0, P0, begin, end, S.d_first, S.hd, S.hs, S.e_T, true, 0u, T);
   else
-    tile_local<false, MIN>(a, S.rows, sh, hmask, S.w0, P0, begin, end, S.d_first, S.hd, S.hs, S.e_T, true, 0u, T);
+    tile_local<false, MIN, VAR>(a, S.rows, sh, hmask, S.w0, P0, begin, end, S.d_first, S.hd, S.hs, S.e_T, true, 0u, T);
   prim::trace(t, 2);
   Pending R;
   R.valid = true;
@@ -1355,7 +1380,8 @@ JSIDX_DEV Pending start_tile(const Args& a, Shared& sh, const TileSetup& S, int6
     const int64_t doff = sh.tr_doff[r];
     uint32_t cc = sh.tr_cc[r];
     const int64_t pos = P0 + (int64_t)r * kRowBytes + (int64_t)lane * kSegBytes;
-    write_row(sh, a.out_idx + doff, (uint64_t)(end - doff), &cc, sh.hF[r][lane], (uint32_t)(pos - doff));
+    write_row<(VAR & kVarDirectFlatten) == 0>(sh, a.out_idx + doff, (uint64_t)(end - doff), &cc, sh.hF[r][lane],
+                                              (uint32_t)(pos - doff));
   }
   prim::wave_sync();
   return R;
@@ -1364,7 +1390,7 @@ JSIDX_DEV Pending start_tile(const Args& a, Shared& sh, const TileSetup& S, int6
 // The look-back of a published tile, the rare exact second pass (when the
 // escape carried in turns out to change the tile's head), its inclusive
 // value, and its head region's positions and head document's result.
-template <bool MIN>
+template <bool MIN, int VAR = 0>
 JSIDX_DEV void finish_tile(const Args& a, Shared& sh, const Pending& R, int64_t pos_g0, int64_t begin, int64_t end,
                            int64_t ntiles, uint32_t epoch) {
   const uint32_t lane = prim::lane();
@@ -1387,7 +1413,7 @@ JSIDX_DEV void finish_tile(const Args& a, Shared& sh, const Pending& R, int64_t 
     prim::trace_count(t, 9);
     const TileSetup S2 = begin_tile(a, S.rows, sh, t, pos_g0, begin, end, ntiles);
     TileFacts T;
-    tile_local<false, MIN>(a, S.rows, sh, head_masks(a, t, S.rows), S2.w0, P0, begin, end, S2.d_first, S2.hd, S2.hs, s_in, false, base,
+    tile_local<false, MIN, VAR>(a, S.rows, sh, head_masks(a, t, S.rows), S2.w0, P0, begin, end, S2.d_first, S2.hd, S2.hs, s_in, false, base,
                       T);
     if (lane == 0 && !R.inc_done) {
       const uint64_t inc = make_inc(T.carry, T.reset_any, T.tail_count, epoch);
@@ -1444,7 +1470,7 @@ JSIDX_DEV void finish_tile(const Args& a, Shared& sh, const Pending& R, int64_t 
         load_segment<false>(a, P0 + (int64_t)r * kRowBytes + (int64_t)lane * kSegBytes, begin, end, w);
         write_bytes(sh, reinterpret_cast<uint8_t*>(a.out_idx) + S.hs, lim, &cc, sh.hF[r][lane], w);
       } else {
-        write_row(sh, out, lim, &cc, sh.hF[r][lane], rel0 + r * (uint32_t)kRowBytes);
+        write_row<(VAR & kVarDirectFlatten) == 0>(sh, out, lim, &cc, sh.hF[r][lane], rel0 + r * (uint32_t)kRowBytes);
       }
     }
     if (R.he_valid && lane == 0) {
@@ -1461,7 +1487,7 @@ JSIDX_DEV void finish_tile(const Args& a, Shared& sh, const Pending& R, int64_t 
 }
 
 // ---------------------------------------------------------------------------
-template <bool MIN = false>
+template <bool MIN = false, int VAR = 0>
 JSIDX_DEVFN void index_tiles(const Args& a) {
   GroupShared& gs = prim::lds_object<GroupShared>();
   const uint32_t wv = prim::wave_id();
@@ -1509,8 +1535,8 @@ JSIDX_DEVFN void index_tiles(const Args& a) {
       if (t >= ntiles) break;
       prim::trace(t, 0);
       const TileSetup S = begin_tile(a, rows, sh, t, pos_g0, begin, end, ntiles);
-      const Pending cur = start_tile<MIN>(a, sh, S, begin, end, ntiles, epoch);
-      if (pend.valid) finish_tile<MIN>(a, sh, pend, pos_g0, begin, end, ntiles, epoch);
+      const Pending cur = start_tile<MIN, VAR>(a, sh, S, begin, end, ntiles, epoch);
+      if (pend.valid) finish_tile<MIN, VAR>(a, sh, pend, pos_g0, begin, end, ntiles, epoch);
       pend = cur;
       tk++;
       if (--left == 0) {
@@ -1520,7 +1546,7 @@ JSIDX_DEVFN void index_tiles(const Args& a) {
         left = tt;
       }
     }
-    if (pend.valid) finish_tile<MIN>(a, sh, pend, pos_g0, begin, end, ntiles, epoch);
+    if (pend.valid) finish_tile<MIN, VAR>(a, sh, pend, pos_g0, begin, end, ntiles, epoch);
   }
 
   // The last workgroup out resets the counters for the next launch and clears

@@ -8,7 +8,11 @@ so it is measured: for every size class b (inputs of 2^b to 2^(b+1) bytes)
 the tuner times a batch of documents of about 1.5 * 2^b bytes, and one
 document of that size, at each candidate tile size and keeps the fastest.  The table goes to the library
 (jsidx_set_tile_rows) and to a JSON cache keyed by the GPU architecture.
-Results never depend on the tile size; only time does.
+The kernel variants (the default and those with one of the paper's stage-1
+optimizations turned off, App. B) are alternatives too: with the table set,
+each is timed on the whole batch and the large document, and the fastest is
+kept (jsidx_set_variant).
+Results never depend on the tile size or the variant; only time does.
 """
 from __future__ import annotations
 
@@ -85,7 +89,9 @@ def autotune(data: bytes, offsets: np.ndarray, single: bytes | None = None, clas
 
     table = [0] * 64
     timings = {}
+    variant, variant_us = 0, {}
     try:
+        binding.set_variant(0)
         binding.set_tile_rows([])
         _time(torch, batch_call(nd_all), stream, 10)  # clocks up, memory touched
         for b in classes:
@@ -119,10 +125,28 @@ def autotune(data: bytes, offsets: np.ndarray, single: bytes | None = None, clas
                 log(f"tune: class 2^{b}: " + "; ".join(
                     f"{k} ({work[k][1]} B): " + " ".join(f"{r}:{res[k][r]:.1f}" for r in CANDIDATES) for k in work)
                     + f" us -> {best} rows")
+        binding.set_tile_rows(table)
+        work = {"batch": batch_call(nd_all)}
+        if single:
+            work["single"] = single_call(len(single))
+        for name, v in binding.VARIANTS.items():
+            binding.set_variant(v)
+            variant_us[name] = {k: round(_time(torch, call, stream, max(3, reps // 4)), 2)
+                                for k, call in work.items()}
+        best_us = {k: min(variant_us[name][k] for name in variant_us) for k in work}
+        chosen = min(variant_us, key=lambda name: (sum(variant_us[name][k] / best_us[k] for k in work),
+                                                   binding.VARIANTS[name]))
+        variant = binding.VARIANTS[chosen]
+        if log:
+            log("tune: variants " + "; ".join(f"{name}: " + " ".join(f"{k} {t:.1f}" for k, t in us.items())
+                                              for name, us in variant_us.items()) + f" us -> {chosen}")
     finally:
+        binding.set_variant(0)
         binding.release(stream)
     binding.set_tile_rows(table)
-    return {"arch": _arch(torch), "table": table, "timings": timings, "when": time.strftime("%Y-%m-%d %H:%M:%S")}
+    binding.set_variant(variant)
+    return {"arch": _arch(torch), "table": table, "timings": timings, "variant": variant, "variant_us": variant_us,
+            "when": time.strftime("%Y-%m-%d %H:%M:%S")}
 
 
 def save(result: dict, path: str | None = None) -> str:
@@ -146,4 +170,5 @@ def load(path: str | None = None) -> dict | None:
     if res.get("arch") != arch or len(res.get("table", [])) != 64:
         return None
     binding.set_tile_rows(res["table"])
+    binding.set_variant(int(res.get("variant", 0)))
     return res

@@ -29,9 +29,10 @@ extern "C" {
 //   counts largest tiles.
 //   rows: rows per tile (0: the kernel picks them for the launch's waves).
 //   minify: run the minify pass (out_idx then receives bytes).
+//   variant: the indexing kernel's variant (0 or one kVar* flag).
 long emu_run(const uint8_t* base, const uint64_t* offsets, uint64_t len, uint32_t ndocs, uint32_t* out_idx,
              uint64_t out_cap, uint32_t* out_n, uint32_t* out_err, int nblocks, void* ws_mem, uint64_t cap_tiles,
-             uint32_t rows, const uint8_t* granule_lo, const uint8_t* granule_hi, int minify) {
+             uint32_t rows, const uint8_t* granule_lo, const uint8_t* granule_hi, int minify, int variant) {
   prim::EmuEnv env;
   env.reads[env.nreads++] = {granule_lo, granule_hi};
   if (offsets) env.reads[env.nreads++] = {offsets, offsets + ndocs + 1};
@@ -70,7 +71,11 @@ long emu_run(const uint8_t* base, const uint64_t* offsets, uint64_t len, uint32_
         prim::tctx.grid = (uint32_t)ngroups;
         prim::tctx.g = groups[(size_t)b];
         prim::tctx.env = &env;
-        if (minify) index_tiles<true>(a); else index_tiles<false>(a);
+        if (minify) index_tiles<true>(a);
+        else if (variant == kVarNaiveClassify) index_tiles<false, kVarNaiveClassify>(a);
+        else if (variant == kVarXorLoop) index_tiles<false, kVarXorLoop>(a);
+        else if (variant == kVarDirectFlatten) index_tiles<false, kVarDirectFlatten>(a);
+        else index_tiles<false>(a);
       });
     }
   }

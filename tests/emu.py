@@ -16,6 +16,8 @@ ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "cpu_emu", "harness.cpp")
 OUT_DIR = os.path.join(HERE, "cpu_emu", "_build")
 LIB = os.path.join(OUT_DIR, "libjsidx_emu.so")
+# indexing kernel variants: naive classification, loop prefix XOR, direct flatten
+VARIANTS = (1, 2, 4)
 _lib = None
 
 
@@ -55,7 +57,7 @@ def load(block_tiles: int | None = None):
     lib = ctypes.CDLL(path)
     vp = ctypes.c_void_p
     lib.emu_run.argtypes = [vp, vp, ctypes.c_uint64, ctypes.c_uint32, vp, ctypes.c_uint64, vp, vp,
-                            ctypes.c_int, vp, ctypes.c_uint64, ctypes.c_uint32, vp, vp, ctypes.c_int]
+                            ctypes.c_int, vp, ctypes.c_uint64, ctypes.c_uint32, vp, vp, ctypes.c_int, ctypes.c_int]
     lib.emu_run.restype = ctypes.c_long
     lib.emu_scopes_run.argtypes = [vp, ctypes.c_uint64, vp, ctypes.c_uint32, vp, vp, vp, ctypes.c_int]
     lib.emu_scopes_run.restype = ctypes.c_long
@@ -97,7 +99,8 @@ def _aligned(nbytes: int, shift: int) -> tuple[np.ndarray, int]:
 
 
 def run(data: bytes, offsets=None, nblocks: int = 2, misalign: int = 0, ws: Workspace | None = None,
-        garbage: int = 0xEE, block_tiles: int | None = None, rows: int | None = None, minify: bool = False):
+        garbage: int = 0xEE, block_tiles: int | None = None, rows: int | None = None, minify: bool = False,
+        variant: int = 0):
     """Index `data` (one document if offsets is None, else a batch).
 
     misalign: the buffer starts this many bytes past a 64-byte boundary.  The
@@ -106,6 +109,7 @@ def run(data: bytes, offsets=None, nblocks: int = 2, misalign: int = 0, ws: Work
     block_tiles: look-back block size of the build (None: the library's).
     rows: rows per tile (None: the largest tile; 0: the kernel picks them).
     minify: run the minify pass; out_idx is then a uint8 array of kept bytes.
+    variant: the indexing kernel's variant (0 or one of VARIANTS).
     Returns (out_idx, out_n, out_err, violations).
     """
     if ws is not None:
@@ -137,7 +141,7 @@ def run(data: bytes, offsets=None, nblocks: int = 2, misalign: int = 0, ws: Work
     v = lib.emu_run(ctypes.c_void_p(base), offs.ctypes.data if offs is not None else None, n, ndocs,
                     out_idx.ctypes.data, out_cap, out_n.ctypes.data, out_err.ctypes.data, nblocks,
                     ws.mem.ctypes.data, ws.cap, tile_bytes() // 2048 if rows is None else rows,
-                    ctypes.c_void_p(glo), ctypes.c_void_p(ghi), 1 if minify else 0)
+                    ctypes.c_void_p(glo), ctypes.c_void_p(ghi), 1 if minify else 0, variant)
     return out_idx, out_n, out_err, int(v)
 
 

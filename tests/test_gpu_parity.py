@@ -261,3 +261,29 @@ def test_every_tile_size(rows):
     finally:
         jx.set_tile_rows([])
     assert jx.diag() == 0
+
+
+@pytest.mark.parametrize("variant", ["naive_classify", "xor_loop", "direct_flatten"])
+def test_ablation_variants(variant):
+    """Each kernel variant with one of the paper's stage-1 optimizations off
+    (jsidx_set_variant) indexes exactly as the oracle: random documents over
+    many tiles, backslash runs over tile edges, a dense generated document,
+    the numeric pretty-printed one, and a batch."""
+    import paper_1902_08318_amd as jx
+    from paper_1902_08318_amd import synth
+    _say(f"case: kernel variant {variant}")
+    jx.set_variant(jx.VARIANTS[variant])
+    try:
+        rng = np.random.default_rng(7 + jx.VARIANTS[variant])
+        for k in range(3):
+            assert_single_matches(_soup(rng, int(rng.integers(1 << 16, 1 << 20))), k * 3, f"{variant} soup {k}")
+        for run in (32767, 32769, 4097):
+            d = b'["' + b"x" * 32765 + b"\\" * run + b'"' + b'",1] "z" [1]'
+            assert_single_matches(d, 1, f"{variant} run {run}")
+        assert_single_matches(synth.gen_c1(70, 16 << 20, pool=64).data, 0, f"{variant} C1-like 16 MiB")
+        assert_single_matches(synth.gen_c2(71, 8 << 20, pool=16).data, 5, f"{variant} C2-like 8 MiB")
+        data, offs, _ = synth.gen_c3(72, ndocs=3000, pool=100)
+        assert_batch_matches(data, offs, 5, f"{variant} batch")
+    finally:
+        jx.set_variant(0)
+    assert jx.diag() == 0

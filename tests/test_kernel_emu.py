@@ -10,19 +10,20 @@ import oracle
 TB = emu.tile_bytes()
 
 
-def _check_single(d, nblocks, misalign, block_tiles=None, rows=None):
-    idx, n, err, viol = emu.run(d, nblocks=nblocks, misalign=misalign, block_tiles=block_tiles, rows=rows)
+def _check_single(d, nblocks, misalign, block_tiles=None, rows=None, variant=0):
+    idx, n, err, viol = emu.run(d, nblocks=nblocks, misalign=misalign, block_tiles=block_tiles, rows=rows,
+                                variant=variant)
     oi, oe = oracle.index(d)
     assert viol == 0
     assert n[0] == len(oi) and err[0] == oe
     assert np.array_equal(idx[:n[0]], oi)
 
 
-def _check_batch(docs, nblocks, misalign, lead, block_tiles=None, rows=None):
+def _check_batch(docs, nblocks, misalign, lead, block_tiles=None, rows=None, variant=0):
     data = b"\x00" * lead + b"".join(docs)
     offs = np.concatenate([[lead], lead + np.cumsum([len(x) for x in docs])]).astype(np.uint64)
     idx, n, err, viol = emu.run(data, offsets=offs, nblocks=nblocks, misalign=misalign, block_tiles=block_tiles,
-                                rows=rows)
+                                rows=rows, variant=variant)
     oi, on, oe = oracle.index_batch(np.frombuffer(data, dtype=np.uint8), offs)
     assert viol == 0
     assert np.array_equal(n, on) and np.array_equal(err, oe)
@@ -131,6 +132,22 @@ def test_smaller_tiles(rows):
         L = 0 if r < 0.15 else (1 if r < 0.25 else int(rng.integers(2, 3000 if r < 0.9 else 3 * tb)))
         docs.append(_soup(rng, L))
     _check_batch(docs, 20, 3, 7, rows=rows)
+
+
+@pytest.mark.parametrize("variant", emu.VARIANTS)
+def test_ablation_variants(variant):
+    """Each variant with one of the paper's stage-1 optimizations off gives the
+    same index: documents over several tiles with dense rows, backslash runs
+    and quotes across edges, batches of ragged documents."""
+    rng = np.random.default_rng(40 + variant)
+    for _ in range(2):
+        _check_single(_soup(rng, int(rng.integers(TB, 3 * TB))), int(rng.integers(1, 12)), int(rng.integers(0, 16)),
+                      variant=variant)
+    _check_single(b"[" + b"1," * 5000 + b"2]", 4, 1, variant=variant)  # every other byte indexed
+    d = b'["' + b"x" * 2000 + b"\\" * 700 + b'\\"' + b'",1] "z" [1]'
+    _check_single(d, 3, 0, variant=variant)
+    docs = [_soup(rng, int(rng.integers(0, 3000))) for _ in range(40)]
+    _check_batch(docs, 16, 3, 7, variant=variant)
 
 
 def _check_minify_single(d, nblocks, misalign, rows=None, block_tiles=None):

@@ -420,8 +420,9 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the numeric and batched workloads")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--size-mib", type=int, default=256)
-    ap.add_argument("--workload", choices=["c1", "c2", "c3"], default="c1",
-                    help="headline workload (c2/c3 only for profiling runs)")
+    ap.add_argument("--workload", choices=["c1", "c2", "c3", "scopes"], default="c1",
+                    help="headline workload (c2/c3/scopes only for profiling runs; scopes: the scope "
+                         "links and structure check over the C1 index)")
     ap.add_argument("--serve-seconds", type=float, default=1.0,
                     help="C4 serving loop: seconds per offered load (0 skips it)")
     ap.add_argument("--no-tune", action="store_true", help="keep the built-in tile size choice")
@@ -462,6 +463,10 @@ def main():
         log("autotuning the tile size on the 100k-document batch and the headline document")
         c3 = synth.gen_c3(3)
         tuning = tune.autotune(c3[0], c3[1], c1.data if c1 is not None else None, log=log)
+    if args.workload == "scopes":
+        print(json.dumps({"workload": "scopes over the C1 index",
+                          **time_scopes(jx, torch, c1.data, args.steps)}), flush=True)
+        return
     if args.workload == "c3":
         data, offs, _ = c3 if c3 is not None else synth.gen_c3(3)
         r3 = time_batch(jx, torch, data, offs, args.steps, args.warmup)

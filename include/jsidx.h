@@ -167,10 +167,10 @@ int jsidx_minify_batch(const uint8_t *bufs, const uint64_t *offsets,
  *              partner, 0xFFFFFFFF for unlinked brackets and other entries.
  *   out_err    device uint32: 0 or the three flags above.
  * The computation is parallel (depth by a scan of clamped depth changes,
- * then each opener's partner, and the closer of each comma's scope, is the
- * first later entry of at most its depth) and gives exactly the stack's
- * links; the structure check then looks at each entry and the one or two
- * before it.  A per-stream workspace of about 18 bytes per entry is allocated on first use and grown as needed
+ * then each opener's partner is the first later entry of at most its depth)
+ * and gives exactly the stack's links; the structure check then looks at each
+ * entry, a few entries around it and the link of a closer just before a
+ * comma.  A per-stream workspace of about 9 bytes per entry is allocated on first use and grown as needed
  * (synchronising the stream).  Asynchronous on `stream`.
  */
 int jsidx_scopes(const uint8_t *buf, uint64_t len, const uint32_t *idx,

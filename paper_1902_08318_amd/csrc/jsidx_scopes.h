@@ -22,6 +22,8 @@
 //      for scopes that leave their chunk, over the chunks' minimum levels and
 //      then inside the first chunk that can hold it, 64 entries per step by a
 //      whole wave (scope_far).
+//   4. With the links known, a per-entry pass checks that the tokens form one
+//      JSON value (scope_check, below).
 #pragma once
 
 #include "jsidx_device.h"
@@ -37,8 +39,14 @@ constexpr uint32_t kUnlinked = 0xFFFFFFFFu;
 constexpr uint32_t kErrUnbalanced = 0x10u;
 constexpr uint32_t kErrMismatched = 0x20u;
 constexpr uint32_t kErrSyntax = 0x40u;
-// Token of an index entry: atoms (numbers, literals, anything else) are kOther.
+// Token of an index entry, by its byte: atoms (numbers, literals, anything
+// else) are kOther, a string is its opening quote.  In the workspace's kind
+// array bit 3 (kRootBit) marks entries at depth 0 and bit 4 (kMemberBit) a
+// linked closer whose opener follows a colon (the scope is a member's value).
 enum : uint32_t { kOther = 0, kOpenSq = 1, kOpenCu = 2, kCloseSq = 3, kCloseCu = 4, kColon = 5, kComma = 6, kStr = 7 };
+constexpr uint32_t kTokMask = 7u;
+constexpr uint32_t kRootBit = 8u;
+constexpr uint32_t kMemberBit = 16u;
 
 struct DepthFn {  // x -> max(x + a, b)
   int64_t a, b;
@@ -71,16 +79,14 @@ struct ScopeArgs {
   uint32_t* chunk_min;  // per chunk: lowest level
   uint32_t* qcount;     // scopes that leave their chunk
   uint32_t* lev;        // per entry: level of a bracket (kNoLevel otherwise)
-  uint32_t* qt;         // per entry: threshold of its search (openers, commas)
-  uint32_t* dep;        // per entry: depth before it
-  uint8_t* kind;        // per entry: token
-  uint8_t* ck;          // per comma: the closing bracket of its scope
+  uint8_t* kind;        // per entry: token (an unmatched closer becomes
+                        // kOther), kRootBit if the depth before it is 0
   uint32_t* queue;      // per entry at most
 };
 
 // Workspace layout for n entries (byte offsets; host side).
 struct ScopeLayout {
-  uint64_t chunk_fn, in_depth, chunk_min, qcount, lev, qt, dep, queue, kind, ck, total;
+  uint64_t chunk_fn, in_depth, chunk_min, qcount, lev, queue, kind, total;
 };
 inline uint64_t scope_align256(uint64_t x) { return (x + 255) & ~(uint64_t)255; }
 inline ScopeLayout scope_layout(uint64_t n) {
@@ -92,11 +98,8 @@ inline ScopeLayout scope_layout(uint64_t n) {
   L.chunk_min = o; o = scope_align256(o + nc * 4);
   L.qcount = o; o = scope_align256(o + 4);
   L.lev = o; o = scope_align256(o + n * 4);
-  L.qt = o; o = scope_align256(o + n * 4);
-  L.dep = o; o = scope_align256(o + n * 4);
   L.queue = o; o = scope_align256(o + n * 4);
   L.kind = o; o = scope_align256(o + n);
-  L.ck = o; o = scope_align256(o + n);
   L.total = o;
   return L;
 }
@@ -117,12 +120,24 @@ JSIDX_DEV uint32_t kind_at(const ScopeArgs& a, uint32_t i) {
        : b == 0x3Au ? kColon : b == 0x2Cu ? kComma : b == 0x22u ? kStr : kOther;
 }
 
+// LDS of the kernels: each takes only what it uses, so that more workgroups
+// fit on a CU.
 struct ScopeGroup {
   DepthFn f[kScopeThreads];
   uint32_t m[kScopeThreads];
   uint32_t L[kScopeChunk];  // levels of the chunk's entries
-  uint32_t T[kScopeChunk];  // search thresholds (scope_local), depths (scope_levels)
-  uint8_t K[kScopeChunk];   // tokens of the chunk's entries
+  alignas(4) uint8_t K[kScopeChunk];  // kinds of the chunk's entries
+};
+struct ScopeFold {
+  DepthFn f[kScopeThreads];
+  alignas(4) uint8_t K[kScopeChunk];
+};
+struct ScopeScanLds {
+  DepthFn f[kScopeThreads];
+};
+constexpr int kCheckWords = (kScopeChunk + 8) / 4;
+struct ScopeCheckLds {
+  uint32_t W[kCheckWords];  // kind bytes of entries c0 - 4 .. c0 + kScopeChunk + 3
 };
 
 JSIDX_DEV uint32_t scope_tid() { return prim::wave_id() * kScopeWave + prim::lane(); }
@@ -130,16 +145,37 @@ JSIDX_DEV uint32_t scope_tid() { return prim::wave_id() * kScopeWave + prim::lan
 // The kinds of chunk c's entries into LDS: consecutive threads read
 // consecutive entries (coalesced), then each thread works on its own run of
 // kScopePer entries in LDS.
-JSIDX_DEV void load_kinds(const ScopeArgs& a, ScopeGroup& g, uint32_t tid, uint32_t c) {
+template <typename G>
+JSIDX_DEV void load_kinds(const ScopeArgs& a, G& g, uint32_t tid, uint32_t c) {
   const uint64_t c0 = (uint64_t)c * kScopeChunk;
   for (uint32_t j = tid; j < (uint32_t)kScopeChunk; j += kScopeThreads)
     g.K[j] = (uint8_t)(c0 + j < a.n ? kind_at(a, (uint32_t)(c0 + j)) : kOther);
   prim::sync();
 }
 
+// The same from the kind array scope_chunk_fn wrote (one word per thread and
+// step; entries past n read as kOther).
+template <typename G>
+JSIDX_DEV void load_stored_kinds(const ScopeArgs& a, G& g, uint32_t tid, uint32_t c) {
+  const uint64_t c0 = (uint64_t)c * kScopeChunk;
+  uint32_t* kw = reinterpret_cast<uint32_t*>(g.K);
+  for (uint32_t w = tid; w < (uint32_t)kScopeChunk / 4; w += kScopeThreads) {
+    const uint64_t b = c0 + 4 * (uint64_t)w;
+    uint32_t v = 0u;  // four kOther
+    if (b < a.n) {
+      v = prim::load4(a.kind + b);
+      const uint64_t valid = a.n - b;
+      if (valid < 4) v &= ~(0xFFFFFFFFu << (8 * valid));
+    }
+    kw[w] = v;
+  }
+  prim::sync();
+}
+
 // Ordered inclusive scan of the workgroup's per-thread functions; returns the
 // composition of the threads before this one.
-JSIDX_DEV DepthFn group_exclusive(ScopeGroup& g, uint32_t tid, DepthFn mine) {
+template <typename G>
+JSIDX_DEV DepthFn group_exclusive(G& g, uint32_t tid, DepthFn mine) {
   g.f[tid] = mine;
   prim::sync();
   for (uint32_t s = 1; s < (uint32_t)kScopeThreads; s <<= 1) {
@@ -155,9 +191,17 @@ JSIDX_DEV DepthFn group_exclusive(ScopeGroup& g, uint32_t tid, DepthFn mine) {
 
 // 1. The composed depth function of each chunk (one workgroup per chunk).
 JSIDX_DEVFN void scope_chunk_fn(const ScopeArgs& a) {
-  ScopeGroup& g = prim::lds_object<ScopeGroup>();
+  ScopeFold& g = prim::lds_object<ScopeFold>();
   const uint32_t tid = scope_tid(), c = prim::block();
   load_kinds(a, g, tid, c);
+  // the kinds go to the workspace as words, for the kernels after this one
+  // (the word holding entry n - 1 lies inside the array's 256-byte padding)
+  const uint64_t c0 = (uint64_t)c * kScopeChunk;
+  const uint32_t* kw = reinterpret_cast<const uint32_t*>(g.K);
+  for (uint32_t w = tid; w < (uint32_t)kScopeChunk / 4; w += kScopeThreads) {
+    if (c0 + 4 * (uint64_t)w >= a.n) break;
+    prim::st_out(reinterpret_cast<uint32_t*>(a.kind + c0) + w, kw[w]);
+  }
   DepthFn f = fn_id();
   for (int k = 0; k < kScopePer; k++) f = fn_then(f, fn_of(g.K[tid * kScopePer + k]));
   const DepthFn ex = group_exclusive(g, tid, f);
@@ -171,7 +215,7 @@ JSIDX_DEVFN void scope_chunk_fn(const ScopeArgs& a) {
 // 2. The depth entering each chunk (one workgroup); also clears the flags and
 //    the queue for the kernels after it.
 JSIDX_DEVFN void scope_scan(const ScopeArgs& a) {
-  ScopeGroup& g = prim::lds_object<ScopeGroup>();
+  ScopeScanLds& g = prim::lds_object<ScopeScanLds>();
   const uint32_t tid = scope_tid();
   const uint32_t per = (a.nchunks + kScopeThreads - 1) / kScopeThreads;
   const uint64_t lo = (uint64_t)tid * per;
@@ -200,7 +244,7 @@ JSIDX_DEVFN void scope_levels(const ScopeArgs& a) {
   ScopeGroup& g = prim::lds_object<ScopeGroup>();
   const uint32_t tid = scope_tid(), c = prim::block();
   const uint64_t c0 = (uint64_t)c * kScopeChunk;
-  load_kinds(a, g, tid, c);
+  load_stored_kinds(a, g, tid, c);
   DepthFn f = fn_id();
   for (int k = 0; k < kScopePer; k++) f = fn_then(f, fn_of(g.K[tid * kScopePer + k]));
   const DepthFn ex = group_exclusive(g, tid, f);
@@ -209,7 +253,7 @@ JSIDX_DEVFN void scope_levels(const ScopeArgs& a) {
   for (int k = 0; k < kScopePer; k++) {
     const uint32_t j = tid * kScopePer + (uint32_t)k;
     uint32_t kd = g.K[j], level = kNoLevel;
-    g.T[j] = (uint32_t)d;
+    const uint32_t root = d == 0 ? kRootBit : 0u;
     if (kd == kOpenSq || kd == kOpenCu) {
       level = (uint32_t)d;
       d++;
@@ -223,7 +267,7 @@ JSIDX_DEVFN void scope_levels(const ScopeArgs& a) {
       }
     }
     g.L[j] = level;
-    g.K[j] = (uint8_t)kd;
+    g.K[j] = (uint8_t)(kd | root);
     if (level < lo_level) lo_level = level;
   }
   if (unmatched) prim::or_agent32(a.err, kErrUnbalanced);
@@ -232,15 +276,8 @@ JSIDX_DEVFN void scope_levels(const ScopeArgs& a) {
   // the chunk's levels, kinds and cleared links go out as consecutive words
   for (uint32_t j = tid; j < (uint32_t)kScopeChunk; j += kScopeThreads) {
     if (c0 + j >= a.n) break;
-    const uint32_t kd = g.K[j], dj = g.T[j];
-    // search threshold: an opener looks for its closer, a comma for the
-    // closer of its scope (none at the root)
-    const uint32_t qt = (kd == kOpenSq || kd == kOpenCu) ? dj : (kd == kComma && dj > 0 ? dj - 1u : kNoLevel);
     prim::st_out(a.lev + c0 + j, g.L[j]);
-    prim::st_out(a.qt + c0 + j, qt);
-    prim::st_out(a.dep + c0 + j, dj);
-    prim::st_byte(a.kind + c0 + j, kd);
-    prim::st_byte(a.ck + c0 + j, 0u);
+    prim::st_byte(a.kind + c0 + j, g.K[j]);
     prim::st_out(a.match + c0 + j, kUnlinked);
   }
   for (uint32_t s = kScopeThreads / 2; s > 0; s >>= 1) {
@@ -250,17 +287,16 @@ JSIDX_DEVFN void scope_levels(const ScopeArgs& a) {
   if (tid == 0) prim::st_out(a.chunk_min + c, g.m[0]);
 }
 
-// The search of entry i (token ki) ended at entry k: an opener is linked with
-// its closer, a comma learns the closer of its scope.
-JSIDX_DEV void resolve(const ScopeArgs& a, uint32_t i, uint32_t k, uint32_t ki) {
-  const uint32_t kk = prim::load1(a.kind + k);
-  if (ki == kComma) {
-    prim::st_byte(a.ck + i, kk);
-    return;
-  }
+// Links opener i (token ki) with closer k.  The closer's kind byte also
+// learns whether the opener follows a colon; only this call writes it (the
+// kernel owning k's chunk has staged its kinds before linking).
+JSIDX_DEV void link(const ScopeArgs& a, uint32_t i, uint32_t k, uint32_t ki) {
   prim::st_out(a.match + i, k);
   prim::st_out(a.match + k, i);
+  const uint32_t kb = prim::load1(a.kind + k);
+  const uint32_t kk = kb & kTokMask;
   if ((ki == kOpenCu) != (kk == kCloseCu)) prim::or_agent32(a.err, kErrMismatched);
+  if (i > 0 && (prim::load1(a.kind + i - 1) & kTokMask) == kColon) prim::st_byte(a.kind + k, kb | kMemberBit);
 }
 
 // 4. Each opener's closer inside its own chunk, searched in LDS; openers whose
@@ -272,8 +308,7 @@ JSIDX_DEVFN void scope_local(const ScopeArgs& a) {
   const uint32_t cend = a.n - c0 < (uint64_t)kScopeChunk ? (uint32_t)(a.n - c0) : (uint32_t)kScopeChunk;
   for (uint32_t j = tid; j < (uint32_t)kScopeChunk; j += kScopeThreads) {
     g.L[j] = j < cend ? prim::load4(reinterpret_cast<const uint8_t*>(a.lev + c0 + j)) : kNoLevel;
-    g.T[j] = j < cend ? prim::load4(reinterpret_cast<const uint8_t*>(a.qt + c0 + j)) : kNoLevel;
-    g.K[j] = (uint8_t)(j < cend ? prim::load1(a.kind + c0 + j) : kOther);
+    g.K[j] = (uint8_t)(j < cend ? prim::load1(a.kind + c0 + j) & kTokMask : kOther);
   }
   prim::sync();
   // lowest level of each thread's run of kScopePer entries
@@ -289,8 +324,8 @@ JSIDX_DEVFN void scope_local(const ScopeArgs& a) {
     if (j >= cend) break;
     const uint32_t i = (uint32_t)(c0 + j);
     const uint32_t ki = g.K[j];
-    const uint32_t lv = g.T[j];
-    if (lv == kNoLevel) continue;  // neither an opener nor a comma inside a scope
+    if (ki != kOpenSq && ki != kOpenCu) continue;
+    const uint32_t lv = g.L[j];
     // the rest of this run, then whole runs by their lowest level, then
     // inside the first run that can hold the closer
     uint32_t p = j + 1;
@@ -304,7 +339,7 @@ JSIDX_DEVFN void scope_local(const ScopeArgs& a) {
         while (g.L[p] > lv) p++;  // ends inside run r: its lowest level is at most lv
     }
     if (p < cend) {
-      resolve(a, i, (uint32_t)(c0 + p), ki);
+      link(a, i, (uint32_t)(c0 + p), ki);
     } else {
       const uint32_t q = prim::add_agent32(a.qcount, 1u);
       prim::st_out(a.queue + q, i);
@@ -322,8 +357,8 @@ JSIDX_DEVFN void scope_far(const ScopeArgs& a) {
   const uint32_t nw = prim::grid() * waves_per_group;
   for (uint32_t q = prim::block() * waves_per_group + prim::wave_id(); q < qn; q += nw) {
     const uint32_t i = prim::readlane(prim::load4(reinterpret_cast<const uint8_t*>(a.queue + q)), 0);
-    const uint32_t lv = prim::readlane(prim::load4(reinterpret_cast<const uint8_t*>(a.qt + i)), 0);
-    const uint32_t ki = prim::readlane(prim::load1(a.kind + i), 0);
+    const uint32_t lv = prim::readlane(prim::load4(reinterpret_cast<const uint8_t*>(a.lev + i)), 0);
+    const uint32_t ki = prim::readlane(prim::load1(a.kind + i) & kTokMask, 0);
     int64_t c2 = -1;
     for (uint64_t base = (uint64_t)i / kScopeChunk + 1; base < a.nchunks; base += kScopeWave) {
       const uint64_t cc = base + lane;
@@ -334,7 +369,7 @@ JSIDX_DEVFN void scope_far(const ScopeArgs& a) {
         break;
       }
     }
-    if (c2 < 0) {  // an opener never closed, or a comma whose scope never closes
+    if (c2 < 0) {
       if (lane == 0) prim::or_agent32(a.err, kErrUnbalanced);
       continue;
     }
@@ -350,57 +385,120 @@ JSIDX_DEVFN void scope_far(const ScopeArgs& a) {
         break;
       }
     }
-    if (found >= 0 && lane == 0) resolve(a, i, (uint32_t)found, ki);
+    if (found >= 0 && lane == 0) link(a, i, (uint32_t)found, ki);
   }
 }
 
-JSIDX_DEV bool value_start(uint32_t t) { return t == kOther || t == kOpenSq || t == kOpenCu || t == kStr; }
-JSIDX_DEV uint32_t tok_at(const ScopeArgs& a, int64_t i) { return i < 0 ? 0xFFu : prim::load1(a.kind + i); }
-// A string at entry j is an object key: it follows '{' or a comma of an object.
-JSIDX_DEV bool is_key(const ScopeArgs& a, int64_t j) {
-  if (j < 1) return false;
-  const uint32_t p = tok_at(a, j - 1);
-  return p == kOpenCu || (p == kComma && prim::load1(a.ck + j - 1) == kCloseCu);
+// ---- Structure ---------------------------------------------------------
+// The entries' tokens must form one JSON value (the grammar of values,
+// objects and arrays recalled in Sec. 1, which the paper's stage 2 enforces
+// while it builds the tape, Sec. 3.2).  Each entry is judged with the few
+// entries around it; the scope of a comma needs no search: the element before
+// the comma ends just before it, and it is an object member exactly when its
+// value (an atom or string there, or the scope ending at a closer there)
+// follows a colon, which link() recorded on the closer.  Every comma must be
+// followed by an element of the same form; the first element after '{' must
+// be a member and after '[' a plain value, so by induction every element has
+// the form of its scope.  A member is a string followed by a colon.
+
+// Entry i of chunk c0 (i in [c0 - 4, c0 + kScopeChunk + 3]) from the staged
+// kinds: its token, kRootBit, or 0xFF outside the index.
+struct Staged {
+  const uint8_t* K;
+  int64_t c0;
+  JSIDX_DEV uint32_t raw(int64_t i) const { return K[i - c0 + 4]; }
+  JSIDX_DEV uint32_t tok(int64_t i) const { const uint32_t k = raw(i); return k == 0xFFu ? k : k & kTokMask; }
+};
+
+// The check as a table: each entry gets a class as the entry being checked
+// (its token, with strings split into keys -- followed by a colon -- and
+// values, and commas at depth 0 apart) and a class as the predecessor of the
+// next entry (its token, with strings split the same way and commas split by
+// the form of the element before them: after an object member, after a plain
+// value).  An entry is valid iff its class is allowed after its
+// predecessor's.
+enum : uint32_t {  // as the entry checked (tokens 0..6 keep their values)
+  cStrVal = 7, cStrKey = 8, cRootComma = 9
+};
+enum : uint32_t {  // as the predecessor (tokens 0..5 keep their values)
+  pCommaArr = 6, pStrVal = 7, pStrKey = 8, pCommaObj = 9, pStart = 10
+};
+constexpr uint32_t cls_bit(uint32_t c) { return 1u << c; }
+constexpr uint32_t kValueStarts = cls_bit(kOther) | cls_bit(kOpenSq) | cls_bit(kOpenCu) | cls_bit(cStrVal);
+constexpr uint32_t kAfterValue = cls_bit(kComma) | cls_bit(kCloseSq) | cls_bit(kCloseCu);
+// allowed classes after each predecessor class, 10 bits each
+constexpr uint64_t kAllowLo =  // predecessors 0..5: atom [ { ] } :
+    ((uint64_t)kAfterValue << 0) | ((uint64_t)(kValueStarts | cls_bit(kCloseSq)) << 10) |
+    ((uint64_t)(cls_bit(cStrKey) | cls_bit(kCloseCu)) << 20) | ((uint64_t)kAfterValue << 30) |
+    ((uint64_t)kAfterValue << 40) | ((uint64_t)kValueStarts << 50);
+constexpr uint64_t kAllowHi =  // predecessors 6..10: array comma, value, key, object comma, start
+    ((uint64_t)kValueStarts << 0) | ((uint64_t)kAfterValue << 10) | ((uint64_t)cls_bit(kColon) << 20) |
+    ((uint64_t)cls_bit(cStrKey) << 30) | ((uint64_t)kValueStarts << 40);
+constexpr uint32_t kLastAllowed = cls_bit(kOther) | cls_bit(cStrVal) | cls_bit(kCloseSq) | cls_bit(kCloseCu);
+
+JSIDX_DEV bool allowed(uint32_t pc, uint32_t cc) {
+  const uint64_t row = pc < 6 ? kAllowLo >> (10 * pc) : kAllowHi >> (10 * (pc - 6));
+  return ((row >> cc) & 1u) != 0u;
 }
 
-// Structure check of entry i: its token must be allowed after the one before
-// it (a comma's successor by the comma's scope, a string's by whether it is a
-// key), nothing may follow the root value, and the last entry must end it.
-JSIDX_DEV void check_entry(const ScopeArgs& a, uint64_t i) {
-  const uint32_t cur = tok_at(a, (int64_t)i);
-  bool bad;
-  if (i == 0) {
-    bad = !value_start(cur);
-  } else {
-    const uint32_t p = tok_at(a, (int64_t)i - 1);
-    const bool key_before = p == kStr && is_key(a, (int64_t)i - 1);
-    if (p == kOpenCu) bad = !(cur == kStr || cur == kCloseCu);
-    else if (p == kOpenSq) bad = !(value_start(cur) || cur == kCloseSq);
-    else if (p == kColon) bad = !value_start(cur);
-    else if (p == kComma) {
-      const uint32_t s = prim::load1(a.ck + i - 1);
-      bad = s == kCloseCu ? cur != kStr : (s == kCloseSq ? !value_start(cur) : true);
-    } else if (key_before) {
-      bad = cur != kColon;
-    } else {  // after a value: a comma or a closer inside a scope, nothing at the root
-      bad = prim::load4(reinterpret_cast<const uint8_t*>(a.dep + i)) == 0u ||
-            !(cur == kComma || cur == kCloseSq || cur == kCloseCu);
+// Structure check of entry i (entries i - 3 .. i + 1 staged).
+JSIDX_DEV bool entry_ok(const ScopeArgs& a, const Staged& st, int64_t i) {
+  const uint32_t t = st.tok(i), nxt = st.tok(i + 1);
+  uint32_t cc = t;
+  if (t == kStr) cc = nxt == kColon ? cStrKey : cStrVal;
+  else if (t == kComma && (st.raw(i) & kRootBit)) cc = cRootComma;
+  uint32_t pc = pStart;
+  if (i > 0) {
+    const uint32_t p = st.tok(i - 1);
+    pc = p;
+    if (p == kStr) {
+      pc = t == kColon ? pStrKey : pStrVal;
+    } else if (p == kComma) {
+      // the element before the comma ends at i - 2: an object member iff its
+      // value (an atom or string there, or the scope a closer there ends)
+      // follows a colon
+      const uint32_t te = st.tok(i - 2);
+      const bool member = (te == kCloseSq || te == kCloseCu) ? (st.raw(i - 2) & kMemberBit) != 0u
+                                                              : st.tok(i - 3) == kColon;
+      pc = member ? pCommaObj : pCommaArr;
     }
   }
-  if (i + 1 == a.n) {  // the last entry ends the root value
-    const bool ends = cur == kOther || cur == kCloseSq || cur == kCloseCu || (cur == kStr && !is_key(a, (int64_t)i));
-    bad = bad || !ends;
-  }
-  if (bad) prim::or_agent32(a.err, kErrSyntax);
+  bool ok = allowed(pc, cc);
+  if ((uint64_t)i + 1 == a.n) ok = ok && (kLastAllowed >> cc) & 1u;
+  return ok;
 }
 
-// 6. The structure check over all entries (a grid-stride loop).  With the
-//    links unbalanced or mismatched the structure is invalid too.
+// 6. The structure check, after the links (one workgroup per chunk, kinds
+//    staged in LDS with coalesced word loads; the rule of entry i reads
+//    entries i - 3 to i + 1 only).  Unbalanced or mismatched brackets are a syntax error
+//    too.
 JSIDX_DEVFN void scope_check(const ScopeArgs& a) {
-  const uint64_t first = (uint64_t)prim::block() * kScopeThreads + scope_tid();
-  if (first == 0 && (prim::ld_agent32(a.err) & (kErrUnbalanced | kErrMismatched)))
+  ScopeCheckLds& g = prim::lds_object<ScopeCheckLds>();
+  const uint32_t tid = scope_tid(), c = prim::block();
+  const int64_t c0 = (int64_t)c * kScopeChunk;
+  if (c == 0 && tid == 0 && (prim::ld_agent32(a.err) & (kErrUnbalanced | kErrMismatched)))
     prim::or_agent32(a.err, kErrSyntax);
-  for (uint64_t i = first; i < a.n; i += (uint64_t)prim::grid() * kScopeThreads) check_entry(a, i);
+  // words of the kind array; bytes outside [0, n) read as 0xFF (the array's
+  // allocation is padded to 256 bytes, so a word holding byte n - 1 is inside)
+  for (uint32_t w = tid; w < (uint32_t)kCheckWords; w += kScopeThreads) {
+    const int64_t b = c0 - 4 + 4 * (int64_t)w;
+    uint32_t v = 0xFFFFFFFFu;
+    if (b >= 0 && (uint64_t)b < a.n) {
+      v = prim::load4(a.kind + b);
+      const uint64_t valid = a.n - (uint64_t)b;
+      if (valid < 4) v |= 0xFFFFFFFFu << (8 * valid);
+    }
+    g.W[w] = v;
+  }
+  prim::sync();
+  const Staged st{reinterpret_cast<const uint8_t*>(g.W), c0};
+  bool ok = true;
+  for (uint32_t j = tid; j < (uint32_t)kScopeChunk; j += kScopeThreads) {
+    const int64_t i = c0 + (int64_t)j;
+    if ((uint64_t)i >= a.n) break;
+    ok = entry_ok(a, st, i) && ok;
+  }
+  if (prim::ballot(!ok) != 0ull && prim::lane() == 0) prim::or_agent32(a.err, kErrSyntax);
 }
 
 }  // namespace jsidx

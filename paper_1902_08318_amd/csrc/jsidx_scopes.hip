@@ -85,11 +85,8 @@ extern "C" int jsidx_scopes(const uint8_t* buf, uint64_t len, const uint32_t* id
   a.chunk_min = reinterpret_cast<uint32_t*>(m + L.chunk_min);
   a.qcount = reinterpret_cast<uint32_t*>(m + L.qcount);
   a.lev = reinterpret_cast<uint32_t*>(m + L.lev);
-  a.qt = reinterpret_cast<uint32_t*>(m + L.qt);
-  a.dep = reinterpret_cast<uint32_t*>(m + L.dep);
   a.queue = reinterpret_cast<uint32_t*>(m + L.queue);
   a.kind = m + L.kind;
-  a.ck = m + L.ck;
   const dim3 block(kScopeThreads);
   if (a.nchunks) hipLaunchKernelGGL(scope_chunk_fn_kernel, dim3(a.nchunks), block, 0, stream, a);
   hipLaunchKernelGGL(scope_scan_kernel, dim3(1), block, 0, stream, a);
@@ -97,8 +94,7 @@ extern "C" int jsidx_scopes(const uint8_t* buf, uint64_t len, const uint32_t* id
     hipLaunchKernelGGL(scope_levels_kernel, dim3(a.nchunks), block, 0, stream, a);
     hipLaunchKernelGGL(scope_local_kernel, dim3(a.nchunks), block, 0, stream, a);
     hipLaunchKernelGGL(scope_far_kernel, dim3(kFarGroups), block, 0, stream, a);
-    hipLaunchKernelGGL(scope_check_kernel, dim3((uint32_t)(((uint64_t)n + kScopeThreads - 1) / kScopeThreads)), block, 0,
-                       stream, a);
+    hipLaunchKernelGGL(scope_check_kernel, dim3(a.nchunks), block, 0, stream, a);
   }
   if (hipGetLastError() != hipSuccess) return JSIDX_E_HIP;
   return JSIDX_OK;

@@ -111,11 +111,8 @@ long emu_scopes_run(const uint8_t* buf, uint64_t len, const uint32_t* idx, uint3
   a.chunk_min = reinterpret_cast<uint32_t*>(m + L.chunk_min);
   a.qcount = reinterpret_cast<uint32_t*>(m + L.qcount);
   a.lev = reinterpret_cast<uint32_t*>(m + L.lev);
-  a.qt = reinterpret_cast<uint32_t*>(m + L.qt);
-  a.dep = reinterpret_cast<uint32_t*>(m + L.dep);
   a.queue = reinterpret_cast<uint32_t*>(m + L.queue);
   a.kind = m + L.kind;
-  a.ck = m + L.ck;
   auto phase = [&](int ngroups, void (*body)(const ScopeArgs&)) {
     std::vector<prim::GroupCtx*> groups;
     for (int b = 0; b < ngroups; b++) groups.push_back(new prim::GroupCtx(kScopeThreads));
@@ -141,7 +138,7 @@ long emu_scopes_run(const uint8_t* buf, uint64_t len, const uint32_t* idx, uint3
     phase((int)a.nchunks, scope_levels);
     phase((int)a.nchunks, scope_local);
     phase(far_groups, scope_far);
-    phase(2, scope_check);  // a grid-stride loop: two groups cover any size
+    phase((int)a.nchunks, scope_check);
   }
   return env.violations.load();
 }

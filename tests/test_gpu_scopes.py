@@ -92,12 +92,18 @@ def test_scopes_full_size_c1():
 
 
 def test_structure_of_every_short_token_sequence():
+    """Every sequence of up to 4 tokens, and 3000 random ones of 5 to 9."""
     _say("case: structure of token sequences up to 4")
     toks = ["{", "}", "[", "]", ":", ",", '"s"', "1"]
     for n in range(0, 5):
         for seq in itertools.product(toks, repeat=n):
             d = " ".join(seq).encode()
             assert_scopes_match(d, repr(d))
+    _say("case: structure of random token sequences of 5 to 9")
+    rng = random.Random(31)
+    for _ in range(3000):
+        d = " ".join(rng.choice(toks) for _ in range(rng.randrange(5, 10))).encode()
+        assert_scopes_match(d, repr(d))
 
 
 def test_structure_edits_of_generated_documents():

@@ -132,21 +132,47 @@ PAPER_ABLATION = {"twitter": {"default": 0.90, "xor_loop": 0.92, "direct_flatten
                   "canada": {"default": 0.90, "xor_loop": 0.94, "direct_flatten": 0.96, "naive_classify": 0.96}}
 
 
-def ablation(jx, torch, docs: dict, steps: int, restore: int) -> dict:
+def ablation(jx, torch, docs: dict, steps: int, restore: int, rounds: int = 5) -> dict:
     """Each kernel variant (one of the paper's stage-1 optimizations turned
-    off) timed on the same documents as the default kernel: microseconds per
-    launch and the cost relative to the default, beside the paper's relative
-    costs (twitter for C1, canada for C2: the same kinds of document)."""
-    out = {}
+    off) timed on the same documents as the default kernel: `rounds` rounds,
+    each timing `steps` launches of every variant in turn between two events
+    (interleaved, so that drifts of the device hit all alike); the median per
+    variant in microseconds per launch and relative to the default, beside the
+    paper's relative costs (twitter for C1, canada for C2: the same kinds of
+    document)."""
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    out = {name: {} for name in jx.VARIANTS}
     try:
-        for name, v in jx.VARIANTS.items():
-            jx.set_variant(v)
-            out[name] = {}
-            for wl, data in docs.items():
-                r = time_single(jx, torch, data, steps, 2)
-                out[name][wl] = {"us_per_launch": round(r["ms_per_launch"] * 1e3, 2),
-                                 "input_GBps": round(r["N"] / (r["ms_per_launch"] / 1e3) / 1e9, 1),
-                                 "index_entries": r["S"]}
+        for wl, data in docs.items():
+            n = len(data)
+            src = torch.frombuffer(bytearray(data), dtype=torch.uint8)
+            bufs = [src.to(dev) for _ in range(3)]
+            idx = torch.empty(n, dtype=torch.int32, device=dev)
+            cnt = torch.empty(1, dtype=torch.int32, device=dev)
+            err = torch.empty(1, dtype=torch.int32, device=dev)
+            jx.reserve(n, stream)
+            times = {name: [] for name in jx.VARIANTS}
+            counts = {}
+            for _ in range(rounds):
+                for name, v in jx.VARIANTS.items():
+                    jx.set_variant(v)
+                    for i in range(2):
+                        jx.build(bufs[i % 3], idx, cnt, err, stream)
+                    a = torch.cuda.Event(enable_timing=True)
+                    b = torch.cuda.Event(enable_timing=True)
+                    a.record(stream)
+                    for i in range(steps):
+                        jx.build(bufs[i % 3], idx, cnt, err, stream)
+                    b.record(stream)
+                    torch.cuda.synchronize()
+                    times[name].append(a.elapsed_time(b) / steps * 1e3)
+                    counts[name] = int(cnt.item())
+            for name in jx.VARIANTS:
+                us = float(np.median(times[name]))
+                out[name][wl] = {"us_per_launch": round(us, 2), "input_GBps": round(n / us / 1e3, 1),
+                                 "index_entries": counts[name]}
+            del bufs, idx
     finally:
         jx.set_variant(restore)
     for name in out:

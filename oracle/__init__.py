@@ -7,7 +7,8 @@ benchmark may import this package; the HIP library never does.
 
 Flag bits (defined here independently of the HIP library's header):
 UTF8 = 0x1, UNCLOSED_STRING = 0x2, TRAILING_ESCAPE = 0x4, EMPTY = 0x8; scope
-matching: UNBALANCED = 0x10, MISMATCHED = 0x20; structure: SYNTAX = 0x40.
+matching: UNBALANCED = 0x10, MISMATCHED = 0x20; structure: SYNTAX = 0x40;
+tape (stage 2, Sec. 3.2): NUMBER = 0x100, STRING = 0x200, LITERAL = 0x400.
 """
 from __future__ import annotations
 
@@ -59,6 +60,8 @@ def _load():
     lib.oracle_scopes.restype = ctypes.c_uint32
     lib.oracle_structure.argtypes = [u8p, u32p, ctypes.c_uint32, u32p]
     lib.oracle_structure.restype = ctypes.c_uint32
+    lib.oracle_tape.argtypes = [u8p, ctypes.c_uint64, u32p, ctypes.c_uint32, u64p, u64p, u8p, u64p, u32p]
+    lib.oracle_tape.restype = ctypes.c_uint32
     lib.oracle_utf8_valid.argtypes = [u8p, ctypes.c_uint64]
     lib.oracle_utf8_valid.restype = ctypes.c_int
     _lib = lib
@@ -176,6 +179,32 @@ def structure(buf, idx) -> int:
         raise ValueError("positions exceed the document")
     return int(_load().oracle_structure(_ptr(a, ctypes.c_uint8) if a.size else None, _ptr(ix, ctypes.c_uint32),
                                         ix.size, _ptr(stack, ctypes.c_uint32)))
+
+
+ERR_NUMBER = 0x100
+ERR_STRING = 0x200
+ERR_LITERAL = 0x400
+
+
+def tape(buf, idx) -> tuple[np.ndarray, bytes, int]:
+    """The stage-2 tape of a document (Sec. 3, Fig. 2) from its index: the
+    tape words (uint64), the string buffer, and the flags of the atoms and
+    strings (NUMBER, STRING, LITERAL).  The tape and buffer are empty unless
+    the structure is valid and no flag is set."""
+    a = _u8(buf)
+    ix = np.ascontiguousarray(idx, dtype=np.uint32)
+    n = ix.size
+    if n and int(ix.max()) >= a.size:
+        raise ValueError("positions exceed the document")
+    words = np.zeros(2 * n + 2, dtype=np.uint64)
+    sbuf = np.zeros(a.size + 2 * n + 1, dtype=np.uint8)
+    stack = np.empty(max(1, n), dtype=np.uint32)
+    tn = np.zeros(1, dtype=np.uint64)
+    sn = np.zeros(1, dtype=np.uint64)
+    flags = _load().oracle_tape(_ptr(a, ctypes.c_uint8) if a.size else None, a.size, _ptr(ix, ctypes.c_uint32), n,
+                                _ptr(words, ctypes.c_uint64), _ptr(tn, ctypes.c_uint64), _ptr(sbuf, ctypes.c_uint8),
+                                _ptr(sn, ctypes.c_uint64), _ptr(stack, ctypes.c_uint32))
+    return words[:int(tn[0])].copy(), sbuf[:int(sn[0])].tobytes(), int(flags)
 
 
 def utf8_valid(buf) -> bool:

@@ -49,8 +49,11 @@
  *   0x4 TRAILING_ESCAPE  the document ends with an odd run of backslashes
  *   0x8 EMPTY            the index is empty
  */
+#include <math.h>
 #include <stddef.h>
 #include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
 
 #define OR_ERR_UTF8 0x1u
 #define OR_ERR_UNCLOSED_STRING 0x2u
@@ -313,4 +316,250 @@ uint32_t oracle_structure(const uint8_t *buf, const uint32_t *idx, uint32_t n,
     }
   }
   return st == ST_DONE ? 0u : 0x40u;
+}
+
+/* ---- The tape (Sec. 3, Fig. 2; stage 2, Sec. 3.2) ----------------------------
+ * oracle_tape walks the index entries in order and writes the tape: 64-bit
+ * words tagged with a character in bits 56..63.
+ *   - root: word 0 is 'r' with the index of the last word, the last word 'r'
+ *     with 0;
+ *   - '{' or '[': the tag with one plus the index of its closing word; '}' or
+ *     ']': the tag with the index of its opening word;
+ *   - a string: '"' with the offset of its entry in the string buffer, which
+ *     holds a 32-bit little-endian length and then the UTF-8 bytes;
+ *   - true, false, null: 't', 'f', 'n';
+ *   - a number: 'l' and the int64 value, or 'd' and the binary64 value.
+ * ':' and ',' write nothing.
+ * Each atom and string is checked on its own (Sec. 3.2: the locations of all
+ * tokens are known, so none depends on another), and the flags collect the
+ * errors of all of them: NUMBER (0x100), STRING (0x200), LITERAL (0x400).
+ * The tape is written only when the structure is valid (oracle_structure) and
+ * no flag is set; otherwise *tape_n and *str_n are 0.
+ *
+ * Numbers (Sec. 3.2, number grammar of the JSON specification): an optional
+ * minus, then 0 or a digit 1-9 followed by digits, then optionally '.' and
+ * digits, then optionally e/E, an optional sign and digits.  Without fraction
+ * and exponent the number is an integer and must lie in [-2^63, 2^63).  With
+ * either it is a double: the correctly rounded (nearest, ties to even)
+ * binary64 value of the decimal, taken from the C library's strtod on the
+ * validated text; a value that rounds to infinity is an error (1e309).  The
+ * atom must end at white space, a structural character or the end of the
+ * document.
+ * Strings (Sec. 3.2.2): the bytes up to the closing quote; a byte below 0x20
+ * is an error; escapes \" \\ \/ \b \f \n \r \t and \uXXXX (four hex digits),
+ * where a high surrogate D800-DBFF must be followed by \u and a low surrogate
+ * DC00-DFFF (the pair is one code point) and a lone surrogate is an error; the
+ * code point is written as UTF-8.  A string that does not close before the
+ * end of the document is an error.
+ * Literals: an atom starting with t, f or n must be exactly true, false or
+ * null, ending as numbers end (else LITERAL); every other atom is read as a
+ * number (so ".1" or "abc" is a NUMBER error).
+ * stack needs room for n entries; tape for 2n + 2 words; strbuf for len + 2n
+ * bytes. */
+#define OR_ERR_NUMBER 0x100u
+#define OR_ERR_STRING 0x200u
+#define OR_ERR_LITERAL 0x400u
+
+static int atom_end(const uint8_t *buf, uint64_t len, uint64_t p) {
+  return p >= len || is_whitespace(buf[p]) || is_structural(buf[p]);
+}
+
+static int hexval(uint8_t c) {
+  if (c >= '0' && c <= '9') return c - '0';
+  if (c >= 'a' && c <= 'f') return c - 'a' + 10;
+  if (c >= 'A' && c <= 'F') return c - 'A' + 10;
+  return -1;
+}
+
+/* four hex digits at p; -1 if not */
+static int32_t hex4(const uint8_t *buf, uint64_t len, uint64_t p) {
+  int32_t v = 0;
+  if (p + 4 > len) return -1;
+  for (int k = 0; k < 4; k++) {
+    int h = hexval(buf[p + k]);
+    if (h < 0) return -1;
+    v = v * 16 + h;
+  }
+  return v;
+}
+
+static uint32_t put_utf8(uint8_t *out, uint32_t cp) {
+  if (cp < 0x80) { out[0] = (uint8_t)cp; return 1; }
+  if (cp < 0x800) { out[0] = (uint8_t)(0xC0 | (cp >> 6)); out[1] = (uint8_t)(0x80 | (cp & 0x3F)); return 2; }
+  if (cp < 0x10000) {
+    out[0] = (uint8_t)(0xE0 | (cp >> 12)); out[1] = (uint8_t)(0x80 | ((cp >> 6) & 0x3F));
+    out[2] = (uint8_t)(0x80 | (cp & 0x3F));
+    return 3;
+  }
+  out[0] = (uint8_t)(0xF0 | (cp >> 18)); out[1] = (uint8_t)(0x80 | ((cp >> 12) & 0x3F));
+  out[2] = (uint8_t)(0x80 | ((cp >> 6) & 0x3F)); out[3] = (uint8_t)(0x80 | (cp & 0x3F));
+  return 4;
+}
+
+/* The string whose opening quote is at q: decoded bytes to out (room for the
+ * raw length), their count to *n.  Returns 0 or OR_ERR_STRING. */
+static uint32_t decode_string(const uint8_t *buf, uint64_t len, uint64_t q, uint8_t *out, uint32_t *n) {
+  uint64_t p = q + 1;
+  uint32_t k = 0;
+  *n = 0;
+  for (;;) {
+    if (p >= len) return OR_ERR_STRING;  /* never closed */
+    uint8_t c = buf[p];
+    if (c == '"') break;
+    if (c < 0x20) return OR_ERR_STRING;
+    if (c != '\\') { out[k++] = c; p++; continue; }
+    if (p + 1 >= len) return OR_ERR_STRING;
+    uint8_t e = buf[p + 1];
+    p += 2;
+    switch (e) {
+      case '"': out[k++] = '"'; break;
+      case '\\': out[k++] = '\\'; break;
+      case '/': out[k++] = '/'; break;
+      case 'b': out[k++] = 0x08; break;
+      case 'f': out[k++] = 0x0C; break;
+      case 'n': out[k++] = 0x0A; break;
+      case 'r': out[k++] = 0x0D; break;
+      case 't': out[k++] = 0x09; break;
+      case 'u': {
+        int32_t u = hex4(buf, len, p);
+        if (u < 0) return OR_ERR_STRING;
+        p += 4;
+        uint32_t cp = (uint32_t)u;
+        if (cp >= 0xDC00 && cp <= 0xDFFF) return OR_ERR_STRING;  /* lone low surrogate */
+        if (cp >= 0xD800 && cp <= 0xDBFF) {
+          if (p + 2 > len || buf[p] != '\\' || buf[p + 1] != 'u') return OR_ERR_STRING;
+          int32_t lo = hex4(buf, len, p + 2);
+          if (lo < 0xDC00 || lo > 0xDFFF) return OR_ERR_STRING;
+          p += 6;
+          cp = 0x10000u + ((cp - 0xD800u) << 10) + ((uint32_t)lo - 0xDC00u);
+        }
+        k += put_utf8(out + k, cp);
+        break;
+      }
+      default: return OR_ERR_STRING;
+    }
+  }
+  *n = k;
+  return 0;
+}
+
+/* The number at p.  Returns 0 (with *is_int and the value in *bits) or
+ * OR_ERR_NUMBER. */
+static uint32_t parse_number(const uint8_t *buf, uint64_t len, uint64_t p0, int *is_int, uint64_t *bits) {
+  uint64_t p = p0;
+  int neg = 0, frac = 0, expo = 0;
+  if (p < len && buf[p] == '-') { neg = 1; p++; }
+  if (p >= len || buf[p] < '0' || buf[p] > '9') return OR_ERR_NUMBER;
+  uint64_t int_start = p;
+  if (buf[p] == '0') p++;
+  else while (p < len && buf[p] >= '0' && buf[p] <= '9') p++;
+  uint64_t int_end = p;
+  if (p < len && buf[p] == '.') {
+    frac = 1;
+    p++;
+    uint64_t s = p;
+    while (p < len && buf[p] >= '0' && buf[p] <= '9') p++;
+    if (p == s) return OR_ERR_NUMBER;
+  }
+  if (p < len && (buf[p] == 'e' || buf[p] == 'E')) {
+    expo = 1;
+    p++;
+    if (p < len && (buf[p] == '+' || buf[p] == '-')) p++;
+    uint64_t s = p;
+    while (p < len && buf[p] >= '0' && buf[p] <= '9') p++;
+    if (p == s) return OR_ERR_NUMBER;
+  }
+  if (!atom_end(buf, len, p)) return OR_ERR_NUMBER;
+  if (!frac && !expo) {
+    /* integer: magnitude at most 2^63 - 1, or 2^63 when negative */
+    const uint64_t lim = neg ? (1ull << 63) : (1ull << 63) - 1;
+    uint64_t m = 0;
+    for (uint64_t i = int_start; i < int_end; i++) {
+      uint64_t d = (uint64_t)(buf[i] - '0');
+      if (m > (lim - d) / 10) return OR_ERR_NUMBER;
+      m = m * 10 + d;
+    }
+    *is_int = 1;
+    *bits = neg ? (uint64_t)0 - m : m;
+    return 0;
+  }
+  /* double: strtod on a NUL-terminated copy of the validated text */
+  size_t L = (size_t)(p - p0);
+  char small[64];
+  char *txt = L < sizeof(small) ? small : (char *)malloc(L + 1);
+  if (!txt) return OR_ERR_NUMBER;
+  memcpy(txt, buf + p0, L);
+  txt[L] = 0;
+  double v = strtod(txt, NULL);
+  if (txt != small) free(txt);
+  if (isinf(v)) return OR_ERR_NUMBER;
+  memcpy(bits, &v, 8);
+  *is_int = 0;
+  return 0;
+}
+
+static uint32_t check_literal(const uint8_t *buf, uint64_t len, uint64_t p, uint8_t *tag) {
+  static const char *const words[3] = {"true", "false", "null"};
+  for (int w = 0; w < 3; w++) {
+    size_t L = strlen(words[w]);
+    if (p + L <= len && memcmp(buf + p, words[w], L) == 0 && atom_end(buf, len, p + L)) {
+      *tag = (uint8_t)words[w][0];
+      return 0;
+    }
+  }
+  return OR_ERR_LITERAL;
+}
+
+static uint64_t tagged(uint8_t tag, uint64_t payload) { return ((uint64_t)tag << 56) | payload; }
+
+uint32_t oracle_tape(const uint8_t *buf, uint64_t len, const uint32_t *idx, uint32_t n, uint64_t *tape,
+                     uint64_t *tape_n, uint8_t *strbuf, uint64_t *str_n, uint32_t *stack) {
+  uint32_t flags = 0;
+  uint64_t t = 1, s = 0;
+  uint32_t top = 0;
+  const int structure_ok = oracle_structure(buf, idx, n, stack) == 0;
+  for (uint32_t i = 0; i < n; i++) {
+    const uint64_t p = idx[i];
+    const uint8_t b = buf[p];
+    if (b == '{' || b == '[') {
+      stack[top++] = (uint32_t)t;
+      tape[t++] = tagged(b, 0);
+    } else if (b == '}' || b == ']') {
+      if (structure_ok) {
+        const uint32_t o = stack[--top];
+        tape[o] |= t + 1;
+        tape[t++] = tagged(b, o);
+      }
+    } else if (b == ':' || b == ',') {
+      /* no tape word */
+    } else if (b == '"') {
+      uint32_t k = 0;
+      uint32_t e = decode_string(buf, len, p, strbuf + s + 4, &k);
+      flags |= e;
+      memcpy(strbuf + s, &k, 4);  /* little-endian host */
+      tape[t++] = tagged('"', s);
+      s += 4 + (uint64_t)k;
+    } else if (b != 't' && b != 'f' && b != 'n') {  /* a number, or an invalid atom */
+      int is_int = 0;
+      uint64_t bits = 0;
+      uint32_t e = parse_number(buf, len, p, &is_int, &bits);
+      flags |= e;
+      tape[t++] = tagged(is_int ? 'l' : 'd', 0);
+      tape[t++] = bits;
+    } else {
+      uint8_t tag = 0;
+      flags |= check_literal(buf, len, p, &tag);
+      tape[t++] = tagged(tag, 0);
+    }
+  }
+  if (!structure_ok || flags) {
+    *tape_n = 0;
+    *str_n = 0;
+    return flags;
+  }
+  tape[0] = tagged('r', t);
+  tape[t] = tagged('r', 0);
+  *tape_n = t + 1;
+  *str_n = s;
+  return flags;
 }

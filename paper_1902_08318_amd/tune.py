@@ -10,8 +10,9 @@ document of that size, at each candidate tile size and keeps the fastest.  The t
 (jsidx_set_tile_rows) and to a JSON cache keyed by the GPU architecture.
 The kernel variants (the default and those with one of the paper's stage-1
 optimizations turned off, App. B) are alternatives too: with the table set,
-each is timed on the whole batch and the large document, and the fastest is
-kept (jsidx_set_variant).
+each is timed on the whole batch and the large document (rounds over the
+variants in turn, medians), and another variant replaces the default only if
+it saves more than VARIANT_MARGIN of the time (jsidx_set_variant).
 Results never depend on the tile size or the variant; only time does.
 """
 from __future__ import annotations
@@ -25,6 +26,8 @@ import numpy as np
 from . import binding
 
 CANDIDATES = (2, 4, 8, 16)
+VARIANT_ROUNDS = 3
+VARIANT_MARGIN = 0.03  # relative time a variant must save over the default
 
 
 def default_cache_path(arch: str) -> str:
@@ -129,13 +132,21 @@ def autotune(data: bytes, offsets: np.ndarray, single: bytes | None = None, clas
         work = {"batch": batch_call(nd_all)}
         if single:
             work["single"] = single_call(len(single))
-        for name, v in binding.VARIANTS.items():
-            binding.set_variant(v)
-            variant_us[name] = {k: round(_time(torch, call, stream, max(3, reps // 4)), 2)
-                                for k, call in work.items()}
-        best_us = {k: min(variant_us[name][k] for name in variant_us) for k in work}
-        chosen = min(variant_us, key=lambda name: (sum(variant_us[name][k] / best_us[k] for k in work),
-                                                   binding.VARIANTS[name]))
+        # rounds over the variants in turn (a drift of the device hits all
+        # alike); the median per variant and workload
+        samples = {name: {k: [] for k in work} for name in binding.VARIANTS}
+        for _ in range(VARIANT_ROUNDS):
+            for name, v in binding.VARIANTS.items():
+                binding.set_variant(v)
+                for k, call in work.items():
+                    samples[name][k].append(_time(torch, call, stream, max(5, reps // 2)))
+        variant_us = {name: {k: round(float(np.median(t)), 2) for k, t in ks.items()} for name, ks in samples.items()}
+        score = {name: sum(variant_us[name][k] / variant_us["default"][k] for k in work) / len(work)
+                 for name in variant_us}
+        # another variant replaces the default only when clearly faster
+        chosen = min(variant_us, key=lambda name: (score[name], binding.VARIANTS[name]))
+        if score[chosen] > 1.0 - VARIANT_MARGIN:
+            chosen = "default"
         variant = binding.VARIANTS[chosen]
         if log:
             log("tune: variants " + "; ".join(f"{name}: " + " ".join(f"{k} {t:.1f}" for k, t in us.items())

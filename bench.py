@@ -309,6 +309,43 @@ def time_scopes(jx, torch, data: bytes, steps: int) -> dict:
             "flags": int(serr.item()) & 0xFFFFFFFF}
 
 
+def time_tape(jx, torch, data: bytes, steps: int) -> dict:
+    """The stage-2 tape (jsidx_tape) over the document's index and links, both
+    already built and resident; two events around the launches."""
+    dev = torch.device("cuda:0")
+    n = len(data)
+    buf = torch.frombuffer(bytearray(data), dtype=torch.uint8).to(dev)
+    idx = torch.empty(n, dtype=torch.int32, device=dev)
+    cnt = torch.empty(1, dtype=torch.int32, device=dev)
+    err = torch.empty(1, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+    jx.build(buf, idx, cnt, err, stream)
+    k = int(cnt.item())
+    match = torch.empty(k, dtype=torch.int32, device=dev)
+    serr = torch.empty(1, dtype=torch.int32, device=dev)
+    jx.scopes(buf, idx, match, serr, stream, n=k)
+    words = torch.empty(2 * k + 2, dtype=torch.int64, device=dev)
+    sbuf = torch.empty(n + 2 * k + 4, dtype=torch.uint8, device=dev)
+    tn = torch.empty(1, dtype=torch.int64, device=dev)
+    sn = torch.empty(1, dtype=torch.int64, device=dev)
+    terr = torch.empty(1, dtype=torch.int32, device=dev)
+    call = lambda: jx.tape(buf, idx, match, words, tn, sbuf, sn, terr, stream, n=k)  # noqa: E731
+    for _ in range(2):
+        call()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(steps):
+        call()
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    return {"entries": k, "tape_words": int(tn.item()), "string_bytes": int(sn.item()), "ms_per_call": round(ms, 4),
+            "input_GBps": round(n / (ms / 1e3) / 1e9, 1), "flags": int(terr.item()) & 0xFFFFFFFF,
+            "scope_flags": int(serr.item()) & 0xFFFFFFFF}
+
+
 def cpu_batch_baseline(data: bytes, offsets: np.ndarray, budget_s: float = 6.0) -> dict:
     """The oracle over a batch: one core, then the documents partitioned into
     contiguous byte-balanced ranges over every host core (one thread each; the
@@ -446,9 +483,9 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the numeric and batched workloads")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--size-mib", type=int, default=256)
-    ap.add_argument("--workload", choices=["c1", "c2", "c3", "scopes"], default="c1",
-                    help="headline workload (c2/c3/scopes only for profiling runs; scopes: the scope "
-                         "links and structure check over the C1 index)")
+    ap.add_argument("--workload", choices=["c1", "c2", "c3", "scopes", "tape"], default="c1",
+                    help="headline workload (c2/c3/scopes/tape only for profiling runs; scopes: the scope "
+                         "links and structure check over the C1 index; tape: the stage-2 tape of C1)")
     ap.add_argument("--serve-seconds", type=float, default=1.0,
                     help="C4 serving loop: seconds per offered load (0 skips it)")
     ap.add_argument("--no-tune", action="store_true", help="keep the built-in tile size choice")
@@ -489,6 +526,9 @@ def main():
         log("autotuning the tile size on the 100k-document batch and the headline document")
         c3 = synth.gen_c3(3)
         tuning = tune.autotune(c3[0], c3[1], c1.data if c1 is not None else None, log=log)
+    if args.workload == "tape":
+        print(json.dumps({"workload": "tape of C1", **time_tape(jx, torch, c1.data, args.steps)}), flush=True)
+        return
     if args.workload == "scopes":
         print(json.dumps({"workload": "scopes over the C1 index",
                           **time_scopes(jx, torch, c1.data, args.steps)}), flush=True)
@@ -538,6 +578,9 @@ def main():
                        "ms_per_launch": round(r2["ms_per_launch"], 4), "launch_ms": r2["launch_ms"]}
         log("scope links over the C1 index")
         extra["scopes"] = {"C1": time_scopes(jx, torch, c1.data, max(3, args.steps // 2))}
+        log("tape: C1 and C2")
+        extra["tape"] = {"C1": time_tape(jx, torch, c1.data, max(3, args.steps // 2)),
+                         "C2": time_tape(jx, torch, c2.data, max(3, args.steps // 2))}
         log("minify: C2 and the C3 batch")
         extra["minify"] = {"C2": time_minify(jx, torch, c2.data, None, args.steps)}
         log("kernel variants (the paper's stage-1 ablation) on C1 and C2")

@@ -178,6 +178,49 @@ int jsidx_scopes(const uint8_t *buf, uint64_t len, const uint32_t *idx,
                  jsidx_stream_t stream);
 
 /*
+ * jsidx_tape -- the tape of the paper's stage 2 (Sec. 3, Fig. 2; Sec. 3.2)
+ * from a document's index and its scope links: 64-bit words, the top 8 bits a
+ * tag character.  Word 0 is 'r' with the index of the last word, which is 'r'
+ * with 0.  Then in index order: '{' or '[' with one plus the index of its
+ * closing word, '}' or ']' with the index of its opening word, '"' with the
+ * offset of the string in the string buffer (a 32-bit little-endian length,
+ * then the UTF-8 bytes; escapes decoded, \uXXXX and surrogate pairs as
+ * UTF-8), 't' 'f' 'n' for the literals, and numbers as two words: 'l' and
+ * the int64 value, or 'd' and the binary64 value (correctly rounded, ties to
+ * even).  ':' and ',' take no word.
+ *   buf, len   device pointer to the document (len < 2^32).
+ *   idx, n     device array of the n index entries (jsidx_build's output for
+ *              this document), n < 2^31.
+ *   match      device array of n links from jsidx_scopes on the same index;
+ *              the brackets' words take their partners from it (0 for an
+ *              unlinked bracket).
+ *   out_tape   device array of at least 2n + 2 uint64.
+ *   out_tape_n device uint64: the number of words written.
+ *   out_str    device buffer of at least len + 2n + 4 bytes.
+ *   out_str_n  device uint64: the string buffer's size.
+ *   out_err    device uint32: 0 or JSIDX_ERR_NUMBER (an atom that is not a
+ *              number per the grammar -- minus, integer part without leading
+ *              zeros, fraction, exponent -- or not ended by white space, a
+ *              structural character or the end; an integer outside
+ *              [-2^63, 2^63); a double that rounds to infinity),
+ *              JSIDX_ERR_STRING (a byte below 0x20, an unknown escape, a bad
+ *              \u, a lone surrogate, no closing quote), JSIDX_ERR_LITERAL (an
+ *              atom starting with t, f or n that is not exactly true, false
+ *              or null).  Every atom and string is checked, each on its own.
+ * The tape is the paper's only when jsidx_scopes reported no flag and out_err
+ * is 0.  A per-stream workspace of about 20 bytes per entry is allocated on
+ * first use and grown as needed (synchronising the stream).  Asynchronous on
+ * `stream`; returns JSIDX_E_INVAL for NULL pointers or sizes out of range.
+ */
+#define JSIDX_ERR_NUMBER 0x100u
+#define JSIDX_ERR_STRING 0x200u
+#define JSIDX_ERR_LITERAL 0x400u
+int jsidx_tape(const uint8_t *buf, uint64_t len, const uint32_t *idx,
+               uint32_t n, const uint32_t *match, uint64_t *out_tape,
+               uint64_t *out_tape_n, uint8_t *out_str, uint64_t *out_str_n,
+               uint32_t *out_err, jsidx_stream_t stream);
+
+/*
  * jsidx_reserve -- size the workspace of `stream` for inputs of up to
  * max_total_len bytes in total (single document or batch) and switch batch
  * calls on that stream to the no-synchronisation mode described above.  Call

@@ -197,7 +197,7 @@ def tape(buf, idx) -> tuple[np.ndarray, bytes, int]:
     if n and int(ix.max()) >= a.size:
         raise ValueError("positions exceed the document")
     words = np.zeros(2 * n + 2, dtype=np.uint64)
-    sbuf = np.zeros(a.size + 2 * n + 1, dtype=np.uint8)
+    sbuf = np.zeros(a.size + 2 * n + 4, dtype=np.uint8)
     stack = np.empty(max(1, n), dtype=np.uint32)
     tn = np.zeros(1, dtype=np.uint64)
     sn = np.zeros(1, dtype=np.uint64)

@@ -17,6 +17,9 @@ ERR_EMPTY = 0x8
 ERR_UNBALANCED = 0x10
 ERR_MISMATCHED = 0x20
 ERR_SYNTAX = 0x40
+ERR_NUMBER = 0x100
+ERR_STRING = 0x200
+ERR_LITERAL = 0x400
 ERR_CAPACITY = 0x80000000
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -38,6 +41,7 @@ SIGNATURES = {
     "jsidx_status_string": ([ctypes.c_int], ctypes.c_char_p),
     "jsidx_set_tile_rows": ([_VP, ctypes.c_uint32], ctypes.c_int),
     "jsidx_set_variant": ([ctypes.c_uint32], ctypes.c_int),
+    "jsidx_tape": ([_VP, ctypes.c_uint64, _VP, ctypes.c_uint32, _VP, _VP, _VP, _VP, _VP, _VP, _VP], ctypes.c_int),
     "jsidx_tile_rows": ([ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint32)], ctypes.c_int),
 }
 
@@ -144,6 +148,16 @@ def set_tile_rows(rows_by_log2) -> None:
     t = bytes(int(r) for r in rows_by_log2)
     buf = ctypes.create_string_buffer(t, max(1, len(t)))
     _check(lib().jsidx_set_tile_rows(ctypes.cast(buf, ctypes.c_void_p), len(t)))
+
+
+def tape(buf, idx, match, out_tape, out_tape_n, out_str, out_str_n, out_err, stream=None, n=None, length=None):
+    """jsidx_tape on device tensors: buf (uint8 document), idx and match (the
+    first n entries and their links), out_tape (>= 2n + 2 int64), out_tape_n
+    and out_str_n (1 int64 each), out_str (>= len + 2n + 4 uint8), out_err (1)."""
+    n = idx.numel() if n is None else int(n)
+    ln = buf.numel() if length is None else int(length)
+    _check(lib().jsidx_tape(_ptr(buf), ln, _ptr(idx), n, _ptr(match), _ptr(out_tape), _ptr(out_tape_n),
+                            _ptr(out_str), _ptr(out_str_n), _ptr(out_err), _stream(stream)))
 
 
 VARIANT_NAIVE_CLASSIFY = 1

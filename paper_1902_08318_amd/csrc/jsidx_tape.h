@@ -1,0 +1,805 @@
+// jsidx_tape.h -- stage 2's tape (Sec. 3, Fig. 2) from a document's structural
+// index and scope links: 64-bit words tagged with a character in bits 56..63,
+// numbers parsed (two words: 'l' and an int64, or 'd' and a binary64), strings
+// normalized into a string buffer (a 32-bit length, then UTF-8), literals
+// checked.  Once the index is known no token depends on another (Sec. 3.2), so
+// every entry is handled by its own thread:
+//   1. tape_count: the words of each entry (0 for ':' and ',', 2 for a number,
+//      else 1) and the buffer bytes of each string (decoded, not written),
+//      summed per chunk of 4096 entries;
+//   2. tape_scan: one workgroup turns the chunk sums into bases and writes the
+//      root words, the sizes, and clears the flags;
+//   3. tape_offsets: each entry's tape index and buffer offset (a scan inside
+//      the chunk);
+//   4. tape_write: every entry's words: brackets with the tape index of their
+//      partner (from the scope links), strings decoded into the buffer,
+//      numbers converted, literals checked.  A double whose rounding the fast
+//      conversion cannot decide is queued;
+//   5. tape_exact: the queued numbers by exact big-integer arithmetic.
+// Written on the same primitives as the other kernels, so that the CPU
+// emulation of the tests runs this source too.
+#pragma once
+
+#include "jsidx_device.h"
+
+#ifndef JSIDX_CONSTANT
+#define JSIDX_CONSTANT __constant__
+#endif
+#include "jsidx_pow5.h"
+
+namespace jsidx {
+
+constexpr uint32_t kErrNumber = 0x100u;
+constexpr uint32_t kErrString = 0x200u;
+constexpr uint32_t kErrLiteral = 0x400u;
+constexpr int kTapeThreads = 256;
+constexpr int kTapePer = 16;
+constexpr int kTapeChunk = kTapeThreads * kTapePer;
+constexpr uint32_t kTapeUnlinked = 0xFFFFFFFFu;
+constexpr int kExactGroups = 64;      // workgroups of tape_exact
+constexpr int kExactThreads = 64;     // one wave each
+constexpr int kMaxDigits = 800;       // significant digits kept by the exact path
+constexpr int kBigLimbs = 300;        // 9600 bits per big integer
+
+struct TapeArgs {
+  const uint8_t* buf;
+  uint64_t len;
+  const uint32_t* idx;
+  uint32_t n;
+  uint32_t nchunks;
+  const uint32_t* match;
+  uint64_t* tape;
+  uint8_t* str;
+  uint64_t* tape_n;
+  uint64_t* str_n;
+  uint32_t* err;
+  // workspace
+  uint64_t* chunk_sum;  // 2 per chunk: words, buffer bytes; then their bases
+  uint32_t* sbytes;     // per entry: buffer bytes of a string, else 0
+  uint32_t* toff;       // per entry: tape index of its first word
+  uint64_t* soff;       // per entry: buffer offset of a string
+  uint32_t* qcount;     // numbers queued for the exact conversion
+  uint32_t* queue;      // their entries
+};
+
+struct TapeLayout {
+  uint64_t chunk_sum, sbytes, toff, soff, qcount, queue, total;
+};
+inline uint64_t tape_align256(uint64_t x) { return (x + 255) & ~(uint64_t)255; }
+inline TapeLayout tape_layout(uint64_t n) {
+  const uint64_t nc = (n + kTapeChunk - 1) / kTapeChunk;
+  TapeLayout L;
+  uint64_t o = 0;
+  L.chunk_sum = o; o = tape_align256(o + nc * 16);
+  L.sbytes = o; o = tape_align256(o + n * 4);
+  L.toff = o; o = tape_align256(o + n * 4);
+  L.soff = o; o = tape_align256(o + n * 8);
+  L.qcount = o; o = tape_align256(o + 4);
+  L.queue = o; o = tape_align256(o + n * 4);
+  L.total = o;
+  return L;
+}
+
+JSIDX_DEV uint32_t tape_tid() { return prim::wave_id() * 64u + prim::lane(); }
+
+JSIDX_DEV uint32_t byte_at(const TapeArgs& a, uint64_t p) { return p < a.len ? prim::load1(a.buf + p) : 0u; }
+
+// The first byte of entry i (0 if its position is not inside the document).
+JSIDX_DEV uint32_t entry_byte(const TapeArgs& a, uint32_t i) {
+  return byte_at(a, prim::load4(reinterpret_cast<const uint8_t*>(a.idx + i)));
+}
+
+JSIDX_DEV bool is_lit_start(uint32_t b) { return b == 't' || b == 'f' || b == 'n'; }
+
+// Tape words of an entry by its first byte.
+JSIDX_DEV uint32_t words_of(uint32_t b) {
+  if (b == ':' || b == ',') return 0;
+  if (b == '{' || b == '}' || b == '[' || b == ']' || b == '"' || is_lit_start(b)) return 1;
+  return 2;  // a number (or an invalid atom, which is a number error)
+}
+
+// An atom ends at white space, a structural character or the document's end.
+JSIDX_DEV bool ends_atom(const TapeArgs& a, uint64_t p) {
+  if (p >= a.len) return true;
+  const uint32_t c = prim::load1(a.buf + p);
+  return c == ' ' || c == '\t' || c == '\n' || c == '\r' || c == ',' || c == ':' || c == '[' || c == ']' ||
+         c == '{' || c == '}';
+}
+
+// ---- Strings (Sec. 3.2.2) ---------------------------------------------------
+JSIDX_DEV int32_t hex_digit(uint32_t c) {
+  if (c >= '0' && c <= '9') return (int32_t)(c - '0');
+  if (c >= 'a' && c <= 'f') return (int32_t)(c - 'a' + 10);
+  if (c >= 'A' && c <= 'F') return (int32_t)(c - 'A' + 10);
+  return -1;
+}
+
+// Four hex digits at p, or -1.
+JSIDX_DEV int32_t hex_quad(const TapeArgs& a, uint64_t p) {
+  if (p + 4 > a.len) return -1;
+  int32_t v = 0;
+  for (int k = 0; k < 4; k++) {
+    const int32_t h = hex_digit(prim::load1(a.buf + p + k));
+    if (h < 0) return -1;
+    v = v * 16 + h;
+  }
+  return v;
+}
+
+template <bool WRITE>
+JSIDX_DEV void emit(uint8_t* out, uint32_t* k, uint32_t v) {
+  if constexpr (WRITE) prim::st_byte(out + *k, v);
+  ++*k;
+}
+
+// The string whose opening quote is at q: its bytes after normalization
+// (escapes decoded, \uXXXX and surrogate pairs as UTF-8) to out (WRITE) and
+// their count to *n.  A byte below 0x20, an unknown escape, a malformed or
+// lone surrogate, or no closing quote is an error (the count then stops
+// there, the same in both modes).
+template <bool WRITE>
+JSIDX_DEV uint32_t normalize_string(const TapeArgs& a, uint64_t q, uint8_t* out, uint32_t* n) {
+  uint64_t p = q + 1;
+  uint32_t k = 0;
+  uint32_t err = 0;
+  for (;;) {
+    if (p >= a.len) { err = kErrString; break; }
+    const uint32_t c = prim::load1(a.buf + p);
+    if (c == '"') break;
+    if (c < 0x20u) { err = kErrString; break; }
+    if (c != '\\') {
+      emit<WRITE>(out, &k, c);
+      p++;
+      continue;
+    }
+    if (p + 1 >= a.len) { err = kErrString; break; }
+    const uint32_t e = prim::load1(a.buf + p + 1);
+    p += 2;
+    uint32_t v = 0xFFFFFFFFu;
+    switch (e) {
+      case '"': v = '"'; break;
+      case '\\': v = '\\'; break;
+      case '/': v = '/'; break;
+      case 'b': v = 0x08u; break;
+      case 'f': v = 0x0Cu; break;
+      case 'n': v = 0x0Au; break;
+      case 'r': v = 0x0Du; break;
+      case 't': v = 0x09u; break;
+      default: break;
+    }
+    if (v != 0xFFFFFFFFu) {
+      emit<WRITE>(out, &k, v);
+      continue;
+    }
+    if (e != 'u') { err = kErrString; break; }
+    const int32_t u = hex_quad(a, p);
+    if (u < 0) { err = kErrString; break; }
+    p += 4;
+    uint32_t cp = (uint32_t)u;
+    if (cp >= 0xDC00u && cp <= 0xDFFFu) { err = kErrString; break; }  // a low surrogate first
+    if (cp >= 0xD800u && cp <= 0xDBFFu) {
+      if (p + 2 > a.len || prim::load1(a.buf + p) != '\\' || prim::load1(a.buf + p + 1) != 'u') {
+        err = kErrString;
+        break;
+      }
+      const int32_t lo = hex_quad(a, p + 2);
+      if (lo < 0xDC00 || lo > 0xDFFF) { err = kErrString; break; }
+      p += 6;
+      cp = 0x10000u + ((cp - 0xD800u) << 10) + ((uint32_t)lo - 0xDC00u);
+    }
+    if (cp < 0x80u) {
+      emit<WRITE>(out, &k, cp);
+    } else if (cp < 0x800u) {
+      emit<WRITE>(out, &k, 0xC0u | (cp >> 6));
+      emit<WRITE>(out, &k, 0x80u | (cp & 0x3Fu));
+    } else if (cp < 0x10000u) {
+      emit<WRITE>(out, &k, 0xE0u | (cp >> 12));
+      emit<WRITE>(out, &k, 0x80u | ((cp >> 6) & 0x3Fu));
+      emit<WRITE>(out, &k, 0x80u | (cp & 0x3Fu));
+    } else {
+      emit<WRITE>(out, &k, 0xF0u | (cp >> 18));
+      emit<WRITE>(out, &k, 0x80u | ((cp >> 12) & 0x3Fu));
+      emit<WRITE>(out, &k, 0x80u | ((cp >> 6) & 0x3Fu));
+      emit<WRITE>(out, &k, 0x80u | (cp & 0x3Fu));
+    }
+  }
+  *n = k;
+  return err;
+}
+
+// ---- Literals ---------------------------------------------------------------
+JSIDX_DEV bool literal_ok(const TapeArgs& a, uint64_t p, uint32_t first) {
+  // true, false, null by their bytes (little-endian words)
+  const uint32_t L = first == 'f' ? 5u : 4u;
+  if (p + L > a.len) return false;
+  uint64_t v = 0;
+  for (uint32_t k = 0; k < L; k++) v |= (uint64_t)prim::load1(a.buf + p + k) << (8 * k);
+  const uint64_t want = first == 't' ? 0x65757274ull : first == 'n' ? 0x6C6C756Eull : 0x65736C6166ull;
+  return v == want && ends_atom(a, p + L);
+}
+
+// ---- Numbers (Sec. 3.2.1) ---------------------------------------------------
+// The number grammar: an optional minus, 0 or a nonzero digit and digits, an
+// optional fraction ('.' and digits), an optional exponent (e or E, a sign,
+// digits); it must end the atom.  The decimal value is w * 10^q, with w the
+// first 19 significant digits; trunc says a nonzero digit was dropped (the
+// value then lies strictly between w * 10^q and (w + 1) * 10^q).
+struct NumText {
+  bool ok, neg, is_int, trunc;
+  uint32_t int_digits;  // digits of the integer part
+  uint64_t w;
+  int64_t q;
+};
+
+JSIDX_DEV bool is_digit(uint32_t c) { return c - '0' <= 9u; }
+
+JSIDX_DEV NumText scan_number(const TapeArgs& a, uint64_t p) {
+  NumText t{false, false, true, false, 0, 0, 0};
+  uint32_t nd = 0;  // significant digits in w
+  int64_t q = 0;
+  uint32_t c = byte_at(a, p);
+  if (c == '-') {
+    t.neg = true;
+    c = byte_at(a, ++p);
+  }
+  if (!is_digit(c)) return t;
+  if (c == '0') {
+    t.int_digits = 1;
+    c = byte_at(a, ++p);
+  } else {
+    while (p < a.len && is_digit(c)) {
+      t.int_digits++;
+      if (nd < 19) {
+        t.w = t.w * 10 + (c - '0');
+        nd++;
+      } else {
+        q++;  // a dropped digit of the integer part scales the rest
+        t.trunc = t.trunc || c != '0';
+      }
+      c = byte_at(a, ++p);
+    }
+  }
+  if (p < a.len && c == '.') {
+    t.is_int = false;
+    c = byte_at(a, ++p);
+    if (!(p < a.len && is_digit(c))) return t;
+    while (p < a.len && is_digit(c)) {
+      if (nd == 0 && c == '0') {
+        q--;  // a leading zero of the fraction
+      } else if (nd < 19) {
+        t.w = t.w * 10 + (c - '0');
+        nd++;
+        q--;
+      } else {
+        t.trunc = t.trunc || c != '0';
+      }
+      c = byte_at(a, ++p);
+    }
+  }
+  if (p < a.len && (c == 'e' || c == 'E')) {
+    t.is_int = false;
+    c = byte_at(a, ++p);
+    bool eneg = false;
+    if (p < a.len && (c == '+' || c == '-')) {
+      eneg = c == '-';
+      c = byte_at(a, ++p);
+    }
+    if (!(p < a.len && is_digit(c))) return t;
+    int64_t e = 0;
+    while (p < a.len && is_digit(c)) {
+      if (e < 100000000) e = e * 10 + (c - '0');
+      c = byte_at(a, ++p);
+    }
+    q += eneg ? -e : e;
+  }
+  t.q = q;
+  t.ok = ends_atom(a, p);
+  return t;
+}
+
+// 64 x 64 -> 128-bit product.
+JSIDX_DEV void mul_64(uint64_t x, uint64_t y, uint64_t* hi, uint64_t* lo) {
+  const uint64_t x0 = (uint32_t)x, x1 = x >> 32, y0 = (uint32_t)y, y1 = y >> 32;
+  const uint64_t p00 = x0 * y0, p01 = x0 * y1, p10 = x1 * y0, p11 = x1 * y1;
+  const uint64_t mid = (p00 >> 32) + (uint32_t)p01 + (uint32_t)p10;
+  *lo = (mid << 32) | (uint32_t)p00;
+  *hi = p11 + (p01 >> 32) + (p10 >> 32) + (mid >> 32);
+}
+
+constexpr uint64_t kInfBits = 0x7FF0000000000000ull;
+enum : int { kConvOk = 0, kConvInf = 1, kConvUndecided = 2 };
+
+// The binary64 nearest to w * 10^q (w > 0), ties to even, when a 128-bit
+// approximation decides it.  w is normalized to 64 bits and multiplied by
+// the table's 128-bit T with 5^q ~ T * 2^k; of the 192-bit product the top
+// 128 bits P are kept, and w * 10^q = P * 2^(64 + k + q - lz) up to an error
+// below 2 units of P's last bit (the dropped low word, and T's own rounding,
+// downward for q >= 0 and upward for q < 0).  The rounding position is the
+// 53rd bit below P's top bit, or the bit of 2^-1074 for subnormal results.
+// The result is undecided when the bits below that position are within 3
+// units of exactly half.
+JSIDX_DEV int fast_double(uint64_t w, int64_t q, uint64_t* bits) {
+  if (q > kPow5Max) return kConvInf;       // at least 10^309
+  if (q < kPow5Min) { *bits = 0; return kConvOk; }  // below 10^-323 / 2
+  const Pow5 T = kPow5[q - kPow5Min];
+  const int lz = __builtin_clzll(w);
+  const uint64_t wn = w << lz;
+  uint64_t a1, a0, b1, b0;
+  mul_64(wn, T.lo, &a1, &a0);
+  mul_64(wn, T.hi, &b1, &b0);
+  const uint64_t plo = b0 + a1;
+  const uint64_t phi = b1 + (plo < b0 ? 1u : 0u);
+  const int msb = (phi >> 63) ? 127 : 126;
+  const int64_t base = 64 + (int64_t)T.k + q - lz;  // value = P * 2^base
+  const int64_t e2 = msb + base;                     // exponent of the top bit
+  if (e2 >= 1024) return kConvInf;
+  const int64_t rp = e2 >= -1022 ? msb - 52 : -1074 - base;  // bit of the result's last place
+  if (rp >= 130) { *bits = 0; return kConvOk; }  // below a quarter of 2^-1074
+  if (rp >= 128) return kConvUndecided;
+  // rp in [74, 127]: the result bits are in phi; R = P mod 2^rp
+  const int sh = (int)rp - 64;
+  uint64_t m = phi >> sh;
+  const uint64_t rhi = phi & ((1ull << sh) - 1u), rlo = plo;
+  const uint64_t hhi = 1ull << (sh - 1);  // half = 2^(rp - 1), low word 0
+  if ((rhi == hhi && rlo <= 3u) || (rhi + 1u == hhi && rlo >= ~0ull - 2u)) return kConvUndecided;
+  const bool up = rhi > hhi || (rhi == hhi && rlo != 0u);
+  m += up ? 1u : 0u;
+  uint64_t b;
+  if (e2 >= -1022) b = ((uint64_t)(e2 + 1023) << 52) + (m - (1ull << 52));  // m in [2^52, 2^53]
+  else b = m;                                                               // subnormal, m <= 2^52
+  if (b >= kInfBits) return kConvInf;
+  *bits = b;
+  return kConvOk;
+}
+
+// ---- The exact conversion (rare: undecided by fast_double) -----------------
+struct Big {
+  uint32_t d[kBigLimbs];  // little-endian limbs
+  int n;                  // limbs in use (no leading zero limb)
+};
+
+JSIDX_DEV void big_set(Big& x, uint32_t v) {
+  x.n = v ? 1 : 0;
+  x.d[0] = v;
+}
+JSIDX_DEV void big_mul_add(Big& x, uint32_t m, uint32_t add) {
+  uint64_t carry = add;
+  for (int i = 0; i < x.n; i++) {
+    const uint64_t t = (uint64_t)x.d[i] * m + carry;
+    x.d[i] = (uint32_t)t;
+    carry = t >> 32;
+  }
+  if (carry && x.n < kBigLimbs) x.d[x.n++] = (uint32_t)carry;
+}
+JSIDX_DEV void big_mul_pow5(Big& x, int64_t e) {
+  while (e >= 13) {
+    big_mul_add(x, 1220703125u, 0);  // 5^13
+    e -= 13;
+  }
+  uint32_t m = 1;
+  while (e-- > 0) m *= 5;
+  if (m != 1) big_mul_add(x, m, 0);
+}
+JSIDX_DEV int64_t big_bits(const Big& x) {
+  return x.n ? 32 * (int64_t)(x.n - 1) + (32 - __builtin_clz(x.d[x.n - 1])) : 0;
+}
+JSIDX_DEV void big_shl(Big& x, int64_t s) {
+  if (!x.n || s <= 0) return;
+  const int w = (int)(s / 32), b = (int)(s % 32);
+  int nn = x.n + w + 1;
+  if (nn > kBigLimbs) nn = kBigLimbs;
+  for (int i = nn - 1; i >= 0; i--) {
+    const int j = i - w;
+    const uint32_t hi = (j >= 0 && j < x.n) ? x.d[j] : 0u;
+    const uint32_t lo = (j - 1 >= 0 && j - 1 < x.n) ? x.d[j - 1] : 0u;
+    x.d[i] = b ? (hi << b) | (lo >> (32 - b)) : hi;
+  }
+  x.n = nn;
+  while (x.n && !x.d[x.n - 1]) x.n--;
+}
+JSIDX_DEV int big_cmp(const Big& x, const Big& y) {
+  if (x.n != y.n) return x.n < y.n ? -1 : 1;
+  for (int i = x.n - 1; i >= 0; i--)
+    if (x.d[i] != y.d[i]) return x.d[i] < y.d[i] ? -1 : 1;
+  return 0;
+}
+JSIDX_DEV void big_sub(Big& x, const Big& y) {  // x -= y, x >= y
+  int64_t borrow = 0;
+  for (int i = 0; i < x.n; i++) {
+    const int64_t t = (int64_t)x.d[i] - (i < y.n ? (int64_t)y.d[i] : 0) - borrow;
+    x.d[i] = (uint32_t)t;
+    borrow = t < 0 ? 1 : 0;
+  }
+  while (x.n && !x.d[x.n - 1]) x.n--;
+}
+// The top 64 bits of x (x != 0; its top bit becomes bit 63) and whether any
+// bit below them is set.
+JSIDX_DEV uint64_t big_top64(const Big& x, bool* sticky) {
+  const int64_t L = big_bits(x);
+  uint64_t r = 0;
+  bool s = false;
+  for (int64_t b = L - 1; b >= 0; b--) {
+    const uint32_t bit = (x.d[b / 32] >> (b % 32)) & 1u;
+    if (L - 1 - b < 64) r |= (uint64_t)bit << (63 - (L - 1 - b));
+    else if (bit) { s = true; break; }
+  }
+  *sticky = s;
+  return r;
+}
+
+// Round m * 2^(e2 - 63) (m with its top bit set), plus a nonzero tail if
+// sticky, to binary64; kConvInf if it overflows.
+JSIDX_DEV int round_to_double(uint64_t m, int64_t e2, bool sticky, uint64_t* bits) {
+  if (e2 > 1023) return kConvInf;
+  const int64_t sh = e2 >= -1022 ? 11 : 11 + (-1022 - e2);  // bits of m below the last place
+  uint64_t r;
+  bool rb, rest;
+  if (sh >= 66) {
+    *bits = 0;
+    return kConvOk;
+  }
+  if (sh >= 64) {
+    r = 0;
+    rb = sh == 64 && (m >> 63);
+    rest = (sh == 64 ? (m << 1) != 0 : m != 0) || sticky;
+  } else {
+    r = m >> sh;
+    rb = (m >> (sh - 1)) & 1u;
+    rest = (m & ((1ull << (sh - 1)) - 1u)) != 0 || sticky;
+  }
+  if (rb && (rest || (r & 1u))) r++;
+  const uint64_t b = e2 >= -1022 ? ((uint64_t)(e2 + 1023) << 52) + (r - (1ull << 52)) : r;
+  if (b >= kInfBits) return kConvInf;
+  *bits = b;
+  return kConvOk;
+}
+
+// The exact binary64 of the number text at p (grammar already checked): all
+// significant digits D (the first kMaxDigits, then a final 1 standing for any
+// nonzero rest) with x = D * 10^e.  For e >= 0, D * 5^e is exact and x its
+// multiple by 2^e; for e < 0 the quotient of D * 2^t by 5^-e is taken by
+// binary long division to 66 bits, x = quotient * 2^(-t + e), and the
+// remainder is the sticky tail.
+JSIDX_DEV int exact_double(const TapeArgs& a, uint64_t p, Big& D, Big& V, Big& S, uint64_t* bits) {
+  big_set(D, 0);
+  int64_t e = 0;
+  int nd = 0;
+  bool drop = false;
+  uint32_t chunk = 0, chunk_mul = 1;
+  auto digit = [&](uint32_t dv) {
+    chunk = chunk * 10 + dv;
+    chunk_mul *= 10;
+    nd++;
+    if (chunk_mul == 1000000000u) {
+      big_mul_add(D, chunk_mul, chunk);
+      chunk = 0;
+      chunk_mul = 1;
+    }
+  };
+  uint32_t c = byte_at(a, p);
+  if (c == '-') c = byte_at(a, ++p);
+  while (p < a.len && is_digit(c)) {
+    if (nd == 0 && c == '0') {
+      // the single leading zero of the integer part
+    } else if (nd < kMaxDigits) {
+      digit(c - '0');
+    } else {
+      e++;
+      drop = drop || c != '0';
+    }
+    c = byte_at(a, ++p);
+  }
+  if (p < a.len && c == '.') {
+    c = byte_at(a, ++p);
+    while (p < a.len && is_digit(c)) {
+      if (nd == 0 && c == '0') {
+        e--;
+      } else if (nd < kMaxDigits) {
+        digit(c - '0');
+        e--;
+      } else {
+        drop = drop || c != '0';
+      }
+      c = byte_at(a, ++p);
+    }
+  }
+  if (chunk_mul > 1) big_mul_add(D, chunk_mul, chunk);
+  if (drop) {  // strictly between D * 10^e and (D + 1) * 10^e
+    big_mul_add(D, 10, 1);
+    e--;
+  }
+  if (p < a.len && (c == 'e' || c == 'E')) {
+    c = byte_at(a, ++p);
+    bool eneg = false;
+    if (c == '+' || c == '-') {
+      eneg = c == '-';
+      c = byte_at(a, ++p);
+    }
+    int64_t x = 0;
+    while (p < a.len && is_digit(c)) {
+      if (x < 100000000) x = x * 10 + (c - '0');
+      c = byte_at(a, ++p);
+    }
+    e += eneg ? -x : x;
+  }
+  if (D.n == 0) { *bits = 0; return kConvOk; }
+  const int64_t dbits = big_bits(D);
+  if (e >= 0) {
+    if (dbits + 3 * e > 2000) return kConvInf;  // 10^e > 2^(3e): far beyond the range
+    big_mul_pow5(D, e);
+    bool sticky;
+    const uint64_t m = big_top64(D, &sticky);
+    return round_to_double(m, big_bits(D) - 1 + e, sticky, bits);
+  }
+  const int64_t c5 = -e;
+  if (dbits - 2 * c5 < -1200) { *bits = 0; return kConvOk; }  // 10^e < 2^(-3.3 c5): far below 2^-1075
+  big_set(V, 1);
+  big_mul_pow5(V, c5);
+  // shift so that the quotient has 66 bits: bits(N) - bits(V') == 65
+  const int64_t t = big_bits(V) - dbits + 65;
+  if (t >= 0) big_shl(D, t);
+  else big_shl(V, -t);
+  uint64_t qhi = 0, qlo = 0;  // the quotient, below 2^66
+  for (int j = 66; j >= 0; j--) {
+    for (int i = 0; i < V.n; i++) S.d[i] = V.d[i];
+    S.n = V.n;
+    big_shl(S, j);
+    if (big_cmp(D, S) >= 0) {
+      big_sub(D, S);
+      if (j >= 64) qhi |= 1ull << (j - 64);
+      else qlo |= 1ull << j;
+    }
+  }
+  const bool rem = D.n != 0;
+  // normalize the quotient to 64 bits
+  const int qb = qhi ? 64 + (64 - __builtin_clzll(qhi)) : 64 - __builtin_clzll(qlo);
+  const int drop_bits = qb - 64;  // 0..3 (the quotient has at least 64 bits)
+  const uint64_t m = drop_bits > 0 ? (qhi << (64 - drop_bits)) | (qlo >> drop_bits) : qlo;
+  const bool sticky = rem || (drop_bits > 0 && (qlo & ((1ull << drop_bits) - 1u)) != 0);
+  return round_to_double(m, (int64_t)qb - 1 - t + e, sticky, bits);
+}
+
+// ---- Kernels ------------------------------------------------------------------
+
+// Buffer bytes of entry i: 4 + the normalized length of a string, else 0.
+JSIDX_DEV uint32_t string_bytes(const TapeArgs& a, uint32_t i, uint32_t b) {
+  if (b != '"') return 0;
+  uint32_t k = 0;
+  (void)normalize_string<false>(a, prim::load4(reinterpret_cast<const uint8_t*>(a.idx + i)), nullptr, &k);
+  return 4 + k;
+}
+
+struct TapeLds {
+  uint64_t w[kTapeThreads];
+  uint64_t s[kTapeThreads];
+};
+
+// Sum over the workgroup (every thread gets it); ex receives the sum of the
+// threads before this one.
+JSIDX_DEV void group_scan2(TapeLds& g, uint32_t tid, uint64_t w, uint64_t s, uint64_t* wex, uint64_t* sex,
+                           uint64_t* wall, uint64_t* sall) {
+  g.w[tid] = w;
+  g.s[tid] = s;
+  prim::sync();
+  for (uint32_t d = 1; d < (uint32_t)kTapeThreads; d <<= 1) {
+    const uint64_t tw = tid >= d ? g.w[tid - d] : 0, ts = tid >= d ? g.s[tid - d] : 0;
+    prim::sync();
+    g.w[tid] += tw;
+    g.s[tid] += ts;
+    prim::sync();
+  }
+  *wex = g.w[tid] - w;
+  *sex = g.s[tid] - s;
+  *wall = g.w[kTapeThreads - 1];
+  *sall = g.s[kTapeThreads - 1];
+  prim::sync();
+}
+
+// 1. Words and buffer bytes per entry (thread t of chunk c takes entries
+//    c * 4096 + 16t .. +15), the buffer bytes kept per entry, sums per chunk.
+JSIDX_DEVFN void tape_count(const TapeArgs& a) {
+  TapeLds& g = prim::lds_object<TapeLds>();
+  const uint32_t tid = tape_tid(), c = prim::block();
+  const uint64_t e0 = (uint64_t)c * kTapeChunk + (uint64_t)tid * kTapePer;
+  uint64_t w = 0, s = 0;
+  for (int k = 0; k < kTapePer; k++) {
+    const uint64_t i = e0 + (uint64_t)k;
+    if (i >= a.n) break;
+    const uint32_t b = entry_byte(a, (uint32_t)i);
+    const uint32_t sb = string_bytes(a, (uint32_t)i, b);
+    prim::st_out(a.sbytes + i, sb);
+    w += words_of(b);
+    s += sb;
+  }
+  uint64_t wex, sex, wall, sall;
+  group_scan2(g, tid, w, s, &wex, &sex, &wall, &sall);
+  if (tid == 0) {
+    prim::st_pair(reinterpret_cast<uint2*>(a.chunk_sum + 2 * (uint64_t)c), (uint32_t)wall, (uint32_t)(wall >> 32));
+    prim::st_pair(reinterpret_cast<uint2*>(a.chunk_sum + 2 * (uint64_t)c + 1), (uint32_t)sall,
+                  (uint32_t)(sall >> 32));
+  }
+}
+
+JSIDX_DEV uint64_t ld64(const uint64_t* p) {
+  const uint2 v = prim::ld_pair(reinterpret_cast<const uint2*>(p));
+  return ((uint64_t)v.y << 32) | v.x;
+}
+JSIDX_DEV void st64(uint64_t* p, uint64_t v) {
+  prim::st_pair(reinterpret_cast<uint2*>(p), (uint32_t)v, (uint32_t)(v >> 32));
+}
+
+// 2. Chunk bases (one workgroup), the root words, the sizes; flags cleared.
+JSIDX_DEVFN void tape_scan(const TapeArgs& a) {
+  TapeLds& g = prim::lds_object<TapeLds>();
+  const uint32_t tid = tape_tid();
+  const uint32_t per = (a.nchunks + kTapeThreads - 1) / kTapeThreads;
+  const uint64_t lo = (uint64_t)tid * per;
+  const uint64_t hi = lo + per < a.nchunks ? lo + per : a.nchunks;
+  uint64_t w = 0, s = 0;
+  for (uint64_t c = lo; c < hi; c++) {
+    w += ld64(a.chunk_sum + 2 * c);
+    s += ld64(a.chunk_sum + 2 * c + 1);
+  }
+  uint64_t wex, sex, wall, sall;
+  group_scan2(g, tid, w, s, &wex, &sex, &wall, &sall);
+  for (uint64_t c = lo; c < hi; c++) {
+    const uint64_t cw = ld64(a.chunk_sum + 2 * c), cs = ld64(a.chunk_sum + 2 * c + 1);
+    st64(a.chunk_sum + 2 * c, wex);
+    st64(a.chunk_sum + 2 * c + 1, sex);
+    wex += cw;
+    sex += cs;
+  }
+  if (tid == 0) {
+    const uint64_t last = wall + 1;  // the root words enclose the words of the entries
+    st64(a.tape, ((uint64_t)'r' << 56) | last);
+    st64(a.tape + last, (uint64_t)'r' << 56);
+    st64(a.tape_n, last + 1);
+    st64(a.str_n, sall);
+    prim::st_out(a.err, 0u);
+    prim::st_out(a.qcount, 0u);
+  }
+}
+
+// 3. Each entry's tape index (after the root word) and buffer offset.
+JSIDX_DEVFN void tape_offsets(const TapeArgs& a) {
+  TapeLds& g = prim::lds_object<TapeLds>();
+  const uint32_t tid = tape_tid(), c = prim::block();
+  const uint64_t e0 = (uint64_t)c * kTapeChunk + (uint64_t)tid * kTapePer;
+  uint64_t w = 0, s = 0;
+  for (int k = 0; k < kTapePer; k++) {
+    const uint64_t i = e0 + (uint64_t)k;
+    if (i >= a.n) break;
+    w += words_of(entry_byte(a, (uint32_t)i));
+    s += prim::load4(reinterpret_cast<const uint8_t*>(a.sbytes + i));
+  }
+  uint64_t wex, sex, wall, sall;
+  group_scan2(g, tid, w, s, &wex, &sex, &wall, &sall);
+  uint64_t tw = 1 + ld64(a.chunk_sum + 2 * (uint64_t)c) + wex;
+  uint64_t ts = ld64(a.chunk_sum + 2 * (uint64_t)c + 1) + sex;
+  for (int k = 0; k < kTapePer; k++) {
+    const uint64_t i = e0 + (uint64_t)k;
+    if (i >= a.n) break;
+    prim::st_out(a.toff + i, (uint32_t)tw);
+    st64(a.soff + i, ts);
+    tw += words_of(entry_byte(a, (uint32_t)i));
+    ts += prim::load4(reinterpret_cast<const uint8_t*>(a.sbytes + i));
+  }
+}
+
+// 4. Every entry's words (one thread per entry, consecutive threads on
+//    consecutive entries).
+JSIDX_DEV uint32_t write_entry(const TapeArgs& a, uint32_t i) {
+  const uint64_t pos = prim::load4(reinterpret_cast<const uint8_t*>(a.idx + i));
+  const uint32_t b = byte_at(a, pos);
+  if (b == ':' || b == ',') return 0;
+  const uint64_t t = prim::load4(reinterpret_cast<const uint8_t*>(a.toff + i));
+  uint64_t* out = a.tape + t;
+  if (b == '{' || b == '[' || b == '}' || b == ']') {
+    const uint32_t k = prim::load4(reinterpret_cast<const uint8_t*>(a.match + i));
+    uint64_t link = 0;
+    if (k != kTapeUnlinked && k < a.n) {
+      const uint64_t tk = prim::load4(reinterpret_cast<const uint8_t*>(a.toff + k));
+      link = (b == '{' || b == '[') ? tk + 1 : tk;
+    }
+    st64(out, ((uint64_t)b << 56) | link);
+    return 0;
+  }
+  if (b == '"') {
+    const uint64_t so = ld64(a.soff + i);
+    uint32_t k = 0;
+    const uint32_t err = normalize_string<true>(a, pos, a.str + so + 4, &k);
+    for (int j = 0; j < 4; j++) prim::st_byte(a.str + so + j, (k >> (8 * j)) & 0xFFu);
+    st64(out, ((uint64_t)'"' << 56) | so);
+    return err;
+  }
+  if (is_lit_start(b)) {
+    st64(out, (uint64_t)b << 56);
+    return literal_ok(a, pos, b) ? 0u : kErrLiteral;
+  }
+  const NumText nt = scan_number(a, pos);
+  if (!nt.ok) {
+    st64(out, (uint64_t)'d' << 56);
+    st64(out + 1, 0);
+    return kErrNumber;
+  }
+  if (nt.is_int) {
+    // at most 19 digits fit; the magnitude limit is 2^63 - 1, or 2^63 if negative
+    const uint64_t lim = nt.neg ? (1ull << 63) : (1ull << 63) - 1u;
+    st64(out, (uint64_t)'l' << 56);
+    if (nt.int_digits > 19 || nt.w > lim) {
+      st64(out + 1, 0);
+      return kErrNumber;
+    }
+    st64(out + 1, nt.neg ? 0ull - nt.w : nt.w);
+    return 0;
+  }
+  st64(out, (uint64_t)'d' << 56);
+  const uint64_t sign = nt.neg ? 1ull << 63 : 0ull;
+  if (nt.w == 0) {
+    st64(out + 1, sign);
+    return 0;
+  }
+  uint64_t bits = 0;
+  int r = fast_double(nt.w, nt.q, &bits);
+  if (r != kConvUndecided && nt.trunc) {
+    // the value lies strictly between w and w + 1 (times 10^q): decided only
+    // if both ends give the same result
+    uint64_t bits2 = 0;
+    const int r2 = fast_double(nt.w + 1, nt.q, &bits2);
+    if (r2 != r || (r == kConvOk && bits2 != bits)) r = kConvUndecided;
+  }
+  if (r == kConvInf) {
+    st64(out + 1, 0);
+    return kErrNumber;
+  }
+  if (r == kConvUndecided) {
+    const uint32_t slot = prim::add_agent32(a.qcount, 1u);
+    prim::st_out(a.queue + slot, i);
+    return 0;
+  }
+  st64(out + 1, bits | sign);
+  return 0;
+}
+
+JSIDX_DEVFN void tape_write(const TapeArgs& a) {
+  const uint32_t tid = tape_tid(), c = prim::block();
+  uint32_t err = 0;
+  for (int k = 0; k < kTapePer; k++) {
+    const uint64_t i = (uint64_t)c * kTapeChunk + (uint64_t)k * kTapeThreads + tid;
+    if (i >= a.n) break;
+    err |= write_entry(a, (uint32_t)i);
+  }
+  // one atomic per wave for each flag that is set
+  const uint32_t lane = prim::lane();
+  for (uint32_t f = kErrNumber; f <= kErrLiteral; f <<= 1)
+    if (prim::ballot((err & f) != 0u) != 0ull && lane == 0) prim::or_agent32(a.err, f);
+}
+
+// 5. The queued numbers, one thread each, by exact arithmetic.
+struct ExactScratch {
+  Big D, V, S;
+};
+
+JSIDX_DEV void exact_entry(const TapeArgs& a, uint32_t i, ExactScratch& x) {
+  const uint64_t pos = prim::load4(reinterpret_cast<const uint8_t*>(a.idx + i));
+  const uint64_t t = prim::load4(reinterpret_cast<const uint8_t*>(a.toff + i));
+  uint64_t bits = 0;
+  const int r = exact_double(a, pos, x.D, x.V, x.S, &bits);
+  if (r == kConvInf) {
+    st64(a.tape + t + 1, 0);
+    prim::or_agent32(a.err, kErrNumber);
+    return;
+  }
+  const uint64_t sign = byte_at(a, pos) == '-' ? 1ull << 63 : 0ull;
+  st64(a.tape + t + 1, bits | sign);
+}
+
+JSIDX_DEVFN void tape_exact(const TapeArgs& a) {
+  ExactScratch x;
+  const uint32_t qn = prim::ld_agent32(a.qcount);
+  const uint32_t stride = prim::grid() * (uint32_t)kExactThreads;
+  for (uint32_t q = prim::block() * (uint32_t)kExactThreads + prim::lane(); q < qn; q += stride)
+    exact_entry(a, prim::load4(reinterpret_cast<const uint8_t*>(a.queue + q)), x);
+}
+
+}  // namespace jsidx

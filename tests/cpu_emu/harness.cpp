@@ -9,6 +9,7 @@
 
 #include "jsidx_kernel.h"
 #include "jsidx_scopes.h"
+#include "jsidx_tape.h"
 
 namespace jsidx {
 namespace prim {
@@ -144,6 +145,106 @@ long emu_scopes_run(const uint8_t* buf, uint64_t len, const uint32_t* idx, uint3
 }
 
 uint64_t emu_scopes_ws_bytes(uint64_t n) { return scope_layout(n).total; }
+
+// The tape kernels (jsidx_tape.h) over one document's index and links.
+// Returns the number of out-of-range accesses.
+long emu_tape_run(const uint8_t* buf, uint64_t len, const uint32_t* idx, uint32_t n, const uint32_t* match,
+                  uint64_t* tape, uint64_t tape_cap, uint8_t* str, uint64_t str_cap, uint64_t* tape_n, uint64_t* str_n,
+                  uint32_t* err, void* ws, int exact_groups, uint32_t* exact_count) {
+  const TapeLayout L = tape_layout(n);
+  prim::EmuEnv env;
+  if (len) env.reads[env.nreads++] = {buf, buf + len};
+  if (n) env.reads[env.nreads++] = {idx, idx + n};
+  if (n) env.reads[env.nreads++] = {match, match + n};
+  env.reads[env.nreads++] = {ws, (const uint8_t*)ws + L.total};
+  env.writes[env.nwrites++] = {tape, tape + tape_cap};
+  env.writes[env.nwrites++] = {str, str + str_cap};
+  env.writes[env.nwrites++] = {tape_n, tape_n + 1};
+  env.writes[env.nwrites++] = {str_n, str_n + 1};
+  env.writes[env.nwrites++] = {err, err + 1};
+  env.writes[env.nwrites++] = {ws, (const uint8_t*)ws + L.total};
+  uint8_t* m = static_cast<uint8_t*>(ws);
+  TapeArgs a;
+  a.buf = buf;
+  a.len = len;
+  a.idx = idx;
+  a.n = n;
+  a.nchunks = (uint32_t)((n + (uint64_t)kTapeChunk - 1) / kTapeChunk);
+  a.match = match;
+  a.tape = tape;
+  a.str = str;
+  a.tape_n = tape_n;
+  a.str_n = str_n;
+  a.err = err;
+  a.chunk_sum = reinterpret_cast<uint64_t*>(m + L.chunk_sum);
+  a.sbytes = reinterpret_cast<uint32_t*>(m + L.sbytes);
+  a.toff = reinterpret_cast<uint32_t*>(m + L.toff);
+  a.soff = reinterpret_cast<uint64_t*>(m + L.soff);
+  a.qcount = reinterpret_cast<uint32_t*>(m + L.qcount);
+  a.queue = reinterpret_cast<uint32_t*>(m + L.queue);
+  auto phase = [&](int ngroups, int nthreads, void (*body)(const TapeArgs&)) {
+    std::vector<prim::GroupCtx*> groups;
+    for (int b = 0; b < ngroups; b++) groups.push_back(new prim::GroupCtx((uint32_t)nthreads));
+    std::vector<std::thread> th;
+    for (int b = 0; b < ngroups; b++) {
+      for (uint32_t t = 0; t < (uint32_t)nthreads; t++) {
+        th.emplace_back([&, b, t] {
+          prim::tctx.tid = t;
+          prim::tctx.block = (uint32_t)b;
+          prim::tctx.grid = (uint32_t)ngroups;
+          prim::tctx.g = groups[(size_t)b];
+          prim::tctx.env = &env;
+          body(a);
+        });
+      }
+    }
+    for (auto& x : th) x.join();
+    for (auto* g : groups) delete g;
+  };
+  if (a.nchunks) phase((int)a.nchunks, kTapeThreads, tape_count);
+  phase(1, kTapeThreads, tape_scan);
+  if (a.nchunks) {
+    phase((int)a.nchunks, kTapeThreads, tape_offsets);
+    phase((int)a.nchunks, kTapeThreads, tape_write);
+    phase(exact_groups, kExactThreads, tape_exact);
+  }
+  *exact_count = n ? *a.qcount : 0u;
+  return env.violations.load();
+}
+
+uint64_t emu_tape_ws_bytes(uint64_t n) { return tape_layout(n).total; }
+
+// One number text through the fast conversion (exact == 0; the grammar scan
+// first) or the exact one (exact == 1).  Returns kConvOk / kConvInf /
+// kConvUndecided (-1: the grammar rejects it), the magnitude's bits in *bits.
+int emu_number(const uint8_t* text, uint64_t len, int exact, uint64_t* bits) {
+  prim::EmuEnv env;
+  env.reads[env.nreads++] = {text, text + len};
+  prim::GroupCtx g(1);
+  prim::tctx.tid = 0;
+  prim::tctx.block = 0;
+  prim::tctx.grid = 1;
+  prim::tctx.g = &g;
+  prim::tctx.env = &env;
+  TapeArgs a{};
+  a.buf = text;
+  a.len = len;
+  const NumText t = scan_number(a, 0);
+  if (!t.ok) return -1;
+  *bits = 0;
+  if (exact) {
+    static thread_local ExactScratch x;
+    return exact_double(a, 0, x.D, x.V, x.S, bits);
+  }
+  if (t.w == 0) return kConvOk;
+  int r = fast_double(t.w, t.q, bits);
+  if (r != kConvUndecided && t.trunc) {
+    uint64_t b2 = 0;
+    const int r2 = fast_double(t.w + 1, t.q, &b2);
+    if (r2 != r || (r == kConvOk && b2 != *bits)) r = kConvUndecided;
+  }
+  return r;
+}
 
 uint64_t emu_ws_bytes(uint64_t cap_tiles) { return workspace_bytes(cap_tiles); }
 uint32_t emu_tile_bytes() { return (uint32_t)kTileBytes; }

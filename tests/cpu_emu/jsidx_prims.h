@@ -22,6 +22,7 @@
 
 #define JSIDX_DEV inline
 #define JSIDX_DEVFN inline
+#define JSIDX_CONSTANT static const
 
 struct uint4 {
   uint32_t x, y, z, w;

@@ -61,6 +61,13 @@ def load(block_tiles: int | None = None):
     lib.emu_run.restype = ctypes.c_long
     lib.emu_scopes_run.argtypes = [vp, ctypes.c_uint64, vp, ctypes.c_uint32, vp, vp, vp, ctypes.c_int]
     lib.emu_scopes_run.restype = ctypes.c_long
+    lib.emu_tape_run.argtypes = [vp, ctypes.c_uint64, vp, ctypes.c_uint32, vp, vp, ctypes.c_uint64, vp,
+                                 ctypes.c_uint64, vp, vp, vp, vp, ctypes.c_int, vp]
+    lib.emu_tape_run.restype = ctypes.c_long
+    lib.emu_number.argtypes = [ctypes.c_char_p, ctypes.c_uint64, ctypes.c_int, vp]
+    lib.emu_number.restype = ctypes.c_int
+    lib.emu_tape_ws_bytes.argtypes = [ctypes.c_uint64]
+    lib.emu_tape_ws_bytes.restype = ctypes.c_uint64
     lib.emu_scopes_ws_bytes.argtypes = [ctypes.c_uint64]
     lib.emu_scopes_ws_bytes.restype = ctypes.c_uint64
     lib.emu_ws_bytes.argtypes = [ctypes.c_uint64]
@@ -159,3 +166,37 @@ def scopes(data: bytes, idx: np.ndarray, far_groups: int = 2, garbage_ws: bool =
     v = lib.emu_scopes_run(buf.ctypes.data, len(data), ix.ctypes.data, n, match.ctypes.data, err.ctypes.data,
                            ws.ctypes.data, far_groups)
     return match[:n], int(err[0]), int(v)
+
+
+def tape(data: bytes, idx: np.ndarray, match: np.ndarray, exact_groups: int = 2):
+    """The tape through the emulated tape kernels.  Returns (tape words,
+    string buffer, flags, violations, numbers taken by the exact conversion);
+    the outputs and the workspace start full of garbage."""
+    lib = load()
+    n = int(idx.size)
+    buf = np.frombuffer(data, dtype=np.uint8) if data else np.zeros(1, dtype=np.uint8)
+    ix = np.ascontiguousarray(idx, dtype=np.uint32) if n else np.zeros(1, dtype=np.uint32)
+    mt = np.ascontiguousarray(match, dtype=np.uint32) if n else np.zeros(1, dtype=np.uint32)
+    tcap = 2 * n + 2
+    scap = len(data) + 2 * n + 4
+    words = np.full(tcap, 0xA5A5A5A5A5A5A5A5, dtype=np.uint64)
+    sbuf = np.full(scap, 0xA5, dtype=np.uint8)
+    tn = np.full(1, 0xFFFF, dtype=np.uint64)
+    sn = np.full(1, 0xFFFF, dtype=np.uint64)
+    err = np.full(1, 0xABABABAB, dtype=np.uint32)
+    ws = np.full(int(lib.emu_tape_ws_bytes(n)) // 4 + 64, 0x5A5A5A5A, dtype=np.uint32)
+    nx = np.zeros(1, dtype=np.uint32)
+    v = lib.emu_tape_run(buf.ctypes.data, len(data), ix.ctypes.data, n, mt.ctypes.data, words.ctypes.data, tcap,
+                         sbuf.ctypes.data, scap, tn.ctypes.data, sn.ctypes.data, err.ctypes.data, ws.ctypes.data,
+                         exact_groups, nx.ctypes.data)
+    return words[:int(tn[0])], sbuf[:int(sn[0])].tobytes(), int(err[0]), int(v), int(nx[0])
+
+
+def number(text: str, exact: bool):
+    """(status, magnitude bits) of the device number conversion on one text:
+    status 0 ok, 1 infinite, 2 undecided by the fast path, -1 rejected."""
+    lib = load()
+    raw = text.encode()
+    bits = np.zeros(1, dtype=np.uint64)
+    r = lib.emu_number(raw, len(raw), 1 if exact else 0, bits.ctypes.data)
+    return int(r), int(bits[0])

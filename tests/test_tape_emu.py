@@ -1,0 +1,150 @@
+"""The tape kernels (jsidx_tape.h), run on the CPU through the emulated
+primitives, against the oracle's tape: words, string buffer and flags."""
+import json
+import os
+import random
+import struct
+
+import numpy as np
+
+import emu
+import oracle
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _check(data: bytes, exact_groups: int = 2) -> int:
+    """Returns how many numbers took the exact conversion."""
+    idx, _ = oracle.index(data)
+    match, serr = oracle.scopes(data, idx)
+    words, sbuf, flags, viol, nexact = emu.tape(data, idx, match, exact_groups)
+    ow, osb, of = oracle.tape(data, idx)
+    assert viol == 0
+    assert flags == of, (hex(flags), hex(of), data[:80])
+    if of == 0 and serr == 0 and oracle.structure(data, idx) == 0:
+        assert words.size == ow.size, (words.size, ow.size)
+        bad = np.nonzero(words != ow)[0]
+        assert bad.size == 0, (int(bad[0]), hex(int(words[bad[0]])), hex(int(ow[bad[0]])), data[:80])
+        assert sbuf == osb
+    return nexact
+
+
+def test_fig1_document():
+    _check(open(os.path.join(GOLDEN, "paper_fig1_document.json"), "rb").read())
+
+
+def test_small_values_and_errors():
+    for t in ("1", "-0", "0.5", '"x"', "true", "null", "[]", "{}", '{"a":[1,2,{"b":null}],"c":"\\u00e9\\ud83d\\ude00"}',
+              "[01]", "[1.]", '["\\x"]', "[tru]", "[1e309]", '["a\\u12"]', '["\\ud800"]', "[-]", "[9223372036854775808]",
+              "[-9223372036854775808, 9223372036854775807]", '"unclosed', "[1, 2"):
+        _check(t.encode())
+
+
+def _numbers(rng, count):
+    out = []
+    for _ in range(count):
+        digits = "".join(rng.choice("0123456789") for _ in range(rng.randrange(1, 30))).lstrip("0") or "0"
+        frac = "" if rng.random() < 0.3 else "." + "".join(rng.choice("0123456789")
+                                                          for _ in range(rng.randrange(1, 25)))
+        exp = "" if rng.random() < 0.3 else "e" + rng.choice(["", "+", "-"]) + str(rng.randrange(0, 340))
+        out.append(rng.choice(["", "-"]) + digits + frac + exp)
+    return out
+
+
+def test_numbers_in_bulk():
+    """Numbers of every shape in arrays (several chunks): random digit counts
+    and exponents over the whole double range, doubles printed with 17
+    digits, and inputs whose rounding the fast conversion cannot decide
+    (halfway points, subnormals, very long mantissas)."""
+    rng = random.Random(21)
+    nums = _numbers(rng, 2500)
+    nums += [repr(struct.unpack("<d", struct.pack("<Q", rng.getrandbits(63)))[0]) for _ in range(1500)]
+    nums = [x for x in nums if x not in ("nan", "inf")]
+    hard = ["9007199254740993", "9007199254740993.0", "2.2250738585072011e-308", "2.2250738585072012e-308",
+            "4.9406564584124654e-324", "2.4703282292062327e-324", "2.4703282292062328e-324", "1e-400",
+            "1.7976931348623157e308", "1.7976931348623158e308", "1.7976931348623159e308", "1e23", "0.1",
+            "123456789012345678901234567890e-10", "7.2057594037927933e16", "1" + "0" * 400 + "e-400",
+            "0." + "0" * 400 + "1e400", "9007199254740992.5", "9007199254740993.000000000000000000001",
+            "2.470328229206232720882e-324", "5e-324", "3e-324", "1.00000000000000011102230246251565404236316680908203125",
+            "1.00000000000000011102230246251565404236316680908203124", "1.00000000000000011102230246251565404236316680908203126",
+            "7.9228162514264337593543950335e28", "8.98846567431157953864652595394512366e307"]
+    for k in range(0, 60):  # exact halfway points between consecutive doubles
+        x = struct.unpack("<d", struct.pack("<Q", rng.getrandbits(62) + (1 << 61)))[0]
+        y = np.nextafter(x, np.inf)
+        from decimal import Decimal, getcontext
+        getcontext().prec = 1000
+        hard.append(str((Decimal(x) + Decimal(float(y))) / 2))
+    data = ("[" + ",".join(nums + hard) + "]").encode()
+    assert _check(data, exact_groups=3) >= 30  # most halfway points need the exact path
+    assert _check(("[" + ",".join(hard) + "]").encode()) >= 30
+
+
+def test_random_documents_across_chunks():
+    rng = random.Random(4)
+
+    def val(d):
+        r = rng.random()
+        if d > 5 or r < 0.45:
+            k = rng.randrange(5)
+            if k == 0:
+                return rng.randrange(-(1 << 63), 1 << 63)
+            if k == 1:
+                return rng.choice([True, False, None])
+            if k == 2:
+                return rng.uniform(-1e300, 1e300) * rng.choice([1, 1e-300, 1e-10])
+            return "".join(rng.choice(["a", " ", '"', "\\", "\n", "\x01", "é", "\U0001F600", "/"])
+                           for _ in range(rng.randrange(0, 6)))
+        if r < 0.7:
+            return [val(d + 1) for _ in range(rng.randrange(0, 6))]
+        return {f"k{i}é": val(d + 1) for i in range(rng.randrange(0, 6))}
+
+    items = []
+    while True:
+        items.append(val(0))
+        text = json.dumps(items, ensure_ascii=rng.random() < 0.5)
+        if oracle.index(text.encode())[0].size > 2 * 4096 + 200:
+            break
+    _check(text.encode())
+    _check(text.replace("true", "tru", 1).encode())
+    _check(text.replace('"', '"\\q', 1).encode())
+
+
+def test_number_conversions_against_python_float():
+    """Both device conversions on their own, number by number: the fast one
+    must be exact whenever it decides, the exact one always (CPython's float()
+    is correctly rounded)."""
+    rng = random.Random(77)
+    texts = _numbers(rng, 4000)
+    texts += [repr(struct.unpack("<d", struct.pack("<Q", rng.getrandbits(63)))[0]) for _ in range(2000)]
+    texts = [t for t in texts if t not in ("nan", "inf")]
+    from decimal import Decimal, getcontext
+    getcontext().prec = 1200
+    for _ in range(300):  # halfway points and their neighbours, subnormal ones too
+        x = struct.unpack("<d", struct.pack("<Q", rng.getrandbits(63)))[0]
+        if not np.isfinite(x) or x == 0:
+            continue
+        y = float(np.nextafter(x, np.inf))
+        if not np.isfinite(y):
+            continue
+        mid = (Decimal(x) + Decimal(y)) / 2
+        ulp = Decimal(y) - Decimal(x)
+        texts += [str(mid), str(mid + ulp / 10 ** 30), str(mid - ulp / 10 ** 30)]
+    for b in range(1, 200):  # subnormals
+        texts.append(str(Decimal(struct.unpack("<d", struct.pack("<Q", rng.randrange(1, 1 << 52)))[0])))
+    undecided = 0
+    for t in texts:
+        f = float(t)
+        want = struct.unpack("<Q", struct.pack("<d", abs(f)))[0]
+        r, bits = emu.number(t, exact=True)
+        if np.isinf(f):
+            assert r == 1, t
+        else:
+            assert r == 0 and bits == want, (t, hex(bits), hex(want))
+        r, bits = emu.number(t, exact=False)
+        if r == 2:
+            undecided += 1
+        elif np.isinf(f):
+            assert r == 1, t
+        else:
+            assert r == 0 and bits == want, ("fast", t, hex(bits), hex(want))
+    assert undecided >= 300

@@ -188,7 +188,7 @@ int jsidx_scopes(const uint8_t *buf, uint64_t len, const uint32_t *idx,
  * UTF-8), 't' 'f' 'n' for the literals, and numbers as two words: 'l' and
  * the int64 value, or 'd' and the binary64 value (correctly rounded, ties to
  * even).  ':' and ',' take no word.
- *   buf, len   device pointer to the document (len < 2^32).
+ *   buf, len   device pointer to the document (len < 2^32 - 2^16).
  *   idx, n     device array of the n index entries (jsidx_build's output for
  *              this document), n < 2^31.
  *   match      device array of n links from jsidx_scopes on the same index;
@@ -208,7 +208,7 @@ int jsidx_scopes(const uint8_t *buf, uint64_t len, const uint32_t *idx,
  *              atom starting with t, f or n that is not exactly true, false
  *              or null).  Every atom and string is checked, each on its own.
  * The tape is the paper's only when jsidx_scopes reported no flag and out_err
- * is 0.  A per-stream workspace of about 20 bytes per entry is allocated on
+ * is 0.  A per-stream workspace of about 13 bytes per entry is allocated on
  * first use and grown as needed (synchronising the stream).  Asynchronous on
  * `stream`; returns JSIDX_E_INVAL for NULL pointers or sizes out of range.
  */

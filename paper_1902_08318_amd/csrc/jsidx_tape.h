@@ -4,18 +4,20 @@
 // normalized into a string buffer (a 32-bit length, then UTF-8), literals
 // checked.  Once the index is known no token depends on another (Sec. 3.2), so
 // every entry is handled by its own thread:
-//   1. tape_count: the words of each entry (0 for ':' and ',', 2 for a number,
-//      else 1) and the buffer bytes of each string (decoded, not written),
-//      summed per chunk of 4096 entries;
+//   1. tape_count: each entry's first byte and the buffer bytes of each string
+//      (decoded, not written) go to the workspace; the words (0 for ':' and
+//      ',', 2 for a number, else 1) and bytes are summed per chunk of 4096
+//      entries;
 //   2. tape_scan: one workgroup turns the chunk sums into bases and writes the
 //      root words, the sizes, and clears the flags;
-//   3. tape_offsets: each entry's tape index and buffer offset (a scan inside
-//      the chunk);
+//   3. tape_offsets: each entry's tape index (a scan inside the chunk);
 //   4. tape_write: every entry's words: brackets with the tape index of their
 //      partner (from the scope links), strings decoded into the buffer,
 //      numbers converted, literals checked.  A double whose rounding the fast
 //      conversion cannot decide is queued;
 //   5. tape_exact: the queued numbers by exact big-integer arithmetic.
+// Consecutive threads take consecutive entries (coalesced); the scans inside
+// a chunk run over the chunk staged in LDS.
 // Written on the same primitives as the other kernels, so that the CPU
 // emulation of the tests runs this source too.
 #pragma once
@@ -56,14 +58,14 @@ struct TapeArgs {
   // workspace
   uint64_t* chunk_sum;  // 2 per chunk: words, buffer bytes; then their bases
   uint32_t* sbytes;     // per entry: buffer bytes of a string, else 0
+  uint8_t* kb;          // per entry: its first byte
   uint32_t* toff;       // per entry: tape index of its first word
-  uint64_t* soff;       // per entry: buffer offset of a string
   uint32_t* qcount;     // numbers queued for the exact conversion
   uint32_t* queue;      // their entries
 };
 
 struct TapeLayout {
-  uint64_t chunk_sum, sbytes, toff, soff, qcount, queue, total;
+  uint64_t chunk_sum, sbytes, kb, toff, qcount, queue, total;
 };
 inline uint64_t tape_align256(uint64_t x) { return (x + 255) & ~(uint64_t)255; }
 inline TapeLayout tape_layout(uint64_t n) {
@@ -72,8 +74,8 @@ inline TapeLayout tape_layout(uint64_t n) {
   uint64_t o = 0;
   L.chunk_sum = o; o = tape_align256(o + nc * 16);
   L.sbytes = o; o = tape_align256(o + n * 4);
+  L.kb = o; o = tape_align256(o + n);
   L.toff = o; o = tape_align256(o + n * 4);
-  L.soff = o; o = tape_align256(o + n * 8);
   L.qcount = o; o = tape_align256(o + 4);
   L.queue = o; o = tape_align256(o + n * 4);
   L.total = o;
@@ -91,6 +93,33 @@ JSIDX_DEV uint32_t entry_byte(const TapeArgs& a, uint32_t i) {
 
 JSIDX_DEV bool is_lit_start(uint32_t b) { return b == 't' || b == 'f' || b == 'n'; }
 
+// Bytes of the document read through a 16-byte window of registers (four
+// aligned words loaded together), so that a short atom costs one or two
+// memory round trips instead of one per byte.  Outside the document: 0.
+struct Cursor {
+  const uint8_t* buf;
+  uint64_t len;
+  uint64_t base;
+  uint32_t w0, w1, w2, w3;
+  JSIDX_DEV uint32_t at(uint64_t p) {
+    if (p >= len) return 0u;
+    uint64_t d = p - base;  // huge when p is below the window (or none is loaded)
+    if (p < base || d >= 16) {
+      const uint32_t off = (uint32_t)(reinterpret_cast<uintptr_t>(buf + p) & 3u);
+      if (p < off || p - off + 16 > len) return prim::load1(buf + p);
+      base = p - off;
+      w0 = prim::load4(buf + base);
+      w1 = prim::load4(buf + base + 4);
+      w2 = prim::load4(buf + base + 8);
+      w3 = prim::load4(buf + base + 12);
+      d = off;
+    }
+    const uint32_t v = d < 8 ? (d < 4 ? w0 : w1) : (d < 12 ? w2 : w3);
+    return (v >> (8 * (uint32_t)(d & 3u))) & 0xFFu;
+  }
+};
+JSIDX_DEV Cursor cursor(const uint8_t* buf, uint64_t len) { return Cursor{buf, len, ~0ull, 0u, 0u, 0u, 0u}; }  // no window
+
 // Tape words of an entry by its first byte.
 JSIDX_DEV uint32_t words_of(uint32_t b) {
   if (b == ':' || b == ',') return 0;
@@ -99,9 +128,9 @@ JSIDX_DEV uint32_t words_of(uint32_t b) {
 }
 
 // An atom ends at white space, a structural character or the document's end.
-JSIDX_DEV bool ends_atom(const TapeArgs& a, uint64_t p) {
-  if (p >= a.len) return true;
-  const uint32_t c = prim::load1(a.buf + p);
+JSIDX_DEV bool ends_atom(Cursor& cur, uint64_t p) {
+  if (p >= cur.len) return true;
+  const uint32_t c = cur.at(p);
   return c == ' ' || c == '\t' || c == '\n' || c == '\r' || c == ',' || c == ':' || c == '[' || c == ']' ||
          c == '{' || c == '}';
 }
@@ -137,12 +166,50 @@ JSIDX_DEV void emit(uint8_t* out, uint32_t* k, uint32_t v) {
 // their count to *n.  A byte below 0x20, an unknown escape, a malformed or
 // lone surrogate, or no closing quote is an error (the count then stops
 // there, the same in both modes).
+// No byte of x is a quote, a backslash or below 0x20 (each test is the exact
+// "some byte is zero / below n" bit trick).
+JSIDX_DEV bool plain_word(uint32_t x) {
+  const uint32_t q = x ^ 0x22222222u, b = x ^ 0x5C5C5C5Cu;
+  const uint32_t hit = ((q - 0x01010101u) & ~q) | ((b - 0x01010101u) & ~b) | ((x - 0x20202020u) & ~x);
+  return (hit & 0x80808080u) == 0u;
+}
+
 template <bool WRITE>
 JSIDX_DEV uint32_t normalize_string(const TapeArgs& a, uint64_t q, uint8_t* out, uint32_t* n) {
   uint64_t p = q + 1;
   uint32_t k = 0;
   uint32_t err = 0;
   for (;;) {
+    // 16 bytes from the aligned word holding p on (four loads in flight): the
+    // plain bytes up to the first quote, backslash or control byte are taken
+    // from registers; that byte is handled below
+    const uint32_t off = (uint32_t)(reinterpret_cast<uintptr_t>(a.buf + p) & 3u);
+    if (p >= off && p - off + 16 <= a.len) {
+      const uint64_t pb = p - off;
+      uint32_t x[4];
+#pragma unroll
+      for (int j = 0; j < 4; j++) x[j] = prim::load4(a.buf + pb + 4 * j);
+      uint32_t first = 16;  // the first special byte at or after p, in the block
+#pragma unroll
+      for (int j = 3; j >= 0; j--) {
+        const uint32_t v = x[j], q2 = v ^ 0x22222222u, b2 = v ^ 0x5C5C5C5Cu;
+        // the lowest flagged byte of a word is exact (a borrow only runs upward)
+        uint32_t hit = (((q2 - 0x01010101u) & ~q2) | ((b2 - 0x01010101u) & ~b2) | ((v - 0x20202020u) & ~v)) &
+                       0x80808080u;
+        if (j == 0) hit &= 0xFFFFFFFFu << (8 * off);  // bytes before p are not the string's
+        if (hit) first = 4 * (uint32_t)j + (uint32_t)__builtin_ctz(hit) / 8;
+      }
+      // bytes [off, first) are plain
+      if constexpr (WRITE) {
+#pragma unroll
+        for (int j = 0; j < 16; j++) {
+          if ((uint32_t)j >= off && (uint32_t)j < first) prim::st_byte(out + k + (j - off), (x[j >> 2] >> (8 * (j & 3))) & 0xFFu);
+        }
+      }
+      k += first - off;
+      p = pb + first;
+      if (first == 16) continue;
+    }
     if (p >= a.len) { err = kErrString; break; }
     const uint32_t c = prim::load1(a.buf + p);
     if (c == '"') break;
@@ -212,10 +279,11 @@ JSIDX_DEV bool literal_ok(const TapeArgs& a, uint64_t p, uint32_t first) {
   // true, false, null by their bytes (little-endian words)
   const uint32_t L = first == 'f' ? 5u : 4u;
   if (p + L > a.len) return false;
+  Cursor cur = cursor(a.buf, a.len);
   uint64_t v = 0;
-  for (uint32_t k = 0; k < L; k++) v |= (uint64_t)prim::load1(a.buf + p + k) << (8 * k);
+  for (uint32_t k = 0; k < L; k++) v |= (uint64_t)cur.at(p + k) << (8 * k);
   const uint64_t want = first == 't' ? 0x65757274ull : first == 'n' ? 0x6C6C756Eull : 0x65736C6166ull;
-  return v == want && ends_atom(a, p + L);
+  return v == want && ends_atom(cur, p + L);
 }
 
 // ---- Numbers (Sec. 3.2.1) ---------------------------------------------------
@@ -235,17 +303,18 @@ JSIDX_DEV bool is_digit(uint32_t c) { return c - '0' <= 9u; }
 
 JSIDX_DEV NumText scan_number(const TapeArgs& a, uint64_t p) {
   NumText t{false, false, true, false, 0, 0, 0};
+  Cursor cur = cursor(a.buf, a.len);
   uint32_t nd = 0;  // significant digits in w
   int64_t q = 0;
-  uint32_t c = byte_at(a, p);
+  uint32_t c = cur.at(p);
   if (c == '-') {
     t.neg = true;
-    c = byte_at(a, ++p);
+    c = cur.at(++p);
   }
   if (!is_digit(c)) return t;
   if (c == '0') {
     t.int_digits = 1;
-    c = byte_at(a, ++p);
+    c = cur.at(++p);
   } else {
     while (p < a.len && is_digit(c)) {
       t.int_digits++;
@@ -256,12 +325,12 @@ JSIDX_DEV NumText scan_number(const TapeArgs& a, uint64_t p) {
         q++;  // a dropped digit of the integer part scales the rest
         t.trunc = t.trunc || c != '0';
       }
-      c = byte_at(a, ++p);
+      c = cur.at(++p);
     }
   }
   if (p < a.len && c == '.') {
     t.is_int = false;
-    c = byte_at(a, ++p);
+    c = cur.at(++p);
     if (!(p < a.len && is_digit(c))) return t;
     while (p < a.len && is_digit(c)) {
       if (nd == 0 && c == '0') {
@@ -273,27 +342,27 @@ JSIDX_DEV NumText scan_number(const TapeArgs& a, uint64_t p) {
       } else {
         t.trunc = t.trunc || c != '0';
       }
-      c = byte_at(a, ++p);
+      c = cur.at(++p);
     }
   }
   if (p < a.len && (c == 'e' || c == 'E')) {
     t.is_int = false;
-    c = byte_at(a, ++p);
+    c = cur.at(++p);
     bool eneg = false;
     if (p < a.len && (c == '+' || c == '-')) {
       eneg = c == '-';
-      c = byte_at(a, ++p);
+      c = cur.at(++p);
     }
     if (!(p < a.len && is_digit(c))) return t;
     int64_t e = 0;
     while (p < a.len && is_digit(c)) {
       if (e < 100000000) e = e * 10 + (c - '0');
-      c = byte_at(a, ++p);
+      c = cur.at(++p);
     }
     q += eneg ? -e : e;
   }
   t.q = q;
-  t.ok = ends_atom(a, p);
+  t.ok = ends_atom(cur, p);
   return t;
 }
 
@@ -561,22 +630,23 @@ JSIDX_DEV int exact_double(const TapeArgs& a, uint64_t p, Big& D, Big& V, Big& S
 
 // ---- Kernels ------------------------------------------------------------------
 
-// Buffer bytes of entry i: 4 + the normalized length of a string, else 0.
-JSIDX_DEV uint32_t string_bytes(const TapeArgs& a, uint32_t i, uint32_t b) {
-  if (b != '"') return 0;
-  uint32_t k = 0;
-  (void)normalize_string<false>(a, prim::load4(reinterpret_cast<const uint8_t*>(a.idx + i)), nullptr, &k);
-  return 4 + k;
-}
-
-struct TapeLds {
+struct TapeScanLds {
   uint64_t w[kTapeThreads];
   uint64_t s[kTapeThreads];
 };
+// A chunk staged in LDS: first bytes, buffer bytes (then their prefix in the
+// chunk), tape indices.
+struct TapeChunkLds {
+  TapeScanLds sc;
+  uint32_t S[kTapeChunk];
+  uint32_t T[kTapeChunk];
+  uint8_t K[kTapeChunk];
+};
 
-// Sum over the workgroup (every thread gets it); ex receives the sum of the
-// threads before this one.
-JSIDX_DEV void group_scan2(TapeLds& g, uint32_t tid, uint64_t w, uint64_t s, uint64_t* wex, uint64_t* sex,
+// Exclusive scan over the workgroup of two sums (ex: the threads before this
+// one; all: every thread).
+template <typename G>
+JSIDX_DEV void group_scan2(G& g, uint32_t tid, uint64_t w, uint64_t s, uint64_t* wex, uint64_t* sex,
                            uint64_t* wall, uint64_t* sall) {
   g.w[tid] = w;
   g.s[tid] = s;
@@ -595,31 +665,6 @@ JSIDX_DEV void group_scan2(TapeLds& g, uint32_t tid, uint64_t w, uint64_t s, uin
   prim::sync();
 }
 
-// 1. Words and buffer bytes per entry (thread t of chunk c takes entries
-//    c * 4096 + 16t .. +15), the buffer bytes kept per entry, sums per chunk.
-JSIDX_DEVFN void tape_count(const TapeArgs& a) {
-  TapeLds& g = prim::lds_object<TapeLds>();
-  const uint32_t tid = tape_tid(), c = prim::block();
-  const uint64_t e0 = (uint64_t)c * kTapeChunk + (uint64_t)tid * kTapePer;
-  uint64_t w = 0, s = 0;
-  for (int k = 0; k < kTapePer; k++) {
-    const uint64_t i = e0 + (uint64_t)k;
-    if (i >= a.n) break;
-    const uint32_t b = entry_byte(a, (uint32_t)i);
-    const uint32_t sb = string_bytes(a, (uint32_t)i, b);
-    prim::st_out(a.sbytes + i, sb);
-    w += words_of(b);
-    s += sb;
-  }
-  uint64_t wex, sex, wall, sall;
-  group_scan2(g, tid, w, s, &wex, &sex, &wall, &sall);
-  if (tid == 0) {
-    prim::st_pair(reinterpret_cast<uint2*>(a.chunk_sum + 2 * (uint64_t)c), (uint32_t)wall, (uint32_t)(wall >> 32));
-    prim::st_pair(reinterpret_cast<uint2*>(a.chunk_sum + 2 * (uint64_t)c + 1), (uint32_t)sall,
-                  (uint32_t)(sall >> 32));
-  }
-}
-
 JSIDX_DEV uint64_t ld64(const uint64_t* p) {
   const uint2 v = prim::ld_pair(reinterpret_cast<const uint2*>(p));
   return ((uint64_t)v.y << 32) | v.x;
@@ -628,9 +673,39 @@ JSIDX_DEV void st64(uint64_t* p, uint64_t v) {
   prim::st_pair(reinterpret_cast<uint2*>(p), (uint32_t)v, (uint32_t)(v >> 32));
 }
 
+// 1. First bytes and string sizes (thread t takes entries c * 4096 + t +
+//    256 k), their sums per chunk.
+JSIDX_DEVFN void tape_count(const TapeArgs& a) {
+  TapeScanLds& g = prim::lds_object<TapeScanLds>();
+  const uint32_t tid = tape_tid(), c = prim::block();
+  uint64_t w = 0, s = 0;
+  for (int k = 0; k < kTapePer; k++) {
+    const uint64_t i = (uint64_t)c * kTapeChunk + (uint64_t)k * kTapeThreads + tid;
+    if (i >= a.n) break;
+    const uint64_t pos = prim::load4(reinterpret_cast<const uint8_t*>(a.idx + i));
+    const uint32_t b = byte_at(a, pos);
+    uint32_t sb = 0;
+    if (b == '"') {
+      uint32_t len = 0;
+      (void)normalize_string<false>(a, pos, nullptr, &len);
+      sb = 4 + len;
+    }
+    prim::st_out(a.sbytes + i, sb);
+    prim::st_byte(a.kb + i, b);
+    w += words_of(b);
+    s += sb;
+  }
+  uint64_t wex, sex, wall, sall;
+  group_scan2(g, tid, w, s, &wex, &sex, &wall, &sall);
+  if (tid == 0) {
+    st64(a.chunk_sum + 2 * (uint64_t)c, wall);
+    st64(a.chunk_sum + 2 * (uint64_t)c + 1, sall);
+  }
+}
+
 // 2. Chunk bases (one workgroup), the root words, the sizes; flags cleared.
 JSIDX_DEVFN void tape_scan(const TapeArgs& a) {
-  TapeLds& g = prim::lds_object<TapeLds>();
+  TapeScanLds& g = prim::lds_object<TapeScanLds>();
   const uint32_t tid = tape_tid();
   const uint32_t per = (a.nchunks + kTapeThreads - 1) / kTapeThreads;
   const uint64_t lo = (uint64_t)tid * per;
@@ -660,39 +735,55 @@ JSIDX_DEVFN void tape_scan(const TapeArgs& a) {
   }
 }
 
-// 3. Each entry's tape index (after the root word) and buffer offset.
-JSIDX_DEVFN void tape_offsets(const TapeArgs& a) {
-  TapeLds& g = prim::lds_object<TapeLds>();
-  const uint32_t tid = tape_tid(), c = prim::block();
-  const uint64_t e0 = (uint64_t)c * kTapeChunk + (uint64_t)tid * kTapePer;
+// Stages chunk c (first bytes and string sizes, loaded coalesced) and turns
+// them into each entry's tape index (T) and buffer offset (S) by a scan over
+// the threads' runs of 16 entries.
+JSIDX_DEV void stage_offsets(const TapeArgs& a, TapeChunkLds& g, uint32_t tid, uint32_t c) {
+  const uint64_t c0 = (uint64_t)c * kTapeChunk;
+  for (uint32_t j = tid; j < (uint32_t)kTapeChunk; j += kTapeThreads) {
+    const bool in = c0 + j < a.n;
+    g.K[j] = (uint8_t)(in ? prim::load1(a.kb + c0 + j) : ':');
+    g.S[j] = in ? prim::load4(reinterpret_cast<const uint8_t*>(a.sbytes + c0 + j)) : 0u;
+  }
+  prim::sync();
   uint64_t w = 0, s = 0;
   for (int k = 0; k < kTapePer; k++) {
-    const uint64_t i = e0 + (uint64_t)k;
-    if (i >= a.n) break;
-    w += words_of(entry_byte(a, (uint32_t)i));
-    s += prim::load4(reinterpret_cast<const uint8_t*>(a.sbytes + i));
+    const uint32_t j = tid * kTapePer + (uint32_t)k;
+    w += words_of(g.K[j]);
+    s += g.S[j];
   }
   uint64_t wex, sex, wall, sall;
-  group_scan2(g, tid, w, s, &wex, &sex, &wall, &sall);
+  group_scan2(g.sc, tid, w, s, &wex, &sex, &wall, &sall);
   uint64_t tw = 1 + ld64(a.chunk_sum + 2 * (uint64_t)c) + wex;
   uint64_t ts = ld64(a.chunk_sum + 2 * (uint64_t)c + 1) + sex;
   for (int k = 0; k < kTapePer; k++) {
-    const uint64_t i = e0 + (uint64_t)k;
-    if (i >= a.n) break;
-    prim::st_out(a.toff + i, (uint32_t)tw);
-    st64(a.soff + i, ts);
-    tw += words_of(entry_byte(a, (uint32_t)i));
-    ts += prim::load4(reinterpret_cast<const uint8_t*>(a.sbytes + i));
+    const uint32_t j = tid * kTapePer + (uint32_t)k;
+    const uint32_t sb = g.S[j];
+    g.T[j] = (uint32_t)tw;
+    g.S[j] = (uint32_t)ts;  // the buffer offset's low word (see tape_write)
+    tw += words_of(g.K[j]);
+    ts += sb;
+  }
+  prim::sync();
+}
+
+// 3. Each entry's tape index, stored coalesced.
+JSIDX_DEVFN void tape_offsets(const TapeArgs& a) {
+  TapeChunkLds& g = prim::lds_object<TapeChunkLds>();
+  const uint32_t tid = tape_tid(), c = prim::block();
+  stage_offsets(a, g, tid, c);
+  const uint64_t c0 = (uint64_t)c * kTapeChunk;
+  for (uint32_t j = tid; j < (uint32_t)kTapeChunk; j += kTapeThreads) {
+    if (c0 + j >= a.n) break;
+    prim::st_out(a.toff + c0 + j, g.T[j]);
   }
 }
 
 // 4. Every entry's words (one thread per entry, consecutive threads on
 //    consecutive entries).
-JSIDX_DEV uint32_t write_entry(const TapeArgs& a, uint32_t i) {
-  const uint64_t pos = prim::load4(reinterpret_cast<const uint8_t*>(a.idx + i));
-  const uint32_t b = byte_at(a, pos);
+JSIDX_DEV uint32_t write_entry(const TapeArgs& a, uint32_t i, uint32_t b, uint64_t t, uint64_t so) {
   if (b == ':' || b == ',') return 0;
-  const uint64_t t = prim::load4(reinterpret_cast<const uint8_t*>(a.toff + i));
+  const uint64_t pos = prim::load4(reinterpret_cast<const uint8_t*>(a.idx + i));
   uint64_t* out = a.tape + t;
   if (b == '{' || b == '[' || b == '}' || b == ']') {
     const uint32_t k = prim::load4(reinterpret_cast<const uint8_t*>(a.match + i));
@@ -705,7 +796,6 @@ JSIDX_DEV uint32_t write_entry(const TapeArgs& a, uint32_t i) {
     return 0;
   }
   if (b == '"') {
-    const uint64_t so = ld64(a.soff + i);
     uint32_t k = 0;
     const uint32_t err = normalize_string<true>(a, pos, a.str + so + 4, &k);
     for (int j = 0; j < 4; j++) prim::st_byte(a.str + so + j, (k >> (8 * j)) & 0xFFu);
@@ -762,12 +852,20 @@ JSIDX_DEV uint32_t write_entry(const TapeArgs& a, uint32_t i) {
 }
 
 JSIDX_DEVFN void tape_write(const TapeArgs& a) {
+  TapeChunkLds& g = prim::lds_object<TapeChunkLds>();
   const uint32_t tid = tape_tid(), c = prim::block();
+  stage_offsets(a, g, tid, c);
+  // a chunk's buffer bytes stay below 2^32 (its strings lie in the document,
+  // len < 2^32 - 2^16), so an offset is the chunk base plus its low word's
+  // distance from the base's
+  const uint64_t sbase = ld64(a.chunk_sum + 2 * (uint64_t)c + 1);
   uint32_t err = 0;
   for (int k = 0; k < kTapePer; k++) {
-    const uint64_t i = (uint64_t)c * kTapeChunk + (uint64_t)k * kTapeThreads + tid;
+    const uint32_t j = (uint32_t)k * kTapeThreads + tid;
+    const uint64_t i = (uint64_t)c * kTapeChunk + j;
     if (i >= a.n) break;
-    err |= write_entry(a, (uint32_t)i);
+    const uint64_t so = sbase + (uint32_t)(g.S[j] - (uint32_t)sbase);
+    err |= write_entry(a, (uint32_t)i, g.K[j], g.T[j], so);
   }
   // one atomic per wave for each flag that is set
   const uint32_t lane = prim::lane();

@@ -63,7 +63,7 @@ extern "C" int jsidx_tape(const uint8_t* buf, uint64_t len, const uint32_t* idx,
   hipStream_t stream = (hipStream_t)stream_;
   if (!out_tape || !out_tape_n || !out_str_n || !out_err) return JSIDX_E_INVAL;
   if (n && (!buf || !idx || !match || !out_str)) return JSIDX_E_INVAL;
-  if (len >= (1ull << 32) || n >= (1u << 31)) return JSIDX_E_INVAL;
+  if (len >= (1ull << 32) - (1ull << 16) || n >= (1u << 31)) return JSIDX_E_INVAL;
   const TapeLayout L = tape_layout(n);
   std::lock_guard<std::mutex> lk(g_tmu);
   void* mem = nullptr;
@@ -85,7 +85,7 @@ extern "C" int jsidx_tape(const uint8_t* buf, uint64_t len, const uint32_t* idx,
   a.chunk_sum = reinterpret_cast<uint64_t*>(m + L.chunk_sum);
   a.sbytes = reinterpret_cast<uint32_t*>(m + L.sbytes);
   a.toff = reinterpret_cast<uint32_t*>(m + L.toff);
-  a.soff = reinterpret_cast<uint64_t*>(m + L.soff);
+  a.kb = m + L.kb;
   a.qcount = reinterpret_cast<uint32_t*>(m + L.qcount);
   a.queue = reinterpret_cast<uint32_t*>(m + L.queue);
   const dim3 block(kTapeThreads);

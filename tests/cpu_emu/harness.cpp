@@ -179,7 +179,7 @@ long emu_tape_run(const uint8_t* buf, uint64_t len, const uint32_t* idx, uint32_
   a.chunk_sum = reinterpret_cast<uint64_t*>(m + L.chunk_sum);
   a.sbytes = reinterpret_cast<uint32_t*>(m + L.sbytes);
   a.toff = reinterpret_cast<uint32_t*>(m + L.toff);
-  a.soff = reinterpret_cast<uint64_t*>(m + L.soff);
+  a.kb = m + L.kb;
   a.qcount = reinterpret_cast<uint32_t*>(m + L.qcount);
   a.queue = reinterpret_cast<uint32_t*>(m + L.queue);
   auto phase = [&](int ngroups, int nthreads, void (*body)(const TapeArgs&)) {

@@ -93,32 +93,44 @@ JSIDX_DEV uint32_t entry_byte(const TapeArgs& a, uint32_t i) {
 
 JSIDX_DEV bool is_lit_start(uint32_t b) { return b == 't' || b == 'f' || b == 'n'; }
 
-// Bytes of the document read through a 16-byte window of registers (four
-// aligned words loaded together), so that a short atom costs one or two
-// memory round trips instead of one per byte.  Outside the document: 0.
-struct Cursor {
+// The 32 bytes from the aligned word holding byte p on, loaded together into
+// registers (eight word loads in flight), so that a short atom costs one
+// memory round trip instead of one per byte.  Bytes past the window, or all
+// bytes when it would leave the document, are loaded one by one; outside the
+// document they read as 0.
+struct Window {
   const uint8_t* buf;
   uint64_t len;
-  uint64_t base;
-  uint32_t w0, w1, w2, w3;
-  JSIDX_DEV uint32_t at(uint64_t p) {
-    if (p >= len) return 0u;
-    uint64_t d = p - base;  // huge when p is below the window (or none is loaded)
-    if (p < base || d >= 16) {
-      const uint32_t off = (uint32_t)(reinterpret_cast<uintptr_t>(buf + p) & 3u);
-      if (p < off || p - off + 16 > len) return prim::load1(buf + p);
-      base = p - off;
-      w0 = prim::load4(buf + base);
-      w1 = prim::load4(buf + base + 4);
-      w2 = prim::load4(buf + base + 8);
-      w3 = prim::load4(buf + base + 12);
-      d = off;
-    }
-    const uint32_t v = d < 8 ? (d < 4 ? w0 : w1) : (d < 12 ? w2 : w3);
-    return (v >> (8 * (uint32_t)(d & 3u))) & 0xFFu;
-  }
+  uint64_t base;  // ~0: no window
+  uint64_t q0, q1, q2, q3;
 };
-JSIDX_DEV Cursor cursor(const uint8_t* buf, uint64_t len) { return Cursor{buf, len, ~0ull, 0u, 0u, 0u, 0u}; }  // no window
+JSIDX_DEV Window window_at(const uint8_t* buf, uint64_t len, uint64_t p) {
+  Window w{buf, len, ~0ull, 0, 0, 0, 0};
+  const uint32_t off = (uint32_t)(reinterpret_cast<uintptr_t>(buf + p) & 3u);
+  if (p < off || p - off + 32 > len) return w;
+  w.base = p - off;
+  uint32_t v[8];
+#pragma unroll
+  for (int j = 0; j < 8; j++) v[j] = prim::load4(buf + w.base + 4 * j);
+  w.q0 = ((uint64_t)v[1] << 32) | v[0];
+  w.q1 = ((uint64_t)v[3] << 32) | v[2];
+  w.q2 = ((uint64_t)v[5] << 32) | v[4];
+  w.q3 = ((uint64_t)v[7] << 32) | v[6];
+  return w;
+}
+// One of four values by mask arithmetic (a chain of selects may be turned
+// into an indexed array in private memory).
+JSIDX_DEV uint64_t pick4(uint64_t a0, uint64_t a1, uint64_t a2, uint64_t a3, uint32_t i) {
+  return (a0 & (0ull - (uint64_t)(i == 0))) | (a1 & (0ull - (uint64_t)(i == 1))) |
+         (a2 & (0ull - (uint64_t)(i == 2))) | (a3 & (0ull - (uint64_t)(i == 3)));
+}
+JSIDX_DEV uint32_t win_byte(const Window& w, uint64_t p) {
+  if (p >= w.len) return 0u;
+  const uint64_t d = p - w.base;
+  if (p < w.base || d >= 32) return prim::load1(w.buf + p);
+  const uint64_t q = pick4(w.q0, w.q1, w.q2, w.q3, (uint32_t)(d >> 3));
+  return (uint32_t)(q >> (8 * (d & 7u))) & 0xFFu;
+}
 
 // Tape words of an entry by its first byte.
 JSIDX_DEV uint32_t words_of(uint32_t b) {
@@ -128,9 +140,9 @@ JSIDX_DEV uint32_t words_of(uint32_t b) {
 }
 
 // An atom ends at white space, a structural character or the document's end.
-JSIDX_DEV bool ends_atom(Cursor& cur, uint64_t p) {
-  if (p >= cur.len) return true;
-  const uint32_t c = cur.at(p);
+JSIDX_DEV bool ends_atom(const Window& w, uint64_t p) {
+  if (p >= w.len) return true;
+  const uint32_t c = win_byte(w, p);
   return c == ' ' || c == '\t' || c == '\n' || c == '\r' || c == ',' || c == ':' || c == '[' || c == ']' ||
          c == '{' || c == '}';
 }
@@ -186,24 +198,43 @@ JSIDX_DEV uint32_t normalize_string(const TapeArgs& a, uint64_t q, uint8_t* out,
     const uint32_t off = (uint32_t)(reinterpret_cast<uintptr_t>(a.buf + p) & 3u);
     if (p >= off && p - off + 16 <= a.len) {
       const uint64_t pb = p - off;
-      uint32_t x[4];
-#pragma unroll
-      for (int j = 0; j < 4; j++) x[j] = prim::load4(a.buf + pb + 4 * j);
-      uint32_t first = 16;  // the first special byte at or after p, in the block
-#pragma unroll
-      for (int j = 3; j >= 0; j--) {
-        const uint32_t v = x[j], q2 = v ^ 0x22222222u, b2 = v ^ 0x5C5C5C5Cu;
-        // the lowest flagged byte of a word is exact (a borrow only runs upward)
-        uint32_t hit = (((q2 - 0x01010101u) & ~q2) | ((b2 - 0x01010101u) & ~b2) | ((v - 0x20202020u) & ~v)) &
-                       0x80808080u;
-        if (j == 0) hit &= 0xFFFFFFFFu << (8 * off);  // bytes before p are not the string's
-        if (hit) first = 4 * (uint32_t)j + (uint32_t)__builtin_ctz(hit) / 8;
-      }
-      // bytes [off, first) are plain
+      const uint32_t x0 = prim::load4(a.buf + pb), x1 = prim::load4(a.buf + pb + 4);
+      const uint32_t x2 = prim::load4(a.buf + pb + 8), x3 = prim::load4(a.buf + pb + 12);
+      // the lowest flagged byte of a word is exact (a borrow only runs upward)
+      auto hits = [](uint32_t v) {
+        const uint32_t q2 = v ^ 0x22222222u, b2 = v ^ 0x5C5C5C5Cu;
+        return (((q2 - 0x01010101u) & ~q2) | ((b2 - 0x01010101u) & ~b2) | ((v - 0x20202020u) & ~v)) & 0x80808080u;
+      };
+      const uint32_t h0 = hits(x0) & (0xFFFFFFFFu << (8 * off)), h1 = hits(x1), h2 = hits(x2), h3 = hits(x3);
+      // the first special byte at or after p, in the block (16: none)
+      const uint32_t first = h0 ? (uint32_t)__builtin_ctz(h0) / 8
+                           : h1 ? 4 + (uint32_t)__builtin_ctz(h1) / 8
+                           : h2 ? 8 + (uint32_t)__builtin_ctz(h2) / 8
+                           : h3 ? 12 + (uint32_t)__builtin_ctz(h3) / 8 : 16u;
+      // bytes [off, first) are plain: whole words where the destination is
+      // aligned (taken from the window shifted as a 128-bit value), single
+      // bytes around them
       if constexpr (WRITE) {
-#pragma unroll
-        for (int j = 0; j < 16; j++) {
-          if ((uint32_t)j >= off && (uint32_t)j < first) prim::st_byte(out + k + (j - off), (x[j >> 2] >> (8 * (j & 3))) & 0xFFu);
+        const uint64_t lo64 = ((uint64_t)x1 << 32) | x0, hi64 = ((uint64_t)x3 << 32) | x2;
+        const uint32_t cnt = first - off;
+        const uint32_t da = (uint32_t)(reinterpret_cast<uintptr_t>(out + k) & 3u);
+        uint32_t m0 = (4u - da) & 3u;
+        if (m0 > cnt) m0 = cnt;
+        const uint32_t nw = (cnt - m0) / 4;
+        for (uint32_t m = 0; m < cnt; m++) {
+          if (m == m0 && nw) m += 4 * nw;  // the words below
+          if (m >= cnt) break;
+          const uint32_t idx = off + m;
+          prim::st_byte(out + k + m, (uint32_t)((idx < 8 ? lo64 >> (8 * idx) : hi64 >> (8 * (idx - 8))) & 0xFFu));
+        }
+        if (nw) {
+          const uint32_t r = 8 * (off + m0);  // below 64: off and m0 are at most 3
+          const uint64_t slo = r ? (lo64 >> r) | (hi64 << (64 - r)) : lo64, shi = hi64 >> r;
+          uint32_t* dw = reinterpret_cast<uint32_t*>(out + k + m0);
+          prim::st_out(dw, (uint32_t)slo);
+          if (nw > 1) prim::st_out(dw + 1, (uint32_t)(slo >> 32));
+          if (nw > 2) prim::st_out(dw + 2, (uint32_t)shi);
+          if (nw > 3) prim::st_out(dw + 3, (uint32_t)(shi >> 32));
         }
       }
       k += first - off;
@@ -279,11 +310,11 @@ JSIDX_DEV bool literal_ok(const TapeArgs& a, uint64_t p, uint32_t first) {
   // true, false, null by their bytes (little-endian words)
   const uint32_t L = first == 'f' ? 5u : 4u;
   if (p + L > a.len) return false;
-  Cursor cur = cursor(a.buf, a.len);
+  const Window w = window_at(a.buf, a.len, p);
   uint64_t v = 0;
-  for (uint32_t k = 0; k < L; k++) v |= (uint64_t)cur.at(p + k) << (8 * k);
+  for (uint32_t k = 0; k < L; k++) v |= (uint64_t)win_byte(w, p + k) << (8 * k);
   const uint64_t want = first == 't' ? 0x65757274ull : first == 'n' ? 0x6C6C756Eull : 0x65736C6166ull;
-  return v == want && ends_atom(cur, p + L);
+  return v == want && ends_atom(w, p + L);
 }
 
 // ---- Numbers (Sec. 3.2.1) ---------------------------------------------------
@@ -303,18 +334,18 @@ JSIDX_DEV bool is_digit(uint32_t c) { return c - '0' <= 9u; }
 
 JSIDX_DEV NumText scan_number(const TapeArgs& a, uint64_t p) {
   NumText t{false, false, true, false, 0, 0, 0};
-  Cursor cur = cursor(a.buf, a.len);
+  const Window w = window_at(a.buf, a.len, p);
   uint32_t nd = 0;  // significant digits in w
   int64_t q = 0;
-  uint32_t c = cur.at(p);
+  uint32_t c = win_byte(w, p);
   if (c == '-') {
     t.neg = true;
-    c = cur.at(++p);
+    c = win_byte(w, ++p);
   }
   if (!is_digit(c)) return t;
   if (c == '0') {
     t.int_digits = 1;
-    c = cur.at(++p);
+    c = win_byte(w, ++p);
   } else {
     while (p < a.len && is_digit(c)) {
       t.int_digits++;
@@ -325,12 +356,12 @@ JSIDX_DEV NumText scan_number(const TapeArgs& a, uint64_t p) {
         q++;  // a dropped digit of the integer part scales the rest
         t.trunc = t.trunc || c != '0';
       }
-      c = cur.at(++p);
+      c = win_byte(w, ++p);
     }
   }
   if (p < a.len && c == '.') {
     t.is_int = false;
-    c = cur.at(++p);
+    c = win_byte(w, ++p);
     if (!(p < a.len && is_digit(c))) return t;
     while (p < a.len && is_digit(c)) {
       if (nd == 0 && c == '0') {
@@ -342,27 +373,27 @@ JSIDX_DEV NumText scan_number(const TapeArgs& a, uint64_t p) {
       } else {
         t.trunc = t.trunc || c != '0';
       }
-      c = cur.at(++p);
+      c = win_byte(w, ++p);
     }
   }
   if (p < a.len && (c == 'e' || c == 'E')) {
     t.is_int = false;
-    c = cur.at(++p);
+    c = win_byte(w, ++p);
     bool eneg = false;
     if (p < a.len && (c == '+' || c == '-')) {
       eneg = c == '-';
-      c = cur.at(++p);
+      c = win_byte(w, ++p);
     }
     if (!(p < a.len && is_digit(c))) return t;
     int64_t e = 0;
     while (p < a.len && is_digit(c)) {
       if (e < 100000000) e = e * 10 + (c - '0');
-      c = cur.at(++p);
+      c = win_byte(w, ++p);
     }
     q += eneg ? -e : e;
   }
   t.q = q;
-  t.ok = ends_atom(cur, p);
+  t.ok = ends_atom(w, p);
   return t;
 }
 

@@ -208,7 +208,7 @@ int jsidx_scopes(const uint8_t *buf, uint64_t len, const uint32_t *idx,
  *              atom starting with t, f or n that is not exactly true, false
  *              or null).  Every atom and string is checked, each on its own.
  * The tape is the paper's only when jsidx_scopes reported no flag and out_err
- * is 0.  A per-stream workspace of about 13 bytes per entry is allocated on
+ * is 0.  A per-stream workspace of about 33 bytes per entry is allocated on
  * first use and grown as needed (synchronising the stream).  Asynchronous on
  * `stream`; returns JSIDX_E_INVAL for NULL pointers or sizes out of range.
  */

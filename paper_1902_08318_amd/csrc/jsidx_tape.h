@@ -11,11 +11,14 @@
 //   2. tape_scan: one workgroup turns the chunk sums into bases and writes the
 //      root words, the sizes, and clears the flags;
 //   3. tape_offsets: each entry's tape index (a scan inside the chunk);
-//   4. tape_write: every entry's words: brackets with the tape index of their
-//      partner (from the scope links), strings decoded into the buffer,
-//      numbers converted, literals checked.  A double whose rounding the fast
-//      conversion cannot decide is queued;
-//   5. tape_exact: the queued numbers by exact big-integer arithmetic.
+//   4. tape_write: the words of brackets (with the tape index of their
+//      partner, from the scope links), literals and strings; strings and
+//      numbers are queued, each kind densely, for
+//   5. tape_strings: strings decoded into the buffer, and
+//   6. tape_numbers: numbers converted; a double whose rounding the fast
+//      conversion cannot decide is queued again for
+//   7. tape_exact: the exact big-integer conversion.
+// Splitting by kind keeps the lanes of a wave on the same path.
 // Consecutive threads take consecutive entries (coalesced); the scans inside
 // a chunk run over the chunk staged in LDS.
 // Written on the same primitives as the other kernels, so that the CPU
@@ -39,6 +42,7 @@ constexpr int kTapePer = 16;
 constexpr int kTapeChunk = kTapeThreads * kTapePer;
 constexpr uint32_t kTapeUnlinked = 0xFFFFFFFFu;
 constexpr int kExactGroups = 64;      // workgroups of tape_exact
+constexpr int kQueueGroups = 8192;    // at most this many workgroups for the string and number queues
 constexpr int kExactThreads = 64;     // one wave each
 constexpr int kMaxDigits = 800;       // significant digits kept by the exact path
 constexpr int kBigLimbs = 300;        // 9600 bits per big integer
@@ -60,12 +64,14 @@ struct TapeArgs {
   uint32_t* sbytes;     // per entry: buffer bytes of a string, else 0
   uint8_t* kb;          // per entry: its first byte
   uint32_t* toff;       // per entry: tape index of its first word
-  uint32_t* qcount;     // numbers queued for the exact conversion
-  uint32_t* queue;      // their entries
+  uint32_t* qcount;     // queue lengths: [0] exact conversions, [1] strings, [2] numbers
+  uint32_t* queue;      // entries for the exact conversion
+  uint64_t* squeue;     // strings: entry and buffer offset
+  uint32_t* nqueue;     // numbers: entry
 };
 
 struct TapeLayout {
-  uint64_t chunk_sum, sbytes, kb, toff, qcount, queue, total;
+  uint64_t chunk_sum, sbytes, kb, toff, qcount, queue, squeue, nqueue, total;
 };
 inline uint64_t tape_align256(uint64_t x) { return (x + 255) & ~(uint64_t)255; }
 inline TapeLayout tape_layout(uint64_t n) {
@@ -76,8 +82,10 @@ inline TapeLayout tape_layout(uint64_t n) {
   L.sbytes = o; o = tape_align256(o + n * 4);
   L.kb = o; o = tape_align256(o + n);
   L.toff = o; o = tape_align256(o + n * 4);
-  L.qcount = o; o = tape_align256(o + 4);
+  L.qcount = o; o = tape_align256(o + 16);
   L.queue = o; o = tape_align256(o + n * 4);
+  L.squeue = o; o = tape_align256(o + n * 16);
+  L.nqueue = o; o = tape_align256(o + n * 4);
   L.total = o;
   return L;
 }
@@ -762,7 +770,7 @@ JSIDX_DEVFN void tape_scan(const TapeArgs& a) {
     st64(a.tape_n, last + 1);
     st64(a.str_n, sall);
     prim::st_out(a.err, 0u);
-    prim::st_out(a.qcount, 0u);
+    for (int q = 0; q < 3; q++) prim::st_out(a.qcount + q, 0u);
   }
 }
 
@@ -810,33 +818,98 @@ JSIDX_DEVFN void tape_offsets(const TapeArgs& a) {
   }
 }
 
-// 4. Every entry's words (one thread per entry, consecutive threads on
-//    consecutive entries).
-JSIDX_DEV uint32_t write_entry(const TapeArgs& a, uint32_t i, uint32_t b, uint64_t t, uint64_t so) {
-  if (b == ':' || b == ',') return 0;
-  const uint64_t pos = prim::load4(reinterpret_cast<const uint8_t*>(a.idx + i));
-  uint64_t* out = a.tape + t;
-  if (b == '{' || b == '[' || b == '}' || b == ']') {
-    const uint32_t k = prim::load4(reinterpret_cast<const uint8_t*>(a.match + i));
-    uint64_t link = 0;
-    if (k != kTapeUnlinked && k < a.n) {
-      const uint64_t tk = prim::load4(reinterpret_cast<const uint8_t*>(a.toff + k));
-      link = (b == '{' || b == '[') ? tk + 1 : tk;
+// Flags of a wave: one atomic per flag that some lane set.
+JSIDX_DEV void or_flags(const TapeArgs& a, uint32_t err) {
+  const uint32_t lane = prim::lane();
+  for (uint32_t f = kErrNumber; f <= kErrLiteral; f <<= 1)
+    if (prim::ballot((err & f) != 0u) != 0ull && lane == 0) prim::or_agent32(a.err, f);
+}
+
+// Appends the lanes with `take` to queue q (one atomic per wave); returns
+// this lane's slot.
+JSIDX_DEV uint32_t wave_append(const TapeArgs& a, int q, bool take) {
+  const uint64_t m = prim::ballot(take);
+  uint32_t base = 0;
+  if (prim::lane() == 0 && m) base = prim::add_agent32(a.qcount + q, (uint32_t)__builtin_popcountll(m));
+  base = prim::readlane(base, 0);
+  return base + prim::mbcnt(m);
+}
+
+// 4. Brackets, literals and the strings' words; strings and numbers queued
+//    (one thread per entry, consecutive threads on consecutive entries).
+JSIDX_DEVFN void tape_write(const TapeArgs& a) {
+  TapeChunkLds& g = prim::lds_object<TapeChunkLds>();
+  const uint32_t tid = tape_tid(), c = prim::block();
+  stage_offsets(a, g, tid, c);
+  // a chunk's buffer bytes stay below 2^32 (its strings lie in the document,
+  // len < 2^32 - 2^16), so an offset is the chunk base plus its low word's
+  // distance from the base's
+  const uint64_t sbase = ld64(a.chunk_sum + 2 * (uint64_t)c + 1);
+  uint32_t err = 0;
+  for (int k = 0; k < kTapePer; k++) {  // every lane runs every step (the queues' ballots)
+    const uint32_t j = (uint32_t)k * kTapeThreads + tid;
+    const uint64_t i = (uint64_t)c * kTapeChunk + j;
+    const bool in = i < a.n;
+    const uint32_t b = in ? g.K[j] : (uint32_t)':';
+    const uint64_t t = g.T[j];
+    const bool str = b == '"', num = words_of(b) == 2;
+    uint64_t so = 0;
+    if (b == '{' || b == '[' || b == '}' || b == ']') {
+      const uint32_t m = prim::load4(reinterpret_cast<const uint8_t*>(a.match + i));
+      uint64_t link = 0;
+      if (m != kTapeUnlinked && m < a.n) {
+        const uint64_t tk = prim::load4(reinterpret_cast<const uint8_t*>(a.toff + m));
+        link = (b == '{' || b == '[') ? tk + 1 : tk;
+      }
+      st64(a.tape + t, ((uint64_t)b << 56) | link);
+    } else if (is_lit_start(b)) {
+      st64(a.tape + t, (uint64_t)b << 56);
+      const uint64_t pos = prim::load4(reinterpret_cast<const uint8_t*>(a.idx + i));
+      if (!literal_ok(a, pos, b)) err |= kErrLiteral;
+    } else if (str) {
+      so = sbase + (uint32_t)(g.S[j] - (uint32_t)sbase);
+      st64(a.tape + t, ((uint64_t)'"' << 56) | so);
     }
-    st64(out, ((uint64_t)b << 56) | link);
-    return 0;
+    const uint32_t ss = wave_append(a, 1, str);
+    if (str) {
+      st64(a.squeue + 2 * (uint64_t)ss, i);
+      st64(a.squeue + 2 * (uint64_t)ss + 1, so);
+    }
+    const uint32_t ns = wave_append(a, 2, num);
+    if (num) prim::st_out(a.nqueue + ns, (uint32_t)i);
   }
-  if (b == '"') {
-    uint32_t k = 0;
-    const uint32_t err = normalize_string<true>(a, pos, a.str + so + 4, &k);
-    for (int j = 0; j < 4; j++) prim::st_byte(a.str + so + j, (k >> (8 * j)) & 0xFFu);
-    st64(out, ((uint64_t)'"' << 56) | so);
-    return err;
+  or_flags(a, err);
+}
+
+// Grid-stride bounds of a queue for this thread.
+JSIDX_DEV uint32_t queue_len(const TapeArgs& a, int q) { return prim::ld_agent32(a.qcount + q); }
+
+// 5. Strings: decoded into the buffer after their 32-bit length.
+JSIDX_DEVFN void tape_strings(const TapeArgs& a) {
+  const uint32_t qn = queue_len(a, 1);
+  const uint32_t stride = prim::grid() * (uint32_t)kTapeThreads;
+  uint32_t err = 0;
+  const uint32_t rounds = (qn + stride - 1) / stride;  // the same for every lane (ballots)
+  for (uint32_t r = 0; r < rounds; r++) {
+    const uint32_t q = r * stride + prim::block() * (uint32_t)kTapeThreads + tape_tid();
+    if (q < qn) {
+      const uint32_t i = (uint32_t)ld64(a.squeue + 2 * (uint64_t)q);
+      const uint64_t so = ld64(a.squeue + 2 * (uint64_t)q + 1);
+      const uint64_t pos = prim::load4(reinterpret_cast<const uint8_t*>(a.idx + i));
+      uint32_t k = 0;
+      err |= normalize_string<true>(a, pos, a.str + so + 4, &k);
+      for (int j = 0; j < 4; j++) prim::st_byte(a.str + so + j, (k >> (8 * j)) & 0xFFu);
+    }
   }
-  if (is_lit_start(b)) {
-    st64(out, (uint64_t)b << 56);
-    return literal_ok(a, pos, b) ? 0u : kErrLiteral;
-  }
+  or_flags(a, err);
+}
+
+// 6. Numbers: both words; undecided doubles queued for tape_exact.
+JSIDX_DEV uint32_t number_entry(const TapeArgs& a, uint32_t i, bool* undecided) {
+  const uint64_t pos = prim::load4(reinterpret_cast<const uint8_t*>(a.idx + i));
+  const uint64_t t = prim::load4(reinterpret_cast<const uint8_t*>(a.toff + i));
+  uint64_t* out = a.tape + t;
+  *undecided = false;
   const NumText nt = scan_number(a, pos);
   if (!nt.ok) {
     st64(out, (uint64_t)'d' << 56);
@@ -874,37 +947,33 @@ JSIDX_DEV uint32_t write_entry(const TapeArgs& a, uint32_t i, uint32_t b, uint64
     return kErrNumber;
   }
   if (r == kConvUndecided) {
-    const uint32_t slot = prim::add_agent32(a.qcount, 1u);
-    prim::st_out(a.queue + slot, i);
+    *undecided = true;
     return 0;
   }
   st64(out + 1, bits | sign);
   return 0;
 }
 
-JSIDX_DEVFN void tape_write(const TapeArgs& a) {
-  TapeChunkLds& g = prim::lds_object<TapeChunkLds>();
-  const uint32_t tid = tape_tid(), c = prim::block();
-  stage_offsets(a, g, tid, c);
-  // a chunk's buffer bytes stay below 2^32 (its strings lie in the document,
-  // len < 2^32 - 2^16), so an offset is the chunk base plus its low word's
-  // distance from the base's
-  const uint64_t sbase = ld64(a.chunk_sum + 2 * (uint64_t)c + 1);
+JSIDX_DEVFN void tape_numbers(const TapeArgs& a) {
+  const uint32_t qn = queue_len(a, 2);
+  const uint32_t stride = prim::grid() * (uint32_t)kTapeThreads;
   uint32_t err = 0;
-  for (int k = 0; k < kTapePer; k++) {
-    const uint32_t j = (uint32_t)k * kTapeThreads + tid;
-    const uint64_t i = (uint64_t)c * kTapeChunk + j;
-    if (i >= a.n) break;
-    const uint64_t so = sbase + (uint32_t)(g.S[j] - (uint32_t)sbase);
-    err |= write_entry(a, (uint32_t)i, g.K[j], g.T[j], so);
+  const uint32_t rounds = (qn + stride - 1) / stride;
+  for (uint32_t r = 0; r < rounds; r++) {
+    const uint32_t q = r * stride + prim::block() * (uint32_t)kTapeThreads + tape_tid();
+    bool undecided = false;
+    uint32_t i = 0;
+    if (q < qn) {
+      i = prim::load4(reinterpret_cast<const uint8_t*>(a.nqueue + q));
+      err |= number_entry(a, i, &undecided);
+    }
+    const uint32_t slot = wave_append(a, 0, undecided);
+    if (undecided) prim::st_out(a.queue + slot, i);
   }
-  // one atomic per wave for each flag that is set
-  const uint32_t lane = prim::lane();
-  for (uint32_t f = kErrNumber; f <= kErrLiteral; f <<= 1)
-    if (prim::ballot((err & f) != 0u) != 0ull && lane == 0) prim::or_agent32(a.err, f);
+  or_flags(a, err);
 }
 
-// 5. The queued numbers, one thread each, by exact arithmetic.
+// 7. The queued numbers, one thread each, by exact arithmetic.
 struct ExactScratch {
   Big D, V, S;
 };

@@ -15,6 +15,8 @@ __global__ void __launch_bounds__(kTapeThreads) tape_count_kernel(TapeArgs a) { 
 __global__ void __launch_bounds__(kTapeThreads) tape_scan_kernel(TapeArgs a) { tape_scan(a); }
 __global__ void __launch_bounds__(kTapeThreads) tape_offsets_kernel(TapeArgs a) { tape_offsets(a); }
 __global__ void __launch_bounds__(kTapeThreads) tape_write_kernel(TapeArgs a) { tape_write(a); }
+__global__ void __launch_bounds__(kTapeThreads) tape_strings_kernel(TapeArgs a) { tape_strings(a); }
+__global__ void __launch_bounds__(kTapeThreads) tape_numbers_kernel(TapeArgs a) { tape_numbers(a); }
 __global__ void __launch_bounds__(kExactThreads) tape_exact_kernel(TapeArgs a) { tape_exact(a); }
 
 namespace {
@@ -88,12 +90,19 @@ extern "C" int jsidx_tape(const uint8_t* buf, uint64_t len, const uint32_t* idx,
   a.kb = m + L.kb;
   a.qcount = reinterpret_cast<uint32_t*>(m + L.qcount);
   a.queue = reinterpret_cast<uint32_t*>(m + L.queue);
+  a.squeue = reinterpret_cast<uint64_t*>(m + L.squeue);
+  a.nqueue = reinterpret_cast<uint32_t*>(m + L.nqueue);
   const dim3 block(kTapeThreads);
   if (a.nchunks) hipLaunchKernelGGL(tape_count_kernel, dim3(a.nchunks), block, 0, stream, a);
   hipLaunchKernelGGL(tape_scan_kernel, dim3(1), block, 0, stream, a);
   if (a.nchunks) {
     hipLaunchKernelGGL(tape_offsets_kernel, dim3(a.nchunks), block, 0, stream, a);
     hipLaunchKernelGGL(tape_write_kernel, dim3(a.nchunks), block, 0, stream, a);
+    // the queues hold at most n entries; a grid-stride loop takes the rest
+    const uint64_t qgroups = ((uint64_t)n + kTapeThreads - 1) / kTapeThreads;
+    const dim3 qgrid((uint32_t)(qgroups < kQueueGroups ? qgroups : kQueueGroups));
+    hipLaunchKernelGGL(tape_strings_kernel, qgrid, block, 0, stream, a);
+    hipLaunchKernelGGL(tape_numbers_kernel, qgrid, block, 0, stream, a);
     hipLaunchKernelGGL(tape_exact_kernel, dim3(kExactGroups), dim3(kExactThreads), 0, stream, a);
   }
   if (hipGetLastError() != hipSuccess) return JSIDX_E_HIP;

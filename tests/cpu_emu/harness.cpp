@@ -182,6 +182,8 @@ long emu_tape_run(const uint8_t* buf, uint64_t len, const uint32_t* idx, uint32_
   a.kb = m + L.kb;
   a.qcount = reinterpret_cast<uint32_t*>(m + L.qcount);
   a.queue = reinterpret_cast<uint32_t*>(m + L.queue);
+  a.squeue = reinterpret_cast<uint64_t*>(m + L.squeue);
+  a.nqueue = reinterpret_cast<uint32_t*>(m + L.nqueue);
   auto phase = [&](int ngroups, int nthreads, void (*body)(const TapeArgs&)) {
     std::vector<prim::GroupCtx*> groups;
     for (int b = 0; b < ngroups; b++) groups.push_back(new prim::GroupCtx((uint32_t)nthreads));
@@ -206,6 +208,8 @@ long emu_tape_run(const uint8_t* buf, uint64_t len, const uint32_t* idx, uint32_
   if (a.nchunks) {
     phase((int)a.nchunks, kTapeThreads, tape_offsets);
     phase((int)a.nchunks, kTapeThreads, tape_write);
+    phase(2, kTapeThreads, tape_strings);
+    phase(2, kTapeThreads, tape_numbers);
     phase(exact_groups, kExactThreads, tape_exact);
   }
   *exact_count = n ? *a.qcount : 0u;

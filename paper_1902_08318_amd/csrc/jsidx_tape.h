@@ -677,6 +677,7 @@ struct TapeScanLds {
 // chunk), tape indices.
 struct TapeChunkLds {
   TapeScanLds sc;
+  uint32_t qbase[2];  // the workgroup's first slots in the string and number queues
   uint32_t S[kTapeChunk];
   uint32_t T[kTapeChunk];
   uint8_t K[kTapeChunk];
@@ -836,24 +837,39 @@ JSIDX_DEV uint32_t wave_append(const TapeArgs& a, int q, bool take) {
 }
 
 // 4. Brackets, literals and the strings' words; strings and numbers queued
-//    (one thread per entry, consecutive threads on consecutive entries).
+//    (one thread per entry, consecutive threads on consecutive entries; one
+//    atomic per workgroup and queue).
 JSIDX_DEVFN void tape_write(const TapeArgs& a) {
   TapeChunkLds& g = prim::lds_object<TapeChunkLds>();
   const uint32_t tid = tape_tid(), c = prim::block();
   stage_offsets(a, g, tid, c);
+  // the workgroup's slots in the two queues
+  uint64_t cs = 0, cn = 0;
+  for (int k = 0; k < kTapePer; k++) {
+    const uint32_t j = (uint32_t)k * kTapeThreads + tid;
+    const uint32_t b = g.K[j];  // entries past n were staged as ':'
+    cs += b == '"';
+    cn += words_of(b) == 2;
+  }
+  uint64_t sex, nex, sall, nall;
+  group_scan2(g.sc, tid, cs, cn, &sex, &nex, &sall, &nall);
+  if (tid == 0) {
+    g.qbase[0] = sall ? prim::add_agent32(a.qcount + 1, (uint32_t)sall) : 0u;
+    g.qbase[1] = nall ? prim::add_agent32(a.qcount + 2, (uint32_t)nall) : 0u;
+  }
+  prim::sync();
+  uint32_t ps = g.qbase[0] + (uint32_t)sex, pn = g.qbase[1] + (uint32_t)nex;
   // a chunk's buffer bytes stay below 2^32 (its strings lie in the document,
   // len < 2^32 - 2^16), so an offset is the chunk base plus its low word's
   // distance from the base's
   const uint64_t sbase = ld64(a.chunk_sum + 2 * (uint64_t)c + 1);
   uint32_t err = 0;
-  for (int k = 0; k < kTapePer; k++) {  // every lane runs every step (the queues' ballots)
+  for (int k = 0; k < kTapePer; k++) {
     const uint32_t j = (uint32_t)k * kTapeThreads + tid;
     const uint64_t i = (uint64_t)c * kTapeChunk + j;
-    const bool in = i < a.n;
-    const uint32_t b = in ? g.K[j] : (uint32_t)':';
+    if (i >= a.n) break;
+    const uint32_t b = g.K[j];
     const uint64_t t = g.T[j];
-    const bool str = b == '"', num = words_of(b) == 2;
-    uint64_t so = 0;
     if (b == '{' || b == '[' || b == '}' || b == ']') {
       const uint32_t m = prim::load4(reinterpret_cast<const uint8_t*>(a.match + i));
       uint64_t link = 0;
@@ -866,17 +882,16 @@ JSIDX_DEVFN void tape_write(const TapeArgs& a) {
       st64(a.tape + t, (uint64_t)b << 56);
       const uint64_t pos = prim::load4(reinterpret_cast<const uint8_t*>(a.idx + i));
       if (!literal_ok(a, pos, b)) err |= kErrLiteral;
-    } else if (str) {
-      so = sbase + (uint32_t)(g.S[j] - (uint32_t)sbase);
+    } else if (b == '"') {
+      const uint64_t so = sbase + (uint32_t)(g.S[j] - (uint32_t)sbase);
       st64(a.tape + t, ((uint64_t)'"' << 56) | so);
+      st64(a.squeue + 2 * (uint64_t)ps, i);
+      st64(a.squeue + 2 * (uint64_t)ps + 1, so);
+      ps++;
+    } else if (words_of(b) == 2) {
+      prim::st_out(a.nqueue + pn, (uint32_t)i);
+      pn++;
     }
-    const uint32_t ss = wave_append(a, 1, str);
-    if (str) {
-      st64(a.squeue + 2 * (uint64_t)ss, i);
-      st64(a.squeue + 2 * (uint64_t)ss + 1, so);
-    }
-    const uint32_t ns = wave_append(a, 2, num);
-    if (num) prim::st_out(a.nqueue + ns, (uint32_t)i);
   }
   or_flags(a, err);
 }

@@ -248,6 +248,10 @@ JSIDX_DEV uint32_t normalize_string(const TapeArgs& a, uint64_t q, uint8_t* out,
       k += first - off;
       p = pb + first;
       if (first == 16) continue;
+      // the special byte is in the registers: a closing quote ends the string
+      // without another load
+      const uint32_t fw = first < 8 ? (first < 4 ? x0 : x1) : (first < 12 ? x2 : x3);
+      if (((fw >> (8 * (first & 3u))) & 0xFFu) == '"') break;
     }
     if (p >= a.len) { err = kErrString; break; }
     const uint32_t c = prim::load1(a.buf + p);

@@ -181,24 +181,83 @@ JSIDX_DEV void emit(uint8_t* out, uint32_t* k, uint32_t v) {
   ++*k;
 }
 
-// The string whose opening quote is at q: its bytes after normalization
-// (escapes decoded, \uXXXX and surrogate pairs as UTF-8) to out (WRITE) and
-// their count to *n.  A byte below 0x20, an unknown escape, a malformed or
-// lone surrogate, or no closing quote is an error (the count then stops
-// there, the same in both modes).
-// No byte of x is a quote, a backslash or below 0x20 (each test is the exact
-// "some byte is zero / below n" bit trick).
-JSIDX_DEV bool plain_word(uint32_t x) {
-  const uint32_t q = x ^ 0x22222222u, b = x ^ 0x5C5C5C5Cu;
-  const uint32_t hit = ((q - 0x01010101u) & ~q) | ((b - 0x01010101u) & ~b) | ((x - 0x20202020u) & ~x);
-  return (hit & 0x80808080u) == 0u;
+constexpr uint32_t kDeferred = 0x80000000u;  // string_run: the budget ran out
+
+// The escape whose backslash is at *p: its bytes (\uXXXX and surrogate pairs
+// as UTF-8) written if `writer`, *p and *k past it.  Returns 0 or kErrString.
+template <bool WRITE>
+JSIDX_DEV uint32_t escape_at(const TapeArgs& a, uint64_t* pp, uint8_t* out, uint32_t* kk, bool writer) {
+  uint64_t p = *pp;
+  uint32_t k = *kk;
+  auto put = [&](uint32_t v) {
+    if constexpr (WRITE) {
+      if (writer) prim::st_byte(out + k, v);
+    }
+    k++;
+  };
+  if (p + 1 >= a.len) return kErrString;
+  const uint32_t e = prim::load1(a.buf + p + 1);
+  p += 2;
+  uint32_t v = 0xFFFFFFFFu;
+  switch (e) {
+    case '"': v = '"'; break;
+    case '\\': v = '\\'; break;
+    case '/': v = '/'; break;
+    case 'b': v = 0x08u; break;
+    case 'f': v = 0x0Cu; break;
+    case 'n': v = 0x0Au; break;
+    case 'r': v = 0x0Du; break;
+    case 't': v = 0x09u; break;
+    default: break;
+  }
+  if (v != 0xFFFFFFFFu) {
+    put(v);
+  } else {
+    if (e != 'u') return kErrString;
+    const int32_t u = hex_quad(a, p);
+    if (u < 0) return kErrString;
+    p += 4;
+    uint32_t cp = (uint32_t)u;
+    if (cp >= 0xDC00u && cp <= 0xDFFFu) return kErrString;  // a low surrogate first
+    if (cp >= 0xD800u && cp <= 0xDBFFu) {
+      if (p + 2 > a.len || prim::load1(a.buf + p) != '\\' || prim::load1(a.buf + p + 1) != 'u') return kErrString;
+      const int32_t lo = hex_quad(a, p + 2);
+      if (lo < 0xDC00 || lo > 0xDFFF) return kErrString;
+      p += 6;
+      cp = 0x10000u + ((cp - 0xD800u) << 10) + ((uint32_t)lo - 0xDC00u);
+    }
+    if (cp < 0x80u) {
+      put(cp);
+    } else if (cp < 0x800u) {
+      put(0xC0u | (cp >> 6));
+      put(0x80u | (cp & 0x3Fu));
+    } else if (cp < 0x10000u) {
+      put(0xE0u | (cp >> 12));
+      put(0x80u | ((cp >> 6) & 0x3Fu));
+      put(0x80u | (cp & 0x3Fu));
+    } else {
+      put(0xF0u | (cp >> 18));
+      put(0x80u | ((cp >> 12) & 0x3Fu));
+      put(0x80u | ((cp >> 6) & 0x3Fu));
+      put(0x80u | (cp & 0x3Fu));
+    }
+  }
+  *pp = p;
+  *kk = k;
+  return 0;
 }
 
+// One thread's part of a string: from byte *p on (inside the string, *k bytes
+// already out) up to the closing quote, with at most `budget` steps over
+// whole plain blocks.  Returns 0 (closed), kErrString (a byte below 0x20, a
+// bad escape, no closing quote; the count then stops there, the same in
+// both modes) or kDeferred (*p and *k say where it stopped).
 template <bool WRITE>
-JSIDX_DEV uint32_t normalize_string(const TapeArgs& a, uint64_t q, uint8_t* out, uint32_t* n) {
-  uint64_t p = q + 1;
-  uint32_t k = 0;
+JSIDX_DEV uint32_t string_run(const TapeArgs& a, uint64_t* pp, uint8_t* out, uint32_t* kk, uint32_t budget) {
+  uint64_t p = *pp;
+  uint32_t k = *kk;
   uint32_t err = 0;
+  uint32_t steps = 0;
   for (;;) {
     // 16 bytes from the aligned word holding p on (four loads in flight): the
     // plain bytes up to the first quote, backslash or control byte are taken
@@ -247,7 +306,10 @@ JSIDX_DEV uint32_t normalize_string(const TapeArgs& a, uint64_t q, uint8_t* out,
       }
       k += first - off;
       p = pb + first;
-      if (first == 16) continue;
+      if (first == 16) {
+        if (++steps >= budget) { err = kDeferred; break; }
+        continue;
+      }
       // the special byte is in the registers: a closing quote ends the string
       // without another load
       const uint32_t fw = first < 8 ? (first < 4 ? x0 : x1) : (first < 12 ? x2 : x3);
@@ -262,55 +324,76 @@ JSIDX_DEV uint32_t normalize_string(const TapeArgs& a, uint64_t q, uint8_t* out,
       p++;
       continue;
     }
-    if (p + 1 >= a.len) { err = kErrString; break; }
-    const uint32_t e = prim::load1(a.buf + p + 1);
-    p += 2;
-    uint32_t v = 0xFFFFFFFFu;
-    switch (e) {
-      case '"': v = '"'; break;
-      case '\\': v = '\\'; break;
-      case '/': v = '/'; break;
-      case 'b': v = 0x08u; break;
-      case 'f': v = 0x0Cu; break;
-      case 'n': v = 0x0Au; break;
-      case 'r': v = 0x0Du; break;
-      case 't': v = 0x09u; break;
-      default: break;
+    err = escape_at<WRITE>(a, &p, out, &k, true);
+    if (err) break;
+  }
+  *pp = p;
+  *kk = k;
+  return err;
+}
+
+// The rest of a string by the whole wave (every lane calls it with the same
+// arguments): 64 bytes per step, one per lane, the first quote, backslash or
+// control byte found by ballot; the plain bytes before it are written by
+// their lanes (coalesced), an escape is decoded by every lane and written by
+// lane 0.  Returns 0 or kErrString; *k as string_run.
+template <bool WRITE>
+JSIDX_DEV uint32_t string_wave(const TapeArgs& a, uint64_t p, uint8_t* out, uint32_t* kk) {
+  const uint32_t lane = prim::lane();
+  uint32_t k = *kk;
+  uint32_t err = 0;
+  for (;;) {
+    const uint64_t pos = p + lane;
+    const uint32_t c = pos < a.len ? prim::load1(a.buf + pos) : 0x100u;
+    const bool special = c >= 0x100u || c == '"' || c == '\\' || c < 0x20u;
+    const uint64_t m = prim::ballot(special);
+    const uint32_t f = m ? (uint32_t)__builtin_ctzll(m) : 64u;
+    if constexpr (WRITE) {
+      if (lane < f) prim::st_byte(out + k + lane, c);
     }
-    if (v != 0xFFFFFFFFu) {
-      emit<WRITE>(out, &k, v);
-      continue;
+    k += f;
+    p += f;
+    if (f == 64) continue;
+    const uint32_t c0 = prim::readlane(c, (int)f);  // the special byte, the same for every lane
+    if (c0 == '"') break;
+    if (c0 >= 0x100u || c0 < 0x20u) { err = kErrString; break; }
+    err = escape_at<WRITE>(a, &p, out, &k, lane == 0);
+    if (err) break;
+  }
+  *kk = k;
+  return err;
+}
+
+// Strings of a wave, each lane's string opening at q (if `has`): its bytes
+// after normalization (escapes decoded, \uXXXX and surrogate pairs as UTF-8)
+// to out (WRITE) and their count to *n.  A byte below 0x20, an unknown
+// escape, a malformed or lone surrogate, or no closing quote is an error (the
+// count then stops there, the same in both modes).  Each lane runs its own
+// string for kStringSteps blocks; the strings that outrun it are then
+// finished one after another by the whole wave.  Every lane of the wave must
+// call this.
+constexpr uint32_t kStringSteps = 2;
+template <bool WRITE>
+JSIDX_DEV uint32_t wave_strings(const TapeArgs& a, bool has, uint64_t q, uint8_t* out, uint32_t* n) {
+  uint64_t p = q + 1;
+  uint32_t k = 0;
+  uint32_t err = has ? string_run<WRITE>(a, &p, out, &k, kStringSteps) : 0u;
+  uint64_t m = prim::ballot(err == kDeferred);
+  while (m) {
+    const int L = __builtin_ctzll(m);
+    m &= m - 1;
+    const uint64_t pL = ((uint64_t)prim::readlane((uint32_t)(p >> 32), L) << 32) | prim::readlane((uint32_t)p, L);
+    uint32_t kL = prim::readlane(k, L);
+    uint8_t* outL = nullptr;
+    if constexpr (WRITE) {
+      const uint64_t o = reinterpret_cast<uintptr_t>(out);
+      outL = reinterpret_cast<uint8_t*>(((uint64_t)prim::readlane((uint32_t)(o >> 32), L) << 32) |
+                                        prim::readlane((uint32_t)o, L));
     }
-    if (e != 'u') { err = kErrString; break; }
-    const int32_t u = hex_quad(a, p);
-    if (u < 0) { err = kErrString; break; }
-    p += 4;
-    uint32_t cp = (uint32_t)u;
-    if (cp >= 0xDC00u && cp <= 0xDFFFu) { err = kErrString; break; }  // a low surrogate first
-    if (cp >= 0xD800u && cp <= 0xDBFFu) {
-      if (p + 2 > a.len || prim::load1(a.buf + p) != '\\' || prim::load1(a.buf + p + 1) != 'u') {
-        err = kErrString;
-        break;
-      }
-      const int32_t lo = hex_quad(a, p + 2);
-      if (lo < 0xDC00 || lo > 0xDFFF) { err = kErrString; break; }
-      p += 6;
-      cp = 0x10000u + ((cp - 0xD800u) << 10) + ((uint32_t)lo - 0xDC00u);
-    }
-    if (cp < 0x80u) {
-      emit<WRITE>(out, &k, cp);
-    } else if (cp < 0x800u) {
-      emit<WRITE>(out, &k, 0xC0u | (cp >> 6));
-      emit<WRITE>(out, &k, 0x80u | (cp & 0x3Fu));
-    } else if (cp < 0x10000u) {
-      emit<WRITE>(out, &k, 0xE0u | (cp >> 12));
-      emit<WRITE>(out, &k, 0x80u | ((cp >> 6) & 0x3Fu));
-      emit<WRITE>(out, &k, 0x80u | (cp & 0x3Fu));
-    } else {
-      emit<WRITE>(out, &k, 0xF0u | (cp >> 18));
-      emit<WRITE>(out, &k, 0x80u | ((cp >> 12) & 0x3Fu));
-      emit<WRITE>(out, &k, 0x80u | ((cp >> 6) & 0x3Fu));
-      emit<WRITE>(out, &k, 0x80u | (cp & 0x3Fu));
+    const uint32_t e = string_wave<WRITE>(a, pL, outL, &kL);
+    if ((int)prim::lane() == L) {
+      k = kL;
+      err = e;
     }
   }
   *n = k;
@@ -723,17 +806,15 @@ JSIDX_DEVFN void tape_count(const TapeArgs& a) {
   TapeScanLds& g = prim::lds_object<TapeScanLds>();
   const uint32_t tid = tape_tid(), c = prim::block();
   uint64_t w = 0, s = 0;
-  for (int k = 0; k < kTapePer; k++) {
+  for (int k = 0; k < kTapePer; k++) {  // every lane runs every step (wave_strings)
     const uint64_t i = (uint64_t)c * kTapeChunk + (uint64_t)k * kTapeThreads + tid;
-    if (i >= a.n) break;
-    const uint64_t pos = prim::load4(reinterpret_cast<const uint8_t*>(a.idx + i));
-    const uint32_t b = byte_at(a, pos);
-    uint32_t sb = 0;
-    if (b == '"') {
-      uint32_t len = 0;
-      (void)normalize_string<false>(a, pos, nullptr, &len);
-      sb = 4 + len;
-    }
+    const bool in = i < a.n;
+    const uint64_t pos = in ? prim::load4(reinterpret_cast<const uint8_t*>(a.idx + i)) : 0u;
+    const uint32_t b = in ? byte_at(a, pos) : 0u;
+    uint32_t len = 0;
+    (void)wave_strings<false>(a, in && b == '"', pos, nullptr, &len);
+    if (!in) continue;
+    const uint32_t sb = b == '"' ? 4 + len : 0u;
     prim::st_out(a.sbytes + i, sb);
     prim::st_byte(a.kb + i, b);
     w += words_of(b);
@@ -908,15 +989,20 @@ JSIDX_DEVFN void tape_strings(const TapeArgs& a) {
   const uint32_t qn = queue_len(a, 1);
   const uint32_t stride = prim::grid() * (uint32_t)kTapeThreads;
   uint32_t err = 0;
-  const uint32_t rounds = (qn + stride - 1) / stride;  // the same for every lane (ballots)
+  const uint32_t rounds = (qn + stride - 1) / stride;  // the same for every lane (wave_strings)
   for (uint32_t r = 0; r < rounds; r++) {
     const uint32_t q = r * stride + prim::block() * (uint32_t)kTapeThreads + tape_tid();
-    if (q < qn) {
+    const bool has = q < qn;
+    uint64_t so = 0, pos = 0;
+    if (has) {
       const uint32_t i = (uint32_t)ld64(a.squeue + 2 * (uint64_t)q);
-      const uint64_t so = ld64(a.squeue + 2 * (uint64_t)q + 1);
-      const uint64_t pos = prim::load4(reinterpret_cast<const uint8_t*>(a.idx + i));
-      uint32_t k = 0;
-      err |= normalize_string<true>(a, pos, a.str + so + 4, &k);
+      so = ld64(a.squeue + 2 * (uint64_t)q + 1);
+      pos = prim::load4(reinterpret_cast<const uint8_t*>(a.idx + i));
+    }
+    uint32_t k = 0;
+    const uint32_t e = wave_strings<true>(a, has, pos, a.str + so + 4, &k);
+    if (has) {
+      err |= e;
       for (int j = 0; j < 4; j++) prim::st_byte(a.str + so + j, (k >> (8 * j)) & 0xFFu);
     }
   }

@@ -148,3 +148,21 @@ def test_number_conversions_against_python_float():
         else:
             assert r == 0 and bits == want, ("fast", t, hex(bits), hex(want))
     assert undecided >= 300
+
+
+def test_long_strings_finished_by_the_wave():
+    """Strings longer than a thread's budget (finished by the whole wave),
+    with escapes, \\u sequences and surrogate pairs at every offset, errors
+    deep inside, and a long string left open at the end."""
+    rng = random.Random(31)
+    pieces = ["a", "bc", " ", "\\\"", "\\\\", "\\n", "\\u00e9", "\\ud83d\\ude00", "é", "日本", "x" * 20, "\\/"]
+    strs = []
+    for _ in range(120):
+        strs.append('"' + "".join(rng.choice(pieces) for _ in range(rng.randrange(1, 120))) + '"')
+    doc = "[" + ",".join(strs) + "]"
+    _check(doc.encode())
+    bad = strs[:]
+    bad[7] = bad[7][:-10] + "\x01" + bad[7][-10:]     # a control byte deep inside
+    bad[11] = bad[11][:-5] + "\\q" + bad[11][-5:]    # an unknown escape
+    _check(("[" + ",".join(bad) + "]").encode())
+    _check(("[" + ",".join(strs[:50]) + ', "' + "y" * 300).encode())  # never closed

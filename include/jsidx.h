@@ -30,6 +30,14 @@
  * both are produced for every document, valid JSON or not.  Flags are sound,
  * not complete: a set bit proves the document is not valid JSON; zero flags
  * do not prove it is (number, string and structure checks belong to stage 2).
+ *
+ * Beyond stage 1 the library offers, on one document's index: minification
+ * (jsidx_minify), the tape's scope links with the structure check
+ * (jsidx_scopes), and the stage-2 tape itself with parsed numbers, normalized
+ * strings and checked literals (jsidx_tape).  The kernels after the index
+ * read only bytes inside the document.  jsidx_set_variant selects variants
+ * of the indexing kernel with one of the paper's stage-1 optimizations turned
+ * off (its ablation, App. B).
  */
 #ifndef JSIDX_H
 #define JSIDX_H

@@ -12,11 +12,11 @@
 //      root words, the sizes, and clears the flags;
 //   3. tape_offsets: each entry's tape index (a scan inside the chunk);
 //   4. tape_write: the words of brackets (with the tape index of their
-//      partner, from the scope links), literals and strings; strings and
-//      numbers are queued, each kind densely, for
+//      partner, from the scope links) and strings; strings, and numbers with
+//      literals, are queued densely for
 //   5. tape_strings: strings decoded into the buffer, and
-//   6. tape_numbers: numbers converted; a double whose rounding the fast
-//      conversion cannot decide is queued again for
+//   6. tape_numbers: literals checked, numbers converted; a double whose
+//      rounding the fast conversion cannot decide is queued again for
 //   7. tape_exact: the exact big-integer conversion.
 // Splitting by kind keeps the lanes of a wave on the same path.
 // Consecutive threads take consecutive entries (coalesced); the scans inside
@@ -921,7 +921,7 @@ JSIDX_DEV uint32_t wave_append(const TapeArgs& a, int q, bool take) {
   return base + prim::mbcnt(m);
 }
 
-// 4. Brackets, literals and the strings' words; strings and numbers queued
+// 4. Brackets and the strings' words; strings, numbers and literals queued
 //    (one thread per entry, consecutive threads on consecutive entries; one
 //    atomic per workgroup and queue).
 JSIDX_DEVFN void tape_write(const TapeArgs& a) {
@@ -934,7 +934,7 @@ JSIDX_DEVFN void tape_write(const TapeArgs& a) {
     const uint32_t j = (uint32_t)k * kTapeThreads + tid;
     const uint32_t b = g.K[j];  // entries past n were staged as ':'
     cs += b == '"';
-    cn += words_of(b) == 2;
+    cn += words_of(b) == 2 || is_lit_start(b);  // numbers and literals share a queue
   }
   uint64_t sex, nex, sall, nall;
   group_scan2(g.sc, tid, cs, cn, &sex, &nex, &sall, &nall);
@@ -963,17 +963,13 @@ JSIDX_DEVFN void tape_write(const TapeArgs& a) {
         link = (b == '{' || b == '[') ? tk + 1 : tk;
       }
       st64(a.tape + t, ((uint64_t)b << 56) | link);
-    } else if (is_lit_start(b)) {
-      st64(a.tape + t, (uint64_t)b << 56);
-      const uint64_t pos = prim::load4(reinterpret_cast<const uint8_t*>(a.idx + i));
-      if (!literal_ok(a, pos, b)) err |= kErrLiteral;
     } else if (b == '"') {
       const uint64_t so = sbase + (uint32_t)(g.S[j] - (uint32_t)sbase);
       st64(a.tape + t, ((uint64_t)'"' << 56) | so);
       st64(a.squeue + 2 * (uint64_t)ps, i);
       st64(a.squeue + 2 * (uint64_t)ps + 1, so);
       ps++;
-    } else if (words_of(b) == 2) {
+    } else if (words_of(b) == 2 || is_lit_start(b)) {
       prim::st_out(a.nqueue + pn, (uint32_t)i);
       pn++;
     }
@@ -1009,12 +1005,18 @@ JSIDX_DEVFN void tape_strings(const TapeArgs& a) {
   or_flags(a, err);
 }
 
-// 6. Numbers: both words; undecided doubles queued for tape_exact.
+// 6. Numbers (both words; undecided doubles queued for tape_exact) and
+//    literals.
 JSIDX_DEV uint32_t number_entry(const TapeArgs& a, uint32_t i, bool* undecided) {
   const uint64_t pos = prim::load4(reinterpret_cast<const uint8_t*>(a.idx + i));
   const uint64_t t = prim::load4(reinterpret_cast<const uint8_t*>(a.toff + i));
   uint64_t* out = a.tape + t;
   *undecided = false;
+  const uint32_t b = byte_at(a, pos);
+  if (is_lit_start(b)) {  // a literal: its tag, and whether it is spelled out
+    st64(out, (uint64_t)b << 56);
+    return literal_ok(a, pos, b) ? 0u : kErrLiteral;
+  }
   const NumText nt = scan_number(a, pos);
   if (!nt.ok) {
     st64(out, (uint64_t)'d' << 56);

@@ -157,7 +157,7 @@ def test_long_strings_finished_by_the_wave():
     rng = random.Random(31)
     pieces = ["a", "bc", " ", "\\\"", "\\\\", "\\n", "\\u00e9", "\\ud83d\\ude00", "é", "日本", "x" * 20, "\\/"]
     strs = []
-    for _ in range(120):
+    for _ in range(70):
         strs.append('"' + "".join(rng.choice(pieces) for _ in range(rng.randrange(1, 120))) + '"')
     doc = "[" + ",".join(strs) + "]"
     _check(doc.encode())

@@ -131,3 +131,23 @@ def test_tape_full_size_c1_and_c2():
     for name, doc in (("C1", synth.gen_c1(1).data), ("C2", synth.gen_c2(2).data)):
         _say(f"case: tape {name} full size {len(doc)}")
         assert_tape_matches(doc, name)
+
+
+def test_tape_flags_on_corrupted_atoms():
+    """One corruption per document, inserted as a new first element of a
+    random array of a generated document: a number with a stray letter, a
+    leading zero or an out-of-range value, a misspelled literal, a string with
+    an unknown escape, a control byte or a lone surrogate.  The flags must
+    equal the oracle's."""
+    from paper_1902_08318_amd import synth
+    rng = random.Random(13)
+    base = synth.gen_c0(5, 1 << 19).data
+    inserts = [b"7x, ", b"012, ", b"99999999999999999999, ", b"1e400, ", b"tru, ", b"nulll, ", b'"a\\qb", ',
+               b'"a\x01b", ', b'"\\ud800x", ']
+    idx, _ = oracle.index(base)
+    starts = [int(p) + 1 for p in idx if base[int(p)] == 0x5B]  # just after a '['
+    for k, ins in enumerate(inserts):
+        p = rng.choice(starts)
+        doc = base[:p] + ins + base[p:]
+        _say(f"case: tape corrupted atom {k}")
+        assert_tape_matches(doc, f"corruption {k}")

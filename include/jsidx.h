@@ -76,6 +76,8 @@ typedef void *jsidx_stream_t;
                                           ']' or a '[' with a '}'             */
 #define JSIDX_ERR_SYNTAX 0x40u          /* jsidx_scopes: the entries' tokens
                                           do not form one JSON value          */
+#define JSIDX_ERR_OFFSETS 0x40000000u  /* not indexed: the batch's offsets
+                                          decrease somewhere (out_n is 0)     */
 #define JSIDX_ERR_CAPACITY 0x80000000u /* not indexed: the batch is larger
                                           than the stream's reserved
                                           workspace (out_n is 0)              */
@@ -113,8 +115,13 @@ int jsidx_build(const uint8_t *buf, uint64_t len, uint32_t *out_idx,
  * reserved size is not indexed: every out_err[d] is set to JSIDX_ERR_CAPACITY
  * and out_n[d] to 0.  Without a reservation the call copies offsets[0] and
  * offsets[ndocs] to the host (synchronising the stream) and grows the stream's
- * workspace if needed.  Offsets that decrease give unspecified results for the
- * affected documents (no fault, no out-of-range access).
+ * workspace if needed.
+ * Offsets are checked on the device before anything is indexed (a first,
+ * small kernel reads all ndocs+1 of them): if offsets[d+1] < offsets[d] for
+ * any d, no document is indexed, no byte of bufs is read and no entry of
+ * out_idx is written, and every out_n[d] is set to 0 and every out_err[d] to
+ * JSIDX_ERR_OFFSETS (the device-side form of rejecting the argument, since
+ * the offsets are not on the host).
  */
 int jsidx_build_batch(const uint8_t *bufs, const uint64_t *offsets,
                       uint32_t ndocs, uint32_t *out_idx, uint32_t *out_n,
@@ -230,18 +237,25 @@ int jsidx_tape(const uint8_t *buf, uint64_t len, const uint32_t *idx,
 
 /*
  * jsidx_reserve -- size the workspace of `stream` for inputs of up to
- * max_total_len bytes in total (single document or batch) and switch batch
- * calls on that stream to the no-synchronisation mode described above.  Call
- * it before capturing a HIP graph so that the captured calls allocate nothing
- * (a later jsidx_build larger than the reservation still grows it).  The
- * workspace (tile descriptors and counters, plus 2 bits per input byte of
- * deferred masks: about a quarter of the input size) is owned by the
- * library, kept per stream until jsidx_release.
+ * max_total_len bytes in total (single document or batch) in up to
+ * max_ndocs documents, and switch batch calls on that stream to the
+ * no-synchronisation mode described above.  Call it before capturing a HIP
+ * graph so that the captured calls allocate nothing (a later jsidx_build
+ * larger than the reservation still grows it).  The workspace (tile
+ * descriptors and counters, plus 2 bits per input byte of deferred masks:
+ * about a quarter of the input size) is owned by the library, kept per stream
+ * until jsidx_release.  Its size depends on the bytes only: per-document
+ * state lives in the caller's out_n and out_err, and documents are found
+ * from the offsets in place, so max_ndocs is accepted and not used (0 is
+ * allowed).  Returns JSIDX_E_NOWORKSPACE if the allocation fails; the
+ * stream then has no workspace and the next call allocates one.
  */
-int jsidx_reserve(uint64_t max_total_len, jsidx_stream_t stream);
+int jsidx_reserve(uint64_t max_total_len, uint32_t max_ndocs,
+                  jsidx_stream_t stream);
 
-/* Bytes of workspace needed for max_total_len input bytes. */
-size_t jsidx_workspace_bytes(uint64_t max_total_len);
+/* Bytes of workspace needed for total_len input bytes in ndocs documents
+ * (ndocs does not change the size; see jsidx_reserve). */
+size_t jsidx_workspace_bytes(uint64_t total_len, uint32_t ndocs);
 
 /* Free the workspace of `stream` (synchronises the stream first). */
 int jsidx_release(jsidx_stream_t stream);

@@ -20,6 +20,7 @@ ERR_SYNTAX = 0x40
 ERR_NUMBER = 0x100
 ERR_STRING = 0x200
 ERR_LITERAL = 0x400
+ERR_OFFSETS = 0x40000000
 ERR_CAPACITY = 0x80000000
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -34,8 +35,8 @@ SIGNATURES = {
     "jsidx_minify": ([_VP, ctypes.c_uint64, _VP, _VP, _VP, _VP], ctypes.c_int),
     "jsidx_minify_batch": ([_VP, _VP, ctypes.c_uint32, _VP, _VP, _VP, _VP], ctypes.c_int),
     "jsidx_scopes": ([_VP, ctypes.c_uint64, _VP, ctypes.c_uint32, _VP, _VP, _VP], ctypes.c_int),
-    "jsidx_reserve": ([ctypes.c_uint64, _VP], ctypes.c_int),
-    "jsidx_workspace_bytes": ([ctypes.c_uint64], ctypes.c_size_t),
+    "jsidx_reserve": ([ctypes.c_uint64, ctypes.c_uint32, _VP], ctypes.c_int),
+    "jsidx_workspace_bytes": ([ctypes.c_uint64, ctypes.c_uint32], ctypes.c_size_t),
     "jsidx_release": ([_VP], ctypes.c_int),
     "jsidx_stream_diag": ([_VP, ctypes.POINTER(ctypes.c_uint32)], ctypes.c_int),
     "jsidx_status_string": ([ctypes.c_int], ctypes.c_char_p),
@@ -128,8 +129,15 @@ def scopes(buf, idx, out_match, out_err, stream=None, n=None, length=None):
     _check(lib().jsidx_scopes(_ptr(buf), ln, _ptr(idx), n, _ptr(out_match), _ptr(out_err), _stream(stream)))
 
 
-def reserve(max_total_len: int, stream=None):
-    _check(lib().jsidx_reserve(int(max_total_len), _stream(stream)))
+def reserve(max_total_len: int, stream=None, max_ndocs: int = 0):
+    """jsidx_reserve: the stream's workspace for up to max_total_len bytes in
+    up to max_ndocs documents."""
+    _check(lib().jsidx_reserve(int(max_total_len), int(max_ndocs), _stream(stream)))
+
+
+def workspace_bytes(total_len: int, ndocs: int = 0) -> int:
+    """jsidx_workspace_bytes."""
+    return int(lib().jsidx_workspace_bytes(int(total_len), int(ndocs)))
 
 
 def release(stream=None):

@@ -23,6 +23,7 @@
 #include <vector>
 
 #include "jsidx.h"
+#include "jsidx_host.h"
 #include "jsidx_kernel.h"
 
 namespace jsidx {
@@ -43,16 +44,15 @@ minify_kernel(Args a) {
   index_tiles<true>(a);
 }
 
+// Checks a batch's offsets before its indexing launch (see offsets_check).
+constexpr int kCheckThreads = 256;
+__global__ void __launch_bounds__(kCheckThreads) offsets_check_kernel(const uint64_t* offsets, uint32_t ndocs,
+                                                                     Workspace* ws) {
+  offsets_check(offsets, ndocs, ws, kCheckThreads);
+}
+
 // ---------------------------------------------------------------------------
 // host side
-struct StreamWs {
-  int device;
-  hipStream_t stream;
-  Workspace* ws;
-  uint64_t cap_tiles;  // in largest tiles
-  bool reserved;  // sized by jsidx_reserve: batch calls trust it and never sync
-};
-
 std::mutex g_mu;
 std::vector<StreamWs> g_ws;
 uint64_t g_rows_tab[4];  // tile rows by size class (jsidx_set_tile_rows), 0 = default
@@ -97,32 +97,46 @@ int slots_for_device(int dev, int kernel) {
   return slots;
 }
 
+// A zeroed device allocation for a workspace of `tiles` largest tiles, or
+// nullptr (nothing left allocated) if any step fails.
+Workspace* alloc_ws(hipStream_t stream, uint64_t tiles) {
+  void* p = nullptr;
+  const size_t bytes = ws_bytes_for_tiles(tiles);
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();  // not left behind for the next launch check
+    return nullptr;
+  }
+  if (hipMemsetAsync(p, 0, bytes, stream) != hipSuccess || hipStreamSynchronize(stream) != hipSuccess) {
+    (void)hipFree(p);
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return (Workspace*)p;
+}
+
 // Find or grow the workspace of (current device, stream).  Caller holds g_mu.
+// A failed growth leaves the stream without a workspace (its entry is
+// removed), so no later launch can see a stale capacity with no memory.
 int get_ws(hipStream_t stream, uint64_t need_tiles, bool grow, StreamWs** out) {
   int dev = 0;
+  *out = nullptr;
   if (hipGetDevice(&dev) != hipSuccess) return JSIDX_E_HIP;
-  for (auto& e : g_ws) {
+  bool reserved = false;
+  for (size_t i = 0; i < g_ws.size(); i++) {
+    StreamWs& e = g_ws[i];
     if (e.device == dev && e.stream == stream) {
       if (e.cap_tiles >= need_tiles || !grow) { *out = &e; return JSIDX_OK; }
       if (hipStreamSynchronize(stream) != hipSuccess) return JSIDX_E_HIP;
+      reserved = e.reserved;
       (void)hipFree(e.ws);
-      e.ws = nullptr;
-      void* p = nullptr;
-      if (hipMalloc(&p, ws_bytes_for_tiles(need_tiles)) != hipSuccess) return JSIDX_E_NOWORKSPACE;
-      if (hipMemsetAsync(p, 0, ws_bytes_for_tiles(need_tiles), stream) != hipSuccess) return JSIDX_E_HIP;
-      if (hipStreamSynchronize(stream) != hipSuccess) return JSIDX_E_HIP;
-      e.ws = (Workspace*)p;
-      e.cap_tiles = need_tiles;
-      *out = &e;
-      return JSIDX_OK;
+      g_ws.erase(g_ws.begin() + (long)i);
+      break;
     }
   }
-  if (!grow) { *out = nullptr; return JSIDX_OK; }
-  void* p = nullptr;
-  if (hipMalloc(&p, ws_bytes_for_tiles(need_tiles)) != hipSuccess) return JSIDX_E_NOWORKSPACE;
-  if (hipMemsetAsync(p, 0, ws_bytes_for_tiles(need_tiles), stream) != hipSuccess) return JSIDX_E_HIP;
-  if (hipStreamSynchronize(stream) != hipSuccess) return JSIDX_E_HIP;
-  g_ws.push_back(StreamWs{dev, stream, (Workspace*)p, need_tiles, false});
+  if (!grow) return JSIDX_OK;
+  Workspace* p = alloc_ws(stream, need_tiles);
+  if (!p) return JSIDX_E_NOWORKSPACE;
+  g_ws.push_back(StreamWs{dev, stream, p, need_tiles, reserved});
   *out = &g_ws.back();
   return JSIDX_OK;
 }
@@ -134,6 +148,7 @@ int get_ws(hipStream_t stream, uint64_t need_tiles, bool grow, StreamWs** out) {
 // the kernel picks the tile size.
 int launch(Args& a, hipStream_t stream, const StreamWs& e, int64_t span, bool minify) {
   int dev = 0;
+  if (!e.ws) return JSIDX_E_NOWORKSPACE;
   if (hipGetDevice(&dev) != hipSuccess) return JSIDX_E_HIP;
   const int kernel = minify ? kMinifySlot : slot_of_variant(g_variant);
   const uint64_t slots = (uint64_t)slots_for_device(dev, kernel);
@@ -152,6 +167,7 @@ int launch(Args& a, hipStream_t stream, const StreamWs& e, int64_t span, bool mi
   uint64_t grid = groups < slots ? groups : slots;
   if (grid < 1) grid = 1;
   a.fill_waves = (uint32_t)(grid * kWaves);
+  (void)hipGetLastError();  // the check after the launch sees only the launch
   switch (kernel) {
     case 0: hipLaunchKernelGGL(index_kernel<0>, dim3((uint32_t)grid), dim3(kGroupThreads), 0, stream, a); break;
     case 1:
@@ -209,6 +225,15 @@ int build_many(const uint8_t* bufs, const uint64_t* offsets, uint32_t ndocs, uin
     rc = get_ws(stream, tiles_for(total), true, &e);
     if (rc) return rc;
   }
+  if (!e || !e->ws) return JSIDX_E_NOWORKSPACE;
+  // the offsets are checked first; the indexing launch reads the verdict
+  {
+    uint64_t g = ((uint64_t)ndocs + kCheckThreads - 1) / kCheckThreads;
+    if (g > 1024) g = 1024;
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(offsets_check_kernel, dim3((uint32_t)g), dim3(kCheckThreads), 0, stream, offsets, ndocs, e->ws);
+    if (hipGetLastError() != hipSuccess) return JSIDX_E_HIP;
+  }
   Args a;
   a.base = bufs;
   a.offsets = offsets;
@@ -245,7 +270,8 @@ int jsidx_minify_batch(const uint8_t* bufs, const uint64_t* offsets, uint32_t nd
                     true);
 }
 
-int jsidx_reserve(uint64_t max_total_len, jsidx_stream_t stream_) {
+int jsidx_reserve(uint64_t max_total_len, uint32_t max_ndocs, jsidx_stream_t stream_) {
+  (void)max_ndocs;  // the workspace is sized by bytes only
   std::lock_guard<std::mutex> lk(g_mu);
   StreamWs* e = nullptr;
   int rc = get_ws((hipStream_t)stream_, tiles_for(max_total_len), true, &e);
@@ -253,7 +279,10 @@ int jsidx_reserve(uint64_t max_total_len, jsidx_stream_t stream_) {
   return rc;
 }
 
-size_t jsidx_workspace_bytes(uint64_t max_total_len) { return ws_bytes_for_tiles(tiles_for(max_total_len)); }
+size_t jsidx_workspace_bytes(uint64_t total_len, uint32_t ndocs) {
+  (void)ndocs;
+  return ws_bytes_for_tiles(tiles_for(total_len));
+}
 
 int jsidx_release(jsidx_stream_t stream_) {
   hipStream_t stream = (hipStream_t)stream_;

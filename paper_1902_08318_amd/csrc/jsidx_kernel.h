@@ -108,6 +108,9 @@ struct Workspace {
   uint32_t done;    // workgroups that have left the tile loop
   uint32_t epoch;   // launch counter (tags descriptors)
   uint32_t diag;    // sticky: 1 = a look-back wait gave up (never expected)
+  uint32_t bad;     // set by offsets_check when a batch's offsets decrease;
+                    // cleared by the last workgroup of the launch after it
+  uint32_t pad;
   uint64_t desc[1];  // one per tile
 };
 
@@ -1509,12 +1512,17 @@ JSIDX_DEVFN void index_tiles(const Args& a) {
   const int64_t tb = (int64_t)rows * kRowBytes;
   const int64_t ntiles = span > 0 ? (span + tb - 1) / tb : 1;
 
-  if ((uint64_t)ntiles > a.cap_tiles || (uint64_t)ntiles * rows > a.cap_rows) {
-    // Not indexed: flag every document.
+  // offsets_check ran before this launch on the same stream (batches only)
+  uint32_t bad = 0;
+  if (a.offsets && lane == 0) bad = prim::ld_agent32(&ws->bad);
+  bad = prim::readlane(bad, 0);
+  if (bad || (uint64_t)ntiles > a.cap_tiles || (uint64_t)ntiles * rows > a.cap_rows) {
+    // Not indexed: flag every document.  Nothing of the input is read.
+    const uint32_t flag = bad ? JSIDX_ERR_OFFSETS : JSIDX_ERR_CAPACITY;
     for (int64_t d = ((int64_t)prim::block() * kWaves + wv) * kThreads + lane; d < a.ndocs;
          d += (int64_t)prim::grid() * kGroupThreads) {
       prim::st_out(a.out_n + d, 0u);
-      prim::st_out(a.out_err + d, JSIDX_ERR_CAPACITY);
+      prim::st_out(a.out_err + d, flag);
     }
   } else {
     // A ticket is tt consecutive tiles.  A workgroup takes its
@@ -1569,9 +1577,20 @@ JSIDX_DEVFN void index_tiles(const Args& a) {
     if (wv == 0 && lane == 0) {
       prim::st_agent32(&ws->ticket, 0u);
       prim::st_agent32(&ws->done, 0u);
+      prim::st_agent32(&ws->bad, 0u);
       prim::st_agent32(&ws->epoch, epoch + 1u);
     }
   }
+}
+
+// Before a batch launch: marks the workspace if offsets[d+1] < offsets[d] for
+// some d (the indexing launch then flags every document instead of reading
+// the input).  A grid-stride pass over the offsets.
+JSIDX_DEVFN void offsets_check(const uint64_t* offsets, uint32_t ndocs, Workspace* ws, uint32_t threads) {
+  uint32_t dec = 0;
+  for (uint64_t d = (uint64_t)prim::block() * threads + prim::tid(); d < ndocs; d += (uint64_t)prim::grid() * threads)
+    dec |= prim::load8(offsets + d + 1) < prim::load8(offsets + d) ? 1u : 0u;
+  if (prim::ballot(dec != 0u) != 0ull && prim::lane() == 0) prim::or_agent32(&ws->bad, 1u);
 }
 
 }  // namespace jsidx

@@ -56,6 +56,28 @@ long emu_run(const uint8_t* base, const uint64_t* offsets, uint64_t len, uint32_
   a.cap_tiles = desc_slots(cap_tiles);
   a.cap_rows = cap_tiles * (uint64_t)kRows;
 
+  // a batch's offsets are checked first, as the library launches it
+  if (offsets) {
+    constexpr int kCheck = 128;
+    std::vector<prim::GroupCtx*> cg;
+    for (int b = 0; b < 2; b++) cg.push_back(new prim::GroupCtx(kCheck));
+    std::vector<std::thread> ct;
+    for (int b = 0; b < 2; b++) {
+      for (uint32_t t = 0; t < (uint32_t)kCheck; t++) {
+        ct.emplace_back([&, b, t] {
+          prim::tctx.tid = t;
+          prim::tctx.block = (uint32_t)b;
+          prim::tctx.grid = 2;
+          prim::tctx.g = cg[(size_t)b];
+          prim::tctx.env = &env;
+          offsets_check(offsets, ndocs, (Workspace*)ws_mem, kCheck);
+        });
+      }
+    }
+    for (auto& x : ct) x.join();
+    for (auto* g : cg) delete g;
+  }
+
   // nblocks counts waves; they run as whole workgroups of kWaves waves
   const int ngroups = (nblocks + kWaves - 1) / kWaves;
   a.rows = rows;

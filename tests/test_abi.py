@@ -44,8 +44,10 @@ def test_invalid_arguments_are_rejected_without_launch():
     assert lib.jsidx_build_batch(one, None, 3, one, one, one, None) == -1
     assert lib.jsidx_stream_diag(None, None) == -1
     assert lib.jsidx_status_string(-1) == b"invalid argument"
-    assert lib.jsidx_workspace_bytes(0) > 0
-    assert lib.jsidx_workspace_bytes(1 << 30) > lib.jsidx_workspace_bytes(1 << 20)
+    assert lib.jsidx_workspace_bytes(0, 0) > 0
+    assert lib.jsidx_workspace_bytes(1 << 30, 1) > lib.jsidx_workspace_bytes(1 << 20, 1)
+    # the size depends on the bytes only (documents are found from the offsets in place)
+    assert lib.jsidx_workspace_bytes(1 << 24, 1) == lib.jsidx_workspace_bytes(1 << 24, 100000)
 
 
 def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):

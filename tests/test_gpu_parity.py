@@ -191,10 +191,18 @@ def test_repeated_launches_reuse_workspace():
 
 
 def test_generated_c1_c2_full_size():
+    """Full-size C1 and C2 against the oracle, and their index sizes against
+    the generators' own count of structural characters, strings and atoms."""
     from paper_1902_08318_amd import synth
     for name, doc in (("C1", synth.gen_c1(1)), ("C2", synth.gen_c2(2))):
         _say(f"case: {name} full size {len(doc.data)}")
         assert_single_matches(doc.data, 0, name)
+        _, n, err = gpu_index_single(doc.data)
+        assert n == doc.expected_index and err == 0
+    for seed in range(3):
+        doc = synth.gen_c0(seed, 1 << 20)
+        _, n, err = gpu_index_single(doc.data)
+        assert n == doc.expected_index and err == 0
 
 
 def test_generated_c3_full_batch():
@@ -286,4 +294,117 @@ def test_ablation_variants(variant):
         assert_batch_matches(data, offs, 5, f"{variant} batch")
     finally:
         jx.set_variant(0)
+    assert jx.diag() == 0
+
+
+# ---- the table of well-formed UTF-8 sequences, invalid side included -------
+import utf8_cases  # noqa: E402
+
+
+@pytest.mark.parametrize("length", [1, 2, 3])
+def test_utf8_every_short_string(length):
+    """Every 1-, 2- and 3-byte string, one document each, in one batch: the
+    flags (and indices) of all of them against the oracle (Sec. 3.1.5)."""
+    data, offs = utf8_cases.equal_length_batch(utf8_cases.all_strings(length), length)
+    _say(f"case: every {length}-byte string, {offs.size - 1} documents")
+    assert_batch_matches(data, offs, 0, f"every {length}-byte string")
+
+
+def test_utf8_four_byte_boundary_alphabet():
+    data, offs = utf8_cases.boundary_four_byte_batch()
+    _say(f"case: four-byte boundary alphabet, {offs.size - 1} documents")
+    assert_batch_matches(data, offs, 0, "four-byte boundary alphabet")
+
+
+def test_utf8_lead_and_second_bytes_at_segment_and_row_edges():
+    """Every lead byte C0..FF with second bytes on each range bound (80 8F 90
+    9F A0 BF, a non-continuation, a lead), completed to the announced length
+    or cut short at the document's end, starting across 32-byte segment edges
+    and 2 KiB row (and tile) edges: invalid pairs E0 80-9F, ED A0-BF,
+    F0 80-8F, F4 90-BF, leads C0, C1 and F5-FF, and their valid neighbours."""
+    data, offs = utf8_cases.placed_batch(utf8_cases.lead_sequences())
+    _say(f"case: placed lead sequences, {offs.size - 1} documents, {len(data)} bytes")
+    _, _, oe = oracle.index_batch(np.frombuffer(data, dtype=np.uint8), offs)
+    bad = (oe & oracle.ERR_UTF8) != 0
+    assert 0 < int(bad.sum()) < bad.size  # both sides of the table are present
+    assert_batch_matches(data, offs, 0, "placed lead sequences")
+
+
+def test_utf8_sequences_across_tile_edges_single_documents():
+    """Single documents with one lead sequence each, starting 3 bytes before
+    to 3 bytes after a 32 KiB tile edge (and the same 64 KiB in)."""
+    seqs = utf8_cases.lead_sequences(seconds=(0x80, 0x9F, 0xA0, 0xBF, 0x8F, 0x90))
+    pick = [s for s in seqs if s[0] in (0xC0, 0xC1, 0xC2, 0xE0, 0xED, 0xEF, 0xF0, 0xF4, 0xF5, 0xFF)]
+    _say(f"case: lead sequences at tile edges, {len(pick)} sequences")
+    for s in pick:
+        for edge in (32768, 65536):
+            for delta in (-3, -2, -1, 0, 1, 2, 3):
+                p = edge + delta
+                d = b'["' + b"x" * (p - 2) + s + b'", 1]'
+                assert_single_matches(d, 0, f"seq {s.hex()} at {p}")
+
+
+def test_lookback_over_more_than_64_blocks():
+    """With 2-row tiles (4 KiB), full-size C1 spans 65,536 tiles in 256
+    look-back blocks and a 90 MB batch about 88: every walk over more than the
+    64 blocks one look-back window holds runs on the device."""
+    import paper_1902_08318_amd as jx
+    from paper_1902_08318_amd import synth
+    jx.set_tile_rows([2] * 64)
+    try:
+        doc = synth.gen_c1(1)
+        _say(f"case: C1 at 2-row tiles, {len(doc.data)} bytes")
+        assert jx.tile_rows(len(doc.data)) == 2
+        assert_single_matches(doc.data, 0, "C1 2-row tiles")
+        data, offs, _ = synth.gen_c3(3, ndocs=30000)
+        _say(f"case: batch at 2-row tiles, {offs.size - 1} docs, {int(offs[-1])} bytes")
+        assert int(offs[-1]) > 64 * 256 * 4096
+        assert_batch_matches(data, offs, 0, "batch 2-row tiles")
+    finally:
+        jx.set_tile_rows([])
+    assert jx.diag() == 0
+
+
+@pytest.mark.parametrize("offs", [[100, 50, 60000, 70000], [0, 5000, 3000, 70000],
+                                  [0, 1000, 500, 2000, 1500, 70000], [0, 70000, 0]])
+def test_decreasing_offsets_flag_every_document(offs):
+    """Offsets that decrease anywhere: the batch is not indexed, every
+    document gets out_n = 0 and JSIDX_ERR_OFFSETS, no index entry is written;
+    a good batch on the same stream afterwards is indexed normally."""
+    import paper_1902_08318_amd as jx
+    rng = np.random.default_rng(2)
+    data = _soup(rng, 70000)
+    _say(f"case: decreasing offsets {offs}")
+    o = np.array(offs, dtype=np.uint64)
+    gi, gn, ge = gpu_index_batch(data, o)
+    assert np.all(gn == 0) and np.all(ge == jx.ERR_OFFSETS)
+    assert np.all(gi == 0xFFFFFFFF)
+    good = np.array([0, 1000, 5000, 70000], dtype=np.uint64)
+    assert_batch_matches(data, good, 0, "good batch after a bad one")
+
+
+def test_failed_workspace_growth_leaves_a_working_stream():
+    """A reservation the device cannot hold fails with JSIDX_E_NOWORKSPACE and
+    leaves the stream without a workspace (no stale capacity); the next calls
+    on that stream allocate again and index correctly."""
+    import torch
+    import paper_1902_08318_amd as jx
+    _say("case: failed workspace growth")
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        jx.reserve(1 << 20, s)
+        with pytest.raises(jx.JsidxError):
+            jx.reserve(1 << 45, s)  # petabytes of workspace
+        d = b'{"a":[1,2,"x\\"y"],"b":null}' * 100
+        buf = torch.frombuffer(bytearray(d), dtype=torch.uint8).to("cuda:0")
+        pos, n, err = jx.index(buf, s)
+        oi, oe = oracle.index(d)
+        assert n == len(oi) and err == oe
+        assert np.array_equal(pos.cpu().numpy().view(np.uint32), oi)
+        offs = torch.tensor([0, 50, len(d)], dtype=torch.int64, device="cuda:0")
+        out, nn, ee = jx.index_batch(buf, offs, s)
+        s.synchronize()
+        on = oracle.index_batch(np.frombuffer(d, dtype=np.uint8), np.array([0, 50, len(d)], dtype=np.uint64))[1]
+        assert np.array_equal(nn.cpu().numpy().view(np.uint32), on)
+        jx.release(s)
     assert jx.diag() == 0

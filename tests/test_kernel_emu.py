@@ -184,3 +184,39 @@ def test_minify(rows):
     for d in range(len(docs)):
         a = int(offs[d])
         assert out[a:a + n[d]].tobytes() == om[a:a + on[d]].tobytes(), d
+
+
+def test_utf8_invalid_side_of_the_table():
+    """Lead bytes C0..FF with second bytes on each range bound, completed or
+    cut short, starting across segment and row edges, as one batch; and the
+    four-byte boundary alphabet."""
+    import utf8_cases
+    seqs = [s for s in utf8_cases.lead_sequences()
+            if s[0] in (0xC0, 0xC1, 0xC2, 0xDF, 0xE0, 0xE1, 0xED, 0xEF, 0xF0, 0xF1, 0xF4, 0xF5, 0xFF)]
+    data, offs = utf8_cases.placed_batch(seqs, residues=(30, 31, 33, 2046, 2047, 0, 1))
+    idx, n, err, viol = emu.run(data, offsets=offs, nblocks=16, misalign=0)
+    oi, on, oe = oracle.index_batch(np.frombuffer(data, dtype=np.uint8), offs)
+    assert viol == 0
+    assert 0 < int(((oe & oracle.ERR_UTF8) != 0).sum()) < oe.size
+    assert np.array_equal(n, on) and np.array_equal(err, oe)
+    data, offs = utf8_cases.boundary_four_byte_batch()
+    idx, n, err, viol = emu.run(data.tobytes(), offsets=offs, nblocks=16, misalign=0)
+    oi, on, oe = oracle.index_batch(data, offs)
+    assert viol == 0 and np.array_equal(n, on) and np.array_equal(err, oe)
+
+
+@pytest.mark.parametrize("offs", [[100, 50, 60000, 70000], [0, 5000, 3000, 70000],
+                                  [0, 1000, 500, 2000, 1500, 70000], [0, 70000, 0]])
+def test_decreasing_offsets_flag_every_document(offs):
+    """A batch whose offsets decrease anywhere is not indexed: no byte of it is
+    read, no index entry is written, and every document gets out_n = 0 and
+    JSIDX_ERR_OFFSETS."""
+    rng = np.random.default_rng(1)
+    data = _soup(rng, 70000)
+    offs = np.array(offs, dtype=np.uint64)
+    # the input may only be read inside [offsets[0], offsets[-1]): an empty
+    # readable range catches any read
+    idx, n, err, viol = emu.run(data, offsets=offs, nblocks=8, misalign=0)
+    assert viol == 0
+    assert np.all(n == 0) and np.all(err == 0x40000000)
+    assert np.all(idx == 0xDEADBEEF)

@@ -319,3 +319,20 @@ def test_valid_json_has_no_flags():
             idx, err = oracle.index(doc)
             assert err == 0, doc
             assert len(idx) > 0
+
+
+# ------------------------------------------- the generators' closed form
+@pytest.mark.parametrize("name,seed,target", [("c0", 0, 1 << 20), ("c0", 3, 300_000), ("c1", 1, 4 << 20),
+                                              ("c1", 5, 1 << 20), ("c2", 2, 4 << 20)])
+def test_generator_closed_form_equals_oracle_count(name, seed, target):
+    """A valid document's index holds one entry per structural character, per
+    string (its opening quote, keys included) and per atom (number, true,
+    false, null).  The generators count these while they emit the document,
+    without the oracle; the oracle's index size must equal that count, and the
+    document carries no flag."""
+    from paper_1902_08318_amd import synth
+    gen = {"c0": synth.gen_c0, "c1": synth.gen_c1, "c2": synth.gen_c2}[name]
+    doc = gen(seed, target) if name == "c0" else gen(seed, target, pool=32)
+    idx, err = oracle.index(doc.data)
+    assert err == 0
+    assert len(idx) == doc.expected_index

@@ -128,6 +128,25 @@ int jsidx_build_batch(const uint8_t *bufs, const uint64_t *offsets,
                       uint32_t *out_err, jsidx_stream_t stream);
 
 /*
+ * jsidx_build_noalloc -- jsidx_build for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, results and stream behaviour as
+ * jsidx_build, for documents of at most JSIDX_NOALLOC_MAX_LEN bytes (larger
+ * ones return JSIDX_E_TOO_LARGE and launch nothing).  The call never
+ * allocates or frees memory: its workspace is a fixed device array inside the
+ * library (about 64.5 MiB on every device the library runs on, held until the
+ * process ends), zeroed by a small kernel on `stream` the first time the
+ * device is used.  Every call on one device shares that array, so calls that
+ * overlap in time on one device (on different streams, or from several host
+ * threads without ordering) race and give wrong results; calls ordered on one
+ * stream are safe.  It shares its kernels with jsidx_build.
+ */
+#define JSIDX_NOALLOC_MAX_LEN 268435440ull /* 256 MiB - 16 */
+int jsidx_build_noalloc(const uint8_t *buf, uint64_t len, uint32_t *out_idx,
+                        uint32_t *out_n, uint32_t *out_err,
+                        jsidx_stream_t stream);
+
+/*
  * jsidx_minify -- minify one document: drop the white-space characters
  * (TAB LF CR SPACE) outside strings and keep every other byte in order, the
  * paper's minified form of a document (its table of dataset sizes; its

@@ -32,6 +32,7 @@ _VP = ctypes.c_void_p
 SIGNATURES = {
     "jsidx_build": ([_VP, ctypes.c_uint64, _VP, _VP, _VP, _VP], ctypes.c_int),
     "jsidx_build_batch": ([_VP, _VP, ctypes.c_uint32, _VP, _VP, _VP, _VP], ctypes.c_int),
+    "jsidx_build_noalloc": ([_VP, ctypes.c_uint64, _VP, _VP, _VP, _VP], ctypes.c_int),
     "jsidx_minify": ([_VP, ctypes.c_uint64, _VP, _VP, _VP, _VP], ctypes.c_int),
     "jsidx_minify_batch": ([_VP, _VP, ctypes.c_uint32, _VP, _VP, _VP, _VP], ctypes.c_int),
     "jsidx_scopes": ([_VP, ctypes.c_uint64, _VP, ctypes.c_uint32, _VP, _VP, _VP], ctypes.c_int),
@@ -99,6 +100,15 @@ def build(buf, out_idx, out_n, out_err, stream=None, length=None):
     """jsidx_build on device tensors (buf: uint8; outputs: int32/uint32)."""
     n = buf.numel() if length is None else int(length)
     _check(lib().jsidx_build(_ptr(buf), n, _ptr(out_idx), _ptr(out_n), _ptr(out_err), _stream(stream)))
+
+
+def build_noalloc(buf, out_idx, out_n, out_err, stream=None, length=None):
+    """jsidx_build_noalloc on device tensors (same arguments as build)."""
+    n = buf.numel() if length is None else int(length)
+    _check(lib().jsidx_build_noalloc(_ptr(buf), n, _ptr(out_idx), _ptr(out_n), _ptr(out_err), _stream(stream)))
+
+
+NOALLOC_MAX_LEN = 268435440
 
 
 def build_batch(bufs, offsets, out_idx, out_n, out_err, stream=None):

@@ -1,6 +1,6 @@
 """Build step for the HIP library (gfx950).
 
-Compiles csrc/jsidx.hip, csrc/jsidx_scopes.hip and csrc/jsidx_tape.hip with hipcc into libjsidx.so
+Compiles csrc/jsidx.hip, csrc/jsidx_noalloc.hip, csrc/jsidx_scopes.hip and csrc/jsidx_tape.hip with hipcc into libjsidx.so
 next to this file.  The
 build runs on a machine without a GPU: hipcc cross-compiles for gfx950.
 """
@@ -26,8 +26,8 @@ HIP_FLAGS = [
 def build_library(verbose: bool = False) -> str:
     """Compile the HIP library; returns the path of libjsidx.so."""
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, *HIP_FLAGS, "-o", tmp, os.path.join(CSRC, "jsidx.hip"), os.path.join(CSRC, "jsidx_scopes.hip"),
-           os.path.join(CSRC, "jsidx_tape.hip")]
+    cmd = [HIPCC, *HIP_FLAGS, "-o", tmp, os.path.join(CSRC, "jsidx.hip"), os.path.join(CSRC, "jsidx_noalloc.hip"),
+           os.path.join(CSRC, "jsidx_scopes.hip"), os.path.join(CSRC, "jsidx_tape.hip")]
     res = subprocess.run(cmd, capture_output=True, text=True)
     noise = "'-packed-fp32-ops' is not a recognized feature"
     msgs = [l for l in (res.stdout + res.stderr).splitlines() if noise not in l]

@@ -23,6 +23,7 @@
 #include <vector>
 
 #include "jsidx.h"
+#include "jsidx_doc.h"
 #include "jsidx_host.h"
 #include "jsidx_kernel.h"
 
@@ -44,6 +45,18 @@ minify_kernel(Args a) {
   index_tiles<true>(a);
 }
 
+// One document (jsidx_build): the kernel of jsidx_doc.h.
+// Waves per SIMD of the one-document kernel (its LDS allows one workgroup of
+// kDocWaves waves per compute unit).
+#ifndef JSIDX_DOC_WAVES_PER_EU
+#define JSIDX_DOC_WAVES_PER_EU (JSIDX_DOC_WAVES / 4)
+#endif
+template <int VAR>
+__global__ void __launch_bounds__(kDocThreads) __attribute__((amdgpu_waves_per_eu(JSIDX_DOC_WAVES_PER_EU)))
+doc_kernel(DocArgs a) {
+  doc_tiles<VAR>(a);
+}
+
 // Checks a batch's offsets before its indexing launch (see offsets_check).
 constexpr int kCheckThreads = 256;
 __global__ void __launch_bounds__(kCheckThreads) offsets_check_kernel(const uint64_t* offsets, uint32_t ndocs,
@@ -57,19 +70,26 @@ std::mutex g_mu;
 std::vector<StreamWs> g_ws;
 uint64_t g_rows_tab[4];  // tile rows by size class (jsidx_set_tile_rows), 0 = default
 uint32_t g_variant = 0;  // indexing kernel variant (jsidx_set_variant)
-// Kernels by slot: the index kernel's variants 0, naive classification, loop
-// prefix XOR, direct flatten; then the minify kernel.
-constexpr int kKernels = 5;
+// Kernels by slot: the batch index kernel's variants 0, naive
+// classification, loop prefix XOR, direct flatten; the minify kernel; then the
+// one-document kernel's variants in the same order.
+constexpr int kKernels = 9;
 constexpr int kMinifySlot = 4;
+constexpr int kDocSlot = 5;
 const void* kernel_at(int k) {
   switch (k) {
     case 0: return reinterpret_cast<const void*>(&index_kernel<0>);
     case 1: return reinterpret_cast<const void*>(&index_kernel<kVarNaiveClassify>);
     case 2: return reinterpret_cast<const void*>(&index_kernel<kVarXorLoop>);
     case 3: return reinterpret_cast<const void*>(&index_kernel<kVarDirectFlatten>);
-    default: return reinterpret_cast<const void*>(&minify_kernel);
+    case 4: return reinterpret_cast<const void*>(&minify_kernel);
+    case 5: return reinterpret_cast<const void*>(&doc_kernel<0>);
+    case 6: return reinterpret_cast<const void*>(&doc_kernel<kVarNaiveClassify>);
+    case 7: return reinterpret_cast<const void*>(&doc_kernel<kVarXorLoop>);
+    default: return reinterpret_cast<const void*>(&doc_kernel<kVarDirectFlatten>);
   }
 }
+int kernel_threads(int k) { return k >= kDocSlot ? kDocThreads : kGroupThreads; }
 int slot_of_variant(uint32_t v) {
   return v == 0 ? 0 : v == (uint32_t)kVarNaiveClassify ? 1 : v == (uint32_t)kVarXorLoop ? 2
        : v == (uint32_t)kVarDirectFlatten ? 3 : -1;
@@ -81,14 +101,15 @@ uint64_t tiles_for(uint64_t total_len) {
   return t ? t : 1;
 }
 
-size_t ws_bytes_for_tiles(uint64_t tiles) { return (size_t)workspace_bytes(tiles); }
+size_t ws_bytes_for_tiles(uint64_t tiles) { return (size_t)stream_ws_bytes(tiles); }
 
 int slots_for_device(int dev, int kernel) {
   if (dev < 0 || dev >= 64) return 1024;
   int& slots = g_slots[kernel][dev];
   if (slots) return slots;
   int per_cu = 0;
-  const hipError_t rc = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel_at(kernel), kGroupThreads, 0);
+  const hipError_t rc =
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel_at(kernel), kernel_threads(kernel), 0);
   if (rc != hipSuccess || per_cu < 1) per_cu = 1;
   hipDeviceProp_t prop;
   int cus = 256;
@@ -183,6 +204,48 @@ int launch(Args& a, hipStream_t stream, const StreamWs& e, int64_t span, bool mi
   return JSIDX_OK;
 }
 
+// One document with the kernel of jsidx_doc.h over workspace e.
+int launch_doc(const uint8_t* buf, uint64_t len, uint32_t* out, uint32_t* out_n, uint32_t* out_err,
+               hipStream_t stream, const StreamWs& e) {
+  int dev = 0;
+  if (!e.ws) return JSIDX_E_NOWORKSPACE;
+  if (hipGetDevice(&dev) != hipSuccess) return JSIDX_E_HIP;
+  const int kernel = kDocSlot + slot_of_variant(g_variant);
+  const uint64_t slots = (uint64_t)slots_for_device(dev, kernel);
+  DocArgs a;
+  a.base = buf ? buf : reinterpret_cast<const uint8_t*>(out);  // never read when len == 0
+  a.len = len;
+  a.out_idx = out;
+  a.out_n = out_n;
+  a.out_err = out_err;
+  a.ws = e.ws;
+  uint8_t* region = reinterpret_cast<uint8_t*>(e.ws) + doc_region_offset(e.cap_tiles);
+  a.cap = doc_cap_for(e.cap_tiles);
+  a.desc = reinterpret_cast<uint64_t*>(region);
+  a.blk = a.desc + a.cap;
+  a.bcnt = reinterpret_cast<uint32_t*>(a.blk + 2 * doc_blocks_for(a.cap));
+  a.p0 = -(int64_t)((uintptr_t)a.base & 15u);
+  a.ntiles = len ? ((int64_t)len - a.p0 + kDocTile - 1) / kDocTile : 0;
+  const uint64_t groups = ((uint64_t)a.ntiles + kDocWaves - 1) / kDocWaves;
+  uint64_t grid = groups < slots ? groups : slots;
+  if (grid < 1) grid = 1;
+  (void)hipGetLastError();
+  switch (kernel) {
+    case kDocSlot: hipLaunchKernelGGL(doc_kernel<0>, dim3((uint32_t)grid), dim3(kDocThreads), 0, stream, a); break;
+    case kDocSlot + 1:
+      hipLaunchKernelGGL(doc_kernel<kVarNaiveClassify>, dim3((uint32_t)grid), dim3(kDocThreads), 0, stream, a);
+      break;
+    case kDocSlot + 2:
+      hipLaunchKernelGGL(doc_kernel<kVarXorLoop>, dim3((uint32_t)grid), dim3(kDocThreads), 0, stream, a);
+      break;
+    default:
+      hipLaunchKernelGGL(doc_kernel<kVarDirectFlatten>, dim3((uint32_t)grid), dim3(kDocThreads), 0, stream, a);
+      break;
+  }
+  if (hipGetLastError() != hipSuccess) return JSIDX_E_HIP;
+  return JSIDX_OK;
+}
+
 }  // namespace jsidx
 
 using namespace jsidx;
@@ -198,6 +261,7 @@ int build_one(const uint8_t* buf, uint64_t len, uint32_t* out, uint32_t* out_n, 
   uint64_t need = tiles_for(len);
   int rc = get_ws(stream, need, true, &e);
   if (rc) return rc;
+  if (!minify) return launch_doc(buf, len, out, out_n, out_err, stream, *e);
   Args a;
   a.base = buf ? buf : reinterpret_cast<const uint8_t*>(out);  // never read when len == 0
   a.offsets = nullptr;
@@ -247,7 +311,23 @@ int build_many(const uint8_t* bufs, const uint64_t* offsets, uint32_t ndocs, uin
 
 }  // namespace jsidx
 
+#ifdef JSIDX_PROBE
+namespace jsidx {
+namespace prim {
+__device__ uint64_t* g_probe;
+}  // namespace prim
+}  // namespace jsidx
+#endif
+
 extern "C" {
+
+#ifdef JSIDX_PROBE
+// Probe builds only: the buffer the tile events are written to (0: none).
+int jsidx_probe_set(void* p) {
+  uint64_t* v = (uint64_t*)p;
+  return hipMemcpyToSymbol(HIP_SYMBOL(jsidx::prim::g_probe), &v, sizeof(v)) == hipSuccess ? 0 : -3;
+}
+#endif
 
 int jsidx_build(const uint8_t* buf, uint64_t len, uint32_t* out_idx, uint32_t* out_n, uint32_t* out_err,
                 jsidx_stream_t stream) {

@@ -27,4 +27,9 @@ extern std::mutex g_mu;
 // document); span < 0: a batch (sizes on the device).  Caller holds g_mu.
 int launch(Args& a, hipStream_t stream, const StreamWs& e, int64_t span, bool minify);
 
+// Launches the one-document kernel (jsidx_doc.h) over workspace e.  Caller
+// holds g_mu.
+int launch_doc(const uint8_t* buf, uint64_t len, uint32_t* out, uint32_t* out_n, uint32_t* out_err,
+               hipStream_t stream, const StreamWs& e);
+
 }  // namespace jsidx

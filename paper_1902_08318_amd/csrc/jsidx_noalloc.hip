@@ -7,6 +7,7 @@
 #include <mutex>
 
 #include "jsidx.h"
+#include "jsidx_doc.h"
 #include "jsidx_host.h"
 
 namespace jsidx {
@@ -17,7 +18,7 @@ namespace jsidx {
 // device address is taken once per device (hipGetSymbolAddress) and only that
 // address is ever passed to a kernel.
 constexpr uint64_t kStaticTiles = (JSIDX_NOALLOC_MAX_LEN + 15 + kTileBytes - 1) / kTileBytes;
-constexpr uint64_t kStaticWsBytes = (workspace_bytes(kStaticTiles) + 255) & ~(uint64_t)255;
+constexpr uint64_t kStaticWsBytes = (stream_ws_bytes(kStaticTiles) + 255) & ~(uint64_t)255;
 static_assert(kStaticWsBytes <= (80ull << 20), "the static workspace stays modest");
 static __device__ __align__(256) uint8_t scratch[kStaticWsBytes];
 
@@ -33,8 +34,9 @@ __global__ void __launch_bounds__(256) zero_words(uint64_t* p, uint64_t n) {
 }
 
 // The static workspace of the current device, set up on first use: its
-// address, and its header, descriptors and block words zeroed on `stream`
-// (the mask slots are written before they are read).  Caller holds g_mu.
+// address, and its header and both kernels' descriptors, block words and
+// counters zeroed on `stream` (the mask slots are written before they are
+// read).  Caller holds g_mu.
 int static_ws(hipStream_t stream, StreamWs* out) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return JSIDX_E_HIP;
@@ -44,8 +46,10 @@ int static_ws(hipStream_t stream, StreamWs* out) {
     void* p = nullptr;
     if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return JSIDX_E_HIP;
     const uint64_t words = mask_offset(desc_slots(kStaticTiles)) / 8;
+    const uint64_t doc0 = doc_region_offset(kStaticTiles) / 8, doc_words = (doc_region_bytes(kStaticTiles) + 7) / 8;
     (void)hipGetLastError();
     hipLaunchKernelGGL(zero_words, dim3(64), dim3(256), 0, stream, (uint64_t*)p, words);
+    hipLaunchKernelGGL(zero_words, dim3(16), dim3(256), 0, stream, (uint64_t*)p + doc0, doc_words);
     if (hipGetLastError() != hipSuccess) return JSIDX_E_HIP;
     s.ptr = p;
     s.ready = true;
@@ -70,15 +74,7 @@ int jsidx_build_noalloc(const uint8_t* buf, uint64_t len, uint32_t* out_idx, uin
   StreamWs e;
   const int rc = static_ws(stream, &e);
   if (rc) return rc;
-  Args a;
-  a.base = buf ? buf : reinterpret_cast<const uint8_t*>(out_idx);  // never read when len == 0
-  a.offsets = nullptr;
-  a.len = len;
-  a.ndocs = 1;
-  a.out_idx = out_idx;
-  a.out_n = out_n;
-  a.out_err = out_err;
-  return launch(a, stream, e, (int64_t)(len + ((uintptr_t)a.base & 15u)), false);
+  return launch_doc(buf, len, out_idx, out_n, out_err, stream, e);
 }
 
 }  // extern "C"

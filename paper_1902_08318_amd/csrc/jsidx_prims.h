@@ -87,6 +87,12 @@ JSIDX_DEV void st_agent(uint64_t* p, uint64_t v) { __hip_atomic_store(p, v, __AT
 JSIDX_DEV void st_agent32(uint32_t* p, uint32_t v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
 JSIDX_DEV uint32_t add_agent32(uint32_t* p, uint32_t v) { return atomicAdd(p, v); }
 JSIDX_DEV void min_lds(int32_t* p, int32_t v) { atomicMin(p, v); }
+// Workgroup-shared (LDS) counters read and updated by several waves.
+JSIDX_DEV uint32_t add_lds32(uint32_t* p, uint32_t v) { return atomicAdd(p, v); }
+JSIDX_DEV uint32_t ld_lds32(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+JSIDX_DEV void st_lds32(uint32_t* p, uint32_t v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); }
 
 // One instance per workgroup (LDS).
 template <class T>
@@ -98,6 +104,19 @@ JSIDX_DEV T& lds_object() {
 // Timing hooks for probe builds (no-ops in the library).
 JSIDX_DEV void trace(int64_t, int) {}
 JSIDX_DEV void trace_count(int64_t, int) {}
+#ifdef JSIDX_PROBE
+// Probe builds only: tile t's event k gets the 100 MHz real-time clock, and
+// event 7 the wave's hardware id, in a buffer the probe host code sets.
+extern __device__ uint64_t* g_probe;
+JSIDX_DEV void dtrace(int64_t t, int k) {
+  if (g_probe && __lane_id() == 0) {
+    g_probe[t * 8 + k] = __builtin_amdgcn_s_memrealtime();
+    if (k == 0) g_probe[t * 8 + 7] = (uint64_t)__builtin_amdgcn_s_getreg((4 << 0) | (0 << 6) | (31 << 11));
+  }
+}
+#else
+JSIDX_DEV void dtrace(int64_t, int) {}
+#endif
 
 JSIDX_DEV uint4 load16(const uint8_t* p) { return *reinterpret_cast<const uint4*>(p); }
 JSIDX_DEV uint32_t load4(const uint8_t* p) { return *reinterpret_cast<const uint32_t*>(p); }

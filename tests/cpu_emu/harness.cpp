@@ -7,6 +7,7 @@
 #include <thread>
 #include <vector>
 
+#include "jsidx_doc.h"
 #include "jsidx_kernel.h"
 #include "jsidx_scopes.h"
 #include "jsidx_tape.h"
@@ -41,8 +42,8 @@ long emu_run(const uint8_t* base, const uint64_t* offsets, uint64_t len, uint32_
   env.writes[env.nwrites++] = {out_idx, reinterpret_cast<const uint8_t*>(out_idx) + out_cap * (minify ? 1 : 4)};
   env.writes[env.nwrites++] = {out_n, out_n + ndocs};
   env.writes[env.nwrites++] = {out_err, out_err + ndocs};
-  env.writes[env.nwrites++] = {ws_mem, (const uint8_t*)ws_mem + workspace_bytes(cap_tiles)};
-  env.reads[env.nreads++] = {ws_mem, (const uint8_t*)ws_mem + workspace_bytes(cap_tiles)};
+  env.writes[env.nwrites++] = {ws_mem, (const uint8_t*)ws_mem + stream_ws_bytes(cap_tiles)};
+  env.reads[env.nreads++] = {ws_mem, (const uint8_t*)ws_mem + stream_ws_bytes(cap_tiles)};
 
   Args a;
   a.base = base;
@@ -272,7 +273,61 @@ int emu_number(const uint8_t* text, uint64_t len, int exact, uint64_t* bits) {
   return r;
 }
 
-uint64_t emu_ws_bytes(uint64_t cap_tiles) { return workspace_bytes(cap_tiles); }
+uint64_t emu_ws_bytes(uint64_t cap_tiles) { return stream_ws_bytes(cap_tiles); }
+
+// One document through the one-document kernel (jsidx_doc.h) with `nwaves`
+// concurrent waves (rounded up to whole workgroups), over the persistent
+// workspace ws_mem of cap_tiles largest tiles.  granule_lo/hi: the bytes the
+// kernel may read.  Returns the number of out-of-range accesses.
+long emu_doc_run(const uint8_t* base, uint64_t len, uint32_t* out_idx, uint64_t out_cap, uint32_t* out_n,
+                 uint32_t* out_err, int nwaves, void* ws_mem, uint64_t cap_tiles, const uint8_t* granule_lo,
+                 const uint8_t* granule_hi, int variant) {
+  prim::EmuEnv env;
+  env.reads[env.nreads++] = {granule_lo, granule_hi};
+  env.writes[env.nwrites++] = {out_idx, out_idx + out_cap};
+  env.writes[env.nwrites++] = {out_n, out_n + 1};
+  env.writes[env.nwrites++] = {out_err, out_err + 1};
+  env.writes[env.nwrites++] = {ws_mem, (const uint8_t*)ws_mem + stream_ws_bytes(cap_tiles)};
+  env.reads[env.nreads++] = {ws_mem, (const uint8_t*)ws_mem + stream_ws_bytes(cap_tiles)};
+  DocArgs a;
+  a.base = base;
+  a.len = len;
+  a.out_idx = out_idx;
+  a.out_n = out_n;
+  a.out_err = out_err;
+  a.ws = (Workspace*)ws_mem;
+  uint8_t* region = (uint8_t*)ws_mem + doc_region_offset(cap_tiles);
+  a.cap = doc_cap_for(cap_tiles);
+  a.desc = (uint64_t*)region;
+  a.blk = a.desc + a.cap;
+  a.bcnt = (uint32_t*)(a.blk + 2 * doc_blocks_for(a.cap));
+  a.p0 = -(int64_t)((uintptr_t)base & 15u);
+  a.ntiles = len ? ((int64_t)len - a.p0 + kDocTile - 1) / kDocTile : 0;
+  const int ngroups = (nwaves + kDocWaves - 1) / kDocWaves;
+  std::vector<prim::GroupCtx*> groups;
+  for (int b = 0; b < ngroups; b++) groups.push_back(new prim::GroupCtx(kDocThreads));
+  std::vector<std::thread> th;
+  for (int b = 0; b < ngroups; b++) {
+    for (uint32_t t = 0; t < (uint32_t)kDocThreads; t++) {
+      th.emplace_back([&, b, t] {
+        prim::tctx.tid = t;
+        prim::tctx.block = (uint32_t)b;
+        prim::tctx.grid = (uint32_t)ngroups;
+        prim::tctx.g = groups[(size_t)b];
+        prim::tctx.env = &env;
+        if (variant == kVarNaiveClassify) doc_tiles<kVarNaiveClassify>(a);
+        else if (variant == kVarXorLoop) doc_tiles<kVarXorLoop>(a);
+        else if (variant == kVarDirectFlatten) doc_tiles<kVarDirectFlatten>(a);
+        else doc_tiles<0>(a);
+      });
+    }
+  }
+  for (auto& x : th) x.join();
+  for (auto* g : groups) delete g;
+  return env.violations.load();
+}
+uint32_t emu_doc_tile_bytes() { return (uint32_t)kDocTile; }
+uint32_t emu_doc_slots() { return (uint32_t)kDocSlots; }
 uint32_t emu_tile_bytes() { return (uint32_t)kTileBytes; }
 uint32_t emu_pick_rows(int64_t span, uint64_t waves) { return pick_rows(span, waves); }
 

@@ -212,6 +212,10 @@ inline void min_lds(int32_t* p, int32_t v) {
   }
 }
 
+inline uint32_t add_lds32(uint32_t* p, uint32_t v) { return __atomic_fetch_add(p, v, __ATOMIC_RELAXED); }
+inline uint32_t ld_lds32(const uint32_t* p) { return __atomic_load_n(p, __ATOMIC_RELAXED); }
+inline void st_lds32(uint32_t* p, uint32_t v) { __atomic_store_n(p, v, __ATOMIC_RELAXED); }
+
 template <class T>
 inline T& lds_object() {
   static_assert(sizeof(T) <= sizeof(GroupCtx::lds), "LDS object too large");
@@ -220,6 +224,7 @@ inline T& lds_object() {
 
 inline void trace(int64_t, int) {}
 inline void trace_count(int64_t, int) {}
+inline void dtrace(int64_t, int) {}
 
 inline uint4 load16(const uint8_t* p) {
   check(p, 16, false);

@@ -28,17 +28,42 @@ def _deps():
     return files
 
 
-def build(block_tiles: int | None = None) -> str:
-    """Build the emulation library; block_tiles overrides the look-back block
-    size (tests use 2 so that small inputs span many blocks)."""
+# Builds with other compile-time parameters of the one-document kernel, by
+# name (the library's own values are the defaults of jsidx_doc.h).
+DOC_BUILDS = {
+    "slots2": ["-DJSIDX_DOC_SLOTS=2", "-DJSIDX_DOC_WAVES=4", "-DJSIDX_DOC_BATCH=4"],
+    "rows4": ["-DJSIDX_DOC_ROWS=4", "-DJSIDX_DOC_AHEAD=1"],
+    "waves4b3": ["-DJSIDX_DOC_WAVES=4", "-DJSIDX_DOC_BATCH=3"],
+}
+
+
+def _lib_path(block_tiles):
+    if block_tiles is None:
+        return LIB
+    return LIB.replace(".so", f"_{block_tiles}.so" if isinstance(block_tiles, str) else f"_b{block_tiles}.so")
+
+
+def build(block_tiles: int | str | None = None) -> str:
+    """Build the emulation library; an int block_tiles overrides the look-back
+    block size of both kernels (tests use 1 or 2 so that small inputs span
+    many blocks), a string names a build of DOC_BUILDS."""
     os.makedirs(OUT_DIR, exist_ok=True)
-    lib = LIB if block_tiles is None else LIB.replace(".so", f"_b{block_tiles}.so")
-    defs = [] if block_tiles is None else [f"-DJSIDX_BLOCK_TILES={block_tiles}"]
+    lib = _lib_path(block_tiles)
+    if block_tiles is None:
+        defs = []
+    elif isinstance(block_tiles, str):
+        defs = DOC_BUILDS[block_tiles]
+    else:
+        defs = [f"-DJSIDX_BLOCK_TILES={block_tiles}", f"-DJSIDX_DOC_BLOCK={block_tiles}"]
+    # built under a private name and renamed, so that parallel test workers
+    # never load a half-written library
+    tmp = f"{lib}.{os.getpid()}.tmp"
     subprocess.run(
         ["g++", "-std=c++17", "-O1", "-g", "-shared", "-fPIC", "-pthread", *defs,
          "-I", os.path.join(HERE, "cpu_emu"), "-I", os.path.join(ROOT, "include"),
-         "-I", os.path.join(ROOT, "paper_1902_08318_amd", "csrc"), "-o", lib, SRC],
+         "-I", os.path.join(ROOT, "paper_1902_08318_amd", "csrc"), "-o", tmp, SRC],
         check=True)
+    os.replace(tmp, lib)
     return lib
 
 
@@ -51,7 +76,7 @@ def load(block_tiles: int | None = None):
         return _lib
     if block_tiles in _libs:
         return _libs[block_tiles]
-    path = LIB if block_tiles is None else LIB.replace(".so", f"_b{block_tiles}.so")
+    path = _lib_path(block_tiles)
     if not os.path.exists(path) or any(os.path.getmtime(f) > os.path.getmtime(path) for f in _deps()):
         build(block_tiles)
     lib = ctypes.CDLL(path)
@@ -73,6 +98,11 @@ def load(block_tiles: int | None = None):
     lib.emu_ws_bytes.argtypes = [ctypes.c_uint64]
     lib.emu_ws_bytes.restype = ctypes.c_uint64
     lib.emu_tile_bytes.restype = ctypes.c_uint32
+    lib.emu_doc_tile_bytes.restype = ctypes.c_uint32
+    lib.emu_doc_slots.restype = ctypes.c_uint32
+    lib.emu_doc_run.argtypes = [vp, ctypes.c_uint64, vp, ctypes.c_uint64, vp, vp, ctypes.c_int, vp, ctypes.c_uint64,
+                                vp, vp, ctypes.c_int]
+    lib.emu_doc_run.restype = ctypes.c_long
     lib.emu_pick_rows.argtypes = [ctypes.c_int64, ctypes.c_uint64]
     lib.emu_pick_rows.restype = ctypes.c_uint32
     if block_tiles is None:
@@ -200,3 +230,39 @@ def number(text: str, exact: bool):
     bits = np.zeros(1, dtype=np.uint64)
     r = lib.emu_number(raw, len(raw), 1 if exact else 0, bits.ctypes.data)
     return int(r), int(bits[0])
+
+
+def doc_tile_bytes() -> int:
+    """Bytes of a tile of the one-document kernel."""
+    return int(load().emu_doc_tile_bytes())
+
+
+def run_doc(data: bytes, nwaves: int = 8, misalign: int = 0, ws: Workspace | None = None, garbage: int = 0xEE,
+            block_tiles: int | None = None, variant: int = 0):
+    """Index one document with the one-document kernel (jsidx_build's).
+
+    misalign: the buffer starts this many bytes past a 64-byte boundary; the
+    bytes around the input inside its 16-byte granules hold `garbage`.
+    Returns (out_idx, out_n, out_err, violations)."""
+    if ws is not None:
+        block_tiles = ws.block_tiles
+    lib = load(block_tiles)
+    n = len(data)
+    raw, off = _aligned(n + 64, misalign + 16)
+    raw[:] = garbage
+    raw[off:off + n] = np.frombuffer(data, dtype=np.uint8)
+    base = raw.ctypes.data + off
+    glo = base & ~15
+    ghi = ((base + n + 15) & ~15) if n else glo
+    out_cap = max(n, 1)
+    out_idx = np.full(out_cap, 0xDEADBEEF, dtype=np.uint32)
+    out_n = np.full(1, 0xDEADBEEF, dtype=np.uint32)
+    out_err = np.full(1, 0xDEADBEEF, dtype=np.uint32)
+    tb = tile_bytes()
+    need = max(1, (n + 15 + tb - 1) // tb)
+    if ws is None:
+        ws = Workspace(need, block_tiles)
+    v = lib.emu_doc_run(ctypes.c_void_p(base), n, out_idx.ctypes.data, out_cap, out_n.ctypes.data,
+                        out_err.ctypes.data, nwaves, ws.mem.ctypes.data, ws.cap, ctypes.c_void_p(glo),
+                        ctypes.c_void_p(ghi), variant)
+    return out_idx, out_n, out_err, int(v)

@@ -39,7 +39,7 @@ constexpr int kDocTile = kDocRows * kRowBytes;      // 16 KiB
 constexpr int kDocWaves = JSIDX_DOC_WAVES;          // independent waves per workgroup
 constexpr int kDocThreads = kDocWaves * kThreads;
 #ifndef JSIDX_DOC_BLOCK
-#define JSIDX_DOC_BLOCK 64
+#define JSIDX_DOC_BLOCK 8
 #endif
 constexpr int kDocBlock = JSIDX_DOC_BLOCK;          // tiles per look-back block (<= 64)
 constexpr int kDocScrub = 4096;                     // tile descriptors cleared per launch
@@ -397,6 +397,138 @@ JSIDX_DEV void doc_row(const DocArgs& a, const uint32_t w[8], int64_t pos, RowCa
   c.e = ce; c.q = cq; c.p = cp; c.u = cu;
 }
 
+// ---- one interior row, carries by lane rotation -------------------------------------
+// Every 1-bit shift that crosses a lane boundary, (x << 1) with bit 0 from bit
+// 31 of the lane before, takes the lane before's x by one DPP wave rotation;
+// lane 0 takes it from the previous row's rotation, kept in a register
+// (`rot`, valid in lane 0), so no carry goes through scalar registers.
+JSIDX_DEV uint32_t shl1_rot(uint32_t x, uint32_t& rot, bool lane0) {
+  const uint32_t r = prim::ror1(x);
+  const uint32_t prev = lane0 ? rot : r;
+  rot = r;
+  return prim::alignbit(x, prev, 31);
+}
+
+// Carries between the interior rows of a tile.
+struct FastCarry {
+  uint32_t rp;          // predecessor class (bit 31, lane 0)
+  uint32_t ru[6];       // UTF-8: 4-byte lead, 3+ lead, continuation needed, E0|F0, ED|F4, F0|F4
+  uint32_t e, q, u;     // escape, in-string, UTF-8 error seen (uniform)
+  uint32_t u8pend;      // a multi-byte sequence is open at the end of the previous row (uniform)
+};
+
+JSIDX_DEV void fast_carry_from(FastCarry& f, const Behind& B) {
+  f.rp = B.p << 31;
+  f.ru[0] = B.uc.l4 << 31; f.ru[1] = B.uc.x << 31; f.ru[2] = B.uc.pa << 31;
+  f.ru[3] = B.uc.m1 << 31; f.ru[4] = B.uc.m2 << 31; f.ru[5] = B.uc.m3 << 31;
+  f.e = B.e; f.q = 0u; f.u = 0u;
+  f.u8pend = u8_carry_pending(B.uc) ? 1u : 0u;
+}
+
+template <int VAR>
+JSIDX_DEV void doc_row_fast(const uint32_t w[8], FastCarry& c, uint2* mrow, uint32_t& a0, uint32_t& a1, DocTile& T,
+                            uint32_t rowpos, bool track_lead) {
+  const uint32_t lane = prim::lane();
+  const bool l0 = lane == 0u;
+  ClassMasks cm;
+  if constexpr ((VAR & kVarNaiveClassify) != 0) {
+    SegWords sw;
+#pragma unroll
+    for (int k = 0; k < 8; k++) sw.w[k] = w[k];
+    cm = classify_bytes(sw);
+  }
+  uint32_t pl[8];
+  bit_planes(w, pl);
+  if constexpr ((VAR & kVarNaiveClassify) == 0) cm = classify_planes(pl);
+
+  // UTF-8 (Sec. 3.1.5): a byte is a continuation exactly where a lead one,
+  // two or three bytes back asks for one; C0, C1, F5..FF never occur; the
+  // byte after E0 / ED / F0 / F4 is range checked.  Rows without a byte >=
+  // 0x80 and with nothing open from the row before skip it (their carries
+  // are then zero, and so are the rotations' bits read later).
+  if (prim::ballot(pl[7] != 0u) != 0ull || c.u8pend) {
+    const uint32_t p7 = pl[7], p6 = pl[6], p5 = pl[5], p4 = pl[4];
+    const uint32_t cont = p7 & ~p6;
+    const uint32_t lead = p7 & p6;
+    const uint32_t L3 = lead & p5;
+    const uint32_t L4 = L3 & p4;
+    const uint32_t A1 = shl1_rot(L4, c.ru[0], l0);
+    const uint32_t A2 = shl1_rot(L3 | A1, c.ru[1], l0);
+    const uint32_t PA = lead | A2;
+    const uint32_t need = shl1_rot(PA, c.ru[2], l0);
+    uint32_t err = cont ^ need;
+    err |= lead & ~(p5 | p4 | pl[3] | pl[2] | pl[1]);        // C0, C1
+    err |= L4 & (pl[3] | (pl[2] & (pl[1] | pl[0])));         // F5..FF
+    const uint32_t lowz = ~(pl[3] | pl[2] | pl[1] | pl[0]);
+    const uint32_t x3 = L3 & ~p4;                            // E0..EF
+    const uint32_t E0 = x3 & lowz;
+    const uint32_t ED = x3 & pl[3] & pl[2] & ~pl[1] & pl[0];
+    const uint32_t F0 = L4 & lowz;
+    const uint32_t F4 = L4 & ~pl[3] & pl[2] & ~pl[1] & ~pl[0];
+    const uint32_t m1 = shl1_rot(E0 | F0, c.ru[3], l0);      // low second bytes are errors
+    const uint32_t m2 = shl1_rot(ED | F4, c.ru[4], l0);      // high second bytes are errors
+    const uint32_t m3 = shl1_rot(F0 | F4, c.ru[5], l0);      // 4-byte lead: the bound is 0x90
+    const uint32_t hi4 = m3 & p4;
+    err |= (m1 & ~p5 & ~hi4) | (m2 & (p5 | hi4));
+    if (prim::ballot(err != 0u) != 0ull) c.u = 1u;
+    // open at the row's end: bit 31 of a lead-derived mask in lane 63
+    c.u8pend = prim::readlane(L4 | (L3 | A1) | PA, 63) >> 31;
+  }
+
+  if (track_lead && T.lead_pos == (uint32_t)kDocTile) {
+    const uint64_t Kc = prim::ballot(cm.B != ~0u);
+    if (Kc) {
+      const int f = __builtin_ctzll(Kc);
+      const uint32_t nb = ~cm.B;
+      const uint32_t j = nb ? (uint32_t)__builtin_ctz(nb) : 0u;
+      T.lead_pos = rowpos + (uint32_t)f * (uint32_t)kSegBytes + prim::readlane(j, f);
+      T.lead_q = prim::readlane((cm.Q >> j) & 1u, f);
+    }
+  }
+
+  // escapes (Fig. 3)
+  uint32_t OD;
+  if (prim::ballot(cm.B != 0u) == 0ull) {
+    OD = l0 ? c.e : 0u;
+    c.e = 0u;
+  } else {
+    const uint32_t nb = ~cm.B;
+    const uint32_t eo = (nb ? (uint32_t)__builtin_clz(nb) : 32u) & 1u;  // the trailing run is odd
+    uint32_t e_lane;
+    if (prim::ballot(cm.B == ~0u) == 0ull) {
+      e_lane = prim::shr1(eo, c.e);
+      c.e = prim::readlane(eo, 63);
+    } else {
+      const uint64_t Kc = prim::ballot(cm.B != ~0u);
+      const uint64_t Ec = prim::ballot(eo != 0u && cm.B != ~0u);
+      const uint64_t mk = Kc & lt_lanes();
+      e_lane = mk ? (uint32_t)((Ec >> msb64(mk)) & 1ull) : c.e;
+      if (Kc) c.e = (uint32_t)((Ec >> msb64(Kc)) & 1ull);
+    }
+    OD = odd_run_ends(cm.B & ~e_lane) | e_lane;
+  }
+  const uint32_t Q = cm.Q & ~OD;
+
+  // string ranges (Fig. 4)
+  const uint32_t PX = (VAR & kVarXorLoop) ? prefix_xor_loop(Q) : prefix_xor(Q);
+  const uint64_t Qb = prim::ballot((__builtin_popcount(Q) & 1u) != 0u);
+  const uint32_t qin = (prim::mbcnt(Qb) & 1u) ^ c.q;
+  const uint32_t R0 = PX ^ (0u - qin);
+  c.q ^= parity64(Qb);
+
+  // structural and pseudo-structural bytes (Fig. 5)
+  const uint32_t P0m = cm.C | cm.W | Q;
+  const uint32_t PR = shl1_rot(P0m, c.rp, l0);
+  const uint32_t K = cm.C | Q | (PR & ~P0m);
+  const uint32_t F0 = K & ~(Q ^ R0);
+  uint2 kf;
+  kf.x = K;
+  kf.y = F0;
+  mrow[lane] = kf;
+  a0 += (uint32_t)__builtin_popcount(F0);
+  a1 += (uint32_t)__builtin_popcount(F0 ^ K);
+}
+
 // ---- the local pass over a tile ------------------------------------------------------
 template <int VAR>
 JSIDX_DEV void doc_local(const DocArgs& a, DocWaveShared& sh, DocTile& T, uint32_t e_in, uint32_t p_in, U8Carry uc,
@@ -483,8 +615,8 @@ JSIDX_DEV void doc_local_fast(const DocArgs& a, DocWaveShared& sh, DocTile& T, B
 #pragma unroll
     for (int k = 0; k < 8; k++) buf[p][k] = S.w[p][k];
   if constexpr (!B_IN) *B = rb_eval(S.rb);
-  RowCarry c;
-  c.e = B->e; c.q = 0u; c.p = B->p; c.u = 0u; c.uc = B->uc;
+  FastCarry c;
+  fast_carry_from(c, *B);
   uint32_t a0 = 0, a1 = 0;
   T.tesc = 0; T.lead_q = 0; T.lead_pos = (uint32_t)kDocTile;
   uint2(*m)[kThreads] = sh.m[T.slot];
@@ -501,15 +633,14 @@ JSIDX_DEV void doc_local_fast(const DocArgs& a, DocWaveShared& sh, DocTile& T, B
         buf[r % kDocAhead][4 * h + 2] = v.z; buf[r % kDocAhead][4 * h + 3] = v.w;
       }
     }
-    const int64_t pos = T.P0 + (int64_t)r * kRowBytes + (int64_t)lane * kSegBytes;
-    doc_row<false, VAR>(a, w, pos, c, m[r], a0, a1, T, (uint32_t)(r * kRowBytes), track_lead);
+    doc_row_fast<VAR>(w, c, m[r], a0, a1, T, (uint32_t)(r * kRowBytes), track_lead);
   }
   T.qpar = c.q;
   T.u = c.u;
   T.c0 = wave_sum(a0);
   T.c1 = wave_sum(a1);
   T.eo = c.e;
-  T.po = c.p;
+  T.po = prim::readlane(c.rp, 0) >> 31;  // the class of the tile's last byte
 }
 
 // ---- the look-back -------------------------------------------------------------------
@@ -630,8 +761,27 @@ JSIDX_DEV bool doc_block_entry(const DocArgs& a, int64_t b, DocFold* out) {
   }
 }
 
-// State entering tile t (t >= 1): q, u and the index count before it.
-JSIDX_DEV bool doc_look_back(const DocArgs& a, int64_t t, uint32_t epoch, DocFold* out) {
+// The look-back's first reads, issued early (a local pass before they are
+// needed, so that their round trip overlaps it): the descriptors of the
+// tiles of t's block before t, one per lane, and the inclusive value of the
+// block before (lane 0).
+struct LbPre {
+  uint64_t d, be;
+};
+
+JSIDX_DEV void doc_lb_issue(const DocArgs& a, int64_t t, LbPre& P) {
+  const uint32_t lane = prim::lane();
+  const int64_t b = t / kDocBlock, j0 = b * kDocBlock;
+  P.d = 0;
+  P.be = 0;
+  if ((int64_t)lane < t - j0) P.d = prim::ld_agent(a.desc + j0 + lane);
+  if (b > 0 && lane == 0) P.be = prim::ld_agent(a.blk + 2 * (b - 1) + 1);
+}
+
+// State entering tile t (t >= 1): q, u and the index count before it.  pre:
+// the first reads, issued earlier (they may be stale; anything not yet
+// published is read again).
+JSIDX_DEV bool doc_look_back(const DocArgs& a, int64_t t, uint32_t epoch, DocFold* out, const LbPre* pre) {
   const uint32_t lane = prim::lane();
   const int64_t b = t / kDocBlock, j0 = b * kDocBlock;
   const int n = (int)(t - j0);
@@ -639,10 +789,14 @@ JSIDX_DEV bool doc_look_back(const DocArgs& a, int64_t t, uint32_t epoch, DocFol
   DocFold entry;
   entry.known = 1; entry.pending = 0; entry.q = 0; entry.u = 0; entry.c0 = 0; entry.c1 = 0;
   for (uint32_t polls = 0;;) {
-    uint64_t d = 0;
-    if ((int)lane < n) d = prim::ld_agent(a.desc + j0 + lane);
-    uint64_t be = 0;
-    if (!have_entry && lane == 0) be = prim::ld_agent(a.blk + 2 * (b - 1) + 1);
+    uint64_t d = 0, be = 0;
+    if (polls == 0 && pre) {
+      d = pre->d;
+      be = pre->be;
+    } else {
+      if ((int)lane < n) d = prim::ld_agent(a.desc + j0 + lane);
+      if (!have_entry && lane == 0) be = prim::ld_agent(a.blk + 2 * (b - 1) + 1);
+    }
     const bool ok = (int)lane < n && doc_current(d, epoch);
     const uint32_t kind = ok ? dd_flag(d) : 0u;
     const uint32_t q = dd_q(d), u = dd_u(d);
@@ -832,8 +986,12 @@ JSIDX_DEV void doc_after_count(const DocArgs& a, int64_t t, uint32_t oldv, uint3
 
 // Positions of F (this lane's 32 bytes start at document position rel) at
 // ranks from *cc plus the lanes below; *cc advances by the row's count.
+// Rows are staged in alternate halves of the buffer, so that a row's writes
+// never meet the previous row's reads (the wave waits for its LDS accesses
+// once per staged row, which also covers the reads of the row before).
 template <bool STAGED>
-JSIDX_DEV void doc_write_row(uint32_t* out, uint32_t* stage, uint32_t* cc, uint32_t F, uint32_t rel, uint64_t lim) {
+JSIDX_DEV void doc_write_row(uint32_t* out, uint32_t* stage, uint32_t* half, uint32_t* cc, uint32_t F, uint32_t rel,
+                             uint64_t lim) {
   const uint32_t n = (uint32_t)__builtin_popcount(F);
   const uint32_t incl = prim::incl_scan(n);
   const uint32_t row_n = prim::readlane(incl, 63);
@@ -841,16 +999,18 @@ JSIDX_DEV void doc_write_row(uint32_t* out, uint32_t* stage, uint32_t* cc, uint3
   const uint32_t base = *cc;
   *cc += row_n;
   const bool safe = (uint64_t)base + row_n <= lim;
-  if (STAGED && safe && row_n <= (uint32_t)kDocStage && prim::ballot(n > (uint32_t)JSIDX_DOC_STAGE_LANE) != 0ull) {
+  if (STAGED && safe && row_n <= (uint32_t)(kDocStage / 2) &&
+      prim::ballot(n > (uint32_t)JSIDX_DOC_STAGE_LANE) != 0ull) {
+    uint32_t* sb = stage + *half;
+    *half ^= (uint32_t)(kDocStage / 2);
     uint32_t k = incl - n;
     while (F) {
       const uint32_t j = (uint32_t)__builtin_ctz(F);
       F &= F - 1u;
-      stage[k++] = rel + j;
+      sb[k++] = rel + j;
     }
     prim::wave_sync();
-    for (uint32_t i = prim::lane(); i < row_n; i += (uint32_t)kThreads) prim::st_out(out + base + i, stage[i]);
-    prim::wave_sync();
+    for (uint32_t i = prim::lane(); i < row_n; i += (uint32_t)kThreads) prim::st_out(out + base + i, sb[i]);
     return;
   }
   uint32_t k = base + incl - n;
@@ -906,14 +1066,14 @@ JSIDX_DEV uint32_t doc_next_tile(const DocArgs& a, DocPre* S) {
 // next ticket and first loads into *nx / *S, then T's positions.
 template <int VAR>
 JSIDX_DEV void doc_finish_tile(const DocArgs& a, DocWaveShared& sh, const DocTile& T, uint32_t epoch, uint32_t* nx,
-                               DocPre* pre) {
+                               DocPre* pre, const LbPre* lb) {
   const uint32_t lane = prim::lane();
   const int64_t t = T.t;
   DocFold S0;
   S0.known = 1; S0.q = 0; S0.u = 0; S0.c0 = 0; S0.c1 = 0; S0.pending = 0;
   prim::dtrace(t, 3);
   if (t > 0) {
-    if (!doc_look_back(a, t, epoch, &S0)) { S0.q = 0; S0.u = 0; S0.c0 = 0; }
+    if (!doc_look_back(a, t, epoch, &S0, lb)) { S0.q = 0; S0.u = 0; S0.c0 = 0; }
     // the tile's inclusive value shortens later look-backs in its block
     if (lane == 0) {
       const uint32_t cnt = S0.c0 + (S0.q ? T.c1 : T.c0);
@@ -935,11 +1095,12 @@ JSIDX_DEV void doc_finish_tile(const DocArgs& a, DocWaveShared& sh, const DocTil
   prim::wave_sync();
   uint32_t* stage = reinterpret_cast<uint32_t*>(&m[0][0]);
   uint32_t cc = S.c0;
+  uint32_t half = 0;
   const uint64_t lim = a.len;
 #pragma unroll
   for (int r = 0; r < kDocRows; r++) {
     const int64_t rel = T.P0 + (int64_t)r * kRowBytes + (int64_t)lane * kSegBytes;
-    doc_write_row<(VAR & kVarDirectFlatten) == 0>(a.out_idx, stage, &cc, Fr[r], (uint32_t)rel, lim);
+    doc_write_row<(VAR & kVarDirectFlatten) == 0>(a.out_idx, stage, &half, &cc, Fr[r], (uint32_t)rel, lim);
   }
   if (t == a.ntiles - 1 && lane == 0) {
     const uint32_t q = S.q ^ T.qpar, u = S.u | T.u;
@@ -990,10 +1151,13 @@ JSIDX_DEVFN void doc_tiles(const DocArgs& a) {
       T.t = (int64_t)tk;
       T.P0 = a.p0 + T.t * (int64_t)kDocTile;
       T.slot = slot;
+      // the look-back reads of the tile finished after this local pass go out now
+      LbPre lb;
+      if (np == kDocSlots - 1) doc_lb_issue(a, pq[0].t, lb);
       const uint32_t cnt = doc_start_tile<VAR>(a, sh, T, epoch, S);
       uint32_t nx = 0;
       if (np == kDocSlots - 1) {
-        doc_finish_tile<VAR>(a, sh, pq[0], epoch, &nx, &S);
+        doc_finish_tile<VAR>(a, sh, pq[0], epoch, &nx, &S, &lb);
 #pragma unroll
         for (int i = 0; i + 1 < kDocSlots - 1; i++) pq[i] = pq[i + 1];
         np--;
@@ -1010,7 +1174,7 @@ JSIDX_DEVFN void doc_tiles(const DocArgs& a) {
     }
 #pragma unroll
     for (int i = 0; i < kDocSlots - 1; i++)
-      if (i < np) doc_finish_tile<VAR>(a, sh, pq[i], epoch, nullptr, nullptr);
+      if (i < np) doc_finish_tile<VAR>(a, sh, pq[i], epoch, nullptr, nullptr, nullptr);
   }
 
   // The last workgroup out resets the counters for the next launch, clears

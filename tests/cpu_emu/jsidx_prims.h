@@ -174,6 +174,10 @@ inline uint32_t shr1(uint32_t v, uint32_t fill) {
   uint32_t r = exchange(v, lane() == 0 ? 0 : (int)lane() - 1);
   return lane() == 0 ? fill : r;
 }
+inline uint32_t ror1(uint32_t v) { return exchange(v, lane() == 0 ? 63 : (int)lane() - 1); }
+inline uint32_t alignbit(uint32_t hi, uint32_t lo, uint32_t s) {
+  return (uint32_t)((((uint64_t)hi << 32) | lo) >> (s & 31));
+}
 inline uint32_t incl_scan(uint32_t v) {
   WaveCtx& w = wave();
   w.slot[lane()] = v;

@@ -29,8 +29,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "structural-index GB/s (1 doc & batched) vs HBM peak; docs/s; p99 latency"
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = ["jsidx.hip", "jsidx_device.h", "jsidx_kernel.h", "jsidx_prims.h"]
-PROFILE = os.path.join(ROOT, "profiles", "index_kernel_c1_256MiB.md")
+KERNEL_SOURCES = ["jsidx.hip", "jsidx_host.h", "jsidx_doc.h", "jsidx_kernel.h", "jsidx_device.h", "jsidx_prims.h"]
+PROFILE = os.path.join(ROOT, "profiles", "doc_kernel_c1_256MiB.md")
 
 
 def kernel_hash() -> str:
@@ -48,12 +48,10 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def profiled_traffic(rows: int, variant: int = 0):
+def profiled_traffic(variant: str = "default"):
     """HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)
-    from the committed C1 profile, if it was taken on the current kernel (the
-    default variant) with the same tile size."""
-    if variant != 0:
-        return None
+    of the one-document kernel on C1, from the committed profile, if it was
+    taken on the current kernel sources and lists this kernel variant."""
     try:
         text = open(PROFILE).read()
     except OSError:
@@ -62,7 +60,7 @@ def profiled_traffic(rows: int, variant: int = 0):
     m_hash = re.search(r"sha256\[:16\]: `([0-9a-f]{16})`", text)
     if not m_hash or m_hash.group(1) != kernel_hash():
         return None
-    m_bytes = re.search(r"traffic_bytes_per_launch \(%d rows of 2 KiB per tile\): (\d+)" % rows, text)
+    m_bytes = re.search(r"traffic_bytes_per_launch \(variant %s\): (\d+)" % re.escape(variant), text)
     return int(m_bytes.group(1)) if m_bytes else None
 
 
@@ -187,11 +185,15 @@ def ablation(jx, torch, docs: dict, steps: int, restore: int, rounds: int = 5) -
 
 
 def pct(x: np.ndarray) -> dict:
-    return {"median": round(float(np.median(x)), 4), "p10": round(float(np.percentile(x, 10)), 4),
-            "p90": round(float(np.percentile(x, 90)), 4), "n": int(x.size)}
+    """Summary of per-launch (or per-call) times: the mean is what a timed
+    region of back-to-back launches sees; the median and the tail show how
+    far single slow launches pull it up."""
+    return {"mean": round(float(np.mean(x)), 4), "median": round(float(np.median(x)), 4),
+            "p10": round(float(np.percentile(x, 10)), 4), "p90": round(float(np.percentile(x, 90)), 4),
+            "p99": round(float(np.percentile(x, 99)), 4), "max": round(float(np.max(x)), 4), "n": int(x.size)}
 
 
-def time_batch(jx, torch, data: bytes, offsets: np.ndarray, steps: int, warmup: int):
+def time_batch(jx, torch, data: bytes, offsets: np.ndarray, steps: int, warmup: int, per_doc_docs: int = 20000):
     dev = torch.device("cuda:0")
     total = int(offsets[-1])
     nd = offsets.size - 1
@@ -228,7 +230,10 @@ def time_batch(jx, torch, data: bytes, offsets: np.ndarray, steps: int, warmup: 
     sp = ctypes.c_void_p(stream.cuda_stream)
     VP = ctypes.c_void_p
     b0, o0, c0, e0 = bufs.data_ptr(), out.data_ptr(), cnt.data_ptr(), err.data_ptr()
-    per_doc_docs = min(nd, 20000)
+    per_doc_docs = min(nd, per_doc_docs)
+    if per_doc_docs <= 0:
+        return {"ms_per_launch": ms, "S": S, "N": total, "ndocs": nd, "launch_ms": pct(per),
+                "docs_per_s": nd / (ms / 1e3)}
     torch.cuda.synchronize()
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
@@ -432,10 +437,14 @@ def copy_ceiling(torch, nbytes: int = 256 << 20, reps: int = 20) -> dict:
             "frac_of_peak": round(2 * nbytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
-def serve_c4(jx, torch, synth, seconds: float, nstreams: int = 3) -> dict:
+def serve_c4(jx, torch, synth, seconds: float, nstreams: int = 3, budget: int = 32 << 30,
+             forced_budget: int = 256 << 20) -> dict:
     """C4: Poisson arrivals of documents of 100 B..16 MB (log-normal) served by
     the continuous-batching loop (batches on `nstreams` streams at once) at
-    30/60/90% of its saturated rate."""
+    30/60/90% of its saturated rate, admitted by device memory (a request
+    holds 5 bytes per input byte: its bytes and its index) under the 32 GB
+    budget, which a 1 GiB ring never fills; then the 90% load again under a
+    forced budget of `forced_budget` held bytes, which binds."""
     from paper_1902_08318_amd import serve
     log("generating C4 (request ring)")
     data, offs = synth.gen_c4(4)
@@ -454,11 +463,14 @@ def serve_c4(jx, torch, synth, seconds: float, nstreams: int = 3) -> dict:
     loads = []
     for i, f in enumerate((0.3, 0.6, 0.9)):
         log(f"C4 serving at {int(f * 100)}% of saturation")
-        loads.append(serve.run_load(ring, sat, f, seconds, 40 + i).as_dict())
+        loads.append(serve.run_load(ring, sat, f, seconds, 40 + i, budget_bytes=budget).as_dict())
+    log(f"C4 serving at 90% of saturation under a forced budget of {forced_budget} bytes")
+    forced = serve.run_load(ring, sat, 0.9, seconds, 42, budget_bytes=forced_budget).as_dict()
     diag = any(jx.diag(st) for st in streams)
     return {"ring_bytes": ring.total, "ring_docs": ring.ndocs, "mean_doc_bytes": round(ring.total / ring.ndocs),
-            "streams": nstreams, "saturated_GBps": round(sat / 1e9, 2), "loads": loads, "budget_bytes": 32 << 30,
-            "cpu_oracle": cpu,
+            "max_doc_bytes": ring.max_doc, "streams": nstreams, "saturated_GBps": round(sat / 1e9, 2),
+            "held_bytes_per_request_byte": serve.REQUEST_BYTES_PER_BYTE, "budget_bytes": budget,
+            "loads": loads, "forced_budget": forced, "cpu_oracle": cpu,
             "note": "request bytes resident in HBM at arrival; latency = host-observed completion - arrival",
             **({"warning": "look-back diagnostic set"} if diag else {})}
 
@@ -491,6 +503,10 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="keep the built-in tile size choice")
     ap.add_argument("--tile-rows", type=int, choices=[2, 4, 8, 16], default=None,
                     help="every launch uses tiles of this many rows (no tuning)")
+    ap.add_argument("--per-doc-docs", type=int, default=20000,
+                    help="C3: documents timed one launch each as the comparator (0 skips it)")
+    ap.add_argument("--variant", choices=["default", "naive_classify", "xor_loop", "direct_flatten"], default=None,
+                    help="use this kernel variant (the tuner then does not choose one)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run plain 256 MiB device copies (scale for the HBM byte counters)")
     args = ap.parse_args()
@@ -523,9 +539,13 @@ def main():
         jx.set_tile_rows([args.tile_rows] * 64)
     elif not args.no_tune:
         from paper_1902_08318_amd import tune
-        log("autotuning the tile size on the 100k-document batch and the headline document")
+        log("autotuning the batch tile size (100k-document batch) and the kernel variant")
         c3 = synth.gen_c3(3)
-        tuning = tune.autotune(c3[0], c3[1], c1.data if c1 is not None else None, log=log)
+        tuning = tune.autotune(c3[0], c3[1], c1.data if c1 is not None else None, log=log,
+                               variants=args.variant is None)
+    if args.variant is not None:
+        jx.set_variant(jx.VARIANTS[args.variant])
+    vname = args.variant or ({v: k for k, v in jx.VARIANTS.items()}[tuning["variant"]] if tuning else "default")
     if args.workload == "tape":
         print(json.dumps({"workload": "tape of C1", **time_tape(jx, torch, c1.data, args.steps)}), flush=True)
         return
@@ -535,12 +555,11 @@ def main():
         return
     if args.workload == "c3":
         data, offs, _ = c3 if c3 is not None else synth.gen_c3(3)
-        r3 = time_batch(jx, torch, data, offs, args.steps, args.warmup)
+        r3 = time_batch(jx, torch, data, offs, args.steps, args.warmup, args.per_doc_docs)
         print(json.dumps({"workload": "C3", **r3}), flush=True)
         return
     log(f"timing {args.workload}: {len(c1.data)} bytes, {args.steps} steps")
     r1 = time_single(jx, torch, c1.data, args.steps, args.warmup)
-    rows1 = jx.tile_rows(len(c1.data))  # device buffers are 16-byte aligned: the span is the length
     value = r1["N"] * args.steps / (r1["ms_total"] / 1e3) / 1e9
     alg_bytes = r1["N"] + 4 * r1["S"]
     achieved = alg_bytes / (r1["ms_per_launch"] / 1e3) / 1e9
@@ -560,16 +579,24 @@ def main():
         "config": {"workload": "C1: one minified twitter-like JSON document, seed 1" if args.workload == "c1"
                    else "C2: one pretty-printed numeric (canada-like) JSON document, seed 2",
                    "bytes": r1["N"], "index_entries": r1["S"], "bytes_per_entry": round(r1["N"] / max(1, r1["S"]), 2),
-                   "flags": r1["flags"], "tile_rows": rows1, "launch_ms": r1["launch_ms"],
-                   "end_to_end_ms": r1["e2e_ms"]},
+                   "flags": r1["flags"], "kernel": f"doc_kernel, variant {vname}: tiles of 8 rows of 2 KiB",
+                   "launch_ms": r1["launch_ms"], "end_to_end_ms": r1["e2e_ms"],
+                   "timed_vs_launch_median": round(r1["ms_per_launch"] / r1["launch_ms"]["median"], 3)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": profiled_traffic(rows1, tuning["variant"] if tuning is not None else 0)
-                     if args.workload == "c1" else None},
+                     "traffic": profiled_traffic(vname) if args.workload == "c1" else None},
     }
     out["roofline"]["copy_ceiling"] = copy_ceiling(torch)
     extra = {}
     if not args.no_extra:
+        log("C0: one 1 MiB pretty-printed document (latency-bound)")
+        c0 = synth.gen_c0(0).data
+        r0 = time_single(jx, torch, c0, max(20, args.steps), args.warmup)
+        extra["C0"] = {"bytes": r0["N"], "index_entries": r0["S"], "ms_per_launch": round(r0["ms_per_launch"], 4),
+                       "input_GBps": round(r0["N"] / (r0["ms_per_launch"] / 1e3) / 1e9, 2),
+                       "launch_ms": r0["launch_ms"], "end_to_end_ms": r0["e2e_ms"]}
+        if not args.no_cpu:
+            extra["C0"]["cpu_oracle"] = cpu_baseline(c0, budget_s=2.0)
         log("generating C2 (numeric, pretty-printed)")
         c2 = synth.gen_c2(2, args.size_mib << 20)
         r2 = time_single(jx, torch, c2.data, args.steps, args.warmup)
@@ -585,7 +612,7 @@ def main():
         extra["minify"] = {"C2": time_minify(jx, torch, c2.data, None, args.steps)}
         log("kernel variants (the paper's stage-1 ablation) on C1 and C2")
         extra["ablation"] = ablation(jx, torch, {"C1": c1.data, "C2": c2.data}, max(3, args.steps // 2),
-                                     tuning["variant"] if tuning is not None else 0)
+                                     jx.VARIANTS[vname])
         del c2
         log("generating C3 (100k-document batch)")
         data, offs, kinds = c3 if c3 is not None else synth.gen_c3(3)
@@ -609,7 +636,8 @@ def main():
     out["paper_context"] = paper_context(r1["N"], r1["S"])
     if tuning is not None:
         out["tuning"] = {"tile_rows_by_log2_bytes": {str(b): r for b, r in enumerate(tuning["table"]) if r},
-                         "variant": tuning["variant"], "variant_us": tuning["variant_us"], "arch": tuning["arch"]}
+                         "variant": tuning["variant"], "variant_us": tuning["variant_us"],
+                         "variant_reason": tuning["variant_reason"], "arch": tuning["arch"]}
     if not args.no_cpu:
         log("timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(c1.data)

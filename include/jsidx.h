@@ -94,6 +94,11 @@ typedef void *jsidx_stream_t;
  * Returns JSIDX_OK or a negative JSIDX_E_* code (then nothing was launched).
  * The first call on a stream may allocate the stream's workspace (see
  * jsidx_reserve); later calls of a size the workspace covers allocate nothing.
+ * One launch: tiles of 16 KiB are taken in increasing order by the running
+ * waves, and each tile's carries (string parity, entry count, a multi-byte
+ * UTF-8 sequence cut at its start) come from the tiles before it by a
+ * two-level look-back (Sec. 3.1: the blocks are independent given the
+ * carries).
  */
 int jsidx_build(const uint8_t *buf, uint64_t len, uint32_t *out_idx,
                 uint32_t *out_n, uint32_t *out_err, jsidx_stream_t stream);
@@ -290,11 +295,13 @@ int jsidx_stream_diag(jsidx_stream_t stream, uint32_t *out_flags);
 
 /*
  * jsidx_set_tile_rows -- tuning: the tile size by input size, for later
- * launches on every device and stream of the process (the autotuner of the
- * Python package measures and sets it).  A launch cuts its input into tiles
- * of `rows` rows of 2 KiB; one wave indexes a tile row after row, so small
- * tiles shorten each wave's serial work and large tiles make fewer tiles
- * (less per-tile work, fewer carries to resolve).
+ * batched launches (jsidx_build_batch, jsidx_minify, jsidx_minify_batch) on
+ * every device and stream of the process (the autotuner of the Python package
+ * measures and sets it).  jsidx_build and jsidx_build_noalloc run a kernel
+ * with a fixed tile size (8 rows) and ignore the table.  A batched launch cuts
+ * its input into tiles of `rows` rows of 2 KiB; one wave indexes a tile row
+ * after row, so small tiles shorten each wave's serial work and large tiles
+ * make fewer tiles (less per-tile work, fewer carries to resolve).
  *   rows_by_log2  host array of n entries: entry b applies to launches whose
  *                 span (bytes from the 16-byte granule holding the first byte
  *                 to the last byte) has floor(log2(span)) == b; 0 keeps the
@@ -329,8 +336,8 @@ int jsidx_set_tile_rows(const uint8_t *rows_by_log2, uint32_t n);
 #define JSIDX_VARIANT_DIRECT_FLATTEN 4u
 int jsidx_set_variant(uint32_t variant);
 
-/* Rows per tile that a launch over `span` bytes would use on the current
- * device (written to *out_rows). */
+/* Rows per tile that a batched launch over `span` bytes would use on the
+ * current device (written to *out_rows). */
 int jsidx_tile_rows(uint64_t span, uint32_t *out_rows);
 
 /* Human-readable text for a status code. */

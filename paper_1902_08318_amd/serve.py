@@ -1,10 +1,16 @@
 """Continuous-batching serving loop over jsidx_build_batch.
 
 Requests are documents of a ring resident in HBM (request r is ring document
-r mod ndocs); each has a host arrival time.  The loop admits every request
-that has arrived (up to an in-flight byte budget) and launches the admitted
-requests as one batch -- a contiguous run of ring documents, so one offsets
-slice and one jsidx_build_batch call -- on a free stream.  Several streams,
+r mod ndocs); each has a host arrival time.  The loop admits requests that
+have arrived by device memory: a request holds its bytes and its index (one
+uint32 per byte at most), REQUEST_BYTES_PER_BYTE bytes per input byte, from
+admission until the host sees it completed, and the admitted requests' held
+bytes never exceed the budget (a request larger than the budget by itself is
+admitted alone, when nothing else is held).  The admitted requests go out as
+one batch -- a contiguous run of ring documents, so one offsets slice and one
+jsidx_build_batch call -- on a free stream; a batch that would pass the budget
+is cut to the requests that fit, and with none fitting the loop waits for
+completions (an admission wait).  Several streams,
 each with its own reserved workspace, keep batches in flight at once: work
 admitted while earlier batches run overlaps with them on the device.  A
 request completes when the host sees the event recorded after its batch; its
@@ -28,6 +34,8 @@ import numpy as np
 
 from . import binding
 
+REQUEST_BYTES_PER_BYTE = 5  # input byte + its uint32 index slot
+
 
 @dataclass
 class ServeResult:
@@ -41,6 +49,10 @@ class ServeResult:
     p90_us: float
     p99_us: float
     max_us: float
+    budget_bytes: int = 0
+    peak_held_bytes: int = 0
+    admission_waits: int = 0
+    budget_cut_batches: int = 0
 
     def as_dict(self):
         return {k: (round(v, 3) if isinstance(v, float) else v) for k, v in self.__dict__.items()} | {
@@ -98,22 +110,51 @@ def poisson_arrivals(rng: np.random.Generator, rate: float, n: int) -> np.ndarra
     return np.cumsum(rng.exponential(1.0 / rate, n))
 
 
-def serve(ring: Ring, arrivals: np.ndarray, budget_bytes: int = 32 << 30) -> tuple:
+@dataclass
+class Admission:
+    """What the device-memory budget did during one run of the loop."""
+    budget_bytes: int
+    peak_held_bytes: int = 0
+    admission_waits: int = 0      # times arrived work waited for completions
+    budget_cut_batches: int = 0   # batches cut short to stay within the budget
+
+
+def admit(ring: Ring, nxt: int, r1: int, held: int, budget: int) -> int:
+    """End (exclusive) of the requests [nxt, r1) that may be admitted with
+    `held` bytes already held: the longest prefix whose held bytes fit in
+    budget - held; one request alone when nothing is held; nxt when none
+    fits (wait)."""
+    d0 = nxt % ring.ndocs
+    room = budget - held
+    cap = ring.offs_h[d0] + room // REQUEST_BYTES_PER_BYTE
+    k = int(np.searchsorted(ring.offs_h, cap, side="right")) - 1 - d0  # whole docs that fit
+    end = nxt + max(0, min(k, r1 - nxt))
+    if end == nxt and held == 0:
+        end = nxt + 1
+    return end
+
+
+def serve(ring: Ring, arrivals: np.ndarray, budget_bytes: int = 32 << 30, stats: Admission | None = None) -> tuple:
     """Run the loop over requests with the given arrival times (seconds from
-    the start), one batch in flight per stream of the ring.  Returns (latency
-    seconds per request, elapsed seconds, served bytes, batches)."""
+    the start), one batch in flight per stream of the ring, admitting by the
+    device-memory budget (held bytes = REQUEST_BYTES_PER_BYTE * request bytes).
+    Returns (latency seconds per request, elapsed seconds, served bytes,
+    batches); `stats`, if given, receives the admission figures."""
     import torch
     nreq = arrivals.size
     ns = len(ring.streams)
     lat = np.empty(nreq)
-    busy = [None] * ns      # per stream: (event, r0, r1, bytes) of its batch in flight
+    busy = [None] * ns      # per stream: (event, r0, r1, held bytes) of its batch in flight
     events = [torch.cuda.Event() for _ in range(ns)]
     nxt = 0                 # first request not launched
     done = 0                # requests completed
-    held = 0                # bytes admitted and not completed
+    held = 0                # bytes held by admitted, not completed requests
     served = 0
     batches = 0
-    budget = min(int(budget_bytes), ring.total)
+    budget = int(budget_bytes)
+    st = stats if stats is not None else Admission(budget)
+    st.budget_bytes = budget
+    waiting = False
     gc_was = gc.isenabled()
     gc.disable()
     try:
@@ -125,11 +166,12 @@ def serve(ring: Ring, arrivals: np.ndarray, budget_bytes: int = 32 << 30) -> tup
                 job = busy[k]
                 if job is not None and job[0].query():
                     tc = time.perf_counter() - t0
-                    _, r0, r1, nb = job
+                    _, r0, r1, hb = job
                     lat[r0:r1] = tc - arrivals[r0:r1]
                     done += r1 - r0
-                    held -= nb
-                    served += nb
+                    held -= hb
+                    d0 = r0 % ring.ndocs
+                    served += int(ring.offs_h[d0 + (r1 - r0)] - ring.offs_h[d0])
                     busy[k] = job = None
                 if job is None:
                     if free < 0:
@@ -147,15 +189,24 @@ def serve(ring: Ring, arrivals: np.ndarray, budget_bytes: int = 32 << 30) -> tup
             r1 = min(r1, oldest + ring.ndocs)
             if r1 <= nxt:
                 continue
-            d0 = nxt % ring.ndocs
-            nb = int(ring.offs_h[d0 + (r1 - nxt)] - ring.offs_h[d0])
-            if held and held + nb > budget:
+            r_fit = admit(ring, nxt, r1, held, budget)
+            if r_fit == nxt:
+                if not waiting:
+                    st.admission_waits += 1
+                    waiting = True
                 continue
+            waiting = False
+            if r_fit < r1:
+                st.budget_cut_batches += 1
+                r1 = r_fit
+            d0 = nxt % ring.ndocs
+            hb = REQUEST_BYTES_PER_BYTE * int(ring.offs_h[d0 + (r1 - nxt)] - ring.offs_h[d0])
             ring.launch(d0, r1 - nxt, free)
             ev = events[free]
             ev.record(ring.streams[free])
-            busy[free] = (ev, nxt, r1, nb)
-            held += nb
+            busy[free] = (ev, nxt, r1, hb)
+            held += hb
+            st.peak_held_bytes = max(st.peak_held_bytes, held)
             nxt = r1
             batches += 1
         elapsed = time.perf_counter() - t0
@@ -180,13 +231,15 @@ def saturated_rate(ring: Ring, seconds: float = 0.5) -> float:
 
 
 def run_load(ring: Ring, sat_bytes_per_s: float, fraction: float, seconds: float, seed: int,
-             min_requests: int = 100_000) -> ServeResult:
+             min_requests: int = 100_000, budget_bytes: int = 32 << 30) -> ServeResult:
     mean = ring.total / ring.ndocs
     rate = fraction * sat_bytes_per_s / mean
     n = max(min_requests, int(rate * seconds))
     rng = np.random.default_rng(seed)
     arr = poisson_arrivals(rng, rate, n)
-    lat, el, served, batches = serve(ring, arr)
+    st = Admission(budget_bytes)
+    lat, el, served, batches = serve(ring, arr, budget_bytes, st)
     us = lat * 1e6
     return ServeResult(fraction, rate, n, el, served, batches, float(np.percentile(us, 50)),
-                       float(np.percentile(us, 90)), float(np.percentile(us, 99)), float(us.max()))
+                       float(np.percentile(us, 90)), float(np.percentile(us, 99)), float(us.max()),
+                       st.budget_bytes, st.peak_held_bytes, st.admission_waits, st.budget_cut_batches)

@@ -1,18 +1,23 @@
-"""Autotuner of the tile size (rows of 2 KiB per tile) by input size.
+"""Autotuner of the batch kernel's tile size and of the kernel variant.
 
-A launch cuts its input into tiles; one wave indexes a tile row after row.
-Small tiles shorten the serial chain of one wave and spread a small input
-over more waves; large tiles amortise the per-tile work (document table,
-carry descriptors, look-back).  Where the balance lies depends on the device,
-so it is measured: for every size class b (inputs of 2^b to 2^(b+1) bytes)
-the tuner times a batch of documents of about 1.5 * 2^b bytes, and one
-document of that size, at each candidate tile size and keeps the fastest.  The table goes to the library
-(jsidx_set_tile_rows) and to a JSON cache keyed by the GPU architecture.
+A batched launch (jsidx_build_batch, jsidx_minify, jsidx_minify_batch) cuts
+its input into tiles; one wave indexes a tile row after row.  Small tiles
+shorten the serial chain of one wave and spread a small input over more
+waves; large tiles amortise the per-tile work (document table, carry
+descriptors, look-back).  Where the balance lies depends on the device, so it
+is measured: for every size class b (inputs of 2^b to 2^(b+1) bytes) the tuner
+times a batch of documents of about 1.5 * 2^b bytes at each candidate tile
+size and keeps the fastest.  The table goes to the library
+(jsidx_set_tile_rows) and to a JSON cache keyed by the GPU architecture.  One
+document (jsidx_build) runs a kernel with a fixed tile size and is not tuned.
 The kernel variants (the default and those with one of the paper's stage-1
 optimizations turned off, App. B) are alternatives too: with the table set,
-each is timed on the whole batch and the large document (rounds over the
-variants in turn, medians), and another variant replaces the default only if
-it saves more than VARIANT_MARGIN of the time (jsidx_set_variant).
+each is timed on the whole batch and, if given, one large document, in
+VARIANT_ROUNDS rounds over the variants in turn.  Another variant replaces the
+default only if it wins on every workload by more than VARIANT_MARGIN of the
+default's median time and by more than the run-to-run spread (each of its
+round times below every round time of the default); the decision and its
+reason are returned and logged (jsidx_set_variant).
 Results never depend on the tile size or the variant; only time does.
 """
 from __future__ import annotations
@@ -26,7 +31,7 @@ import numpy as np
 from . import binding
 
 CANDIDATES = (2, 4, 8, 16)
-VARIANT_ROUNDS = 3
+VARIANT_ROUNDS = 7
 VARIANT_MARGIN = 0.03  # relative time a variant must save over the default
 
 
@@ -57,14 +62,37 @@ def _time(torch, call, stream, reps):
     return a.elapsed_time(b) / reps * 1e3
 
 
+def choose_variant(samples: dict, margin: float = VARIANT_MARGIN) -> tuple[str, str]:
+    """The variant to use from round times (samples[name][workload] = list of
+    microseconds per launch): the fastest by mean relative median among those
+    that beat the default on every workload by more than `margin` of its
+    median and by more than the spread (every round time below every round
+    time of the default); the default if none does.  Returns (name, reason)."""
+    base = samples["default"]
+    ok = {}
+    for name, ks in samples.items():
+        if name == "default":
+            continue
+        wins = all(np.median(t) < (1.0 - margin) * np.median(base[k]) and max(t) < min(base[k])
+                   for k, t in ks.items())
+        if wins:
+            ok[name] = float(np.mean([np.median(t) / np.median(base[k]) for k, t in ks.items()]))
+    if not ok:
+        return "default", (f"no variant beat the default on every workload by more than {margin:.0%} "
+                           "and beyond the spread of its round times")
+    best = min(ok, key=lambda n: (ok[n], binding.VARIANTS[n]))
+    return best, f"{best} beat the default on every workload (mean relative median {ok[best]:.3f})"
+
+
 def autotune(data: bytes, offsets: np.ndarray, single: bytes | None = None, classes=range(12, 29),
-             reps: int = 20, log=None) -> dict:
+             reps: int = 20, log=None, variants: bool = True) -> dict:
     """Measure every size class b on a prefix of the batch (whole documents,
-    about 1.5 * 2^b bytes) and, if given, a prefix of one large document, at
-    each candidate tile size; keep the size with the smallest sum of times
-    relative to the best of each workload (ties: the larger tile).  Classes
-    that neither input reaches keep the built-in choice.  Sets the table in
-    the library and returns it with the timings (microseconds per launch)."""
+    about 1.5 * 2^b bytes) at each candidate tile size; keep the size with
+    the smallest time (ties: the larger tile).  Classes the batch does not
+    reach keep the built-in choice.  Then, if `variants`, time the kernel
+    variants on the whole batch and on `single` (one document) and keep one by
+    choose_variant.  Sets both in the library and returns them with the
+    timings (microseconds per launch) and the reason for the variant."""
     import ctypes
     import torch
     VP = ctypes.c_void_p
@@ -81,7 +109,7 @@ def autotune(data: bytes, offsets: np.ndarray, single: bytes | None = None, clas
     cnt = torch.empty(max(1, nd_all), dtype=torch.int32, device=dev)
     err = torch.empty(max(1, nd_all), dtype=torch.int32, device=dev)
     sbuf = torch.frombuffer(bytearray(single), dtype=torch.uint8).to(dev) if single else None
-    binding.reserve(cap, stream)
+    binding.reserve(cap, stream, max_ndocs=nd_all)
     b0, o0, out0, c0, e0 = bufs.data_ptr(), offs.data_ptr(), out.data_ptr(), cnt.data_ptr(), err.data_ptr()
 
     def batch_call(nd):
@@ -92,72 +120,60 @@ def autotune(data: bytes, offsets: np.ndarray, single: bytes | None = None, clas
 
     table = [0] * 64
     timings = {}
-    variant, variant_us = 0, {}
+    variant, variant_us, reason = 0, {}, "variants not tuned"
     try:
         binding.set_variant(0)
         binding.set_tile_rows([])
         _time(torch, batch_call(nd_all), stream, 10)  # clocks up, memory touched
         for b in classes:
-            work = {}
             want = int(1.5 * (1 << b))
             nd = int(np.searchsorted(offsets, offsets[0] + want, side="right")) - 1
             nd = max(1, min(nd, nd_all))
             got = int(offsets[nd] - offsets[0])
-            if (1 << b) <= got < (1 << (b + 1)) - 16:
-                work["batch"] = (batch_call(nd), got, nd)
-            if single:
-                n = min(len(single), want)
-                if (1 << b) <= n < (1 << (b + 1)) - 16:
-                    work["single"] = (single_call(n), n, 1)
-            if not work:
+            if not (1 << b) <= got < (1 << (b + 1)) - 16:
                 continue
-            res = {k: {} for k in work}
+            call = batch_call(nd)
+            res = {}
             for r in CANDIDATES:
                 t = [0] * 64
                 t[b] = r
                 binding.set_tile_rows(t)
-                for k, (call, _, _) in work.items():
-                    res[k][r] = _time(torch, call, stream, reps)
-            score = {r: sum(res[k][r] / min(res[k].values()) for k in work) for r in CANDIDATES}
-            best = min(CANDIDATES, key=lambda r: (score[r], -r))
+                res[r] = _time(torch, call, stream, reps)
+            best = min(CANDIDATES, key=lambda r: (res[r], -r))
             table[b] = best
-            timings[b] = {k: {"bytes": work[k][1], "docs": work[k][2],
-                              "us": {str(r): round(v, 2) for r, v in res[k].items()}} for k in work}
-            timings[b]["rows"] = best
+            timings[b] = {"bytes": got, "docs": nd, "us": {str(r): round(v, 2) for r, v in res.items()}, "rows": best}
             if log:
-                log(f"tune: class 2^{b}: " + "; ".join(
-                    f"{k} ({work[k][1]} B): " + " ".join(f"{r}:{res[k][r]:.1f}" for r in CANDIDATES) for k in work)
-                    + f" us -> {best} rows")
+                log(f"tune: class 2^{b}: batch of {nd} docs ({got} B): "
+                    + " ".join(f"{r}:{res[r]:.1f}" for r in CANDIDATES) + f" us -> {best} rows")
         binding.set_tile_rows(table)
-        work = {"batch": batch_call(nd_all)}
-        if single:
-            work["single"] = single_call(len(single))
-        # rounds over the variants in turn (a drift of the device hits all
-        # alike); the median per variant and workload
-        samples = {name: {k: [] for k in work} for name in binding.VARIANTS}
-        for _ in range(VARIANT_ROUNDS):
-            for name, v in binding.VARIANTS.items():
-                binding.set_variant(v)
-                for k, call in work.items():
-                    samples[name][k].append(_time(torch, call, stream, max(5, reps // 2)))
-        variant_us = {name: {k: round(float(np.median(t)), 2) for k, t in ks.items()} for name, ks in samples.items()}
-        score = {name: sum(variant_us[name][k] / variant_us["default"][k] for k in work) / len(work)
-                 for name in variant_us}
-        # another variant replaces the default only when clearly faster
-        chosen = min(variant_us, key=lambda name: (score[name], binding.VARIANTS[name]))
-        if score[chosen] > 1.0 - VARIANT_MARGIN:
-            chosen = "default"
-        variant = binding.VARIANTS[chosen]
-        if log:
-            log("tune: variants " + "; ".join(f"{name}: " + " ".join(f"{k} {t:.1f}" for k, t in us.items())
-                                              for name, us in variant_us.items()) + f" us -> {chosen}")
+        if variants:
+            work = {"batch": batch_call(nd_all)}
+            if single:
+                work["single"] = single_call(len(single))
+            # rounds over the variants in turn (a drift of the device hits all alike)
+            samples = {name: {k: [] for k in work} for name in binding.VARIANTS}
+            for _ in range(VARIANT_ROUNDS):
+                for name, v in binding.VARIANTS.items():
+                    binding.set_variant(v)
+                    for k, call in work.items():
+                        samples[name][k].append(_time(torch, call, stream, max(5, reps // 2)))
+            variant_us = {name: {k: {"median": round(float(np.median(t)), 2), "min": round(min(t), 2),
+                                     "max": round(max(t), 2)} for k, t in ks.items()}
+                          for name, ks in samples.items()}
+            chosen, reason = choose_variant(samples)
+            variant = binding.VARIANTS[chosen]
+            if log:
+                log("tune: variants " + "; ".join(
+                    f"{name}: " + " ".join(f"{k} {t['median']:.1f} [{t['min']:.1f}..{t['max']:.1f}]"
+                                           for k, t in us.items()) for name, us in variant_us.items())
+                    + f" us -> {chosen} ({reason})")
     finally:
         binding.set_variant(0)
         binding.release(stream)
     binding.set_tile_rows(table)
     binding.set_variant(variant)
     return {"arch": _arch(torch), "table": table, "timings": timings, "variant": variant, "variant_us": variant_us,
-            "when": time.strftime("%Y-%m-%d %H:%M:%S")}
+            "variant_reason": reason, "when": time.strftime("%Y-%m-%d %H:%M:%S")}
 
 
 def save(result: dict, path: str | None = None) -> str:

@@ -79,3 +79,47 @@ def test_serving_loop_over_many_turns_of_the_ring():
         assert np.array_equal(gi[a:a + n], oi[a:a + n]), f"slot {d} differs"
     for st in streams:
         assert jx.diag(st) == 0
+
+
+def test_forced_small_budget_binds_and_results_hold():
+    """Admission by device memory with a budget far below one turn of the
+    ring (room for about five of its largest requests): held bytes never pass
+    the budget, the loop waits for completions and cuts batches, and every
+    slot still holds the result of indexing its document alone and the
+    oracle's."""
+    import torch
+    import paper_1902_08318_amd as jx
+    from paper_1902_08318_amd import serve, synth
+    data, offs = synth.gen_c4(9, ring_bytes=6 << 20, hi=256 << 10, pool=40)
+    nd = offs.size - 1
+    biggest = int(np.diff(offs.astype(np.int64)).max())
+    budget = serve.REQUEST_BYTES_PER_BYTE * 5 * biggest
+    assert budget < serve.REQUEST_BYTES_PER_BYTE * len(data)
+    _say(f"case: forced budget {budget} bytes, ring {len(data)} bytes, {nd} docs, 3 streams")
+    streams = [torch.cuda.Stream() for _ in range(3)]
+    ring = serve.Ring(data, offs, 4 << 20, streams)
+    ring.cnt.fill_(-1)
+    ring.err.fill_(-1)
+    torch.cuda.synchronize()
+    st = serve.Admission(budget)
+    arr = np.zeros(2 * nd)  # everything waiting at once: the budget is the only limit
+    lat, el, served, batches = serve.serve(ring, arr, budget, st)
+    torch.cuda.synchronize()
+    _say(f"peak held {st.peak_held_bytes}, waits {st.admission_waits}, cut batches {st.budget_cut_batches}")
+    assert served == 2 * len(data) and np.all(lat > 0)
+    assert 0 < st.peak_held_bytes <= budget
+    assert st.admission_waits > 0 and st.budget_cut_batches > 0
+    on_n = ring.cnt.cpu().numpy().view(np.uint32)
+    on_e = ring.err.cpu().numpy().view(np.uint32)
+    gi = ring.out[:len(data)].cpu().numpy().view(np.uint32)
+    oi, on, oe = oracle.index_batch(np.frombuffer(data, dtype=np.uint8), offs)
+    assert np.array_equal(on_n, on) and np.array_equal(on_e, oe)
+    for d in range(nd):
+        a, b = int(offs[d]), int(offs[d + 1])
+        assert np.array_equal(gi[a:a + on[d]], oi[a:a + on[d]]), f"slot {d} differs from the oracle"
+        if d % 7 == 0:
+            alone, n, e = jx.index(ring.bufs[a:b].clone())
+            assert n == on_n[d] and e == on_e[d]
+            assert np.array_equal(alone.cpu().numpy().view(np.uint32), gi[a:a + n]), f"doc {d}: alone vs mix"
+    for s in streams:
+        assert jx.diag(s) == 0

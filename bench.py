@@ -29,7 +29,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "structural-index GB/s (1 doc & batched) vs HBM peak; docs/s; p99 latency"
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = ["jsidx.hip", "jsidx_host.h", "jsidx_doc.h", "jsidx_kernel.h", "jsidx_device.h", "jsidx_prims.h"]
+KERNEL_SOURCES = ["jsidx.hip", "jsidx_doc.h", "jsidx_kernel.h", "jsidx_device.h", "jsidx_prims.h"]
 PROFILE = os.path.join(ROOT, "profiles", "doc_kernel_c1_256MiB.md")
 
 

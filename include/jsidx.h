@@ -139,7 +139,7 @@ int jsidx_build_batch(const uint8_t *bufs, const uint64_t *offsets,
  * jsidx_build, for documents of at most JSIDX_NOALLOC_MAX_LEN bytes (larger
  * ones return JSIDX_E_TOO_LARGE and launch nothing).  The call never
  * allocates or frees memory: its workspace is a fixed device array inside the
- * library (about 65 MiB on every device the library runs on, held until the
+ * library (168.5 KiB on every device the library runs on, held until the
  * process ends), zeroed by a small kernel on `stream` the first time the
  * device is used.  Every call on one device shares that array, so calls that
  * overlap in time on one device (on different streams, or from several host

@@ -157,7 +157,7 @@ int get_ws(hipStream_t stream, uint64_t need_tiles, bool grow, StreamWs** out) {
   if (!grow) return JSIDX_OK;
   Workspace* p = alloc_ws(stream, need_tiles);
   if (!p) return JSIDX_E_NOWORKSPACE;
-  g_ws.push_back(StreamWs{dev, stream, p, need_tiles, reserved});
+  g_ws.push_back(StreamWs{dev, stream, p, need_tiles, reserved, doc_region_offset(need_tiles)});
   *out = &g_ws.back();
   return JSIDX_OK;
 }
@@ -219,7 +219,7 @@ int launch_doc(const uint8_t* buf, uint64_t len, uint32_t* out, uint32_t* out_n,
   a.out_n = out_n;
   a.out_err = out_err;
   a.ws = e.ws;
-  uint8_t* region = reinterpret_cast<uint8_t*>(e.ws) + doc_region_offset(e.cap_tiles);
+  uint8_t* region = reinterpret_cast<uint8_t*>(e.ws) + e.doc_off;
   a.cap = doc_cap_for(e.cap_tiles);
   a.desc = reinterpret_cast<uint64_t*>(region);
   a.blk = a.desc + a.cap;

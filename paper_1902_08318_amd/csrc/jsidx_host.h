@@ -17,6 +17,7 @@ struct StreamWs {
   Workspace* ws;
   uint64_t cap_tiles;  // in largest tiles
   bool reserved;  // sized by jsidx_reserve: batch calls trust it and never sync
+  uint64_t doc_off;  // byte offset of the one-document kernel's region from ws
 };
 
 // Guards the library's host state (workspaces, tuning table, variant).

@@ -13,13 +13,18 @@
 namespace jsidx {
 
 // ---- a workspace that needs no allocation ----------------------------------
-// jsidx_build_noalloc runs the same launch over a workspace in a file-scope
-// device array.  Each device holds its own copy until the process ends; its
-// device address is taken once per device (hipGetSymbolAddress) and only that
-// address is ever passed to a kernel.
+// jsidx_build_noalloc runs the one-document kernel over a workspace in a
+// file-scope device array: the header (counters, epoch, diagnostic) and the
+// kernel's region (tile descriptors, block words and counters) right after it;
+// that kernel keeps its masks in LDS, so nothing else is needed.  Each device
+// holds its own copy until the process ends; its device address is taken once
+// per device (hipGetSymbolAddress) and only that address is ever passed to a
+// kernel.
 constexpr uint64_t kStaticTiles = (JSIDX_NOALLOC_MAX_LEN + 15 + kTileBytes - 1) / kTileBytes;
-constexpr uint64_t kStaticWsBytes = (stream_ws_bytes(kStaticTiles) + 255) & ~(uint64_t)255;
-static_assert(kStaticWsBytes <= (80ull << 20), "the static workspace stays modest");
+constexpr uint64_t kStaticDocOff = 256;
+constexpr uint64_t kStaticWsBytes = (kStaticDocOff + doc_region_bytes(kStaticTiles) + 255) & ~(uint64_t)255;
+static_assert(sizeof(Workspace) <= kStaticDocOff, "the header fits before the region");
+static_assert(kStaticWsBytes <= (1ull << 20), "the static workspace stays modest");
 static __device__ __align__(256) uint8_t scratch[kStaticWsBytes];
 
 struct StaticWs {
@@ -34,9 +39,7 @@ __global__ void __launch_bounds__(256) zero_words(uint64_t* p, uint64_t n) {
 }
 
 // The static workspace of the current device, set up on first use: its
-// address, and its header and both kernels' descriptors, block words and
-// counters zeroed on `stream` (the mask slots are written before they are
-// read).  Caller holds g_mu.
+// address, and all of it zeroed on `stream`.  Caller holds g_mu.
 int static_ws(hipStream_t stream, StreamWs* out) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return JSIDX_E_HIP;
@@ -45,16 +48,13 @@ int static_ws(hipStream_t stream, StreamWs* out) {
   if (!s.ready) {
     void* p = nullptr;
     if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return JSIDX_E_HIP;
-    const uint64_t words = mask_offset(desc_slots(kStaticTiles)) / 8;
-    const uint64_t doc0 = doc_region_offset(kStaticTiles) / 8, doc_words = (doc_region_bytes(kStaticTiles) + 7) / 8;
     (void)hipGetLastError();
-    hipLaunchKernelGGL(zero_words, dim3(64), dim3(256), 0, stream, (uint64_t*)p, words);
-    hipLaunchKernelGGL(zero_words, dim3(16), dim3(256), 0, stream, (uint64_t*)p + doc0, doc_words);
+    hipLaunchKernelGGL(zero_words, dim3(64), dim3(256), 0, stream, (uint64_t*)p, kStaticWsBytes / 8);
     if (hipGetLastError() != hipSuccess) return JSIDX_E_HIP;
     s.ptr = p;
     s.ready = true;
   }
-  *out = StreamWs{dev, stream, (Workspace*)s.ptr, kStaticTiles, true};
+  *out = StreamWs{dev, stream, (Workspace*)s.ptr, kStaticTiles, true, kStaticDocOff};
   return JSIDX_OK;
 }
 

@@ -63,10 +63,11 @@ constexpr int kDocStage = kDocRows * kThreads * 2;  // uint32 entries of a tile'
 #endif
 constexpr int kDocSlots = JSIDX_DOC_SLOTS;
 static_assert(kDocSlots >= 2 && kDocSlots <= 4, "mask slots per wave");
-// A row is written through LDS (coalesced stores) when some lane holds more
-// than this many positions; otherwise each lane stores its own.
+// A row is written through LDS (coalesced stores, four positions per lane and
+// store) when some lane holds more than this many positions; otherwise each
+// lane stores its own.
 #ifndef JSIDX_DOC_STAGE_LANE
-#define JSIDX_DOC_STAGE_LANE 8
+#define JSIDX_DOC_STAGE_LANE 5
 #endif
 static_assert(kDocBlock >= 1 && kDocBlock <= 64, "a block is read by one wave");
 static_assert(kDocTile <= 32768, "tile counts fit in 15 bits");
@@ -125,7 +126,9 @@ JSIDX_DEV uint32_t dd_c1(uint64_t d) { return (uint32_t)(d >> 22) & 0x7FFFu; }
 JSIDX_DEV uint32_t dd_count(uint64_t d) { return (uint32_t)(d >> 7); }
 
 // Block words (cleared at the end of every launch, so no epoch):
-//   aggregate: 1 | q flip << 2 | u << 3 | C0 << 4 (30 bits) | C1 << 34 (30 bits)
+//   aggregate: 1 | q flip << 2 | u << 3 | C0 << 4 (30 bits) | C1 << 34 (30 bits),
+//              set by an atomic OR; bit 1 (kBlkPrev) is ORed in by the chain of
+//              inclusive values when it reaches the block (see doc_chain)
 //   inclusive: 2 | q << 2 | u << 3 | count << 4
 JSIDX_DEV uint64_t blk_agg(uint32_t qf, uint32_t u, uint32_t c0, uint32_t c1) {
   return 1ull | ((uint64_t)qf << 2) | ((uint64_t)u << 3) | ((uint64_t)(c0 & 0x3FFFFFFFu) << 4) |
@@ -134,6 +137,7 @@ JSIDX_DEV uint64_t blk_agg(uint32_t qf, uint32_t u, uint32_t c0, uint32_t c1) {
 JSIDX_DEV uint64_t blk_inc(uint32_t q, uint32_t u, uint32_t count) {
   return 2ull | ((uint64_t)q << 2) | ((uint64_t)u << 3) | ((uint64_t)count << 4);
 }
+constexpr uint64_t kBlkPrev = 2ull;
 
 struct DocArgs {
   const uint8_t* base;  // the document: base[0 .. len)
@@ -153,7 +157,7 @@ struct DocArgs {
 // Per-wave LDS: the masks (K, F0) of two tiles, one in its local pass and one
 // waiting for its finish pass; a finishing tile's slot doubles as the
 // flatten staging buffer once its masks are in registers.
-struct DocWaveShared {
+struct alignas(16) DocWaveShared {
   uint2 m[kDocSlots][kDocRows][kThreads];
 };
 struct DocGroupShared {
@@ -726,14 +730,14 @@ JSIDX_DEV bool doc_block_entry(const DocArgs& a, int64_t b, DocFold* out) {
     const int n = (int)(hi - lo);
     const int64_t j = lo + (int64_t)lane;
     uint64_t inc = 0, agg = 0;
-    if ((int)lane < n) {
+    if ((int)lane < n) {  // both words at once: one round trip
+      agg = prim::ld_agent(a.blk + 2 * j);
       inc = prim::ld_agent(a.blk + 2 * j + 1);
-      if ((inc & 3u) != 2u) agg = prim::ld_agent(a.blk + 2 * j);
     }
     uint32_t kind = 0, q = 0, u = 0, c0 = 0, c1 = 0;
     if ((inc & 3u) == 2u) {
       kind = 2; q = (uint32_t)(inc >> 2) & 1u; u = (uint32_t)(inc >> 3) & 1u; c0 = (uint32_t)(inc >> 4);
-    } else if ((agg & 3u) == 1u) {
+    } else if ((agg & 1u) != 0u) {
       kind = 1; q = (uint32_t)(agg >> 2) & 1u; u = (uint32_t)(agg >> 3) & 1u;
       c0 = (uint32_t)(agg >> 4) & 0x3FFFFFFFu; c1 = (uint32_t)(agg >> 34) & 0x3FFFFFFFu;
     }
@@ -803,6 +807,7 @@ JSIDX_DEV bool doc_look_back(const DocArgs& a, int64_t t, uint32_t epoch, DocFol
     const uint32_t c0 = kind == 2u ? dd_count(d) : dd_c0(d), c1 = dd_c1(d);
     DocFold F = doc_fold(kind, q, u, c0, c1, n);
     if (F.pending) {
+      prim::dcount(t, 1u);
       if (++polls > prim::kSpinLimit) { prim::st_agent32(&a.ws->diag, 1u); return false; }
       doc_poll_sleep(polls);
       continue;
@@ -814,8 +819,9 @@ JSIDX_DEV bool doc_look_back(const DocArgs& a, int64_t t, uint32_t epoch, DocFol
       const uint64_t bv = ((uint64_t)bhi << 32) | blo;
       if ((bv & 3u) == 2u) {
         entry.q = (uint32_t)(bv >> 2) & 1u; entry.u = (uint32_t)(bv >> 3) & 1u; entry.c0 = (uint32_t)(bv >> 4);
-      } else if (!doc_block_entry(a, b, &entry)) {
-        return false;
+      } else {
+        prim::dcount(t, 1u << 8);
+        if (!doc_block_entry(a, b, &entry)) return false;
       }
     }
     *out = n == 0 ? entry : doc_then(entry, F);
@@ -823,10 +829,62 @@ JSIDX_DEV bool doc_look_back(const DocArgs& a, int64_t t, uint32_t epoch, DocFol
   }
 }
 
-// The last tile of a block to publish folds the block's tile descriptors and
-// publishes the block's aggregate, and its inclusive value if the state
-// entering the block is already known.
-JSIDX_DEV void doc_fold_block(const DocArgs& a, int64_t b, uint32_t epoch) {
+// The chain of block inclusive values.  With the state after block x - 1
+// known (E), it publishes the inclusive values of blocks x, x + 1, ... whose
+// aggregates are in, 64 blocks per read (a scan over the lanes), and stops at
+// the first block without one, handing the chain over: it ORs kBlkPrev into
+// that block's aggregate word, and that block's fold ORs its aggregate into
+// the same word; whichever of the two comes second (it sees the other's bit)
+// continues the chain, so exactly one does, and the block inclusive values
+// follow the folds closely.
+JSIDX_DEV DocFold blk_state_agg(uint64_t w) {
+  DocFold F;
+  F.known = 0; F.pending = 0;
+  F.q = (uint32_t)(w >> 2) & 1u; F.u = (uint32_t)(w >> 3) & 1u;
+  F.c0 = (uint32_t)(w >> 4) & 0x3FFFFFFFu; F.c1 = (uint32_t)(w >> 34) & 0x3FFFFFFFu;
+  return F;
+}
+
+JSIDX_DEV void doc_chain(const DocArgs& a, int64_t x, DocFold E) {
+  const uint32_t lane = prim::lane();
+  const int64_t nb = (a.ntiles + kDocBlock - 1) / kDocBlock;
+  while (x < nb) {
+    const int64_t j = x + (int64_t)lane;
+    uint64_t w = 0;
+    if (j < nb) w = prim::ld_agent(a.blk + 2 * j);
+    const uint64_t ready = prim::ballot(j < nb && (w & 1ull) != 0ull);
+    const int g = ~ready ? (int)__builtin_ctzll(~ready) : 64;  // blocks [x, x + g) are in
+    if (g > 0) {
+      const bool in = (int)lane < g;
+      const DocFold A = blk_state_agg(w);
+      const uint32_t q_in = E.q ^ (prim::mbcnt(prim::ballot(in && A.q != 0u)) & 1u);
+      const uint32_t cnt = E.c0 + prim::incl_scan(in ? (q_in ? A.c1 : A.c0) : 0u);
+      const uint32_t qo = q_in ^ A.q;
+      const uint32_t uo = E.u | ((prim::ballot(in && A.u != 0u) & lanes_below((int)lane + 1)) != 0ull ? 1u : 0u);
+      if (in) prim::st_agent(a.blk + 2 * j + 1, blk_inc(qo, uo, cnt));
+      E.q = prim::readlane(qo, g - 1);
+      E.u = prim::readlane(uo, g - 1);
+      E.c0 = prim::readlane(cnt, g - 1);
+      x += g;
+    }
+    if (g == 64 || x >= nb) continue;
+    uint64_t old = 0;
+    if (lane == 0) old = prim::or_agent64(a.blk + 2 * x, kBlkPrev);
+    const uint32_t olo = prim::readlane((uint32_t)old, 0), ohi = prim::readlane((uint32_t)(old >> 32), 0);
+    old = ((uint64_t)ohi << 32) | olo;
+    if ((old & 1ull) == 0ull || (old & kBlkPrev) != 0ull) return;  // the block's fold continues
+    E = doc_then(E, blk_state_agg(old));
+    if (lane == 0) prim::st_agent(a.blk + 2 * x + 1, blk_inc(E.q, E.u, E.c0));
+    x += 1;
+  }
+}
+
+// The last tile of a block to publish folds the block's tile descriptors:
+// it publishes the block's inclusive value if a tile of the block already
+// has one (and carries the chain on from there), else ORs the aggregate into
+// the block's aggregate word, and carries the chain on if it had reached the
+// block.
+JSIDX_DEV void doc_fold_block(const DocArgs& a, int64_t b, uint32_t epoch, int64_t t) {
   const uint32_t lane = prim::lane();
   const int64_t j0 = b * kDocBlock;
   const int64_t n64 = a.ntiles - j0 < kDocBlock ? a.ntiles - j0 : kDocBlock;
@@ -839,28 +897,39 @@ JSIDX_DEV void doc_fold_block(const DocArgs& a, int64_t b, uint32_t epoch) {
     const uint32_t kind = ok ? dd_flag(d) : 0u;
     F = doc_fold(kind, dd_q(d), dd_u(d), kind == 2u ? dd_count(d) : dd_c0(d), dd_c1(d), n);
     if (!F.pending) break;
-    // every tile of the block has counted itself after its store completed;
-    // a stale read is retried
+    // a descriptor whose store is still on its way reads as not published:
+    // read again
+    prim::dcount(t, 1ull << 16);
     if (++polls > prim::kSpinLimit) { prim::st_agent32(&a.ws->diag, 1u); return; }
     doc_poll_sleep(polls);
   }
-  if (lane == 0) {
-    if (F.known) {
-      prim::st_agent(a.blk + 2 * b + 1, blk_inc(F.q, F.u, F.c0));
-    } else {
-      prim::st_agent(a.blk + 2 * b, blk_agg(F.q, F.u, F.c0, F.c1));
-      if (b > 0) {
-        const uint64_t pv = prim::ld_agent(a.blk + 2 * (b - 1) + 1);
-        if ((pv & 3u) == 2u) {
-          DocFold E;
-          E.known = 1; E.pending = 0; E.q = (uint32_t)(pv >> 2) & 1u; E.u = (uint32_t)(pv >> 3) & 1u;
-          E.c0 = (uint32_t)(pv >> 4); E.c1 = 0;
-          const DocFold W = doc_then(E, F);
-          prim::st_agent(a.blk + 2 * b + 1, blk_inc(W.q, W.u, W.c0));
-        }
-      }
-    }
+  if (F.known) {
+    if (lane == 0) prim::st_agent(a.blk + 2 * b + 1, blk_inc(F.q, F.u, F.c0));
+    doc_chain(a, b + 1, F);
+    return;
   }
+  uint64_t old = 0;
+  if (lane == 0) old = prim::or_agent64(a.blk + 2 * b, blk_agg(F.q, F.u, F.c0, F.c1));
+  if ((prim::readlane((uint32_t)old, 0) & (uint32_t)kBlkPrev) == 0u) return;
+  // the chain is waiting here: the block before has its inclusive value
+  // (stored before the chain's OR; read until it shows)
+  DocFold E;
+  for (uint32_t polls = 0;;) {
+    uint64_t pv = 0;
+    if (lane == 0) pv = prim::ld_agent(a.blk + 2 * (b - 1) + 1);
+    const uint32_t plo = prim::readlane((uint32_t)pv, 0), phi = prim::readlane((uint32_t)(pv >> 32), 0);
+    pv = ((uint64_t)phi << 32) | plo;
+    if ((pv & 3u) == 2u) {
+      E.known = 1; E.pending = 0; E.q = (uint32_t)(pv >> 2) & 1u; E.u = (uint32_t)(pv >> 3) & 1u;
+      E.c0 = (uint32_t)(pv >> 4); E.c1 = 0;
+      break;
+    }
+    if (++polls > prim::kSpinLimit) { prim::st_agent32(&a.ws->diag, 1u); return; }
+    doc_poll_sleep(polls);
+  }
+  const DocFold W = doc_then(E, F);
+  if (lane == 0) prim::st_agent(a.blk + 2 * b + 1, blk_inc(W.q, W.u, W.c0));
+  doc_chain(a, b + 1, W);
 }
 
 // The escape state entering tile t when the bytes before it are 64 or more
@@ -980,7 +1049,10 @@ JSIDX_DEV void doc_after_count(const DocArgs& a, int64_t t, uint32_t oldv, uint3
   const uint32_t old = prim::readlane(oldv, 0);
   const int64_t b = t / kDocBlock;
   const int64_t nb = a.ntiles - b * kDocBlock < kDocBlock ? a.ntiles - b * kDocBlock : kDocBlock;
-  if ((int64_t)old == nb - 1) doc_fold_block(a, b, epoch);
+  if ((int64_t)old == nb - 1) {
+    prim::dcount(t, 1ull << 24);
+    doc_fold_block(a, b, epoch, t);
+  }
   prim::dtrace(t, 2);
 }
 
@@ -1010,7 +1082,12 @@ JSIDX_DEV void doc_write_row(uint32_t* out, uint32_t* stage, uint32_t* half, uin
       sb[k++] = rel + j;
     }
     prim::wave_sync();
-    for (uint32_t i = prim::lane(); i < row_n; i += (uint32_t)kThreads) prim::st_out(out + base + i, sb[i]);
+    // four positions per lane and store, then the last few one by one
+    const uint32_t full = row_n & ~3u;
+    for (uint32_t i = 4u * prim::lane(); i < full; i += 4u * (uint32_t)kThreads)
+      prim::st_out4(out + base + i, prim::ld_lds128(sb + i));
+    const uint32_t i = full + prim::lane();
+    if (i < row_n) prim::st_out(out + base + i, sb[i]);
     return;
   }
   uint32_t k = base + incl - n;
@@ -1062,11 +1139,14 @@ JSIDX_DEV uint32_t doc_next_tile(const DocArgs& a, DocPre* S) {
   return nx;
 }
 
-// Tile T's look-back, then (once this wave no longer waits for anything) its
-// next ticket and first loads into *nx / *S, then T's positions.
+// Tile T's look-back; then the block fold of tile fold_t if it was the last
+// of its block to count itself (fold_cnt: the count's old value; fold_t < 0:
+// none), so that the fold waits for no flatten; then (once this wave no
+// longer waits for anything) its next ticket and first loads into *nx / *S,
+// then T's positions.
 template <int VAR>
 JSIDX_DEV void doc_finish_tile(const DocArgs& a, DocWaveShared& sh, const DocTile& T, uint32_t epoch, uint32_t* nx,
-                               DocPre* pre, const LbPre* lb) {
+                               DocPre* pre, const LbPre* lb, int64_t fold_t = -1, uint32_t fold_cnt = 0) {
   const uint32_t lane = prim::lane();
   const int64_t t = T.t;
   DocFold S0;
@@ -1081,6 +1161,7 @@ JSIDX_DEV void doc_finish_tile(const DocArgs& a, DocWaveShared& sh, const DocTil
     }
   }
   prim::dtrace(t, 4);
+  if (fold_t >= 0) doc_after_count(a, fold_t, fold_cnt, epoch);
   if (nx) *nx = doc_next_tile(a, pre);
   const DocFold& S = S0;
   // the rows' index masks, all loaded before the first write; the slot is
@@ -1118,7 +1199,7 @@ JSIDX_DEV void doc_finish_tile(const DocArgs& a, DocWaveShared& sh, const DocTil
 
 // ---- the launch ------------------------------------------------------------------------
 template <int VAR = 0>
-JSIDX_DEVFN void doc_tiles(const DocArgs& a) {
+JSIDX_DEV void doc_tiles(const DocArgs& a) {
   DocGroupShared& gs = prim::lds_object<DocGroupShared>();
   const uint32_t wv = prim::wave_id();
   DocWaveShared& sh = gs.w[wv];
@@ -1157,14 +1238,14 @@ JSIDX_DEVFN void doc_tiles(const DocArgs& a) {
       const uint32_t cnt = doc_start_tile<VAR>(a, sh, T, epoch, S);
       uint32_t nx = 0;
       if (np == kDocSlots - 1) {
-        doc_finish_tile<VAR>(a, sh, pq[0], epoch, &nx, &S, &lb);
+        doc_finish_tile<VAR>(a, sh, pq[0], epoch, &nx, &S, &lb, T.t, cnt);
 #pragma unroll
         for (int i = 0; i + 1 < kDocSlots - 1; i++) pq[i] = pq[i + 1];
         np--;
       } else {
         nx = doc_next_tile(a, &S);
+        doc_after_count(a, T.t, cnt, epoch);
       }
-      doc_after_count(a, T.t, cnt, epoch);
 #pragma unroll
       for (int i = 0; i < kDocSlots - 1; i++)
         if (i == np) pq[i] = T;

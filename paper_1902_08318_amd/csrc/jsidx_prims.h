@@ -118,8 +118,13 @@ JSIDX_DEV void dtrace(int64_t t, int k) {
     if (k == 0) g_probe[t * 8 + 7] = (uint64_t)__builtin_amdgcn_s_getreg((4 << 0) | (0 << 6) | (31 << 11));
   }
 }
+// Probe builds only: adds v to tile t's counter word (slot 6).
+JSIDX_DEV void dcount(int64_t t, uint64_t v) {
+  if (g_probe && __lane_id() == 0) g_probe[t * 8 + 6] += v;
+}
 #else
 JSIDX_DEV void dtrace(int64_t, int) {}
+JSIDX_DEV void dcount(int64_t, uint64_t) {}
 #endif
 
 JSIDX_DEV uint4 load16(const uint8_t* p) { return *reinterpret_cast<const uint4*>(p); }
@@ -127,7 +132,19 @@ JSIDX_DEV uint32_t load4(const uint8_t* p) { return *reinterpret_cast<const uint
 JSIDX_DEV uint64_t load8(const uint64_t* p) { return *p; }
 JSIDX_DEV uint32_t load1(const uint8_t* p) { return *p; }
 JSIDX_DEV uint32_t or_agent32(uint32_t* p, uint32_t v) { return atomicOr(p, v); }
+JSIDX_DEV uint64_t or_agent64(uint64_t* p, uint64_t v) {
+  return __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 JSIDX_DEV void st_out(uint32_t* p, uint32_t v) { *p = v; }
+// 16 bytes to a 4-byte aligned global address (one vector store: global
+// accesses only need dword alignment).
+typedef uint32_t u32x4_a4 __attribute__((ext_vector_type(4), aligned(4)));
+JSIDX_DEV void st_out4(uint32_t* p, uint4 v) {
+  const u32x4_a4 w = {v.x, v.y, v.z, v.w};
+  *reinterpret_cast<u32x4_a4*>(p) = w;
+}
+// 16 bytes from a 16-byte aligned LDS address.
+JSIDX_DEV uint4 ld_lds128(const uint32_t* p) { return *reinterpret_cast<const uint4*>(p); }
 JSIDX_DEV void st_byte(uint8_t* p, uint32_t v) { *p = (uint8_t)v; }
 JSIDX_DEV void st_pair(uint2* p, uint32_t x, uint32_t y) { *p = make_uint2(x, y); }
 JSIDX_DEV uint2 ld_pair(const uint2* p) { return *p; }

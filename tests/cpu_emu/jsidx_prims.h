@@ -210,6 +210,7 @@ inline void st_agent(uint64_t* p, uint64_t v) { __atomic_store_n(p, v, __ATOMIC_
 inline void st_agent32(uint32_t* p, uint32_t v) { __atomic_store_n(p, v, __ATOMIC_RELAXED); }
 inline uint32_t add_agent32(uint32_t* p, uint32_t v) { return __atomic_fetch_add(p, v, __ATOMIC_RELAXED); }
 inline uint32_t or_agent32(uint32_t* p, uint32_t v) { return __atomic_fetch_or(p, v, __ATOMIC_RELAXED); }
+inline uint64_t or_agent64(uint64_t* p, uint64_t v) { return __atomic_fetch_or(p, v, __ATOMIC_RELAXED); }
 inline void min_lds(int32_t* p, int32_t v) {
   int32_t cur = __atomic_load_n(p, __ATOMIC_RELAXED);
   while (v < cur && !__atomic_compare_exchange_n(p, &cur, v, false, __ATOMIC_RELAXED, __ATOMIC_RELAXED)) {
@@ -229,6 +230,7 @@ inline T& lds_object() {
 inline void trace(int64_t, int) {}
 inline void trace_count(int64_t, int) {}
 inline void dtrace(int64_t, int) {}
+inline void dcount(int64_t, uint64_t) {}
 
 inline uint4 load16(const uint8_t* p) {
   check(p, 16, false);
@@ -257,6 +259,23 @@ inline uint64_t load8(const uint64_t* p) {
 inline void st_out(uint32_t* p, uint32_t v) {
   check(p, 4, true);
   *p = v;
+}
+inline void st_out4(uint32_t* p, uint4 v) {
+  check(p, 16, true);
+  if ((uintptr_t)p & 3) {
+    fprintf(stderr, "cpu_emu: misaligned 16-byte store at %p\n", (void*)p);
+    tctx.env->violations++;
+  }
+  memcpy(p, &v, 16);
+}
+inline uint4 ld_lds128(const uint32_t* p) {
+  if ((uintptr_t)p & 15) {
+    fprintf(stderr, "cpu_emu: misaligned 16-byte LDS read at %p\n", (const void*)p);
+    tctx.env->violations++;
+  }
+  uint4 v;
+  memcpy(&v, p, 16);
+  return v;
 }
 inline void st_byte(uint8_t* p, uint32_t v) {
   check(p, 1, true);

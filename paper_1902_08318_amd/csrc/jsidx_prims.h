@@ -59,7 +59,7 @@ JSIDX_DEV uint32_t incl_max_scan(uint32_t v) {
 // Value of the previous lane (DPP wave_shr:1); lane 0 gets `fill`.
 JSIDX_DEV uint32_t shr1(uint32_t v, uint32_t fill) { return __builtin_amdgcn_update_dpp(fill, v, 0x138, 0xF, 0xF, false); }
 // Value of the previous lane, lane 0 getting lane 63's (DPP wave_ror:1).
-JSIDX_DEV uint32_t ror1(uint32_t v) { return __builtin_amdgcn_update_dpp(0u, v, 0x13C, 0xF, 0xF, false); }
+JSIDX_DEV uint32_t ror1(uint32_t v) { return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x13C, 0xF, 0xF, false); }
 // (hi:lo >> s) truncated to 32 bits (v_alignbit_b32).
 JSIDX_DEV uint32_t alignbit(uint32_t hi, uint32_t lo, uint32_t s) { return __builtin_amdgcn_alignbit(hi, lo, s); }
 

@@ -209,12 +209,64 @@ int jsidx_minify_batch(const uint8_t *bufs, const uint64_t *offsets,
  * then each opener's partner is the first later entry of at most its depth)
  * and gives exactly the stack's links; the structure check then looks at each
  * entry, a few entries around it and the link of a closer just before a
- * comma.  A per-stream workspace of about 9 bytes per entry is allocated on first use and grown as needed
- * (synchronising the stream).  Asynchronous on `stream`.
+ * comma.  A per-stream workspace of about 9 bytes per entry is allocated on
+ * first use and grown as needed (synchronising the stream); after
+ * jsidx_scopes_reserve for at least n entries the call never allocates or
+ * synchronises, so it can be captured in a HIP graph.  Asynchronous on
+ * `stream`.
  */
 int jsidx_scopes(const uint8_t *buf, uint64_t len, const uint32_t *idx,
                  uint32_t n, uint32_t *out_match, uint32_t *out_err,
                  jsidx_stream_t stream);
+
+/*
+ * jsidx_scopes_batch -- jsidx_scopes for many independent documents in one
+ * call (the paper's stage 2 takes each document on its own, Sec. 3.2; here
+ * the documents' entries are laid end to end, the depth starts again at each
+ * document's first entry, and a document's levels are offset past every
+ * level of the documents before it, so that no link or check crosses into
+ * another document).
+ *   bufs       device pointer to the concatenated document bytes.
+ *   offsets    device array of ndocs+1 nondecreasing uint64, as for
+ *              jsidx_build_batch (document d is bufs[offsets[d] ..
+ *              offsets[d+1])).
+ *   ndocs      number of documents, >= 1.
+ *   idx        device array: document d's n[d] entries at idx + offsets[d],
+ *              positions relative to its first byte, as jsidx_build_batch
+ *              writes them.
+ *   n          device array of ndocs uint32: each document's entry count
+ *              (jsidx_build_batch's out_n).
+ *   out_match  device array laid out like idx: document d's links at
+ *              out_match + offsets[d], entry numbers relative to the
+ *              document (0xFFFFFFFF: unlinked or not a bracket).
+ *   out_err    device array of ndocs uint32: each document's flags, exactly
+ *              those jsidx_scopes gives for it alone.
+ * Results per document are identical to jsidx_scopes on that document.
+ * After jsidx_scopes_reserve(max_entries, max_ndocs) on the stream with
+ * max_ndocs >= ndocs, the call never allocates or synchronises (it can be
+ * captured in a HIP graph), and a batch with more than max_entries entries
+ * in total is not linked: every out_err[d] is set to JSIDX_ERR_CAPACITY and
+ * out_match is left as it was.  Without a reservation the call copies
+ * offsets[0] and offsets[ndocs] to the host (synchronising the stream) and
+ * sizes the workspace for one entry per byte (about 17 bytes per byte).
+ * Returns JSIDX_E_INVAL for NULL pointers or ndocs == 0.
+ */
+int jsidx_scopes_batch(const uint8_t *bufs, const uint64_t *offsets,
+                       uint32_t ndocs, const uint32_t *idx, const uint32_t *n,
+                       uint32_t *out_match, uint32_t *out_err,
+                       jsidx_stream_t stream);
+
+/*
+ * jsidx_scopes_reserve -- sizes the stream's scope workspace for documents
+ * of up to max_entries index entries (jsidx_scopes) and for batches of up to
+ * max_entries entries in total in up to max_ndocs documents
+ * (jsidx_scopes_batch; 0 counts as 1): about 17 bytes per entry and 4 per
+ * document.  Synchronises the stream if it has to grow the workspace.
+ * Returns JSIDX_E_TOO_LARGE for max_entries >= 2^31, JSIDX_E_NOWORKSPACE if
+ * the allocation fails (the stream then has no scope workspace).
+ */
+int jsidx_scopes_reserve(uint64_t max_entries, uint32_t max_ndocs,
+                         jsidx_stream_t stream);
 
 /*
  * jsidx_tape -- the tape of the paper's stage 2 (Sec. 3, Fig. 2; Sec. 3.2)

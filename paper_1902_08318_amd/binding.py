@@ -36,6 +36,8 @@ SIGNATURES = {
     "jsidx_minify": ([_VP, ctypes.c_uint64, _VP, _VP, _VP, _VP], ctypes.c_int),
     "jsidx_minify_batch": ([_VP, _VP, ctypes.c_uint32, _VP, _VP, _VP, _VP], ctypes.c_int),
     "jsidx_scopes": ([_VP, ctypes.c_uint64, _VP, ctypes.c_uint32, _VP, _VP, _VP], ctypes.c_int),
+    "jsidx_scopes_batch": ([_VP, _VP, ctypes.c_uint32, _VP, _VP, _VP, _VP, _VP], ctypes.c_int),
+    "jsidx_scopes_reserve": ([ctypes.c_uint64, ctypes.c_uint32, _VP], ctypes.c_int),
     "jsidx_reserve": ([ctypes.c_uint64, ctypes.c_uint32, _VP], ctypes.c_int),
     "jsidx_workspace_bytes": ([ctypes.c_uint64, ctypes.c_uint32], ctypes.c_size_t),
     "jsidx_release": ([_VP], ctypes.c_int),
@@ -137,6 +139,19 @@ def scopes(buf, idx, out_match, out_err, stream=None, n=None, length=None):
     n = idx.numel() if n is None else int(n)
     ln = buf.numel() if length is None else int(length)
     _check(lib().jsidx_scopes(_ptr(buf), ln, _ptr(idx), n, _ptr(out_match), _ptr(out_err), _stream(stream)))
+
+
+def scopes_batch(bufs, offsets, idx, n, out_match, out_err, stream=None, ndocs=None):
+    """jsidx_scopes_batch on device tensors: bufs (uint8), offsets (ndocs+1
+    int64), idx and out_match in the batch layout, n and out_err (ndocs)."""
+    nd = offsets.numel() - 1 if ndocs is None else int(ndocs)
+    _check(lib().jsidx_scopes_batch(_ptr(bufs), _ptr(offsets), nd, _ptr(idx), _ptr(n), _ptr(out_match),
+                                    _ptr(out_err), _stream(stream)))
+
+
+def scopes_reserve(max_entries: int, max_ndocs: int = 0, stream=None):
+    """jsidx_scopes_reserve."""
+    _check(lib().jsidx_scopes_reserve(int(max_entries), int(max_ndocs), _stream(stream)))
 
 
 def reserve(max_total_len: int, stream=None, max_ndocs: int = 0):

@@ -55,8 +55,11 @@ constexpr int64_t kNegInf = -(1ll << 62);
 
 JSIDX_DEV DepthFn fn_id() { return DepthFn{0, kNegInf}; }
 JSIDX_DEV DepthFn fn_then(const DepthFn& f, const DepthFn& g) {  // f, then g
-  const int64_t fb = f.b + g.a;
-  return DepthFn{f.a + g.a, fb > g.b ? fb : g.b};
+  // terms stay in [kNegInf, 2^32), so one sum cannot overflow; clamping at
+  // kNegInf keeps it so through any number of resets (batches)
+  const int64_t a = f.a + g.a, fb = f.b + g.a;
+  const int64_t b = fb > g.b ? fb : g.b;
+  return DepthFn{a < kNegInf ? kNegInf : a, b < kNegInf ? kNegInf : b};
 }
 JSIDX_DEV int64_t fn_apply(const DepthFn& f, int64_t x) { return x + f.a > f.b ? x + f.a : f.b; }
 JSIDX_DEV DepthFn fn_of(uint32_t kind) {
@@ -82,7 +85,24 @@ struct ScopeArgs {
   uint8_t* kind;        // per entry: token (an unmatched closer becomes
                         // kOther), kRootBit if the depth before it is 0
   uint32_t* queue;      // per entry at most
+  // batches (jsidx_scopes_batch): the documents' entries laid end to end as
+  // one sequence of "virtual" entries; n and nchunks then live on the device
+  const uint64_t* offsets;  // ndocs + 1 byte offsets of the documents in buf
+  const uint32_t* dn;       // per document: its entry count (idx holds them at idx + offsets[d])
+  uint32_t ndocs;
+  uint32_t cap;             // virtual entries the workspace holds
+  uint32_t* vn;             // [0] virtual entries, [1] their chunks (set by scope_batch_count)
+  uint32_t* vstart;         // ndocs + 1: first virtual entry of each document
+  uint32_t* docid;          // per virtual entry: its document
+  uint32_t* out_match;      // batch layout, like idx
 };
+
+// Kind-array bits of batches: the first and last entry of a document.
+constexpr uint32_t kDocStartBit = 32u;
+constexpr uint32_t kDocEndBit = 64u;
+// x -> 0: the depth at a document's first entry (the composition then adds
+// the entry's own step).
+JSIDX_DEV DepthFn fn_reset() { return DepthFn{kNegInf, 0}; }
 
 // Workspace layout for n entries (byte offsets; host side).
 struct ScopeLayout {
@@ -100,6 +120,30 @@ inline ScopeLayout scope_layout(uint64_t n) {
   L.lev = o; o = scope_align256(o + n * 4);
   L.queue = o; o = scope_align256(o + n * 4);
   L.kind = o; o = scope_align256(o + n);
+  L.total = o;
+  return L;
+}
+
+// Workspace layout of a batch of up to cap virtual entries in up to maxdocs
+// documents (byte offsets; host side).
+struct ScopeBatchLayout {
+  uint64_t vn, qcount, vstart, docid, chunk_fn, in_depth, chunk_min, lev, queue, match, kind, total;
+};
+inline ScopeBatchLayout scope_batch_layout(uint64_t cap, uint64_t maxdocs) {
+  const uint64_t nc = (cap + kScopeChunk - 1) / kScopeChunk;
+  ScopeBatchLayout L;
+  uint64_t o = 0;
+  L.vn = o; o = scope_align256(o + 8);
+  L.qcount = o; o = scope_align256(o + 4);
+  L.vstart = o; o = scope_align256(o + (maxdocs + 1) * 4);
+  L.docid = o; o = scope_align256(o + cap * 4);
+  L.chunk_fn = o; o = scope_align256(o + nc * 16);
+  L.in_depth = o; o = scope_align256(o + nc * 8);
+  L.chunk_min = o; o = scope_align256(o + nc * 4);
+  L.lev = o; o = scope_align256(o + cap * 4);
+  L.queue = o; o = scope_align256(o + cap * 4);
+  L.match = o; o = scope_align256(o + cap * 4);
+  L.kind = o; o = scope_align256(o + cap);
   L.total = o;
   return L;
 }
@@ -142,6 +186,24 @@ struct ScopeCheckLds {
 
 JSIDX_DEV uint32_t scope_tid() { return prim::wave_id() * kScopeWave + prim::lane(); }
 
+// Entries and chunks of the launch: the arguments for one document, the
+// device for a batch (scope_batch_count wrote them).
+template <bool BATCH>
+JSIDX_DEV uint32_t n_of(const ScopeArgs& a) { return BATCH ? prim::ld_agent32(a.vn) : a.n; }
+template <bool BATCH>
+JSIDX_DEV uint32_t nchunks_of(const ScopeArgs& a) { return BATCH ? prim::ld_agent32(a.vn + 1) : a.nchunks; }
+// The flags word an error of virtual entry i goes to.
+template <bool BATCH>
+JSIDX_DEV uint32_t* err_of(const ScopeArgs& a, uint64_t i) {
+  return BATCH ? a.err + prim::load4(reinterpret_cast<const uint8_t*>(a.docid + i)) : a.err;
+}
+// An entry's step of the depth: at a document's first entry (batches) the
+// depth starts again from 0.
+JSIDX_DEV DepthFn fn_of_entry(uint32_t kb) {
+  const DepthFn f = fn_of(kb & kTokMask);
+  return (kb & kDocStartBit) ? fn_then(fn_reset(), f) : f;
+}
+
 // The kinds of chunk c's entries into LDS: consecutive threads read
 // consecutive entries (coalesced), then each thread works on its own run of
 // kScopePer entries in LDS.
@@ -153,18 +215,19 @@ JSIDX_DEV void load_kinds(const ScopeArgs& a, G& g, uint32_t tid, uint32_t c) {
   prim::sync();
 }
 
-// The same from the kind array scope_chunk_fn wrote (one word per thread and
-// step; entries past n read as kOther).
+// The same from the kind array (written by scope_chunk_fn, or for a batch by
+// scope_batch_compact; one word per thread and step; entries past n read as
+// kOther).
 template <typename G>
-JSIDX_DEV void load_stored_kinds(const ScopeArgs& a, G& g, uint32_t tid, uint32_t c) {
+JSIDX_DEV void load_stored_kinds(const ScopeArgs& a, uint32_t n, G& g, uint32_t tid, uint32_t c) {
   const uint64_t c0 = (uint64_t)c * kScopeChunk;
   uint32_t* kw = reinterpret_cast<uint32_t*>(g.K);
   for (uint32_t w = tid; w < (uint32_t)kScopeChunk / 4; w += kScopeThreads) {
     const uint64_t b = c0 + 4 * (uint64_t)w;
     uint32_t v = 0u;  // four kOther
-    if (b < a.n) {
+    if (b < n) {
       v = prim::load4(a.kind + b);
-      const uint64_t valid = a.n - b;
+      const uint64_t valid = n - b;
       if (valid < 4) v &= ~(0xFFFFFFFFu << (8 * valid));
     }
     kw[w] = v;
@@ -190,36 +253,48 @@ JSIDX_DEV DepthFn group_exclusive(G& g, uint32_t tid, DepthFn mine) {
 }
 
 // 1. The composed depth function of each chunk (one workgroup per chunk).
+template <bool BATCH>
 JSIDX_DEVFN void scope_chunk_fn(const ScopeArgs& a) {
   ScopeFold& g = prim::lds_object<ScopeFold>();
-  const uint32_t tid = scope_tid(), c = prim::block();
-  load_kinds(a, g, tid, c);
-  // the kinds go to the workspace as words, for the kernels after this one
-  // (the word holding entry n - 1 lies inside the array's 256-byte padding)
-  const uint64_t c0 = (uint64_t)c * kScopeChunk;
-  const uint32_t* kw = reinterpret_cast<const uint32_t*>(g.K);
-  for (uint32_t w = tid; w < (uint32_t)kScopeChunk / 4; w += kScopeThreads) {
-    if (c0 + 4 * (uint64_t)w >= a.n) break;
-    prim::st_out(reinterpret_cast<uint32_t*>(a.kind + c0) + w, kw[w]);
+  const uint32_t tid = scope_tid();
+  const uint32_t n = n_of<BATCH>(a), nchunks = nchunks_of<BATCH>(a);
+  for (uint32_t c = prim::block(); c < nchunks; c += prim::grid()) {
+  if (BATCH) {
+    load_stored_kinds(a, n, g, tid, c);
+  } else {
+    load_kinds(a, g, tid, c);
+    // the kinds go to the workspace as words, for the kernels after this one
+    // (the word holding entry n - 1 lies inside the array's 256-byte padding)
+    const uint64_t c0 = (uint64_t)c * kScopeChunk;
+    const uint32_t* kw = reinterpret_cast<const uint32_t*>(g.K);
+    for (uint32_t w = tid; w < (uint32_t)kScopeChunk / 4; w += kScopeThreads) {
+      if (c0 + 4 * (uint64_t)w >= a.n) break;
+      prim::st_out(reinterpret_cast<uint32_t*>(a.kind + c0) + w, kw[w]);
+    }
   }
   DepthFn f = fn_id();
-  for (int k = 0; k < kScopePer; k++) f = fn_then(f, fn_of(g.K[tid * kScopePer + k]));
+  for (int k = 0; k < kScopePer; k++) f = fn_then(f, fn_of_entry(g.K[tid * kScopePer + k]));
   const DepthFn ex = group_exclusive(g, tid, f);
   if (tid == kScopeThreads - 1) {
     const DepthFn all = fn_then(ex, f);
     prim::st_pair(a.chunk_fn + 2 * (uint64_t)c, pack64(all.a).x, pack64(all.a).y);
     prim::st_pair(a.chunk_fn + 2 * (uint64_t)c + 1, pack64(all.b).x, pack64(all.b).y);
   }
+  prim::sync();
+  }
 }
 
-// 2. The depth entering each chunk (one workgroup); also clears the flags and
-//    the queue for the kernels after it.
+// 2. The depth entering each chunk (one workgroup); for one document also
+//    clears the flags and the queue for the kernels after it (a batch's
+//    scope_batch_count did).
+template <bool BATCH>
 JSIDX_DEVFN void scope_scan(const ScopeArgs& a) {
   ScopeScanLds& g = prim::lds_object<ScopeScanLds>();
   const uint32_t tid = scope_tid();
-  const uint32_t per = (a.nchunks + kScopeThreads - 1) / kScopeThreads;
+  const uint32_t nchunks = nchunks_of<BATCH>(a);
+  const uint32_t per = (nchunks + kScopeThreads - 1) / kScopeThreads;
   const uint64_t lo = (uint64_t)tid * per;
-  const uint64_t hi = lo + per < a.nchunks ? lo + per : a.nchunks;
+  const uint64_t hi = lo + per < nchunks ? lo + per : nchunks;
   DepthFn f = fn_id();
   for (uint64_t c = lo; c < hi; c++) {
     const DepthFn fc{unpack64(prim::ld_pair(a.chunk_fn + 2 * c)), unpack64(prim::ld_pair(a.chunk_fn + 2 * c + 1))};
@@ -232,50 +307,64 @@ JSIDX_DEVFN void scope_scan(const ScopeArgs& a) {
     const DepthFn fc{unpack64(prim::ld_pair(a.chunk_fn + 2 * c)), unpack64(prim::ld_pair(a.chunk_fn + 2 * c + 1))};
     x = fn_apply(fc, x);
   }
-  if (tid == 0) {
+  if (!BATCH && tid == 0) {
     prim::st_out(a.err, a.n ? 0u : kErrSyntax);  // an empty index holds no value
     prim::st_out(a.qcount, 0u);
   }
 }
 
 // 3. Levels and kinds of the entries, the lowest level of each chunk, and
-//    every link cleared (one workgroup per chunk).
+//    every link cleared (one workgroup per chunk).  In a batch a level is
+//    offset by the first virtual entry of its document, which is more than
+//    any level of an earlier document, so no search ever crosses into
+//    another document.
+template <bool BATCH>
 JSIDX_DEVFN void scope_levels(const ScopeArgs& a) {
   ScopeGroup& g = prim::lds_object<ScopeGroup>();
-  const uint32_t tid = scope_tid(), c = prim::block();
+  const uint32_t tid = scope_tid();
+  const uint32_t n = n_of<BATCH>(a), nchunks = nchunks_of<BATCH>(a);
+  for (uint32_t c = prim::block(); c < nchunks; c += prim::grid()) {
   const uint64_t c0 = (uint64_t)c * kScopeChunk;
-  load_stored_kinds(a, g, tid, c);
+  load_stored_kinds(a, n, g, tid, c);
   DepthFn f = fn_id();
-  for (int k = 0; k < kScopePer; k++) f = fn_then(f, fn_of(g.K[tid * kScopePer + k]));
+  for (int k = 0; k < kScopePer; k++) f = fn_then(f, fn_of_entry(g.K[tid * kScopePer + k]));
   const DepthFn ex = group_exclusive(g, tid, f);
   int64_t d = fn_apply(ex, unpack64(prim::ld_pair(a.in_depth + c)));
-  uint32_t lo_level = kNoLevel, unmatched = 0;
+  // the level offset of the run's first entry's document (batches)
+  uint32_t off = 0;
+  const uint64_t r0 = c0 + (uint64_t)tid * kScopePer;
+  if (BATCH && r0 < n) off = prim::load4(reinterpret_cast<const uint8_t*>(a.vstart + prim::load4(reinterpret_cast<const uint8_t*>(a.docid + r0))));
+  uint32_t lo_level = kNoLevel;
   for (int k = 0; k < kScopePer; k++) {
     const uint32_t j = tid * kScopePer + (uint32_t)k;
-    uint32_t kd = g.K[j], level = kNoLevel;
+    const uint32_t kb = g.K[j];
+    uint32_t kd = kb & kTokMask, level = kNoLevel;
+    if (kb & kDocStartBit) {
+      d = 0;
+      off = (uint32_t)(c0 + j);
+    }
     const uint32_t root = d == 0 ? kRootBit : 0u;
     if (kd == kOpenSq || kd == kOpenCu) {
-      level = (uint32_t)d;
+      level = off + (uint32_t)d;
       d++;
     } else if (kd == kCloseSq || kd == kCloseCu) {
       if (d > 0) {
         d--;
-        level = (uint32_t)d;
+        level = off + (uint32_t)d;
       } else {
         kd = kOther;  // a closer with nothing open: left unlinked
-        unmatched = 1;
+        if (c0 + j < n) prim::or_agent32(err_of<BATCH>(a, c0 + j), kErrUnbalanced);
       }
     }
     g.L[j] = level;
-    g.K[j] = (uint8_t)(kd | root);
+    g.K[j] = (uint8_t)(kd | root | (kb & (kDocStartBit | kDocEndBit)));
     if (level < lo_level) lo_level = level;
   }
-  if (unmatched) prim::or_agent32(a.err, kErrUnbalanced);
   g.m[tid] = lo_level;
   prim::sync();
   // the chunk's levels, kinds and cleared links go out as consecutive words
   for (uint32_t j = tid; j < (uint32_t)kScopeChunk; j += kScopeThreads) {
-    if (c0 + j >= a.n) break;
+    if (c0 + j >= n) break;
     prim::st_out(a.lev + c0 + j, g.L[j]);
     prim::st_byte(a.kind + c0 + j, g.K[j]);
     prim::st_out(a.match + c0 + j, kUnlinked);
@@ -285,27 +374,35 @@ JSIDX_DEVFN void scope_levels(const ScopeArgs& a) {
     prim::sync();
   }
   if (tid == 0) prim::st_out(a.chunk_min + c, g.m[0]);
+  prim::sync();
+  }
 }
 
 // Links opener i (token ki) with closer k.  The closer's kind byte also
-// learns whether the opener follows a colon; only this call writes it (the
-// kernel owning k's chunk has staged its kinds before linking).
+// learns whether the opener follows a colon (in its own document); only this
+// call writes it (the kernel owning k's chunk has staged its kinds before
+// linking).
+template <bool BATCH>
 JSIDX_DEV void link(const ScopeArgs& a, uint32_t i, uint32_t k, uint32_t ki) {
   prim::st_out(a.match + i, k);
   prim::st_out(a.match + k, i);
   const uint32_t kb = prim::load1(a.kind + k);
   const uint32_t kk = kb & kTokMask;
-  if ((ki == kOpenCu) != (kk == kCloseCu)) prim::or_agent32(a.err, kErrMismatched);
-  if (i > 0 && (prim::load1(a.kind + i - 1) & kTokMask) == kColon) prim::st_byte(a.kind + k, kb | kMemberBit);
+  if ((ki == kOpenCu) != (kk == kCloseCu)) prim::or_agent32(err_of<BATCH>(a, i), kErrMismatched);
+  const bool first = BATCH && (prim::load1(a.kind + i) & kDocStartBit) != 0u;
+  if (i > 0 && !first && (prim::load1(a.kind + i - 1) & kTokMask) == kColon) prim::st_byte(a.kind + k, kb | kMemberBit);
 }
 
 // 4. Each opener's closer inside its own chunk, searched in LDS; openers whose
 //    scope leaves the chunk are queued (one workgroup per chunk).
+template <bool BATCH>
 JSIDX_DEVFN void scope_local(const ScopeArgs& a) {
   ScopeGroup& g = prim::lds_object<ScopeGroup>();
-  const uint32_t tid = scope_tid(), c = prim::block();
+  const uint32_t tid = scope_tid();
+  const uint32_t n = n_of<BATCH>(a), nchunks = nchunks_of<BATCH>(a);
+  for (uint32_t c = prim::block(); c < nchunks; c += prim::grid()) {
   const uint64_t c0 = (uint64_t)c * kScopeChunk;
-  const uint32_t cend = a.n - c0 < (uint64_t)kScopeChunk ? (uint32_t)(a.n - c0) : (uint32_t)kScopeChunk;
+  const uint32_t cend = n - c0 < (uint64_t)kScopeChunk ? (uint32_t)(n - c0) : (uint32_t)kScopeChunk;
   for (uint32_t j = tid; j < (uint32_t)kScopeChunk; j += kScopeThreads) {
     g.L[j] = j < cend ? prim::load4(reinterpret_cast<const uint8_t*>(a.lev + c0 + j)) : kNoLevel;
     g.K[j] = (uint8_t)(j < cend ? prim::load1(a.kind + c0 + j) & kTokMask : kOther);
@@ -339,53 +436,65 @@ JSIDX_DEVFN void scope_local(const ScopeArgs& a) {
         while (g.L[p] > lv) p++;  // ends inside run r: its lowest level is at most lv
     }
     if (p < cend) {
-      link(a, i, (uint32_t)(c0 + p), ki);
+      link<BATCH>(a, i, (uint32_t)(c0 + p), ki);
     } else {
       const uint32_t q = prim::add_agent32(a.qcount, 1u);
       prim::st_out(a.queue + q, i);
     }
   }
+  prim::sync();
+  }
 }
 
 // 5. Queued openers: the first later chunk whose lowest level is at most the
 //    opener's, then the first such entry in it; one wave per opener, 64
-//    chunks or entries per step.
+//    chunks or entries per step.  (In a batch the search stops at the chunk
+//    of the document's last entry.)
+template <bool BATCH>
 JSIDX_DEVFN void scope_far(const ScopeArgs& a) {
   const uint32_t lane = prim::lane();
   const uint32_t qn = prim::readlane(prim::ld_agent32(a.qcount), 0);
+  const uint32_t n = prim::readlane(n_of<BATCH>(a), 0);
   const uint32_t waves_per_group = kScopeThreads / kScopeWave;
   const uint32_t nw = prim::grid() * waves_per_group;
   for (uint32_t q = prim::block() * waves_per_group + prim::wave_id(); q < qn; q += nw) {
     const uint32_t i = prim::readlane(prim::load4(reinterpret_cast<const uint8_t*>(a.queue + q)), 0);
     const uint32_t lv = prim::readlane(prim::load4(reinterpret_cast<const uint8_t*>(a.lev + i)), 0);
     const uint32_t ki = prim::readlane(prim::load1(a.kind + i) & kTokMask, 0);
+    uint64_t end = n;  // entries [i, end) can hold the closer
+    if (BATCH) {
+      const uint32_t d = prim::readlane(prim::load4(reinterpret_cast<const uint8_t*>(a.docid + i)), 0);
+      end = prim::readlane(prim::load4(reinterpret_cast<const uint8_t*>(a.vstart + d + 1)), 0);
+    }
+    const uint64_t cend = (end + kScopeChunk - 1) / kScopeChunk;
     int64_t c2 = -1;
-    for (uint64_t base = (uint64_t)i / kScopeChunk + 1; base < a.nchunks; base += kScopeWave) {
+    for (uint64_t base = (uint64_t)i / kScopeChunk + 1; base < cend; base += kScopeWave) {
       const uint64_t cc = base + lane;
-      const bool ok = cc < a.nchunks && prim::load4(reinterpret_cast<const uint8_t*>(a.chunk_min + cc)) <= lv;
+      const bool ok = cc < cend && prim::load4(reinterpret_cast<const uint8_t*>(a.chunk_min + cc)) <= lv;
       const uint64_t bm = prim::ballot(ok);
       if (bm) {
         c2 = (int64_t)(base + (uint64_t)__builtin_ctzll(bm));
         break;
       }
     }
-    if (c2 < 0) {
-      if (lane == 0) prim::or_agent32(a.err, kErrUnbalanced);
-      continue;
-    }
-    const uint64_t start = (uint64_t)c2 * kScopeChunk;
-    const uint64_t stop = start + kScopeChunk < a.n ? start + kScopeChunk : a.n;
     int64_t found = -1;
-    for (uint64_t p0 = start; p0 < stop; p0 += kScopeWave) {
-      const uint64_t p = p0 + lane;
-      const bool ok = p < stop && prim::load4(reinterpret_cast<const uint8_t*>(a.lev + p)) <= lv;
-      const uint64_t bm = prim::ballot(ok);
-      if (bm) {
-        found = (int64_t)(p0 + (uint64_t)__builtin_ctzll(bm));
-        break;
+    if (c2 >= 0) {
+      const uint64_t start = (uint64_t)c2 * kScopeChunk;
+      const uint64_t stop = start + kScopeChunk < end ? start + kScopeChunk : end;
+      for (uint64_t p0 = start; p0 < stop; p0 += kScopeWave) {
+        const uint64_t p = p0 + lane;
+        const bool ok = p < stop && prim::load4(reinterpret_cast<const uint8_t*>(a.lev + p)) <= lv;
+        const uint64_t bm = prim::ballot(ok);
+        if (bm) {
+          found = (int64_t)(p0 + (uint64_t)__builtin_ctzll(bm));
+          break;
+        }
       }
     }
-    if (found >= 0 && lane == 0) link(a, i, (uint32_t)found, ki);
+    if (lane == 0) {
+      if (found >= 0) link<BATCH>(a, i, (uint32_t)found, ki);
+      else prim::or_agent32(err_of<BATCH>(a, i), kErrUnbalanced);
+    }
   }
 }
 
@@ -441,14 +550,22 @@ JSIDX_DEV bool allowed(uint32_t pc, uint32_t cc) {
   return ((row >> cc) & 1u) != 0u;
 }
 
-// Structure check of entry i (entries i - 3 .. i + 1 staged).
-JSIDX_DEV bool entry_ok(const ScopeArgs& a, const Staged& st, int64_t i) {
-  const uint32_t t = st.tok(i), nxt = st.tok(i + 1);
+// Structure check of entry i (entries i - 3 .. i + 1 staged; n entries).  In
+// a batch, entries of other documents count as outside the index.
+template <bool BATCH>
+JSIDX_DEV bool entry_ok(uint32_t n, const Staged& st, int64_t i) {
+  const uint32_t r0 = st.raw(i);
+  const bool first = BATCH ? (r0 & kDocStartBit) != 0u : i == 0;
+  const bool last = BATCH ? (r0 & kDocEndBit) != 0u : (uint64_t)i + 1 == n;
+  // i - 2 and i - 3 are in i's document only if no document starts after them
+  const bool in2 = !BATCH || !first ? !BATCH || (st.raw(i - 1) & kDocStartBit) == 0u : false;
+  const bool in3 = in2 && (!BATCH || (st.raw(i - 2) & kDocStartBit) == 0u);
+  const uint32_t t = st.tok(i), nxt = last ? 0xFFu : st.tok(i + 1);
   uint32_t cc = t;
   if (t == kStr) cc = nxt == kColon ? cStrKey : cStrVal;
-  else if (t == kComma && (st.raw(i) & kRootBit)) cc = cRootComma;
+  else if (t == kComma && (r0 & kRootBit)) cc = cRootComma;
   uint32_t pc = pStart;
-  if (i > 0) {
+  if (!first) {
     const uint32_t p = st.tok(i - 1);
     pc = p;
     if (p == kStr) {
@@ -457,35 +574,38 @@ JSIDX_DEV bool entry_ok(const ScopeArgs& a, const Staged& st, int64_t i) {
       // the element before the comma ends at i - 2: an object member iff its
       // value (an atom or string there, or the scope a closer there ends)
       // follows a colon
-      const uint32_t te = st.tok(i - 2);
+      const uint32_t te = in2 ? st.tok(i - 2) : 0xFFu;
       const bool member = (te == kCloseSq || te == kCloseCu) ? (st.raw(i - 2) & kMemberBit) != 0u
-                                                              : st.tok(i - 3) == kColon;
+                                                              : (in3 ? st.tok(i - 3) : 0xFFu) == kColon;
       pc = member ? pCommaObj : pCommaArr;
     }
   }
   bool ok = allowed(pc, cc);
-  if ((uint64_t)i + 1 == a.n) ok = ok && (kLastAllowed >> cc) & 1u;
+  if (last) ok = ok && (kLastAllowed >> cc) & 1u;
   return ok;
 }
 
 // 6. The structure check, after the links (one workgroup per chunk, kinds
 //    staged in LDS with coalesced word loads; the rule of entry i reads
-//    entries i - 3 to i + 1 only).  Unbalanced or mismatched brackets are a syntax error
-//    too.
+//    entries i - 3 to i + 1 only).  Unbalanced or mismatched brackets are a
+//    syntax error too (for a batch, scope_batch_finish adds that).
+template <bool BATCH>
 JSIDX_DEVFN void scope_check(const ScopeArgs& a) {
   ScopeCheckLds& g = prim::lds_object<ScopeCheckLds>();
-  const uint32_t tid = scope_tid(), c = prim::block();
+  const uint32_t tid = scope_tid();
+  const uint32_t n = n_of<BATCH>(a), nchunks = nchunks_of<BATCH>(a);
+  for (uint32_t c = prim::block(); c < nchunks; c += prim::grid()) {
   const int64_t c0 = (int64_t)c * kScopeChunk;
-  if (c == 0 && tid == 0 && (prim::ld_agent32(a.err) & (kErrUnbalanced | kErrMismatched)))
+  if (!BATCH && c == 0 && tid == 0 && (prim::ld_agent32(a.err) & (kErrUnbalanced | kErrMismatched)))
     prim::or_agent32(a.err, kErrSyntax);
   // words of the kind array; bytes outside [0, n) read as 0xFF (the array's
   // allocation is padded to 256 bytes, so a word holding byte n - 1 is inside)
   for (uint32_t w = tid; w < (uint32_t)kCheckWords; w += kScopeThreads) {
     const int64_t b = c0 - 4 + 4 * (int64_t)w;
     uint32_t v = 0xFFFFFFFFu;
-    if (b >= 0 && (uint64_t)b < a.n) {
+    if (b >= 0 && (uint64_t)b < n) {
       v = prim::load4(a.kind + b);
-      const uint64_t valid = a.n - (uint64_t)b;
+      const uint64_t valid = n - (uint64_t)b;
       if (valid < 4) v |= 0xFFFFFFFFu << (8 * valid);
     }
     g.W[w] = v;
@@ -495,10 +615,100 @@ JSIDX_DEVFN void scope_check(const ScopeArgs& a) {
   bool ok = true;
   for (uint32_t j = tid; j < (uint32_t)kScopeChunk; j += kScopeThreads) {
     const int64_t i = c0 + (int64_t)j;
-    if ((uint64_t)i >= a.n) break;
-    ok = entry_ok(a, st, i) && ok;
+    if ((uint64_t)i >= n) break;
+    const bool e = entry_ok<BATCH>(n, st, i);
+    if (BATCH && !e) prim::or_agent32(err_of<true>(a, (uint64_t)i), kErrSyntax);
+    ok = e && ok;
   }
-  if (prim::ballot(!ok) != 0ull && prim::lane() == 0) prim::or_agent32(a.err, kErrSyntax);
+  if (!BATCH && prim::ballot(!ok) != 0ull && prim::lane() == 0) prim::or_agent32(a.err, kErrSyntax);
+  prim::sync();
+  }
+}
+
+// ---- Batches ---------------------------------------------------------------
+// 0. The first virtual entry of each document (an exclusive scan of the
+//    entry counts, one workgroup), the totals, the flags cleared (an empty
+//    index is a syntax error) and the queue emptied.  A batch with more
+//    entries than the workspace holds is not linked: every document gets
+//    JSIDX_ERR_CAPACITY (0x80000000) and the kernels after this one do
+//    nothing.
+constexpr uint32_t kErrCapacity = 0x80000000u;
+JSIDX_DEVFN void scope_batch_count(const ScopeArgs& a) {
+  ScopeScanLds& g = prim::lds_object<ScopeScanLds>();
+  const uint32_t tid = scope_tid();
+  const uint32_t per = (a.ndocs + kScopeThreads - 1) / kScopeThreads;
+  const uint64_t lo = (uint64_t)tid * per;
+  const uint64_t hi = lo + per < a.ndocs ? lo + per : a.ndocs;
+  uint64_t sum = 0;
+  for (uint64_t d = lo; d < hi; d++) sum += prim::load4(reinterpret_cast<const uint8_t*>(a.dn + d));
+  // exclusive scan of the threads' sums (as depth functions x -> x + sum)
+  const DepthFn ex = group_exclusive(g, tid, DepthFn{(int64_t)sum, kNegInf});
+  uint64_t v = (uint64_t)ex.a;
+  const uint64_t total = (uint64_t)g.f[kScopeThreads - 1].a;  // the scan leaves the inclusive values in LDS
+  const bool over = total > (uint64_t)a.cap;
+  for (uint64_t d = lo; d < hi; d++) {
+    const uint32_t nd = prim::load4(reinterpret_cast<const uint8_t*>(a.dn + d));
+    if (!over) prim::st_out(a.vstart + d, (uint32_t)v);
+    prim::st_out(a.err + d, over ? kErrCapacity : (nd ? 0u : kErrSyntax));
+    v += nd;
+  }
+  if (tid == kScopeThreads - 1) {
+    if (!over) prim::st_out(a.vstart + a.ndocs, (uint32_t)total);
+    prim::st_out(a.vn, over ? 0u : (uint32_t)total);
+    prim::st_out(a.vn + 1, over ? 0u : (uint32_t)((total + kScopeChunk - 1) / kScopeChunk));
+    prim::st_out(a.qcount, 0u);
+  }
+}
+
+// 1b. Each document's entries into the virtual sequence: kind bytes (with
+//     the first and last entry of the document marked) and document numbers,
+//     one wave per document.
+JSIDX_DEVFN void scope_batch_compact(const ScopeArgs& a) {
+  const uint32_t lane = prim::lane();
+  if (prim::ld_agent32(a.vn + 1) == 0u) return;
+  const uint32_t waves_per_group = kScopeThreads / kScopeWave;
+  const uint32_t nw = prim::grid() * waves_per_group;
+  for (uint32_t d = prim::block() * waves_per_group + prim::wave_id(); d < a.ndocs; d += nw) {
+    const uint64_t base = prim::load8(a.offsets + d), len = prim::load8(a.offsets + d + 1) - base;
+    const uint32_t nd = prim::load4(reinterpret_cast<const uint8_t*>(a.dn + d));
+    const uint32_t v0 = prim::load4(reinterpret_cast<const uint8_t*>(a.vstart + d));
+    for (uint32_t j = lane; j < nd; j += kScopeWave) {
+      const uint32_t p = prim::load4(reinterpret_cast<const uint8_t*>(a.idx + base + j));
+      uint32_t k = kOther;
+      if ((uint64_t)p < len) {
+        const uint32_t b = prim::load1(a.buf + base + p);
+        k = b == 0x5Bu ? kOpenSq : b == 0x7Bu ? kOpenCu : b == 0x5Du ? kCloseSq : b == 0x7Du ? kCloseCu
+          : b == 0x3Au ? kColon : b == 0x2Cu ? kComma : b == 0x22u ? kStr : kOther;
+      }
+      if (j == 0) k |= kDocStartBit;
+      if (j + 1 == nd) k |= kDocEndBit;
+      prim::st_byte(a.kind + v0 + j, k);
+      prim::st_out(a.docid + v0 + j, d);
+    }
+  }
+}
+
+// 7. Links back into the batch layout (document-relative entry numbers at
+//    out_match + offsets[d]) and the flags completed: unbalanced or
+//    mismatched brackets are a syntax error.  One wave per document.
+JSIDX_DEVFN void scope_batch_finish(const ScopeArgs& a) {
+  const uint32_t lane = prim::lane();
+  if (prim::ld_agent32(a.vn + 1) == 0u) return;
+  const uint32_t waves_per_group = kScopeThreads / kScopeWave;
+  const uint32_t nw = prim::grid() * waves_per_group;
+  for (uint32_t d = prim::block() * waves_per_group + prim::wave_id(); d < a.ndocs; d += nw) {
+    const uint64_t base = prim::load8(a.offsets + d);
+    const uint32_t nd = prim::load4(reinterpret_cast<const uint8_t*>(a.dn + d));
+    const uint32_t v0 = prim::load4(reinterpret_cast<const uint8_t*>(a.vstart + d));
+    for (uint32_t j = lane; j < nd; j += kScopeWave) {
+      const uint32_t m = prim::load4(reinterpret_cast<const uint8_t*>(a.match + v0 + j));
+      prim::st_out(a.out_match + base + j, m == kUnlinked ? kUnlinked : m - v0);
+    }
+    if (lane == 0) {
+      const uint32_t e = prim::ld_agent32(a.err + d);
+      if (e & (kErrUnbalanced | kErrMismatched)) prim::st_out(a.err + d, e | kErrSyntax);
+    }
+  }
 }
 
 }  // namespace jsidx

@@ -156,18 +156,91 @@ long emu_scopes_run(const uint8_t* buf, uint64_t len, const uint32_t* idx, uint3
     for (auto& x : th) x.join();
     for (auto* g : groups) delete g;
   };
-  if (a.nchunks) phase((int)a.nchunks, scope_chunk_fn);
-  phase(1, scope_scan);
+  if (a.nchunks) phase((int)a.nchunks, scope_chunk_fn<false>);
+  phase(1, scope_scan<false>);
   if (a.nchunks) {
-    phase((int)a.nchunks, scope_levels);
-    phase((int)a.nchunks, scope_local);
-    phase(far_groups, scope_far);
-    phase((int)a.nchunks, scope_check);
+    phase((int)a.nchunks, scope_levels<false>);
+    phase((int)a.nchunks, scope_local<false>);
+    phase(far_groups, scope_far<false>);
+    phase((int)a.nchunks, scope_check<false>);
   }
   return env.violations.load();
 }
 
 uint64_t emu_scopes_ws_bytes(uint64_t n) { return scope_layout(n).total; }
+uint64_t emu_scopes_batch_ws_bytes(uint64_t cap, uint64_t ndocs) { return scope_batch_layout(cap, ndocs).total; }
+
+// The batched scope kernels over ndocs documents (bytes at buf, offsets,
+// index entries at idx + offsets[d], counts n[d]), with chunk_groups
+// workgroups for the chunk kernels and doc_groups for the per-document ones.
+long emu_scopes_batch_run(const uint8_t* buf, const uint64_t* offsets, uint32_t ndocs, const uint32_t* idx,
+                          const uint32_t* n, uint32_t* match, uint32_t* err, void* ws, uint64_t cap, int chunk_groups,
+                          int doc_groups, int far_groups) {
+  const ScopeBatchLayout L = scope_batch_layout(cap, ndocs);
+  const uint64_t total = offsets[ndocs];
+  prim::EmuEnv env;
+  if (total) env.reads[env.nreads++] = {buf, buf + total};
+  env.reads[env.nreads++] = {offsets, offsets + ndocs + 1};
+  if (total) env.reads[env.nreads++] = {idx, idx + total};
+  env.reads[env.nreads++] = {n, n + ndocs};
+  if (total) env.writes[env.nwrites++] = {match, match + total};
+  env.writes[env.nwrites++] = {err, err + ndocs};
+  env.writes[env.nwrites++] = {ws, (const uint8_t*)ws + L.total};
+  env.reads[env.nreads++] = {ws, (const uint8_t*)ws + L.total};
+  uint8_t* m = static_cast<uint8_t*>(ws);
+  ScopeArgs a;
+  a.buf = buf;
+  a.len = 0;
+  a.idx = idx;
+  a.n = 0;
+  a.nchunks = 0;
+  a.match = reinterpret_cast<uint32_t*>(m + L.match);
+  a.err = err;
+  a.chunk_fn = reinterpret_cast<uint2*>(m + L.chunk_fn);
+  a.in_depth = reinterpret_cast<uint2*>(m + L.in_depth);
+  a.chunk_min = reinterpret_cast<uint32_t*>(m + L.chunk_min);
+  a.qcount = reinterpret_cast<uint32_t*>(m + L.qcount);
+  a.lev = reinterpret_cast<uint32_t*>(m + L.lev);
+  a.queue = reinterpret_cast<uint32_t*>(m + L.queue);
+  a.kind = m + L.kind;
+  a.offsets = offsets;
+  a.dn = n;
+  a.ndocs = ndocs;
+  a.cap = (uint32_t)cap;
+  a.vn = reinterpret_cast<uint32_t*>(m + L.vn);
+  a.vstart = reinterpret_cast<uint32_t*>(m + L.vstart);
+  a.docid = reinterpret_cast<uint32_t*>(m + L.docid);
+  a.out_match = match;
+  auto phase = [&](int ngroups, void (*body)(const ScopeArgs&)) {
+    std::vector<prim::GroupCtx*> groups;
+    for (int b = 0; b < ngroups; b++) groups.push_back(new prim::GroupCtx(kScopeThreads));
+    std::vector<std::thread> th;
+    for (int b = 0; b < ngroups; b++) {
+      for (uint32_t t = 0; t < (uint32_t)kScopeThreads; t++) {
+        th.emplace_back([&, b, t] {
+          prim::tctx.tid = t;
+          prim::tctx.block = (uint32_t)b;
+          prim::tctx.grid = (uint32_t)ngroups;
+          prim::tctx.g = groups[(size_t)b];
+          prim::tctx.env = &env;
+          body(a);
+        });
+      }
+    }
+    for (auto& x : th) x.join();
+    for (auto* g : groups) delete g;
+  };
+  phase(1, scope_batch_count);
+  phase(doc_groups, scope_batch_compact);
+  phase(chunk_groups, scope_chunk_fn<true>);
+  phase(1, scope_scan<true>);
+  phase(chunk_groups, scope_levels<true>);
+  phase(chunk_groups, scope_local<true>);
+  phase(far_groups, scope_far<true>);
+  phase(chunk_groups, scope_check<true>);
+  phase(doc_groups, scope_batch_finish);
+  return env.violations.load();
+}
 
 // The tape kernels (jsidx_tape.h) over one document's index and links.
 // Returns the number of out-of-range accesses.

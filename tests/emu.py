@@ -95,6 +95,11 @@ def load(block_tiles: int | None = None):
     lib.emu_tape_ws_bytes.restype = ctypes.c_uint64
     lib.emu_scopes_ws_bytes.argtypes = [ctypes.c_uint64]
     lib.emu_scopes_ws_bytes.restype = ctypes.c_uint64
+    lib.emu_scopes_batch_ws_bytes.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+    lib.emu_scopes_batch_ws_bytes.restype = ctypes.c_uint64
+    lib.emu_scopes_batch_run.argtypes = [vp, vp, ctypes.c_uint32, vp, vp, vp, vp, vp, ctypes.c_uint64, ctypes.c_int,
+                                         ctypes.c_int, ctypes.c_int]
+    lib.emu_scopes_batch_run.restype = ctypes.c_long
     lib.emu_ws_bytes.argtypes = [ctypes.c_uint64]
     lib.emu_ws_bytes.restype = ctypes.c_uint64
     lib.emu_tile_bytes.restype = ctypes.c_uint32
@@ -196,6 +201,29 @@ def scopes(data: bytes, idx: np.ndarray, far_groups: int = 2, garbage_ws: bool =
     v = lib.emu_scopes_run(buf.ctypes.data, len(data), ix.ctypes.data, n, match.ctypes.data, err.ctypes.data,
                            ws.ctypes.data, far_groups)
     return match[:n], int(err[0]), int(v)
+
+
+def scopes_batch(data: bytes, offsets: np.ndarray, idx: np.ndarray, n: np.ndarray, cap: int | None = None,
+                 chunk_groups: int = 2, doc_groups: int = 2, far_groups: int = 2):
+    """Batched scope links through the emulated kernels: idx and the result
+    in the batch layout (document d at offsets[d]), n the entry counts.
+    Returns (match, err per document, violations); outputs and workspace
+    start full of garbage."""
+    lib = load()
+    nd = offsets.size - 1
+    total = int(offsets[-1])
+    cap = int(n.sum()) if cap is None else cap
+    buf = np.frombuffer(data, dtype=np.uint8) if data else np.zeros(1, dtype=np.uint8)
+    offs = np.ascontiguousarray(offsets, dtype=np.uint64)
+    ix = np.ascontiguousarray(idx, dtype=np.uint32) if total else np.zeros(1, dtype=np.uint32)
+    cnt = np.ascontiguousarray(n, dtype=np.uint32)
+    match = np.full(max(1, total), 0xABABABAB, dtype=np.uint32)
+    err = np.full(nd, 0xABABABAB, dtype=np.uint32)
+    ws = np.full(int(lib.emu_scopes_batch_ws_bytes(cap, nd)) // 4 + 64, 0x5A5A5A5A, dtype=np.uint32)
+    v = lib.emu_scopes_batch_run(buf.ctypes.data, offs.ctypes.data, nd, ix.ctypes.data, cnt.ctypes.data,
+                                 match.ctypes.data, err.ctypes.data, ws.ctypes.data, cap, chunk_groups, doc_groups,
+                                 far_groups)
+    return match, err, int(v)
 
 
 def tape(data: bytes, idx: np.ndarray, match: np.ndarray, exact_groups: int = 2):

@@ -82,3 +82,75 @@ def test_structure_edits_across_chunks():
         p = big.index(old, int(at * len(big)))
         _check((big[:p] + new + big[p + 1:]).encode(), far_groups=2)
     _check((big + " 1").encode())
+
+
+def _oracle_batch(data: bytes, offs: np.ndarray):
+    """The oracle per document: (index in batch layout, counts, expected links
+    in batch layout, expected flags)."""
+    oi, on, _ = oracle.index_batch(np.frombuffer(data, dtype=np.uint8), offs)
+    em = np.full(max(1, int(offs[-1])), 0xFFFFFFFF, dtype=np.uint32)
+    ee = np.zeros(offs.size - 1, dtype=np.uint32)
+    for d in range(offs.size - 1):
+        a, b = int(offs[d]), int(offs[d + 1])
+        ix = oi[a:a + on[d]]
+        m, e = oracle.scopes(data[a:b], ix)
+        ee[d] = e | oracle.structure(data[a:b], ix)
+        em[a:a + on[d]] = m
+    return oi, on, em, ee
+
+
+def _check_batch(docs, **kw):
+    data = b"".join(docs)
+    offs = np.zeros(len(docs) + 1, dtype=np.uint64)
+    np.cumsum([len(x) for x in docs], out=offs[1:])
+    oi, on, em, ee = _oracle_batch(data, offs)
+    m, e, v = emu.scopes_batch(data, offs, oi, on, **kw)
+    assert v == 0
+    assert np.array_equal(e, ee), [(d, hex(e[d]), hex(ee[d])) for d in np.nonzero(e != ee)[0][:5]]
+    for d in range(len(docs)):
+        a = int(offs[d])
+        assert np.array_equal(m[a:a + on[d]], em[a:a + on[d]]), d
+    return data, offs, on
+
+
+def test_batch_of_documents():
+    """A batch in the batched scope kernels: small valid and invalid
+    documents, empty ones, documents that straddle chunk edges of the
+    virtual sequence, one of more than a chunk (its scopes leave their
+    chunk), unclosed openers whose search must stop at their document's
+    end, and fewer workgroups than chunks and documents."""
+    rng = random.Random(11)
+    small = [b"", b"1", b"[]", b"{}", b"[}", b"]", b"[[", b"[ ] ]", b'{"a":[1,{"b":[]}]}', b"{ [ } ]",
+             b"]]]][[[[", b"[" * 50 + b"]" * 49, b'{"a":1,"b":[2,3]}', b'[1,2', b'{"k" 1}', b",", b'"s"', b"  "]
+
+    def val(dp):
+        r = rng.random()
+        if dp > 6 or r < 0.4:
+            return rng.choice([1, "s]", None, True])
+        if r < 0.7:
+            return [val(dp + 1) for _ in range(rng.randrange(0, 5))]
+        return {f"k{i}": val(dp + 1) for i in range(rng.randrange(0, 5))}
+
+    docs = []
+    for k in range(160):
+        if k % 3 == 0:
+            docs.append(rng.choice(small))
+        else:
+            d = json.dumps(val(0), separators=(",", ":")).encode()
+            if k % 7 == 0 and len(d) > 2:
+                d = d[:-1]  # unclosed
+            docs.append(d)
+    big = json.dumps([val(0) for _ in range(900)], separators=(",", ":")).encode()
+    docs.insert(40, big)
+    docs.insert(90, big[:-1])
+    _, _, on = _check_batch(docs, chunk_groups=2, doc_groups=3, far_groups=2)
+    assert int(on.sum()) > 3 * 4096 and int(on.max()) > 4096
+
+
+def test_batch_capacity_flag():
+    docs = [b"[1,2]", b'{"a":[]}', b"[[[]]]"]
+    data = b"".join(docs)
+    offs = np.array([0, 5, 13, 19], dtype=np.uint64)
+    oi, on, _, _ = _oracle_batch(data, offs)
+    m, e, v = emu.scopes_batch(data, offs, oi, on, cap=int(on.sum()) - 1)
+    assert v == 0 and np.all(e == 0x80000000)

@@ -300,7 +300,9 @@ int jsidx_scopes_reserve(uint64_t max_entries, uint32_t max_ndocs,
  *              or null).  Every atom and string is checked, each on its own.
  * The tape is the paper's only when jsidx_scopes reported no flag and out_err
  * is 0.  A per-stream workspace of about 33 bytes per entry is allocated on
- * first use and grown as needed (synchronising the stream).  Asynchronous on
+ * first use and grown as needed (synchronising the stream); after
+ * jsidx_tape_reserve for at least n entries the call never allocates or
+ * synchronises (it can be captured in a HIP graph).  Asynchronous on
  * `stream`; returns JSIDX_E_INVAL for NULL pointers or sizes out of range.
  */
 #define JSIDX_ERR_NUMBER 0x100u
@@ -310,6 +312,57 @@ int jsidx_tape(const uint8_t *buf, uint64_t len, const uint32_t *idx,
                uint32_t n, const uint32_t *match, uint64_t *out_tape,
                uint64_t *out_tape_n, uint8_t *out_str, uint64_t *out_str_n,
                uint32_t *out_err, jsidx_stream_t stream);
+
+/*
+ * jsidx_tape_batch -- jsidx_tape for many independent documents in one call
+ * (stage 2 takes each token on its own once the index is known, Sec. 3.2).
+ * The documents' tapes are laid end to end in out_tape, and their string
+ * buffers end to end in out_str; each document's tape is exactly what
+ * jsidx_tape writes for it alone (word 0 its own 'r', links and string
+ * offsets relative to its own tape and string buffer; an empty document's
+ * tape is its two 'r' words).
+ *   bufs, offsets, ndocs   as for jsidx_build_batch; the batch's bytes
+ *              (offsets[ndocs] - offsets[0]) must be below 2^32 - 2^16.
+ *   idx, n     jsidx_build_batch's index (document d's n[d] entries at
+ *              idx + offsets[d]) and counts.
+ *   match      jsidx_scopes_batch's links, in the same layout.
+ *   out_tape   device array of tape_cap uint64 (2 * (entries + ndocs)
+ *              always suffice).
+ *   out_str    device buffer of str_cap bytes (the batch's bytes plus twice
+ *              its entries, plus 4, always suffice).
+ *   out_pos    device array of 4 * ndocs uint64: for document d, the index
+ *              of its first word in out_tape, its word count, the offset of
+ *              its string buffer in out_str and that buffer's size.
+ *   out_err    device array of ndocs uint32: each document's flags, those
+ *              jsidx_tape gives for it alone.
+ * After jsidx_tape_reserve(max_entries, max_ndocs) on the stream with
+ * max_ndocs >= ndocs, the call never allocates or synchronises (it can be
+ * captured in a HIP graph).  A batch with more than max_entries + ndocs
+ * entries and empty documents, whose bytes reach 2^32 - 2^16, or whose tape or
+ * strings exceed tape_cap or str_cap, is not written: every out_err[d] is
+ * set to JSIDX_ERR_CAPACITY.  Without a reservation the call copies
+ * offsets[0] and offsets[ndocs] to the host (synchronising the stream) and
+ * sizes the workspace for one entry per byte.  Returns JSIDX_E_INVAL for
+ * NULL pointers or ndocs == 0.
+ */
+int jsidx_tape_batch(const uint8_t *bufs, const uint64_t *offsets,
+                     uint32_t ndocs, const uint32_t *idx, const uint32_t *n,
+                     const uint32_t *match, uint64_t *out_tape,
+                     uint64_t tape_cap, uint8_t *out_str, uint64_t str_cap,
+                     uint64_t *out_pos, uint32_t *out_err,
+                     jsidx_stream_t stream);
+
+/*
+ * jsidx_tape_reserve -- sizes the stream's tape workspace for documents of up
+ * to max_entries index entries (jsidx_tape) and for batches of up to
+ * max_entries entries in up to max_ndocs documents (jsidx_tape_batch; 0
+ * counts as 1): about 50 bytes per entry and 33 per document.  Synchronises
+ * the stream if it has to grow the workspace.  Returns JSIDX_E_TOO_LARGE for
+ * max_entries >= 2^31, JSIDX_E_NOWORKSPACE if the allocation fails (the
+ * stream then has no tape workspace).
+ */
+int jsidx_tape_reserve(uint64_t max_entries, uint32_t max_ndocs,
+                       jsidx_stream_t stream);
 
 /*
  * jsidx_reserve -- size the workspace of `stream` for inputs of up to

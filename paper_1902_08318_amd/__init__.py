@@ -10,5 +10,5 @@ from .binding import (  # noqa: F401
     ERR_CAPACITY, ERR_EMPTY, ERR_OFFSETS, ERR_LITERAL, ERR_MISMATCHED, ERR_NUMBER, ERR_STRING, ERR_SYNTAX, ERR_TRAILING_ESCAPE,
     ERR_UNBALANCED, ERR_UNCLOSED_STRING, ERR_UTF8,
     JsidxError, build, build_batch, diag, index, index_batch, library_path, minify, minify_batch, release, reserve,
-    VARIANTS, scopes, scopes_batch, scopes_reserve, set_tile_rows, set_variant, tape, tile_rows, workspace_bytes,
+    VARIANTS, scopes, scopes_batch, scopes_reserve, set_tile_rows, set_variant, tape, tape_batch, tape_reserve, tile_rows, workspace_bytes,
 )

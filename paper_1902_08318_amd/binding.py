@@ -37,6 +37,9 @@ SIGNATURES = {
     "jsidx_minify_batch": ([_VP, _VP, ctypes.c_uint32, _VP, _VP, _VP, _VP], ctypes.c_int),
     "jsidx_scopes": ([_VP, ctypes.c_uint64, _VP, ctypes.c_uint32, _VP, _VP, _VP], ctypes.c_int),
     "jsidx_scopes_batch": ([_VP, _VP, ctypes.c_uint32, _VP, _VP, _VP, _VP, _VP], ctypes.c_int),
+    "jsidx_tape_batch": ([_VP, _VP, ctypes.c_uint32, _VP, _VP, _VP, _VP, ctypes.c_uint64, _VP, ctypes.c_uint64, _VP,
+                          _VP, _VP], ctypes.c_int),
+    "jsidx_tape_reserve": ([ctypes.c_uint64, ctypes.c_uint32, _VP], ctypes.c_int),
     "jsidx_scopes_reserve": ([ctypes.c_uint64, ctypes.c_uint32, _VP], ctypes.c_int),
     "jsidx_reserve": ([ctypes.c_uint64, ctypes.c_uint32, _VP], ctypes.c_int),
     "jsidx_workspace_bytes": ([ctypes.c_uint64, ctypes.c_uint32], ctypes.c_size_t),
@@ -147,6 +150,21 @@ def scopes_batch(bufs, offsets, idx, n, out_match, out_err, stream=None, ndocs=N
     nd = offsets.numel() - 1 if ndocs is None else int(ndocs)
     _check(lib().jsidx_scopes_batch(_ptr(bufs), _ptr(offsets), nd, _ptr(idx), _ptr(n), _ptr(out_match),
                                     _ptr(out_err), _stream(stream)))
+
+
+def tape_batch(bufs, offsets, idx, n, match, out_tape, out_str, out_pos, out_err, stream=None, ndocs=None):
+    """jsidx_tape_batch on device tensors: out_tape (int64/uint64 words) and
+    out_str (uint8) give their capacities by their sizes; out_pos holds
+    4 * ndocs int64."""
+    nd = offsets.numel() - 1 if ndocs is None else int(ndocs)
+    _check(lib().jsidx_tape_batch(_ptr(bufs), _ptr(offsets), nd, _ptr(idx), _ptr(n), _ptr(match), _ptr(out_tape),
+                                  out_tape.numel(), _ptr(out_str), out_str.numel(), _ptr(out_pos), _ptr(out_err),
+                                  _stream(stream)))
+
+
+def tape_reserve(max_entries: int, max_ndocs: int = 0, stream=None):
+    """jsidx_tape_reserve."""
+    _check(lib().jsidx_tape_reserve(int(max_entries), int(max_ndocs), _stream(stream)))
 
 
 def scopes_reserve(max_entries: int, max_ndocs: int = 0, stream=None):

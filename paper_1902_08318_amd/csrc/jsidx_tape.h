@@ -68,7 +68,56 @@ struct TapeArgs {
   uint32_t* queue;      // entries for the exact conversion
   uint64_t* squeue;     // strings: entry and buffer offset
   uint32_t* nqueue;     // numbers: entry
+  // batches (jsidx_tape_batch): the documents' entries laid end to end as
+  // "virtual" entries (an empty document gets one placeholder entry, so that
+  // its two root words have an owner), every position absolute in buf, and
+  // each document's tape and strings laid end to end in the outputs
+  const uint64_t* offsets;  // ndocs + 1
+  const uint32_t* dn;       // per document: its entry count (idx and match at + offsets[d])
+  uint32_t ndocs;
+  uint32_t cap;             // virtual entries the workspace holds
+  uint64_t tape_cap, str_cap;  // words and bytes the outputs hold
+  uint32_t* vn;             // [0] virtual entries, [1] their chunks, [2] 1 if the outputs hold the batch
+  uint64_t* tot;            // total words and string bytes
+  uint32_t* vstart;         // ndocs + 1: first virtual entry of each document
+  uint32_t* docid;          // per virtual entry
+  uint64_t* vpos;           // per virtual entry: absolute position of its first byte
+  uint8_t* vflag;           // per virtual entry: kVFirst, kVLast, kVEmpty
+  uint64_t* dbase;          // per document: first word of its tape, first byte of its strings
+  uint64_t* out_pos;        // per document: tape start, tape words, string start, string bytes
 };
+
+constexpr uint32_t kVFirst = 1u, kVLast = 2u, kVEmpty = 4u;
+constexpr uint32_t kTapeErrCapacity = 0x80000000u;
+
+// Workspace layout of a batch (byte offsets; host side).
+struct TapeBatchLayout {
+  uint64_t vn, tot, qcount, vstart, docid, vpos, vflag, dbase, chunk_sum, sbytes, kb, toff, queue, squeue, nqueue,
+      total;
+};
+inline TapeBatchLayout tape_batch_layout(uint64_t cap, uint64_t maxdocs) {
+  const uint64_t nc = (cap + kTapeChunk - 1) / kTapeChunk;
+  TapeBatchLayout L;
+  uint64_t o = 0;
+  auto al = [](uint64_t x) { return (x + 255) & ~(uint64_t)255; };
+  L.vn = o; o = al(o + 16);
+  L.tot = o; o = al(o + 16);
+  L.qcount = o; o = al(o + 16);
+  L.vstart = o; o = al(o + (maxdocs + 1) * 4);
+  L.docid = o; o = al(o + cap * 4);
+  L.vpos = o; o = al(o + cap * 8);
+  L.vflag = o; o = al(o + cap);
+  L.dbase = o; o = al(o + maxdocs * 16);
+  L.chunk_sum = o; o = al(o + nc * 16);
+  L.sbytes = o; o = al(o + cap * 4);
+  L.kb = o; o = al(o + cap);
+  L.toff = o; o = al(o + cap * 4);
+  L.queue = o; o = al(o + cap * 4);
+  L.squeue = o; o = al(o + cap * 16);
+  L.nqueue = o; o = al(o + cap * 4);
+  L.total = o;
+  return L;
+}
 
 struct TapeLayout {
   uint64_t chunk_sum, sbytes, kb, toff, qcount, queue, squeue, nqueue, total;
@@ -390,7 +439,10 @@ JSIDX_DEV uint32_t wave_strings(const TapeArgs& a, bool has, uint64_t q, uint8_t
       outL = reinterpret_cast<uint8_t*>(((uint64_t)prim::readlane((uint32_t)(o >> 32), L) << 32) |
                                         prim::readlane((uint32_t)o, L));
     }
-    const uint32_t e = string_wave<WRITE>(a, pL, outL, &kL);
+    // the lane's own document bound (a batch's lanes may hold different documents)
+    TapeArgs aL = a;
+    aL.len = ((uint64_t)prim::readlane((uint32_t)(a.len >> 32), L) << 32) | prim::readlane((uint32_t)a.len, L);
+    const uint32_t e = string_wave<WRITE>(aL, pL, outL, &kL);
     if ((int)prim::lane() == L) {
       k = kL;
       err = e;
@@ -762,12 +814,14 @@ struct TapeScanLds {
 };
 // A chunk staged in LDS: first bytes, buffer bytes (then their prefix in the
 // chunk), tape indices.
-struct TapeChunkLds {
+template <bool BATCH>
+struct TapeChunkT {
   TapeScanLds sc;
   uint32_t qbase[2];  // the workgroup's first slots in the string and number queues
   uint32_t S[kTapeChunk];
   uint32_t T[kTapeChunk];
   uint8_t K[kTapeChunk];
+  uint8_t F[BATCH ? kTapeChunk : 4];  // batch flags of the entries
 };
 
 // Exclusive scan over the workgroup of two sums (ex: the threads before this
@@ -800,24 +854,55 @@ JSIDX_DEV void st64(uint64_t* p, uint64_t v) {
   prim::st_pair(reinterpret_cast<uint2*>(p), (uint32_t)v, (uint32_t)(v >> 32));
 }
 
+// Entry i's position (absolute for a batch) and the arguments to parse it
+// with (for a batch, the bound is its document's end).
+template <bool BATCH>
+JSIDX_DEV uint64_t entry_pos(const TapeArgs& a, uint64_t i) {
+  return BATCH ? ld64(a.vpos + i) : prim::load4(reinterpret_cast<const uint8_t*>(a.idx + i));
+}
+template <bool BATCH>
+JSIDX_DEV uint32_t entry_doc(const TapeArgs& a, uint64_t i) {
+  return BATCH ? prim::load4(reinterpret_cast<const uint8_t*>(a.docid + i)) : 0u;
+}
+template <bool BATCH>
+JSIDX_DEV TapeArgs entry_args(const TapeArgs& a, uint32_t d) {
+  TapeArgs r = a;
+  if (BATCH) r.len = prim::load8(a.offsets + d + 1);
+  return r;
+}
+template <bool BATCH>
+JSIDX_DEV uint32_t n_of(const TapeArgs& a) { return BATCH ? prim::ld_agent32(a.vn) : a.n; }
+template <bool BATCH>
+JSIDX_DEV uint32_t nchunks_of(const TapeArgs& a) { return BATCH ? prim::ld_agent32(a.vn + 1) : a.nchunks; }
+// Tape words of an entry with first byte b and batch flags f: its own, plus
+// its document's root words if it is the document's first or last entry.
+JSIDX_DEV uint32_t entry_words(uint32_t b, uint32_t f) {
+  return words_of(b) + (f & kVFirst ? 1u : 0u) + (f & kVLast ? 1u : 0u);
+}
+
 // 1. First bytes and string sizes (thread t takes entries c * 4096 + t +
 //    256 k), their sums per chunk.
+template <bool BATCH>
 JSIDX_DEVFN void tape_count(const TapeArgs& a) {
   TapeScanLds& g = prim::lds_object<TapeScanLds>();
-  const uint32_t tid = tape_tid(), c = prim::block();
+  const uint32_t tid = tape_tid();
+  const uint32_t n = n_of<BATCH>(a), nchunks = nchunks_of<BATCH>(a);
+  for (uint32_t c = prim::block(); c < nchunks; c += prim::grid()) {
   uint64_t w = 0, s = 0;
   for (int k = 0; k < kTapePer; k++) {  // every lane runs every step (wave_strings)
     const uint64_t i = (uint64_t)c * kTapeChunk + (uint64_t)k * kTapeThreads + tid;
-    const bool in = i < a.n;
-    const uint64_t pos = in ? prim::load4(reinterpret_cast<const uint8_t*>(a.idx + i)) : 0u;
-    const uint32_t b = in ? byte_at(a, pos) : 0u;
+    const bool in = i < n;
+    const uint32_t f = BATCH && in ? prim::load1(a.vflag + i) : 0u;
+    const TapeArgs la = entry_args<BATCH>(a, in ? entry_doc<BATCH>(a, i) : 0u);
+    const uint64_t pos = in ? entry_pos<BATCH>(a, i) : 0u;
+    const uint32_t b = !in ? 0u : (f & kVEmpty) ? (uint32_t)':' : byte_at(la, pos);
     uint32_t len = 0;
-    (void)wave_strings<false>(a, in && b == '"', pos, nullptr, &len);
+    (void)wave_strings<false>(la, in && b == '"', pos, nullptr, &len);
     if (!in) continue;
     const uint32_t sb = b == '"' ? 4 + len : 0u;
     prim::st_out(a.sbytes + i, sb);
     prim::st_byte(a.kb + i, b);
-    w += words_of(b);
+    w += entry_words(b, f);
     s += sb;
   }
   uint64_t wex, sex, wall, sall;
@@ -826,15 +911,21 @@ JSIDX_DEVFN void tape_count(const TapeArgs& a) {
     st64(a.chunk_sum + 2 * (uint64_t)c, wall);
     st64(a.chunk_sum + 2 * (uint64_t)c + 1, sall);
   }
+  prim::sync();
+  }
 }
 
 // 2. Chunk bases (one workgroup), the root words, the sizes; flags cleared.
+//    For a batch: the totals, checked against the outputs (a batch that does
+//    not fit is not written: every document gets JSIDX_ERR_CAPACITY).
+template <bool BATCH>
 JSIDX_DEVFN void tape_scan(const TapeArgs& a) {
   TapeScanLds& g = prim::lds_object<TapeScanLds>();
   const uint32_t tid = tape_tid();
-  const uint32_t per = (a.nchunks + kTapeThreads - 1) / kTapeThreads;
+  const uint32_t nchunks = nchunks_of<BATCH>(a);
+  const uint32_t per = (nchunks + kTapeThreads - 1) / kTapeThreads;
   const uint64_t lo = (uint64_t)tid * per;
-  const uint64_t hi = lo + per < a.nchunks ? lo + per : a.nchunks;
+  const uint64_t hi = lo + per < nchunks ? lo + per : nchunks;
   uint64_t w = 0, s = 0;
   for (uint64_t c = lo; c < hi; c++) {
     w += ld64(a.chunk_sum + 2 * c);
@@ -849,6 +940,18 @@ JSIDX_DEVFN void tape_scan(const TapeArgs& a) {
     wex += cw;
     sex += cs;
   }
+  if (BATCH) {
+    if (nchunks == 0) return;  // tape_batch_count flagged the batch
+    const bool fits = wall <= a.tape_cap && sall <= a.str_cap;
+    if (!fits)
+      for (uint32_t d = tid; d < a.ndocs; d += (uint32_t)kTapeThreads) prim::st_out(a.err + d, kTapeErrCapacity);
+    if (tid == 0) {
+      st64(a.tot, wall);
+      st64(a.tot + 1, sall);
+      prim::st_out(a.vn + 2, fits ? 1u : 0u);
+    }
+    return;
+  }
   if (tid == 0) {
     const uint64_t last = wall + 1;  // the root words enclose the words of the entries
     st64(a.tape, ((uint64_t)'r' << 56) | last);
@@ -860,53 +963,80 @@ JSIDX_DEVFN void tape_scan(const TapeArgs& a) {
   }
 }
 
+// Whether a batch's outputs hold it (kernels after tape_scan).
+template <bool BATCH>
+JSIDX_DEV bool batch_go(const TapeArgs& a) { return !BATCH || prim::ld_agent32(a.vn + 2) != 0u; }
+
 // Stages chunk c (first bytes and string sizes, loaded coalesced) and turns
 // them into each entry's tape index (T) and buffer offset (S) by a scan over
-// the threads' runs of 16 entries.
-JSIDX_DEV void stage_offsets(const TapeArgs& a, TapeChunkLds& g, uint32_t tid, uint32_t c) {
+// the threads' runs of 16 entries.  (For a batch, T is the index of the
+// entry's own first word, after its document's opening root word if it is
+// the document's first entry; F holds the batch flags.)
+template <bool BATCH>
+JSIDX_DEV void stage_offsets(const TapeArgs& a, uint32_t n, TapeChunkT<BATCH>& g, uint32_t tid, uint32_t c) {
   const uint64_t c0 = (uint64_t)c * kTapeChunk;
   for (uint32_t j = tid; j < (uint32_t)kTapeChunk; j += kTapeThreads) {
-    const bool in = c0 + j < a.n;
+    const bool in = c0 + j < n;
     g.K[j] = (uint8_t)(in ? prim::load1(a.kb + c0 + j) : ':');
     g.S[j] = in ? prim::load4(reinterpret_cast<const uint8_t*>(a.sbytes + c0 + j)) : 0u;
+    if (BATCH) g.F[j] = (uint8_t)(in ? prim::load1(a.vflag + c0 + j) : 0u);
   }
   prim::sync();
   uint64_t w = 0, s = 0;
   for (int k = 0; k < kTapePer; k++) {
     const uint32_t j = tid * kTapePer + (uint32_t)k;
-    w += words_of(g.K[j]);
+    w += BATCH ? entry_words(g.K[j], g.F[j]) : words_of(g.K[j]);
     s += g.S[j];
   }
   uint64_t wex, sex, wall, sall;
   group_scan2(g.sc, tid, w, s, &wex, &sex, &wall, &sall);
-  uint64_t tw = 1 + ld64(a.chunk_sum + 2 * (uint64_t)c) + wex;
+  uint64_t tw = (BATCH ? 0 : 1) + ld64(a.chunk_sum + 2 * (uint64_t)c) + wex;
   uint64_t ts = ld64(a.chunk_sum + 2 * (uint64_t)c + 1) + sex;
   for (int k = 0; k < kTapePer; k++) {
     const uint32_t j = tid * kTapePer + (uint32_t)k;
     const uint32_t sb = g.S[j];
-    g.T[j] = (uint32_t)tw;
+    const uint32_t first = BATCH && (g.F[j] & kVFirst) ? 1u : 0u;
+    if (BATCH && first && c0 + j < n) {
+      // the document's bases: its opening root word and its first string byte
+      const uint32_t d = prim::load4(reinterpret_cast<const uint8_t*>(a.docid + c0 + j));
+      st64(a.dbase + 2 * (uint64_t)d, tw);
+      st64(a.dbase + 2 * (uint64_t)d + 1, ts);
+    }
+    g.T[j] = (uint32_t)(tw + first);
     g.S[j] = (uint32_t)ts;  // the buffer offset's low word (see tape_write)
-    tw += words_of(g.K[j]);
+    tw += BATCH ? entry_words(g.K[j], g.F[j]) : words_of(g.K[j]);
     ts += sb;
   }
   prim::sync();
 }
 
 // 3. Each entry's tape index, stored coalesced.
+template <bool BATCH>
 JSIDX_DEVFN void tape_offsets(const TapeArgs& a) {
-  TapeChunkLds& g = prim::lds_object<TapeChunkLds>();
-  const uint32_t tid = tape_tid(), c = prim::block();
-  stage_offsets(a, g, tid, c);
-  const uint64_t c0 = (uint64_t)c * kTapeChunk;
-  for (uint32_t j = tid; j < (uint32_t)kTapeChunk; j += kTapeThreads) {
-    if (c0 + j >= a.n) break;
-    prim::st_out(a.toff + c0 + j, g.T[j]);
+  TapeChunkT<BATCH>& g = prim::lds_object<TapeChunkT<BATCH>>();
+  const uint32_t tid = tape_tid();
+  if (!batch_go<BATCH>(a)) return;
+  const uint32_t n = n_of<BATCH>(a), nchunks = nchunks_of<BATCH>(a);
+  for (uint32_t c = prim::block(); c < nchunks; c += prim::grid()) {
+    stage_offsets<BATCH>(a, n, g, tid, c);
+    const uint64_t c0 = (uint64_t)c * kTapeChunk;
+    for (uint32_t j = tid; j < (uint32_t)kTapeChunk; j += kTapeThreads) {
+      if (c0 + j >= n) break;
+      prim::st_out(a.toff + c0 + j, g.T[j]);
+    }
+    prim::sync();
   }
 }
 
-// Flags of a wave: one atomic per flag that some lane set.
-JSIDX_DEV void or_flags(const TapeArgs& a, uint32_t err) {
+// Flags of a wave: one atomic per flag that some lane set (for a batch, one
+// per lane with a flag, to its document's word).
+template <bool BATCH>
+JSIDX_DEV void or_flags(const TapeArgs& a, uint32_t err, uint32_t d) {
   const uint32_t lane = prim::lane();
+  if (BATCH) {
+    if (err) prim::or_agent32(a.err + d, err);
+    return;
+  }
   for (uint32_t f = kErrNumber; f <= kErrLiteral; f <<= 1)
     if (prim::ballot((err & f) != 0u) != 0ull && lane == 0) prim::or_agent32(a.err, f);
 }
@@ -921,13 +1051,38 @@ JSIDX_DEV uint32_t wave_append(const TapeArgs& a, int q, bool take) {
   return base + prim::mbcnt(m);
 }
 
+// 3b. Each document's root words and its place in the outputs (batches; one
+//     thread per document).
+JSIDX_DEVFN void tape_batch_docs(const TapeArgs& a) {
+  if (!batch_go<true>(a)) return;
+  const uint32_t stride = prim::grid() * (uint32_t)kTapeThreads;
+  const uint64_t tw = ld64(a.tot), ts = ld64(a.tot + 1);
+  for (uint32_t d = prim::block() * (uint32_t)kTapeThreads + tape_tid(); d < a.ndocs; d += stride) {
+    const uint64_t w0 = ld64(a.dbase + 2 * (uint64_t)d), s0 = ld64(a.dbase + 2 * (uint64_t)d + 1);
+    const uint64_t w1 = d + 1 < a.ndocs ? ld64(a.dbase + 2 * (uint64_t)d + 2) : tw;
+    const uint64_t s1 = d + 1 < a.ndocs ? ld64(a.dbase + 2 * (uint64_t)d + 3) : ts;
+    const uint64_t last = w1 - w0 - 1;
+    st64(a.tape + w0, ((uint64_t)'r' << 56) | last);
+    st64(a.tape + w0 + last, (uint64_t)'r' << 56);
+    st64(a.out_pos + 4 * (uint64_t)d, w0);
+    st64(a.out_pos + 4 * (uint64_t)d + 1, w1 - w0);
+    st64(a.out_pos + 4 * (uint64_t)d + 2, s0);
+    st64(a.out_pos + 4 * (uint64_t)d + 3, s1 - s0);
+  }
+}
+
 // 4. Brackets and the strings' words; strings, numbers and literals queued
 //    (one thread per entry, consecutive threads on consecutive entries; one
-//    atomic per workgroup and queue).
+//    atomic per workgroup and queue).  In a batch, links and string offsets
+//    are relative to the entry's document's tape and strings.
+template <bool BATCH>
 JSIDX_DEVFN void tape_write(const TapeArgs& a) {
-  TapeChunkLds& g = prim::lds_object<TapeChunkLds>();
-  const uint32_t tid = tape_tid(), c = prim::block();
-  stage_offsets(a, g, tid, c);
+  TapeChunkT<BATCH>& g = prim::lds_object<TapeChunkT<BATCH>>();
+  const uint32_t tid = tape_tid();
+  if (!batch_go<BATCH>(a)) return;
+  const uint32_t n = n_of<BATCH>(a), nchunks = nchunks_of<BATCH>(a);
+  for (uint32_t c = prim::block(); c < nchunks; c += prim::grid()) {
+  stage_offsets<BATCH>(a, n, g, tid, c);
   // the workgroup's slots in the two queues
   uint64_t cs = 0, cn = 0;
   for (int k = 0; k < kTapePer; k++) {
@@ -944,72 +1099,95 @@ JSIDX_DEVFN void tape_write(const TapeArgs& a) {
   }
   prim::sync();
   uint32_t ps = g.qbase[0] + (uint32_t)sex, pn = g.qbase[1] + (uint32_t)nex;
-  // a chunk's buffer bytes stay below 2^32 (its strings lie in the document,
-  // len < 2^32 - 2^16), so an offset is the chunk base plus its low word's
-  // distance from the base's
+  // a chunk's buffer bytes stay below 2^32 (its strings lie in the input,
+  // fewer than 2^32 - 2^16 bytes), so an offset is the chunk base plus its
+  // low word's distance from the base's
   const uint64_t sbase = ld64(a.chunk_sum + 2 * (uint64_t)c + 1);
-  uint32_t err = 0;
   for (int k = 0; k < kTapePer; k++) {
     const uint32_t j = (uint32_t)k * kTapeThreads + tid;
     const uint64_t i = (uint64_t)c * kTapeChunk + j;
-    if (i >= a.n) break;
+    if (i >= n) break;
     const uint32_t b = g.K[j];
     const uint64_t t = g.T[j];
-    if (b == '{' || b == '[' || b == '}' || b == ']') {
-      const uint32_t m = prim::load4(reinterpret_cast<const uint8_t*>(a.match + i));
+    const bool bracket = b == '{' || b == '[' || b == '}' || b == ']';
+    if (!bracket && b != '"' && !(words_of(b) == 2 || is_lit_start(b))) continue;
+    uint32_t d = 0;
+    uint64_t w0 = 0, s0 = 0;
+    if (BATCH) {
+      d = prim::load4(reinterpret_cast<const uint8_t*>(a.docid + i));
+      w0 = ld64(a.dbase + 2 * (uint64_t)d);
+      s0 = ld64(a.dbase + 2 * (uint64_t)d + 1);
+    }
+    if (bracket) {
       uint64_t link = 0;
-      if (m != kTapeUnlinked && m < a.n) {
-        const uint64_t tk = prim::load4(reinterpret_cast<const uint8_t*>(a.toff + m));
+      uint32_t m = kTapeUnlinked, lim = n, mv = 0;
+      if (BATCH) {
+        const uint32_t v0 = prim::load4(reinterpret_cast<const uint8_t*>(a.vstart + d));
+        const uint64_t ob = prim::load8(a.offsets + d);
+        m = prim::load4(reinterpret_cast<const uint8_t*>(a.match + ob + (i - v0)));
+        lim = prim::load4(reinterpret_cast<const uint8_t*>(a.dn + d));
+        mv = v0 + m;
+      } else {
+        m = prim::load4(reinterpret_cast<const uint8_t*>(a.match + i));
+        mv = m;
+      }
+      if (m != kTapeUnlinked && m < lim) {
+        const uint64_t tk = prim::load4(reinterpret_cast<const uint8_t*>(a.toff + mv)) - w0;
         link = (b == '{' || b == '[') ? tk + 1 : tk;
       }
       st64(a.tape + t, ((uint64_t)b << 56) | link);
     } else if (b == '"') {
       const uint64_t so = sbase + (uint32_t)(g.S[j] - (uint32_t)sbase);
-      st64(a.tape + t, ((uint64_t)'"' << 56) | so);
+      st64(a.tape + t, ((uint64_t)'"' << 56) | (so - s0));
       st64(a.squeue + 2 * (uint64_t)ps, i);
       st64(a.squeue + 2 * (uint64_t)ps + 1, so);
       ps++;
-    } else if (words_of(b) == 2 || is_lit_start(b)) {
+    } else {
       prim::st_out(a.nqueue + pn, (uint32_t)i);
       pn++;
     }
   }
-  or_flags(a, err);
+  prim::sync();
+  }
 }
 
 // Grid-stride bounds of a queue for this thread.
 JSIDX_DEV uint32_t queue_len(const TapeArgs& a, int q) { return prim::ld_agent32(a.qcount + q); }
 
 // 5. Strings: decoded into the buffer after their 32-bit length.
+template <bool BATCH>
 JSIDX_DEVFN void tape_strings(const TapeArgs& a) {
+  if (!batch_go<BATCH>(a)) return;
   const uint32_t qn = queue_len(a, 1);
   const uint32_t stride = prim::grid() * (uint32_t)kTapeThreads;
-  uint32_t err = 0;
   const uint32_t rounds = (qn + stride - 1) / stride;  // the same for every lane (wave_strings)
   for (uint32_t r = 0; r < rounds; r++) {
     const uint32_t q = r * stride + prim::block() * (uint32_t)kTapeThreads + tape_tid();
     const bool has = q < qn;
     uint64_t so = 0, pos = 0;
+    uint32_t d = 0;
     if (has) {
       const uint32_t i = (uint32_t)ld64(a.squeue + 2 * (uint64_t)q);
       so = ld64(a.squeue + 2 * (uint64_t)q + 1);
-      pos = prim::load4(reinterpret_cast<const uint8_t*>(a.idx + i));
+      pos = entry_pos<BATCH>(a, i);
+      d = entry_doc<BATCH>(a, i);
     }
+    const TapeArgs la = entry_args<BATCH>(a, d);
     uint32_t k = 0;
-    const uint32_t e = wave_strings<true>(a, has, pos, a.str + so + 4, &k);
+    const uint32_t e = wave_strings<true>(la, has, pos, a.str + so + 4, &k);
+    uint32_t err = 0;
     if (has) {
-      err |= e;
+      err = e;
       for (int j = 0; j < 4; j++) prim::st_byte(a.str + so + j, (k >> (8 * j)) & 0xFFu);
     }
+    or_flags<BATCH>(a, err, d);
   }
-  or_flags(a, err);
 }
 
 // 6. Numbers (both words; undecided doubles queued for tape_exact) and
-//    literals.
-JSIDX_DEV uint32_t number_entry(const TapeArgs& a, uint32_t i, bool* undecided) {
-  const uint64_t pos = prim::load4(reinterpret_cast<const uint8_t*>(a.idx + i));
-  const uint64_t t = prim::load4(reinterpret_cast<const uint8_t*>(a.toff + i));
+//    literals.  (a: arguments whose bound is the entry's document; pos its
+//    first byte.)
+JSIDX_DEV uint32_t number_entry(const TapeArgs& a, uint64_t pos, uint64_t t, bool* undecided) {
   uint64_t* out = a.tape + t;
   *undecided = false;
   const uint32_t b = byte_at(a, pos);
@@ -1061,23 +1239,26 @@ JSIDX_DEV uint32_t number_entry(const TapeArgs& a, uint32_t i, bool* undecided) 
   return 0;
 }
 
+template <bool BATCH>
 JSIDX_DEVFN void tape_numbers(const TapeArgs& a) {
+  if (!batch_go<BATCH>(a)) return;
   const uint32_t qn = queue_len(a, 2);
   const uint32_t stride = prim::grid() * (uint32_t)kTapeThreads;
-  uint32_t err = 0;
   const uint32_t rounds = (qn + stride - 1) / stride;
   for (uint32_t r = 0; r < rounds; r++) {
     const uint32_t q = r * stride + prim::block() * (uint32_t)kTapeThreads + tape_tid();
     bool undecided = false;
-    uint32_t i = 0;
+    uint32_t i = 0, d = 0, err = 0;
     if (q < qn) {
       i = prim::load4(reinterpret_cast<const uint8_t*>(a.nqueue + q));
-      err |= number_entry(a, i, &undecided);
+      d = entry_doc<BATCH>(a, i);
+      const uint64_t t = prim::load4(reinterpret_cast<const uint8_t*>(a.toff + i));
+      err = number_entry(entry_args<BATCH>(a, d), entry_pos<BATCH>(a, i), t, &undecided);
     }
     const uint32_t slot = wave_append(a, 0, undecided);
     if (undecided) prim::st_out(a.queue + slot, i);
+    or_flags<BATCH>(a, err, d);
   }
-  or_flags(a, err);
 }
 
 // 7. The queued numbers, one thread each, by exact arithmetic.
@@ -1085,26 +1266,95 @@ struct ExactScratch {
   Big D, V, S;
 };
 
+template <bool BATCH>
 JSIDX_DEV void exact_entry(const TapeArgs& a, uint32_t i, ExactScratch& x) {
-  const uint64_t pos = prim::load4(reinterpret_cast<const uint8_t*>(a.idx + i));
+  const uint32_t d = entry_doc<BATCH>(a, i);
+  const TapeArgs la = entry_args<BATCH>(a, d);
+  const uint64_t pos = entry_pos<BATCH>(a, i);
   const uint64_t t = prim::load4(reinterpret_cast<const uint8_t*>(a.toff + i));
   uint64_t bits = 0;
-  const int r = exact_double(a, pos, x.D, x.V, x.S, &bits);
+  const int r = exact_double(la, pos, x.D, x.V, x.S, &bits);
   if (r == kConvInf) {
     st64(a.tape + t + 1, 0);
-    prim::or_agent32(a.err, kErrNumber);
+    prim::or_agent32(a.err + d, kErrNumber);
     return;
   }
-  const uint64_t sign = byte_at(a, pos) == '-' ? 1ull << 63 : 0ull;
+  const uint64_t sign = byte_at(la, pos) == '-' ? 1ull << 63 : 0ull;
   st64(a.tape + t + 1, bits | sign);
 }
 
+template <bool BATCH>
 JSIDX_DEVFN void tape_exact(const TapeArgs& a) {
+  if (!batch_go<BATCH>(a)) return;
   ExactScratch x;
   const uint32_t qn = prim::ld_agent32(a.qcount);
   const uint32_t stride = prim::grid() * (uint32_t)kExactThreads;
   for (uint32_t q = prim::block() * (uint32_t)kExactThreads + prim::lane(); q < qn; q += stride)
-    exact_entry(a, prim::load4(reinterpret_cast<const uint8_t*>(a.queue + q)), x);
+    exact_entry<BATCH>(a, prim::load4(reinterpret_cast<const uint8_t*>(a.queue + q)), x);
+}
+
+// ---- Batches ---------------------------------------------------------------
+// 0. The first virtual entry of each document (an empty document counts one
+//    placeholder entry), the totals, the flags cleared and the queues
+//    emptied (one workgroup).  A batch with more virtual entries than the
+//    workspace holds, or whose bytes reach 2^32 - 2^16, is not written: every
+//    document gets JSIDX_ERR_CAPACITY and the kernels after this one do
+//    nothing.
+JSIDX_DEVFN void tape_batch_count(const TapeArgs& a) {
+  TapeScanLds& g = prim::lds_object<TapeScanLds>();
+  const uint32_t tid = tape_tid();
+  const uint32_t per = (a.ndocs + kTapeThreads - 1) / kTapeThreads;
+  const uint64_t lo = (uint64_t)tid * per;
+  const uint64_t hi = lo + per < a.ndocs ? lo + per : a.ndocs;
+  uint64_t sum = 0;
+  for (uint64_t d = lo; d < hi; d++) {
+    const uint32_t nd = prim::load4(reinterpret_cast<const uint8_t*>(a.dn + d));
+    sum += nd ? nd : 1u;
+  }
+  uint64_t ex, sx, total, st;
+  group_scan2(g, tid, sum, 0, &ex, &sx, &total, &st);
+  const uint64_t span = prim::load8(a.offsets + a.ndocs) - prim::load8(a.offsets);
+  const bool over = total > (uint64_t)a.cap || span >= (1ull << 32) - (1ull << 16);
+  uint64_t v = ex;
+  for (uint64_t d = lo; d < hi; d++) {
+    const uint32_t nd = prim::load4(reinterpret_cast<const uint8_t*>(a.dn + d));
+    if (!over) prim::st_out(a.vstart + d, (uint32_t)v);
+    prim::st_out(a.err + d, over ? kTapeErrCapacity : 0u);
+    v += nd ? nd : 1u;
+  }
+  if (tid == kTapeThreads - 1) {
+    if (!over) prim::st_out(a.vstart + a.ndocs, (uint32_t)total);
+    prim::st_out(a.vn, over ? 0u : (uint32_t)total);
+    prim::st_out(a.vn + 1, over ? 0u : (uint32_t)((total + kTapeChunk - 1) / kTapeChunk));
+    prim::st_out(a.vn + 2, 0u);
+    for (int q = 0; q < 3; q++) prim::st_out(a.qcount + q, 0u);
+  }
+}
+
+// 1b. Each document's entries into the virtual sequence: absolute positions,
+//     document numbers and flags (one wave per document).
+JSIDX_DEVFN void tape_batch_compact(const TapeArgs& a) {
+  const uint32_t lane = prim::lane();
+  if (prim::ld_agent32(a.vn + 1) == 0u) return;
+  const uint32_t waves_per_group = kTapeThreads / 64u;
+  const uint32_t nw = prim::grid() * waves_per_group;
+  for (uint32_t d = prim::block() * waves_per_group + prim::wave_id(); d < a.ndocs; d += nw) {
+    const uint64_t base = prim::load8(a.offsets + d);
+    const uint32_t nd = prim::load4(reinterpret_cast<const uint8_t*>(a.dn + d));
+    const uint32_t v0 = prim::load4(reinterpret_cast<const uint8_t*>(a.vstart + d));
+    const uint32_t cnt = nd ? nd : 1u;
+    for (uint32_t j = lane; j < cnt; j += 64u) {
+      uint32_t f = 0;
+      uint64_t pos = base;
+      if (nd) pos += prim::load4(reinterpret_cast<const uint8_t*>(a.idx + base + j));
+      else f |= kVEmpty;
+      if (j == 0) f |= kVFirst;
+      if (j + 1 == cnt) f |= kVLast;
+      st64(a.vpos + v0 + j, pos);
+      prim::st_byte(a.vflag + v0 + j, f);
+      prim::st_out(a.docid + v0 + j, d);
+    }
+  }
 }
 
 }  // namespace jsidx

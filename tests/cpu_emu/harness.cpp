@@ -299,20 +299,104 @@ long emu_tape_run(const uint8_t* buf, uint64_t len, const uint32_t* idx, uint32_
     for (auto& x : th) x.join();
     for (auto* g : groups) delete g;
   };
-  if (a.nchunks) phase((int)a.nchunks, kTapeThreads, tape_count);
-  phase(1, kTapeThreads, tape_scan);
+  if (a.nchunks) phase((int)a.nchunks, kTapeThreads, tape_count<false>);
+  phase(1, kTapeThreads, tape_scan<false>);
   if (a.nchunks) {
-    phase((int)a.nchunks, kTapeThreads, tape_offsets);
-    phase((int)a.nchunks, kTapeThreads, tape_write);
-    phase(2, kTapeThreads, tape_strings);
-    phase(2, kTapeThreads, tape_numbers);
-    phase(exact_groups, kExactThreads, tape_exact);
+    phase((int)a.nchunks, kTapeThreads, tape_offsets<false>);
+    phase((int)a.nchunks, kTapeThreads, tape_write<false>);
+    phase(2, kTapeThreads, tape_strings<false>);
+    phase(2, kTapeThreads, tape_numbers<false>);
+    phase(exact_groups, kExactThreads, tape_exact<false>);
   }
   *exact_count = n ? *a.qcount : 0u;
   return env.violations.load();
 }
 
 uint64_t emu_tape_ws_bytes(uint64_t n) { return tape_layout(n).total; }
+uint64_t emu_tape_batch_ws_bytes(uint64_t cap, uint64_t ndocs) { return tape_batch_layout(cap, ndocs).total; }
+
+// The batched tape kernels over ndocs documents (index and links in the
+// batch layout); out_pos receives each document's tape start and words,
+// string start and bytes.  Returns the number of out-of-range accesses.
+long emu_tape_batch_run(const uint8_t* buf, const uint64_t* offsets, uint32_t ndocs, const uint32_t* idx,
+                        const uint32_t* n, const uint32_t* match, uint64_t* tape, uint64_t tape_cap, uint8_t* str,
+                        uint64_t str_cap, uint64_t* out_pos, uint32_t* err, void* ws, uint64_t cap, int chunk_groups,
+                        int doc_groups, int exact_groups) {
+  const TapeBatchLayout L = tape_batch_layout(cap, ndocs);
+  const uint64_t total = offsets[ndocs];
+  prim::EmuEnv env;
+  if (total) env.reads[env.nreads++] = {buf, buf + total};
+  env.reads[env.nreads++] = {offsets, offsets + ndocs + 1};
+  if (total) env.reads[env.nreads++] = {idx, idx + total};
+  if (total) env.reads[env.nreads++] = {match, match + total};
+  env.reads[env.nreads++] = {n, n + ndocs};
+  env.reads[env.nreads++] = {ws, (const uint8_t*)ws + L.total};
+  env.writes[env.nwrites++] = {tape, tape + tape_cap};
+  env.writes[env.nwrites++] = {str, str + str_cap};
+  env.writes[env.nwrites++] = {out_pos, out_pos + 4 * (uint64_t)ndocs};
+  env.writes[env.nwrites++] = {err, err + ndocs};
+  env.writes[env.nwrites++] = {ws, (const uint8_t*)ws + L.total};
+  uint8_t* m = static_cast<uint8_t*>(ws);
+  TapeArgs a{};
+  a.buf = buf;
+  a.idx = idx;
+  a.match = match;
+  a.tape = tape;
+  a.str = str;
+  a.err = err;
+  a.chunk_sum = reinterpret_cast<uint64_t*>(m + L.chunk_sum);
+  a.sbytes = reinterpret_cast<uint32_t*>(m + L.sbytes);
+  a.toff = reinterpret_cast<uint32_t*>(m + L.toff);
+  a.kb = m + L.kb;
+  a.qcount = reinterpret_cast<uint32_t*>(m + L.qcount);
+  a.queue = reinterpret_cast<uint32_t*>(m + L.queue);
+  a.squeue = reinterpret_cast<uint64_t*>(m + L.squeue);
+  a.nqueue = reinterpret_cast<uint32_t*>(m + L.nqueue);
+  a.offsets = offsets;
+  a.dn = n;
+  a.ndocs = ndocs;
+  a.cap = (uint32_t)cap;
+  a.tape_cap = tape_cap;
+  a.str_cap = str_cap;
+  a.vn = reinterpret_cast<uint32_t*>(m + L.vn);
+  a.tot = reinterpret_cast<uint64_t*>(m + L.tot);
+  a.vstart = reinterpret_cast<uint32_t*>(m + L.vstart);
+  a.docid = reinterpret_cast<uint32_t*>(m + L.docid);
+  a.vpos = reinterpret_cast<uint64_t*>(m + L.vpos);
+  a.vflag = m + L.vflag;
+  a.dbase = reinterpret_cast<uint64_t*>(m + L.dbase);
+  a.out_pos = out_pos;
+  auto phase = [&](int ngroups, int nthreads, void (*body)(const TapeArgs&)) {
+    std::vector<prim::GroupCtx*> groups;
+    for (int b = 0; b < ngroups; b++) groups.push_back(new prim::GroupCtx((uint32_t)nthreads));
+    std::vector<std::thread> th;
+    for (int b = 0; b < ngroups; b++) {
+      for (uint32_t t = 0; t < (uint32_t)nthreads; t++) {
+        th.emplace_back([&, b, t] {
+          prim::tctx.tid = t;
+          prim::tctx.block = (uint32_t)b;
+          prim::tctx.grid = (uint32_t)ngroups;
+          prim::tctx.g = groups[(size_t)b];
+          prim::tctx.env = &env;
+          body(a);
+        });
+      }
+    }
+    for (auto& x : th) x.join();
+    for (auto* g : groups) delete g;
+  };
+  phase(1, kTapeThreads, tape_batch_count);
+  phase(doc_groups, kTapeThreads, tape_batch_compact);
+  phase(chunk_groups, kTapeThreads, tape_count<true>);
+  phase(1, kTapeThreads, tape_scan<true>);
+  phase(chunk_groups, kTapeThreads, tape_offsets<true>);
+  phase(doc_groups, kTapeThreads, tape_batch_docs);
+  phase(chunk_groups, kTapeThreads, tape_write<true>);
+  phase(2, kTapeThreads, tape_strings<true>);
+  phase(2, kTapeThreads, tape_numbers<true>);
+  phase(exact_groups, kExactThreads, tape_exact<true>);
+  return env.violations.load();
+}
 
 // One number text through the fast conversion (exact == 0; the grammar scan
 // first) or the exact one (exact == 1).  Returns kConvOk / kConvInf /

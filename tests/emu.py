@@ -95,6 +95,11 @@ def load(block_tiles: int | None = None):
     lib.emu_tape_ws_bytes.restype = ctypes.c_uint64
     lib.emu_scopes_ws_bytes.argtypes = [ctypes.c_uint64]
     lib.emu_scopes_ws_bytes.restype = ctypes.c_uint64
+    lib.emu_tape_batch_ws_bytes.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+    lib.emu_tape_batch_ws_bytes.restype = ctypes.c_uint64
+    lib.emu_tape_batch_run.argtypes = [vp, vp, ctypes.c_uint32, vp, vp, vp, vp, ctypes.c_uint64, vp, ctypes.c_uint64,
+                                       vp, vp, vp, ctypes.c_uint64, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.emu_tape_batch_run.restype = ctypes.c_long
     lib.emu_scopes_batch_ws_bytes.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
     lib.emu_scopes_batch_ws_bytes.restype = ctypes.c_uint64
     lib.emu_scopes_batch_run.argtypes = [vp, vp, ctypes.c_uint32, vp, vp, vp, vp, vp, ctypes.c_uint64, ctypes.c_int,
@@ -248,6 +253,36 @@ def tape(data: bytes, idx: np.ndarray, match: np.ndarray, exact_groups: int = 2)
                          sbuf.ctypes.data, scap, tn.ctypes.data, sn.ctypes.data, err.ctypes.data, ws.ctypes.data,
                          exact_groups, nx.ctypes.data)
     return words[:int(tn[0])], sbuf[:int(sn[0])].tobytes(), int(err[0]), int(v), int(nx[0])
+
+
+def tape_batch(data: bytes, offsets: np.ndarray, idx: np.ndarray, n: np.ndarray, match: np.ndarray,
+               cap: int | None = None, tape_cap: int | None = None, str_cap: int | None = None,
+               chunk_groups: int = 2, doc_groups: int = 2, exact_groups: int = 2):
+    """The batched tape through the emulated kernels (index, counts and links
+    in the batch layout).  Returns (words, string buffer, out_pos (ndocs x 4),
+    flags per document, violations); outputs and workspace start full of
+    garbage."""
+    lib = load()
+    nd = offsets.size - 1
+    total = int(offsets[-1])
+    ent = int(n.sum())
+    cap = ent + nd if cap is None else cap
+    tcap = 2 * ent + 2 * nd if tape_cap is None else tape_cap
+    scap = total + 2 * ent + 4 if str_cap is None else str_cap
+    buf = np.frombuffer(data, dtype=np.uint8) if data else np.zeros(1, dtype=np.uint8)
+    offs = np.ascontiguousarray(offsets, dtype=np.uint64)
+    ix = np.ascontiguousarray(idx, dtype=np.uint32) if total else np.zeros(1, dtype=np.uint32)
+    mt = np.ascontiguousarray(match, dtype=np.uint32) if total else np.zeros(1, dtype=np.uint32)
+    cnt = np.ascontiguousarray(n, dtype=np.uint32)
+    words = np.full(max(1, tcap), 0xA5A5A5A5A5A5A5A5, dtype=np.uint64)
+    sbuf = np.full(max(1, scap), 0xA5, dtype=np.uint8)
+    pos = np.full(4 * nd, 0xFFFF, dtype=np.uint64)
+    err = np.full(nd, 0xABABABAB, dtype=np.uint32)
+    ws = np.full(int(lib.emu_tape_batch_ws_bytes(cap, nd)) // 4 + 64, 0x5A5A5A5A, dtype=np.uint32)
+    v = lib.emu_tape_batch_run(buf.ctypes.data, offs.ctypes.data, nd, ix.ctypes.data, cnt.ctypes.data,
+                               mt.ctypes.data, words.ctypes.data, tcap, sbuf.ctypes.data, scap, pos.ctypes.data,
+                               err.ctypes.data, ws.ctypes.data, cap, chunk_groups, doc_groups, exact_groups)
+    return words, sbuf.tobytes(), pos.reshape(nd, 4), err, int(v)
 
 
 def number(text: str, exact: bool):

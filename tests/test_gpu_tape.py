@@ -151,3 +151,187 @@ def test_tape_flags_on_corrupted_atoms():
         doc = base[:p] + ins + base[p:]
         _say(f"case: tape corrupted atom {k}")
         assert_tape_matches(doc, f"corruption {k}")
+
+
+class _Batch:
+    """A batch on the device: index, counts and links (jsidx_build_batch and
+    jsidx_scopes_batch), and the outputs of jsidx_tape_batch."""
+
+    def __init__(self, data: bytes, offs: np.ndarray, stream=None, reserve=True, tape_cap=None):
+        import torch
+        import paper_1902_08318_amd as jx
+        dev = torch.device("cuda:0")
+        self.data, self.offs = data, offs
+        total, nd = int(offs[-1]), offs.size - 1
+        self.buf = torch.frombuffer(bytearray(data), dtype=torch.uint8).to(dev)
+        self.o = torch.from_numpy(offs.astype(np.int64)).to(dev)
+        self.idx = torch.empty(max(1, total), dtype=torch.int32, device=dev)
+        self.cnt = torch.empty(nd, dtype=torch.int32, device=dev)
+        err = torch.empty(nd, dtype=torch.int32, device=dev)
+        jx.build_batch(self.buf, self.o, self.idx, self.cnt, err, stream)
+        torch.cuda.synchronize()
+        ent = int(self.cnt.to(torch.int64).sum().item())
+        jx.scopes_reserve(ent, nd, stream)
+        self.match = torch.empty(max(1, total), dtype=torch.int32, device=dev)
+        self.serr = torch.empty(nd, dtype=torch.int32, device=dev)
+        jx.scopes_batch(self.buf, self.o, self.idx, self.cnt, self.match, self.serr, stream)
+        if reserve:
+            jx.tape_reserve(ent, nd, stream)
+        self.words = torch.full((tape_cap or 2 * (ent + nd),), -1, dtype=torch.int64, device=dev)
+        self.sbuf = torch.full((total + 2 * ent + 4,), 0xA5, dtype=torch.uint8, device=dev)
+        self.pos = torch.full((4 * nd,), -1, dtype=torch.int64, device=dev)
+        self.terr = torch.full((nd,), -1, dtype=torch.int32, device=dev)
+
+    def run(self, stream=None):
+        import paper_1902_08318_amd as jx
+        jx.tape_batch(self.buf, self.o, self.idx, self.cnt, self.match, self.words, self.sbuf, self.pos, self.terr,
+                      stream)
+
+    def check(self, label: str):
+        """Every document's flags, and words and strings where the tape is
+        defined, against the oracle's tape of that document alone."""
+        import torch
+        torch.cuda.synchronize()
+        oi, on, _ = oracle.index_batch(np.frombuffer(self.data, dtype=np.uint8), self.offs)
+        assert np.array_equal(self.cnt.cpu().numpy().view(np.uint32), on), f"{label}: counts"
+        words = self.words.cpu().numpy().view(np.uint64)
+        sbuf = self.sbuf.cpu().numpy().tobytes()
+        pos = self.pos.cpu().numpy().view(np.uint64).reshape(-1, 4)
+        terr = self.terr.cpu().numpy().view(np.uint32)
+        serr = self.serr.cpu().numpy().view(np.uint32)
+        compared = 0
+        for d in range(self.offs.size - 1):
+            a, b = int(self.offs[d]), int(self.offs[d + 1])
+            doc = self.data[a:b]
+            ow, osb, of = oracle.tape(doc, oi[a:a + on[d]])
+            assert terr[d] == of, f"{label}: document {d} flags {terr[d]:#x} != {of:#x}"
+            if of == 0 and serr[d] == 0:
+                w0, nw, s0, ns = (int(x) for x in pos[d])
+                assert nw == ow.size and np.array_equal(words[w0:w0 + nw], ow), f"{label}: document {d} words"
+                assert sbuf[s0:s0 + ns] == osb, f"{label}: document {d} strings"
+                compared += 1
+        return compared
+
+
+def test_tape_batch_mixed_documents():
+    """Numbers (exact-path ones too), strings with escapes, literals, errors,
+    empty documents and documents of more than a chunk, in one batch."""
+    rng = random.Random(23)
+    singles = ["1", "-0", "0.5", '"x"', "true", "null", "[]", "{}", '{"a":[1,2,{"b":null}],"c":"\\u00e9\\ud83d\\ude00"}',
+               "[01]", "[1.]", '["\\x"]', "[tru]", "[1e309]", '["a\\u12"]', '["\\ud800"]', "[-]",
+               "[9223372036854775808]", "[-9223372036854775808, 9223372036854775807]", '"unclosed', "[1, 2", "",
+               "  ", "[2.2250738585072011e-308, 1.7976931348623157e308, 0.1, 123456789012345678901234567890]"]
+
+    def val(dp):
+        r = rng.random()
+        if dp > 5 or r < 0.45:
+            return rng.choice([1, -7, 2.5e-7, 1e300, "s\\\"q", "café", None, True, False, 12345678901234])
+        if r < 0.7:
+            return [val(dp + 1) for _ in range(rng.randrange(0, 5))]
+        return {f"k{i}": val(dp + 1) for i in range(rng.randrange(0, 5))}
+
+    docs = []
+    for k in range(4000):
+        docs.append(rng.choice(singles).encode() if k % 4 == 0 else json.dumps(val(0), ensure_ascii=k % 3 == 0).encode())
+    for p in (7, 2000, 3999):
+        docs.insert(p, json.dumps([val(0) for _ in range(3000)]).encode())
+    data = b"".join(docs)
+    offs = np.zeros(len(docs) + 1, dtype=np.uint64)
+    np.cumsum([len(x) for x in docs], out=offs[1:])
+    _say(f"case: tape batch mixed, {len(docs)} documents, {len(data)} bytes")
+    b = _Batch(data, offs)
+    b.run()
+    assert b.check("mixed") > 2500
+
+
+def test_tape_batch_full_c3():
+    """The whole C3 batch (100,000 documents, 1% corrupted)."""
+    from paper_1902_08318_amd import synth
+    data, offs, _ = synth.gen_c3(3)
+    _say(f"case: tape batch C3, {offs.size - 1} documents, {len(data)} bytes")
+    b = _Batch(data, offs)
+    b.run()
+    assert b.check("C3") > 90000
+
+
+def test_tape_batch_capacity_flag():
+    docs = [b"[1,2]", b'{"a":"b"}', b"[[[]]]"]
+    data = b"".join(docs)
+    offs = np.array([0, 5, 14, 20], dtype=np.uint64)
+    _say("case: tape batch over its output capacity")
+    b = _Batch(data, offs, tape_cap=4)
+    b.run()
+    import torch
+    torch.cuda.synchronize()
+    assert np.all(b.terr.cpu().numpy().view(np.uint32) == 0x80000000)
+
+
+def test_tape_batch_replayed_from_graph():
+    """After jsidx_tape_reserve the batched tape is captured in a HIP graph and
+    replayed on new batches (index and links rebuilt eagerly between replays,
+    same document count); every replay equals an eager call and the oracle."""
+    import torch
+    import paper_1902_08318_amd as jx
+    from paper_1902_08318_amd import synth
+    dev = torch.device("cuda:0")
+    ndocs, cap = 500, 4 << 20
+    batches = []
+    for sd in (51, 52, 53):
+        data, o, _ = synth.gen_c3(sd, ndocs=ndocs, pool=80, median=1024, hi=16384, corrupt_frac=0.05)
+        assert int(o[-1]) <= cap
+        batches.append((data, o))
+    s = torch.cuda.Stream()
+    b = _Batch.__new__(_Batch)
+    b.buf = torch.zeros(cap, dtype=torch.uint8, device=dev)
+    b.o = torch.zeros(ndocs + 1, dtype=torch.int64, device=dev)
+    b.idx = torch.zeros(cap, dtype=torch.int32, device=dev)
+    b.cnt = torch.zeros(ndocs, dtype=torch.int32, device=dev)
+    b.match = torch.zeros(cap, dtype=torch.int32, device=dev)
+    b.serr = torch.zeros(ndocs, dtype=torch.int32, device=dev)
+    b.words = torch.zeros(2 * (cap + ndocs), dtype=torch.int64, device=dev)
+    b.sbuf = torch.zeros(3 * cap + 4, dtype=torch.uint8, device=dev)
+    b.pos = torch.zeros(4 * ndocs, dtype=torch.int64, device=dev)
+    b.terr = torch.zeros(ndocs, dtype=torch.int32, device=dev)
+    err = torch.zeros(ndocs, dtype=torch.int32, device=dev)
+
+    def load(k):
+        data, o = batches[k]
+        b.data, b.offs = data, o
+        b.buf[:len(data)].copy_(torch.frombuffer(bytearray(data), dtype=torch.uint8))
+        b.o.copy_(torch.from_numpy(o.astype(np.int64)))
+        jx.build_batch(b.buf, b.o, b.idx, b.cnt, err, s)
+        jx.scopes_batch(b.buf, b.o, b.idx, b.cnt, b.match, b.serr, s)
+        b.words.fill_(-1)
+        b.terr.fill_(-1)
+        b.pos.fill_(-1)
+
+    with torch.cuda.stream(s):
+        jx.reserve(cap, s)
+        jx.scopes_reserve(cap, ndocs, s)
+        jx.tape_reserve(cap, ndocs, s)
+        load(0)
+        b.run(s)  # eager warm-up on the capture stream
+    s.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        b.run(s)
+    for r in range(4):
+        k = r % len(batches)
+        _say(f"case: tape batch graph replay {r} (batch {k})")
+        with torch.cuda.stream(s):
+            load(k)
+            b.run(s)
+        s.synchronize()
+        e_w, e_p, e_e = b.words.clone(), b.pos.clone(), b.terr.clone()
+        with torch.cuda.stream(s):
+            b.words.fill_(-1)
+            b.terr.fill_(-1)
+            b.pos.fill_(-1)
+        s.synchronize()
+        g.replay()
+        s.synchronize()
+        assert torch.equal(b.terr, e_e) and torch.equal(b.pos, e_p), f"replay {r}"
+        last = e_p.view(-1, 4)[-1]
+        tw = int(last[0].item() + last[1].item())
+        assert torch.equal(b.words[:tw], e_w[:tw]), f"replay {r}: words"
+        assert b.check(f"replay {r}") > 0

@@ -166,3 +166,74 @@ def test_long_strings_finished_by_the_wave():
     bad[11] = bad[11][:-5] + "\\q" + bad[11][-5:]    # an unknown escape
     _check(("[" + ",".join(bad) + "]").encode())
     _check(("[" + ",".join(strs[:50]) + ', "' + "y" * 300).encode())  # never closed
+
+
+def _check_batch(docs, **kw):
+    """The batched tape kernels against the oracle's tape of each document
+    alone: flags always, words and strings for documents whose tape is
+    defined (valid structure, no flag)."""
+    data = b"".join(docs)
+    offs = np.zeros(len(docs) + 1, dtype=np.uint64)
+    np.cumsum([len(x) for x in docs], out=offs[1:])
+    oi, on, _ = oracle.index_batch(np.frombuffer(data, dtype=np.uint8), offs)
+    match = np.full(max(1, int(offs[-1])), 0xFFFFFFFF, dtype=np.uint32)
+    valid = []
+    for d in range(len(docs)):
+        a = int(offs[d])
+        ix = oi[a:a + on[d]]
+        m, se = oracle.scopes(docs[d], ix)
+        match[a:a + on[d]] = m
+        valid.append(se == 0 and oracle.structure(docs[d], ix) == 0)
+    words, sbuf, pos, err, viol = emu.tape_batch(data, offs, oi, on, match, **kw)
+    assert viol == 0
+    for d in range(len(docs)):
+        a = int(offs[d])
+        ow, osb, of = oracle.tape(docs[d], oi[a:a + on[d]])
+        assert err[d] == of, (d, hex(err[d]), hex(of), docs[d][:60])
+        if of == 0 and valid[d]:
+            w0, nw, s0, ns = (int(x) for x in pos[d])
+            assert nw == ow.size, (d, nw, ow.size)
+            assert np.array_equal(words[w0:w0 + nw], ow), (d, docs[d][:60])
+            assert sbuf[s0:s0 + ns] == osb, d
+    return pos
+
+
+def test_batch_of_documents():
+    """Documents of every kind in one batch: numbers (with exact-path ones),
+    strings with escapes, literals, errors, empty documents and one larger
+    than a chunk of 4096 entries; fewer workgroups than chunks."""
+    rng = random.Random(21)
+    singles = ["1", "-0", "0.5", '"x"', "true", "null", "[]", "{}", '{"a":[1,2,{"b":null}],"c":"\\u00e9\\ud83d\\ude00"}',
+               "[01]", "[1.]", '["\\x"]', "[tru]", "[1e309]", '["a\\u12"]', '["\\ud800"]', "[-]",
+               "[9223372036854775808]", "[-9223372036854775808, 9223372036854775807]", '"unclosed', "[1, 2", "",
+               "  ", "[2.2250738585072011e-308, 1.7976931348623157e308, 0.1, 123456789012345678901234567890]"]
+
+    def val(dp):
+        r = rng.random()
+        if dp > 5 or r < 0.45:
+            return rng.choice([1, -7, 2.5e-7, 1e300, "s\\\"q", "café", None, True, False, 12345678901234])
+        if r < 0.7:
+            return [val(dp + 1) for _ in range(rng.randrange(0, 5))]
+        return {f"k{i}": val(dp + 1) for i in range(rng.randrange(0, 5))}
+
+    docs = []
+    for k in range(120):
+        if k % 4 == 0:
+            docs.append(rng.choice(singles).encode())
+        else:
+            docs.append(json.dumps(val(0), ensure_ascii=k % 3 == 0).encode())
+    docs.insert(50, json.dumps([val(0) for _ in range(1500)]).encode())
+    pos = _check_batch(docs, chunk_groups=2, doc_groups=3, exact_groups=2)
+    assert int(pos[:, 1].sum()) > 4096
+
+
+def test_batch_capacity_flag():
+    docs = [b"[1,2]", b'{"a":"b"}', b"[[[]]]"]
+    data = b"".join(docs)
+    offs = np.array([0, 5, 14, 20], dtype=np.uint64)
+    oi, on, _ = oracle.index_batch(np.frombuffer(data, dtype=np.uint8), offs)
+    match = np.full(20, 0xFFFFFFFF, dtype=np.uint32)
+    _, _, _, err, viol = emu.tape_batch(data, offs, oi, on, match, tape_cap=4)
+    assert viol == 0 and np.all(err == 0x80000000)
+    _, _, _, err, viol = emu.tape_batch(data, offs, oi, on, match, cap=int(on.sum()) - 1)
+    assert viol == 0 and np.all(err == 0x80000000)

@@ -351,6 +351,51 @@ def time_tape(jx, torch, data: bytes, steps: int) -> dict:
             "scope_flags": int(serr.item()) & 0xFFFFFFFF}
 
 
+def time_stage2_batch(jx, torch, data: bytes, offsets: np.ndarray, steps: int) -> dict:
+    """The batched scope links (jsidx_scopes_batch) and the batched tape
+    (jsidx_tape_batch) over the batch's resident index, after reserving both
+    workspaces; two events around the launches of each."""
+    dev = torch.device("cuda:0")
+    nd = offsets.size - 1
+    total = int(offsets[-1])
+    buf = torch.frombuffer(bytearray(data), dtype=torch.uint8).to(dev)
+    o = torch.from_numpy(offsets.astype(np.int64)).to(dev)
+    idx = torch.empty(total, dtype=torch.int32, device=dev)
+    cnt = torch.empty(nd, dtype=torch.int32, device=dev)
+    err = torch.empty(nd, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+    jx.build_batch(buf, o, idx, cnt, err, stream)
+    torch.cuda.synchronize()
+    ent = int(cnt.to(torch.int64).sum().item())
+    jx.scopes_reserve(ent, nd, stream)
+    jx.tape_reserve(ent, nd, stream)
+    match = torch.empty(total, dtype=torch.int32, device=dev)
+    serr = torch.empty(nd, dtype=torch.int32, device=dev)
+    words = torch.empty(2 * (ent + nd), dtype=torch.int64, device=dev)
+    sbuf = torch.empty(total + 2 * ent + 4, dtype=torch.uint8, device=dev)
+    pos = torch.empty(4 * nd, dtype=torch.int64, device=dev)
+    terr = torch.empty(nd, dtype=torch.int32, device=dev)
+    out = {"docs": nd, "entries": ent}
+    for name, call in (("scopes_batch", lambda: jx.scopes_batch(buf, o, idx, cnt, match, serr, stream)),
+                       ("tape_batch", lambda: jx.tape_batch(buf, o, idx, cnt, match, words, sbuf, pos, terr, stream))):
+        for _ in range(2):
+            call()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(steps):
+            call()
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / steps
+        out[name] = {"ms_per_call": round(ms, 4), "docs_per_s": round(nd / (ms / 1e3)),
+                     "input_GBps": round(total / (ms / 1e3) / 1e9, 1)}
+    ef = terr.cpu().numpy().view(np.uint32) | serr.cpu().numpy().view(np.uint32)
+    out["documents_flagged"] = int(np.count_nonzero(ef))
+    return out
+
+
 def cpu_batch_baseline(data: bytes, offsets: np.ndarray, budget_s: float = 6.0) -> dict:
     """The oracle over a batch: one core, then the documents partitioned into
     contiguous byte-balanced ranges over every host core (one thread each; the
@@ -625,6 +670,8 @@ def main():
                        "batched_vs_per_doc": round(r3["docs_per_s"] / r3["per_doc_launch_docs_per_s"], 1),
                        "ms_per_launch": round(r3["ms_per_launch"], 4), "launch_ms": r3["launch_ms"]}
         extra["minify"]["C3"] = time_minify(jx, torch, data, offs, max(3, args.steps // 2))
+        log("stage 2 over the C3 batch: scope links and tape, batched")
+        extra["stage2_C3_batch"] = time_stage2_batch(jx, torch, data, offs, max(3, args.steps // 4))
         if not args.no_cpu:
             log("timing the CPU oracle on C3 (1 core, then all cores)")
             extra["C3"]["cpu_oracle"] = cpu_batch_baseline(data, offs)

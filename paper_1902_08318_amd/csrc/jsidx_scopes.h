@@ -27,6 +27,7 @@
 #pragma once
 
 #include "jsidx_device.h"
+#include "jsidx_docscan.h"
 
 namespace jsidx {
 
@@ -91,7 +92,9 @@ struct ScopeArgs {
   const uint32_t* dn;       // per document: its entry count (idx holds them at idx + offsets[d])
   uint32_t ndocs;
   uint32_t cap;             // virtual entries the workspace holds
-  uint32_t* vn;             // [0] virtual entries, [1] their chunks (set by scope_batch_count)
+  uint32_t* vn;             // [0] virtual entries, [1] their chunks, [2] 1 if the batch is over
+                            // capacity (set by scope_batch_bases)
+  uint64_t* part;           // per 2048 documents: entry sum, then base
   uint32_t* vstart;         // ndocs + 1: first virtual entry of each document
   uint32_t* docid;          // per virtual entry: its document
   uint32_t* out_match;      // batch layout, like idx
@@ -127,7 +130,7 @@ inline ScopeLayout scope_layout(uint64_t n) {
 // Workspace layout of a batch of up to cap virtual entries in up to maxdocs
 // documents (byte offsets; host side).
 struct ScopeBatchLayout {
-  uint64_t vn, qcount, vstart, docid, chunk_fn, in_depth, chunk_min, lev, queue, match, kind, total;
+  uint64_t vn, qcount, part, vstart, docid, chunk_fn, in_depth, chunk_min, lev, queue, match, kind, total;
 };
 inline ScopeBatchLayout scope_batch_layout(uint64_t cap, uint64_t maxdocs) {
   const uint64_t nc = (cap + kScopeChunk - 1) / kScopeChunk;
@@ -135,6 +138,7 @@ inline ScopeBatchLayout scope_batch_layout(uint64_t cap, uint64_t maxdocs) {
   uint64_t o = 0;
   L.vn = o; o = scope_align256(o + 8);
   L.qcount = o; o = scope_align256(o + 4);
+  L.part = o; o = scope_align256(o + (docscan_groups(maxdocs) + 1) * 8);
   L.vstart = o; o = scope_align256(o + (maxdocs + 1) * 4);
   L.docid = o; o = scope_align256(o + cap * 4);
   L.chunk_fn = o; o = scope_align256(o + nc * 16);
@@ -187,7 +191,7 @@ struct ScopeCheckLds {
 JSIDX_DEV uint32_t scope_tid() { return prim::wave_id() * kScopeWave + prim::lane(); }
 
 // Entries and chunks of the launch: the arguments for one document, the
-// device for a batch (scope_batch_count wrote them).
+// device for a batch (scope_batch_bases wrote them).
 template <bool BATCH>
 JSIDX_DEV uint32_t n_of(const ScopeArgs& a) { return BATCH ? prim::ld_agent32(a.vn) : a.n; }
 template <bool BATCH>
@@ -285,8 +289,8 @@ JSIDX_DEVFN void scope_chunk_fn(const ScopeArgs& a) {
 }
 
 // 2. The depth entering each chunk (one workgroup); for one document also
-//    clears the flags and the queue for the kernels after it (a batch's
-//    scope_batch_count did).
+//    clears the flags and the queue for the kernels after it (for a batch,
+//    scope_batch_bases and scope_batch_starts did).
 template <bool BATCH>
 JSIDX_DEVFN void scope_scan(const ScopeArgs& a) {
   ScopeScanLds& g = prim::lds_object<ScopeScanLds>();
@@ -626,38 +630,34 @@ JSIDX_DEVFN void scope_check(const ScopeArgs& a) {
 }
 
 // ---- Batches ---------------------------------------------------------------
-// 0. The first virtual entry of each document (an exclusive scan of the
-//    entry counts, one workgroup), the totals, the flags cleared (an empty
-//    index is a syntax error) and the queue emptied.  A batch with more
-//    entries than the workspace holds is not linked: every document gets
-//    JSIDX_ERR_CAPACITY (0x80000000) and the kernels after this one do
-//    nothing.
+// 0. The first virtual entry of each document: the entry counts summed per
+//    2048 documents (scope_batch_sums), the sums scanned with the totals and
+//    the queue emptied (scope_batch_bases, one workgroup), then every
+//    document's start and cleared flags (scope_batch_starts; an empty index
+//    is a syntax error).  A batch with more entries than the workspace holds
+//    is not linked: every document gets JSIDX_ERR_CAPACITY (0x80000000) and
+//    the kernels after these do nothing.
 constexpr uint32_t kErrCapacity = 0x80000000u;
-JSIDX_DEVFN void scope_batch_count(const ScopeArgs& a) {
-  ScopeScanLds& g = prim::lds_object<ScopeScanLds>();
-  const uint32_t tid = scope_tid();
-  const uint32_t per = (a.ndocs + kScopeThreads - 1) / kScopeThreads;
-  const uint64_t lo = (uint64_t)tid * per;
-  const uint64_t hi = lo + per < a.ndocs ? lo + per : a.ndocs;
-  uint64_t sum = 0;
-  for (uint64_t d = lo; d < hi; d++) sum += prim::load4(reinterpret_cast<const uint8_t*>(a.dn + d));
-  // exclusive scan of the threads' sums (as depth functions x -> x + sum)
-  const DepthFn ex = group_exclusive(g, tid, DepthFn{(int64_t)sum, kNegInf});
-  uint64_t v = (uint64_t)ex.a;
-  const uint64_t total = (uint64_t)g.f[kScopeThreads - 1].a;  // the scan leaves the inclusive values in LDS
-  const bool over = total > (uint64_t)a.cap;
-  for (uint64_t d = lo; d < hi; d++) {
-    const uint32_t nd = prim::load4(reinterpret_cast<const uint8_t*>(a.dn + d));
-    if (!over) prim::st_out(a.vstart + d, (uint32_t)v);
-    prim::st_out(a.err + d, over ? kErrCapacity : (nd ? 0u : kErrSyntax));
-    v += nd;
-  }
-  if (tid == kScopeThreads - 1) {
+JSIDX_DEVFN void scope_batch_sums(const ScopeArgs& a) { docscan_sums(a.dn, a.ndocs, false, a.part); }
+
+JSIDX_DEVFN void scope_batch_bases(const ScopeArgs& a) {
+  const uint64_t total = docscan_bases((uint32_t)docscan_groups(a.ndocs), a.part);
+  if (scope_tid() == 0) {
+    const bool over = total > (uint64_t)a.cap;
     if (!over) prim::st_out(a.vstart + a.ndocs, (uint32_t)total);
     prim::st_out(a.vn, over ? 0u : (uint32_t)total);
     prim::st_out(a.vn + 1, over ? 0u : (uint32_t)((total + kScopeChunk - 1) / kScopeChunk));
+    prim::st_out(a.vn + 2, over ? 1u : 0u);
     prim::st_out(a.qcount, 0u);
   }
+}
+
+JSIDX_DEVFN void scope_batch_starts(const ScopeArgs& a) {
+  const bool over = prim::ld_agent32(a.vn + 2) != 0u;
+  docscan_starts(a.dn, a.ndocs, false, a.part, [&](uint64_t d, uint64_t start, uint32_t cnt) {
+    if (!over) prim::st_out(a.vstart + d, (uint32_t)start);
+    prim::st_out(a.err + d, over ? kErrCapacity : (cnt ? 0u : kErrSyntax));
+  });
 }
 
 // 1b. Each document's entries into the virtual sequence: kind bytes (with

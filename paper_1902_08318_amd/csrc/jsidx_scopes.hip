@@ -24,7 +24,9 @@ template <bool B>
 __global__ void __launch_bounds__(kScopeThreads) scope_far_kernel(ScopeArgs a) { scope_far<B>(a); }
 template <bool B>
 __global__ void __launch_bounds__(kScopeThreads) scope_check_kernel(ScopeArgs a) { scope_check<B>(a); }
-__global__ void __launch_bounds__(kScopeThreads) scope_batch_count_kernel(ScopeArgs a) { scope_batch_count(a); }
+__global__ void __launch_bounds__(kScopeThreads) scope_batch_sums_kernel(ScopeArgs a) { scope_batch_sums(a); }
+__global__ void __launch_bounds__(kScopeThreads) scope_batch_bases_kernel(ScopeArgs a) { scope_batch_bases(a); }
+__global__ void __launch_bounds__(kScopeThreads) scope_batch_starts_kernel(ScopeArgs a) { scope_batch_starts(a); }
 __global__ void __launch_bounds__(kScopeThreads) scope_batch_compact_kernel(ScopeArgs a) { scope_batch_compact(a); }
 __global__ void __launch_bounds__(kScopeThreads) scope_batch_finish_kernel(ScopeArgs a) { scope_batch_finish(a); }
 
@@ -190,6 +192,7 @@ extern "C" int jsidx_scopes_batch(const uint8_t* bufs, const uint64_t* offsets, 
   a.ndocs = ndocs;
   a.cap = (uint32_t)cap;
   a.vn = reinterpret_cast<uint32_t*>(m + L.vn);
+  a.part = reinterpret_cast<uint64_t*>(m + L.part);
   a.vstart = reinterpret_cast<uint32_t*>(m + L.vstart);
   a.docid = reinterpret_cast<uint32_t*>(m + L.docid);
   a.out_match = out_match;
@@ -201,7 +204,10 @@ extern "C" int jsidx_scopes_batch(const uint8_t* bufs, const uint64_t* offsets, 
   const uint32_t doc_groups = (uint32_t)(dg < 2048 ? dg : 2048);
   const dim3 block(kScopeThreads);
   (void)hipGetLastError();
-  hipLaunchKernelGGL(scope_batch_count_kernel, dim3(1), block, 0, stream, a);
+  const dim3 sgrid((uint32_t)docscan_groups(ndocs));
+  hipLaunchKernelGGL(scope_batch_sums_kernel, sgrid, block, 0, stream, a);
+  hipLaunchKernelGGL(scope_batch_bases_kernel, dim3(1), block, 0, stream, a);
+  hipLaunchKernelGGL(scope_batch_starts_kernel, sgrid, block, 0, stream, a);
   hipLaunchKernelGGL(scope_batch_compact_kernel, dim3(doc_groups), block, 0, stream, a);
   hipLaunchKernelGGL(scope_chunk_fn_kernel<true>, dim3(chunk_groups), block, 0, stream, a);
   hipLaunchKernelGGL(scope_scan_kernel<true>, dim3(1), block, 0, stream, a);

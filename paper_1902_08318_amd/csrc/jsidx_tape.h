@@ -26,6 +26,7 @@
 #pragma once
 
 #include "jsidx_device.h"
+#include "jsidx_docscan.h"
 
 #ifndef JSIDX_CONSTANT
 #define JSIDX_CONSTANT __constant__
@@ -77,7 +78,9 @@ struct TapeArgs {
   uint32_t ndocs;
   uint32_t cap;             // virtual entries the workspace holds
   uint64_t tape_cap, str_cap;  // words and bytes the outputs hold
-  uint32_t* vn;             // [0] virtual entries, [1] their chunks, [2] 1 if the outputs hold the batch
+  uint32_t* vn;             // [0] virtual entries, [1] their chunks, [2] 1 if the outputs hold the
+                            // batch, [3] 1 if the batch is over the workspace's capacity
+  uint64_t* part;           // per 2048 documents: entry sum, then base
   uint64_t* tot;            // total words and string bytes
   uint32_t* vstart;         // ndocs + 1: first virtual entry of each document
   uint32_t* docid;          // per virtual entry
@@ -92,8 +95,8 @@ constexpr uint32_t kTapeErrCapacity = 0x80000000u;
 
 // Workspace layout of a batch (byte offsets; host side).
 struct TapeBatchLayout {
-  uint64_t vn, tot, qcount, vstart, docid, vpos, vflag, dbase, chunk_sum, sbytes, kb, toff, queue, squeue, nqueue,
-      total;
+  uint64_t vn, tot, qcount, part, vstart, docid, vpos, vflag, dbase, chunk_sum, sbytes, kb, toff, queue, squeue,
+      nqueue, total;
 };
 inline TapeBatchLayout tape_batch_layout(uint64_t cap, uint64_t maxdocs) {
   const uint64_t nc = (cap + kTapeChunk - 1) / kTapeChunk;
@@ -103,6 +106,7 @@ inline TapeBatchLayout tape_batch_layout(uint64_t cap, uint64_t maxdocs) {
   L.vn = o; o = al(o + 16);
   L.tot = o; o = al(o + 16);
   L.qcount = o; o = al(o + 16);
+  L.part = o; o = al(o + (docscan_groups(maxdocs) + 1) * 8);
   L.vstart = o; o = al(o + (maxdocs + 1) * 4);
   L.docid = o; o = al(o + cap * 4);
   L.vpos = o; o = al(o + cap * 8);
@@ -941,7 +945,7 @@ JSIDX_DEVFN void tape_scan(const TapeArgs& a) {
     sex += cs;
   }
   if (BATCH) {
-    if (nchunks == 0) return;  // tape_batch_count flagged the batch
+    if (nchunks == 0) return;  // tape_batch_bases flagged the batch
     const bool fits = wall <= a.tape_cap && sall <= a.str_cap;
     if (!fits)
       for (uint32_t d = tid; d < a.ndocs; d += (uint32_t)kTapeThreads) prim::st_out(a.err + d, kTapeErrCapacity);
@@ -1295,40 +1299,35 @@ JSIDX_DEVFN void tape_exact(const TapeArgs& a) {
 
 // ---- Batches ---------------------------------------------------------------
 // 0. The first virtual entry of each document (an empty document counts one
-//    placeholder entry), the totals, the flags cleared and the queues
-//    emptied (one workgroup).  A batch with more virtual entries than the
-//    workspace holds, or whose bytes reach 2^32 - 2^16, is not written: every
-//    document gets JSIDX_ERR_CAPACITY and the kernels after this one do
+//    placeholder entry): sums per 2048 documents (tape_batch_sums), the sums
+//    scanned with the totals and the queues emptied (tape_batch_bases, one
+//    workgroup), every document's start and cleared flags
+//    (tape_batch_starts).  A batch with more virtual entries than the
+//    workspace holds, or whose bytes reach 2^32 - 2^16, is not written:
+//    every document gets JSIDX_ERR_CAPACITY and the kernels after these do
 //    nothing.
-JSIDX_DEVFN void tape_batch_count(const TapeArgs& a) {
-  TapeScanLds& g = prim::lds_object<TapeScanLds>();
-  const uint32_t tid = tape_tid();
-  const uint32_t per = (a.ndocs + kTapeThreads - 1) / kTapeThreads;
-  const uint64_t lo = (uint64_t)tid * per;
-  const uint64_t hi = lo + per < a.ndocs ? lo + per : a.ndocs;
-  uint64_t sum = 0;
-  for (uint64_t d = lo; d < hi; d++) {
-    const uint32_t nd = prim::load4(reinterpret_cast<const uint8_t*>(a.dn + d));
-    sum += nd ? nd : 1u;
-  }
-  uint64_t ex, sx, total, st;
-  group_scan2(g, tid, sum, 0, &ex, &sx, &total, &st);
-  const uint64_t span = prim::load8(a.offsets + a.ndocs) - prim::load8(a.offsets);
-  const bool over = total > (uint64_t)a.cap || span >= (1ull << 32) - (1ull << 16);
-  uint64_t v = ex;
-  for (uint64_t d = lo; d < hi; d++) {
-    const uint32_t nd = prim::load4(reinterpret_cast<const uint8_t*>(a.dn + d));
-    if (!over) prim::st_out(a.vstart + d, (uint32_t)v);
-    prim::st_out(a.err + d, over ? kTapeErrCapacity : 0u);
-    v += nd ? nd : 1u;
-  }
-  if (tid == kTapeThreads - 1) {
+JSIDX_DEVFN void tape_batch_sums(const TapeArgs& a) { docscan_sums(a.dn, a.ndocs, true, a.part); }
+
+JSIDX_DEVFN void tape_batch_bases(const TapeArgs& a) {
+  const uint64_t total = docscan_bases((uint32_t)docscan_groups(a.ndocs), a.part);
+  if (tape_tid() == 0) {
+    const uint64_t span = prim::load8(a.offsets + a.ndocs) - prim::load8(a.offsets);
+    const bool over = total > (uint64_t)a.cap || span >= (1ull << 32) - (1ull << 16);
     if (!over) prim::st_out(a.vstart + a.ndocs, (uint32_t)total);
     prim::st_out(a.vn, over ? 0u : (uint32_t)total);
     prim::st_out(a.vn + 1, over ? 0u : (uint32_t)((total + kTapeChunk - 1) / kTapeChunk));
     prim::st_out(a.vn + 2, 0u);
+    prim::st_out(a.vn + 3, over ? 1u : 0u);
     for (int q = 0; q < 3; q++) prim::st_out(a.qcount + q, 0u);
   }
+}
+
+JSIDX_DEVFN void tape_batch_starts(const TapeArgs& a) {
+  const bool over = prim::ld_agent32(a.vn + 3) != 0u;
+  docscan_starts(a.dn, a.ndocs, true, a.part, [&](uint64_t d, uint64_t start, uint32_t) {
+    if (!over) prim::st_out(a.vstart + d, (uint32_t)start);
+    prim::st_out(a.err + d, over ? kTapeErrCapacity : 0u);
+  });
 }
 
 // 1b. Each document's entries into the virtual sequence: absolute positions,

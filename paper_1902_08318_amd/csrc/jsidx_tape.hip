@@ -25,7 +25,9 @@ template <bool B>
 __global__ void __launch_bounds__(kTapeThreads) tape_numbers_kernel(TapeArgs a) { tape_numbers<B>(a); }
 template <bool B>
 __global__ void __launch_bounds__(kExactThreads) tape_exact_kernel(TapeArgs a) { tape_exact<B>(a); }
-__global__ void __launch_bounds__(kTapeThreads) tape_batch_count_kernel(TapeArgs a) { tape_batch_count(a); }
+__global__ void __launch_bounds__(kTapeThreads) tape_batch_sums_kernel(TapeArgs a) { tape_batch_sums(a); }
+__global__ void __launch_bounds__(kTapeThreads) tape_batch_bases_kernel(TapeArgs a) { tape_batch_bases(a); }
+__global__ void __launch_bounds__(kTapeThreads) tape_batch_starts_kernel(TapeArgs a) { tape_batch_starts(a); }
 __global__ void __launch_bounds__(kTapeThreads) tape_batch_compact_kernel(TapeArgs a) { tape_batch_compact(a); }
 __global__ void __launch_bounds__(kTapeThreads) tape_batch_docs_kernel(TapeArgs a) { tape_batch_docs(a); }
 
@@ -209,6 +211,7 @@ extern "C" int jsidx_tape_batch(const uint8_t* bufs, const uint64_t* offsets, ui
   a.str_cap = str_cap;
   a.vn = reinterpret_cast<uint32_t*>(m + L.vn);
   a.tot = reinterpret_cast<uint64_t*>(m + L.tot);
+  a.part = reinterpret_cast<uint64_t*>(m + L.part);
   a.vstart = reinterpret_cast<uint32_t*>(m + L.vstart);
   a.docid = reinterpret_cast<uint32_t*>(m + L.docid);
   a.vpos = reinterpret_cast<uint64_t*>(m + L.vpos);
@@ -225,7 +228,10 @@ extern "C" int jsidx_tape_batch(const uint8_t* bufs, const uint64_t* offsets, ui
   const dim3 qgrid((uint32_t)(qgroups < kQueueGroups ? qgroups : kQueueGroups));
   const dim3 block(kTapeThreads);
   (void)hipGetLastError();
-  hipLaunchKernelGGL(tape_batch_count_kernel, dim3(1), block, 0, stream, a);
+  const dim3 sgrid((uint32_t)docscan_groups(ndocs));
+  hipLaunchKernelGGL(tape_batch_sums_kernel, sgrid, block, 0, stream, a);
+  hipLaunchKernelGGL(tape_batch_bases_kernel, dim3(1), block, 0, stream, a);
+  hipLaunchKernelGGL(tape_batch_starts_kernel, sgrid, block, 0, stream, a);
   hipLaunchKernelGGL(tape_batch_compact_kernel, dim3(doc_groups), block, 0, stream, a);
   hipLaunchKernelGGL(tape_count_kernel<true>, dim3(chunk_groups), block, 0, stream, a);
   hipLaunchKernelGGL(tape_scan_kernel<true>, dim3(1), block, 0, stream, a);

@@ -208,6 +208,7 @@ long emu_scopes_batch_run(const uint8_t* buf, const uint64_t* offsets, uint32_t 
   a.ndocs = ndocs;
   a.cap = (uint32_t)cap;
   a.vn = reinterpret_cast<uint32_t*>(m + L.vn);
+  a.part = reinterpret_cast<uint64_t*>(m + L.part);
   a.vstart = reinterpret_cast<uint32_t*>(m + L.vstart);
   a.docid = reinterpret_cast<uint32_t*>(m + L.docid);
   a.out_match = match;
@@ -230,7 +231,10 @@ long emu_scopes_batch_run(const uint8_t* buf, const uint64_t* offsets, uint32_t 
     for (auto& x : th) x.join();
     for (auto* g : groups) delete g;
   };
-  phase(1, scope_batch_count);
+  const int sg = (int)docscan_groups(ndocs);
+  phase(sg, scope_batch_sums);
+  phase(1, scope_batch_bases);
+  phase(sg, scope_batch_starts);
   phase(doc_groups, scope_batch_compact);
   phase(chunk_groups, scope_chunk_fn<true>);
   phase(1, scope_scan<true>);
@@ -360,6 +364,7 @@ long emu_tape_batch_run(const uint8_t* buf, const uint64_t* offsets, uint32_t nd
   a.str_cap = str_cap;
   a.vn = reinterpret_cast<uint32_t*>(m + L.vn);
   a.tot = reinterpret_cast<uint64_t*>(m + L.tot);
+  a.part = reinterpret_cast<uint64_t*>(m + L.part);
   a.vstart = reinterpret_cast<uint32_t*>(m + L.vstart);
   a.docid = reinterpret_cast<uint32_t*>(m + L.docid);
   a.vpos = reinterpret_cast<uint64_t*>(m + L.vpos);
@@ -385,7 +390,10 @@ long emu_tape_batch_run(const uint8_t* buf, const uint64_t* offsets, uint32_t nd
     for (auto& x : th) x.join();
     for (auto* g : groups) delete g;
   };
-  phase(1, kTapeThreads, tape_batch_count);
+  const int sg = (int)docscan_groups(ndocs);
+  phase(sg, kTapeThreads, tape_batch_sums);
+  phase(1, kTapeThreads, tape_batch_bases);
+  phase(sg, kTapeThreads, tape_batch_starts);
   phase(doc_groups, kTapeThreads, tape_batch_compact);
   phase(chunk_groups, kTapeThreads, tape_count<true>);
   phase(1, kTapeThreads, tape_scan<true>);

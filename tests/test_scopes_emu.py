@@ -154,3 +154,12 @@ def test_batch_capacity_flag():
     oi, on, _, _ = _oracle_batch(data, offs)
     m, e, v = emu.scopes_batch(data, offs, oi, on, cap=int(on.sum()) - 1)
     assert v == 0 and np.all(e == 0x80000000)
+
+
+def test_batch_of_many_documents():
+    """More documents than one workgroup of the per-document scan takes (2048):
+    the scan's group sums and bases, with empty documents among them."""
+    rng = random.Random(12)
+    pool = [b"", b"1", b"[]", b"[1,[2]]", b'{"a":{}}', b"]", b"[[", b'"x"']
+    docs = [rng.choice(pool) for _ in range(5000)]
+    _check_batch(docs, chunk_groups=2, doc_groups=4, far_groups=2)

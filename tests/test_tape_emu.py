@@ -237,3 +237,11 @@ def test_batch_capacity_flag():
     assert viol == 0 and np.all(err == 0x80000000)
     _, _, _, err, viol = emu.tape_batch(data, offs, oi, on, match, cap=int(on.sum()) - 1)
     assert viol == 0 and np.all(err == 0x80000000)
+
+
+def test_batch_of_many_documents():
+    """More documents than one workgroup of the per-document scan takes (2048),
+    empty ones (a placeholder entry each) among them."""
+    rng = random.Random(22)
+    pool = [b"", b"1", b"[]", b"[1,[2.5]]", b'{"a":{"b":"c\\n"}}', b"tru", b'"x"', b"  ", b"[1e400]"]
+    _check_batch([rng.choice(pool) for _ in range(5000)], chunk_groups=2, doc_groups=4, exact_groups=2)

@@ -143,8 +143,13 @@ JSIDX_DEV void st_out4(uint32_t* p, uint4 v) {
   const u32x4_a4 w = {v.x, v.y, v.z, v.w};
   *reinterpret_cast<u32x4_a4*>(p) = w;
 }
-// 16 bytes from a 16-byte aligned LDS address.
+// 16 bytes from / to a 16-byte aligned LDS address.
 JSIDX_DEV uint4 ld_lds128(const uint32_t* p) { return *reinterpret_cast<const uint4*>(p); }
+JSIDX_DEV void st_lds128(uint32_t* p, uint4 v) { *reinterpret_cast<uint4*>(p) = v; }
+// Single LDS bytes and words.
+JSIDX_DEV uint32_t lds_ld1(const uint8_t* p) { return *p; }
+JSIDX_DEV void lds_st1(uint8_t* p, uint32_t v) { *p = (uint8_t)v; }
+JSIDX_DEV void lds_st4(uint32_t* p, uint32_t v) { *p = v; }
 JSIDX_DEV void st_byte(uint8_t* p, uint32_t v) { *p = (uint8_t)v; }
 JSIDX_DEV void st_pair(uint2* p, uint32_t x, uint32_t y) { *p = make_uint2(x, y); }
 JSIDX_DEV uint2 ld_pair(const uint2* p) { return *p; }

@@ -6,18 +6,17 @@
 // every entry is handled by its own thread:
 //   1. tape_count: each entry's first byte and the buffer bytes of each string
 //      (decoded, not written) go to the workspace; the words (0 for ':' and
-//      ',', 2 for a number, else 1) and bytes are summed per chunk of 4096
+//      ',', 2 for a number, else 1) and bytes are summed per chunk of 2048
 //      entries;
 //   2. tape_scan: one workgroup turns the chunk sums into bases and writes the
 //      root words, the sizes, and clears the flags;
 //   3. tape_offsets: each entry's tape index (a scan inside the chunk);
 //   4. tape_write: the words of brackets (with the tape index of their
-//      partner, from the scope links) and strings; strings, and numbers with
-//      literals, are queued densely for
-//   5. tape_strings: strings decoded into the buffer, and
-//   6. tape_numbers: literals checked, numbers converted; a double whose
+//      partner, from the scope links) and strings; strings decoded into the
+//      buffer; numbers with literals queued densely for
+//   5. tape_numbers: literals checked, numbers converted; a double whose
 //      rounding the fast conversion cannot decide is queued again for
-//   7. tape_exact: the exact big-integer conversion.
+//   6. tape_exact: the exact big-integer conversion.
 // Splitting by kind keeps the lanes of a wave on the same path.
 // Consecutive threads take consecutive entries (coalesced); the scans inside
 // a chunk run over the chunk staged in LDS.
@@ -39,8 +38,11 @@ constexpr uint32_t kErrNumber = 0x100u;
 constexpr uint32_t kErrString = 0x200u;
 constexpr uint32_t kErrLiteral = 0x400u;
 constexpr int kTapeThreads = 256;
-constexpr int kTapePer = 16;
+constexpr int kTapePer = 8;
 constexpr int kTapeChunk = kTapeThreads * kTapePer;
+constexpr int kTapeSuper = 4;  // groups of 64 entries in a run (below)
+static_assert(kTapePer % kTapeSuper == 0, "a wave's entries are whole runs");
+constexpr uint32_t kRunMax = 64u * kTapeSuper;  // entries of a run
 constexpr uint32_t kTapeUnlinked = 0xFFFFFFFFu;
 constexpr int kExactGroups = 64;      // workgroups of tape_exact
 constexpr int kQueueGroups = 8192;    // at most this many workgroups for the string and number queues
@@ -64,10 +66,10 @@ struct TapeArgs {
   uint64_t* chunk_sum;  // 2 per chunk: words, buffer bytes; then their bases
   uint32_t* sbytes;     // per entry: buffer bytes of a string, else 0
   uint8_t* kb;          // per entry: its first byte
+  uint8_t* runbad;      // per run of kRunMax entries: 1 if its strings take the per-string path
   uint32_t* toff;       // per entry: tape index of its first word
-  uint32_t* qcount;     // queue lengths: [0] exact conversions, [1] strings, [2] numbers
+  uint32_t* qcount;     // queue lengths: [0] exact conversions, [1] numbers
   uint32_t* queue;      // entries for the exact conversion
-  uint64_t* squeue;     // strings: entry and buffer offset
   uint32_t* nqueue;     // numbers: entry
   // batches (jsidx_tape_batch): the documents' entries laid end to end as
   // "virtual" entries (an empty document gets one placeholder entry, so that
@@ -95,7 +97,7 @@ constexpr uint32_t kTapeErrCapacity = 0x80000000u;
 
 // Workspace layout of a batch (byte offsets; host side).
 struct TapeBatchLayout {
-  uint64_t vn, tot, qcount, part, vstart, docid, vpos, vflag, dbase, chunk_sum, sbytes, kb, toff, queue, squeue,
+  uint64_t vn, tot, qcount, part, vstart, docid, vpos, vflag, dbase, chunk_sum, sbytes, kb, runbad, toff, queue,
       nqueue, total;
 };
 inline TapeBatchLayout tape_batch_layout(uint64_t cap, uint64_t maxdocs) {
@@ -115,16 +117,16 @@ inline TapeBatchLayout tape_batch_layout(uint64_t cap, uint64_t maxdocs) {
   L.chunk_sum = o; o = al(o + nc * 16);
   L.sbytes = o; o = al(o + cap * 4);
   L.kb = o; o = al(o + cap);
+  L.runbad = o; o = al(o + cap / kRunMax + 1);
   L.toff = o; o = al(o + cap * 4);
   L.queue = o; o = al(o + cap * 4);
-  L.squeue = o; o = al(o + cap * 16);
   L.nqueue = o; o = al(o + cap * 4);
   L.total = o;
   return L;
 }
 
 struct TapeLayout {
-  uint64_t chunk_sum, sbytes, kb, toff, qcount, queue, squeue, nqueue, total;
+  uint64_t chunk_sum, sbytes, kb, runbad, toff, qcount, queue, nqueue, total;
 };
 inline uint64_t tape_align256(uint64_t x) { return (x + 255) & ~(uint64_t)255; }
 inline TapeLayout tape_layout(uint64_t n) {
@@ -134,10 +136,10 @@ inline TapeLayout tape_layout(uint64_t n) {
   L.chunk_sum = o; o = tape_align256(o + nc * 16);
   L.sbytes = o; o = tape_align256(o + n * 4);
   L.kb = o; o = tape_align256(o + n);
+  L.runbad = o; o = tape_align256(o + n / kRunMax + 1);
   L.toff = o; o = tape_align256(o + n * 4);
   L.qcount = o; o = tape_align256(o + 16);
   L.queue = o; o = tape_align256(o + n * 4);
-  L.squeue = o; o = tape_align256(o + n * 16);
   L.nqueue = o; o = tape_align256(o + n * 4);
   L.total = o;
   return L;
@@ -152,7 +154,19 @@ JSIDX_DEV uint32_t entry_byte(const TapeArgs& a, uint32_t i) {
   return byte_at(a, prim::load4(reinterpret_cast<const uint8_t*>(a.idx + i)));
 }
 
-JSIDX_DEV bool is_lit_start(uint32_t b) { return b == 't' || b == 'f' || b == 'n'; }
+// Sets of first bytes as two 64-bit masks (bytes 0..63, 64..127), tested
+// without branches: chains of comparisons become branches and mask
+// arithmetic in divergent code.
+constexpr uint64_t set_lo(uint32_t c) { return c < 64 ? 1ull << c : 0ull; }
+constexpr uint64_t set_hi(uint32_t c) { return c >= 64 && c < 128 ? 1ull << (c - 64) : 0ull; }
+JSIDX_DEV bool in_set(uint32_t b, uint64_t lo, uint64_t hi) {
+  const uint64_t m = (b & 64u) ? hi : lo;
+  return ((uint32_t)(m >> (b & 63u)) & (b < 128u ? 1u : 0u)) != 0u;
+}
+constexpr uint64_t kLitHi = set_hi('t') | set_hi('f') | set_hi('n');
+constexpr uint64_t kBracketHi = set_hi('{') | set_hi('}') | set_hi('[') | set_hi(']');
+constexpr uint64_t kNoWordLo = set_lo(':') | set_lo(',');
+JSIDX_DEV bool is_lit_start(uint32_t b) { return in_set(b, 0u, kLitHi); }
 
 // The 32 bytes from the aligned word holding byte p on, loaded together into
 // registers (eight word loads in flight), so that a short atom costs one
@@ -195,9 +209,10 @@ JSIDX_DEV uint32_t win_byte(const Window& w, uint64_t p) {
 
 // Tape words of an entry by its first byte.
 JSIDX_DEV uint32_t words_of(uint32_t b) {
-  if (b == ':' || b == ',') return 0;
-  if (b == '{' || b == '}' || b == '[' || b == ']' || b == '"' || is_lit_start(b)) return 1;
-  return 2;  // a number (or an invalid atom, which is a number error)
+  // none for ':' and ',', one for brackets, strings and literals, else two
+  // (a number, or an invalid atom, which is a number error)
+  const bool none = in_set(b, kNoWordLo, 0u), one = in_set(b, set_lo('"'), kBracketHi | kLitHi);
+  return 2u - (none ? 2u : 0u) - (one ? 1u : 0u);
 }
 
 // An atom ends at white space, a structural character or the document's end.
@@ -209,6 +224,127 @@ JSIDX_DEV bool ends_atom(const Window& w, uint64_t p) {
 }
 
 // ---- Strings (Sec. 3.2.2) ---------------------------------------------------
+// The string passes take the entries 64 at a time, one per lane of a wave.
+// The wave first copies the document bytes of its group (from the group's
+// first entry, or first string, up to the entry after the group: every
+// string of the group lies there) into LDS with 16-byte loads, consecutive
+// lanes on consecutive blocks, so that the document is read once and
+// coalesced; each lane then scans its own string there, 16 bytes per step.
+// Bytes past the copy (a group longer than kStrIn bytes) are read from the
+// document itself.  The writing pass also stages the group's output (each
+// string's length word and bytes, contiguous in the buffer) in LDS and
+// stores it with 16-byte stores; a string whose output does not fit there
+// is written to the buffer directly.
+constexpr uint32_t kStrIn = 2048;   // staged document bytes per wave
+constexpr uint32_t kStrOut = 2048;  // staged buffer bytes per wave
+struct StrLds {
+  uint32_t in[kStrIn / 4];
+  uint32_t out[kStrOut / 4];
+};
+
+// Where a lane reads its string: the document (its bytes below len belong to
+// the entry's document; 16-byte loads start at or after blo) and the wave's
+// copy of positions [lo, hi) (lo 16-byte aligned as an address; hi == lo:
+// nothing staged).
+struct StrSrc {
+  const uint8_t* buf;
+  uint64_t len;
+  uint64_t blo;
+  uint64_t lo, hi;
+};
+
+// Word k (0..3) of four, by mask arithmetic (a runtime index, or a chain of
+// selects the compiler may turn into one, would put the words in private
+// memory).
+JSIDX_DEV uint32_t word_in(const uint32_t x[4], uint32_t k) {
+  return (x[0] & (0u - (uint32_t)(k == 0))) | (x[1] & (0u - (uint32_t)(k == 1))) |
+         (x[2] & (0u - (uint32_t)(k == 2))) | (x[3] & (0u - (uint32_t)(k == 3)));
+}
+
+// Byte p (p < len).
+JSIDX_DEV uint32_t src_byte(const StrSrc& s, const StrLds& L, uint64_t p) {
+  if (p >= s.lo && p < s.hi) return prim::lds_ld1(reinterpret_cast<const uint8_t*>(L.in) + (p - s.lo));
+  return prim::load1(s.buf + p);
+}
+
+// The 16-byte aligned block holding byte p, if all of it lies inside the
+// entry's document: its words in x, its first position returned (else ~0).
+JSIDX_DEV uint64_t src_block(const StrSrc& s, const StrLds& L, uint64_t p, uint32_t x[4]) {
+  const uint64_t off = reinterpret_cast<uintptr_t>(s.buf + p) & 15u;
+  if (p < s.blo + off || p - off + 16 > s.len) return ~0ull;
+  const uint64_t pb = p - off;
+  const uint4 v = pb >= s.lo && pb + 16 <= s.hi ? prim::ld_lds128(L.in + (pb - s.lo) / 4) : prim::load16(s.buf + pb);
+  x[0] = v.x;
+  x[1] = v.y;
+  x[2] = v.z;
+  x[3] = v.w;
+  return pb;
+}
+
+// Copies positions [lo, hi) of buf into L.in (whole wave; 16-byte loads
+// where the block lies inside [blo, bhi), bytes at the buffer's ends) and
+// returns the staged end (hi rounded up to the block, within bhi).
+JSIDX_DEV uint64_t stage_in(StrLds& L, const uint8_t* buf, uint64_t lo, uint64_t hi, uint64_t bhi) {
+  const uint32_t nblk = (uint32_t)((hi - lo + 15) / 16);
+  for (uint32_t m = prim::lane(); m < nblk; m += 64u) {
+    const uint64_t pb = lo + 16ull * m;
+    uint4 v;
+    if (pb + 16 <= bhi) {
+      v = prim::load16(buf + pb);
+    } else {
+      uint32_t w[4] = {0u, 0u, 0u, 0u};
+      for (uint32_t b = 0; b < 16u; b++)
+        if (pb + b < bhi) w[b / 4] |= prim::load1(buf + pb + b) << (8 * (b % 4));
+      v = uint4{w[0], w[1], w[2], w[3]};
+    }
+    prim::st_lds128(L.in + 4 * m, v);
+  }
+  const uint64_t end = lo + 16ull * nblk;
+  return end < bhi ? end : bhi;
+}
+
+// Stages the bytes of a group that start at p0 (its first entry or string)
+// and end before p1 (the entry after the group, or the buffer's end), at most
+// kStrIn of them, for the lanes' reads (whole wave; the range is the same
+// for every lane).  [blo, bhi) is the readable buffer.
+JSIDX_DEV StrSrc stage_group(StrLds& L, const uint8_t* buf, uint64_t p0, uint64_t p1, uint64_t blo, uint64_t bhi) {
+  StrSrc s{buf, 0, blo, 0, 0};
+  const uint64_t off = reinterpret_cast<uintptr_t>(buf + p0) & 15u;
+  uint64_t lo = p0 - off;
+  if (p0 < blo + off) lo = p0 + ((16u - off) & 15u);  // the buffer's first bytes stay in memory
+  uint64_t hi = p1 > lo ? p1 : lo;
+  if (hi > lo + kStrIn) hi = lo + kStrIn;
+  if (hi > bhi) hi = bhi > lo ? bhi : lo;
+  prim::wave_sync();  // the previous group's reads are done
+  s.lo = lo;
+  s.hi = stage_in(L, buf, lo, hi, bhi);
+  prim::wave_sync();
+  return s;
+}
+
+// Where a lane writes its string's bytes: the buffer at g, or (staged) the
+// wave's output copy at L.out byte li, which has g's alignment.
+struct StrDst {
+  uint8_t* g;
+  uint32_t li;
+  bool staged;
+};
+JSIDX_DEV void dst_byte(const StrDst& o, StrLds& L, uint32_t k, uint32_t v) {
+  if (!o.staged) {
+    prim::st_byte(o.g + k, v);
+  } else if (o.li + k < kStrOut) {  // always (the count pass sized the string)
+    prim::lds_st1(reinterpret_cast<uint8_t*>(L.out) + o.li + k, v);
+  }
+}
+// A word to a 4-byte aligned destination.
+JSIDX_DEV void dst_word(const StrDst& o, StrLds& L, uint32_t k, uint32_t v) {
+  if (!o.staged) {
+    prim::st_out(reinterpret_cast<uint32_t*>(o.g + k), v);
+  } else if (o.li + k + 4 <= kStrOut) {
+    prim::lds_st4(L.out + (o.li + k) / 4, v);
+  }
+}
+
 JSIDX_DEV int32_t hex_digit(uint32_t c) {
   if (c >= '0' && c <= '9') return (int32_t)(c - '0');
   if (c >= 'a' && c <= 'f') return (int32_t)(c - 'a' + 10);
@@ -217,21 +353,15 @@ JSIDX_DEV int32_t hex_digit(uint32_t c) {
 }
 
 // Four hex digits at p, or -1.
-JSIDX_DEV int32_t hex_quad(const TapeArgs& a, uint64_t p) {
-  if (p + 4 > a.len) return -1;
+JSIDX_DEV int32_t hex_quad(const StrSrc& s, const StrLds& L, uint64_t p) {
+  if (p + 4 > s.len) return -1;
   int32_t v = 0;
   for (int k = 0; k < 4; k++) {
-    const int32_t h = hex_digit(prim::load1(a.buf + p + k));
+    const int32_t h = hex_digit(src_byte(s, L, p + k));
     if (h < 0) return -1;
     v = v * 16 + h;
   }
   return v;
-}
-
-template <bool WRITE>
-JSIDX_DEV void emit(uint8_t* out, uint32_t* k, uint32_t v) {
-  if constexpr (WRITE) prim::st_byte(out + *k, v);
-  ++*k;
 }
 
 constexpr uint32_t kDeferred = 0x80000000u;  // string_run: the budget ran out
@@ -239,17 +369,17 @@ constexpr uint32_t kDeferred = 0x80000000u;  // string_run: the budget ran out
 // The escape whose backslash is at *p: its bytes (\uXXXX and surrogate pairs
 // as UTF-8) written if `writer`, *p and *k past it.  Returns 0 or kErrString.
 template <bool WRITE>
-JSIDX_DEV uint32_t escape_at(const TapeArgs& a, uint64_t* pp, uint8_t* out, uint32_t* kk, bool writer) {
+JSIDX_DEV uint32_t escape_at(const StrSrc& s, StrLds& L, uint64_t* pp, const StrDst& o, uint32_t* kk, bool writer) {
   uint64_t p = *pp;
   uint32_t k = *kk;
   auto put = [&](uint32_t v) {
     if constexpr (WRITE) {
-      if (writer) prim::st_byte(out + k, v);
+      if (writer) dst_byte(o, L, k, v);
     }
     k++;
   };
-  if (p + 1 >= a.len) return kErrString;
-  const uint32_t e = prim::load1(a.buf + p + 1);
+  if (p + 1 >= s.len) return kErrString;
+  const uint32_t e = src_byte(s, L, p + 1);
   p += 2;
   uint32_t v = 0xFFFFFFFFu;
   switch (e) {
@@ -267,14 +397,14 @@ JSIDX_DEV uint32_t escape_at(const TapeArgs& a, uint64_t* pp, uint8_t* out, uint
     put(v);
   } else {
     if (e != 'u') return kErrString;
-    const int32_t u = hex_quad(a, p);
+    const int32_t u = hex_quad(s, L, p);
     if (u < 0) return kErrString;
     p += 4;
     uint32_t cp = (uint32_t)u;
     if (cp >= 0xDC00u && cp <= 0xDFFFu) return kErrString;  // a low surrogate first
     if (cp >= 0xD800u && cp <= 0xDBFFu) {
-      if (p + 2 > a.len || prim::load1(a.buf + p) != '\\' || prim::load1(a.buf + p + 1) != 'u') return kErrString;
-      const int32_t lo = hex_quad(a, p + 2);
+      if (p + 2 > s.len || src_byte(s, L, p) != '\\' || src_byte(s, L, p + 1) != 'u') return kErrString;
+      const int32_t lo = hex_quad(s, L, p + 2);
       if (lo < 0xDC00 || lo > 0xDFFF) return kErrString;
       p += 6;
       cp = 0x10000u + ((cp - 0xD800u) << 10) + ((uint32_t)lo - 0xDC00u);
@@ -300,63 +430,71 @@ JSIDX_DEV uint32_t escape_at(const TapeArgs& a, uint64_t* pp, uint8_t* out, uint
   return 0;
 }
 
-// One thread's part of a string: from byte *p on (inside the string, *k bytes
-// already out) up to the closing quote, with at most `budget` steps over
-// whole plain blocks.  Returns 0 (closed), kErrString (a byte below 0x20, a
-// bad escape, no closing quote; the count then stops there, the same in
-// both modes) or kDeferred (*p and *k say where it stopped).
+// Bytes [off, first) of a 16-byte block (words x) to the destination at k:
+// single bytes up to a 4-byte aligned destination, whole words taken from
+// the block shifted as a 128-bit value, single bytes after them.
+JSIDX_DEV void copy_plain(const StrDst& o, StrLds& L, uint32_t k, const uint32_t x[4], uint32_t off, uint32_t first) {
+  const uint64_t lo64 = ((uint64_t)x[1] << 32) | x[0], hi64 = ((uint64_t)x[3] << 32) | x[2];
+  const uint32_t cnt = first - off;
+  const uint32_t da = (uint32_t)(reinterpret_cast<uintptr_t>(o.g + k) & 3u);
+  uint32_t m0 = (4u - da) & 3u;
+  if (m0 > cnt) m0 = cnt;
+  const uint32_t nw = (cnt - m0) / 4;
+  for (uint32_t m = 0; m < cnt; m++) {
+    if (m == m0 && nw) m += 4 * nw;  // the words below
+    if (m >= cnt) break;
+    const uint32_t idx = off + m;
+    dst_byte(o, L, k + m, (uint32_t)((idx < 8 ? lo64 >> (8 * idx) : hi64 >> (8 * (idx - 8))) & 0xFFu));
+  }
+  if (nw) {
+    const uint32_t r = 8 * (off + m0);  // at most 96: off + m0 + 4 <= first <= 16
+    const uint64_t slo = r == 0 ? lo64 : r < 64 ? (lo64 >> r) | (hi64 << (64 - r)) : hi64 >> (r - 64);
+    const uint64_t shi = r < 64 ? hi64 >> r : 0ull;
+    dst_word(o, L, k + m0, (uint32_t)slo);
+    if (nw > 1) dst_word(o, L, k + m0 + 4, (uint32_t)(slo >> 32));
+    if (nw > 2) dst_word(o, L, k + m0 + 8, (uint32_t)shi);
+    if (nw > 3) dst_word(o, L, k + m0 + 12, (uint32_t)(shi >> 32));
+  }
+}
+
+// One lane's part of a string: from byte *p on (inside the string, *k bytes
+// already out) up to the closing quote, in at most `budget` steps (a block
+// of plain bytes, or one escape or single byte each).  Returns 0 (closed),
+// kErrString (a byte below 0x20, a bad escape, no closing quote; the count
+// then stops there, the same in both passes) or kDeferred (*p and *k say
+// where it stopped).
 template <bool WRITE>
-JSIDX_DEV uint32_t string_run(const TapeArgs& a, uint64_t* pp, uint8_t* out, uint32_t* kk, uint32_t budget) {
+JSIDX_DEV uint32_t string_run(const StrSrc& s, StrLds& L, uint64_t* pp, const StrDst& o, uint32_t* kk,
+                              uint32_t budget) {
   uint64_t p = *pp;
   uint32_t k = *kk;
   uint32_t err = 0;
   uint32_t steps = 0;
   for (;;) {
-    // 16 bytes from the aligned word holding p on (four loads in flight): the
-    // plain bytes up to the first quote, backslash or control byte are taken
-    // from registers; that byte is handled below
-    const uint32_t off = (uint32_t)(reinterpret_cast<uintptr_t>(a.buf + p) & 3u);
-    if (p >= off && p - off + 16 <= a.len) {
-      const uint64_t pb = p - off;
-      const uint32_t x0 = prim::load4(a.buf + pb), x1 = prim::load4(a.buf + pb + 4);
-      const uint32_t x2 = prim::load4(a.buf + pb + 8), x3 = prim::load4(a.buf + pb + 12);
+    // the aligned block holding p: the plain bytes up to the first quote,
+    // backslash or control byte are taken from registers; that byte is
+    // handled below
+    uint32_t x[4];
+    const uint64_t pb = src_block(s, L, p, x);
+    if (pb != ~0ull) {
+      const uint32_t off = (uint32_t)(p - pb);
       // the lowest flagged byte of a word is exact (a borrow only runs upward)
       auto hits = [](uint32_t v) {
         const uint32_t q2 = v ^ 0x22222222u, b2 = v ^ 0x5C5C5C5Cu;
         return (((q2 - 0x01010101u) & ~q2) | ((b2 - 0x01010101u) & ~b2) | ((v - 0x20202020u) & ~v)) & 0x80808080u;
       };
-      const uint32_t h0 = hits(x0) & (0xFFFFFFFFu << (8 * off)), h1 = hits(x1), h2 = hits(x2), h3 = hits(x3);
+      // bytes of word j at or after p
+      auto keep = [off](uint32_t j) {
+        return off <= 4 * j ? 0xFFFFFFFFu : off >= 4 * j + 4 ? 0u : 0xFFFFFFFFu << (8 * (off - 4 * j));
+      };
+      const uint32_t h0 = hits(x[0]) & keep(0), h1 = hits(x[1]) & keep(1);
+      const uint32_t h2 = hits(x[2]) & keep(2), h3 = hits(x[3]) & keep(3);
       // the first special byte at or after p, in the block (16: none)
       const uint32_t first = h0 ? (uint32_t)__builtin_ctz(h0) / 8
                            : h1 ? 4 + (uint32_t)__builtin_ctz(h1) / 8
                            : h2 ? 8 + (uint32_t)__builtin_ctz(h2) / 8
                            : h3 ? 12 + (uint32_t)__builtin_ctz(h3) / 8 : 16u;
-      // bytes [off, first) are plain: whole words where the destination is
-      // aligned (taken from the window shifted as a 128-bit value), single
-      // bytes around them
-      if constexpr (WRITE) {
-        const uint64_t lo64 = ((uint64_t)x1 << 32) | x0, hi64 = ((uint64_t)x3 << 32) | x2;
-        const uint32_t cnt = first - off;
-        const uint32_t da = (uint32_t)(reinterpret_cast<uintptr_t>(out + k) & 3u);
-        uint32_t m0 = (4u - da) & 3u;
-        if (m0 > cnt) m0 = cnt;
-        const uint32_t nw = (cnt - m0) / 4;
-        for (uint32_t m = 0; m < cnt; m++) {
-          if (m == m0 && nw) m += 4 * nw;  // the words below
-          if (m >= cnt) break;
-          const uint32_t idx = off + m;
-          prim::st_byte(out + k + m, (uint32_t)((idx < 8 ? lo64 >> (8 * idx) : hi64 >> (8 * (idx - 8))) & 0xFFu));
-        }
-        if (nw) {
-          const uint32_t r = 8 * (off + m0);  // below 64: off and m0 are at most 3
-          const uint64_t slo = r ? (lo64 >> r) | (hi64 << (64 - r)) : lo64, shi = hi64 >> r;
-          uint32_t* dw = reinterpret_cast<uint32_t*>(out + k + m0);
-          prim::st_out(dw, (uint32_t)slo);
-          if (nw > 1) prim::st_out(dw + 1, (uint32_t)(slo >> 32));
-          if (nw > 2) prim::st_out(dw + 2, (uint32_t)shi);
-          if (nw > 3) prim::st_out(dw + 3, (uint32_t)(shi >> 32));
-        }
-      }
+      if constexpr (WRITE) copy_plain(o, L, k, x, off, first);
       k += first - off;
       p = pb + first;
       if (first == 16) {
@@ -365,44 +503,168 @@ JSIDX_DEV uint32_t string_run(const TapeArgs& a, uint64_t* pp, uint8_t* out, uin
       }
       // the special byte is in the registers: a closing quote ends the string
       // without another load
-      const uint32_t fw = first < 8 ? (first < 4 ? x0 : x1) : (first < 12 ? x2 : x3);
-      if (((fw >> (8 * (first & 3u))) & 0xFFu) == '"') break;
+      if (((word_in(x, first / 4) >> (8 * (first & 3u))) & 0xFFu) == '"') break;
     }
-    if (p >= a.len) { err = kErrString; break; }
-    const uint32_t c = prim::load1(a.buf + p);
+    if (p >= s.len) { err = kErrString; break; }
+    const uint32_t c = src_byte(s, L, p);
     if (c == '"') break;
     if (c < 0x20u) { err = kErrString; break; }
     if (c != '\\') {
-      emit<WRITE>(out, &k, c);
+      if constexpr (WRITE) dst_byte(o, L, k, c);
+      k++;
       p++;
-      continue;
+    } else {
+      err = escape_at<WRITE>(s, L, &p, o, &k, true);
+      if (err) break;
     }
-    err = escape_at<WRITE>(a, &p, out, &k, true);
-    if (err) break;
+    if (++steps >= budget) { err = kDeferred; break; }
   }
   *pp = p;
   *kk = k;
   return err;
 }
 
-// The rest of a string by the whole wave (every lane calls it with the same
-// arguments): 64 bytes per step, one per lane, the first quote, backslash or
-// control byte found by ballot; the plain bytes before it are written by
-// their lanes (coalesced), an escape is decoded by every lane and written by
-// lane 0.  Returns 0 or kErrString; *k as string_run.
+JSIDX_DEV uint64_t readlane64(uint64_t v, int l) {
+  return ((uint64_t)prim::readlane((uint32_t)(v >> 32), l) << 32) | prim::readlane((uint32_t)v, l);
+}
+
+// UTF-8 of code point cp: its bytes, lowest first, in one word; *n their count.
+JSIDX_DEV uint32_t utf8_of(uint32_t cp, uint32_t* n) {
+  if (cp < 0x80u) { *n = 1; return cp; }
+  if (cp < 0x800u) { *n = 2; return (0xC0u | (cp >> 6)) | ((0x80u | (cp & 0x3Fu)) << 8); }
+  if (cp < 0x10000u) {
+    *n = 3;
+    return (0xE0u | (cp >> 12)) | ((0x80u | ((cp >> 6) & 0x3Fu)) << 8) | ((0x80u | (cp & 0x3Fu)) << 16);
+  }
+  *n = 4;
+  return (0xF0u | (cp >> 18)) | ((0x80u | ((cp >> 12) & 0x3Fu)) << 8) | ((0x80u | ((cp >> 6) & 0x3Fu)) << 16) |
+         ((0x80u | (cp & 0x3Fu)) << 24);
+}
+
+// The byte an escape letter stands for (0x100: not an escape letter; 'u' is
+// handled apart).
+JSIDX_DEV uint32_t escape_char(uint32_t e) {
+  switch (e) {
+    case '"': return '"';
+    case '\\': return '\\';
+    case '/': return '/';
+    case 'b': return 0x08u;
+    case 'f': return 0x0Cu;
+    case 'n': return 0x0Au;
+    case 'r': return 0x0Du;
+    case 't': return 0x09u;
+    default: return 0x100u;
+  }
+}
+
+// 64 bytes of a string from p on (p not inside an escape) by the whole wave,
+// one byte per lane, every escape in them decoded at once (every lane calls
+// it with the same arguments).  The escapes are found from the backslash
+// mask: the lowest backslash left starts one, which covers the byte after it
+// (scalar work, a few steps per window).  The window ends at the closing
+// quote, or before an escape that runs past its 64 bytes.  Returns the bytes
+// taken (*closed: up to the closing quote) after writing their decoded bytes
+// at *k (prefix sum of each lane's byte count), or -1 without writing if the
+// bytes taken would hold a byte below 0x20, a bad escape or a bad \u
+// sequence, or run past the document (the serial step then takes them, with
+// its error rules).
 template <bool WRITE>
-JSIDX_DEV uint32_t string_wave(const TapeArgs& a, uint64_t p, uint8_t* out, uint32_t* kk) {
+JSIDX_DEV int string_window(const StrSrc& s, StrLds& L, uint64_t p, const StrDst& o, uint32_t* kk, bool* closed) {
+  const uint32_t lane = prim::lane();
+  const uint64_t pos = p + lane;
+  const uint32_t c = pos < s.len ? src_byte(s, L, pos) : 0x100u;
+  const uint64_t bsl = prim::ballot(c == '\\'), quo = prim::ballot(c == '"');
+  const uint64_t ctl = prim::ballot(c < 0x20u || c >= 0x100u);
+  uint64_t esc = 0, st = 0, rem = bsl;  // escaped bytes, escape-starting backslashes
+  while (rem) {
+    const int i = __builtin_ctzll(rem);
+    st |= 1ull << i;
+    if (i == 63) break;
+    esc |= 2ull << i;
+    rem &= i == 62 ? 0ull : ~((4ull << i) - 1);
+  }
+  const bool is_esc = prim::lane_bit(esc), is_st = prim::lane_bit(st);
+  // \u escapes: the letter's lane reads the four hex digits (and those of a
+  // low surrogate after a high one)
+  const bool is_u = is_esc && c == 'u';
+  int32_t cp = -1;
+  bool pair = false;
+  if (is_u) {
+    cp = hex_quad(s, L, pos + 1);
+    if (cp >= 0xD800 && cp <= 0xDBFF) {
+      const int32_t lo = pos + 6 < s.len && src_byte(s, L, pos + 5) == '\\' && src_byte(s, L, pos + 6) == 'u'
+                             ? hex_quad(s, L, pos + 7) : -1;
+      if (lo >= 0xDC00 && lo <= 0xDFFF) {
+        cp = 0x10000 + ((cp - 0xD800) << 10) + (lo - 0xDC00);
+        pair = true;
+      } else {
+        cp = -1;
+      }
+    } else if (cp >= 0xDC00 && cp <= 0xDFFF) {
+      cp = -1;
+    }
+  }
+  const uint64_t um = prim::ballot(is_u), pm = prim::ballot(pair);
+  const uint64_t hex = (um << 1) | (um << 2) | (um << 3) | (um << 4) | (pm << 5) | (pm << 6);  // the pair's
+  // second backslash is in st already; its letter and digits are covered by
+  // pm << 6 and um's own shifts (the second letter is escaped too)
+  const uint64_t second = pm << 6;
+  // the closing quote, and the first escape whose bytes do not all lie in the window
+  const uint64_t endq = quo & ~esc & ~hex;
+  const uint32_t end = endq ? (uint32_t)__builtin_ctzll(endq) : 64u;
+  const uint32_t seq = prim::lane_bit(um >> 1) ? (prim::lane_bit(pm >> 1) ? 12u : 6u) : 2u;
+  const uint64_t over = prim::ballot(is_st && lane + seq > 64u);
+  const uint32_t cut = over ? (uint32_t)__builtin_ctzll(over) : 64u;
+  const uint32_t W = end < cut ? end : cut;
+  const uint64_t take = W >= 64 ? ~0ull : (1ull << W) - 1;
+  // anything the fast path does not decode
+  const bool bad_here = (is_esc && !(second >> lane & 1ull) && (c == 'u' ? cp < 0 : escape_char(c) == 0x100u));
+  const uint64_t bad = (ctl | prim::ballot(bad_here)) & take & ~(hex & ~second);
+  if (bad) return -1;
+  // each lane's bytes
+  uint32_t n = 0, v = 0;
+  if (lane < W && !is_st && !(hex >> lane & 1ull)) {
+    if (is_u) v = utf8_of((uint32_t)cp, &n);
+    else if (is_esc) { v = escape_char(c); n = 1; }
+    else { v = c; n = 1; }
+  }
+  const uint32_t incl = prim::incl_scan(n);
+  uint32_t k = *kk;
+  if constexpr (WRITE) {
+    for (uint32_t j = 0; j < n; j++) dst_byte(o, L, k + incl - n + j, (v >> (8 * j)) & 0xFFu);
+  }
+  k += prim::readlane(incl, 63);
+  *kk = k;
+  *closed = end < cut;
+  return (int)W;
+}
+
+// The rest of a string by the whole wave (every lane calls it with the same
+// arguments): 64 bytes per step (string_window); a window holding an error
+// candidate is taken serially instead: its plain bytes up to the first quote,
+// backslash or control byte, found by ballot, written by their lanes, then
+// that byte (an escape is decoded by every lane and written by lane 0).
+// Returns 0 or kErrString; *k as string_run.
+template <bool WRITE>
+JSIDX_DEV uint32_t string_wave(const StrSrc& s, StrLds& L, uint64_t p, const StrDst& o, uint32_t* kk) {
   const uint32_t lane = prim::lane();
   uint32_t k = *kk;
   uint32_t err = 0;
   for (;;) {
+    bool closed = false;
+    const int w = string_window<WRITE>(s, L, p, o, &k, &closed);
+    if (w >= 0) {
+      p += (uint32_t)w;
+      if (closed) break;
+      continue;
+    }
     const uint64_t pos = p + lane;
-    const uint32_t c = pos < a.len ? prim::load1(a.buf + pos) : 0x100u;
+    const uint32_t c = pos < s.len ? src_byte(s, L, pos) : 0x100u;
     const bool special = c >= 0x100u || c == '"' || c == '\\' || c < 0x20u;
     const uint64_t m = prim::ballot(special);
     const uint32_t f = m ? (uint32_t)__builtin_ctzll(m) : 64u;
     if constexpr (WRITE) {
-      if (lane < f) prim::st_byte(out + k + lane, c);
+      if (lane < f) dst_byte(o, L, k + lane, c);
     }
     k += f;
     p += f;
@@ -410,50 +672,375 @@ JSIDX_DEV uint32_t string_wave(const TapeArgs& a, uint64_t p, uint8_t* out, uint
     const uint32_t c0 = prim::readlane(c, (int)f);  // the special byte, the same for every lane
     if (c0 == '"') break;
     if (c0 >= 0x100u || c0 < 0x20u) { err = kErrString; break; }
-    err = escape_at<WRITE>(a, &p, out, &k, lane == 0);
+    err = escape_at<WRITE>(s, L, &p, o, &k, lane == 0);
     if (err) break;
   }
   *kk = k;
   return err;
 }
 
+
 // Strings of a wave, each lane's string opening at q (if `has`): its bytes
 // after normalization (escapes decoded, \uXXXX and surrogate pairs as UTF-8)
-// to out (WRITE) and their count to *n.  A byte below 0x20, an unknown
-// escape, a malformed or lone surrogate, or no closing quote is an error (the
-// count then stops there, the same in both modes).  Each lane runs its own
-// string for kStringSteps blocks; the strings that outrun it are then
-// finished one after another by the whole wave.  Every lane of the wave must
-// call this.
-constexpr uint32_t kStringSteps = 2;
+// to o (WRITE) and their count to *n.  A byte below 0x20, an unknown escape,
+// a malformed or lone surrogate, or no closing quote is an error (the count
+// then stops there, the same in both passes).  Each lane runs its own string
+// for kStringSteps steps; the strings that outrun it are then finished one
+// after another by the whole wave.  Every lane of the wave must call this.
+constexpr uint32_t kStringSteps = 3;
 template <bool WRITE>
-JSIDX_DEV uint32_t wave_strings(const TapeArgs& a, bool has, uint64_t q, uint8_t* out, uint32_t* n) {
+JSIDX_DEV uint32_t wave_strings(const StrSrc& s, StrLds& L, bool has, uint64_t q, const StrDst& o, uint32_t* n) {
   uint64_t p = q + 1;
   uint32_t k = 0;
-  uint32_t err = has ? string_run<WRITE>(a, &p, out, &k, kStringSteps) : 0u;
+  uint32_t err = has ? string_run<WRITE>(s, L, &p, o, &k, kStringSteps) : 0u;
   uint64_t m = prim::ballot(err == kDeferred);
   while (m) {
-    const int L = __builtin_ctzll(m);
+    const int l = __builtin_ctzll(m);
     m &= m - 1;
-    const uint64_t pL = ((uint64_t)prim::readlane((uint32_t)(p >> 32), L) << 32) | prim::readlane((uint32_t)p, L);
-    uint32_t kL = prim::readlane(k, L);
-    uint8_t* outL = nullptr;
+    const uint64_t pl = readlane64(p, l);
+    uint32_t kl = prim::readlane(k, l);
+    // the lane's own document bound and destination
+    StrSrc sl = s;
+    sl.len = readlane64(s.len, l);
+    StrDst ol{nullptr, 0u, false};
     if constexpr (WRITE) {
-      const uint64_t o = reinterpret_cast<uintptr_t>(out);
-      outL = reinterpret_cast<uint8_t*>(((uint64_t)prim::readlane((uint32_t)(o >> 32), L) << 32) |
-                                        prim::readlane((uint32_t)o, L));
+      ol.g = reinterpret_cast<uint8_t*>(readlane64(reinterpret_cast<uintptr_t>(o.g), l));
+      ol.li = prim::readlane(o.li, l);
+      ol.staged = prim::readlane(o.staged ? 1u : 0u, l) != 0u;
     }
-    // the lane's own document bound (a batch's lanes may hold different documents)
-    TapeArgs aL = a;
-    aL.len = ((uint64_t)prim::readlane((uint32_t)(a.len >> 32), L) << 32) | prim::readlane((uint32_t)a.len, L);
-    const uint32_t e = string_wave<WRITE>(aL, pL, outL, &kL);
-    if ((int)prim::lane() == L) {
-      k = kL;
+    const uint32_t e = string_wave<WRITE>(sl, L, pl, ol, &kl);
+    if ((int)prim::lane() == l) {
+      k = kl;
       err = e;
     }
   }
   *n = k;
   return err;
+}
+
+// Stores a wave's staged output: buffer bytes [A, B), staged from L.out byte
+// d on (d: A's offset in its 16-byte block); whole blocks with 16-byte
+// stores, the partial blocks at both ends byte by byte (whole wave).
+JSIDX_DEV void copy_out(StrLds& L, uint8_t* str, uint64_t A, uint64_t B, uint32_t d) {
+  prim::wave_sync();  // every lane's staged bytes are written
+  const uint32_t end = (uint32_t)(B - A) + d;  // staged bytes [d, end)
+  const uint32_t nblk = (end + 15) / 16;
+  for (uint32_t m = prim::lane(); m < nblk; m += 64u) {
+    const uint32_t u0 = 16 * m;
+    if (u0 >= d && u0 + 16 <= end) {
+      prim::st_out4(reinterpret_cast<uint32_t*>(str + (A + (u0 - d))), prim::ld_lds128(L.out + 4 * m));
+    } else {
+      for (uint32_t b = 0; b < 16u; b++) {
+        const uint32_t u = u0 + b;
+        if (u >= d && u < end)
+          prim::st_byte(str + (A + (u - d)), prim::lds_ld1(reinterpret_cast<const uint8_t*>(L.out) + u));
+      }
+    }
+  }
+}
+
+// ---- Strings, byte-parallel ---------------------------------------------------
+// The fast path of a run of kRunMax entries: the bytes from its first string
+// on are taken 1 KiB per step, lane l holding bytes 16 l .. 16 l + 15 of the
+// step (one 16-byte load), and every byte is classified at once (quote,
+// backslash, byte below 0x20) by word arithmetic.  What a byte is follows
+// from masks and from carries between lanes and steps:
+//  - the escapes: the lowest backslash not yet covered starts one, which
+//    covers the byte after it; a run of backslashes reaches the next lane
+//    only through its parity (a lane of 16 backslashes passes the carry on);
+//  - the string bytes: the unescaped quotes toggle between outside and
+//    inside (the run starts outside every string), the parity of those in
+//    the lanes before coming from a ballot;
+//  - the output: string j of the run (its 32-bit length, then its decoded
+//    bytes) starts at O0 + 4 j + R, R the decoded bytes of the run's strings
+//    before it, from one wave scan of each lane's (strings opened, bytes).
+// A run whose bytes hold something this does not decode, or does not decode
+// the same way as the per-string scan, is left to the per-string path: a
+// byte below 0x20 in a string, a bad escape or \u sequence, a \u sequence
+// that runs into the next lane, a backslash outside strings, or quotes that
+// do not open a string exactly at each string entry and close it before its
+// document ends.  The counting pass records which runs were left; the writing
+// pass follows that.
+constexpr uint32_t kRingBytes = 2048;  // the writing pass's output, per wave (a step adds at most 1366)
+
+struct RunCountLds {        // per wave
+  uint32_t epos[kRunMax];   // string j: its entry's position, from the span's base
+  uint32_t eend[kRunMax];   // string j: its document's end, from the span's base
+  uint32_t val[kRunMax];    // string j: the run's decoded bytes before its opening quote
+  uint32_t slen[kRunMax];   // string j: its decoded bytes
+};
+struct RunWriteLds {        // per wave
+  uint32_t val[kRunMax];    // string j: its buffer bytes, as counted
+  uint32_t ring[kRingBytes / 4 + 1];  // the output, then a spare word for bytes that write nothing
+};
+
+// Bit b of the result: byte b of the 16 bytes in x equals c (a zero-byte test
+// per byte: no borrow crosses a byte).
+JSIDX_DEV uint32_t bytes_zero(const uint32_t x[4], uint32_t pat, uint32_t keep) {
+  uint32_t r = 0;
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    const uint32_t t = (x[k] ^ pat) & keep;
+    const uint32_t z = ~(((t & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | t) & 0x80808080u;
+    uint32_t f = z >> 7;  // bits 0, 8, 16, 24 to 0..3
+    f |= f >> 7;
+    f |= f >> 14;
+    r |= (f & 0xFu) << (4 * k);
+  }
+  return r;
+}
+JSIDX_DEV uint32_t bytes_eq(const uint32_t x[4], uint32_t c) { return bytes_zero(x, c * 0x01010101u, ~0u); }
+JSIDX_DEV uint32_t bytes_ctl(const uint32_t x[4]) { return bytes_zero(x, 0u, 0xE0E0E0E0u); }  // below 0x20
+JSIDX_DEV uint32_t byte_in(const uint32_t x[4], uint32_t i) { return (word_in(x, i / 4) >> (8 * (i & 3u))) & 0xFFu; }
+
+// Four hex digits at p of the buffer (below bhi), or -1.
+JSIDX_DEV int32_t hex_at(const uint8_t* buf, uint64_t p, uint64_t bhi) {
+  if (p + 4 > bhi) return -1;
+  int32_t v = 0;
+  for (int k = 0; k < 4; k++) {
+    const int32_t h = hex_digit(prim::load1(buf + p + k));
+    if (h < 0) return -1;
+    v = v * 16 + h;
+  }
+  return v;
+}
+
+// Stores output bytes [from, to) of a run (indices from the 16-byte block
+// holding its first byte O0, which is byte d of it; from a multiple of 16):
+// whole blocks with 16-byte stores, the bytes of partial blocks one by one.
+JSIDX_DEV void ring_store(const uint32_t* ring, uint8_t* str, uint64_t O0, uint32_t d, uint32_t from, uint32_t to) {
+  const uint32_t nb = to > from ? (to - from + 15) / 16 : 0u;
+  const uint8_t* r8 = reinterpret_cast<const uint8_t*>(ring);
+  for (uint32_t m = prim::lane(); m < nb; m += 64u) {
+    const uint32_t r0 = from + 16 * m;
+    if (r0 >= d && r0 + 16 <= to) {
+      prim::st_out4(reinterpret_cast<uint32_t*>(str + O0 + (r0 - d)), prim::ld_lds128(ring + (r0 & (kRingBytes - 1)) / 4));
+    } else {
+      for (uint32_t b = 0; b < 16u; b++) {
+        const uint32_t r = r0 + b;
+        if (r >= d && r < to) prim::st_byte(str + O0 + (r - d), prim::lds_ld1(r8 + (r & (kRingBytes - 1))));
+      }
+    }
+  }
+}
+
+// A run's bytes are read from the 16-byte aligned address at or below its
+// start: the span's base.
+JSIDX_DEV int64_t span_base(const uint8_t* buf, uint64_t p0) {
+  return (int64_t)p0 - (int64_t)(reinterpret_cast<uintptr_t>(buf + p0) & 15u);
+}
+// This lane's 16 bytes of step `step` of a span (whole 16-byte loads inside
+// [blo, bhi), single bytes at the buffer's ends, 0 outside).
+JSIDX_DEV uint4 span_load(const uint8_t* buf, int64_t base, uint32_t step, uint64_t blo, uint64_t bhi) {
+  const int64_t pb = base + 1024ll * step + 16ll * prim::lane();
+  if (pb >= (int64_t)blo && pb + 16 <= (int64_t)bhi) return prim::load16(buf + pb);
+  uint32_t x[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+  for (int b = 0; b < 16; b++)
+    if (pb + b >= (int64_t)blo && pb + b < (int64_t)bhi) x[b / 4] |= prim::load1(buf + pb + b) << (8 * (b % 4));
+  return uint4{x[0], x[1], x[2], x[3]};
+}
+JSIDX_DEV uint32_t span_steps(int64_t base, uint64_t p1) { return (uint32_t)(((int64_t)p1 - base + 1023) / 1024); }
+
+// The run's strings, in its bytes from p0 (its first entry) to p1 (the entry
+// after the run, or the buffer's end), nstr of them; [blo, bhi) is the
+// readable buffer; s0 and s1 this lane's bytes of the first two steps,
+// loaded by the caller (later steps are loaded one step ahead).  Counting
+// (!WRITE): T.epos and T.eend hold the string entries; fills T.slen.
+// Writing: T.val holds each string's buffer bytes; stores the run's output
+// from buffer offset O0 on.  Returns whether the run was left to the
+// per-string path (the same for the whole wave; when counting only).
+template <bool WRITE, class Tables>
+JSIDX_DEV bool fast_run(Tables& T, const uint8_t* buf, uint64_t p0, uint64_t p1, uint64_t blo, uint64_t bhi,
+                        uint32_t nstr, uint8_t* str, uint64_t O0, uint4 s0, uint4 s1) {
+  const uint32_t lane = prim::lane();
+  const uint64_t below = (1ull << lane) - 1u;
+  const int64_t base = span_base(buf, p0);
+  const uint32_t nsteps = span_steps(base, p1);
+  uint32_t ecarry = 0, pcarry = 0, J = 0, R = 0;
+  bool bad = false;
+  uint32_t d = 0, flushed = 0;
+  if constexpr (WRITE) d = (uint32_t)(reinterpret_cast<uintptr_t>(str + O0) & 15u);
+  uint4 cur = s0, nxt = s1;
+  for (uint32_t step = 0; step < nsteps && !bad; step++) {
+    const int64_t pb = base + 1024ll * step + 16ll * lane;
+    const uint32_t x[4] = {cur.x, cur.y, cur.z, cur.w};
+    cur = nxt;
+    if (step + 2 < nsteps) nxt = span_load(buf, base, step + 2, blo, bhi);
+    // the run's bytes: [p0, p1)
+    const int64_t vlo = (int64_t)p0 - pb, vhi = (int64_t)p1 - pb;
+    uint32_t valid = 0xFFFFu;
+    if (vlo > 0) valid = vlo >= 16 ? 0u : (0xFFFFu << vlo) & 0xFFFFu;
+    if (vhi < 16) valid &= vhi <= 0 ? 0u : (1u << vhi) - 1u;
+    const uint32_t qm = bytes_eq(x, '"') & valid, bm = bytes_eq(x, '\\') & valid;
+    const uint32_t cm = bytes_ctl(x) & valid, um = bytes_eq(x, 'u') & valid;
+    bool bad_l = false;
+    // escapes
+    const bool all_bs = bm == 0xFFFFu;
+    const uint32_t top = (uint32_t)__builtin_clz(~(bm << 16));  // backslashes ending the lane
+    const uint64_t np = prim::ballot(!all_bs), gm = prim::ballot((top & 1u) != 0u);
+    const uint64_t npb = np & below;
+    const uint32_t ein = npb ? (uint32_t)(gm >> (63 - __builtin_clzll(npb))) & 1u : ecarry;
+    ecarry = np ? (uint32_t)(gm >> (63 - __builtin_clzll(np))) & 1u : ecarry;
+    uint32_t esc = 0, st = 0, rem = bm;
+    if (ein) {
+      esc = 1u;
+      rem &= ~1u;
+    }
+    while (rem) {
+      const uint32_t i = (uint32_t)__builtin_ctz(rem);
+      st |= 1u << i;
+      esc |= 2u << i;
+      rem &= ~((4u << i) - 1u);
+    }
+    esc &= 0xFFFFu;
+    // \u escapes: the letter's lane reads the digits (and a low surrogate's
+    // escape after a high one), all of which must lie in the lane
+    uint32_t cov = 0, extra = 0;
+    uint32_t upos[3] = {16u, 16u, 16u}, uval[3] = {0u, 0u, 0u}, un[3] = {0u, 0u, 0u};
+    uint32_t ue = esc & um;
+#pragma unroll
+    for (int t = 0; t < 3; t++) {
+      if (ue) {
+        const uint32_t u = (uint32_t)__builtin_ctz(ue);
+        const uint64_t P = (uint64_t)(pb + u);
+        int32_t cp = hex_at(buf, P + 1, bhi);
+        uint32_t c = 4;
+        if (cp >= 0xD800 && cp <= 0xDBFF) {
+          const int32_t lo = P + 7 <= bhi && prim::load1(buf + P + 5) == '\\' && prim::load1(buf + P + 6) == 'u'
+                                 ? hex_at(buf, P + 7, bhi) : -1;
+          if (lo >= 0xDC00 && lo <= 0xDFFF) {
+            cp = 0x10000 + ((cp - 0xD800) << 10) + (lo - 0xDC00);
+            c = 10;
+          } else {
+            cp = -1;
+          }
+        } else if (cp >= 0xDC00 && cp <= 0xDFFF) {
+          cp = -1;
+        }
+        if (cp < 0 || u + c > 15u) {
+          bad_l = true;
+        } else {
+          uint32_t n = 0;
+          uval[t] = utf8_of((uint32_t)cp, &n);
+          un[t] = n;
+          upos[t] = u;
+          extra += n - 1;
+          cov |= ((1u << c) - 1u) << (u + 1);
+        }
+        ue &= ~cov & ~((2u << u) - 1u);
+      }
+    }
+    if (ue) bad_l = true;
+    // string bytes: the unescaped quotes toggle
+    const uint32_t uq = qm & ~esc & ~cov;
+    const uint64_t pm = prim::ballot((__builtin_popcount(uq) & 1) != 0);
+    const uint32_t pin = ((uint32_t)__builtin_popcountll(pm & below) & 1u) ^ pcarry;
+    pcarry ^= (uint32_t)__builtin_popcountll(pm) & 1u;
+    uint32_t px = uq;
+    px ^= px << 1;
+    px ^= px << 2;
+    px ^= px << 4;
+    px ^= px << 8;
+    const uint32_t inside = (px ^ (pin ? 0xFFFFu : 0u)) & 0xFFFFu;
+    const uint32_t opn = uq & inside, cls = uq & ~inside, content = inside & ~uq;
+    if ((cm & content) || ((st | esc) & ~content)) bad_l = true;
+    for (uint32_t el = esc & ~um; el; el &= el - 1u)
+      if (escape_char(byte_in(x, (uint32_t)__builtin_ctz(el))) == 0x100u) bad_l = true;
+    // the lane's decoded bytes and opened strings, and those before it
+    const uint32_t outm = content & ~st & ~cov;
+    const uint32_t v = ((uint32_t)__builtin_popcount(opn) << 16) | ((uint32_t)__builtin_popcount(outm) + extra);
+    const uint32_t incl = prim::incl_scan(v);
+    const uint32_t Jl = J + ((incl - v) >> 16), Rl = R + ((incl - v) & 0xFFFFu);
+    const uint32_t tot = prim::readlane(incl, 63);
+    J += tot >> 16;
+    R += tot & 0xFFFFu;
+    auto r_at = [&](uint32_t i) {  // the run's decoded bytes before byte i of the lane
+      uint32_t r = Rl + (uint32_t)__builtin_popcount(outm & ((1u << i) - 1u));
+#pragma unroll
+      for (int t = 0; t < 3; t++) r += upos[t] < i ? un[t] - 1u : 0u;
+      return r;
+    };
+    if constexpr (!WRITE) {
+      for (uint32_t o = opn; o; o &= o - 1u) {
+        const uint32_t i = (uint32_t)__builtin_ctz(o);
+        const uint32_t j = Jl + (uint32_t)__builtin_popcount(opn & ((1u << i) - 1u));
+        if (j >= nstr || T.epos[j] != (uint32_t)(pb + i - base)) bad_l = true;
+        else T.val[j] = r_at(i);
+      }
+      prim::wave_sync();
+      for (uint32_t o = cls; o; o &= o - 1u) {
+        const uint32_t i = (uint32_t)__builtin_ctz(o);
+        const uint32_t jo = Jl + (uint32_t)__builtin_popcount(opn & ((1u << i) - 1u));  // strings opened before
+        if (jo == 0 || jo > nstr || (uint32_t)(pb + i - base) >= T.eend[jo - 1]) bad_l = true;
+        else T.slen[jo - 1] = r_at(i) - T.val[jo - 1];
+      }
+    } else if (upos[0] == 16u) {
+      // no \u escape in the lane: every plain byte written (bytes that write
+      // nothing go to a spare slot, so that the 16 stores need no branch),
+      // then the escaped letters and the length words
+      uint8_t* ring = reinterpret_cast<uint8_t*>(T.ring);
+      const uint32_t o0 = d + 4 * Jl + Rl, plain = outm & ~esc;
+#pragma unroll
+      for (int b = 0; b < 16; b++) {
+        const uint32_t mb = (1u << b) - 1u;
+        const uint32_t o = o0 + (uint32_t)__builtin_popcount(outm & mb) + 4u * (uint32_t)__builtin_popcount(opn & mb);
+        prim::lds_st1(ring + ((plain >> b) & 1u ? (o & (kRingBytes - 1)) : kRingBytes), (x[b / 4] >> (8 * (b % 4))) & 0xFFu);
+      }
+      for (uint32_t e = outm & esc; e; e &= e - 1u) {
+        const uint32_t b = (uint32_t)__builtin_ctz(e), mb = (1u << b) - 1u;
+        const uint32_t o = o0 + (uint32_t)__builtin_popcount(outm & mb) + 4u * (uint32_t)__builtin_popcount(opn & mb);
+        prim::lds_st1(ring + (o & (kRingBytes - 1)), escape_char(byte_in(x, b)));
+      }
+      for (uint32_t e = opn; e; e &= e - 1u) {
+        const uint32_t b = (uint32_t)__builtin_ctz(e), mb = (1u << b) - 1u;
+        const uint32_t k = (uint32_t)__builtin_popcount(opn & mb);
+        const uint32_t o = o0 + (uint32_t)__builtin_popcount(outm & mb) + 4u * k;
+        const uint32_t len = (Jl + k < nstr ? T.val[Jl + k] : 4u) - 4u;
+        for (uint32_t q = 0; q < 4u; q++) prim::lds_st1(ring + ((o + q) & (kRingBytes - 1)), (len >> (8 * q)) & 0xFFu);
+      }
+    } else {
+      uint8_t* ring = reinterpret_cast<uint8_t*>(T.ring);
+      uint32_t jj = Jl, rr = Rl;
+#pragma unroll
+      for (int b = 0; b < 16; b++) {
+        const uint32_t bit = 1u << b;
+        if (opn & bit) {  // the string's length word
+          const uint32_t o = d + 4 * jj + rr, len = (jj < nstr ? T.val[jj] : 4u) - 4u;
+          for (uint32_t k = 0; k < 4u; k++) prim::lds_st1(ring + ((o + k) & (kRingBytes - 1)), (len >> (8 * k)) & 0xFFu);
+          jj++;
+        } else if (outm & bit) {
+          const uint32_t ch = (x[b / 4] >> (8 * (b % 4))) & 0xFFu;
+          uint32_t val = ch, n = 1;
+          if (esc & bit) {
+            val = escape_char(ch);
+#pragma unroll
+            for (int t = 0; t < 3; t++)
+              if (upos[t] == (uint32_t)b) {
+                val = uval[t];
+                n = un[t];
+              }
+          }
+          const uint32_t o = d + 4 * jj + rr;
+          for (uint32_t k = 0; k < n; k++) prim::lds_st1(ring + ((o + k) & (kRingBytes - 1)), (val >> (8 * k)) & 0xFFu);
+          rr += n;
+        }
+      }
+    }
+    if constexpr (WRITE) {
+      prim::wave_sync();
+      const uint32_t done = (d + 4 * J + R) & ~15u;  // whole blocks written
+      ring_store(T.ring, str, O0, d, flushed, done);
+      flushed = done > flushed ? done : flushed;
+      prim::wave_sync();
+    }
+    bad = prim::ballot(bad_l) != 0u;
+  }
+  if constexpr (WRITE) {
+    ring_store(T.ring, str, O0, d, flushed, d + 4 * J + R);
+    prim::wave_sync();
+  }
+  return bad || pcarry != 0u || J != nstr;
 }
 
 // ---- Literals ---------------------------------------------------------------
@@ -821,7 +1408,8 @@ struct TapeScanLds {
 template <bool BATCH>
 struct TapeChunkT {
   TapeScanLds sc;
-  uint32_t qbase[2];  // the workgroup's first slots in the string and number queues
+  uint64_t send;   // the next chunk's first buffer byte
+  uint32_t qbase;  // the workgroup's first slot in the number queue
   uint32_t S[kTapeChunk];
   uint32_t T[kTapeChunk];
   uint8_t K[kTapeChunk];
@@ -884,33 +1472,162 @@ JSIDX_DEV uint32_t entry_words(uint32_t b, uint32_t f) {
   return words_of(b) + (f & kVFirst ? 1u : 0u) + (f & kVLast ? 1u : 0u);
 }
 
-// 1. First bytes and string sizes (thread t takes entries c * 4096 + t +
-//    256 k), their sums per chunk.
+// The readable positions of buf: [buf_lo, buf_hi).
 template <bool BATCH>
-JSIDX_DEVFN void tape_count(const TapeArgs& a) {
-  TapeScanLds& g = prim::lds_object<TapeScanLds>();
-  const uint32_t tid = tape_tid();
+JSIDX_DEV uint64_t buf_lo(const TapeArgs& a) { return BATCH ? prim::load8(a.offsets) : 0u; }
+template <bool BATCH>
+JSIDX_DEV uint64_t buf_hi(const TapeArgs& a) { return BATCH ? prim::load8(a.offsets + a.ndocs) : a.len; }
+
+// LDS of the counting pass: the workgroup's scan and, per wave, the tables
+// of the byte-parallel path or the per-string path's staged bytes.
+union CountWaveLds {
+  StrLds s;
+  RunCountLds r;
+};
+struct TapeCountLds {
+  TapeScanLds sc;
+  CountWaveLds w[kTapeThreads / 64];
+};
+
+// Each wave takes 512 consecutive entries of a chunk as two runs of
+// kTapeSuper groups of 64 (one entry per lane); the loads for all the
+// entries of a run (positions, documents, links) are issued together before
+// any of them is used, so that a run costs a few memory round trips, not a
+// few per group.
+
+// Element q of a per-group array held in registers, by mask arithmetic (a
+// runtime index, or a chain of selects the compiler may turn into one, would
+// put the array in private memory).
+template <typename T>
+JSIDX_DEV T pick_group(const T (&v)[kTapeSuper], int q) {
+  T r = 0;
+#pragma unroll
+  for (int j = 0; j < kTapeSuper; j++) r |= v[j] & (T)(0 - (T)(q == j));
+  return r;
+}
+
+// The first entry of run h of this wave in chunk c.
+JSIDX_DEV uint64_t run_first(uint32_t c, int h) {
+  return (uint64_t)c * kTapeChunk +
+         ((uint64_t)prim::wave_id() * (kTapePer / kTapeSuper) + (uint64_t)h) * (64u * kTapeSuper);
+}
+
+// Index of this lane's entry among the run's strings (sm: the strings of
+// each group, q: this lane's group).
+JSIDX_DEV uint32_t run_index(const uint64_t (&sm)[kTapeSuper], int q) {
+  uint32_t k = 0;
+#pragma unroll
+  for (int j = 0; j < kTapeSuper; j++) k += j < q ? (uint32_t)__builtin_popcountll(sm[j]) : 0u;
+  return k + prim::mbcnt(pick_group(sm, q));
+}
+
+// The position of the run's first string (whole wave; sm as above, pos the
+// lanes' positions per group).
+JSIDX_DEV uint64_t run_first_string(const uint64_t (&sm)[kTapeSuper], const uint64_t (&pos)[kTapeSuper]) {
+  int q = kTapeSuper - 1;
+#pragma unroll
+  for (int j = kTapeSuper - 1; j >= 0; j--) q = sm[j] ? j : q;
+  return readlane64(pick_group(pos, q), __builtin_ctzll(pick_group(sm, q)));
+}
+
+// 1. First bytes and string sizes, their sums per chunk.  A run's strings
+//    take the byte-parallel path unless it leaves them to the per-string one
+//    (recorded for the writing pass).
+template <bool BATCH>
+JSIDX_DEV void tape_count(const TapeArgs& a) {
+  TapeCountLds& g = prim::lds_object<TapeCountLds>();
+  CountWaveLds& W = g.w[prim::wave_id()];
+  const uint32_t tid = tape_tid(), lane = prim::lane();
   const uint32_t n = n_of<BATCH>(a), nchunks = nchunks_of<BATCH>(a);
+  const uint64_t blo = buf_lo<BATCH>(a), bhi = buf_hi<BATCH>(a);
   for (uint32_t c = prim::block(); c < nchunks; c += prim::grid()) {
   uint64_t w = 0, s = 0;
-  for (int k = 0; k < kTapePer; k++) {  // every lane runs every step (wave_strings)
-    const uint64_t i = (uint64_t)c * kTapeChunk + (uint64_t)k * kTapeThreads + tid;
-    const bool in = i < n;
-    const uint32_t f = BATCH && in ? prim::load1(a.vflag + i) : 0u;
-    const TapeArgs la = entry_args<BATCH>(a, in ? entry_doc<BATCH>(a, i) : 0u);
-    const uint64_t pos = in ? entry_pos<BATCH>(a, i) : 0u;
-    const uint32_t b = !in ? 0u : (f & kVEmpty) ? (uint32_t)':' : byte_at(la, pos);
-    uint32_t len = 0;
-    (void)wave_strings<false>(la, in && b == '"', pos, nullptr, &len);
-    if (!in) continue;
-    const uint32_t sb = b == '"' ? 4 + len : 0u;
-    prim::st_out(a.sbytes + i, sb);
-    prim::st_byte(a.kb + i, b);
-    w += entry_words(b, f);
-    s += sb;
+  for (int h = 0; h < kTapePer / kTapeSuper; h++) {
+    const uint64_t e0 = run_first(c, h);
+    if (e0 >= n) break;  // the same for the whole wave
+    uint64_t pos[kTapeSuper], len[kTapeSuper], sm[kTapeSuper];
+    uint32_t fl[kTapeSuper], by[kTapeSuper], sl[kTapeSuper];
+#pragma unroll
+    for (int q = 0; q < kTapeSuper; q++) {
+      const uint64_t i = e0 + 64u * q + lane;
+      const bool in = i < n;
+      fl[q] = BATCH && in ? prim::load1(a.vflag + i) : 0u;
+      pos[q] = in ? entry_pos<BATCH>(a, i) : 0u;
+      len[q] = !BATCH ? a.len : in ? prim::load8(a.offsets + entry_doc<BATCH>(a, i) + 1) : 0u;
+    }
+    const uint64_t e1 = e0 + 64u * kTapeSuper;
+    const uint64_t p1 = e1 < n ? entry_pos<BATCH>(a, e1) : bhi;
+    // the first bytes, and the first two steps of the run's bytes in flight together
+    const uint64_t p0 = readlane64(pos[0], 0);
+    const int64_t sbase0 = span_base(a.buf, p0);
+    const uint32_t nsteps = span_steps(sbase0, p1);
+    const uint4 s0 = span_load(a.buf, sbase0, 0, blo, bhi);
+    const uint4 s1 = nsteps > 1 ? span_load(a.buf, sbase0, 1, blo, bhi) : uint4{0u, 0u, 0u, 0u};
+    uint32_t nstr = 0;
+#pragma unroll
+    for (int q = 0; q < kTapeSuper; q++) {
+      const bool in = e0 + 64u * q + lane < n;
+      by[q] = !in ? 0u : (fl[q] & kVEmpty) ? (uint32_t)':' : pos[q] < len[q] ? prim::load1(a.buf + pos[q]) : 0u;
+      sm[q] = prim::ballot(by[q] == '"');
+      nstr += (uint32_t)__builtin_popcountll(sm[q]);
+      sl[q] = 0;
+    }
+    bool slow = false;
+    if (nstr) {
+      // the byte-parallel path, given each string entry's place
+      const uint64_t base = (uint64_t)sbase0;
+      prim::wave_sync();  // the previous run's reads are done
+#pragma unroll
+      for (int q = 0; q < kTapeSuper; q++) {
+        if (by[q] == '"') {
+          const uint32_t k = run_index(sm, q);
+          W.r.epos[k] = (uint32_t)(pos[q] - base);
+          W.r.eend[k] = len[q] - base < 0xFFFFFFFFull ? (uint32_t)(len[q] - base) : 0xFFFFFFFFu;
+        }
+      }
+      prim::wave_sync();
+      slow = fast_run<false>(W.r, a.buf, p0, p1, blo, bhi, nstr, nullptr, 0u, s0, s1);
+      prim::wave_sync();
+      if (!slow) {
+#pragma unroll
+        for (int q = 0; q < kTapeSuper; q++)
+          if (by[q] == '"') sl[q] = W.r.slen[run_index(sm, q)];
+      }
+      if (lane == 0) prim::st_byte(a.runbad + e0 / kRunMax, slow ? 1u : 0u);
+    }
+    if (!slow) {
+#pragma unroll
+      for (int q = 0; q < kTapeSuper; q++) {
+        const uint64_t i = e0 + 64u * q + lane;
+        if (i >= n) continue;
+        const uint32_t sb = by[q] == '"' ? 4 + sl[q] : 0u;
+        prim::st_out(a.sbytes + i, sb);
+        prim::st_byte(a.kb + i, by[q]);
+        w += entry_words(by[q], fl[q]);
+        s += sb;
+      }
+      continue;
+    }
+    // the per-string path
+    StrSrc src = stage_group(W.s, a.buf, run_first_string(sm, pos), p1, blo, bhi);
+    for (int q = 0; q < kTapeSuper; q++) {
+      if (e0 + 64u * q >= n) break;  // the same for the whole wave
+      const uint64_t i = e0 + 64u * q + lane;
+      const bool in = i < n;
+      const uint32_t b = pick_group(by, q);
+      src.len = pick_group(len, q);
+      uint32_t slen = 0;
+      (void)wave_strings<false>(src, W.s, in && b == '"', pick_group(pos, q), StrDst{nullptr, 0u, false}, &slen);
+      if (!in) continue;
+      const uint32_t sb = b == '"' ? 4 + slen : 0u;
+      prim::st_out(a.sbytes + i, sb);
+      prim::st_byte(a.kb + i, b);
+      w += entry_words(b, pick_group(fl, q));
+      s += sb;
+    }
   }
   uint64_t wex, sex, wall, sall;
-  group_scan2(g, tid, w, s, &wex, &sex, &wall, &sall);
+  group_scan2(g.sc, tid, w, s, &wex, &sex, &wall, &sall);
   if (tid == 0) {
     st64(a.chunk_sum + 2 * (uint64_t)c, wall);
     st64(a.chunk_sum + 2 * (uint64_t)c + 1, sall);
@@ -1011,6 +1728,7 @@ JSIDX_DEV void stage_offsets(const TapeArgs& a, uint32_t n, TapeChunkT<BATCH>& g
     tw += BATCH ? entry_words(g.K[j], g.F[j]) : words_of(g.K[j]);
     ts += sb;
   }
+  if (tid == kTapeThreads - 1) g.send = ts;
   prim::sync();
 }
 
@@ -1075,80 +1793,194 @@ JSIDX_DEVFN void tape_batch_docs(const TapeArgs& a) {
   }
 }
 
-// 4. Brackets and the strings' words; strings, numbers and literals queued
-//    (one thread per entry, consecutive threads on consecutive entries; one
-//    atomic per workgroup and queue).  In a batch, links and string offsets
-//    are relative to the entry's document's tape and strings.
+// LDS of the writing pass: the chunk and, per wave, the byte-parallel
+// path's sizes and output or the per-string path's staged bytes.
+union WriteWaveLds {
+  StrLds s;
+  RunWriteLds r;
+};
 template <bool BATCH>
-JSIDX_DEVFN void tape_write(const TapeArgs& a) {
-  TapeChunkT<BATCH>& g = prim::lds_object<TapeChunkT<BATCH>>();
-  const uint32_t tid = tape_tid();
+struct TapeWriteLds {
+  TapeChunkT<BATCH> ch;
+  WriteWaveLds w[kTapeThreads / 64];
+};
+
+// The strings of a group of 64 entries (whole wave; `has`: this lane's entry
+// is a string at pos, in a document ending at len, whose output, the length
+// word and the bytes, takes sz buffer bytes from offset so, as counted), read
+// through src.  Returns the lane's error flags.
+JSIDX_DEV uint32_t write_strings(const TapeArgs& a, StrLds& L, StrSrc src, bool has, uint64_t pos, uint64_t len,
+                                 uint64_t so, uint64_t sz) {
+  const int f = __builtin_ctzll(prim::ballot(has));  // the group's first string
+  src.len = len;
+  // the group's output is contiguous from the first string's on; the strings
+  // that fit in kStrOut bytes with it (a prefix of them) are staged
+  const uint64_t A = readlane64(so, f);
+  const uint32_t d = (uint32_t)(reinterpret_cast<uintptr_t>(a.str + A) & 15u);
+  const uint64_t rel = so - A + d;
+  const bool staged = has && rel + sz <= kStrOut;
+  const StrDst o{a.str + so + 4, (uint32_t)(staged ? rel + 4 : 0u), staged};
+  prim::wave_sync();  // the previous group's output is stored
+  uint32_t cnt = 0;
+  const uint32_t err = wave_strings<true>(src, L, has, pos, o, &cnt);
+  if (has) {
+    for (uint32_t j = 0; j < 4u; j++) {  // the length word
+      const uint32_t v = (cnt >> (8 * j)) & 0xFFu;
+      if (staged) prim::lds_st1(reinterpret_cast<uint8_t*>(L.out) + rel + j, v);
+      else prim::st_byte(a.str + so + j, v);
+    }
+  }
+  const uint64_t sm = prim::ballot(staged);
+  if (sm) copy_out(L, a.str, A, readlane64(so + sz, 63 - __builtin_clzll(sm)), d);
+  return err;
+}
+
+JSIDX_DEV bool is_bracket(uint32_t b) { return in_set(b, 0u, kBracketHi); }
+// numbers and literals
+JSIDX_DEV bool is_queued(uint32_t b) { return !in_set(b, kNoWordLo | set_lo('"'), kBracketHi); }
+
+// 4. Brackets, strings and the strings' words; numbers and literals queued
+//    (one atomic per workgroup).  In a batch, links and string offsets are
+//    relative to the entry's document's tape and strings.
+template <bool BATCH>
+JSIDX_DEV void tape_write(const TapeArgs& a) {
+  TapeWriteLds<BATCH>& G = prim::lds_object<TapeWriteLds<BATCH>>();
+  TapeChunkT<BATCH>& g = G.ch;
+  WriteWaveLds& W = G.w[prim::wave_id()];
+  const uint32_t tid = tape_tid(), lane = prim::lane();
   if (!batch_go<BATCH>(a)) return;
   const uint32_t n = n_of<BATCH>(a), nchunks = nchunks_of<BATCH>(a);
+  const uint64_t blo = buf_lo<BATCH>(a), bhi = buf_hi<BATCH>(a);
   for (uint32_t c = prim::block(); c < nchunks; c += prim::grid()) {
   stage_offsets<BATCH>(a, n, g, tid, c);
-  // the workgroup's slots in the two queues
-  uint64_t cs = 0, cn = 0;
-  for (int k = 0; k < kTapePer; k++) {
-    const uint32_t j = (uint32_t)k * kTapeThreads + tid;
-    const uint32_t b = g.K[j];  // entries past n were staged as ':'
-    cs += b == '"';
-    cn += words_of(b) == 2 || is_lit_start(b);  // numbers and literals share a queue
-  }
-  uint64_t sex, nex, sall, nall;
-  group_scan2(g.sc, tid, cs, cn, &sex, &nex, &sall, &nall);
-  if (tid == 0) {
-    g.qbase[0] = sall ? prim::add_agent32(a.qcount + 1, (uint32_t)sall) : 0u;
-    g.qbase[1] = nall ? prim::add_agent32(a.qcount + 2, (uint32_t)nall) : 0u;
-  }
+  const uint64_t c0 = (uint64_t)c * kTapeChunk;
+  // the workgroup's slots in the number queue, each thread's in entry order
+  const uint32_t jt = (uint32_t)(run_first(c, 0) - c0) + lane;  // this thread's entries: jt + 64 k
+  uint64_t cn = 0;
+  for (int k = 0; k < kTapePer; k++) cn += is_queued(g.K[jt + 64u * k]);  // entries past n were staged as ':'
+  uint64_t nex, nall, zex, zall;
+  group_scan2(g.sc, tid, cn, 0u, &nex, &zex, &nall, &zall);
+  if (tid == 0) g.qbase = nall ? prim::add_agent32(a.qcount + 1, (uint32_t)nall) : 0u;
   prim::sync();
-  uint32_t ps = g.qbase[0] + (uint32_t)sex, pn = g.qbase[1] + (uint32_t)nex;
+  uint32_t pn = g.qbase + (uint32_t)nex;
   // a chunk's buffer bytes stay below 2^32 (its strings lie in the input,
   // fewer than 2^32 - 2^16 bytes), so an offset is the chunk base plus its
   // low word's distance from the base's
   const uint64_t sbase = ld64(a.chunk_sum + 2 * (uint64_t)c + 1);
-  for (int k = 0; k < kTapePer; k++) {
-    const uint32_t j = (uint32_t)k * kTapeThreads + tid;
-    const uint64_t i = (uint64_t)c * kTapeChunk + j;
-    if (i >= n) break;
-    const uint32_t b = g.K[j];
-    const uint64_t t = g.T[j];
-    const bool bracket = b == '{' || b == '[' || b == '}' || b == ']';
-    if (!bracket && b != '"' && !(words_of(b) == 2 || is_lit_start(b))) continue;
-    uint32_t d = 0;
-    uint64_t w0 = 0, s0 = 0;
-    if (BATCH) {
-      d = prim::load4(reinterpret_cast<const uint8_t*>(a.docid + i));
-      w0 = ld64(a.dbase + 2 * (uint64_t)d);
-      s0 = ld64(a.dbase + 2 * (uint64_t)d + 1);
+  for (int h = 0; h < kTapePer / kTapeSuper; h++) {
+    const uint64_t e0 = run_first(c, h);
+    if (e0 >= n) break;  // the same for the whole wave
+    const uint32_t j0 = (uint32_t)(e0 - c0);
+    // the run's loads: documents, positions and links, then the documents'
+    // bases and (batches) links, then the partners' tape indices
+    uint32_t dq[kTapeSuper], mq[kTapeSuper], v0q[kTapeSuper], limq[kTapeSuper];
+    uint64_t pos[kTapeSuper], len[kTapeSuper], w0q[kTapeSuper], s0q[kTapeSuper], obq[kTapeSuper];
+    bool any_str = false;
+#pragma unroll
+    for (int q = 0; q < kTapeSuper; q++) {
+      const uint64_t i = e0 + 64u * q + lane;
+      const uint32_t b = g.K[j0 + 64u * q + lane];
+      const bool in = i < n, br = in && is_bracket(b), st = in && b == '"';
+      any_str |= st;
+      dq[q] = BATCH && (br || st) ? prim::load4(reinterpret_cast<const uint8_t*>(a.docid + i)) : 0u;
+      pos[q] = st ? entry_pos<BATCH>(a, i) : 0u;
+      mq[q] = !BATCH && br ? prim::load4(reinterpret_cast<const uint8_t*>(a.match + i)) : kTapeUnlinked;
     }
-    if (bracket) {
-      uint64_t link = 0;
-      uint32_t m = kTapeUnlinked, lim = n, mv = 0;
-      if (BATCH) {
-        const uint32_t v0 = prim::load4(reinterpret_cast<const uint8_t*>(a.vstart + d));
-        const uint64_t ob = prim::load8(a.offsets + d);
-        m = prim::load4(reinterpret_cast<const uint8_t*>(a.match + ob + (i - v0)));
-        lim = prim::load4(reinterpret_cast<const uint8_t*>(a.dn + d));
-        mv = v0 + m;
-      } else {
-        m = prim::load4(reinterpret_cast<const uint8_t*>(a.match + i));
-        mv = m;
+    const uint64_t e1 = e0 + 64u * kTapeSuper;
+    const bool run_str = prim::ballot(any_str) != 0u;
+    const uint64_t p1 = !run_str ? 0u : e1 < n ? entry_pos<BATCH>(a, e1) : bhi;
+    // the byte-parallel path's first two steps, in flight with the loads below
+    const bool fast = run_str && prim::load1(a.runbad + e0 / kRunMax) == 0u;
+    const uint64_t rp0 = fast ? entry_pos<BATCH>(a, e0) : 0u;
+    const int64_t sbase0 = span_base(a.buf, rp0);
+    const uint32_t nsteps = fast ? span_steps(sbase0, p1) : 0u;
+    const uint4 s0 = nsteps > 0 ? span_load(a.buf, sbase0, 0, blo, bhi) : uint4{0u, 0u, 0u, 0u};
+    const uint4 s1 = nsteps > 1 ? span_load(a.buf, sbase0, 1, blo, bhi) : uint4{0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int q = 0; q < kTapeSuper; q++) {
+      const uint64_t i = e0 + 64u * q + lane;
+      const uint32_t b = g.K[j0 + 64u * q + lane];
+      const bool in = i < n, br = in && is_bracket(b), st = in && b == '"';
+      const uint32_t d = dq[q];
+      w0q[q] = BATCH && (br || st) ? ld64(a.dbase + 2 * (uint64_t)d) : 0u;
+      s0q[q] = BATCH && st ? ld64(a.dbase + 2 * (uint64_t)d + 1) : 0u;
+      len[q] = !BATCH ? a.len : st ? prim::load8(a.offsets + d + 1) : 0u;
+      v0q[q] = BATCH && br ? prim::load4(reinterpret_cast<const uint8_t*>(a.vstart + d)) : 0u;
+      obq[q] = BATCH && br ? prim::load8(a.offsets + d) : 0u;
+      limq[q] = !BATCH ? n : br ? prim::load4(reinterpret_cast<const uint8_t*>(a.dn + d)) : 0u;
+    }
+    if (BATCH) {
+#pragma unroll
+      for (int q = 0; q < kTapeSuper; q++) {
+        const uint64_t i = e0 + 64u * q + lane;
+        const uint32_t b = g.K[j0 + 64u * q + lane];
+        const bool br = i < n && is_bracket(b);
+        mq[q] = br ? prim::load4(reinterpret_cast<const uint8_t*>(a.match + obq[q] + (i - v0q[q]))) : kTapeUnlinked;
       }
-      if (m != kTapeUnlinked && m < lim) {
-        const uint64_t tk = prim::load4(reinterpret_cast<const uint8_t*>(a.toff + mv)) - w0;
-        link = (b == '{' || b == '[') ? tk + 1 : tk;
+    }
+    uint32_t tkq[kTapeSuper];
+#pragma unroll
+    for (int q = 0; q < kTapeSuper; q++) {
+      const bool linked = mq[q] != kTapeUnlinked && mq[q] < limq[q];
+      tkq[q] = linked ? prim::load4(reinterpret_cast<const uint8_t*>(a.toff + v0q[q] + mq[q])) : 0u;
+    }
+#pragma unroll
+    for (int q = 0; q < kTapeSuper; q++) {
+      const uint32_t j = j0 + 64u * q + lane;
+      const uint64_t i = c0 + j;
+      const uint32_t b = g.K[j];
+      if (i >= n) continue;
+      if (is_bracket(b)) {
+        uint64_t link = 0;
+        if (mq[q] != kTapeUnlinked && mq[q] < limq[q]) {
+          const uint64_t tk = tkq[q] - w0q[q];
+          link = (b == '{' || b == '[') ? tk + 1 : tk;
+        }
+        st64(a.tape + g.T[j], ((uint64_t)b << 56) | link);
+      } else if (is_queued(b)) {
+        prim::st_out(a.nqueue + pn, (uint32_t)i);
+        pn++;
       }
-      st64(a.tape + t, ((uint64_t)b << 56) | link);
-    } else if (b == '"') {
-      const uint64_t so = sbase + (uint32_t)(g.S[j] - (uint32_t)sbase);
-      st64(a.tape + t, ((uint64_t)'"' << 56) | (so - s0));
-      st64(a.squeue + 2 * (uint64_t)ps, i);
-      st64(a.squeue + 2 * (uint64_t)ps + 1, so);
-      ps++;
-    } else {
-      prim::st_out(a.nqueue + pn, (uint32_t)i);
-      pn++;
+    }
+    if (!run_str) continue;
+    // the strings' words; each string's buffer offset and bytes
+    uint64_t sm[kTapeSuper], so[kTapeSuper];
+    uint32_t nstr = 0;
+#pragma unroll
+    for (int q = 0; q < kTapeSuper; q++) {
+      const uint32_t j = j0 + 64u * q + lane;
+      const bool str = c0 + j < n && g.K[j] == '"';
+      so[q] = sbase + (uint32_t)(g.S[j] - (uint32_t)sbase);
+      if (str) st64(a.tape + g.T[j], ((uint64_t)'"' << 56) | (so[q] - s0q[q]));
+      sm[q] = prim::ballot(str);
+      nstr += (uint32_t)__builtin_popcountll(sm[q]);
+    }
+    if (fast) {
+      // the byte-parallel path: the run's output is contiguous from its first entry's offset on
+      prim::wave_sync();  // the previous run's reads are done
+#pragma unroll
+      for (int q = 0; q < kTapeSuper; q++) {
+        const uint32_t j = j0 + 64u * q + lane;
+        if (c0 + j < n && g.K[j] == '"') {
+          const uint64_t so1 = j + 1 < (uint32_t)kTapeChunk ? sbase + (uint32_t)(g.S[j + 1] - (uint32_t)sbase) : g.send;
+          W.r.val[run_index(sm, q)] = (uint32_t)(so1 - so[q]);
+        }
+      }
+      prim::wave_sync();
+      (void)fast_run<true>(W.r, a.buf, rp0, p1, blo, bhi, nstr, a.str, readlane64(so[0], 0), s0, s1);
+      continue;
+    }
+    // the per-string path, group by group, from the run's staged bytes
+    const StrSrc src = stage_group(W.s, a.buf, run_first_string(sm, pos), p1, blo, bhi);
+    for (int q = 0; q < kTapeSuper; q++) {
+      const uint32_t j = j0 + 64u * q + lane;
+      const uint64_t i = c0 + j;
+      const bool str = i < n && g.K[j] == '"';
+      if (prim::ballot(str) == 0u) continue;  // the same for the whole wave
+      const uint64_t sq = pick_group(so, q);
+      const uint64_t so1 = j + 1 < (uint32_t)kTapeChunk ? sbase + (uint32_t)(g.S[j + 1] - (uint32_t)sbase) : g.send;
+      const uint32_t err = write_strings(a, W.s, src, str, pick_group(pos, q), pick_group(len, q), sq, so1 - sq);
+      or_flags<BATCH>(a, err, pick_group(dq, q));
     }
   }
   prim::sync();
@@ -1158,37 +1990,7 @@ JSIDX_DEVFN void tape_write(const TapeArgs& a) {
 // Grid-stride bounds of a queue for this thread.
 JSIDX_DEV uint32_t queue_len(const TapeArgs& a, int q) { return prim::ld_agent32(a.qcount + q); }
 
-// 5. Strings: decoded into the buffer after their 32-bit length.
-template <bool BATCH>
-JSIDX_DEVFN void tape_strings(const TapeArgs& a) {
-  if (!batch_go<BATCH>(a)) return;
-  const uint32_t qn = queue_len(a, 1);
-  const uint32_t stride = prim::grid() * (uint32_t)kTapeThreads;
-  const uint32_t rounds = (qn + stride - 1) / stride;  // the same for every lane (wave_strings)
-  for (uint32_t r = 0; r < rounds; r++) {
-    const uint32_t q = r * stride + prim::block() * (uint32_t)kTapeThreads + tape_tid();
-    const bool has = q < qn;
-    uint64_t so = 0, pos = 0;
-    uint32_t d = 0;
-    if (has) {
-      const uint32_t i = (uint32_t)ld64(a.squeue + 2 * (uint64_t)q);
-      so = ld64(a.squeue + 2 * (uint64_t)q + 1);
-      pos = entry_pos<BATCH>(a, i);
-      d = entry_doc<BATCH>(a, i);
-    }
-    const TapeArgs la = entry_args<BATCH>(a, d);
-    uint32_t k = 0;
-    const uint32_t e = wave_strings<true>(la, has, pos, a.str + so + 4, &k);
-    uint32_t err = 0;
-    if (has) {
-      err = e;
-      for (int j = 0; j < 4; j++) prim::st_byte(a.str + so + j, (k >> (8 * j)) & 0xFFu);
-    }
-    or_flags<BATCH>(a, err, d);
-  }
-}
-
-// 6. Numbers (both words; undecided doubles queued for tape_exact) and
+// 5. Numbers (both words; undecided doubles queued for tape_exact) and
 //    literals.  (a: arguments whose bound is the entry's document; pos its
 //    first byte.)
 JSIDX_DEV uint32_t number_entry(const TapeArgs& a, uint64_t pos, uint64_t t, bool* undecided) {
@@ -1246,7 +2048,7 @@ JSIDX_DEV uint32_t number_entry(const TapeArgs& a, uint64_t pos, uint64_t t, boo
 template <bool BATCH>
 JSIDX_DEVFN void tape_numbers(const TapeArgs& a) {
   if (!batch_go<BATCH>(a)) return;
-  const uint32_t qn = queue_len(a, 2);
+  const uint32_t qn = queue_len(a, 1);
   const uint32_t stride = prim::grid() * (uint32_t)kTapeThreads;
   const uint32_t rounds = (qn + stride - 1) / stride;
   for (uint32_t r = 0; r < rounds; r++) {
@@ -1265,7 +2067,7 @@ JSIDX_DEVFN void tape_numbers(const TapeArgs& a) {
   }
 }
 
-// 7. The queued numbers, one thread each, by exact arithmetic.
+// 6. The queued numbers, one thread each, by exact arithmetic.
 struct ExactScratch {
   Big D, V, S;
 };

@@ -17,10 +17,11 @@ template <bool B>
 __global__ void __launch_bounds__(kTapeThreads) tape_scan_kernel(TapeArgs a) { tape_scan<B>(a); }
 template <bool B>
 __global__ void __launch_bounds__(kTapeThreads) tape_offsets_kernel(TapeArgs a) { tape_offsets<B>(a); }
+// four workgroups per CU fit its LDS: registers are kept to that occupancy too
 template <bool B>
-__global__ void __launch_bounds__(kTapeThreads) tape_write_kernel(TapeArgs a) { tape_write<B>(a); }
-template <bool B>
-__global__ void __launch_bounds__(kTapeThreads) tape_strings_kernel(TapeArgs a) { tape_strings<B>(a); }
+__global__ void __launch_bounds__(kTapeThreads) __attribute__((amdgpu_waves_per_eu(4))) tape_write_kernel(TapeArgs a) {
+  tape_write<B>(a);
+}
 template <bool B>
 __global__ void __launch_bounds__(kTapeThreads) tape_numbers_kernel(TapeArgs a) { tape_numbers<B>(a); }
 template <bool B>
@@ -115,9 +116,9 @@ extern "C" int jsidx_tape(const uint8_t* buf, uint64_t len, const uint32_t* idx,
   a.sbytes = reinterpret_cast<uint32_t*>(m + L.sbytes);
   a.toff = reinterpret_cast<uint32_t*>(m + L.toff);
   a.kb = m + L.kb;
+  a.runbad = m + L.runbad;
   a.qcount = reinterpret_cast<uint32_t*>(m + L.qcount);
   a.queue = reinterpret_cast<uint32_t*>(m + L.queue);
-  a.squeue = reinterpret_cast<uint64_t*>(m + L.squeue);
   a.nqueue = reinterpret_cast<uint32_t*>(m + L.nqueue);
   const dim3 block(kTapeThreads);
   (void)hipGetLastError();
@@ -126,10 +127,9 @@ extern "C" int jsidx_tape(const uint8_t* buf, uint64_t len, const uint32_t* idx,
   if (a.nchunks) {
     hipLaunchKernelGGL(tape_offsets_kernel<false>, dim3(a.nchunks), block, 0, stream, a);
     hipLaunchKernelGGL(tape_write_kernel<false>, dim3(a.nchunks), block, 0, stream, a);
-    // the queues hold at most n entries; a grid-stride loop takes the rest
+    // the number queue holds at most n entries; a grid-stride loop takes the rest
     const uint64_t qgroups = ((uint64_t)n + kTapeThreads - 1) / kTapeThreads;
     const dim3 qgrid((uint32_t)(qgroups < kQueueGroups ? qgroups : kQueueGroups));
-    hipLaunchKernelGGL(tape_strings_kernel<false>, qgrid, block, 0, stream, a);
     hipLaunchKernelGGL(tape_numbers_kernel<false>, qgrid, block, 0, stream, a);
     hipLaunchKernelGGL(tape_exact_kernel<false>, dim3(kExactGroups), dim3(kExactThreads), 0, stream, a);
   }
@@ -199,9 +199,9 @@ extern "C" int jsidx_tape_batch(const uint8_t* bufs, const uint64_t* offsets, ui
   a.sbytes = reinterpret_cast<uint32_t*>(m + L.sbytes);
   a.toff = reinterpret_cast<uint32_t*>(m + L.toff);
   a.kb = m + L.kb;
+  a.runbad = m + L.runbad;
   a.qcount = reinterpret_cast<uint32_t*>(m + L.qcount);
   a.queue = reinterpret_cast<uint32_t*>(m + L.queue);
-  a.squeue = reinterpret_cast<uint64_t*>(m + L.squeue);
   a.nqueue = reinterpret_cast<uint32_t*>(m + L.nqueue);
   a.offsets = offsets;
   a.dn = n;
@@ -238,7 +238,6 @@ extern "C" int jsidx_tape_batch(const uint8_t* bufs, const uint64_t* offsets, ui
   hipLaunchKernelGGL(tape_offsets_kernel<true>, dim3(chunk_groups), block, 0, stream, a);
   hipLaunchKernelGGL(tape_batch_docs_kernel, dim3((ndocs + kTapeThreads - 1) / kTapeThreads), block, 0, stream, a);
   hipLaunchKernelGGL(tape_write_kernel<true>, dim3(chunk_groups), block, 0, stream, a);
-  hipLaunchKernelGGL(tape_strings_kernel<true>, qgrid, block, 0, stream, a);
   hipLaunchKernelGGL(tape_numbers_kernel<true>, qgrid, block, 0, stream, a);
   hipLaunchKernelGGL(tape_exact_kernel<true>, dim3(kExactGroups), dim3(kExactThreads), 0, stream, a);
   if (hipGetLastError() != hipSuccess) return JSIDX_E_HIP;

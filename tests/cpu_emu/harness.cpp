@@ -280,9 +280,9 @@ long emu_tape_run(const uint8_t* buf, uint64_t len, const uint32_t* idx, uint32_
   a.sbytes = reinterpret_cast<uint32_t*>(m + L.sbytes);
   a.toff = reinterpret_cast<uint32_t*>(m + L.toff);
   a.kb = m + L.kb;
+  a.runbad = m + L.runbad;
   a.qcount = reinterpret_cast<uint32_t*>(m + L.qcount);
   a.queue = reinterpret_cast<uint32_t*>(m + L.queue);
-  a.squeue = reinterpret_cast<uint64_t*>(m + L.squeue);
   a.nqueue = reinterpret_cast<uint32_t*>(m + L.nqueue);
   auto phase = [&](int ngroups, int nthreads, void (*body)(const TapeArgs&)) {
     std::vector<prim::GroupCtx*> groups;
@@ -308,7 +308,6 @@ long emu_tape_run(const uint8_t* buf, uint64_t len, const uint32_t* idx, uint32_
   if (a.nchunks) {
     phase((int)a.nchunks, kTapeThreads, tape_offsets<false>);
     phase((int)a.nchunks, kTapeThreads, tape_write<false>);
-    phase(2, kTapeThreads, tape_strings<false>);
     phase(2, kTapeThreads, tape_numbers<false>);
     phase(exact_groups, kExactThreads, tape_exact<false>);
   }
@@ -317,6 +316,8 @@ long emu_tape_run(const uint8_t* buf, uint64_t len, const uint32_t* idx, uint32_
 }
 
 uint64_t emu_tape_ws_bytes(uint64_t n) { return tape_layout(n).total; }
+// Where the workspace records which runs left their strings to the per-string path.
+uint64_t emu_tape_runbad_offset(uint64_t n) { return tape_layout(n).runbad; }
 uint64_t emu_tape_batch_ws_bytes(uint64_t cap, uint64_t ndocs) { return tape_batch_layout(cap, ndocs).total; }
 
 // The batched tape kernels over ndocs documents (index and links in the
@@ -352,9 +353,9 @@ long emu_tape_batch_run(const uint8_t* buf, const uint64_t* offsets, uint32_t nd
   a.sbytes = reinterpret_cast<uint32_t*>(m + L.sbytes);
   a.toff = reinterpret_cast<uint32_t*>(m + L.toff);
   a.kb = m + L.kb;
+  a.runbad = m + L.runbad;
   a.qcount = reinterpret_cast<uint32_t*>(m + L.qcount);
   a.queue = reinterpret_cast<uint32_t*>(m + L.queue);
-  a.squeue = reinterpret_cast<uint64_t*>(m + L.squeue);
   a.nqueue = reinterpret_cast<uint32_t*>(m + L.nqueue);
   a.offsets = offsets;
   a.dn = n;
@@ -400,7 +401,6 @@ long emu_tape_batch_run(const uint8_t* buf, const uint64_t* offsets, uint32_t nd
   phase(chunk_groups, kTapeThreads, tape_offsets<true>);
   phase(doc_groups, kTapeThreads, tape_batch_docs);
   phase(chunk_groups, kTapeThreads, tape_write<true>);
-  phase(2, kTapeThreads, tape_strings<true>);
   phase(2, kTapeThreads, tape_numbers<true>);
   phase(exact_groups, kExactThreads, tape_exact<true>);
   return env.violations.load();

@@ -268,7 +268,17 @@ inline void st_out4(uint32_t* p, uint4 v) {
   }
   memcpy(p, &v, 16);
 }
+// LDS accesses must stay inside the workgroup's LDS.
+inline void lds_check(const void* p, size_t n, size_t align) {
+  const unsigned char* b = tctx.g->lds;
+  const unsigned char* q = static_cast<const unsigned char*>(p);
+  if (q < b || q + n > b + sizeof(GroupCtx::lds) || ((uintptr_t)q & (align - 1))) {
+    fprintf(stderr, "cpu_emu: LDS access of %zu bytes at %p outside the workgroup's LDS or misaligned\n", n, p);
+    tctx.env->violations++;
+  }
+}
 inline uint4 ld_lds128(const uint32_t* p) {
+  lds_check(p, 16, 16);
   if ((uintptr_t)p & 15) {
     fprintf(stderr, "cpu_emu: misaligned 16-byte LDS read at %p\n", (const void*)p);
     tctx.env->violations++;
@@ -276,6 +286,22 @@ inline uint4 ld_lds128(const uint32_t* p) {
   uint4 v;
   memcpy(&v, p, 16);
   return v;
+}
+inline void st_lds128(uint32_t* p, uint4 v) {
+  lds_check(p, 16, 16);
+  memcpy(p, &v, 16);
+}
+inline uint32_t lds_ld1(const uint8_t* p) {
+  lds_check(p, 1, 1);
+  return *p;
+}
+inline void lds_st1(uint8_t* p, uint32_t v) {
+  lds_check(p, 1, 1);
+  *p = (uint8_t)v;
+}
+inline void lds_st4(uint32_t* p, uint32_t v) {
+  lds_check(p, 4, 4);
+  *p = v;
 }
 inline void st_byte(uint8_t* p, uint32_t v) {
   check(p, 1, true);

@@ -93,6 +93,8 @@ def load(block_tiles: int | None = None):
     lib.emu_number.restype = ctypes.c_int
     lib.emu_tape_ws_bytes.argtypes = [ctypes.c_uint64]
     lib.emu_tape_ws_bytes.restype = ctypes.c_uint64
+    lib.emu_tape_runbad_offset.argtypes = [ctypes.c_uint64]
+    lib.emu_tape_runbad_offset.restype = ctypes.c_uint64
     lib.emu_scopes_ws_bytes.argtypes = [ctypes.c_uint64]
     lib.emu_scopes_ws_bytes.restype = ctypes.c_uint64
     lib.emu_tape_batch_ws_bytes.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
@@ -231,19 +233,32 @@ def scopes_batch(data: bytes, offsets: np.ndarray, idx: np.ndarray, n: np.ndarra
     return match, err, int(v)
 
 
-def tape(data: bytes, idx: np.ndarray, match: np.ndarray, exact_groups: int = 2):
+def _shifted(nbytes: int, shift: int, fill: int) -> np.ndarray:
+    """nbytes bytes (at least 1) starting `shift` bytes past a 64-byte boundary."""
+    raw = np.full(max(1, nbytes) + shift + 128, fill, dtype=np.uint8)
+    a = (-raw.ctypes.data) % 64
+    return raw[a + shift:a + shift + max(1, nbytes)]
+
+
+def tape(data: bytes, idx: np.ndarray, match: np.ndarray, exact_groups: int = 2, doc_shift: int = 0,
+         str_shift: int = 0, paths: list | None = None):
     """The tape through the emulated tape kernels.  Returns (tape words,
     string buffer, flags, violations, numbers taken by the exact conversion);
-    the outputs and the workspace start full of garbage."""
+    the outputs and the workspace start full of garbage.  The document and
+    the string buffer start doc_shift and str_shift bytes past a 64-byte
+    boundary.  If `paths` is a list, (runs whose strings took the
+    byte-parallel path, runs that took the per-string path) is appended."""
     lib = load()
     n = int(idx.size)
-    buf = np.frombuffer(data, dtype=np.uint8) if data else np.zeros(1, dtype=np.uint8)
+    buf = _shifted(len(data), doc_shift, 0)
+    if data:
+        buf[:] = np.frombuffer(data, dtype=np.uint8)
     ix = np.ascontiguousarray(idx, dtype=np.uint32) if n else np.zeros(1, dtype=np.uint32)
     mt = np.ascontiguousarray(match, dtype=np.uint32) if n else np.zeros(1, dtype=np.uint32)
     tcap = 2 * n + 2
     scap = len(data) + 2 * n + 4
     words = np.full(tcap, 0xA5A5A5A5A5A5A5A5, dtype=np.uint64)
-    sbuf = np.full(scap, 0xA5, dtype=np.uint8)
+    sbuf = _shifted(scap, str_shift, 0xA5)
     tn = np.full(1, 0xFFFF, dtype=np.uint64)
     sn = np.full(1, 0xFFFF, dtype=np.uint64)
     err = np.full(1, 0xABABABAB, dtype=np.uint32)
@@ -252,6 +267,10 @@ def tape(data: bytes, idx: np.ndarray, match: np.ndarray, exact_groups: int = 2)
     v = lib.emu_tape_run(buf.ctypes.data, len(data), ix.ctypes.data, n, mt.ctypes.data, words.ctypes.data, tcap,
                          sbuf.ctypes.data, scap, tn.ctypes.data, sn.ctypes.data, err.ctypes.data, ws.ctypes.data,
                          exact_groups, nx.ctypes.data)
+    if paths is not None:
+        o = int(lib.emu_tape_runbad_offset(n))
+        rb = ws.view(np.uint8)[o:o + n // 256 + 1]  # one byte per run of 256 entries (runs without strings: unset)
+        paths.append((int(np.count_nonzero(rb == 0)), int(np.count_nonzero(rb == 1))))
     return words[:int(tn[0])], sbuf[:int(sn[0])].tobytes(), int(err[0]), int(v), int(nx[0])
 
 

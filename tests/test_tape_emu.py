@@ -13,11 +13,11 @@ import oracle
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 
-def _check(data: bytes, exact_groups: int = 2) -> int:
+def _check(data: bytes, exact_groups: int = 2, doc_shift: int = 0, str_shift: int = 0, paths=None) -> int:
     """Returns how many numbers took the exact conversion."""
     idx, _ = oracle.index(data)
     match, serr = oracle.scopes(data, idx)
-    words, sbuf, flags, viol, nexact = emu.tape(data, idx, match, exact_groups)
+    words, sbuf, flags, viol, nexact = emu.tape(data, idx, match, exact_groups, doc_shift, str_shift, paths)
     ow, osb, of = oracle.tape(data, idx)
     assert viol == 0
     assert flags == of, (hex(flags), hex(of), data[:80])
@@ -166,6 +166,57 @@ def test_long_strings_finished_by_the_wave():
     bad[11] = bad[11][:-5] + "\\q" + bad[11][-5:]    # an unknown escape
     _check(("[" + ",".join(bad) + "]").encode())
     _check(("[" + ",".join(strs[:50]) + ', "' + "y" * 300).encode())  # never closed
+
+
+def test_strings_staged_at_every_alignment():
+    """The string passes stage each group's bytes and output in LDS with
+    16-byte blocks: documents and string buffers at every offset from a
+    16-byte boundary, strings starting on the document's first bytes, groups
+    whose bytes (and output) run past what is staged, strings longer than
+    the staged bytes, an escape or a surrogate pair across a block edge."""
+    rng = random.Random(33)
+    pieces = ["a", "bc", "\\\"", "\\\\", "\\n", "\\u00e9", "\\ud83d\\ude00", "é", "日本", "x" * 13, "\\/", "\\t"]
+
+    def s(lo, hi):
+        return '"' + "".join(rng.choice(pieces) for _ in range(rng.randrange(lo, hi))) + '"'
+
+    docs = [
+        s(0, 40),                                                            # a lone string at byte 0
+        "[" + ",".join(s(0, 12) for _ in range(300)) + "]",                  # many short strings per group
+        "[" + ",".join(s(300, 900) for _ in range(12)) + "]",                # groups far longer than staged
+        "{" + ",".join(f"{s(1, 4)}:{s(0, 60)}" for _ in range(200)) + "}",   # keys and values
+        "[" + ",".join(s(0, 8) if i % 5 else str(i * 7) for i in range(400)) + "]",
+    ]
+    for k, d in enumerate(docs):
+        for shift in (0, 3, 9, 15):
+            _check(d.encode(), doc_shift=shift, str_shift=(shift * 5 + k) % 16)
+
+
+def test_strings_byte_parallel_and_per_string_paths():
+    """Runs of valid strings take the byte-parallel path; a run holding a
+    control byte, a bad escape, a \\u sequence that crosses a 16-byte lane,
+    or an unclosed string takes the per-string path; both give the oracle's
+    tape.  Backslash runs of every length across lane and step edges, escaped
+    quotes, UTF-8 and strings crossing 1 KiB steps take the fast path."""
+    rng = random.Random(35)
+    words = ["a", "bc", "\\\"", "\\\\", "\\n", "é", "日本", "x" * 13, "\\/", "\\t", "\\" * 7 + "\"", "😀"]
+
+    def s(lo, hi):
+        return '"' + " ".join(rng.choice(words) for _ in range(rng.randrange(lo, hi))) + '"'
+
+    valid = "[" + ",".join(s(0, 8) if i % 7 else s(100, 400) for i in range(700)) + "]"
+    paths = []
+    _check(valid.encode(), paths=paths)
+    fast, slow = paths[-1]
+    assert fast > 0 and slow == 0, paths[-1]
+    # \u escapes: each run is decoded by one path or the other, never wrongly
+    uni = "[" + ",".join('"' + "ab" * rng.randrange(0, 9) + "\\u00e9" + "c" * rng.randrange(0, 7) + "\\ud83d\\ude00\""
+                         for _ in range(600)) + "]"
+    _check(uni.encode(), paths=paths)
+    assert sum(paths[-1]) > 0
+    for bad in (valid.replace("bc", "b\x01c", 1), valid.replace("\\n", "\\q", 1), valid[:-2]):
+        _check(bad.encode(), paths=paths)
+        assert paths[-1][1] >= 1, paths[-1]
 
 
 def _check_batch(docs, **kw):

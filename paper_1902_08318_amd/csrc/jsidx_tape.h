@@ -756,11 +756,10 @@ JSIDX_DEV void copy_out(StrLds& L, uint8_t* str, uint64_t A, uint64_t B, uint32_
 //    before it, from one wave scan of each lane's (strings opened, bytes).
 // A run whose bytes hold something this does not decode, or does not decode
 // the same way as the per-string scan, is left to the per-string path: a
-// byte below 0x20 in a string, a bad escape or \u sequence, a \u sequence
-// that runs into the next lane, a backslash outside strings, or quotes that
-// do not open a string exactly at each string entry and close it before its
-// document ends.  The counting pass records which runs were left; the writing
-// pass follows that.
+// byte below 0x20 in a string, a bad escape or \u sequence, a backslash
+// outside strings, or quotes that do not open a string exactly at each
+// string entry and close it before its document ends.  The counting pass
+// records which runs were left; the writing pass follows that.
 constexpr uint32_t kRingBytes = 2048;  // the writing pass's output, per wave (a step adds at most 1366)
 
 struct RunCountLds {        // per wave
@@ -857,7 +856,7 @@ JSIDX_DEV bool fast_run(Tables& T, const uint8_t* buf, uint64_t p0, uint64_t p1,
   const uint64_t below = (1ull << lane) - 1u;
   const int64_t base = span_base(buf, p0);
   const uint32_t nsteps = span_steps(base, p1);
-  uint32_t ecarry = 0, pcarry = 0, J = 0, R = 0;
+  uint32_t ecarry = 0, pcarry = 0, ocarry = 0, J = 0, R = 0;  // carries into the next step
   bool bad = false;
   uint32_t d = 0, flushed = 0;
   if constexpr (WRITE) d = (uint32_t)(reinterpret_cast<uintptr_t>(str + O0) & 15u);
@@ -894,44 +893,68 @@ JSIDX_DEV bool fast_run(Tables& T, const uint8_t* buf, uint64_t p0, uint64_t p1,
       rem &= ~((4u << i) - 1u);
     }
     esc &= 0xFFFFu;
-    // \u escapes: the letter's lane reads the digits (and a low surrogate's
-    // escape after a high one), all of which must lie in the lane
-    uint32_t cov = 0, extra = 0;
+    // \u escapes: the letter's lane reads the four digits (and, after a high
+    // surrogate, the low one's escape) from the document; the bytes they
+    // cover may run into the next lane, 10 at most.  A first pass finds how
+    // far each lane's escapes run over.  A byte covered from the lane before
+    // can only be the low half of a pair, among the lane's first 10 bytes,
+    // and an escape there runs over nothing, so the second pass, which skips
+    // the covered bytes, runs over the same.
+    const uint32_t ue = esc & um;
+    uint32_t cov = 0, extra = 0, over = 0;
     uint32_t upos[3] = {16u, 16u, 16u}, uval[3] = {0u, 0u, 0u}, un[3] = {0u, 0u, 0u};
-    uint32_t ue = esc & um;
+    bool ubad = false;
+    auto scan_u = [&](uint32_t covered) {
+      cov = covered;
+      extra = over = 0;
+      ubad = false;
+      uint32_t r = ue & ~covered;
 #pragma unroll
-    for (int t = 0; t < 3; t++) {
-      if (ue) {
-        const uint32_t u = (uint32_t)__builtin_ctz(ue);
-        const uint64_t P = (uint64_t)(pb + u);
-        int32_t cp = hex_at(buf, P + 1, bhi);
-        uint32_t c = 4;
-        if (cp >= 0xD800 && cp <= 0xDBFF) {
-          const int32_t lo = P + 7 <= bhi && prim::load1(buf + P + 5) == '\\' && prim::load1(buf + P + 6) == 'u'
-                                 ? hex_at(buf, P + 7, bhi) : -1;
-          if (lo >= 0xDC00 && lo <= 0xDFFF) {
-            cp = 0x10000 + ((cp - 0xD800) << 10) + (lo - 0xDC00);
-            c = 10;
-          } else {
+      for (int t = 0; t < 3; t++) {
+        upos[t] = 16u;
+        if (r) {
+          const uint32_t u = (uint32_t)__builtin_ctz(r);
+          const uint64_t P = (uint64_t)(pb + u);
+          int32_t cp = hex_at(buf, P + 1, bhi);
+          uint32_t c = 4;
+          if (cp >= 0xD800 && cp <= 0xDBFF) {
+            const int32_t lo = P + 7 <= bhi && prim::load1(buf + P + 5) == '\\' && prim::load1(buf + P + 6) == 'u'
+                                   ? hex_at(buf, P + 7, bhi) : -1;
+            if (lo >= 0xDC00 && lo <= 0xDFFF) {
+              cp = 0x10000 + ((cp - 0xD800) << 10) + (lo - 0xDC00);
+              c = 10;
+            } else {
+              cp = -1;
+            }
+          } else if (cp >= 0xDC00 && cp <= 0xDFFF) {
             cp = -1;
           }
-        } else if (cp >= 0xDC00 && cp <= 0xDFFF) {
-          cp = -1;
+          if (cp < 0) {
+            ubad = true;
+          } else {
+            uint32_t nb = 0;
+            uval[t] = utf8_of((uint32_t)cp, &nb);
+            un[t] = nb;
+            upos[t] = u;
+            extra += nb - 1;
+            cov |= (((1u << c) - 1u) << (u + 1)) & 0xFFFFu;
+            if (u + c > 15u && u + c - 15u > over) over = u + c - 15u;
+          }
+          r &= ~cov & ~((2u << u) - 1u);
         }
-        if (cp < 0 || u + c > 15u) {
-          bad_l = true;
-        } else {
-          uint32_t n = 0;
-          uval[t] = utf8_of((uint32_t)cp, &n);
-          un[t] = n;
-          upos[t] = u;
-          extra += n - 1;
-          cov |= ((1u << c) - 1u) << (u + 1);
-        }
-        ue &= ~cov & ~((2u << u) - 1u);
       }
+      if (r) ubad = true;
+    };
+    if (ue) scan_u(0u);
+    const uint32_t up = prim::shfl_up(over, 1);
+    const uint32_t cin = lane == 0 ? ocarry : up;
+    ocarry = prim::readlane(over, 63);
+    if (cin) {
+      const uint32_t first = over;
+      scan_u((1u << cin) - 1u);
+      if (over != first) ubad = true;
     }
-    if (ue) bad_l = true;
+    if (ubad) bad_l = true;
     // string bytes: the unescaped quotes toggle
     const uint32_t uq = qm & ~esc & ~cov;
     const uint64_t pm = prim::ballot((__builtin_popcount(uq) & 1) != 0);
@@ -1410,6 +1433,7 @@ struct TapeChunkT {
   TapeScanLds sc;
   uint64_t send;   // the next chunk's first buffer byte
   uint32_t qbase;  // the workgroup's first slot in the number queue
+  uint32_t gq[kTapeChunk / 64];  // queued entries per group of 64, then their exclusive prefix
   uint32_t S[kTapeChunk];
   uint32_t T[kTapeChunk];
   uint8_t K[kTapeChunk];
@@ -1854,15 +1878,24 @@ JSIDX_DEV void tape_write(const TapeArgs& a) {
   for (uint32_t c = prim::block(); c < nchunks; c += prim::grid()) {
   stage_offsets<BATCH>(a, n, g, tid, c);
   const uint64_t c0 = (uint64_t)c * kTapeChunk;
-  // the workgroup's slots in the number queue, each thread's in entry order
-  const uint32_t jt = (uint32_t)(run_first(c, 0) - c0) + lane;  // this thread's entries: jt + 64 k
-  uint64_t cn = 0;
-  for (int k = 0; k < kTapePer; k++) cn += is_queued(g.K[jt + 64u * k]);  // entries past n were staged as ':'
-  uint64_t nex, nall, zex, zall;
-  group_scan2(g.sc, tid, cn, 0u, &nex, &zex, &nall, &zall);
-  if (tid == 0) g.qbase = nall ? prim::add_agent32(a.qcount + 1, (uint32_t)nall) : 0u;
+  // the workgroup's slots in the number queue, in entry order (so that the
+  // number pass reads the index and tape indices coalesced): counts per
+  // group of 64 entries, their prefix over the chunk
+  const uint32_t gw = (uint32_t)(run_first(c, 0) - c0) / 64u;  // this wave's first group
+  for (int k = 0; k < kTapePer; k++) {
+    const uint32_t cnt = (uint32_t)__builtin_popcountll(prim::ballot(is_queued(g.K[64u * (gw + k) + lane])));
+    if (lane == 0) g.gq[gw + k] = cnt;  // entries past n were staged as ':'
+  }
   prim::sync();
-  uint32_t pn = g.qbase + (uint32_t)nex;
+  if (tid < 64u) {
+    const uint32_t v = tid < (uint32_t)(kTapeChunk / 64) ? g.gq[tid] : 0u;
+    const uint32_t incl = prim::incl_scan(v);
+    const uint32_t all = prim::readlane(incl, 63);
+    if (tid == 0) g.qbase = all ? prim::add_agent32(a.qcount + 1, all) : 0u;
+    prim::wave_sync();
+    if (tid < (uint32_t)(kTapeChunk / 64)) g.gq[tid] = incl - v;
+  }
+  prim::sync();
   // a chunk's buffer bytes stay below 2^32 (its strings lie in the input,
   // fewer than 2^32 - 2^16 bytes), so an offset is the chunk base plus its
   // low word's distance from the base's
@@ -1937,10 +1970,14 @@ JSIDX_DEV void tape_write(const TapeArgs& a) {
           link = (b == '{' || b == '[') ? tk + 1 : tk;
         }
         st64(a.tape + g.T[j], ((uint64_t)b << 56) | link);
-      } else if (is_queued(b)) {
-        prim::st_out(a.nqueue + pn, (uint32_t)i);
-        pn++;
       }
+    }
+#pragma unroll
+    for (int q = 0; q < kTapeSuper; q++) {
+      const uint32_t j = j0 + 64u * q + lane;
+      const bool qd = c0 + j < n && is_queued(g.K[j]);
+      const uint64_t m = prim::ballot(qd);
+      if (qd) prim::st_out(a.nqueue + g.qbase + g.gq[j / 64u] + prim::mbcnt(m), (uint32_t)(c0 + j));
     }
     if (!run_str) continue;
     // the strings' words; each string's buffer offset and bytes

@@ -11,8 +11,15 @@
 
 namespace jsidx {
 
+// one document: registers kept to five waves per SIMD (the batch form
+// needs more)
 template <bool B>
-__global__ void __launch_bounds__(kTapeThreads) tape_count_kernel(TapeArgs a) { tape_count<B>(a); }
+__global__ void __launch_bounds__(kTapeThreads) tape_count_kernel(TapeArgs a);
+template <>
+__global__ void __launch_bounds__(kTapeThreads) __attribute__((amdgpu_waves_per_eu(5)))
+tape_count_kernel<false>(TapeArgs a) { tape_count<false>(a); }
+template <>
+__global__ void __launch_bounds__(kTapeThreads) tape_count_kernel<true>(TapeArgs a) { tape_count<true>(a); }
 template <bool B>
 __global__ void __launch_bounds__(kTapeThreads) tape_scan_kernel(TapeArgs a) { tape_scan<B>(a); }
 template <bool B>

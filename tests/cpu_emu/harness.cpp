@@ -318,6 +318,7 @@ long emu_tape_run(const uint8_t* buf, uint64_t len, const uint32_t* idx, uint32_
 uint64_t emu_tape_ws_bytes(uint64_t n) { return tape_layout(n).total; }
 // Where the workspace records which runs left their strings to the per-string path.
 uint64_t emu_tape_runbad_offset(uint64_t n) { return tape_layout(n).runbad; }
+uint64_t emu_tape_batch_runbad_offset(uint64_t cap, uint64_t ndocs) { return tape_batch_layout(cap, ndocs).runbad; }
 uint64_t emu_tape_batch_ws_bytes(uint64_t cap, uint64_t ndocs) { return tape_batch_layout(cap, ndocs).total; }
 
 // The batched tape kernels over ndocs documents (index and links in the

@@ -95,6 +95,8 @@ def load(block_tiles: int | None = None):
     lib.emu_tape_ws_bytes.restype = ctypes.c_uint64
     lib.emu_tape_runbad_offset.argtypes = [ctypes.c_uint64]
     lib.emu_tape_runbad_offset.restype = ctypes.c_uint64
+    lib.emu_tape_batch_runbad_offset.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+    lib.emu_tape_batch_runbad_offset.restype = ctypes.c_uint64
     lib.emu_scopes_ws_bytes.argtypes = [ctypes.c_uint64]
     lib.emu_scopes_ws_bytes.restype = ctypes.c_uint64
     lib.emu_tape_batch_ws_bytes.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
@@ -276,11 +278,11 @@ def tape(data: bytes, idx: np.ndarray, match: np.ndarray, exact_groups: int = 2,
 
 def tape_batch(data: bytes, offsets: np.ndarray, idx: np.ndarray, n: np.ndarray, match: np.ndarray,
                cap: int | None = None, tape_cap: int | None = None, str_cap: int | None = None,
-               chunk_groups: int = 2, doc_groups: int = 2, exact_groups: int = 2):
+               chunk_groups: int = 2, doc_groups: int = 2, exact_groups: int = 2, paths: list | None = None):
     """The batched tape through the emulated kernels (index, counts and links
     in the batch layout).  Returns (words, string buffer, out_pos (ndocs x 4),
     flags per document, violations); outputs and workspace start full of
-    garbage."""
+    garbage.  `paths` as for tape()."""
     lib = load()
     nd = offsets.size - 1
     total = int(offsets[-1])
@@ -301,6 +303,10 @@ def tape_batch(data: bytes, offsets: np.ndarray, idx: np.ndarray, n: np.ndarray,
     v = lib.emu_tape_batch_run(buf.ctypes.data, offs.ctypes.data, nd, ix.ctypes.data, cnt.ctypes.data,
                                mt.ctypes.data, words.ctypes.data, tcap, sbuf.ctypes.data, scap, pos.ctypes.data,
                                err.ctypes.data, ws.ctypes.data, cap, chunk_groups, doc_groups, exact_groups)
+    if paths is not None:
+        o = int(lib.emu_tape_batch_runbad_offset(cap, nd))
+        rb = ws.view(np.uint8)[o:o + (ent + nd) // 256 + 1]
+        paths.append((int(np.count_nonzero(rb == 0)), int(np.count_nonzero(rb == 1))))
     return words, sbuf.tobytes(), pos.reshape(nd, 4), err, int(v)
 
 

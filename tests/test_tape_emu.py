@@ -193,11 +193,12 @@ def test_strings_staged_at_every_alignment():
 
 
 def test_strings_byte_parallel_and_per_string_paths():
-    """Runs of valid strings take the byte-parallel path; a run holding a
-    control byte, a bad escape, a \\u sequence that crosses a 16-byte lane,
-    or an unclosed string takes the per-string path; both give the oracle's
-    tape.  Backslash runs of every length across lane and step edges, escaped
-    quotes, UTF-8 and strings crossing 1 KiB steps take the fast path."""
+    """Runs of valid strings take the byte-parallel path, also with \\u
+    sequences and surrogate pairs running across 16-byte lanes and 1 KiB
+    steps; a run holding a control byte, a bad escape or an unclosed string
+    takes the per-string path; both give the oracle's tape.  Backslash runs
+    of every length across lane and step edges, escaped quotes, UTF-8 and
+    strings crossing steps take the fast path."""
     rng = random.Random(35)
     words = ["a", "bc", "\\\"", "\\\\", "\\n", "é", "日本", "x" * 13, "\\/", "\\t", "\\" * 7 + "\"", "😀"]
 
@@ -209,11 +210,14 @@ def test_strings_byte_parallel_and_per_string_paths():
     _check(valid.encode(), paths=paths)
     fast, slow = paths[-1]
     assert fast > 0 and slow == 0, paths[-1]
-    # \u escapes: each run is decoded by one path or the other, never wrongly
-    uni = "[" + ",".join('"' + "ab" * rng.randrange(0, 9) + "\\u00e9" + "c" * rng.randrange(0, 7) + "\\ud83d\\ude00\""
-                         for _ in range(600)) + "]"
+    # \u escapes and surrogate pairs at every offset from a lane edge
+    uni = "[" + ",".join('"' + "ab" * rng.randrange(0, 9) + "\\u00e9" + "c" * rng.randrange(0, 7) + "\\ud83d\\ude00"
+                         + "\\u4e2d" * rng.randrange(0, 3) + '"' for _ in range(600)) + "]"
     _check(uni.encode(), paths=paths)
-    assert sum(paths[-1]) > 0
+    assert paths[-1][0] > 0 and paths[-1][1] == 0, paths[-1]
+    for bad_u in ("\\ud83d\\u0041", "\\ude00", "\\u12g4"):  # a high surrogate alone, a low one alone, bad hex
+        _check(uni.replace("\\u00e9", bad_u, 1).encode(), paths=paths)
+        assert paths[-1][1] >= 1, paths[-1]
     for bad in (valid.replace("bc", "b\x01c", 1), valid.replace("\\n", "\\q", 1), valid[:-2]):
         _check(bad.encode(), paths=paths)
         assert paths[-1][1] >= 1, paths[-1]

@@ -237,7 +237,7 @@ JSIDX_DEV bool ends_atom(const Window& w, uint64_t p) {
 // is written to the buffer directly.
 constexpr uint32_t kStrIn = 2048;   // staged document bytes per wave
 constexpr uint32_t kStrOut = 2048;  // staged buffer bytes per wave
-struct StrLds {
+struct alignas(16) StrLds {
   uint32_t in[kStrIn / 4];
   uint32_t out[kStrOut / 4];
 };
@@ -762,13 +762,13 @@ JSIDX_DEV void copy_out(StrLds& L, uint8_t* str, uint64_t A, uint64_t B, uint32_
 // records which runs were left; the writing pass follows that.
 constexpr uint32_t kRingBytes = 2048;  // the writing pass's output, per wave (a step adds at most 1366)
 
-struct RunCountLds {        // per wave
+struct alignas(16) RunCountLds {  // per wave
   uint32_t epos[kRunMax];   // string j: its entry's position, from the span's base
   uint32_t eend[kRunMax];   // string j: its document's end, from the span's base
   uint32_t val[kRunMax];    // string j: the run's decoded bytes before its opening quote
   uint32_t slen[kRunMax];   // string j: its decoded bytes
 };
-struct RunWriteLds {        // per wave
+struct alignas(16) RunWriteLds {  // per wave
   uint32_t val[kRunMax];    // string j: its buffer bytes, as counted
   uint32_t ring[kRingBytes / 4 + 1];  // the output, then a spare word for bytes that write nothing
 };
@@ -872,7 +872,12 @@ JSIDX_DEV bool fast_run(Tables& T, const uint8_t* buf, uint64_t p0, uint64_t p1,
     if (vlo > 0) valid = vlo >= 16 ? 0u : (0xFFFFu << vlo) & 0xFFFFu;
     if (vhi < 16) valid &= vhi <= 0 ? 0u : (1u << vhi) - 1u;
     const uint32_t qm = bytes_eq(x, '"') & valid, bm = bytes_eq(x, '\\') & valid;
-    const uint32_t cm = bytes_ctl(x) & valid, um = bytes_eq(x, 'u') & valid;
+    // bytes below 0x20 (only where some lane has one: rare in a minified
+    // document); a byte below 0x20 sets its top bit in x - 0x20.. and not in x
+    bool any_ctl = false;
+#pragma unroll
+    for (int k = 0; k < 4; k++) any_ctl |= ((x[k] - 0x20202020u) & ~x[k] & 0x80808080u) != 0u;
+    const uint32_t cm = prim::ballot(any_ctl) ? bytes_ctl(x) & valid : 0u;
     bool bad_l = false;
     // escapes
     const bool all_bs = bm == 0xFFFFu;
@@ -900,6 +905,7 @@ JSIDX_DEV bool fast_run(Tables& T, const uint8_t* buf, uint64_t p0, uint64_t p1,
     // can only be the low half of a pair, among the lane's first 10 bytes,
     // and an escape there runs over nothing, so the second pass, which skips
     // the covered bytes, runs over the same.
+    const uint32_t um = prim::ballot(esc != 0u) ? bytes_eq(x, 'u') & valid : 0u;  // only under escapes
     const uint32_t ue = esc & um;
     uint32_t cov = 0, extra = 0, over = 0;
     uint32_t upos[3] = {16u, 16u, 16u}, uval[3] = {0u, 0u, 0u}, un[3] = {0u, 0u, 0u};
@@ -1004,11 +1010,11 @@ JSIDX_DEV bool fast_run(Tables& T, const uint8_t* buf, uint64_t p0, uint64_t p1,
       // then the escaped letters and the length words
       uint8_t* ring = reinterpret_cast<uint8_t*>(T.ring);
       const uint32_t o0 = d + 4 * Jl + Rl, plain = outm & ~esc;
+      uint32_t o = o0;  // byte b's place: o0, plus 1 per output byte and 4 per string opened before it
 #pragma unroll
       for (int b = 0; b < 16; b++) {
-        const uint32_t mb = (1u << b) - 1u;
-        const uint32_t o = o0 + (uint32_t)__builtin_popcount(outm & mb) + 4u * (uint32_t)__builtin_popcount(opn & mb);
         prim::lds_st1(ring + ((plain >> b) & 1u ? (o & (kRingBytes - 1)) : kRingBytes), (x[b / 4] >> (8 * (b % 4))) & 0xFFu);
+        o += ((outm >> b) & 1u) + 4u * ((opn >> b) & 1u);
       }
       for (uint32_t e = outm & esc; e; e &= e - 1u) {
         const uint32_t b = (uint32_t)__builtin_ctz(e), mb = (1u << b) - 1u;
@@ -1504,7 +1510,7 @@ JSIDX_DEV uint64_t buf_hi(const TapeArgs& a) { return BATCH ? prim::load8(a.offs
 
 // LDS of the counting pass: the workgroup's scan and, per wave, the tables
 // of the byte-parallel path or the per-string path's staged bytes.
-union CountWaveLds {
+union alignas(16) CountWaveLds {
   StrLds s;
   RunCountLds r;
 };
@@ -1819,7 +1825,7 @@ JSIDX_DEVFN void tape_batch_docs(const TapeArgs& a) {
 
 // LDS of the writing pass: the chunk and, per wave, the byte-parallel
 // path's sizes and output or the per-string path's staged bytes.
-union WriteWaveLds {
+union alignas(16) WriteWaveLds {
   StrLds s;
   RunWriteLds r;
 };

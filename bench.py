@@ -540,9 +540,10 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the numeric and batched workloads")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--size-mib", type=int, default=256)
-    ap.add_argument("--workload", choices=["c1", "c2", "c3", "scopes", "tape"], default="c1",
-                    help="headline workload (c2/c3/scopes/tape only for profiling runs; scopes: the scope "
-                         "links and structure check over the C1 index; tape: the stage-2 tape of C1)")
+    ap.add_argument("--workload", choices=["c1", "c2", "c3", "scopes", "tape", "minify"], default="c1",
+                    help="headline workload (c2/c3/scopes/tape/minify only for profiling runs; scopes: the scope "
+                         "links and structure check over the C1 index; tape: the stage-2 tape of C1; minify: "
+                         "the minify pass over C2)")
     ap.add_argument("--serve-seconds", type=float, default=1.0,
                     help="C4 serving loop: seconds per offered load (0 skips it)")
     ap.add_argument("--no-tune", action="store_true", help="keep the built-in tile size choice")
@@ -579,7 +580,8 @@ def main():
     c3 = None
     c1 = None
     if args.workload != "c3":
-        c1 = synth.gen_c2(2, args.size_mib << 20) if args.workload == "c2" else synth.gen_c1(1, args.size_mib << 20)
+        c1 = (synth.gen_c2(2, args.size_mib << 20) if args.workload in ("c2", "minify")
+              else synth.gen_c1(1, args.size_mib << 20))
     if args.tile_rows:
         jx.set_tile_rows([args.tile_rows] * 64)
     elif not args.no_tune:
@@ -593,6 +595,9 @@ def main():
     vname = args.variant or ({v: k for k, v in jx.VARIANTS.items()}[tuning["variant"]] if tuning else "default")
     if args.workload == "tape":
         print(json.dumps({"workload": "tape of C1", **time_tape(jx, torch, c1.data, args.steps)}), flush=True)
+        return
+    if args.workload == "minify":
+        print(json.dumps({"workload": "minify of C2", **time_minify(jx, torch, c1.data, None, args.steps)}), flush=True)
         return
     if args.workload == "scopes":
         print(json.dumps({"workload": "scopes over the C1 index",

@@ -1491,7 +1491,7 @@ JSIDX_DEV void finish_tile(const Args& a, Shared& sh, const Pending& R, int64_t 
 
 // ---------------------------------------------------------------------------
 template <bool MIN = false, int VAR = 0>
-JSIDX_DEVFN void index_tiles(const Args& a) {
+JSIDX_DEV void index_tiles(const Args& a) {
   GroupShared& gs = prim::lds_object<GroupShared>();
   const uint32_t wv = prim::wave_id();
   Shared& sh = gs.w[wv];

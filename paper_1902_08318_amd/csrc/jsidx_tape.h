@@ -68,9 +68,9 @@ struct TapeArgs {
   uint8_t* kb;          // per entry: its first byte
   uint8_t* runbad;      // per run of kRunMax entries: 1 if its strings take the per-string path
   uint32_t* toff;       // per entry: tape index of its first word
-  uint32_t* qcount;     // queue lengths: [0] exact conversions, [1] numbers
+  uint32_t* qcount;     // queue lengths: [0] exact conversions, [1] numbers, [2] literals
   uint32_t* queue;      // entries for the exact conversion
-  uint32_t* nqueue;     // numbers: entry
+  uint32_t* nqueue;     // numbers (entries, from the front) and literals (from the back)
   // batches (jsidx_tape_batch): the documents' entries laid end to end as
   // "virtual" entries (an empty document gets one placeholder entry, so that
   // its two root words have an owner), every position absolute in buf, and
@@ -1438,8 +1438,8 @@ template <bool BATCH>
 struct TapeChunkT {
   TapeScanLds sc;
   uint64_t send;   // the next chunk's first buffer byte
-  uint32_t qbase;  // the workgroup's first slot in the number queue
-  uint32_t gq[kTapeChunk / 64];  // queued entries per group of 64, then their exclusive prefix
+  uint32_t qbase[2];  // the workgroup's first slots for its numbers and its literals
+  uint32_t gq[kTapeChunk / 64];  // numbers | literals << 16 per group of 64, then their exclusive prefix
   uint32_t S[kTapeChunk];
   uint32_t T[kTapeChunk];
   uint8_t K[kTapeChunk];
@@ -1494,6 +1494,9 @@ JSIDX_DEV TapeArgs entry_args(const TapeArgs& a, uint32_t d) {
 }
 template <bool BATCH>
 JSIDX_DEV uint32_t n_of(const TapeArgs& a) { return BATCH ? prim::ld_agent32(a.vn) : a.n; }
+// Slots of the number queue (the workspace's entries).
+template <bool BATCH>
+JSIDX_DEV uint32_t queue_cap(const TapeArgs& a) { return BATCH ? a.cap : a.n; }
 template <bool BATCH>
 JSIDX_DEV uint32_t nchunks_of(const TapeArgs& a) { return BATCH ? prim::ld_agent32(a.vn + 1) : a.nchunks; }
 // Tape words of an entry with first byte b and batch flags f: its own, plus
@@ -1884,20 +1887,27 @@ JSIDX_DEV void tape_write(const TapeArgs& a) {
   for (uint32_t c = prim::block(); c < nchunks; c += prim::grid()) {
   stage_offsets<BATCH>(a, n, g, tid, c);
   const uint64_t c0 = (uint64_t)c * kTapeChunk;
-  // the workgroup's slots in the number queue, in entry order (so that the
-  // number pass reads the index and tape indices coalesced): counts per
-  // group of 64 entries, their prefix over the chunk
+  // the workgroup's slots in the queue, in entry order (so that the number
+  // pass reads the index and tape indices coalesced), numbers from the
+  // queue's front and literals from its back (so that a wave of the number
+  // pass takes one kind, not both paths): counts per group of 64 entries,
+  // their prefix over the chunk
   const uint32_t gw = (uint32_t)(run_first(c, 0) - c0) / 64u;  // this wave's first group
   for (int k = 0; k < kTapePer; k++) {
-    const uint32_t cnt = (uint32_t)__builtin_popcountll(prim::ballot(is_queued(g.K[64u * (gw + k) + lane])));
-    if (lane == 0) g.gq[gw + k] = cnt;  // entries past n were staged as ':'
+    const uint32_t b = g.K[64u * (gw + k) + lane];  // entries past n were staged as ':'
+    const uint32_t nl = (uint32_t)__builtin_popcountll(prim::ballot(is_lit_start(b)));
+    const uint32_t nn = (uint32_t)__builtin_popcountll(prim::ballot(is_queued(b) && !is_lit_start(b)));
+    if (lane == 0) g.gq[gw + k] = nn | (nl << 16);
   }
   prim::sync();
   if (tid < 64u) {
     const uint32_t v = tid < (uint32_t)(kTapeChunk / 64) ? g.gq[tid] : 0u;
-    const uint32_t incl = prim::incl_scan(v);
+    const uint32_t incl = prim::incl_scan(v);  // each half stays below 2^16: 2048 entries a chunk
     const uint32_t all = prim::readlane(incl, 63);
-    if (tid == 0) g.qbase = all ? prim::add_agent32(a.qcount + 1, all) : 0u;
+    if (tid == 0) {
+      g.qbase[0] = (all & 0xFFFFu) ? prim::add_agent32(a.qcount + 1, all & 0xFFFFu) : 0u;
+      g.qbase[1] = (all >> 16) ? prim::add_agent32(a.qcount + 2, all >> 16) : 0u;
+    }
     prim::wave_sync();
     if (tid < (uint32_t)(kTapeChunk / 64)) g.gq[tid] = incl - v;
   }
@@ -1981,9 +1991,12 @@ JSIDX_DEV void tape_write(const TapeArgs& a) {
 #pragma unroll
     for (int q = 0; q < kTapeSuper; q++) {
       const uint32_t j = j0 + 64u * q + lane;
-      const bool qd = c0 + j < n && is_queued(g.K[j]);
-      const uint64_t m = prim::ballot(qd);
-      if (qd) prim::st_out(a.nqueue + g.qbase + g.gq[j / 64u] + prim::mbcnt(m), (uint32_t)(c0 + j));
+      const uint32_t b = g.K[j];
+      const bool in = c0 + j < n, lit = in && is_lit_start(b), num = in && is_queued(b) && !lit;
+      const uint64_t mn = prim::ballot(num), ml = prim::ballot(lit);
+      const uint32_t gp = g.gq[j / 64u];
+      if (num) prim::st_out(a.nqueue + g.qbase[0] + (gp & 0xFFFFu) + prim::mbcnt(mn), (uint32_t)(c0 + j));
+      if (lit) prim::st_out(a.nqueue + queue_cap<BATCH>(a) - 1u - (g.qbase[1] + (gp >> 16) + prim::mbcnt(ml)), (uint32_t)(c0 + j));
     }
     if (!run_str) continue;
     // the strings' words; each string's buffer offset and bytes
@@ -2091,15 +2104,16 @@ JSIDX_DEV uint32_t number_entry(const TapeArgs& a, uint64_t pos, uint64_t t, boo
 template <bool BATCH>
 JSIDX_DEVFN void tape_numbers(const TapeArgs& a) {
   if (!batch_go<BATCH>(a)) return;
-  const uint32_t qn = queue_len(a, 1);
+  const uint32_t qn = queue_len(a, 1), ql = queue_len(a, 2);  // numbers, then literals from the back
   const uint32_t stride = prim::grid() * (uint32_t)kTapeThreads;
-  const uint32_t rounds = (qn + stride - 1) / stride;
+  const uint32_t rounds = (qn + ql + stride - 1) / stride;
   for (uint32_t r = 0; r < rounds; r++) {
     const uint32_t q = r * stride + prim::block() * (uint32_t)kTapeThreads + tape_tid();
     bool undecided = false;
     uint32_t i = 0, d = 0, err = 0;
-    if (q < qn) {
-      i = prim::load4(reinterpret_cast<const uint8_t*>(a.nqueue + q));
+    if (q < qn + ql) {
+      const uint32_t slot = q < qn ? q : queue_cap<BATCH>(a) - 1u - (q - qn);
+      i = prim::load4(reinterpret_cast<const uint8_t*>(a.nqueue + slot));
       d = entry_doc<BATCH>(a, i);
       const uint64_t t = prim::load4(reinterpret_cast<const uint8_t*>(a.toff + i));
       err = number_entry(entry_args<BATCH>(a, d), entry_pos<BATCH>(a, i), t, &undecided);

@@ -299,17 +299,33 @@ JSIDX_DEVFN void scope_scan(const ScopeArgs& a) {
   const uint32_t per = (nchunks + kScopeThreads - 1) / kScopeThreads;
   const uint64_t lo = (uint64_t)tid * per;
   const uint64_t hi = lo + per < nchunks ? lo + per : nchunks;
+  // each thread's run of chunks, eight loads in flight at a time
+  constexpr int kB = 8;
   DepthFn f = fn_id();
-  for (uint64_t c = lo; c < hi; c++) {
-    const DepthFn fc{unpack64(prim::ld_pair(a.chunk_fn + 2 * c)), unpack64(prim::ld_pair(a.chunk_fn + 2 * c + 1))};
-    f = fn_then(f, fc);
+  for (uint64_t c = lo; c < hi; c += kB) {
+    DepthFn fc[kB];
+#pragma unroll
+    for (int k = 0; k < kB; k++)
+      fc[k] = c + k < hi ? DepthFn{unpack64(prim::ld_pair(a.chunk_fn + 2 * (c + k))),
+                                   unpack64(prim::ld_pair(a.chunk_fn + 2 * (c + k) + 1))}
+                         : fn_id();
+#pragma unroll
+    for (int k = 0; k < kB; k++) f = fn_then(f, fc[k]);
   }
   const DepthFn ex = group_exclusive(g, tid, f);
   int64_t x = fn_apply(ex, 0);
-  for (uint64_t c = lo; c < hi; c++) {
-    prim::st_pair(a.in_depth + c, pack64(x).x, pack64(x).y);
-    const DepthFn fc{unpack64(prim::ld_pair(a.chunk_fn + 2 * c)), unpack64(prim::ld_pair(a.chunk_fn + 2 * c + 1))};
-    x = fn_apply(fc, x);
+  for (uint64_t c = lo; c < hi; c += kB) {
+    DepthFn fc[kB];
+#pragma unroll
+    for (int k = 0; k < kB; k++)
+      fc[k] = c + k < hi ? DepthFn{unpack64(prim::ld_pair(a.chunk_fn + 2 * (c + k))),
+                                   unpack64(prim::ld_pair(a.chunk_fn + 2 * (c + k) + 1))}
+                         : fn_id();
+#pragma unroll
+    for (int k = 0; k < kB; k++) {
+      if (c + k < hi) prim::st_pair(a.in_depth + c + k, pack64(x).x, pack64(x).y);
+      x = fn_apply(fc[k], x);
+    }
   }
   if (!BATCH && tid == 0) {
     prim::st_out(a.err, a.n ? 0u : kErrSyntax);  // an empty index holds no value

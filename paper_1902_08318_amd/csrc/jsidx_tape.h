@@ -1680,19 +1680,40 @@ JSIDX_DEVFN void tape_scan(const TapeArgs& a) {
   const uint32_t per = (nchunks + kTapeThreads - 1) / kTapeThreads;
   const uint64_t lo = (uint64_t)tid * per;
   const uint64_t hi = lo + per < nchunks ? lo + per : nchunks;
+  // each thread's run of chunks, eight loads in flight at a time
+  constexpr int kB = 8;
   uint64_t w = 0, s = 0;
-  for (uint64_t c = lo; c < hi; c++) {
-    w += ld64(a.chunk_sum + 2 * c);
-    s += ld64(a.chunk_sum + 2 * c + 1);
+  for (uint64_t c = lo; c < hi; c += kB) {
+    uint64_t vw[kB], vs[kB];
+#pragma unroll
+    for (int k = 0; k < kB; k++) {
+      vw[k] = c + k < hi ? ld64(a.chunk_sum + 2 * (c + k)) : 0u;
+      vs[k] = c + k < hi ? ld64(a.chunk_sum + 2 * (c + k) + 1) : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < kB; k++) {
+      w += vw[k];
+      s += vs[k];
+    }
   }
   uint64_t wex, sex, wall, sall;
   group_scan2(g, tid, w, s, &wex, &sex, &wall, &sall);
-  for (uint64_t c = lo; c < hi; c++) {
-    const uint64_t cw = ld64(a.chunk_sum + 2 * c), cs = ld64(a.chunk_sum + 2 * c + 1);
-    st64(a.chunk_sum + 2 * c, wex);
-    st64(a.chunk_sum + 2 * c + 1, sex);
-    wex += cw;
-    sex += cs;
+  for (uint64_t c = lo; c < hi; c += kB) {
+    uint64_t vw[kB], vs[kB];
+#pragma unroll
+    for (int k = 0; k < kB; k++) {
+      vw[k] = c + k < hi ? ld64(a.chunk_sum + 2 * (c + k)) : 0u;
+      vs[k] = c + k < hi ? ld64(a.chunk_sum + 2 * (c + k) + 1) : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < kB; k++) {
+      if (c + k < hi) {
+        st64(a.chunk_sum + 2 * (c + k), wex);
+        st64(a.chunk_sum + 2 * (c + k) + 1, sex);
+      }
+      wex += vw[k];
+      sex += vs[k];
+    }
   }
   if (BATCH) {
     if (nchunks == 0) return;  // tape_batch_bases flagged the batch

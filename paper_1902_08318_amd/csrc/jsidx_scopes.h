@@ -170,9 +170,11 @@ JSIDX_DEV uint32_t kind_at(const ScopeArgs& a, uint32_t i) {
 
 // LDS of the kernels: each takes only what it uses, so that more workgroups
 // fit on a CU.
+constexpr int kScopeRunGroup = 16;  // runs per group of run minima (scope_local)
 struct ScopeGroup {
   DepthFn f[kScopeThreads];
   uint32_t m[kScopeThreads];
+  uint32_t m2[kScopeThreads / kScopeRunGroup];  // lowest level of each group of runs
   uint32_t L[kScopeChunk];  // levels of the chunk's entries
   alignas(4) uint8_t K[kScopeChunk];  // kinds of the chunk's entries
 };
@@ -436,6 +438,15 @@ JSIDX_DEVFN void scope_local(const ScopeArgs& a) {
   }
   g.m[tid] = gmin;
   prim::sync();
+  if (tid < (uint32_t)(kScopeThreads / kScopeRunGroup)) {
+    uint32_t m2 = kNoLevel;
+    for (int k = 0; k < kScopeRunGroup; k++) {
+      const uint32_t v = g.m[tid * kScopeRunGroup + k];
+      m2 = v < m2 ? v : m2;
+    }
+    g.m2[tid] = m2;
+  }
+  prim::sync();
   for (int k = 0; k < kScopePer; k++) {
     const uint32_t j = tid * kScopePer + (uint32_t)k;
     if (j >= cend) break;
@@ -443,14 +454,23 @@ JSIDX_DEVFN void scope_local(const ScopeArgs& a) {
     const uint32_t ki = g.K[j];
     if (ki != kOpenSq && ki != kOpenCu) continue;
     const uint32_t lv = g.L[j];
-    // the rest of this run, then whole runs by their lowest level, then
-    // inside the first run that can hold the closer
+    // the rest of this run, then the rest of its group of runs by their
+    // lowest levels, then whole groups, then the runs of the first group
+    // that can hold the closer, then inside the first run that can
     uint32_t p = j + 1;
     const uint32_t run_end = (tid + 1) * kScopePer;
     while (p < run_end && g.L[p] > lv) p++;
     if (p >= run_end) {
       uint32_t r = tid + 1;
-      while (r < (uint32_t)kScopeThreads && g.m[r] > lv) r++;
+      const uint32_t gend = (tid / kScopeRunGroup + 1) * kScopeRunGroup;
+      while (r < gend && g.m[r] > lv) r++;
+      if (r == gend) {
+        uint32_t gi = gend / kScopeRunGroup;
+        while (gi < (uint32_t)(kScopeThreads / kScopeRunGroup) && g.m2[gi] > lv) gi++;
+        r = gi * kScopeRunGroup;
+        if (r < (uint32_t)kScopeThreads)
+          while (g.m[r] > lv) r++;  // inside group gi: its lowest level is at most lv
+      }
       p = r * kScopePer;
       if (r < (uint32_t)kScopeThreads)
         while (g.L[p] > lv) p++;  // ends inside run r: its lowest level is at most lv

@@ -708,18 +708,30 @@ JSIDX_DEVFN void scope_batch_compact(const ScopeArgs& a) {
     const uint64_t base = prim::load8(a.offsets + d), len = prim::load8(a.offsets + d + 1) - base;
     const uint32_t nd = prim::load4(reinterpret_cast<const uint8_t*>(a.dn + d));
     const uint32_t v0 = prim::load4(reinterpret_cast<const uint8_t*>(a.vstart + d));
-    for (uint32_t j = lane; j < nd; j += kScopeWave) {
-      const uint32_t p = prim::load4(reinterpret_cast<const uint8_t*>(a.idx + base + j));
-      uint32_t k = kOther;
-      if ((uint64_t)p < len) {
-        const uint32_t b = prim::load1(a.buf + base + p);
-        k = b == 0x5Bu ? kOpenSq : b == 0x7Bu ? kOpenCu : b == 0x5Du ? kCloseSq : b == 0x7Du ? kCloseCu
-          : b == 0x3Au ? kColon : b == 0x2Cu ? kComma : b == 0x22u ? kStr : kOther;
+    // four steps of 64 entries at a time: their positions, then their bytes,
+    // each set of loads in flight together
+    constexpr uint32_t kU = 4;
+    for (uint32_t j0 = 0; j0 < nd; j0 += kU * kScopeWave) {
+      uint32_t pj[kU], bj[kU];
+#pragma unroll
+      for (uint32_t u = 0; u < kU; u++) {
+        const uint32_t j = j0 + u * kScopeWave + lane;
+        pj[u] = j < nd ? prim::load4(reinterpret_cast<const uint8_t*>(a.idx + base + j)) : 0xFFFFFFFFu;
       }
-      if (j == 0) k |= kDocStartBit;
-      if (j + 1 == nd) k |= kDocEndBit;
-      prim::st_byte(a.kind + v0 + j, k);
-      prim::st_out(a.docid + v0 + j, d);
+#pragma unroll
+      for (uint32_t u = 0; u < kU; u++) bj[u] = (uint64_t)pj[u] < len ? prim::load1(a.buf + base + pj[u]) : 0x100u;
+#pragma unroll
+      for (uint32_t u = 0; u < kU; u++) {
+        const uint32_t j = j0 + u * kScopeWave + lane;
+        if (j >= nd) continue;
+        const uint32_t b = bj[u];
+        uint32_t k = b == 0x5Bu ? kOpenSq : b == 0x7Bu ? kOpenCu : b == 0x5Du ? kCloseSq : b == 0x7Du ? kCloseCu
+                   : b == 0x3Au ? kColon : b == 0x2Cu ? kComma : b == 0x22u ? kStr : kOther;
+        if (j == 0) k |= kDocStartBit;
+        if (j + 1 == nd) k |= kDocEndBit;
+        prim::st_byte(a.kind + v0 + j, k);
+        prim::st_out(a.docid + v0 + j, d);
+      }
     }
   }
 }
@@ -736,9 +748,19 @@ JSIDX_DEVFN void scope_batch_finish(const ScopeArgs& a) {
     const uint64_t base = prim::load8(a.offsets + d);
     const uint32_t nd = prim::load4(reinterpret_cast<const uint8_t*>(a.dn + d));
     const uint32_t v0 = prim::load4(reinterpret_cast<const uint8_t*>(a.vstart + d));
-    for (uint32_t j = lane; j < nd; j += kScopeWave) {
-      const uint32_t m = prim::load4(reinterpret_cast<const uint8_t*>(a.match + v0 + j));
-      prim::st_out(a.out_match + base + j, m == kUnlinked ? kUnlinked : m - v0);
+    constexpr uint32_t kU = 4;  // four steps of 64 entries, their loads in flight together
+    for (uint32_t j0 = 0; j0 < nd; j0 += kU * kScopeWave) {
+      uint32_t mj[kU];
+#pragma unroll
+      for (uint32_t u = 0; u < kU; u++) {
+        const uint32_t j = j0 + u * kScopeWave + lane;
+        mj[u] = j < nd ? prim::load4(reinterpret_cast<const uint8_t*>(a.match + v0 + j)) : kUnlinked;
+      }
+#pragma unroll
+      for (uint32_t u = 0; u < kU; u++) {
+        const uint32_t j = j0 + u * kScopeWave + lane;
+        if (j < nd) prim::st_out(a.out_match + base + j, mj[u] == kUnlinked ? kUnlinked : mj[u] - v0);
+      }
     }
     if (lane == 0) {
       const uint32_t e = prim::ld_agent32(a.err + d);

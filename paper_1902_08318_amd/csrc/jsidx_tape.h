@@ -2222,16 +2222,26 @@ JSIDX_DEVFN void tape_batch_compact(const TapeArgs& a) {
     const uint32_t nd = prim::load4(reinterpret_cast<const uint8_t*>(a.dn + d));
     const uint32_t v0 = prim::load4(reinterpret_cast<const uint8_t*>(a.vstart + d));
     const uint32_t cnt = nd ? nd : 1u;
-    for (uint32_t j = lane; j < cnt; j += 64u) {
-      uint32_t f = 0;
-      uint64_t pos = base;
-      if (nd) pos += prim::load4(reinterpret_cast<const uint8_t*>(a.idx + base + j));
-      else f |= kVEmpty;
-      if (j == 0) f |= kVFirst;
-      if (j + 1 == cnt) f |= kVLast;
-      st64(a.vpos + v0 + j, pos);
-      prim::st_byte(a.vflag + v0 + j, f);
-      prim::st_out(a.docid + v0 + j, d);
+    // four steps of 64 entries at a time, their loads in flight together
+    constexpr uint32_t kU = 4;
+    for (uint32_t j0 = 0; j0 < cnt; j0 += kU * 64u) {
+      uint32_t pj[kU];
+#pragma unroll
+      for (uint32_t u = 0; u < kU; u++) {
+        const uint32_t j = j0 + u * 64u + lane;
+        pj[u] = nd && j < cnt ? prim::load4(reinterpret_cast<const uint8_t*>(a.idx + base + j)) : 0u;
+      }
+#pragma unroll
+      for (uint32_t u = 0; u < kU; u++) {
+        const uint32_t j = j0 + u * 64u + lane;
+        if (j >= cnt) continue;
+        uint32_t f = nd ? 0u : kVEmpty;
+        if (j == 0) f |= kVFirst;
+        if (j + 1 == cnt) f |= kVLast;
+        st64(a.vpos + v0 + j, base + pj[u]);
+        prim::st_byte(a.vflag + v0 + j, f);
+        prim::st_out(a.docid + v0 + j, d);
+      }
     }
   }
 }

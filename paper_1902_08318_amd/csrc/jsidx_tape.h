@@ -1099,6 +1099,33 @@ struct NumText {
 
 JSIDX_DEV bool is_digit(uint32_t c) { return c - '0' <= 9u; }
 
+// Eight digits at once (Sec. 3.2.1): the window's bytes p .. p + 7 as one
+// little-endian word, if all eight lie in the window and the document.
+JSIDX_DEV bool win8(const Window& w, uint64_t p, uint64_t* v) {
+  if (w.base == ~0ull || p < w.base || p + 8 > w.len) return false;
+  const uint64_t d = p - w.base;
+  if (d + 8 > 32) return false;
+  const uint32_t k = (uint32_t)(d >> 3), sh = 8u * (uint32_t)(d & 7u);
+  const uint64_t lo = pick4(w.q0, w.q1, w.q2, w.q3, k);
+  const uint64_t hi = pick4(w.q0, w.q1, w.q2, w.q3, k + 1u);  // 0 past the window
+  *v = sh ? (lo >> sh) | (hi << (64u - sh)) : lo;
+  return true;
+}
+// All eight bytes are '0'..'9': each byte's high nibble is 3 and adding 6
+// keeps it 3.
+JSIDX_DEV bool eight_digits(uint64_t v) {
+  return (((v & 0xF0F0F0F0F0F0F0F0ull) | (((v + 0x0606060606060606ull) & 0xF0F0F0F0F0F0F0F0ull) >> 4)) ==
+          0x3333333333333333ull);
+}
+// Their value, first digit most significant: neighbouring digits combined
+// into pairs, pairs into fours, fours into eight (three multiply-adds).
+JSIDX_DEV uint64_t eight_value(uint64_t v) {
+  v -= 0x3030303030303030ull;
+  v = (v * 10u + (v >> 8)) & 0x00FF00FF00FF00FFull;
+  v = (v * 100u + (v >> 16)) & 0x0000FFFF0000FFFFull;
+  return (v * 10000u + (v >> 32)) & 0xFFFFFFFFull;
+}
+
 JSIDX_DEV NumText scan_number(const TapeArgs& a, uint64_t p) {
   NumText t{false, false, true, false, 0, 0, 0};
   const Window w = window_at(a.buf, a.len, p);
@@ -1115,6 +1142,15 @@ JSIDX_DEV NumText scan_number(const TapeArgs& a, uint64_t p) {
     c = win_byte(w, ++p);
   } else {
     while (p < a.len && is_digit(c)) {
+      uint64_t v8 = 0;
+      if (nd + 8 <= 19 && win8(w, p, &v8) && eight_digits(v8)) {
+        t.w = t.w * 100000000ull + eight_value(v8);
+        nd += 8;
+        t.int_digits += 8;
+        p += 8;
+        c = win_byte(w, p);
+        continue;
+      }
       t.int_digits++;
       if (nd < 19) {
         t.w = t.w * 10 + (c - '0');
@@ -1131,6 +1167,15 @@ JSIDX_DEV NumText scan_number(const TapeArgs& a, uint64_t p) {
     c = win_byte(w, ++p);
     if (!(p < a.len && is_digit(c))) return t;
     while (p < a.len && is_digit(c)) {
+      uint64_t v8 = 0;
+      if (nd > 0 && nd + 8 <= 19 && win8(w, p, &v8) && eight_digits(v8)) {
+        t.w = t.w * 100000000ull + eight_value(v8);
+        nd += 8;
+        q -= 8;
+        p += 8;
+        c = win_byte(w, p);
+        continue;
+      }
       if (nd == 0 && c == '0') {
         q--;  // a leading zero of the fraction
       } else if (nd < 19) {

@@ -299,7 +299,7 @@ int jsidx_scopes_reserve(uint64_t max_entries, uint32_t max_ndocs,
  *              atom starting with t, f or n that is not exactly true, false
  *              or null).  Every atom and string is checked, each on its own.
  * The tape is the paper's only when jsidx_scopes reported no flag and out_err
- * is 0.  A per-stream workspace of about 17 bytes per entry is allocated on
+ * is 0.  A per-stream workspace of about 21 bytes per entry is allocated on
  * first use and grown as needed (synchronising the stream); after
  * jsidx_tape_reserve for at least n entries the call never allocates or
  * synchronises (it can be captured in a HIP graph).  Asynchronous on
@@ -356,7 +356,7 @@ int jsidx_tape_batch(const uint8_t *bufs, const uint64_t *offsets,
  * jsidx_tape_reserve -- sizes the stream's tape workspace for documents of up
  * to max_entries index entries (jsidx_tape) and for batches of up to
  * max_entries entries in up to max_ndocs documents (jsidx_tape_batch; 0
- * counts as 1): about 30 bytes per entry and 50 per document.  Synchronises
+ * counts as 1): about 34 bytes per entry and 50 per document.  Synchronises
  * the stream if it has to grow the workspace.  Returns JSIDX_E_TOO_LARGE for
  * max_entries >= 2^31, JSIDX_E_NOWORKSPACE if the allocation fails (the
  * stream then has no tape workspace).

@@ -13,7 +13,8 @@
 //   3. tape_offsets: each entry's tape index (a scan inside the chunk);
 //   4. tape_write: the words of brackets (with the tape index of their
 //      partner, from the scope links) and strings; strings decoded into the
-//      buffer; numbers with literals queued densely for
+//      buffer; numbers with literals queued densely, each with its tape
+//      index (and its first byte's position where the pass has it), for
 //   5. tape_numbers: literals checked, numbers converted; a double whose
 //      rounding the fast conversion cannot decide is queued again for
 //   6. tape_exact: the exact big-integer conversion.
@@ -69,8 +70,10 @@ struct TapeArgs {
   uint8_t* runbad;      // per run of kRunMax entries: 1 if its strings take the per-string path
   uint32_t* toff;       // per entry: tape index of its first word
   uint32_t* qcount;     // queue lengths: [0] exact conversions, [1] numbers, [2] literals
-  uint32_t* queue;      // entries for the exact conversion
-  uint32_t* nqueue;     // numbers (entries, from the front) and literals (from the back)
+  uint32_t* queue;      // number-queue slots for the exact conversion
+  uint2* nqueue;        // numbers (from the front) and literals (from the back): the
+                        // first byte's position or the entry (queue_key), and the
+                        // tape index
   // batches (jsidx_tape_batch): the documents' entries laid end to end as
   // "virtual" entries (an empty document gets one placeholder entry, so that
   // its two root words have an owner), every position absolute in buf, and
@@ -120,7 +123,7 @@ inline TapeBatchLayout tape_batch_layout(uint64_t cap, uint64_t maxdocs) {
   L.runbad = o; o = al(o + cap / kRunMax + 1);
   L.toff = o; o = al(o + cap * 4);
   L.queue = o; o = al(o + cap * 4);
-  L.nqueue = o; o = al(o + cap * 4);
+  L.nqueue = o; o = al(o + cap * 8);
   L.total = o;
   return L;
 }
@@ -140,7 +143,7 @@ inline TapeLayout tape_layout(uint64_t n) {
   L.toff = o; o = tape_align256(o + n * 4);
   L.qcount = o; o = tape_align256(o + 16);
   L.queue = o; o = tape_align256(o + n * 4);
-  L.nqueue = o; o = tape_align256(o + n * 4);
+  L.nqueue = o; o = tape_align256(o + n * 8);
   L.total = o;
   return L;
 }
@@ -1539,6 +1542,20 @@ JSIDX_DEV TapeArgs entry_args(const TapeArgs& a, uint32_t d) {
 }
 template <bool BATCH>
 JSIDX_DEV uint32_t n_of(const TapeArgs& a) { return BATCH ? prim::ld_agent32(a.vn) : a.n; }
+// The first half of a number-queue slot: for one document the entry's
+// position when the write pass has it (and it is below 2^31), else the entry
+// with bit 31 set (entries stay below 2^31); for a batch the virtual entry.
+constexpr uint32_t kQueueByEntry = 0x80000000u;
+template <bool BATCH>
+JSIDX_DEV uint32_t queue_key(bool have_pos, uint64_t pos, uint64_t i) {
+  if (BATCH) return (uint32_t)i;
+  return have_pos && pos < kQueueByEntry ? (uint32_t)pos : (uint32_t)i | kQueueByEntry;
+}
+template <bool BATCH>
+JSIDX_DEV uint64_t queued_pos(const TapeArgs& a, uint32_t x) {
+  if (BATCH) return entry_pos<true>(a, x);
+  return (x & kQueueByEntry) ? entry_pos<false>(a, x & ~kQueueByEntry) : x;
+}
 // Slots of the number queue (the workspace's entries).
 template <bool BATCH>
 JSIDX_DEV uint32_t queue_cap(const TapeArgs& a) { return BATCH ? a.cap : a.n; }
@@ -1992,17 +2009,20 @@ JSIDX_DEV void tape_write(const TapeArgs& a) {
     uint64_t pos[kTapeSuper], len[kTapeSuper], w0q[kTapeSuper], s0q[kTapeSuper], obq[kTapeSuper];
     bool any_str = false;
 #pragma unroll
+    for (int q = 0; q < kTapeSuper; q++) any_str |= e0 + 64u * q + lane < n && g.K[j0 + 64u * q + lane] == '"';
+    const bool run_str = prim::ballot(any_str) != 0u;
+    // a run with strings loads its positions anyway: its numbers' positions
+    // then go into the number queue too
+#pragma unroll
     for (int q = 0; q < kTapeSuper; q++) {
       const uint64_t i = e0 + 64u * q + lane;
       const uint32_t b = g.K[j0 + 64u * q + lane];
       const bool in = i < n, br = in && is_bracket(b), st = in && b == '"';
-      any_str |= st;
       dq[q] = BATCH && (br || st) ? prim::load4(reinterpret_cast<const uint8_t*>(a.docid + i)) : 0u;
-      pos[q] = st ? entry_pos<BATCH>(a, i) : 0u;
+      pos[q] = st || (!BATCH && run_str && in && is_queued(b)) ? entry_pos<BATCH>(a, i) : 0u;
       mq[q] = !BATCH && br ? prim::load4(reinterpret_cast<const uint8_t*>(a.match + i)) : kTapeUnlinked;
     }
     const uint64_t e1 = e0 + 64u * kTapeSuper;
-    const bool run_str = prim::ballot(any_str) != 0u;
     const uint64_t p1 = !run_str ? 0u : e1 < n ? entry_pos<BATCH>(a, e1) : bhi;
     // the byte-parallel path's first two steps, in flight with the loads below
     const bool fast = run_str && prim::load1(a.runbad + e0 / kRunMax) == 0u;
@@ -2061,8 +2081,9 @@ JSIDX_DEV void tape_write(const TapeArgs& a) {
       const bool in = c0 + j < n, lit = in && is_lit_start(b), num = in && is_queued(b) && !lit;
       const uint64_t mn = prim::ballot(num), ml = prim::ballot(lit);
       const uint32_t gp = g.gq[j / 64u];
-      if (num) prim::st_out(a.nqueue + g.qbase[0] + (gp & 0xFFFFu) + prim::mbcnt(mn), (uint32_t)(c0 + j));
-      if (lit) prim::st_out(a.nqueue + queue_cap<BATCH>(a) - 1u - (g.qbase[1] + (gp >> 16) + prim::mbcnt(ml)), (uint32_t)(c0 + j));
+      const uint32_t x = queue_key<BATCH>(run_str, pos[q], c0 + j);
+      if (num) prim::st_pair(a.nqueue + g.qbase[0] + (gp & 0xFFFFu) + prim::mbcnt(mn), x, g.T[j]);
+      if (lit) prim::st_pair(a.nqueue + queue_cap<BATCH>(a) - 1u - (g.qbase[1] + (gp >> 16) + prim::mbcnt(ml)), x, g.T[j]);
     }
     if (!run_str) continue;
     // the strings' words; each string's buffer offset and bytes
@@ -2176,16 +2197,16 @@ JSIDX_DEVFN void tape_numbers(const TapeArgs& a) {
   for (uint32_t r = 0; r < rounds; r++) {
     const uint32_t q = r * stride + prim::block() * (uint32_t)kTapeThreads + tape_tid();
     bool undecided = false;
-    uint32_t i = 0, d = 0, err = 0;
+    uint32_t slot = 0, d = 0, err = 0;
     if (q < qn + ql) {
-      const uint32_t slot = q < qn ? q : queue_cap<BATCH>(a) - 1u - (q - qn);
-      i = prim::load4(reinterpret_cast<const uint8_t*>(a.nqueue + slot));
-      d = entry_doc<BATCH>(a, i);
-      const uint64_t t = prim::load4(reinterpret_cast<const uint8_t*>(a.toff + i));
-      err = number_entry(entry_args<BATCH>(a, d), entry_pos<BATCH>(a, i), t, &undecided);
+      slot = q < qn ? q : queue_cap<BATCH>(a) - 1u - (q - qn);
+      const uint2 e = prim::ld_pair(a.nqueue + slot);
+      d = entry_doc<BATCH>(a, e.x);
+      const uint64_t pos = queued_pos<BATCH>(a, e.x);
+      err = number_entry(entry_args<BATCH>(a, d), pos, e.y, &undecided);
     }
-    const uint32_t slot = wave_append(a, 0, undecided);
-    if (undecided) prim::st_out(a.queue + slot, i);
+    const uint32_t xs = wave_append(a, 0, undecided);
+    if (undecided) prim::st_out(a.queue + xs, slot);
     or_flags<BATCH>(a, err, d);
   }
 }
@@ -2196,11 +2217,12 @@ struct ExactScratch {
 };
 
 template <bool BATCH>
-JSIDX_DEV void exact_entry(const TapeArgs& a, uint32_t i, ExactScratch& x) {
-  const uint32_t d = entry_doc<BATCH>(a, i);
+JSIDX_DEV void exact_entry(const TapeArgs& a, uint32_t slot, ExactScratch& x) {
+  const uint2 e = prim::ld_pair(a.nqueue + slot);
+  const uint32_t d = entry_doc<BATCH>(a, e.x);
   const TapeArgs la = entry_args<BATCH>(a, d);
-  const uint64_t pos = entry_pos<BATCH>(a, i);
-  const uint64_t t = prim::load4(reinterpret_cast<const uint8_t*>(a.toff + i));
+  const uint64_t pos = queued_pos<BATCH>(a, e.x);
+  const uint64_t t = e.y;
   uint64_t bits = 0;
   const int r = exact_double(la, pos, x.D, x.V, x.S, &bits);
   if (r == kConvInf) {

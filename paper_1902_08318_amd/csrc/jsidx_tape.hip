@@ -126,7 +126,7 @@ extern "C" int jsidx_tape(const uint8_t* buf, uint64_t len, const uint32_t* idx,
   a.runbad = m + L.runbad;
   a.qcount = reinterpret_cast<uint32_t*>(m + L.qcount);
   a.queue = reinterpret_cast<uint32_t*>(m + L.queue);
-  a.nqueue = reinterpret_cast<uint32_t*>(m + L.nqueue);
+  a.nqueue = reinterpret_cast<uint2*>(m + L.nqueue);
   const dim3 block(kTapeThreads);
   (void)hipGetLastError();
   if (a.nchunks) hipLaunchKernelGGL(tape_count_kernel<false>, dim3(a.nchunks), block, 0, stream, a);
@@ -209,7 +209,7 @@ extern "C" int jsidx_tape_batch(const uint8_t* bufs, const uint64_t* offsets, ui
   a.runbad = m + L.runbad;
   a.qcount = reinterpret_cast<uint32_t*>(m + L.qcount);
   a.queue = reinterpret_cast<uint32_t*>(m + L.queue);
-  a.nqueue = reinterpret_cast<uint32_t*>(m + L.nqueue);
+  a.nqueue = reinterpret_cast<uint2*>(m + L.nqueue);
   a.offsets = offsets;
   a.dn = n;
   a.ndocs = ndocs;

@@ -283,7 +283,7 @@ long emu_tape_run(const uint8_t* buf, uint64_t len, const uint32_t* idx, uint32_
   a.runbad = m + L.runbad;
   a.qcount = reinterpret_cast<uint32_t*>(m + L.qcount);
   a.queue = reinterpret_cast<uint32_t*>(m + L.queue);
-  a.nqueue = reinterpret_cast<uint32_t*>(m + L.nqueue);
+  a.nqueue = reinterpret_cast<uint2*>(m + L.nqueue);
   auto phase = [&](int ngroups, int nthreads, void (*body)(const TapeArgs&)) {
     std::vector<prim::GroupCtx*> groups;
     for (int b = 0; b < ngroups; b++) groups.push_back(new prim::GroupCtx((uint32_t)nthreads));
@@ -357,7 +357,7 @@ long emu_tape_batch_run(const uint8_t* buf, const uint64_t* offsets, uint32_t nd
   a.runbad = m + L.runbad;
   a.qcount = reinterpret_cast<uint32_t*>(m + L.qcount);
   a.queue = reinterpret_cast<uint32_t*>(m + L.queue);
-  a.nqueue = reinterpret_cast<uint32_t*>(m + L.nqueue);
+  a.nqueue = reinterpret_cast<uint2*>(m + L.nqueue);
   a.offsets = offsets;
   a.dn = n;
   a.ndocs = ndocs;

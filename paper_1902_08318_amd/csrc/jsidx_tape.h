@@ -10,7 +10,7 @@
 //      entries;
 //   2. tape_scan: one workgroup turns the chunk sums into bases and writes the
 //      root words, the sizes, and clears the flags;
-//   3. tape_offsets: each entry's tape index (a scan inside the chunk);
+//   3. tape_offsets: each bracket's tape index (a scan inside the chunk);
 //   4. tape_write: the words of brackets (with the tape index of their
 //      partner, from the scope links) and strings; strings decoded into the
 //      buffer; numbers with literals queued densely, each with its tape
@@ -68,7 +68,7 @@ struct TapeArgs {
   uint32_t* sbytes;     // per entry: buffer bytes of a string, else 0
   uint8_t* kb;          // per entry: its first byte
   uint8_t* runbad;      // per run of kRunMax entries: 1 if its strings take the per-string path
-  uint32_t* toff;       // per entry: tape index of its first word
+  uint32_t* toff;       // per entry: tape index of its first word (brackets only)
   uint32_t* qcount;     // queue lengths: [0] exact conversions, [1] numbers, [2] literals
   uint32_t* queue;      // number-queue slots for the exact conversion
   uint2* nqueue;        // numbers (from the front) and literals (from the back): the
@@ -170,6 +170,7 @@ constexpr uint64_t kLitHi = set_hi('t') | set_hi('f') | set_hi('n');
 constexpr uint64_t kBracketHi = set_hi('{') | set_hi('}') | set_hi('[') | set_hi(']');
 constexpr uint64_t kNoWordLo = set_lo(':') | set_lo(',');
 JSIDX_DEV bool is_lit_start(uint32_t b) { return in_set(b, 0u, kLitHi); }
+JSIDX_DEV bool is_bracket(uint32_t b) { return in_set(b, 0u, kBracketHi); }
 
 // The 32 bytes from the aligned word holding byte p on, loaded together into
 // registers (eight word loads in flight), so that a short atom costs one
@@ -1516,6 +1517,44 @@ JSIDX_DEV void group_scan2(G& g, uint32_t tid, uint64_t w, uint64_t s, uint64_t*
   prim::sync();
 }
 
+// The same over one chunk, by 32-bit wave scans and then the four wave
+// totals (two barriers).  When some thread's values reach 2^23 (so that the
+// sums might not fit 32 bits) the whole workgroup takes group_scan2 instead.
+template <typename G>
+JSIDX_DEV void chunk_scan2(G& g, uint32_t tid, uint64_t w, uint64_t s, uint64_t* wex, uint64_t* sex,
+                           uint64_t* wall, uint64_t* sall) {
+  static_assert(kTapeThreads == 256, "four waves");
+  constexpr uint64_t kBig = 1ull << 23, kFlag = 1ull << 63;
+  const bool big = prim::ballot(w >= kBig || s >= kBig) != 0ull;
+  const uint32_t wi = prim::incl_scan((uint32_t)w), si = prim::incl_scan((uint32_t)s), wv = tid / 64u;
+  if ((tid & 63u) == 63u) {
+    g.w[wv] = (uint64_t)wi | (big ? kFlag : 0ull);
+    g.s[wv] = si;
+  }
+  prim::sync();
+  uint32_t wb = 0, sb = 0, wt = 0, st = 0;
+  bool any_big = false;
+#pragma unroll
+  for (uint32_t k = 0; k < 4u; k++) {
+    const uint64_t x = g.w[k];
+    const uint32_t y = (uint32_t)g.s[k];
+    any_big |= (x & kFlag) != 0ull;
+    wb += k < wv ? (uint32_t)x : 0u;
+    sb += k < wv ? y : 0u;
+    wt += (uint32_t)x;
+    st += y;
+  }
+  prim::sync();
+  if (any_big) {  // the same for every thread
+    group_scan2(g, tid, w, s, wex, sex, wall, sall);
+    return;
+  }
+  *wex = wb + wi - (uint32_t)w;
+  *sex = sb + si - (uint32_t)s;
+  *wall = wt;
+  *sall = st;
+}
+
 JSIDX_DEV uint64_t ld64(const uint64_t* p) {
   const uint2 v = prim::ld_pair(reinterpret_cast<const uint2*>(p));
   return ((uint64_t)v.y << 32) | v.x;
@@ -1722,7 +1761,7 @@ JSIDX_DEV void tape_count(const TapeArgs& a) {
     }
   }
   uint64_t wex, sex, wall, sall;
-  group_scan2(g.sc, tid, w, s, &wex, &sex, &wall, &sall);
+  chunk_scan2(g.sc, tid, w, s, &wex, &sex, &wall, &sall);
   if (tid == 0) {
     st64(a.chunk_sum + 2 * (uint64_t)c, wall);
     st64(a.chunk_sum + 2 * (uint64_t)c + 1, sall);
@@ -1826,7 +1865,7 @@ JSIDX_DEV void stage_offsets(const TapeArgs& a, uint32_t n, TapeChunkT<BATCH>& g
     s += g.S[j];
   }
   uint64_t wex, sex, wall, sall;
-  group_scan2(g.sc, tid, w, s, &wex, &sex, &wall, &sall);
+  chunk_scan2(g.sc, tid, w, s, &wex, &sex, &wall, &sall);
   uint64_t tw = (BATCH ? 0 : 1) + ld64(a.chunk_sum + 2 * (uint64_t)c) + wex;
   uint64_t ts = ld64(a.chunk_sum + 2 * (uint64_t)c + 1) + sex;
   for (int k = 0; k < kTapePer; k++) {
@@ -1848,7 +1887,9 @@ JSIDX_DEV void stage_offsets(const TapeArgs& a, uint32_t n, TapeChunkT<BATCH>& g
   prim::sync();
 }
 
-// 3. Each entry's tape index, stored coalesced.
+// 3. The tape index of each bracket (the only entries whose index another
+//    chunk looks up: their partners'), stored coalesced.  (A batch also
+//    writes each document's bases here, which needs the string sizes.)
 template <bool BATCH>
 JSIDX_DEVFN void tape_offsets(const TapeArgs& a) {
   TapeChunkT<BATCH>& g = prim::lds_object<TapeChunkT<BATCH>>();
@@ -1856,11 +1897,42 @@ JSIDX_DEVFN void tape_offsets(const TapeArgs& a) {
   if (!batch_go<BATCH>(a)) return;
   const uint32_t n = n_of<BATCH>(a), nchunks = nchunks_of<BATCH>(a);
   for (uint32_t c = prim::block(); c < nchunks; c += prim::grid()) {
-    stage_offsets<BATCH>(a, n, g, tid, c);
     const uint64_t c0 = (uint64_t)c * kTapeChunk;
+    if (!BATCH) {
+      // one document: each thread's 8 entries from one 8-byte load of their
+      // first bytes (past n they read as ':', which has no word)
+      const uint64_t e = c0 + (uint64_t)tid * kTapePer;
+      uint32_t lo = 0x3A3A3A3Au, hi = 0x3A3A3A3Au;
+      if (e + kTapePer <= n) {
+        const uint2 v = prim::ld_pair(reinterpret_cast<const uint2*>(a.kb + e));
+        lo = v.x;
+        hi = v.y;
+      } else {
+        for (int k = 0; k < kTapePer; k++) {
+          if (e + k >= n) break;
+          const uint32_t sh = 8u * (uint32_t)(k & 3), b = prim::load1(a.kb + e + k);
+          if (k < 4) lo = (lo & ~(0xFFu << sh)) | (b << sh);
+          else hi = (hi & ~(0xFFu << sh)) | (b << sh);
+        }
+      }
+      uint32_t w = 0;
+#pragma unroll
+      for (int k = 0; k < kTapePer; k++) w += words_of(((k < 4 ? lo : hi) >> (8 * (k & 3))) & 0xFFu);
+      uint64_t wex, sex, wall, sall;
+      chunk_scan2(g.sc, tid, w, 0u, &wex, &sex, &wall, &sall);
+      uint32_t t = (uint32_t)(1u + ld64(a.chunk_sum + 2 * (uint64_t)c) + wex);
+#pragma unroll
+      for (int k = 0; k < kTapePer; k++) {
+        const uint32_t b = ((k < 4 ? lo : hi) >> (8 * (k & 3))) & 0xFFu;
+        if (is_bracket(b)) prim::st_out(a.toff + e + k, t);
+        t += words_of(b);
+      }
+      continue;
+    }
+    stage_offsets<BATCH>(a, n, g, tid, c);
     for (uint32_t j = tid; j < (uint32_t)kTapeChunk; j += kTapeThreads) {
       if (c0 + j >= n) break;
-      prim::st_out(a.toff + c0 + j, g.T[j]);
+      if (is_bracket(g.K[j])) prim::st_out(a.toff + c0 + j, g.T[j]);
     }
     prim::sync();
   }
@@ -1951,7 +2023,6 @@ JSIDX_DEV uint32_t write_strings(const TapeArgs& a, StrLds& L, StrSrc src, bool 
   return err;
 }
 
-JSIDX_DEV bool is_bracket(uint32_t b) { return in_set(b, 0u, kBracketHi); }
 // numbers and literals
 JSIDX_DEV bool is_queued(uint32_t b) { return !in_set(b, kNoWordLo | set_lo('"'), kBracketHi); }
 

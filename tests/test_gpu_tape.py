@@ -133,6 +133,29 @@ def test_tape_full_size_c1_and_c2():
         assert_tape_matches(doc, name)
 
 
+def test_tape_strings_above_2_23_bytes():
+    """Strings of more than 2^23 bytes in one chunk: the chunk scans take their
+    64-bit form (one document, and a batch of such documents)."""
+    rng = random.Random(29)
+
+    def big(k):
+        body = "".join(rng.choice(["a", "b", " ", "\\n", "\\u00e9", "\\\""]) for _ in range(200))
+        return body * k
+
+    doc = ('[' + '"' + big(50000) + '", 1, {"k": "' + big(48000) + '", "v": [2.5, true, null]}, "z"]').encode()
+    assert len(doc) > 2 * (1 << 23)
+    _say(f"case: tape strings above 2^23 bytes, {len(doc)} bytes")
+    assert_tape_matches(doc, "big strings")
+    docs = [doc, b'["x", 3]', ('{"s": "' + big(45000) + '"}').encode()]
+    data = b"".join(docs)
+    offs = np.zeros(len(docs) + 1, dtype=np.uint64)
+    np.cumsum([len(x) for x in docs], out=offs[1:])
+    _say(f"case: tape batch with strings above 2^23 bytes, {len(data)} bytes")
+    b = _Batch(data, offs)
+    b.run()
+    assert b.check("big strings batch") == 3
+
+
 def test_tape_flags_on_corrupted_atoms():
     """One corruption per document, inserted as a new first element of a
     random array of a generated document: a number with a stray letter, a

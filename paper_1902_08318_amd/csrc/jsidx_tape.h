@@ -1843,45 +1843,69 @@ JSIDX_DEVFN void tape_scan(const TapeArgs& a) {
 template <bool BATCH>
 JSIDX_DEV bool batch_go(const TapeArgs& a) { return !BATCH || prim::ld_agent32(a.vn + 2) != 0u; }
 
-// Stages chunk c (first bytes and string sizes, loaded coalesced) and turns
-// them into each entry's tape index (T) and buffer offset (S) by a scan over
-// the threads' runs of 16 entries.  (For a batch, T is the index of the
+// Stages chunk c (first bytes and string sizes, each thread's run of 8
+// entries in wide loads) and turns them into each entry's tape index (T) and
+// buffer offset (S) by a scan over the runs.  (For a batch, T is the index of the
 // entry's own first word, after its document's opening root word if it is
 // the document's first entry; F holds the batch flags.)
 template <bool BATCH>
 JSIDX_DEV void stage_offsets(const TapeArgs& a, uint32_t n, TapeChunkT<BATCH>& g, uint32_t tid, uint32_t c) {
   const uint64_t c0 = (uint64_t)c * kTapeChunk;
-  for (uint32_t j = tid; j < (uint32_t)kTapeChunk; j += kTapeThreads) {
-    const bool in = c0 + j < n;
-    g.K[j] = (uint8_t)(in ? prim::load1(a.kb + c0 + j) : ':');
-    g.S[j] = in ? prim::load4(reinterpret_cast<const uint8_t*>(a.sbytes + c0 + j)) : 0u;
-    if (BATCH) g.F[j] = (uint8_t)(in ? prim::load1(a.vflag + c0 + j) : 0u);
+  const uint32_t j0 = tid * (uint32_t)kTapePer;
+  const uint64_t e = c0 + j0;
+  // the thread's 8 entries in wide loads (past n: ':', no bytes, no flags)
+  uint32_t k8[2] = {0x3A3A3A3Au, 0x3A3A3A3Au}, f8[2] = {0u, 0u}, sv[kTapePer];
+  if (e + kTapePer <= n) {
+    const uint2 kv = prim::ld_pair(reinterpret_cast<const uint2*>(a.kb + e));
+    const uint4 s0 = prim::load16(reinterpret_cast<const uint8_t*>(a.sbytes + e));
+    const uint4 s1 = prim::load16(reinterpret_cast<const uint8_t*>(a.sbytes + e + 4));
+    k8[0] = kv.x;
+    k8[1] = kv.y;
+    sv[0] = s0.x, sv[1] = s0.y, sv[2] = s0.z, sv[3] = s0.w;
+    sv[4] = s1.x, sv[5] = s1.y, sv[6] = s1.z, sv[7] = s1.w;
+    if (BATCH) {
+      const uint2 fv = prim::ld_pair(reinterpret_cast<const uint2*>(a.vflag + e));
+      f8[0] = fv.x;
+      f8[1] = fv.y;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < kTapePer; k++) {
+      const bool in = e + k < n;
+      const uint32_t sh = 8u * (uint32_t)(k & 3), keep = ~(0xFFu << sh);
+      if (in) k8[k / 4] = (k8[k / 4] & keep) | (prim::load1(a.kb + e + k) << sh);
+      sv[k] = in ? prim::load4(reinterpret_cast<const uint8_t*>(a.sbytes + e + k)) : 0u;
+      if (BATCH && in) f8[k / 4] |= prim::load1(a.vflag + e + k) << sh;
+    }
   }
-  prim::sync();
+  uint32_t kb[kTapePer], fl[kTapePer];
   uint64_t w = 0, s = 0;
+#pragma unroll
   for (int k = 0; k < kTapePer; k++) {
-    const uint32_t j = tid * kTapePer + (uint32_t)k;
-    w += BATCH ? entry_words(g.K[j], g.F[j]) : words_of(g.K[j]);
-    s += g.S[j];
+    kb[k] = (k8[k / 4] >> (8 * (k & 3))) & 0xFFu;
+    fl[k] = (f8[k / 4] >> (8 * (k & 3))) & 0xFFu;
+    g.K[j0 + k] = (uint8_t)kb[k];
+    if (BATCH) g.F[j0 + k] = (uint8_t)fl[k];
+    w += BATCH ? entry_words(kb[k], fl[k]) : words_of(kb[k]);
+    s += sv[k];
   }
   uint64_t wex, sex, wall, sall;
   chunk_scan2(g.sc, tid, w, s, &wex, &sex, &wall, &sall);
   uint64_t tw = (BATCH ? 0 : 1) + ld64(a.chunk_sum + 2 * (uint64_t)c) + wex;
   uint64_t ts = ld64(a.chunk_sum + 2 * (uint64_t)c + 1) + sex;
+#pragma unroll
   for (int k = 0; k < kTapePer; k++) {
-    const uint32_t j = tid * kTapePer + (uint32_t)k;
-    const uint32_t sb = g.S[j];
-    const uint32_t first = BATCH && (g.F[j] & kVFirst) ? 1u : 0u;
-    if (BATCH && first && c0 + j < n) {
+    const uint32_t first = BATCH && (fl[k] & kVFirst) ? 1u : 0u;
+    if (BATCH && first && e + k < n) {
       // the document's bases: its opening root word and its first string byte
-      const uint32_t d = prim::load4(reinterpret_cast<const uint8_t*>(a.docid + c0 + j));
+      const uint32_t d = prim::load4(reinterpret_cast<const uint8_t*>(a.docid + e + k));
       st64(a.dbase + 2 * (uint64_t)d, tw);
       st64(a.dbase + 2 * (uint64_t)d + 1, ts);
     }
-    g.T[j] = (uint32_t)(tw + first);
-    g.S[j] = (uint32_t)ts;  // the buffer offset's low word (see tape_write)
-    tw += BATCH ? entry_words(g.K[j], g.F[j]) : words_of(g.K[j]);
-    ts += sb;
+    g.T[j0 + k] = (uint32_t)(tw + first);
+    g.S[j0 + k] = (uint32_t)ts;  // the buffer offset's low word (see tape_write)
+    tw += BATCH ? entry_words(kb[k], fl[k]) : words_of(kb[k]);
+    ts += sv[k];
   }
   if (tid == kTapeThreads - 1) g.send = ts;
   prim::sync();

@@ -241,19 +241,34 @@ JSIDX_DEV void load_stored_kinds(const ScopeArgs& a, uint32_t n, G& g, uint32_t 
   prim::sync();
 }
 
-// Ordered inclusive scan of the workgroup's per-thread functions; returns the
-// composition of the threads before this one.
+// A lane's function from the lane d below it (shuffled as four words).
+JSIDX_DEV DepthFn fn_shfl_up(const DepthFn& f, int d) {
+  const uint64_t a = (uint64_t)f.a, b = (uint64_t)f.b;
+  const uint64_t ua = ((uint64_t)prim::shfl_up((uint32_t)(a >> 32), d) << 32) | prim::shfl_up((uint32_t)a, d);
+  const uint64_t ub = ((uint64_t)prim::shfl_up((uint32_t)(b >> 32), d) << 32) | prim::shfl_up((uint32_t)b, d);
+  return DepthFn{(int64_t)ua, (int64_t)ub};
+}
+
+// Ordered exclusive scan of the workgroup's per-thread functions: each wave
+// scans its lanes by shuffles, then the four wave totals are composed in
+// order (two barriers); returns the composition of the threads before this
+// one.
 template <typename G>
 JSIDX_DEV DepthFn group_exclusive(G& g, uint32_t tid, DepthFn mine) {
-  g.f[tid] = mine;
-  prim::sync();
-  for (uint32_t s = 1; s < (uint32_t)kScopeThreads; s <<= 1) {
-    const DepthFn t = tid >= s ? fn_then(g.f[tid - s], g.f[tid]) : g.f[tid];
-    prim::sync();
-    g.f[tid] = t;
-    prim::sync();
+  static_assert(kScopeThreads == 4 * kScopeWave, "four waves");
+  const uint32_t lane = tid % (uint32_t)kScopeWave, wv = tid / (uint32_t)kScopeWave;
+  DepthFn incl = mine;
+#pragma unroll
+  for (int d = 1; d < kScopeWave; d <<= 1) {
+    const DepthFn up = fn_shfl_up(incl, d);
+    if (lane >= (uint32_t)d) incl = fn_then(up, incl);
   }
-  const DepthFn ex = tid ? g.f[tid - 1] : fn_id();
+  const DepthFn up1 = fn_shfl_up(incl, 1);
+  if (lane == (uint32_t)kScopeWave - 1) g.f[wv] = incl;
+  prim::sync();
+  DepthFn ex = fn_id();
+  for (uint32_t k = 0; k < wv; k++) ex = fn_then(ex, g.f[k]);
+  if (lane) ex = fn_then(ex, up1);
   prim::sync();
   return ex;
 }

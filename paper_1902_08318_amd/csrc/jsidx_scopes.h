@@ -160,10 +160,7 @@ JSIDX_DEV uint2 pack64(int64_t v) {
 }
 JSIDX_DEV int64_t unpack64(uint2 v) { return (int64_t)(((uint64_t)v.y << 32) | v.x); }
 
-JSIDX_DEV uint32_t kind_at(const ScopeArgs& a, uint32_t i) {
-  const uint32_t p = prim::load4(reinterpret_cast<const uint8_t*>(a.idx + i));
-  if ((uint64_t)p >= a.len) return kOther;  // not a position of this document
-  const uint32_t b = prim::load1(a.buf + p);
+JSIDX_DEV uint32_t kind_of_byte(uint32_t b) {
   return b == 0x5Bu ? kOpenSq : b == 0x7Bu ? kOpenCu : b == 0x5Du ? kCloseSq : b == 0x7Du ? kCloseCu
        : b == 0x3Au ? kColon : b == 0x2Cu ? kComma : b == 0x22u ? kStr : kOther;
 }
@@ -216,8 +213,19 @@ JSIDX_DEV DepthFn fn_of_entry(uint32_t kb) {
 template <typename G>
 JSIDX_DEV void load_kinds(const ScopeArgs& a, G& g, uint32_t tid, uint32_t c) {
   const uint64_t c0 = (uint64_t)c * kScopeChunk;
-  for (uint32_t j = tid; j < (uint32_t)kScopeChunk; j += kScopeThreads)
-    g.K[j] = (uint8_t)(c0 + j < a.n ? kind_at(a, (uint32_t)(c0 + j)) : kOther);
+  constexpr int kR = kScopeChunk / kScopeThreads;
+  // all positions, then all bytes, in flight together (a position outside
+  // the document, and an entry past n, is kOther)
+  uint32_t p[kR], b[kR];
+#pragma unroll
+  for (int k = 0; k < kR; k++) {
+    const uint64_t i = c0 + tid + (uint64_t)k * kScopeThreads;
+    p[k] = i < a.n ? prim::load4(reinterpret_cast<const uint8_t*>(a.idx + i)) : 0xFFFFFFFFu;
+  }
+#pragma unroll
+  for (int k = 0; k < kR; k++) b[k] = (uint64_t)p[k] < a.len ? prim::load1(a.buf + p[k]) : 0u;
+#pragma unroll
+  for (int k = 0; k < kR; k++) g.K[tid + (uint32_t)k * kScopeThreads] = (uint8_t)kind_of_byte(b[k]);
   prim::sync();
 }
 
@@ -399,12 +407,23 @@ JSIDX_DEVFN void scope_levels(const ScopeArgs& a) {
   }
   g.m[tid] = lo_level;
   prim::sync();
-  // the chunk's levels, kinds and cleared links go out as consecutive words
-  for (uint32_t j = tid; j < (uint32_t)kScopeChunk; j += kScopeThreads) {
-    if (c0 + j >= n) break;
-    prim::st_out(a.lev + c0 + j, g.L[j]);
-    prim::st_byte(a.kind + c0 + j, g.K[j]);
-    prim::st_out(a.match + c0 + j, kUnlinked);
+  // the chunk's levels, kinds and cleared links go out as consecutive words,
+  // four entries per thread and store (bytes past n are left as they were)
+  const uint32_t* kw = reinterpret_cast<const uint32_t*>(g.K);
+  for (uint32_t q = tid; q < (uint32_t)kScopeChunk / 4; q += kScopeThreads) {
+    const uint64_t e = c0 + 4 * (uint64_t)q;
+    if (e >= n) break;
+    if (e + 4 <= n) {
+      prim::st_out4(a.lev + e, uint4{g.L[4 * q], g.L[4 * q + 1], g.L[4 * q + 2], g.L[4 * q + 3]});
+      prim::st_out(reinterpret_cast<uint32_t*>(a.kind + e), kw[q]);
+      prim::st_out4(a.match + e, uint4{kUnlinked, kUnlinked, kUnlinked, kUnlinked});
+      continue;
+    }
+    for (uint32_t k = 0; k < 4u && e + k < n; k++) {
+      prim::st_out(a.lev + e + k, g.L[4 * q + k]);
+      prim::st_byte(a.kind + e + k, g.K[4 * q + k]);
+      prim::st_out(a.match + e + k, kUnlinked);
+    }
   }
   for (uint32_t s = kScopeThreads / 2; s > 0; s >>= 1) {
     if (tid < s && g.m[tid + s] < g.m[tid]) g.m[tid] = g.m[tid + s];

@@ -459,9 +459,40 @@ JSIDX_DEVFN void scope_local(const ScopeArgs& a) {
   for (uint32_t c = prim::block(); c < nchunks; c += prim::grid()) {
   const uint64_t c0 = (uint64_t)c * kScopeChunk;
   const uint32_t cend = n - c0 < (uint64_t)kScopeChunk ? (uint32_t)(n - c0) : (uint32_t)kScopeChunk;
-  for (uint32_t j = tid; j < (uint32_t)kScopeChunk; j += kScopeThreads) {
-    g.L[j] = j < cend ? prim::load4(reinterpret_cast<const uint8_t*>(a.lev + c0 + j)) : kNoLevel;
-    g.K[j] = (uint8_t)(j < cend ? prim::load1(a.kind + c0 + j) & kTokMask : kOther);
+  // levels and whole kind bytes, four entries per load (past the end: no
+  // level, kOther)
+  {
+    constexpr int kR = kScopeChunk / 4 / kScopeThreads;
+    uint4 lq[kR];
+    uint32_t kq[kR];
+#pragma unroll
+    for (int r = 0; r < kR; r++) {
+      const uint32_t j = 4u * (tid + (uint32_t)r * kScopeThreads);
+      if (j + 4 <= cend) {
+        lq[r] = prim::load16(reinterpret_cast<const uint8_t*>(a.lev + c0 + j));
+        kq[r] = prim::load4(a.kind + c0 + j);
+      } else {
+        uint32_t l[4], kw = 0;
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+          const bool in = j + k < cend;
+          l[k] = in ? prim::load4(reinterpret_cast<const uint8_t*>(a.lev + c0 + j + k)) : kNoLevel;
+          kw |= (in ? prim::load1(a.kind + c0 + j + k) : (uint32_t)kOther) << (8 * k);
+        }
+        lq[r] = uint4{l[0], l[1], l[2], l[3]};
+        kq[r] = kw;
+      }
+    }
+    uint32_t* kw = reinterpret_cast<uint32_t*>(g.K);
+#pragma unroll
+    for (int r = 0; r < kR; r++) {
+      const uint32_t q = tid + (uint32_t)r * kScopeThreads;
+      g.L[4 * q] = lq[r].x;
+      g.L[4 * q + 1] = lq[r].y;
+      g.L[4 * q + 2] = lq[r].z;
+      g.L[4 * q + 3] = lq[r].w;
+      kw[q] = kq[r];
+    }
   }
   prim::sync();
   // lowest level of each thread's run of kScopePer entries
@@ -485,7 +516,7 @@ JSIDX_DEVFN void scope_local(const ScopeArgs& a) {
     const uint32_t j = tid * kScopePer + (uint32_t)k;
     if (j >= cend) break;
     const uint32_t i = (uint32_t)(c0 + j);
-    const uint32_t ki = g.K[j];
+    const uint32_t ki = g.K[j] & kTokMask;
     if (ki != kOpenSq && ki != kOpenCu) continue;
     const uint32_t lv = g.L[j];
     // the rest of this run, then the rest of its group of runs by their
@@ -510,7 +541,15 @@ JSIDX_DEVFN void scope_local(const ScopeArgs& a) {
         while (g.L[p] > lv) p++;  // ends inside run r: its lowest level is at most lv
     }
     if (p < cend) {
-      link<BATCH>(a, i, (uint32_t)(c0 + p), ki);
+      // as link(), with the kind bytes from LDS (only this call changes the
+      // closer's)
+      const uint32_t k = (uint32_t)(c0 + p), kb = g.K[p];
+      prim::st_out(a.match + i, k);
+      prim::st_out(a.match + k, i);
+      if ((ki == kOpenCu) != ((kb & kTokMask) == kCloseCu)) prim::or_agent32(err_of<BATCH>(a, i), kErrMismatched);
+      const bool first = BATCH && (g.K[j] & kDocStartBit) != 0u;
+      const uint32_t prev = j ? g.K[j - 1] : i ? prim::load1(a.kind + i - 1) : (uint32_t)kOther;
+      if (i > 0 && !first && (prev & kTokMask) == kColon) prim::st_byte(a.kind + k, kb | kMemberBit);
     } else {
       const uint32_t q = prim::add_agent32(a.qcount, 1u);
       prim::st_out(a.queue + q, i);

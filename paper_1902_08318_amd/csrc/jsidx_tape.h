@@ -2148,11 +2148,14 @@ JSIDX_DEV void tape_write(const TapeArgs& a) {
         mq[q] = br ? prim::load4(reinterpret_cast<const uint8_t*>(a.match + obq[q] + (i - v0q[q]))) : kTapeUnlinked;
       }
     }
+    // the partners' tape indices: from this chunk's staged ones when the
+    // partner is in the chunk, else as the offsets pass stored them
     uint32_t tkq[kTapeSuper];
 #pragma unroll
     for (int q = 0; q < kTapeSuper; q++) {
       const bool linked = mq[q] != kTapeUnlinked && mq[q] < limq[q];
-      tkq[q] = linked ? prim::load4(reinterpret_cast<const uint8_t*>(a.toff + v0q[q] + mq[q])) : 0u;
+      const uint64_t pe = (uint64_t)v0q[q] + mq[q], pj = pe - c0;
+      tkq[q] = !linked ? 0u : pj < (uint64_t)kTapeChunk ? g.T[pj] : prim::load4(reinterpret_cast<const uint8_t*>(a.toff + pe));
     }
 #pragma unroll
     for (int q = 0; q < kTapeSuper; q++) {

@@ -2051,8 +2051,9 @@ JSIDX_DEV uint32_t write_strings(const TapeArgs& a, StrLds& L, StrSrc src, bool 
 JSIDX_DEV bool is_queued(uint32_t b) { return !in_set(b, kNoWordLo | set_lo('"'), kBracketHi); }
 
 // 4. Brackets, strings and the strings' words; numbers and literals queued
-//    (one atomic per workgroup).  In a batch, links and string offsets are
-//    relative to the entry's document's tape and strings.
+//    with their tape indices (one atomic per workgroup).  In a batch, links
+//    and string offsets are relative to the entry's document's tape and
+//    strings.
 template <bool BATCH>
 JSIDX_DEV void tape_write(const TapeArgs& a) {
   TapeWriteLds<BATCH>& G = prim::lds_object<TapeWriteLds<BATCH>>();
@@ -2066,10 +2067,10 @@ JSIDX_DEV void tape_write(const TapeArgs& a) {
   stage_offsets<BATCH>(a, n, g, tid, c);
   const uint64_t c0 = (uint64_t)c * kTapeChunk;
   // the workgroup's slots in the queue, in entry order (so that the number
-  // pass reads the index and tape indices coalesced), numbers from the
-  // queue's front and literals from its back (so that a wave of the number
-  // pass takes one kind, not both paths): counts per group of 64 entries,
-  // their prefix over the chunk
+  // pass's windows and tape words of a wave lie close together), numbers
+  // from the queue's front and literals from its back (so that a wave of the
+  // number pass takes one kind, not both paths): counts per group of 64
+  // entries, their prefix over the chunk
   const uint32_t gw = (uint32_t)(run_first(c, 0) - c0) / 64u;  // this wave's first group
   for (int k = 0; k < kTapePer; k++) {
     const uint32_t b = g.K[64u * (gw + k) + lane];  // entries past n were staged as ':'

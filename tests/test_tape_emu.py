@@ -168,6 +168,16 @@ def test_long_strings_finished_by_the_wave():
     _check(("[" + ",".join(strs[:50]) + ', "' + "y" * 300).encode())  # never closed
 
 
+def test_string_sizes_around_2_16_bytes():
+    """Strings whose buffer bytes (4 + decoded length) lie just below, at and
+    above 2^16, with and without escapes."""
+    strs = ['"' + "a" * k + '"' for k in (65530, 65531, 65532, 70000)]
+    strs.insert(2, '"' + "\\u00e9" * 2 + "é" * 32764 + '"')   # 65532 bytes decoded
+    strs.append('"' + "\\n" * 70000 + '"')                     # escapes: 70000 bytes decoded
+    doc = "[" + ", ".join(strs + ['"short"', "1", "true"]) + "]"
+    _check(doc.encode())
+
+
 def test_strings_staged_at_every_alignment():
     """The string passes stage each group's bytes and output in LDS with
     16-byte blocks: documents and string buffers at every offset from a

@@ -1077,11 +1077,10 @@ JSIDX_DEV bool fast_run(Tables& T, const uint8_t* buf, uint64_t p0, uint64_t p1,
 }
 
 // ---- Literals ---------------------------------------------------------------
-JSIDX_DEV bool literal_ok(const TapeArgs& a, uint64_t p, uint32_t first) {
+JSIDX_DEV bool literal_ok(const TapeArgs& a, const Window& w, uint64_t p, uint32_t first) {
   // true, false, null by their bytes (little-endian words)
   const uint32_t L = first == 'f' ? 5u : 4u;
   if (p + L > a.len) return false;
-  const Window w = window_at(a.buf, a.len, p);
   uint64_t v = 0;
   for (uint32_t k = 0; k < L; k++) v |= (uint64_t)win_byte(w, p + k) << (8 * k);
   const uint64_t want = first == 't' ? 0x65757274ull : first == 'n' ? 0x6C6C756Eull : 0x65736C6166ull;
@@ -1130,9 +1129,8 @@ JSIDX_DEV uint64_t eight_value(uint64_t v) {
   return (v * 10000u + (v >> 32)) & 0xFFFFFFFFull;
 }
 
-JSIDX_DEV NumText scan_number(const TapeArgs& a, uint64_t p) {
+JSIDX_DEV NumText scan_number(const TapeArgs& a, const Window& w, uint64_t p) {
   NumText t{false, false, true, false, 0, 0, 0};
-  const Window w = window_at(a.buf, a.len, p);
   uint32_t nd = 0;  // significant digits in w
   int64_t q = 0;
   uint32_t c = win_byte(w, p);
@@ -2232,18 +2230,30 @@ JSIDX_DEV void tape_write(const TapeArgs& a) {
 // Grid-stride bounds of a queue for this thread.
 JSIDX_DEV uint32_t queue_len(const TapeArgs& a, int q) { return prim::ld_agent32(a.qcount + q); }
 
+JSIDX_DEV NumText scan_number(const TapeArgs& a, uint64_t p) { return scan_number(a, window_at(a.buf, a.len, p), p); }
+
+// The window of an atom at p: loaded anywhere below hi (for a batch, the
+// batch's end, so that the loads need not wait for the document's bounds),
+// read only inside the entry's document.
+JSIDX_DEV Window atom_window(const TapeArgs& a, uint64_t hi, uint64_t p) {
+  Window w = window_at(a.buf, hi, p);
+  w.len = a.len;
+  return w;
+}
+
 // 5. Numbers (both words; undecided doubles queued for tape_exact) and
-//    literals.  (a: arguments whose bound is the entry's document; pos its
-//    first byte.)
-JSIDX_DEV uint32_t number_entry(const TapeArgs& a, uint64_t pos, uint64_t t, bool* undecided) {
+//    literals.  (a: arguments whose bound is the entry's document; hi the
+//    end of the readable bytes; pos its first byte.)
+JSIDX_DEV uint32_t number_entry(const TapeArgs& a, uint64_t hi, uint64_t pos, uint64_t t, bool* undecided) {
   uint64_t* out = a.tape + t;
   *undecided = false;
-  const uint32_t b = byte_at(a, pos);
+  const Window w = atom_window(a, hi, pos);
+  const uint32_t b = win_byte(w, pos);
   if (is_lit_start(b)) {  // a literal: its tag, and whether it is spelled out
     st64(out, (uint64_t)b << 56);
-    return literal_ok(a, pos, b) ? 0u : kErrLiteral;
+    return literal_ok(a, w, pos, b) ? 0u : kErrLiteral;
   }
-  const NumText nt = scan_number(a, pos);
+  const NumText nt = scan_number(a, w, pos);
   if (!nt.ok) {
     st64(out, (uint64_t)'d' << 56);
     st64(out + 1, 0);
@@ -2291,6 +2301,7 @@ template <bool BATCH>
 JSIDX_DEVFN void tape_numbers(const TapeArgs& a) {
   if (!batch_go<BATCH>(a)) return;
   const uint32_t qn = queue_len(a, 1), ql = queue_len(a, 2);  // numbers, then literals from the back
+  const uint64_t bhi = buf_hi<BATCH>(a);
   const uint32_t stride = prim::grid() * (uint32_t)kTapeThreads;
   const uint32_t rounds = (qn + ql + stride - 1) / stride;
   for (uint32_t r = 0; r < rounds; r++) {
@@ -2302,7 +2313,7 @@ JSIDX_DEVFN void tape_numbers(const TapeArgs& a) {
       const uint2 e = prim::ld_pair(a.nqueue + slot);
       d = entry_doc<BATCH>(a, e.x);
       const uint64_t pos = queued_pos<BATCH>(a, e.x);
-      err = number_entry(entry_args<BATCH>(a, d), pos, e.y, &undecided);
+      err = number_entry(entry_args<BATCH>(a, d), bhi, pos, e.y, &undecided);
     }
     const uint32_t xs = wave_append(a, 0, undecided);
     if (undecided) prim::st_out(a.queue + xs, slot);

@@ -29,8 +29,12 @@ template <bool B>
 __global__ void __launch_bounds__(kTapeThreads) __attribute__((amdgpu_waves_per_eu(4))) tape_write_kernel(TapeArgs a) {
   tape_write<B>(a);
 }
+// a thread per atom waits mostly on its window: registers kept to eight
+// waves per SIMD (64, no spills) to have more atoms in flight
 template <bool B>
-__global__ void __launch_bounds__(kTapeThreads) tape_numbers_kernel(TapeArgs a) { tape_numbers<B>(a); }
+__global__ void __launch_bounds__(kTapeThreads) __attribute__((amdgpu_waves_per_eu(8))) tape_numbers_kernel(TapeArgs a) {
+  tape_numbers<B>(a);
+}
 template <bool B>
 __global__ void __launch_bounds__(kExactThreads) tape_exact_kernel(TapeArgs a) { tape_exact<B>(a); }
 __global__ void __launch_bounds__(kTapeThreads) tape_batch_sums_kernel(TapeArgs a) { tape_batch_sums(a); }

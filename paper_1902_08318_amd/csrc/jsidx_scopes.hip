@@ -12,8 +12,12 @@
 
 namespace jsidx {
 
+// the fold waits on its gathers: eight waves per SIMD keep more of them in
+// flight (57 registers, no spills)
 template <bool B>
-__global__ void __launch_bounds__(kScopeThreads) scope_chunk_fn_kernel(ScopeArgs a) { scope_chunk_fn<B>(a); }
+__global__ void __launch_bounds__(kScopeThreads) __attribute__((amdgpu_waves_per_eu(8))) scope_chunk_fn_kernel(ScopeArgs a) {
+  scope_chunk_fn<B>(a);
+}
 template <bool B>
 __global__ void __launch_bounds__(kScopeThreads) scope_scan_kernel(ScopeArgs a) { scope_scan<B>(a); }
 template <bool B>
